@@ -1,0 +1,256 @@
+"""CPU oracle of the stereo VIO frontend -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. It wraps ``oracle.cpp``, a plain C++
+statement of the frontend written from the paper (Sec. III-C to III-E) that
+shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+TRACKED, DETECTED, MATCHED, LOST_FB, LOST_OOB, LOST_DEGENERATE, LOST_CAP = range(7)
+
+RECORD_DTYPE = np.dtype([
+    ("id", "<i8"), ("x", "<f4"), ("y", "<f4"), ("theta", "<f4"), ("fb_err", "<f4"),
+    ("resid_rms", "<f4"), ("age", "<i4"), ("camera", "<i2"), ("status", "<i2"), ("score", "<i4"),
+])
+assert RECORD_DTYPE.itemsize == 40
+
+
+def build() -> str:
+    """Compile the oracle with g++ -O2 (no fast-math, no SIMD intrinsics)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("levels", ctypes.c_int32), ("gn_iters", ctypes.c_int32), ("cell_size", ctypes.c_int32),
+        ("k_per_cell", ctypes.c_int32), ("n_thresholds", ctypes.c_int32),
+        ("thresholds", ctypes.c_int32 * 4),
+        ("edge_margin", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
+        ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float),
+    ]
+
+
+def _lib_():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        vp, i32, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        lib.orc_pyramid.argtypes = [vp, i32, i32, i32, vp]
+        lib.orc_fast_scores.argtypes = [vp, i32, i32, vp]
+        lib.orc_detect.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, vp]
+        lib.orc_track.argtypes = [vp, vp, i32, i32, i32, i32, f64, i32, vp, vp, vp, vp, i32, vp, vp]
+        lib.orc_klt_pass.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+        lib.orc_template.argtypes = [vp, i32, i32, f64, f64, vp]
+        lib.orc_pattern.argtypes = [vp, vp]
+        lib.orc_se2_exp.argtypes = [f64, f64, f64, vp, vp]
+        lib.orc_se2_exp.restype = None
+        lib.orc_inverse3.argtypes = [vp, vp]
+        lib.orc_inverse3.restype = f64
+        lib.orc_fe_create.argtypes = [i32, vp, vp, i32, ctypes.POINTER(Params)]
+        lib.orc_fe_create.restype = vp
+        lib.orc_fe_destroy.argtypes = [vp]
+        lib.orc_fe_destroy.restype = None
+        lib.orc_fe_push.argtypes = [vp, vp, vp]
+        lib.orc_fe_get.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_fe_set_keypoints.argtypes = [vp, i32, i32, vp, vp, vp]
+        lib.orc_fe_get_keypoints.argtypes = [vp, i32, i32, vp, vp, vp]
+        lib.orc_fe_next_id.argtypes = [vp]
+        lib.orc_fe_next_id.restype = ctypes.c_int64
+        _lib = lib
+    return _lib
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, np.uint8)
+
+
+def pyramid(img, levels):
+    """List of pyramid levels (Sec. III-C eqs. 1-3)."""
+    img = _u8(img)
+    h, w = img.shape
+    sizes = [(h >> l, w >> l) for l in range(levels)]
+    out = np.zeros(sum(a * b for a, b in sizes), np.uint8)
+    assert _lib_().orc_pyramid(img.ctypes.data, w, h, levels, out.ctypes.data) == 0
+    res, off = [], 0
+    for a, b in sizes:
+        res.append(out[off:off + a * b].reshape(a, b))
+        off += a * b
+    return res
+
+
+def fast_scores(img):
+    """FAST-9 score map (Sec. III-D); INT32_MIN where undefined (3-px border)."""
+    img = _u8(img)
+    h, w = img.shape
+    out = np.zeros((h, w), np.int32)
+    assert _lib_().orc_fast_scores(img.ctypes.data, w, h, out.ctypes.data) == 0
+    return out
+
+
+def detect(img, cell, k=1, thresholds=(40, 20, 10, 5), margin=8, single_pass=False):
+    """Per-cell winners [n_cells, k, 3] = (x, y, score), -1 where none."""
+    img = _u8(img)
+    h, w = img.shape
+    ncells = ((w + cell - 1) // cell) * ((h + cell - 1) // cell)
+    thr = np.asarray(thresholds, np.int32)
+    out = np.zeros((ncells, k, 3), np.int32)
+    assert _lib_().orc_detect(img.ctypes.data, w, h, cell, k, thr.ctypes.data, len(thr), margin,
+                              int(single_pass), out.ctypes.data) == 0
+    return out
+
+
+def track(src, dst, pts, init, levels, iters, fb_threshold=0.3, double=False):
+    """Forward-backward tracking; returns (xy_theta_fb_resid [n,5], status [n])."""
+    src, dst = _u8(src), _u8(dst)
+    h, w = src.shape
+    pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
+    init = np.ascontiguousarray(init, np.float64).reshape(-1, 2)
+    n = len(pts)
+    px, py = np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1])
+    ix, iy = np.ascontiguousarray(init[:, 0]), np.ascontiguousarray(init[:, 1])
+    out = np.zeros((n, 5), np.float64)
+    st = np.zeros(n, np.int32)
+    assert _lib_().orc_track(src.ctypes.data, dst.ctypes.data, w, h, levels, iters, fb_threshold, n,
+                             px.ctypes.data, py.ctypes.data, ix.ctypes.data, iy.ctypes.data, int(double),
+                             out.ctypes.data, st.ctypes.data) == 0
+    return out, st
+
+
+def klt_pass(src, dst, pts, init, levels, iters, theta0=None):
+    """One forward pass in FP64: [n, 6] = tx, ty, theta, resid, last_step, status."""
+    src, dst = _u8(src), _u8(dst)
+    h, w = src.shape
+    pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
+    init = np.ascontiguousarray(init, np.float64).reshape(-1, 2)
+    n = len(pts)
+    th = np.zeros(n) if theta0 is None else np.ascontiguousarray(theta0, np.float64)
+    cols = [np.ascontiguousarray(a) for a in (pts[:, 0], pts[:, 1], init[:, 0], init[:, 1], th)]
+    out = np.zeros((n, 6), np.float64)
+    assert _lib_().orc_klt_pass(src.ctypes.data, dst.ctypes.data, w, h, levels, iters, n,
+                                *[c.ctypes.data for c in cols], out.ctypes.data) == 0
+    return out
+
+
+def template(img, px, py):
+    img = _u8(img)
+    h, w = img.shape
+    out = np.zeros(20)
+    _lib_().orc_template(img.ctypes.data, w, h, px, py, out.ctypes.data)
+    return out[:9].reshape(3, 3), out[9:18].reshape(3, 3), bool(out[18]), bool(out[19])
+
+
+def pattern():
+    u = np.zeros(52, np.float32)
+    v = np.zeros(52, np.float32)
+    _lib_().orc_pattern(u.ctypes.data, v.ctypes.data)
+    return u, v
+
+
+def se2_exp(a, b, phi):
+    tx, ty = ctypes.c_double(), ctypes.c_double()
+    _lib_().orc_se2_exp(a, b, phi, ctypes.byref(tx), ctypes.byref(ty))
+    return tx.value, ty.value
+
+
+def inverse3(m):
+    m = np.ascontiguousarray(m, np.float64)
+    inv = np.zeros(9)
+    det = _lib_().orc_inverse3(m.ctypes.data, inv.ctypes.data)
+    return det, inv.reshape(3, 3)
+
+
+def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40, 20, 10, 5),
+                edge_margin=8, max_keypoints=300, fb_threshold=0.3, disparity0=32.5) -> Params:
+    p = Params()
+    p.struct_size = ctypes.sizeof(Params)
+    p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
+    p.n_thresholds = len(thresholds)
+    for i, t in enumerate(thresholds):
+        p.thresholds[i] = t
+    p.edge_margin, p.max_keypoints = edge_margin, max_keypoints
+    p.fb_threshold, p.disparity0 = fb_threshold, disparity0
+    return p
+
+
+def params_for(workload, **overrides) -> Params:
+    kw = dict(levels=workload.levels, gn_iters=workload.gn_iters, cell_size=workload.cell_size,
+              thresholds=workload.thresholds, edge_margin=workload.edge_margin,
+              max_keypoints=workload.max_keypoints, fb_threshold=workload.fb_threshold,
+              disparity0=workload.disparity0)
+    kw.update(overrides)
+    return make_params(**kw)
+
+
+class Frontend:
+    """The whole per-frame pipeline (Sec. III-B) on the CPU."""
+
+    def __init__(self, widths, heights, stereo, params: Params):
+        self.n_cams = len(widths)
+        w = np.asarray(widths, np.int32)
+        h = np.asarray(heights, np.int32)
+        self._h = _lib_().orc_fe_create(self.n_cams, w.ctypes.data, h.ctypes.data, int(stereo),
+                                        ctypes.byref(params))
+        if not self._h:
+            raise ValueError("oracle frontend rejected its parameters")
+        self.params = params
+
+    def close(self):
+        if self._h:
+            _lib_().orc_fe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def push(self, images):
+        imgs = [_u8(im) for im in images]
+        ptrs = (ctypes.c_void_p * len(imgs))(*[im.ctypes.data for im in imgs])
+        strides = np.asarray([im.shape[1] for im in imgs], np.int32)
+        assert _lib_().orc_fe_push(self._h, ptrs, strides.ctypes.data) == 0
+
+    def records(self):
+        n = ctypes.c_int()
+        _lib_().orc_fe_get(self._h, None, 0, ctypes.byref(n))
+        out = np.zeros(n.value, RECORD_DTYPE)
+        assert _lib_().orc_fe_get(self._h, out.ctypes.data, n.value, ctypes.byref(n)) == 0
+        return out
+
+    def set_keypoints(self, cam, ids, xy, pxy, age):
+        ids = np.ascontiguousarray(ids, np.int64)
+        n = len(ids)
+        st = np.ascontiguousarray(np.concatenate([np.asarray(xy, np.float32).reshape(n, 2),
+                                                  np.asarray(pxy, np.float32).reshape(n, 2)], 1))
+        age = np.ascontiguousarray(age, np.int32)
+        assert _lib_().orc_fe_set_keypoints(self._h, cam, n, ids.ctypes.data, st.ctypes.data,
+                                            age.ctypes.data) == 0
+
+    def keypoints(self, cam, capacity=1 << 16):
+        ids = np.zeros(capacity, np.int64)
+        st = np.zeros((capacity, 4), np.float32)
+        age = np.zeros(capacity, np.int32)
+        n = _lib_().orc_fe_get_keypoints(self._h, cam, capacity, ids.ctypes.data, st.ctypes.data,
+                                         age.ctypes.data)
+        assert n >= 0
+        return ids[:n], st[:n, :2], st[:n, 2:], age[:n]
+
+    @property
+    def next_id(self):
+        return _lib_().orc_fe_next_id(self._h)

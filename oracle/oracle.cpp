@@ -1,0 +1,761 @@
+// CPU oracle of the stereo VIO frontend (VkVIO, arXiv 2609.30459, Sec. III).
+//
+// TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the CPU
+// baseline leg of the benchmark load this library; the product path never does.
+// It is a plain, slow, loop-by-loop statement of what the frontend computes and
+// shares no code, header or table with the GPU implementation.
+//
+// Precision: the pyramid and the detector are integer. The tracker is a template
+// on its real type; the float instantiation takes the tracked/lost decisions in
+// the same precision as the GPU kernels (the workloads fix FP32), the double
+// instantiation serves the closed-form and brute-force pins.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace orc {
+
+// ----------------------------------------------------------------------------
+// Images
+// ----------------------------------------------------------------------------
+struct Img {
+  int w = 0, h = 0;
+  std::vector<uint8_t> p;
+  int at(int x, int y) const { return p[(size_t)y * w + x]; }
+};
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ----------------------------------------------------------------------------
+// Pyramid, Sec. III-C, eqs. (1)-(3).
+// Horizontal pass V(x, y) = sum_i w_i L(2x+i, y), then vertical pass
+// L'(x, y) = (sum_j w_j V(x, 2y+j) + 128) >> 8 with w = [1 4 6 4 1].
+// Reading: eq. (1) rounds to nearest and eq. (3) shifts; the +128 bias before
+// the shift satisfies both (round half up). Taps outside the image are clamped
+// to the edge. The next level has floor(W/2) x floor(H/2) pixels.
+// ----------------------------------------------------------------------------
+static const int BINOM[5] = {1, 4, 6, 4, 1};
+
+Img downsample(const Img& s) {
+  Img d;
+  d.w = s.w / 2;
+  d.h = s.h / 2;
+  d.p.assign((size_t)d.w * d.h, 0);
+  // eq. (2): V has d.w columns and s.h rows
+  std::vector<uint32_t> V((size_t)d.w * s.h);
+  for (int y = 0; y < s.h; ++y)
+    for (int x = 0; x < d.w; ++x) {
+      uint32_t acc = 0;
+      for (int i = -2; i <= 2; ++i) acc += BINOM[i + 2] * s.at(clampi(2 * x + i, 0, s.w - 1), y);
+      V[(size_t)y * d.w + x] = acc;
+    }
+  // eq. (3)
+  for (int y = 0; y < d.h; ++y)
+    for (int x = 0; x < d.w; ++x) {
+      uint32_t acc = 0;
+      for (int j = -2; j <= 2; ++j) acc += BINOM[j + 2] * V[(size_t)clampi(2 * y + j, 0, s.h - 1) * d.w + x];
+      d.p[(size_t)y * d.w + x] = (uint8_t)((acc + 128) >> 8);
+    }
+  return d;
+}
+
+std::vector<Img> pyramid(const Img& l0, int L) {
+  std::vector<Img> pyr{l0};
+  for (int l = 1; l < L; ++l) pyr.push_back(downsample(pyr.back()));
+  return pyr;
+}
+
+// ----------------------------------------------------------------------------
+// FAST-9 score, Sec. III-D. A pixel is a corner at threshold tau if at least 9
+// contiguous pixels of the 16-pixel Bresenham circle of radius 3 are all
+// brighter than I(p)+tau or all darker than I(p)-tau; the score is the largest
+// such tau. With strict inequalities and integer tau this is
+//   m = max over polarity and arc start of min over the 9 arc pixels of the
+//       signed difference, score = max(m - 1, -1)  (-1: no tau >= 0 works).
+// Circle order: start at (0,-3) and go clockwise (x right, y down).
+// ----------------------------------------------------------------------------
+static const int CIRCLE[16][2] = {{0, -3}, {1, -3}, {2, -2}, {3, -1}, {3, 0},  {3, 1},  {2, 2},   {1, 3},
+                                  {0, 3},  {-1, 3}, {-2, 2}, {-3, 1}, {-3, 0}, {-3, -1}, {-2, -2}, {-1, -3}};
+
+int fast_score(const Img& I, int x, int y) {
+  const int c = I.at(x, y);
+  int d[16];
+  for (int k = 0; k < 16; ++k) d[k] = I.at(x + CIRCLE[k][0], y + CIRCLE[k][1]) - c;
+  int best = std::numeric_limits<int>::min();
+  for (int pol = 0; pol < 2; ++pol)
+    for (int s = 0; s < 16; ++s) {
+      int m = std::numeric_limits<int>::max();
+      for (int k = 0; k < 9; ++k) {
+        const int v = pol == 0 ? d[(s + k) % 16] : -d[(s + k) % 16];
+        m = std::min(m, v);
+      }
+      best = std::max(best, m);
+    }
+  return std::max(best - 1, -1);
+}
+
+// score map; pixels closer than 3 px to the border have no score (INT_MIN)
+std::vector<int> score_map(const Img& I) {
+  std::vector<int> S((size_t)I.w * I.h, std::numeric_limits<int>::min());
+  for (int y = 3; y < I.h - 3; ++y)
+    for (int x = 3; x < I.w - 3; ++x) S[(size_t)y * I.w + x] = fast_score(I, x, y);
+  return S;
+}
+
+// ----------------------------------------------------------------------------
+// Grid detection, Sec. III-D. Cells of C x C pixels from (0,0), row-major,
+// partial cells included. Per cell the threshold sequence is walked in order;
+// at each threshold the survivors of a strict 3x3 non-maximum suppression with
+// score >= threshold are ranked by (score desc, y asc, x asc) and the first k
+// kept; the walk stops once k are found. Candidates keep an edge margin E.
+// ----------------------------------------------------------------------------
+struct Corner {
+  int x, y, score;
+};
+
+static bool nms_survivor(const std::vector<int>& S, int w, int x, int y) {
+  const int s = S[(size_t)y * w + x];
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      if (!dx && !dy) continue;
+      if (!(s > S[(size_t)(y + dy) * w + x + dx])) return false;
+    }
+  return true;
+}
+
+static bool corner_before(const Corner& a, const Corner& b) {
+  if (a.score != b.score) return a.score > b.score;
+  if (a.y != b.y) return a.y < b.y;
+  return a.x < b.x;
+}
+
+// winners[cell] = up to k corners in rank order
+std::vector<std::vector<Corner>> detect_cells(const Img& I, int C, int k, const int* thr, int nthr, int E,
+                                              bool single_pass) {
+  const std::vector<int> S = score_map(I);
+  const int ncx = (I.w + C - 1) / C, ncy = (I.h + C - 1) / C;
+  std::vector<std::vector<Corner>> win((size_t)ncx * ncy);
+  for (int cy = 0; cy < ncy; ++cy)
+    for (int cx = 0; cx < ncx; ++cx) {
+      const int x0 = std::max(cx * C, E), x1 = std::min(cx * C + C - 1, I.w - 1 - E);
+      const int y0 = std::max(cy * C, E), y1 = std::min(cy * C + C - 1, I.h - 1 - E);
+      std::vector<Corner> kept;
+      for (int ti = single_pass ? nthr - 1 : 0; ti < nthr; ++ti) {
+        std::vector<Corner> surv;
+        for (int y = y0; y <= y1; ++y)
+          for (int x = x0; x <= x1; ++x) {
+            const int s = S[(size_t)y * I.w + x];
+            if (s >= thr[ti] && nms_survivor(S, I.w, x, y)) surv.push_back({x, y, s});
+          }
+        std::sort(surv.begin(), surv.end(), corner_before);
+        if ((int)surv.size() > k) surv.resize(k);
+        kept = surv;
+        if ((int)kept.size() >= k) break;
+      }
+      win[(size_t)cy * ncx + cx] = kept;
+    }
+  return win;
+}
+
+// ----------------------------------------------------------------------------
+// Patch tracker, Sec. III-E, eqs. (4)-(5).
+// Pattern: 52 half-integer offsets (u, v) in {+-0.5 .. +-3.5}^2 with
+// u^2 + v^2 <= 16, ordered by v then u.
+// ----------------------------------------------------------------------------
+struct Pattern {
+  float u[52], v[52];
+  Pattern() {
+    int n = 0;
+    for (int j = 0; j < 8; ++j)
+      for (int i = 0; i < 8; ++i) {
+        const float uu = -3.5f + i, vv = -3.5f + j;
+        if (uu * uu + vv * vv <= 16.0f) {
+          u[n] = uu;
+          v[n] = vv;
+          ++n;
+        }
+      }
+  }
+};
+static const Pattern PAT;
+
+enum Status { TRACKED = 0, DETECTED = 1, MATCHED = 2, LOST_FB = 3, LOST_OOB = 4, LOST_DEGENERATE = 5, LOST_CAP = 6 };
+
+template <class R>
+static bool in_domain(const Img& I, R x, R y) {
+  return x >= R(0) && x <= R(I.w - 1) && y >= R(0) && y <= R(I.h - 1);
+}
+
+// bilinear interpolation, defined on [0, W-1] x [0, H-1]
+template <class R>
+static R bilinear(const Img& I, R x, R y) {
+  const int ix = std::min((int)std::floor(x), I.w - 2), iy = std::min((int)std::floor(y), I.h - 2);
+  const R fx = x - R(ix), fy = y - R(iy);
+  const R a = R(I.at(ix, iy)), b = R(I.at(ix + 1, iy)), c = R(I.at(ix, iy + 1)), d = R(I.at(ix + 1, iy + 1));
+  return (R(1) - fy) * ((R(1) - fx) * a + fx * b) + fy * ((R(1) - fx) * c + fx * d);
+}
+
+template <class R>
+struct Template {
+  bool fits = false, valid = false;
+  R T[52], G[52][3];
+  R H[3][3], Hinv[3][3];
+};
+
+// 3x3 inverse by cofactors; returns the determinant
+template <class R>
+static R inverse3(const R m[3][3], R inv[3][3]) {
+  const R c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+  const R c01 = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+  const R c02 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+  const R det = m[0][0] * c00 + m[0][1] * c01 + m[0][2] * c02;
+  const R id = R(1) / det;
+  inv[0][0] = c00 * id;
+  inv[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+  inv[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+  inv[1][0] = c01 * id;
+  inv[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+  inv[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+  inv[2][0] = c02 * id;
+  inv[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+  inv[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
+  return det;
+}
+
+// Template on image I at (px, py): samples I_i = I(p + x_i), gradient by central
+// differences of bilinear samples at +-1 px, mean-normalised (Sec. III-E):
+// T_i = I_i / mean, g_i = grad I_i / mean, J_i = [gx, gy, gy u_i - gx v_i],
+// H = sum J_i^T J_i, G_i = H^-1 J_i^T. Invalid if the mean is not positive,
+// H is near singular (det <= 1e-6 (tr/3)^3) or a gain is not finite.
+template <class R>
+static Template<R> make_template(const Img& I, R px, R py) {
+  Template<R> t;
+  R Iv[52], gx[52], gy[52];
+  for (int i = 0; i < 52; ++i) {
+    const R sx = px + R(PAT.u[i]), sy = py + R(PAT.v[i]);
+    if (!in_domain(I, sx - R(1), sy) || !in_domain(I, sx + R(1), sy) || !in_domain(I, sx, sy - R(1)) ||
+        !in_domain(I, sx, sy + R(1)))
+      return t;
+  }
+  t.fits = true;
+  for (int i = 0; i < 52; ++i) {
+    const R sx = px + R(PAT.u[i]), sy = py + R(PAT.v[i]);
+    Iv[i] = bilinear(I, sx, sy);
+    gx[i] = (bilinear(I, sx + R(1), sy) - bilinear(I, sx - R(1), sy)) / R(2);
+    gy[i] = (bilinear(I, sx, sy + R(1)) - bilinear(I, sx, sy - R(1))) / R(2);
+  }
+  R sum = 0;
+  for (int i = 0; i < 52; ++i) sum += Iv[i];
+  const R mean = sum / R(52);
+  if (!(mean > R(0))) return t;
+  R J[52][3];
+  for (int i = 0; i < 52; ++i) {
+    t.T[i] = Iv[i] / mean;
+    const R nx = gx[i] / mean, ny = gy[i] / mean;
+    J[i][0] = nx;
+    J[i][1] = ny;
+    J[i][2] = ny * R(PAT.u[i]) - nx * R(PAT.v[i]);
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      R s = 0;
+      for (int i = 0; i < 52; ++i) s += J[i][a] * J[i][b];
+      t.H[a][b] = s;
+    }
+  const R det = inverse3(t.H, t.Hinv);
+  const R tr3 = (t.H[0][0] + t.H[1][1] + t.H[2][2]) / R(3);
+  if (!(det > R(1e-6) * tr3 * tr3 * tr3)) return t;
+  for (int i = 0; i < 52; ++i)
+    for (int a = 0; a < 3; ++a) {
+      t.G[i][a] = t.Hinv[a][0] * J[i][0] + t.Hinv[a][1] * J[i][1] + t.Hinv[a][2] * J[i][2];
+      if (!std::isfinite(t.G[i][a])) return t;
+    }
+  t.valid = true;
+  return t;
+}
+
+// SE(2) exponential of (a, b, phi): rotation phi, translation V(phi) (a, b)
+template <class R>
+static void se2_exp(R a, R b, R phi, R& tx, R& ty) {
+  R s, c;
+  if (std::fabs(phi) < R(1e-4)) {
+    s = R(1) - phi * phi / R(6);
+    c = phi / R(2);
+  } else {
+    s = std::sin(phi) / phi;
+    c = (R(1) - std::cos(phi)) / phi;
+  }
+  tx = s * a - c * b;
+  ty = c * a + s * b;
+}
+
+template <class R>
+struct Pose {
+  R tx, ty, th;
+};
+
+template <class R>
+struct PassOut {
+  int status = TRACKED;
+  Pose<R> T{};
+  R resid = 0;
+  R last_step = 0;
+};
+
+// One coarse-to-fine pass (Sec. III-E): template on `src` at p, warp
+// initialised at `init` (level-0 position and rotation), exactly N Gauss-Newton
+// iterations per level from level L-1 to 0 with t doubled between levels. A
+// level whose template does not fit the image is skipped (level 0: LOST_OOB).
+// Iteration (eqs. 4-5): x'_i = R(th) x_i + t; e_i = I'(x'_i)/mean' - T_i;
+// delta = -sum_i G_i e_i; T <- T o exp(delta).
+template <class R>
+static PassOut<R> klt_pass(const std::vector<Img>& src, const std::vector<Img>& dst, R px, R py, Pose<R> init,
+                           int L, int N) {
+  PassOut<R> o;
+  R tx = std::ldexp(init.tx, -(L - 1)), ty = std::ldexp(init.ty, -(L - 1)), th = init.th;
+  for (int l = L - 1; l >= 0; --l) {
+    if (l < L - 1) {
+      tx = tx * R(2);
+      ty = ty * R(2);
+    }
+    const Template<R> tm = make_template(src[l], std::ldexp(px, -l), std::ldexp(py, -l));
+    if (!tm.fits) {
+      if (l == 0) {
+        o.status = LOST_OOB;
+        return o;
+      }
+      continue;
+    }
+    if (!tm.valid) {
+      o.status = LOST_DEGENERATE;
+      return o;
+    }
+    const Img& I = dst[l];
+    for (int it = 0; it < N; ++it) {
+      const R c = std::cos(th), s = std::sin(th);
+      R Iw[52];
+      for (int i = 0; i < 52; ++i) {
+        const R wx = (c * R(PAT.u[i]) - s * R(PAT.v[i])) + tx;
+        const R wy = (s * R(PAT.u[i]) + c * R(PAT.v[i])) + ty;
+        if (!in_domain(I, wx, wy)) {
+          o.status = LOST_OOB;
+          return o;
+        }
+        Iw[i] = bilinear(I, wx, wy);
+      }
+      R sum = 0;
+      for (int i = 0; i < 52; ++i) sum += Iw[i];
+      const R mean = sum / R(52);
+      if (!(mean > R(0))) {
+        o.status = LOST_OOB;
+        return o;
+      }
+      R d0 = 0, d1 = 0, d2 = 0, ss = 0;
+      for (int i = 0; i < 52; ++i) {
+        const R e = Iw[i] / mean - tm.T[i];
+        d0 -= tm.G[i][0] * e;
+        d1 -= tm.G[i][1] * e;
+        d2 -= tm.G[i][2] * e;
+        ss += e * e;
+      }
+      if (l == 0 && it == N - 1) o.resid = std::sqrt(ss / R(52));
+      R vx, vy;
+      se2_exp(d0, d1, d2, vx, vy);
+      tx = tx + (c * vx - s * vy);
+      ty = ty + (s * vx + c * vy);
+      th = th + d2;
+      o.last_step = std::sqrt(d0 * d0 + d1 * d1);
+    }
+  }
+  o.T = {tx, ty, th};
+  return o;
+}
+
+template <class R>
+struct TrackOut {
+  int status;
+  R x, y, th, fb, resid;
+};
+
+// Forward-backward tracking (Sec. III-E, Fig. 4). The backward pass rebuilds
+// the template on the target at the forward result and starts from the inverse
+// of the forward motion (position p, rotation -theta); the track is lost when
+// the returned position is farther than fb_thr from p.
+template <class R>
+static TrackOut<R> track(const std::vector<Img>& src, const std::vector<Img>& dst, R px, R py, R ix, R iy, int L,
+                         int N, R fb_thr) {
+  TrackOut<R> r{TRACKED, ix, iy, 0, 0, 0};
+  const PassOut<R> f = klt_pass<R>(src, dst, px, py, {ix, iy, R(0)}, L, N);
+  if (f.status != TRACKED) {
+    r.status = f.status;
+    return r;
+  }
+  r.x = f.T.tx;
+  r.y = f.T.ty;
+  r.th = f.T.th;
+  r.resid = f.resid;
+  const PassOut<R> b = klt_pass<R>(dst, src, f.T.tx, f.T.ty, {px, py, -f.T.th}, L, N);
+  if (b.status != TRACKED) {
+    r.status = b.status;
+    return r;
+  }
+  const R dx = b.T.tx - px, dy = b.T.ty - py;
+  r.fb = std::sqrt(dx * dx + dy * dy);
+  r.status = r.fb > fb_thr ? LOST_FB : TRACKED;
+  return r;
+}
+
+// ----------------------------------------------------------------------------
+// Frontend pipeline per frame (Sec. III-B): pyramid, temporal tracking of every
+// camera's live keypoints, detection on the first camera of each mono camera or
+// stereo pair with cells masked by surviving tracks, stereo matching of the new
+// detections into the second camera of the pair.
+// ----------------------------------------------------------------------------
+struct Params {
+  uint32_t struct_size;
+  int32_t levels, gn_iters, cell_size, k_per_cell, n_thresholds;
+  int32_t thresholds[4];
+  int32_t edge_margin, max_keypoints;
+  float fb_threshold, disparity0;
+};
+
+struct Record {  // 40 bytes
+  int64_t id;
+  float x, y, theta, fb_err, resid_rms;
+  int32_t age;
+  int16_t camera, status;
+  int32_t score;
+};
+static_assert(sizeof(Record) == 40, "record layout");
+
+struct Keypoint {
+  int64_t id;
+  float x, y, px, py;
+  int32_t age;
+};
+
+struct Camera {
+  int w, h;
+  std::vector<Img> prev;
+  bool has_prev = false;
+  std::vector<Keypoint> live;  // ascending id
+};
+
+struct Frontend {
+  Params P;
+  int n_cams;
+  bool stereo;
+  std::vector<Camera> cams;
+  int64_t next_id = 0;
+  std::vector<Record> records;
+};
+
+static Record make_record(int64_t id, int cam, int status, float x, float y, float th, float fb, float res,
+                          int age, int score) {
+  Record r;
+  r.id = id;
+  r.camera = (int16_t)cam;
+  r.status = (int16_t)status;
+  r.x = x;
+  r.y = y;
+  r.theta = th;
+  r.fb_err = fb;
+  r.resid_rms = res;
+  r.age = age;
+  r.score = score;
+  return r;
+}
+
+static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* strides) {
+  const Params& P = F.P;
+  const int L = P.levels, N = P.gn_iters;
+  std::vector<std::vector<Img>> cur(F.n_cams);
+  for (int c = 0; c < F.n_cams; ++c) {
+    Img l0;
+    l0.w = F.cams[c].w;
+    l0.h = F.cams[c].h;
+    l0.p.resize((size_t)l0.w * l0.h);
+    for (int y = 0; y < l0.h; ++y) std::memcpy(&l0.p[(size_t)y * l0.w], imgs[c] + (size_t)y * strides[c], l0.w);
+    cur[c] = pyramid(l0, L);
+  }
+  F.records.clear();
+  std::vector<std::vector<Record>> rec(F.n_cams);
+  // temporal tracking with the constant-velocity initialisation; a camera with
+  // no previous frame carries its keypoints over unchanged (nothing to track
+  // against) and reports no temporal records
+  for (int c = 0; c < F.n_cams; ++c) {
+    Camera& cam = F.cams[c];
+    if (!cam.has_prev) continue;
+    std::vector<Keypoint> surv;
+    {
+      for (const Keypoint& k : cam.live) {
+        const float ix = k.x + (k.x - k.px), iy = k.y + (k.y - k.py);
+        const TrackOut<float> r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, L, N, P.fb_threshold);
+        if (r.status == TRACKED) {
+          surv.push_back({k.id, r.x, r.y, k.x, k.y, k.age + 1});
+          rec[c].push_back(make_record(k.id, c, TRACKED, r.x, r.y, r.th, r.fb, r.resid, k.age + 1, -1));
+        } else {
+          rec[c].push_back(make_record(k.id, c, r.status, r.x, r.y, r.th, r.fb, r.resid, k.age, -1));
+        }
+      }
+    }
+    cam.live = surv;
+  }
+  // detection, selection and stereo matching per mono camera / stereo pair
+  const int group = F.stereo ? 2 : 1;
+  for (int g = 0; g < F.n_cams; g += group) {
+    Camera& left = F.cams[g];
+    const Img& I0 = cur[g][0];
+    const int C = P.cell_size, k = P.k_per_cell;
+    const auto win = detect_cells(I0, C, k, P.thresholds, P.n_thresholds, P.edge_margin, false);
+    const int ncx = (I0.w + C - 1) / C, ncy = (I0.h + C - 1) / C;
+    std::vector<int> occ((size_t)ncx * ncy, 0);
+    for (const Keypoint& kp : left.live) {
+      const int cx = (int)std::floor(kp.x / (float)C), cy = (int)std::floor(kp.y / (float)C);
+      if (cx >= 0 && cx < ncx && cy >= 0 && cy < ncy) occ[(size_t)cy * ncx + cx]++;
+    }
+    struct Cand {
+      int cell, rank;
+      Corner c;
+    };
+    std::vector<Cand> cand;
+    for (int cell = 0; cell < ncx * ncy; ++cell) {
+      if (occ[cell] >= k) continue;
+      for (int r = 0; r < (int)win[cell].size(); ++r) cand.push_back({cell, r, win[cell][r]});
+    }
+    // global cap: keep the best (score desc, cell asc, rank asc)
+    std::sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+      if (a.c.score != b.c.score) return a.c.score > b.c.score;
+      if (a.cell != b.cell) return a.cell < b.cell;
+      return a.rank < b.rank;
+    });
+    const int room = std::max(0, P.max_keypoints - (int)left.live.size());
+    if ((int)cand.size() > room) cand.resize(room);
+    // identifiers in cell order
+    std::sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+      if (a.cell != b.cell) return a.cell < b.cell;
+      return a.rank < b.rank;
+    });
+    std::vector<Keypoint> fresh;
+    for (const Cand& cd : cand) {
+      const Keypoint kp{F.next_id++, (float)cd.c.x, (float)cd.c.y, (float)cd.c.x, (float)cd.c.y, 0};
+      fresh.push_back(kp);
+      left.live.push_back(kp);
+      rec[g].push_back(make_record(kp.id, g, DETECTED, kp.x, kp.y, 0, 0, 0, 0, cd.c.score));
+    }
+    if (F.stereo) {
+      Camera& right = F.cams[g + 1];
+      for (const Keypoint& kp : fresh) {
+        const float ix = kp.x - P.disparity0, iy = kp.y;
+        const TrackOut<float> r = track<float>(cur[g], cur[g + 1], kp.x, kp.y, ix, iy, L, N, P.fb_threshold);
+        int st = r.status == TRACKED ? MATCHED : r.status;
+        if (st == MATCHED && (int)right.live.size() >= P.max_keypoints) st = LOST_CAP;
+        if (st == MATCHED) right.live.push_back({kp.id, r.x, r.y, r.x, r.y, 0});
+        rec[g + 1].push_back(make_record(kp.id, g + 1, st, r.x, r.y, r.th, r.fb, r.resid, 0, -1));
+      }
+    }
+  }
+  for (int c = 0; c < F.n_cams; ++c) {
+    F.cams[c].prev = cur[c];
+    F.cams[c].has_prev = true;
+    F.records.insert(F.records.end(), rec[c].begin(), rec[c].end());
+  }
+}
+
+}  // namespace orc
+
+// ============================================================================
+// C ABI for the test suite
+// ============================================================================
+using namespace orc;
+
+extern "C" {
+
+static Img make_img(const uint8_t* p, int w, int h) {
+  Img I;
+  I.w = w;
+  I.h = h;
+  I.p.assign(p, p + (size_t)w * h);
+  return I;
+}
+
+// Levels 0..L-1 packed one after another (level l is floor(W/2^l) x floor(H/2^l)).
+int orc_pyramid(const uint8_t* img, int w, int h, int L, uint8_t* out) {
+  if (!img || !out || w < 2 || h < 2 || L < 1) return -1;
+  const auto pyr = pyramid(make_img(img, w, h), L);
+  size_t off = 0;
+  for (const Img& I : pyr) {
+    std::memcpy(out + off, I.p.data(), I.p.size());
+    off += I.p.size();
+  }
+  return 0;
+}
+
+// FAST score of every pixel at least 3 px from the border; INT32_MIN elsewhere.
+int orc_fast_scores(const uint8_t* img, int w, int h, int32_t* out) {
+  if (!img || !out || w < 7 || h < 7) return -1;
+  const auto S = score_map(make_img(img, w, h));
+  std::memcpy(out, S.data(), S.size() * sizeof(int32_t));
+  return 0;
+}
+
+// Per-cell winners: out[(cell * k + r) * 3 + {0,1,2}] = x, y, score (-1 = none).
+int orc_detect(const uint8_t* img, int w, int h, int C, int k, const int32_t* thr, int nthr, int E,
+               int single_pass, int32_t* out) {
+  if (!img || !out || !thr || C < 1 || k < 1 || nthr < 1) return -1;
+  const auto win = detect_cells(make_img(img, w, h), C, k, thr, nthr, E, single_pass != 0);
+  for (size_t cell = 0; cell < win.size(); ++cell)
+    for (int r = 0; r < k; ++r) {
+      int32_t* o = out + (cell * k + r) * 3;
+      if (r < (int)win[cell].size()) {
+        o[0] = win[cell][r].x;
+        o[1] = win[cell][r].y;
+        o[2] = win[cell][r].score;
+      } else {
+        o[0] = o[1] = o[2] = -1;
+      }
+    }
+  return 0;
+}
+
+// Forward-backward tracking of n keypoints from the pyramid of `src` to that of
+// `dst` (both level-0 images w x h). double_prec selects the FP64 instantiation.
+// out_f[i*5 + {0..4}] = x, y, theta, fb, resid; out_status[i].
+int orc_track(const uint8_t* src, const uint8_t* dst, int w, int h, int L, int N, double fb_thr, int n,
+              const double* px, const double* py, const double* ix, const double* iy, int double_prec,
+              double* out_f, int32_t* out_status) {
+  if (!src || !dst || L < 1 || N < 0 || n < 0) return -1;
+  const auto S = pyramid(make_img(src, w, h), L), D = pyramid(make_img(dst, w, h), L);
+  for (int i = 0; i < n; ++i) {
+    if (double_prec) {
+      const auto r = track<double>(S, D, px[i], py[i], ix[i], iy[i], L, N, fb_thr);
+      out_status[i] = r.status;
+      const double v[5] = {r.x, r.y, r.th, r.fb, r.resid};
+      std::memcpy(out_f + 5 * i, v, sizeof v);
+    } else {
+      const auto r = track<float>(S, D, (float)px[i], (float)py[i], (float)ix[i], (float)iy[i], L, N,
+                                  (float)fb_thr);
+      out_status[i] = r.status;
+      const double v[5] = {r.x, r.y, r.th, r.fb, r.resid};
+      std::memcpy(out_f + 5 * i, v, sizeof v);
+    }
+  }
+  return 0;
+}
+
+// One coarse-to-fine forward pass only (no backward check), FP64.
+// out[i*6 + {0..5}] = tx, ty, theta, resid, last_step, status
+int orc_klt_pass(const uint8_t* src, const uint8_t* dst, int w, int h, int L, int N, int n, const double* px,
+                 const double* py, const double* ix, const double* iy, const double* ith, double* out) {
+  if (!src || !dst || L < 1 || N < 0) return -1;
+  const auto S = pyramid(make_img(src, w, h), L), D = pyramid(make_img(dst, w, h), L);
+  for (int i = 0; i < n; ++i) {
+    const auto r = klt_pass<double>(S, D, px[i], py[i], {ix[i], iy[i], ith[i]}, L, N);
+    const double v[6] = {r.T.tx, r.T.ty, r.T.th, r.resid, r.last_step, (double)r.status};
+    std::memcpy(out + 6 * i, v, sizeof v);
+  }
+  return 0;
+}
+
+// Template quantities at one point of a single image (no pyramid), FP64:
+// out[0..8] = H, out[9..17] = H^-1, out[18] = fits, out[19] = valid.
+int orc_template(const uint8_t* img, int w, int h, double px, double py, double* out) {
+  const Img I = make_img(img, w, h);
+  const auto t = make_template<double>(I, px, py);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      out[3 * a + b] = t.H[a][b];
+      out[9 + 3 * a + b] = t.Hinv[a][b];
+    }
+  out[18] = t.fits;
+  out[19] = t.valid;
+  return 0;
+}
+
+int orc_pattern(float* u, float* v) {
+  for (int i = 0; i < 52; ++i) {
+    u[i] = PAT.u[i];
+    v[i] = PAT.v[i];
+  }
+  return 52;
+}
+
+// SE(2) exponential (a, b, phi) -> translation part; FP64.
+void orc_se2_exp(double a, double b, double phi, double* tx, double* ty) { se2_exp<double>(a, b, phi, *tx, *ty); }
+
+double orc_inverse3(const double* m, double* inv) {
+  double M[3][3], I[3][3];
+  for (int i = 0; i < 9; ++i) M[i / 3][i % 3] = m[i];
+  const double det = inverse3<double>(M, I);
+  for (int i = 0; i < 9; ++i) inv[i] = I[i / 3][i % 3];
+  return det;
+}
+
+// ---- frontend --------------------------------------------------------------
+void* orc_fe_create(int n_cams, const int32_t* widths, const int32_t* heights, int stereo, const Params* p) {
+  if (!p || p->struct_size != sizeof(Params) || n_cams < 1 || (stereo && n_cams % 2)) return nullptr;
+  auto* F = new Frontend();
+  F->P = *p;
+  F->n_cams = n_cams;
+  F->stereo = stereo != 0;
+  F->cams.resize(n_cams);
+  for (int c = 0; c < n_cams; ++c) {
+    F->cams[c].w = widths[c];
+    F->cams[c].h = heights[c];
+  }
+  return F;
+}
+
+void orc_fe_destroy(void* h) { delete static_cast<Frontend*>(h); }
+
+int orc_fe_push(void* h, const uint8_t* const* imgs, const int32_t* strides) {
+  if (!h || !imgs || !strides) return -1;
+  push_frame(*static_cast<Frontend*>(h), imgs, strides);
+  return 0;
+}
+
+int orc_fe_get(void* h, Record* out, int capacity, int* n_out) {
+  auto* F = static_cast<Frontend*>(h);
+  if (!F || !n_out) return -1;
+  *n_out = (int)F->records.size();
+  if (capacity < (int)F->records.size()) return -4;
+  std::memcpy(out, F->records.data(), F->records.size() * sizeof(Record));
+  return 0;
+}
+
+// Replace camera `cam`'s live keypoints (id, x, y, px, py, age per entry, ids
+// ascending) -- the keypoint state the host uploads before a frame.
+int orc_fe_set_keypoints(void* h, int cam, int n, const int64_t* id, const float* xy_pxy, const int32_t* age) {
+  auto* F = static_cast<Frontend*>(h);
+  if (!F || cam < 0 || cam >= F->n_cams || n < 0) return -1;
+  std::vector<Keypoint> kps;
+  for (int i = 0; i < n; ++i) {
+    kps.push_back({id[i], xy_pxy[4 * i], xy_pxy[4 * i + 1], xy_pxy[4 * i + 2], xy_pxy[4 * i + 3], age[i]});
+    F->next_id = std::max(F->next_id, id[i] + 1);
+  }
+  F->cams[cam].live = kps;
+  return 0;
+}
+
+int orc_fe_get_keypoints(void* h, int cam, int capacity, int64_t* id, float* xy_pxy, int32_t* age) {
+  auto* F = static_cast<Frontend*>(h);
+  if (!F || cam < 0 || cam >= F->n_cams) return -1;
+  const auto& L = F->cams[cam].live;
+  if ((int)L.size() > capacity) return -(int)L.size();
+  for (size_t i = 0; i < L.size(); ++i) {
+    id[i] = L[i].id;
+    xy_pxy[4 * i] = L[i].x;
+    xy_pxy[4 * i + 1] = L[i].y;
+    xy_pxy[4 * i + 2] = L[i].px;
+    xy_pxy[4 * i + 3] = L[i].py;
+    age[i] = L[i].age;
+  }
+  return (int)L.size();
+}
+
+int64_t orc_fe_next_id(void* h) { return static_cast<Frontend*>(h)->next_id; }
+
+}  // extern "C"
