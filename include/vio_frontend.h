@@ -1,0 +1,211 @@
+/*
+ * vio_frontend.h -- C ABI of the MI355X (gfx950) stereo VIO frontend.
+ *
+ * The frontend is the data-parallel half of a visual-inertial odometry
+ * pipeline as stated in VkVIO (arXiv 2609.30459), Sec. III-B: per frame it
+ *   1. builds an image pyramid per camera (Sec. III-C, eqs. 1-3),
+ *   2. tracks every camera's previous keypoints KP_{t-1} into the new frame with
+ *      inverse-compositional SE(2) patch alignment and a forward-backward check
+ *      (Sec. III-E, eqs. 4-5),
+ *   3. detects FAST-9 corners on a grid of cells with 3x3 non-maximum
+ *      suppression, masking cells that still hold a track (Sec. III-D),
+ *   4. matches the new detections of each stereo pair's left camera into its
+ *      right camera with the same tracker (Sec. III-B, "cross-camera matching"),
+ * and hands back the tracked/matched positions (TR_t) and the new detections
+ * (DET_t) after one synchronous submit and wait (Sec. III-B, Fig. 2).
+ *
+ * Conventions
+ *  - Every call returns VIO_OK (0) or a negative vio_result. No C++ exception
+ *    crosses this boundary. On any error other than VIO_EDEVICE the handle is
+ *    unchanged. VIO_EDEVICE (a HIP runtime error) poisons the handle: every
+ *    later call except destroy/last_error returns VIO_EDEVICE.
+ *  - A handle is single-threaded; separate handles are independent.
+ *  - The library owns the handle and all device memory, allocated once in
+ *    vio_frontend_create (Sec. III-B: resources are allocated at
+ *    initialisation and reused every frame). Pointers passed in are borrowed
+ *    for the duration of the call only.
+ *  - Pixel coordinates are level-0 pixels, origin at the centre of the top-left
+ *    pixel, x to the right, y down.
+ */
+#ifndef VIO_FRONTEND_H
+#define VIO_FRONTEND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VIO_MAX_LEVELS 6
+#define VIO_MAX_CAMERAS 64
+
+typedef enum vio_result {
+  VIO_OK = 0,
+  VIO_EINVAL = -1,       /* null pointer, bad size, unknown stream or camera */
+  VIO_ENOMEM = -2,       /* device or pinned host allocation failed */
+  VIO_EDEVICE = -3,      /* HIP runtime error; the handle is poisoned */
+  VIO_ETOOSMALL = -4,    /* output capacity too small; *n_out holds the count needed */
+  VIO_ESTATE = -5,       /* call out of order (e.g. get before any push, timestamps not increasing) */
+  VIO_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} vio_result;
+
+/* Per-record status. */
+typedef enum vio_status {
+  VIO_TRACKED = 0,         /* temporal track kept (passed the forward-backward check) */
+  VIO_DETECTED = 1,        /* new keypoint detected in this frame (left / mono camera) */
+  VIO_MATCHED = 2,         /* new keypoint matched into the right camera of its pair */
+  VIO_LOST_FB = 3,         /* forward-backward distance above the threshold */
+  VIO_LOST_OOB = 4,        /* the patch left the image */
+  VIO_LOST_DEGENERATE = 5, /* template Hessian near singular or patch mean not positive */
+  VIO_LOST_CAP = 6         /* stereo match dropped: the right camera is full */
+} vio_status;
+
+typedef enum vio_init_mode {
+  VIO_INIT_CONST_VEL = 0, /* p + (p - p_prev); the caller's predictions override it */
+  VIO_INIT_LEARNED = 1    /* learned displacement guess refined by the tracker */
+} vio_init_mode;
+
+/* One input stream: a mono camera, a stereo pair (cameras 0,1), or two stereo
+ * pairs (0,1) and (2,3). All cameras of a stream share the image size. */
+typedef struct vio_stream_desc {
+  int32_t n_cameras;     /* 1, 2 or 4 */
+  int32_t width, height; /* level-0 size in pixels, 16..4096 each, width*height < 2^24 */
+  int32_t max_keypoints; /* per camera; 0 = take vio_frontend_params.max_keypoints */
+  int32_t cell_size;     /* detection cell edge in px; 0 = take vio_frontend_params.cell_size */
+} vio_stream_desc;
+
+/* Frontend parameters (versioned by struct_size). Defaults: see
+ * vio_frontend_default_params. */
+typedef struct vio_frontend_params {
+  uint32_t struct_size;   /* sizeof(vio_frontend_params) */
+  int32_t levels;         /* pyramid levels L including level 0, 1..VIO_MAX_LEVELS (Sec. III-C) */
+  int32_t gn_iters;       /* Gauss-Newton iterations per level N, 1..32 (Sec. III-E) */
+  int32_t cell_size;      /* default cell edge C in px (Sec. III-D) */
+  int32_t k_per_cell;     /* keypoints per cell; this build implements k = 1 (Sec. III-D) */
+  int32_t n_thresholds;   /* 1..4 */
+  int32_t thresholds[4];  /* FAST threshold walk, e.g. 40, 20, 10, 5 (Sec. III-D) */
+  int32_t edge_margin;    /* detections keep this distance to the border, >= 4 px */
+  int32_t max_keypoints;  /* default per-camera keypoint cap */
+  float fb_threshold;     /* forward-backward distance limit in px (Sec. III-E) */
+  float disparity0;       /* stereo initialisation: right = left - (disparity0, 0) */
+  int32_t init_mode;      /* vio_init_mode */
+  int32_t learned_levels; /* tracker budget when the learned guess is used */
+  int32_t learned_iters;
+  float learned_rho;      /* residual RMS above which a learned track falls back to the plain tracker */
+} vio_frontend_params;
+
+/* Output record: one per previous keypoint of each camera (tracked or lost) and
+ * one per new detection / stereo match, sorted by (camera, id). */
+typedef struct vio_track {
+  int64_t id;       /* keypoint identifier, shared by a left keypoint and its right match */
+  float x, y;       /* level-0 position in this frame (forward result for tracks) */
+  float theta;      /* estimated in-plane patch rotation, radians */
+  float fb_err;     /* forward-backward distance, px (0 for detections) */
+  float resid_rms;  /* RMS of the photometric residual at the last level-0 iteration */
+  int32_t age;      /* frames this keypoint has been tracked */
+  int16_t camera;   /* camera index within the stream */
+  int16_t status;   /* vio_status */
+  int32_t score;    /* FAST score for VIO_DETECTED, -1 otherwise */
+} vio_track;        /* 40 bytes */
+
+/* A live keypoint (the state KP_{t-1} the paper uploads from the host). */
+typedef struct vio_keypoint {
+  int64_t id;
+  float x, y;   /* position in the last frame */
+  float px, py; /* position one frame earlier (equal to x, y for a new keypoint) */
+  int32_t age;
+  int32_t reserved;
+} vio_keypoint;  /* 32 bytes */
+
+/* A caller-side prediction of a keypoint's position in the new frame (Sec.
+ * III-E: the backend projects the pattern through its predicted pose). It
+ * replaces the constant-velocity initialisation of that keypoint. */
+typedef struct vio_kp_prediction {
+  int64_t id;
+  int32_t camera;
+  float x, y;
+} vio_kp_prediction;
+
+typedef struct vio_stats {
+  int64_t frames;        /* frames processed by the handle */
+  double last_gpu_ms;    /* device time of the last frame (first kernel to last) */
+  double last_stage_ms[3]; /* HIP-event time of the last frame's pyramid+detector, tracker and
+                              selection kernels, on the stream they ran on */
+  int32_t last_tracked;  /* VIO_TRACKED records of the last frame, all cameras */
+  int32_t last_lost;     /* lost temporal records of the last frame */
+  int32_t last_detected; /* VIO_DETECTED records */
+  int32_t last_matched;  /* VIO_MATCHED records */
+} vio_stats;
+
+typedef struct vio_frontend vio_frontend;
+
+/* Fills *p with the paper's standard configuration: L = 4, N = 5, cells of 50
+ * px, k = 1, thresholds 40/20/10/5, margin 8, 300 keypoints, FB threshold 0.3
+ * px, disparity prior 32.5 px, constant-velocity init. */
+void vio_frontend_default_params(vio_frontend_params* p);
+
+/* Creates a frontend for n_streams streams (1..VIO_MAX_CAMERAS cameras in all).
+ * Allocates every device buffer and the pinned host staging here; nothing is
+ * allocated per frame. On success *out receives the handle (caller frees it
+ * with vio_frontend_destroy). Errors: VIO_EINVAL, VIO_ENOMEM, VIO_EDEVICE,
+ * VIO_EUNSUPPORTED (k_per_cell != 1, learned init without weights). */
+int vio_frontend_create(const vio_stream_desc* streams, int32_t n_streams, const vio_frontend_params* params,
+                        vio_frontend** out);
+
+/* Releases the handle and all its memory. NULL is a no-op. */
+void vio_frontend_destroy(vio_frontend* h);
+
+/* Processes one frame of `stream`: images[c] points to camera c's width x height
+ * uint8 image with row stride strides[c] bytes (host memory, read before the
+ * call returns). pred (n_pred entries, may be NULL when n_pred == 0) overrides
+ * the initialisation of the listed keypoints. t_ns must increase strictly per
+ * stream. Synchronous: returns once the frame's records are ready for
+ * vio_frontend_get_tracks. */
+int vio_frontend_push_stereo_frame(vio_frontend* h, int32_t stream, int64_t t_ns, const uint8_t* const* images,
+                                   const int32_t* strides, const vio_kp_prediction* pred, int32_t n_pred);
+
+/* As above with device-resident images: d_images[c] is a device pointer with
+ * row pitch pitches[c] bytes, read on `hip_stream` (a hipStream_t, NULL = the
+ * handle's own stream) during this call only. The frame runs on that stream. */
+int vio_frontend_push_stereo_frame_device(vio_frontend* h, int32_t stream, int64_t t_ns,
+                                          const void* const* d_images, const int32_t* pitches, void* hip_stream);
+
+/* Copies the last frame's records of `stream` into out[0..capacity). *n_out
+ * receives the record count; VIO_ETOOSMALL (nothing written) when capacity is
+ * smaller. VIO_ESTATE before the stream's first push. */
+int vio_frontend_get_tracks(vio_frontend* h, int32_t stream, vio_track* out, int32_t capacity, int32_t* n_out);
+
+/* Replaces camera `camera`'s live keypoints of `stream` with kps[0..n) (ids
+ * strictly ascending, n <= the camera's keypoint cap): the host upload of
+ * KP_{t-1} (Sec. III-B, Fig. 2). New identifiers continue above the largest id
+ * seen. */
+int vio_frontend_set_keypoints(vio_frontend* h, int32_t stream, int32_t camera, const vio_keypoint* kps,
+                               int32_t n);
+
+/* Copies camera `camera`'s live keypoints (after the last frame) into out. */
+int vio_frontend_get_keypoints(vio_frontend* h, int32_t stream, int32_t camera, vio_keypoint* out,
+                               int32_t capacity, int32_t* n_out);
+
+/* Diagnostics: copies pyramid level `level` of the last frame of a camera into
+ * out (width>>level columns, height>>level rows, packed). */
+int vio_frontend_get_pyramid(vio_frontend* h, int32_t stream, int32_t camera, int32_t level, uint8_t* out,
+                             size_t capacity);
+
+/* Diagnostics: per-cell detector winners of the last frame of a detecting
+ * camera (mono or left), before masking and the cap: out[3*cell + {0,1,2}] =
+ * x, y, score, or -1, -1, -1 for a cell without a corner. *n_out = cells. */
+int vio_frontend_get_cell_winners(vio_frontend* h, int32_t stream, int32_t camera, int32_t* out,
+                                  int32_t capacity, int32_t* n_out);
+
+int vio_frontend_get_stats(vio_frontend* h, vio_stats* out);
+
+/* Human-readable description of the handle's last error ("" when none). The
+ * string lives as long as the handle. */
+const char* vio_frontend_last_error(const vio_frontend* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIO_FRONTEND_H */

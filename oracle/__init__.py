@@ -69,6 +69,7 @@ def _lib_():
         lib.orc_fe_destroy.argtypes = [vp]
         lib.orc_fe_destroy.restype = None
         lib.orc_fe_push.argtypes = [vp, vp, vp]
+        lib.orc_fe_push_pred.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         lib.orc_fe_get.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
         lib.orc_fe_set_keypoints.argtypes = [vp, i32, i32, vp, vp, vp]
         lib.orc_fe_get_keypoints.argtypes = [vp, i32, i32, vp, vp, vp]
@@ -220,11 +221,19 @@ class Frontend:
     def __del__(self):
         self.close()
 
-    def push(self, images):
+    def push(self, images, predictions=None):
+        """predictions: iterable of (id, camera, x, y) replacing those keypoints' initialisation."""
         imgs = [_u8(im) for im in images]
         ptrs = (ctypes.c_void_p * len(imgs))(*[im.ctypes.data for im in imgs])
         strides = np.asarray([im.shape[1] for im in imgs], np.int32)
-        assert _lib_().orc_fe_push(self._h, ptrs, strides.ctypes.data) == 0
+        if predictions is None or not len(predictions):
+            assert _lib_().orc_fe_push(self._h, ptrs, strides.ctypes.data) == 0
+            return
+        pid = np.ascontiguousarray([int(p[0]) for p in predictions], np.int64)
+        pcam = np.ascontiguousarray([int(p[1]) for p in predictions], np.int32)
+        pxy = np.ascontiguousarray([[float(p[2]), float(p[3])] for p in predictions], np.float32)
+        assert _lib_().orc_fe_push_pred(self._h, ptrs, strides.ctypes.data, len(pid), pid.ctypes.data,
+                                        pcam.ctypes.data, pxy.ctypes.data) == 0
 
     def records(self):
         n = ctypes.c_int()

@@ -469,7 +469,17 @@ static Record make_record(int64_t id, int cam, int status, float x, float y, flo
   return r;
 }
 
-static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* strides) {
+struct Pred {
+  int64_t id;
+  int cam;
+  float x, y;
+};
+
+// A caller prediction (id, camera, position in the new frame) replaces the
+// constant-velocity initialisation of that keypoint (Sec. III-E: the warp is
+// initialised from the backend's prediction).
+static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* strides,
+                       const std::vector<Pred>& preds) {
   const Params& P = F.P;
   const int L = P.levels, N = P.gn_iters;
   std::vector<std::vector<Img>> cur(F.n_cams);
@@ -492,7 +502,12 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     std::vector<Keypoint> surv;
     {
       for (const Keypoint& k : cam.live) {
-        const float ix = k.x + (k.x - k.px), iy = k.y + (k.y - k.py);
+        float ix = k.x + (k.x - k.px), iy = k.y + (k.y - k.py);
+        for (const Pred& q : preds)
+          if (q.cam == c && q.id == k.id) {
+            ix = q.x;
+            iy = q.y;
+          }
         const TrackOut<float> r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, L, N, P.fb_threshold);
         if (r.status == TRACKED) {
           surv.push_back({k.id, r.x, r.y, k.x, k.y, k.age + 1});
@@ -713,7 +728,17 @@ void orc_fe_destroy(void* h) { delete static_cast<Frontend*>(h); }
 
 int orc_fe_push(void* h, const uint8_t* const* imgs, const int32_t* strides) {
   if (!h || !imgs || !strides) return -1;
-  push_frame(*static_cast<Frontend*>(h), imgs, strides);
+  push_frame(*static_cast<Frontend*>(h), imgs, strides, {});
+  return 0;
+}
+
+// As orc_fe_push with n predictions: pred_id[i], pred_cam[i], pred_xy[2i..2i+1].
+int orc_fe_push_pred(void* h, const uint8_t* const* imgs, const int32_t* strides, int n, const int64_t* pred_id,
+                     const int32_t* pred_cam, const float* pred_xy) {
+  if (!h || !imgs || !strides || n < 0) return -1;
+  std::vector<Pred> v;
+  for (int i = 0; i < n; ++i) v.push_back({pred_id[i], pred_cam[i], pred_xy[2 * i], pred_xy[2 * i + 1]});
+  push_frame(*static_cast<Frontend*>(h), imgs, strides, v);
   return 0;
 }
 

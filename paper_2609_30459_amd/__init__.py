@@ -1,0 +1,166 @@
+"""MI355X (gfx950) stereo VIO frontend: Python binding of the C ABI.
+
+The frontend of VkVIO (arXiv 2609.30459, Sec. III): image pyramid, grid FAST-9
+detection with non-maximum suppression, inverse-compositional SE(2) patch
+tracking with a forward-backward check, temporal tracking and stereo matching.
+Every step runs in the library's HIP kernels; this module only marshals
+arguments (numpy for host data, torch tensors for device memory and streams).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native as _n
+from ._native import (KEYPOINT_DTYPE, TRACK_DTYPE, VIO_DETECTED, VIO_LOST_CAP, VIO_LOST_DEGENERATE,  # noqa: F401
+                      VIO_LOST_FB, VIO_LOST_OOB, VIO_MATCHED, VIO_TRACKED, VioError)
+
+__all__ = ["Frontend", "default_params", "make_params", "TRACK_DTYPE", "KEYPOINT_DTYPE", "VioError"]
+
+
+def default_params() -> _n.vio_frontend_params:
+    p = _n.vio_frontend_params()
+    _n.lib.vio_frontend_default_params(ctypes.byref(p))
+    return p
+
+
+def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40, 20, 10, 5), edge_margin=8,
+                max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0, learned_levels=2,
+                learned_iters=3, learned_rho=0.0) -> _n.vio_frontend_params:
+    p = default_params()
+    p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
+    p.n_thresholds = len(thresholds)
+    for i, t in enumerate(thresholds):
+        p.thresholds[i] = t
+    p.edge_margin, p.max_keypoints = edge_margin, max_keypoints
+    p.fb_threshold, p.disparity0, p.init_mode = fb_threshold, disparity0, init_mode
+    p.learned_levels, p.learned_iters, p.learned_rho = learned_levels, learned_iters, learned_rho
+    return p
+
+
+def params_for(workload, **overrides) -> _n.vio_frontend_params:
+    kw = dict(levels=workload.levels, gn_iters=workload.gn_iters, cell_size=workload.cell_size,
+              thresholds=workload.thresholds, edge_margin=workload.edge_margin,
+              max_keypoints=workload.max_keypoints, fb_threshold=workload.fb_threshold,
+              disparity0=workload.disparity0)
+    kw.update(overrides)
+    return make_params(**kw)
+
+
+class Frontend:
+    """A frontend handle (vio_frontend_create .. vio_frontend_destroy).
+
+    streams: list of (n_cameras, width, height[, max_keypoints[, cell_size]]).
+    """
+
+    def __init__(self, streams, params: _n.vio_frontend_params):
+        descs = (_n.vio_stream_desc * len(streams))()
+        for d, s in zip(descs, streams):
+            s = tuple(s) + (0,) * (5 - len(s))
+            d.n_cameras, d.width, d.height, d.max_keypoints, d.cell_size = s
+        self.streams = [tuple(s) for s in streams]
+        self.params = params
+        h = ctypes.c_void_p()
+        rc = _n.lib.vio_frontend_create(descs, len(streams), ctypes.byref(params), ctypes.byref(h))
+        if rc != 0:
+            raise VioError(rc, "vio_frontend_create")
+        self._h = h
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _n.lib.vio_frontend_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc, where):
+        if rc != 0:
+            raise VioError(rc, where, _n.lib.vio_frontend_last_error(self._h).decode(errors="replace"))
+
+    # -- frames ------------------------------------------------------------
+    def push_stereo_frame(self, stream, t_ns, images, predictions=None):
+        """images: one uint8 HxW numpy array per camera of the stream."""
+        imgs = [np.ascontiguousarray(im, np.uint8) for im in images]
+        ptrs = (ctypes.c_void_p * len(imgs))(*[im.ctypes.data for im in imgs])
+        strides = np.asarray([im.strides[0] for im in imgs], np.int32)
+        pred_arr, n_pred = None, 0
+        if predictions is not None and len(predictions):
+            n_pred = len(predictions)
+            pred_arr = (_n.vio_kp_prediction * n_pred)()
+            for q, (pid, cam, x, y) in zip(pred_arr, predictions):
+                q.id, q.camera, q.x, q.y = int(pid), int(cam), float(x), float(y)
+        rc = _n.lib.vio_frontend_push_stereo_frame(self._h, stream, int(t_ns), ptrs, strides.ctypes.data,
+                                                   pred_arr, n_pred)
+        self._check(rc, "vio_frontend_push_stereo_frame")
+
+    def push_stereo_frame_device(self, stream, t_ns, images, hip_stream=None):
+        """images: one device uint8 tensor (HxW, row-contiguous) per camera."""
+        ptrs = (ctypes.c_void_p * len(images))(*[int(t.data_ptr()) for t in images])
+        pitches = np.asarray([int(t.stride(0)) * t.element_size() for t in images], np.int32)
+        st = None
+        if hip_stream is not None:
+            st = ctypes.c_void_p(int(getattr(hip_stream, "cuda_stream", hip_stream)))
+        rc = _n.lib.vio_frontend_push_stereo_frame_device(self._h, stream, int(t_ns), ptrs, pitches.ctypes.data, st)
+        self._check(rc, "vio_frontend_push_stereo_frame_device")
+
+    def get_tracks(self, stream=0) -> np.ndarray:
+        n = ctypes.c_int32()
+        rc = _n.lib.vio_frontend_get_tracks(self._h, stream, None, 0, ctypes.byref(n))
+        if rc not in (0, _n.VIO_ETOOSMALL):
+            self._check(rc, "vio_frontend_get_tracks")
+        out = np.zeros(n.value, TRACK_DTYPE)
+        rc = _n.lib.vio_frontend_get_tracks(self._h, stream, out.ctypes.data, n.value, ctypes.byref(n))
+        self._check(rc, "vio_frontend_get_tracks")
+        return out
+
+    # -- keypoint state ----------------------------------------------------
+    def set_keypoints(self, stream, camera, kps: np.ndarray):
+        kps = np.ascontiguousarray(kps, KEYPOINT_DTYPE)
+        rc = _n.lib.vio_frontend_set_keypoints(self._h, stream, camera, kps.ctypes.data if len(kps) else None,
+                                               len(kps))
+        self._check(rc, "vio_frontend_set_keypoints")
+
+    def get_keypoints(self, stream, camera) -> np.ndarray:
+        n = ctypes.c_int32()
+        rc = _n.lib.vio_frontend_get_keypoints(self._h, stream, camera, None, 0, ctypes.byref(n))
+        if rc not in (0, _n.VIO_ETOOSMALL):
+            self._check(rc, "vio_frontend_get_keypoints")
+        out = np.zeros(n.value, KEYPOINT_DTYPE)
+        rc = _n.lib.vio_frontend_get_keypoints(self._h, stream, camera, out.ctypes.data, n.value, ctypes.byref(n))
+        self._check(rc, "vio_frontend_get_keypoints")
+        return out
+
+    # -- diagnostics -------------------------------------------------------
+    def get_pyramid(self, stream, camera, level) -> np.ndarray:
+        _, w, h = self.streams[stream][:3]
+        out = np.zeros((h >> level, w >> level), np.uint8)
+        rc = _n.lib.vio_frontend_get_pyramid(self._h, stream, camera, level, out.ctypes.data, out.size)
+        self._check(rc, "vio_frontend_get_pyramid")
+        return out
+
+    def get_cell_winners(self, stream, camera) -> np.ndarray:
+        n = ctypes.c_int32()
+        rc = _n.lib.vio_frontend_get_cell_winners(self._h, stream, camera, None, 0, ctypes.byref(n))
+        if rc not in (0, _n.VIO_ETOOSMALL):
+            self._check(rc, "vio_frontend_get_cell_winners")
+        out = np.zeros((n.value, 3), np.int32)
+        rc = _n.lib.vio_frontend_get_cell_winners(self._h, stream, camera, out.ctypes.data, out.size,
+                                                  ctypes.byref(n))
+        self._check(rc, "vio_frontend_get_cell_winners")
+        return out
+
+    def stats(self) -> dict:
+        s = _n.vio_stats()
+        self._check(_n.lib.vio_frontend_get_stats(self._h, ctypes.byref(s)), "vio_frontend_get_stats")
+        return {"frames": s.frames, "last_gpu_ms": s.last_gpu_ms, "last_stage_ms": list(s.last_stage_ms),
+                "last_tracked": s.last_tracked, "last_lost": s.last_lost, "last_detected": s.last_detected,
+                "last_matched": s.last_matched}

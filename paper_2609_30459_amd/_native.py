@@ -1,0 +1,95 @@
+"""ctypes binding of libvio_frontend.so (the C ABI in include/vio_frontend.h).
+
+Argument marshalling only: every step of the frontend runs in the library's HIP
+kernels. Importing this module raises when the library has not been built, so
+nothing can silently fall back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvio_frontend.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2609_30459_amd.build` "
+        "(hipcc, gfx950) before using the frontend")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+VIO_OK, VIO_EINVAL, VIO_ENOMEM, VIO_EDEVICE, VIO_ETOOSMALL, VIO_ESTATE, VIO_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+ERR_NAMES = {0: "VIO_OK", -1: "VIO_EINVAL", -2: "VIO_ENOMEM", -3: "VIO_EDEVICE", -4: "VIO_ETOOSMALL",
+             -5: "VIO_ESTATE", -6: "VIO_EUNSUPPORTED"}
+(VIO_TRACKED, VIO_DETECTED, VIO_MATCHED, VIO_LOST_FB, VIO_LOST_OOB, VIO_LOST_DEGENERATE,
+ VIO_LOST_CAP) = range(7)
+VIO_INIT_CONST_VEL, VIO_INIT_LEARNED = 0, 1
+VIO_MAX_LEVELS = 6
+VIO_MAX_CAMERAS = 64
+
+
+class vio_stream_desc(ctypes.Structure):
+    _fields_ = [("n_cameras", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("max_keypoints", ctypes.c_int32), ("cell_size", ctypes.c_int32)]
+
+
+class vio_frontend_params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("levels", ctypes.c_int32), ("gn_iters", ctypes.c_int32),
+        ("cell_size", ctypes.c_int32), ("k_per_cell", ctypes.c_int32), ("n_thresholds", ctypes.c_int32),
+        ("thresholds", ctypes.c_int32 * 4), ("edge_margin", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
+        ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float), ("init_mode", ctypes.c_int32),
+        ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32), ("learned_rho", ctypes.c_float),
+    ]
+
+
+class vio_kp_prediction(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("camera", ctypes.c_int32), ("x", ctypes.c_float), ("y", ctypes.c_float)]
+
+
+class vio_stats(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_int64), ("last_gpu_ms", ctypes.c_double),
+                ("last_stage_ms", ctypes.c_double * 3), ("last_tracked", ctypes.c_int32),
+                ("last_lost", ctypes.c_int32), ("last_detected", ctypes.c_int32),
+                ("last_matched", ctypes.c_int32)]
+
+
+TRACK_DTYPE = np.dtype([
+    ("id", "<i8"), ("x", "<f4"), ("y", "<f4"), ("theta", "<f4"), ("fb_err", "<f4"), ("resid_rms", "<f4"),
+    ("age", "<i4"), ("camera", "<i2"), ("status", "<i2"), ("score", "<i4"),
+])
+KEYPOINT_DTYPE = np.dtype([("id", "<i8"), ("x", "<f4"), ("y", "<f4"), ("px", "<f4"), ("py", "<f4"),
+                           ("age", "<i4"), ("reserved", "<i4")])
+assert TRACK_DTYPE.itemsize == 40 and KEYPOINT_DTYPE.itemsize == 32
+
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_P = ctypes.POINTER
+
+lib.vio_frontend_default_params.argtypes = [_P(vio_frontend_params)]
+lib.vio_frontend_default_params.restype = None
+lib.vio_frontend_create.argtypes = [_P(vio_stream_desc), _i32, _P(vio_frontend_params), _P(_vp)]
+lib.vio_frontend_destroy.argtypes = [_vp]
+lib.vio_frontend_destroy.restype = None
+lib.vio_frontend_push_stereo_frame.argtypes = [_vp, _i32, _i64, _vp, _vp, _vp, _i32]
+lib.vio_frontend_push_stereo_frame_device.argtypes = [_vp, _i32, _i64, _vp, _vp, _vp]
+lib.vio_frontend_get_tracks.argtypes = [_vp, _i32, _vp, _i32, _P(_i32)]
+lib.vio_frontend_set_keypoints.argtypes = [_vp, _i32, _i32, _vp, _i32]
+lib.vio_frontend_get_keypoints.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
+lib.vio_frontend_get_pyramid.argtypes = [_vp, _i32, _i32, _i32, _vp, _sz]
+lib.vio_frontend_get_cell_winners.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
+lib.vio_frontend_get_stats.argtypes = [_vp, _P(vio_stats)]
+lib.vio_frontend_last_error.argtypes = [_vp]
+lib.vio_frontend_last_error.restype = ctypes.c_char_p
+for _name in ("vio_frontend_create", "vio_frontend_push_stereo_frame", "vio_frontend_push_stereo_frame_device",
+              "vio_frontend_get_tracks", "vio_frontend_set_keypoints", "vio_frontend_get_keypoints",
+              "vio_frontend_get_pyramid", "vio_frontend_get_cell_winners", "vio_frontend_get_stats"):
+    getattr(lib, _name).restype = ctypes.c_int
+
+
+class VioError(RuntimeError):
+    def __init__(self, code, where, detail=""):
+        self.code = code
+        super().__init__(f"{where} -> {ERR_NAMES.get(code, code)} {detail}".strip())

@@ -1,0 +1,623 @@
+// Host runtime behind the C ABI in vio_frontend.h.
+//
+// Device memory is one arena allocated at create (Sec. III-B: every resource
+// is allocated once and reused). Per frame the runtime fills a small frame
+// table in pinned memory, copies it (and the images, for a host push) to the
+// device, launches three kernels on one stream, copies the records back and
+// waits: the synchronous submit-and-fence of the paper's pipeline.
+//
+// Per camera and frame parity p the arena holds: pyramid levels, keypoint
+// state, per-cell winner keys; plus temporal and stereo results and records.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fe_common.h"
+
+using namespace vio;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxCellsAbi = 8192;  // matches the selection kernel's LDS tables
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct StreamInfo {
+  int first_cam, n_cams, w, h, cap, cell;
+  int64_t frames = 0;
+  int64_t last_t = 0;
+  int tile_begin = 0, n_tiles = 0;
+  int seg_begin = 0, n_segs = 0, n_items = 0;
+  size_t rec_off = 0, rec_n = 0;  // record range (in vio_track units) of the stream's cameras
+};
+
+}  // namespace
+
+struct vio_frontend {
+  vio_frontend_params P{};
+  std::vector<StreamInfo> streams;
+  std::vector<CamDesc> cams;
+  std::vector<TrackSeg> segs;
+  std::vector<int> stream_cams;
+  int total_tiles = 0;
+  size_t rec_total = 0;
+  // device
+  void* arena = nullptr;
+  CamDesc* d_cams = nullptr;
+  FrameTable* d_frame = nullptr;
+  Counters* d_cnt = nullptr;
+  TrackSeg* d_segs = nullptr;
+  int* d_stream_cams = nullptr;
+  Prediction* d_pred = nullptr;
+  vio_track* d_rec = nullptr;
+  int pred_cap = 0;
+  // pinned host
+  FrameTable* h_frame = nullptr;
+  Counters* h_cnt = nullptr;
+  vio_track* h_rec = nullptr;
+  uint8_t* h_stage = nullptr;
+  size_t stage_bytes = 0;
+  Prediction* h_pred = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int device = 0;
+  bool poisoned = false;
+  bool fault_device = false;
+  std::string err;
+  vio_stats stats{};
+};
+
+namespace {
+
+int fail(vio_frontend* h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(vio_frontend* h, int code, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->err = buf;
+    if (code == VIO_EDEVICE) h->poisoned = true;
+  }
+  return code;
+}
+
+#define HIP_CHECK(h, expr)                                                                          \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return fail((h), VIO_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+int check_params(const vio_frontend_params* p, std::string& why) {
+  if (p->struct_size != sizeof(vio_frontend_params)) return why = "struct_size mismatch", VIO_EINVAL;
+  if (p->levels < 1 || p->levels > VIO_MAX_LEVELS) return why = "levels out of 1..6", VIO_EINVAL;
+  if (p->gn_iters < 1 || p->gn_iters > 32) return why = "gn_iters out of 1..32", VIO_EINVAL;
+  if (p->n_thresholds < 1 || p->n_thresholds > 4) return why = "n_thresholds out of 1..4", VIO_EINVAL;
+  for (int i = 0; i < p->n_thresholds; ++i)
+    if (p->thresholds[i] < 0 || p->thresholds[i] > 254) return why = "threshold out of 0..254", VIO_EINVAL;
+  if (p->edge_margin < 4) return why = "edge_margin below 4", VIO_EINVAL;
+  if (!(p->fb_threshold > 0.f)) return why = "fb_threshold must be positive", VIO_EINVAL;
+  if (p->k_per_cell != 1) return why = "only k_per_cell = 1 is implemented", VIO_EUNSUPPORTED;
+  if (p->init_mode != VIO_INIT_CONST_VEL) return why = "learned init needs weights", VIO_EUNSUPPORTED;
+  return VIO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vio_frontend_default_params(vio_frontend_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->struct_size = sizeof *p;
+  p->levels = 4;
+  p->gn_iters = 5;
+  p->cell_size = 50;
+  p->k_per_cell = 1;
+  p->n_thresholds = 4;
+  p->thresholds[0] = 40;
+  p->thresholds[1] = 20;
+  p->thresholds[2] = 10;
+  p->thresholds[3] = 5;
+  p->edge_margin = 8;
+  p->max_keypoints = 300;
+  p->fb_threshold = 0.3f;
+  p->disparity0 = 32.5f;
+  p->init_mode = VIO_INIT_CONST_VEL;
+  p->learned_levels = 2;
+  p->learned_iters = 3;
+  p->learned_rho = 0.f;
+}
+
+void vio_frontend_destroy(vio_frontend* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->arena) (void)hipFree(h->arena);
+  if (h->h_frame) (void)hipHostFree(h->h_frame);
+  if (h->h_cnt) (void)hipHostFree(h->h_cnt);
+  if (h->h_rec) (void)hipHostFree(h->h_rec);
+  if (h->h_stage) (void)hipHostFree(h->h_stage);
+  if (h->h_pred) (void)hipHostFree(h->h_pred);
+  for (hipEvent_t& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_streams) {
+  const vio_frontend_params& P = h->P;
+  // ---- layout (host only) ---------------------------------------------------
+  int n_cams = 0;
+  for (int s = 0; s < n_streams; ++s) n_cams += sd[s].n_cameras;
+  h->cams.resize(n_cams);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = round_up(off + bytes, kAlign);
+    return o;
+  };
+  struct CamOffs {
+    size_t lvl[2][kMaxLevels], state[2], res, keys[2], sres, rec;
+  };
+  std::vector<CamOffs> co(n_cams);
+  int cam = 0, tiles = 0;
+  size_t rec_total = 0, stage = 0;
+  for (int s = 0; s < n_streams; ++s) {
+    StreamInfo si;
+    si.first_cam = cam;
+    si.n_cams = sd[s].n_cameras;
+    si.w = sd[s].width;
+    si.h = sd[s].height;
+    si.cap = sd[s].max_keypoints > 0 ? sd[s].max_keypoints : P.max_keypoints;
+    si.cell = sd[s].cell_size > 0 ? sd[s].cell_size : P.cell_size;
+    si.tile_begin = tiles;
+    si.rec_off = rec_total;
+    si.seg_begin = (int)h->segs.size();
+    int items = 0;
+    for (int k = 0; k < si.n_cams; ++k, ++cam) {
+      CamDesc& c = h->cams[cam];
+      std::memset(&c, 0, sizeof c);
+      c.w = si.w;
+      c.h = si.h;
+      c.levels = P.levels;
+      c.cap = si.cap;
+      c.cell = si.cell;
+      c.ncx = (si.w + si.cell - 1) / si.cell;
+      c.ncy = (si.h + si.cell - 1) / si.cell;
+      c.ncells = c.ncx * c.ncy;
+      c.detect = (si.n_cams == 1 || k % 2 == 0) ? 1 : 0;
+      c.partner = si.n_cams == 1 ? -1 : (k % 2 == 0 ? cam + 1 : cam - 1);
+      c.stream = s;
+      c.local = k;
+      c.tiles_x = (si.w + kTile - 1) / kTile;
+      c.tiles_y = (si.h + kTile - 1) / kTile;
+      c.tile_begin = tiles;
+      tiles += c.tiles_x * c.tiles_y;
+      for (int l = 0; l < P.levels; ++l) {
+        c.pitch[l] = (int)round_up((size_t)(si.w >> l), 64);
+        for (int par = 0; par < 2; ++par) co[cam].lvl[par][l] = take((size_t)c.pitch[l] * (size_t)(si.h >> l));
+      }
+      for (int par = 0; par < 2; ++par) co[cam].state[par] = take(sizeof(Kp) * si.cap);
+      co[cam].res = take(sizeof(TrackRes) * si.cap);
+      if (c.detect) {
+        for (int par = 0; par < 2; ++par) co[cam].keys[par] = take(sizeof(uint32_t) * c.ncells);
+        co[cam].sres = take(sizeof(TrackRes) * c.ncells);
+      }
+      c.rec_cap = 2 * si.cap;
+      co[cam].rec = rec_total;
+      rec_total += c.rec_cap;
+      stage += (size_t)si.w * si.h;
+      // tracking work items: temporal for every camera, stereo for left cameras of pairs
+      h->segs.push_back({cam, kModeTemporal, items, si.cap});
+      items += si.cap;
+    }
+    for (int k = 0; k < si.n_cams; ++k) {
+      const int cc = si.first_cam + k;
+      if (si.n_cams >= 2 && k % 2 == 0) {
+        h->segs.push_back({cc, kModeStereo, items, h->cams[cc].ncells});
+        items += h->cams[cc].ncells;
+      }
+    }
+    si.n_segs = (int)h->segs.size() - si.seg_begin;
+    si.n_items = items;
+    si.n_tiles = tiles - si.tile_begin;
+    si.rec_n = rec_total - si.rec_off;
+    h->streams.push_back(si);
+    h->stream_cams.push_back(si.first_cam);
+    h->stream_cams.push_back(si.n_cams);
+  }
+  h->total_tiles = tiles;
+  h->rec_total = rec_total;
+  h->pred_cap = 0;
+  for (auto& c : h->cams) h->pred_cap += c.cap;
+  const size_t o_cams = take(sizeof(CamDesc) * n_cams);
+  const size_t o_frame = take(sizeof(FrameTable));
+  const size_t o_cnt = take(sizeof(Counters));
+  const size_t o_segs = take(sizeof(TrackSeg) * h->segs.size());
+  const size_t o_sc = take(sizeof(int) * h->stream_cams.size());
+  const size_t o_pred = take(sizeof(Prediction) * std::max(1, h->pred_cap));
+  const size_t o_rec = take(sizeof(vio_track) * rec_total);
+  const size_t arena_bytes = off;
+
+  // ---- device ---------------------------------------------------------------
+  if (const char* fi = std::getenv("VIO_FAULT_INJECT")) {
+    if (!std::strcmp(fi, "alloc")) return fail(h, VIO_ENOMEM, "injected allocation failure");
+    if (!std::strcmp(fi, "device")) h->fault_device = true;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(h, VIO_EDEVICE, "no HIP device");
+  HIP_CHECK(h, hipGetDevice(&h->device));
+  int lds_max = 0;
+  HIP_CHECK(h, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+  const size_t lds_need = pyr_detect_lds_bytes(P.levels);
+  if (lds_need == 0 || lds_need > (size_t)lds_max)
+    return fail(h, VIO_EUNSUPPORTED, "%d levels need %zu bytes of LDS per workgroup, the device offers %d", P.levels,
+                lds_need, lds_max);
+  if (hipMalloc(&h->arena, arena_bytes) != hipSuccess) {
+    h->arena = nullptr;
+    return fail(h, VIO_ENOMEM, "device arena of %zu bytes", arena_bytes);
+  }
+  HIP_CHECK(h, hipMemset(h->arena, 0, arena_bytes));
+  uint8_t* base = static_cast<uint8_t*>(h->arena);
+  for (int c = 0; c < n_cams; ++c) {
+    CamDesc& d = h->cams[c];
+    for (int l = 0; l < P.levels; ++l)
+      for (int par = 0; par < 2; ++par) d.lvl[par][l] = base + co[c].lvl[par][l];
+    for (int par = 0; par < 2; ++par) d.state[par] = reinterpret_cast<Kp*>(base + co[c].state[par]);
+    d.res = reinterpret_cast<TrackRes*>(base + co[c].res);
+    if (d.detect) {
+      for (int par = 0; par < 2; ++par) d.keys[par] = reinterpret_cast<uint32_t*>(base + co[c].keys[par]);
+      d.sres = reinterpret_cast<TrackRes*>(base + co[c].sres);
+    }
+  }
+  h->d_cams = reinterpret_cast<CamDesc*>(base + o_cams);
+  h->d_frame = reinterpret_cast<FrameTable*>(base + o_frame);
+  h->d_cnt = reinterpret_cast<Counters*>(base + o_cnt);
+  h->d_segs = reinterpret_cast<TrackSeg*>(base + o_segs);
+  h->d_stream_cams = reinterpret_cast<int*>(base + o_sc);
+  h->d_pred = reinterpret_cast<Prediction*>(base + o_pred);
+  h->d_rec = reinterpret_cast<vio_track*>(base + o_rec);
+  for (int c = 0; c < n_cams; ++c) h->cams[c].rec = h->d_rec + co[c].rec;
+  HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
+  HIP_CHECK(h, hipMemcpy(h->d_segs, h->segs.data(), sizeof(TrackSeg) * h->segs.size(), hipMemcpyHostToDevice));
+  HIP_CHECK(h, hipMemcpy(h->d_stream_cams, h->stream_cams.data(), sizeof(int) * h->stream_cams.size(),
+                         hipMemcpyHostToDevice));
+  // pinned host buffers
+  h->stage_bytes = stage;
+  if (hipHostMalloc((void**)&h->h_frame, sizeof(FrameTable)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_cnt, sizeof(Counters)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * rec_total) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_stage, stage) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * std::max(1, h->pred_cap)) != hipSuccess)
+    return fail(h, VIO_ENOMEM, "pinned host buffers");
+  std::memset(h->h_frame, 0, sizeof(FrameTable));
+  std::memset(h->h_cnt, 0, sizeof(Counters));
+  HIP_CHECK(h, hipStreamCreate(&h->stream));
+  for (hipEvent_t& e : h->ev) HIP_CHECK(h, hipEventCreate(&e));
+  return VIO_OK;
+}
+
+int vio_frontend_create(const vio_stream_desc* streams, int32_t n_streams, const vio_frontend_params* params,
+                        vio_frontend** out) {
+  if (!streams || !params || !out || n_streams < 1) return VIO_EINVAL;
+  *out = nullptr;
+  std::string why;
+  const int pc = check_params(params, why);
+  if (pc != VIO_OK) return pc;
+  int n_cams = 0;
+  for (int s = 0; s < n_streams; ++s) {
+    const vio_stream_desc& d = streams[s];
+    if (d.n_cameras != 1 && d.n_cameras != 2 && d.n_cameras != 4) return VIO_EINVAL;
+    if (d.width < 16 || d.height < 16 || d.width > 4096 || d.height > 4096) return VIO_EINVAL;
+    if ((int64_t)d.width * d.height >= (1 << 24)) return VIO_EINVAL;
+    if ((d.width >> (params->levels - 1)) < 2 || (d.height >> (params->levels - 1)) < 2) return VIO_EINVAL;
+    const int cap = d.max_keypoints > 0 ? d.max_keypoints : params->max_keypoints;
+    const int cell = d.cell_size > 0 ? d.cell_size : params->cell_size;
+    if (cap < 1 || cap > kMaxCellsAbi || cell < 4) return VIO_EINVAL;
+    if ((int64_t)((d.width + cell - 1) / cell) * ((d.height + cell - 1) / cell) > kMaxCellsAbi) return VIO_EINVAL;
+    n_cams += d.n_cameras;
+  }
+  if (n_cams > kMaxCams) return VIO_EINVAL;
+  auto* h = new (std::nothrow) vio_frontend();
+  if (!h) return VIO_ENOMEM;
+  h->P = *params;
+  const int rc = create_impl(h, streams, n_streams);
+  if (rc != VIO_OK) {
+    vio_frontend_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return VIO_OK;
+}
+
+const char* vio_frontend_last_error(const vio_frontend* h) { return h ? h->err.c_str() : "null handle"; }
+
+static Tuning tuning(const vio_frontend* h) {
+  Tuning t;
+  t.levels = h->P.levels;
+  t.iters = h->P.gn_iters;
+  t.fb_threshold = h->P.fb_threshold;
+  t.disparity0 = h->P.disparity0;
+  t.k = h->P.k_per_cell;
+  t.tmin = h->P.thresholds[h->P.n_thresholds - 1];
+  t.margin = h->P.edge_margin;
+  return t;
+}
+
+// Runs one frame of stream s whose level-0 sources are already in h_frame.
+static int run_frame(vio_frontend* h, int s, hipStream_t st) {
+  StreamInfo& si = h->streams[s];
+  const Tuning tune = tuning(h);
+  HIP_CHECK(h, hipMemcpyAsync(h->d_frame, h->h_frame, sizeof(FrameTable), hipMemcpyHostToDevice, st));
+  HIP_CHECK(h, hipEventRecord(h->ev[0], st));
+  HIP_CHECK(h, launch_pyr_detect_range(h->d_cams, h->d_frame, si.first_cam, si.first_cam + si.n_cams, si.tile_begin,
+                                       si.n_tiles, tune.levels, tune.tmin, tune.margin, st));
+  HIP_CHECK(h, hipEventRecord(h->ev[1], st));
+  HIP_CHECK(h, launch_track(h->d_cams, h->d_frame, h->d_cnt, h->d_segs + si.seg_begin, si.n_segs, si.n_items,
+                            h->d_pred, tune, st));
+  HIP_CHECK(h, hipEventRecord(h->ev[2], st));
+  HIP_CHECK(h, launch_select(h->d_cams, h->d_frame, h->d_cnt, h->d_stream_cams + 2 * s, 1, si.n_cams, tune, st));
+  HIP_CHECK(h, hipEventRecord(h->ev[3], st));
+  HIP_CHECK(h, hipMemcpyAsync(h->h_cnt, h->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(h, hipMemcpyAsync(h->h_rec + si.rec_off, h->d_rec + si.rec_off, sizeof(vio_track) * si.rec_n,
+                              hipMemcpyDeviceToHost, st));
+  HIP_CHECK(h, hipStreamSynchronize(st));
+  float ms = 0.f;
+  HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[3]));
+  for (int k = 0; k < 3; ++k) {
+    float m = 0.f;
+    HIP_CHECK(h, hipEventElapsedTime(&m, h->ev[k], h->ev[k + 1]));
+    h->stats.last_stage_ms[k] = m;
+  }
+  si.frames += 1;
+  h->stats.frames += 1;
+  h->stats.last_gpu_ms = ms;
+  int tr = 0, lost = 0, det = 0, mat = 0;
+  for (int k = 0; k < si.n_cams; ++k) {
+    const CamDesc& c = h->cams[si.first_cam + k];
+    const int n = h->h_cnt->rec_count[si.first_cam + k];
+    const vio_track* r = h->h_rec + (c.rec - h->d_rec);
+    for (int i = 0; i < n; ++i) {
+      switch (r[i].status) {
+        case VIO_TRACKED: ++tr; break;
+        case VIO_DETECTED: ++det; break;
+        case VIO_MATCHED: ++mat; break;
+        default:
+          if (r[i].age > 0 || c.detect) ++lost;
+      }
+    }
+  }
+  h->stats.last_tracked = tr;
+  h->stats.last_lost = lost;
+  h->stats.last_detected = det;
+  h->stats.last_matched = mat;
+  return VIO_OK;
+}
+
+static int check_push(vio_frontend* h, int32_t s, int64_t t_ns) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (si.frames > 0 && t_ns <= si.last_t) return fail(h, VIO_ESTATE, "timestamps must increase");
+  if (h->fault_device) return fail(h, VIO_EDEVICE, "injected device failure");
+  return VIO_OK;
+}
+
+static void fill_frame(vio_frontend* h, int s) {
+  const StreamInfo& si = h->streams[s];
+  const int par = (int)(si.frames & 1);
+  for (int c = 0; c < (int)h->cams.size(); ++c) h->h_frame->cam[c].active = 0;
+  for (int k = 0; k < si.n_cams; ++k) {
+    FrameCam& f = h->h_frame->cam[si.first_cam + k];
+    f.parity = par;
+    f.has_prev = si.frames > 0;
+    f.active = 1;
+    f.n_pred = 0;
+    f.pred_off = 0;
+  }
+}
+
+static int upload_predictions(vio_frontend* h, int s, const vio_kp_prediction* pred, int32_t n_pred, hipStream_t st) {
+  const StreamInfo& si = h->streams[s];
+  if (n_pred == 0) return VIO_OK;
+  if (!pred || n_pred < 0) return fail(h, VIO_EINVAL, "bad prediction list");
+  std::vector<vio_kp_prediction> v(pred, pred + n_pred);
+  for (const auto& q : v)
+    if (q.camera < 0 || q.camera >= si.n_cams) return fail(h, VIO_EINVAL, "prediction camera out of range");
+  std::stable_sort(v.begin(), v.end(), [](const vio_kp_prediction& a, const vio_kp_prediction& b) {
+    return a.camera != b.camera ? a.camera < b.camera : a.id < b.id;
+  });
+  for (size_t i = 1; i < v.size(); ++i)
+    if (v[i].camera == v[i - 1].camera && v[i].id == v[i - 1].id) return fail(h, VIO_EINVAL, "duplicate prediction");
+  if (n_pred > h->pred_cap) return fail(h, VIO_EINVAL, "more predictions than keypoint capacity");
+  int at = 0;
+  for (int k = 0; k < si.n_cams; ++k) {
+    FrameCam& f = h->h_frame->cam[si.first_cam + k];
+    f.pred_off = at;
+    for (const auto& q : v)
+      if (q.camera == k) h->h_pred[at++] = Prediction{q.id, q.x, q.y};
+    f.n_pred = at - f.pred_off;
+  }
+  HIP_CHECK(h, hipMemcpyAsync(h->d_pred, h->h_pred, sizeof(Prediction) * at, hipMemcpyHostToDevice, st));
+  return VIO_OK;
+}
+
+int vio_frontend_push_stereo_frame(vio_frontend* h, int32_t s, int64_t t_ns, const uint8_t* const* images,
+                                   const int32_t* strides, const vio_kp_prediction* pred, int32_t n_pred) {
+  int rc = check_push(h, s, t_ns);
+  if (rc != VIO_OK) return rc;
+  StreamInfo& si = h->streams[s];
+  if (!images || !strides) return fail(h, VIO_EINVAL, "null images or strides");
+  for (int k = 0; k < si.n_cams; ++k)
+    if (!images[k] || strides[k] < si.w) return fail(h, VIO_EINVAL, "camera %d: null image or stride < width", k);
+  fill_frame(h, s);
+  rc = upload_predictions(h, s, pred, n_pred, h->stream);
+  if (rc != VIO_OK) return rc;
+  const int par = (int)(si.frames & 1);
+  size_t so = 0;
+  for (int k = 0; k < si.first_cam; ++k) so += (size_t)h->cams[k].w * h->cams[k].h;
+  for (int k = 0; k < si.n_cams; ++k) {
+    const int c = si.first_cam + k;
+    const CamDesc& cd = h->cams[c];
+    uint8_t* stg = h->h_stage + so;
+    for (int y = 0; y < si.h; ++y) std::memcpy(stg + (size_t)y * si.w, images[k] + (size_t)y * strides[k], si.w);
+    HIP_CHECK(h, hipMemcpy2DAsync(cd.lvl[par][0], cd.pitch[0], stg, si.w, si.w, si.h, hipMemcpyHostToDevice, h->stream));
+    FrameCam& f = h->h_frame->cam[c];
+    f.src = cd.lvl[par][0];
+    f.src_pitch = cd.pitch[0];
+    f.copy_l0 = 0;
+    so += (size_t)si.w * si.h;
+  }
+  rc = run_frame(h, s, h->stream);
+  if (rc != VIO_OK) return rc;
+  si.last_t = t_ns;
+  return VIO_OK;
+}
+
+int vio_frontend_push_stereo_frame_device(vio_frontend* h, int32_t s, int64_t t_ns, const void* const* d_images,
+                                          const int32_t* pitches, void* hip_stream) {
+  int rc = check_push(h, s, t_ns);
+  if (rc != VIO_OK) return rc;
+  StreamInfo& si = h->streams[s];
+  if (!d_images || !pitches) return fail(h, VIO_EINVAL, "null images or pitches");
+  for (int k = 0; k < si.n_cams; ++k)
+    if (!d_images[k] || pitches[k] < si.w) return fail(h, VIO_EINVAL, "camera %d: null image or pitch < width", k);
+  fill_frame(h, s);
+  for (int k = 0; k < si.n_cams; ++k) {
+    FrameCam& f = h->h_frame->cam[si.first_cam + k];
+    f.src = static_cast<const uint8_t*>(d_images[k]);
+    f.src_pitch = pitches[k];
+    f.copy_l0 = 1;
+  }
+  hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : h->stream;
+  rc = run_frame(h, s, st);
+  if (rc != VIO_OK) return rc;
+  si.last_t = t_ns;
+  return VIO_OK;
+}
+
+int vio_frontend_get_tracks(vio_frontend* h, int32_t s, vio_track* out, int32_t capacity, int32_t* n_out) {
+  if (!h || !n_out) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (si.frames == 0) return fail(h, VIO_ESTATE, "no frame pushed yet");
+  int n = 0;
+  for (int k = 0; k < si.n_cams; ++k) n += h->h_cnt->rec_count[si.first_cam + k];
+  *n_out = n;
+  if (capacity < n) return VIO_ETOOSMALL;
+  if (n > 0 && !out) return VIO_EINVAL;
+  int at = 0;
+  for (int k = 0; k < si.n_cams; ++k) {
+    const CamDesc& c = h->cams[si.first_cam + k];
+    const int m = h->h_cnt->rec_count[si.first_cam + k];
+    std::memcpy(out + at, h->h_rec + (c.rec - h->d_rec), sizeof(vio_track) * m);
+    at += m;
+  }
+  return VIO_OK;
+}
+
+static int state_slot(const StreamInfo& si) { return (int)((si.frames & 1) ^ 1); }
+
+int vio_frontend_set_keypoints(vio_frontend* h, int32_t s, int32_t camera, const vio_keypoint* kps, int32_t n) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera out of range");
+  if (n < 0 || n > si.cap || (n > 0 && !kps)) return fail(h, VIO_EINVAL, "bad keypoint count");
+  int64_t max_id = -1;
+  for (int i = 0; i < n; ++i) {
+    if (i > 0 && kps[i].id <= kps[i - 1].id) return fail(h, VIO_EINVAL, "ids must ascend");
+    if (kps[i].id < 0) return fail(h, VIO_EINVAL, "negative id");
+    max_id = kps[i].id;
+  }
+  const int c = si.first_cam + camera;
+  const int slot = state_slot(si);
+  if (n > 0) HIP_CHECK(h, hipMemcpy(h->cams[c].state[slot], kps, sizeof(Kp) * n, hipMemcpyHostToDevice));
+  HIP_CHECK(h, hipMemcpy(&h->d_cnt->n_live[slot][c], &n, sizeof(int32_t), hipMemcpyHostToDevice));
+  int64_t next = 0;
+  HIP_CHECK(h, hipMemcpy(&next, &h->d_cnt->next_id[s], sizeof next, hipMemcpyDeviceToHost));
+  next = std::max(next, max_id + 1);
+  HIP_CHECK(h, hipMemcpy(&h->d_cnt->next_id[s], &next, sizeof next, hipMemcpyHostToDevice));
+  return VIO_OK;
+}
+
+int vio_frontend_get_keypoints(vio_frontend* h, int32_t s, int32_t camera, vio_keypoint* out, int32_t capacity,
+                               int32_t* n_out) {
+  if (!h || !n_out) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera out of range");
+  const int c = si.first_cam + camera;
+  const int slot = state_slot(si);
+  int32_t n = 0;
+  HIP_CHECK(h, hipMemcpy(&n, &h->d_cnt->n_live[slot][c], sizeof n, hipMemcpyDeviceToHost));
+  *n_out = n;
+  if (capacity < n) return VIO_ETOOSMALL;
+  if (n > 0) HIP_CHECK(h, hipMemcpy(out, h->cams[c].state[slot], sizeof(Kp) * n, hipMemcpyDeviceToHost));
+  return VIO_OK;
+}
+
+int vio_frontend_get_pyramid(vio_frontend* h, int32_t s, int32_t camera, int32_t level, uint8_t* out,
+                             size_t capacity) {
+  if (!h || !out) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams || level < 0 || level >= h->P.levels) return fail(h, VIO_EINVAL, "bad camera/level");
+  if (si.frames == 0) return fail(h, VIO_ESTATE, "no frame pushed yet");
+  const CamDesc& c = h->cams[si.first_cam + camera];
+  const int w = c.w >> level, hh = c.h >> level;
+  if (capacity < (size_t)w * hh) return VIO_ETOOSMALL;
+  const int par = (int)((si.frames - 1) & 1);
+  HIP_CHECK(h, hipMemcpy2D(out, w, c.lvl[par][level], c.pitch[level], w, hh, hipMemcpyDeviceToHost));
+  return VIO_OK;
+}
+
+int vio_frontend_get_cell_winners(vio_frontend* h, int32_t s, int32_t camera, int32_t* out, int32_t capacity,
+                                  int32_t* n_out) {
+  if (!h || !n_out) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera out of range");
+  const CamDesc& c = h->cams[si.first_cam + camera];
+  if (!c.detect) return fail(h, VIO_EINVAL, "camera %d does not detect", camera);
+  if (si.frames == 0) return fail(h, VIO_ESTATE, "no frame pushed yet");
+  *n_out = c.ncells;
+  if (capacity < 3 * c.ncells) return VIO_ETOOSMALL;
+  if (!out) return VIO_EINVAL;
+  std::vector<uint32_t> keys(c.ncells);
+  const int par = (int)((si.frames - 1) & 1);
+  HIP_CHECK(h, hipMemcpy(keys.data(), c.keys[par], sizeof(uint32_t) * c.ncells, hipMemcpyDeviceToHost));
+  for (int i = 0; i < c.ncells; ++i) {
+    if (!keys[i]) {
+      out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = -1;
+      continue;
+    }
+    const int idx = 0xFFFFFF - (int)(keys[i] & 0xFFFFFFu);
+    out[3 * i] = idx % c.w;
+    out[3 * i + 1] = idx / c.w;
+    out[3 * i + 2] = (int)(keys[i] >> 24);
+  }
+  return VIO_OK;
+}
+
+int vio_frontend_get_stats(vio_frontend* h, vio_stats* out) {
+  if (!h || !out) return VIO_EINVAL;
+  *out = h->stats;
+  return VIO_OK;
+}
+
+}  // extern "C"

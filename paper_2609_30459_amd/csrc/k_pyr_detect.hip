@@ -1,0 +1,278 @@
+// Fused pyramid + corner detector for gfx950.
+//
+// One 256-thread workgroup owns a 64x64 level-0 tile of one camera. It stages
+// the tile plus an apron in LDS with coalesced dword loads, then
+//  * computes the FAST-9 score (Sec. III-D) of the tile and a one-pixel ring,
+//    keeps strict 3x3 maxima with score >= the last threshold and folds each
+//    into its cell's packed key with one atomicMax, and
+//  * builds every coarser pyramid level of the tile (Sec. III-C, eqs. 2-3)
+//    from LDS, recomputing the apron instead of reading it back from HBM, so
+//    level 0 is read from HBM once per frame and the L-1 level-serial
+//    dispatches of the paper become one launch.
+// All arithmetic is integer, so the result is bit-identical to a level-serial
+// build.
+//
+// Threshold walk (Sec. III-D): with one keypoint per cell, walking the
+// thresholds 40, 20, 10, 5 and stopping at the first non-empty level picks the
+// same corner as one pass at the last threshold, because a strict local
+// maximum does not depend on the threshold (a neighbour below it scores less
+// than the candidate anyway). The cell winner is the maximum of
+// key = score << 24 | (2^24 - 1 - (y * W + x)), i.e. highest score, then
+// smallest y, then smallest x.
+#include "fe_common.h"
+
+namespace vio {
+namespace {
+
+template <int L>
+struct PyrGeom {
+  // apron of level l so that the tile of level L-1 can be computed: A[L-1] = 0,
+  // A[l] = 2 A[l+1] + 2, i.e. A[l] = 2^(L-l) - 2
+  static constexpr __host__ __device__ int apron(int l) { return (1 << (L - l)) - 2; }
+  static constexpr __host__ __device__ int tile(int l) { return kTile >> l; }
+  static constexpr __host__ __device__ int region(int l) { return tile(l) + 2 * apron(l); }
+  // level-0 staging: apron at least 4 (FAST radius 3 plus the NMS ring)
+  static constexpr int a0 = apron(0) > 4 ? apron(0) : 4;
+  static constexpr int a0x = (a0 + 3) & ~3;  // left apron rounded to a dword
+  static constexpr int sw0 = ((kTile + a0x + a0) + 3) & ~3;
+  static constexpr int sh0 = kTile + 2 * a0;
+  static constexpr int vbytes = L > 1 ? (region(0) - 1) * region(1) : 1;
+  static constexpr int lvl_bytes = L > 1 ? region(1) * region(1) : 1;
+};
+
+constexpr int kScoreEdge = kTile + 2;
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// FAST-9 score of the pixel at LDS offset `o` (row pitch `sp`), or -1 when it
+// is below `tmin`. Bresenham circle of radius 3 from (0,-3) clockwise.
+__device__ __forceinline__ int fast_score_lds(const uint8_t* img, int o, int sp, int tmin) {
+  const int c = img[o];
+  int d[16];
+  d[0] = img[o - 3 * sp] - c;
+  d[1] = img[o - 3 * sp + 1] - c;
+  d[2] = img[o - 2 * sp + 2] - c;
+  d[3] = img[o - sp + 3] - c;
+  d[4] = img[o + 3] - c;
+  d[5] = img[o + sp + 3] - c;
+  d[6] = img[o + 2 * sp + 2] - c;
+  d[7] = img[o + 3 * sp + 1] - c;
+  d[8] = img[o + 3 * sp] - c;
+  d[9] = img[o + 3 * sp - 1] - c;
+  d[10] = img[o + 2 * sp - 2] - c;
+  d[11] = img[o + sp - 3] - c;
+  d[12] = img[o - 3] - c;
+  d[13] = img[o - sp - 3] - c;
+  d[14] = img[o - 2 * sp - 2] - c;
+  d[15] = img[o - 3 * sp - 1] - c;
+  // every 9-arc holds one of {0, 8} and one of {4, 12}: exact early rejection
+  const bool bright = (d[0] > tmin || d[8] > tmin) && (d[4] > tmin || d[12] > tmin);
+  const bool dark = (d[0] < -tmin || d[8] < -tmin) && (d[4] < -tmin || d[12] < -tmin);
+  if (!bright && !dark) return -1;
+  int best = -256;
+#pragma unroll
+  for (int pol = 0; pol < 2; ++pol) {
+    int e[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) e[k] = pol ? -d[k] : d[k];
+    int m2[16], m4[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m2[k] = min(e[k], e[(k + 1) & 15]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m4[k] = min(m2[k], m2[(k + 2) & 15]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int m9 = min(min(m4[k], m4[(k + 4) & 15]), e[(k + 8) & 15]);
+      best = max(best, m9);
+    }
+  }
+  const int score = max(best - 1, -1);
+  return score >= tmin ? score : -1;
+}
+
+template <int L>
+__global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __restrict__ cams,
+                                                           const FrameTable* __restrict__ frame, int cam_begin,
+                                                           int cam_end, int tile_base, int tmin, int margin) {
+  using G = PyrGeom<L>;
+  __shared__ __align__(16) uint8_t s_l0[G::sh0 * G::sw0];
+  __shared__ uint8_t s_score[kScoreEdge * kScoreEdge];
+  __shared__ uint16_t s_v[G::vbytes];
+  __shared__ uint8_t s_lv[2][G::lvl_bytes];
+
+  const int gtile = tile_base + (int)blockIdx.x;
+  int c = cam_begin;
+  while (c + 1 < cam_end && cams[c + 1].tile_begin <= gtile) ++c;
+  const CamDesc& cd = cams[c];
+  const FrameCam& fc = frame->cam[c];
+  if (!fc.active) return;
+  const int t = gtile - cd.tile_begin;
+  const int x0 = (t % cd.tiles_x) * kTile, y0 = (t / cd.tiles_x) * kTile;
+  const int W = cd.w, H = cd.h, par = fc.parity;
+  const int tid = threadIdx.x;
+
+  // ---- stage level 0 (tile + apron) -------------------------------------
+  const int ox0 = x0 - G::a0x, oy0 = y0 - G::a0;
+  const uint8_t* src = fc.src;
+  const int sp = fc.src_pitch;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)sp) & 3) == 0;
+  constexpr int qrow = G::sw0 / 4;
+  for (int i = tid; i < G::sh0 * qrow; i += kPyrThreads) {
+    const int r = i / qrow, q = i - r * qrow;
+    const int y = oy0 + r, x = ox0 + 4 * q;
+    uint32_t v = 0;
+    if (y >= 0 && y < H) {
+      const uint8_t* row = src + (size_t)y * sp;
+      if (aligned && x >= 0 && x + 3 < W) {
+        v = *reinterpret_cast<const uint32_t*>(row + x);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (x + k >= 0 && x + k < W) v |= (uint32_t)row[x + k] << (8 * k);
+      }
+    }
+    *reinterpret_cast<uint32_t*>(&s_l0[r * G::sw0 + 4 * q]) = v;
+  }
+  __syncthreads();
+
+  // ---- copy level 0 into the own pyramid when it came from outside --------
+  if (fc.copy_l0) {
+    uint8_t* dst = cd.lvl[par][0];
+    const int dp = cd.pitch[0];
+    for (int i = tid; i < kTile * (kTile / 4); i += kPyrThreads) {
+      const int r = i / (kTile / 4), q = i - r * (kTile / 4);
+      const int y = y0 + r, x = x0 + 4 * q;
+      if (y >= H || x >= W) continue;
+      const uint8_t* s = &s_l0[(y - oy0) * G::sw0 + (x - ox0)];
+      if (x + 3 < W) {
+        *reinterpret_cast<uint32_t*>(dst + (size_t)y * dp + x) = *reinterpret_cast<const uint32_t*>(s);
+      } else {
+        for (int k = 0; x + k < W; ++k) dst[(size_t)y * dp + x + k] = s[k];
+      }
+    }
+  }
+
+  // ---- FAST-9 + strict NMS + per-cell key ---------------------------------
+  if (cd.detect) {
+    for (int i = tid; i < kScoreEdge * kScoreEdge; i += kPyrThreads) {
+      const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
+      int s8 = 0;
+      if (sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin) {
+        const int s = fast_score_lds(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, tmin);
+        s8 = s + 1;  // 0: below the last threshold
+      }
+      s_score[i] = (uint8_t)s8;
+    }
+    __syncthreads();
+    uint32_t* keys = cd.keys[par];
+    for (int i = tid; i < kTile * kTile; i += kPyrThreads) {
+      const int ly = i / kTile, lx = i % kTile;
+      const int x = x0 + lx, y = y0 + ly;
+      if (x < margin || x > W - 1 - margin || y < margin || y > H - 1 - margin) continue;
+      const uint8_t* sc = &s_score[(ly + 1) * kScoreEdge + lx + 1];
+      const int s = sc[0];
+      if (!s) continue;
+      const bool peak = s > sc[-kScoreEdge - 1] && s > sc[-kScoreEdge] && s > sc[-kScoreEdge + 1] && s > sc[-1] &&
+                        s > sc[1] && s > sc[kScoreEdge - 1] && s > sc[kScoreEdge] && s > sc[kScoreEdge + 1];
+      if (!peak) continue;
+      const uint32_t key = ((uint32_t)(s - 1) << 24) | (0xFFFFFFu - (uint32_t)(y * W + x));
+      const int cell = (y / cd.cell) * cd.ncx + x / cd.cell;
+      atomicMax(&keys[cell], key);
+    }
+  }
+
+  // ---- coarser levels from LDS (eqs. 2-3) ---------------------------------
+  if constexpr (L > 1) {
+    const uint8_t* cur = s_l0;
+    int cur_ox = ox0, cur_oy = oy0, cur_p = G::sw0;
+#pragma unroll
+    for (int l = 0; l < L - 1; ++l) {
+      const int Wc = W >> l, Hc = H >> l, Wn = W >> (l + 1), Hn = H >> (l + 1);
+      const int S = G::region(l + 1);
+      const int o_x = (x0 >> (l + 1)) - G::apron(l + 1), o_y = (y0 >> (l + 1)) - G::apron(l + 1);
+      const int X0 = max(0, o_x), X1 = min(Wn - 1, o_x + S - 1);
+      const int Y0 = max(0, o_y), Y1 = min(Hn - 1, o_y + S - 1);
+      const int vy0 = max(0, 2 * o_y - 2), vy1 = min(Hc - 1, 2 * (o_y + S - 1) + 2);
+      const int ncol = X1 - X0 + 1;
+      // block-uniform: a level with nothing inside the image ends the tile
+      if (X0 > X1 || Y0 > Y1) break;
+      {
+        // eq. (2): horizontal pass over level-l rows vy0..vy1
+        const int nv = (vy1 - vy0 + 1) * ncol;
+        for (int i = tid; i < nv; i += kPyrThreads) {
+          const int r = i / ncol, X = X0 + i % ncol;
+          const uint8_t* row = cur + (vy0 + r - cur_oy) * cur_p - cur_ox;
+          const int xa = 2 * X;
+          const uint32_t v = row[clampi(xa - 2, 0, Wc - 1)] + 4u * row[clampi(xa - 1, 0, Wc - 1)] +
+                             6u * row[xa] + 4u * row[clampi(xa + 1, 0, Wc - 1)] + row[clampi(xa + 2, 0, Wc - 1)];
+          s_v[r * S + (X - o_x)] = (uint16_t)v;
+        }
+        __syncthreads();
+        // eq. (3): vertical pass, +128 then >> 8
+        uint8_t* nxt = s_lv[l & 1];
+        uint8_t* gdst = cd.lvl[par][l + 1];
+        const int gp = cd.pitch[l + 1];
+        const int tx0 = x0 >> (l + 1), ty0 = y0 >> (l + 1), te = kTile >> (l + 1);
+        const int nn = (Y1 - Y0 + 1) * ncol;
+        for (int i = tid; i < nn; i += kPyrThreads) {
+          const int Y = Y0 + i / ncol, X = X0 + i % ncol;
+          const uint16_t* col = s_v + (X - o_x);
+          const int ya = 2 * Y;
+          const uint32_t s = col[(clampi(ya - 2, 0, Hc - 1) - vy0) * S] + 4u * col[(clampi(ya - 1, 0, Hc - 1) - vy0) * S] +
+                             6u * col[(ya - vy0) * S] + 4u * col[(clampi(ya + 1, 0, Hc - 1) - vy0) * S] +
+                             col[(clampi(ya + 2, 0, Hc - 1) - vy0) * S];
+          const uint8_t val = (uint8_t)((s + 128u) >> 8);
+          nxt[(Y - o_y) * S + (X - o_x)] = val;
+          if (X >= tx0 && X < tx0 + te && Y >= ty0 && Y < ty0 + te) gdst[(size_t)Y * gp + X] = val;
+        }
+        __syncthreads();
+        cur = nxt;
+        cur_ox = o_x;
+        cur_oy = o_y;
+        cur_p = S;
+      }
+    }
+  }
+}
+
+template <int L>
+hipError_t launch_L(const CamDesc* cams, const FrameTable* frame, int cam_begin, int cam_end, int tile_base,
+                    int n_tiles, int tmin, int margin, hipStream_t s) {
+  hipLaunchKernelGGL(k_pyr_detect<L>, dim3(n_tiles), dim3(kPyrThreads), 0, s, cams, frame, cam_begin, cam_end,
+                     tile_base, tmin, margin);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Static LDS bytes of the pyramid/detector kernel for `levels` (0 if unknown).
+size_t pyr_detect_lds_bytes(int levels) {
+  hipFuncAttributes a{};
+  hipError_t e = hipErrorInvalidValue;
+  switch (levels) {
+    case 1: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<1>)); break;
+    case 2: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<2>)); break;
+    case 3: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<3>)); break;
+    case 4: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<4>)); break;
+    case 5: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<5>)); break;
+    case 6: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<6>)); break;
+    default: break;
+  }
+  return e == hipSuccess ? a.sharedSizeBytes : 0;
+}
+
+hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end,
+                                   int tile_base, int n_tiles, int levels, int tmin, int margin, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (levels) {
+    case 1: return launch_L<1>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 2: return launch_L<2>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 3: return launch_L<3>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 4: return launch_L<4>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 5: return launch_L<5>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 6: return launch_L<6>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace vio

@@ -1,0 +1,266 @@
+// Keypoint bookkeeping after tracking (Sec. III-B/III-D): cell mask, global
+// cap, new identifiers, stable compaction of the surviving tracks, acceptance
+// of stereo matches and the output records TR_t / DET_t.
+//
+// One 1024-thread workgroup per stream; camera groups (mono camera or stereo
+// pair) are handled in order so identifiers are assigned in (group, cell)
+// order. Every ordering decision is a prefix count over flags (wave ballots
+// plus a scan of the 16 wave totals), so the result does not depend on thread
+// timing.
+//
+// Rules (all on integers):
+//  * a cell is masked when it holds at least k surviving tracks of the camera;
+//  * the candidates are the winners of the unmasked cells; the best
+//    (score desc, cell asc) up to cap - live are kept, found with a 256-bin
+//    score histogram instead of a sort;
+//  * the kept ones get consecutive identifiers in cell order;
+//  * a stereo match is accepted while the right camera has room.
+#include "fe_common.h"
+
+namespace vio {
+
+constexpr int kMaxCells = 8192;
+
+namespace {
+
+constexpr int kWaves = kSelectThreads / 64;
+
+struct ScanScratch {
+  int wave_tot[kWaves];
+  int wave_off[kWaves + 1];
+};
+
+// Exclusive prefix count of `flag` over the block's threads in thread order;
+// returns the thread's offset and sets `total`. All threads must call it.
+__device__ __forceinline__ int block_scan_flag(bool flag, ScanScratch& sc, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int below = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) sc.wave_tot[wave] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      sc.wave_off[w] = acc;
+      acc += sc.wave_tot[w];
+    }
+    sc.wave_off[kWaves] = acc;
+  }
+  __syncthreads();
+  const int r = sc.wave_off[wave] + below;
+  total = sc.wave_off[kWaves];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ vio_track make_rec(int64_t id, int cam, int status, float x, float y, float th, float fb,
+                                              float res, int age, int score) {
+  vio_track t;
+  t.id = id;
+  t.x = x;
+  t.y = y;
+  t.theta = th;
+  t.fb_err = fb;
+  t.resid_rms = res;
+  t.age = age;
+  t.camera = (int16_t)cam;
+  t.status = (int16_t)status;
+  t.score = score;
+  return t;
+}
+
+__device__ __forceinline__ Kp make_kp(int64_t id, float x, float y, float px, float py, int age) {
+  Kp k;
+  k.id = id;
+  k.x = x;
+  k.y = y;
+  k.px = px;
+  k.py = py;
+  k.age = age;
+  k.reserved = 0;
+  return k;
+}
+
+// Carries camera c's previous keypoints into its current state: the survivors
+// of temporal tracking (all of them when there was no previous frame) in their
+// old order, with their records. Adds the survivors to `occ` when given.
+// Returns the survivor count; *n_rec receives the number of records written.
+__device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev, unsigned* occ, ScanScratch& sc,
+                               int* n_rec) {
+  const int P = fc.parity, Q = P ^ 1;
+  int base = 0;
+  for (int j0 = 0; j0 < n_prev; j0 += kSelectThreads) {
+    const int j = j0 + (int)threadIdx.x;
+    bool alive = false;
+    Kp kp{};
+    TrackRes r{};
+    if (j < n_prev) {
+      kp = cd.state[Q][j];
+      if (fc.has_prev) {
+        r = cd.res[j];
+        alive = r.status == VIO_TRACKED;
+      } else {
+        r.x = kp.x;
+        r.y = kp.y;
+        alive = true;
+      }
+    }
+    int total;
+    const int pos = base + block_scan_flag(alive, sc, total);
+    if (j < n_prev) {
+      if (alive) {
+        if (occ) {
+          const int cx = (int)floorf(r.x / (float)cd.cell), cy = (int)floorf(r.y / (float)cd.cell);
+          if (cx >= 0 && cx < cd.ncx && cy >= 0 && cy < cd.ncy) atomicAdd(&occ[cy * cd.ncx + cx], 1u);
+        }
+        cd.state[P][pos] = fc.has_prev ? make_kp(kp.id, r.x, r.y, kp.x, kp.y, kp.age + 1) : kp;
+      }
+      if (fc.has_prev)
+        cd.rec[j] = make_rec(kp.id, cd.local, r.status, r.x, r.y, r.theta, r.fb, r.resid,
+                             alive ? kp.age + 1 : kp.age, -1);
+    }
+    base += total;
+  }
+  *n_rec = fc.has_prev ? n_prev : 0;
+  return base;
+}
+
+__global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __restrict__ cams,
+                                                          const FrameTable* __restrict__ frame, Counters* cnt,
+                                                          const int* __restrict__ stream_cams, Tuning tune) {
+  __shared__ ScanScratch sc;
+  __shared__ unsigned s_occ[kMaxCells];
+  __shared__ uint16_t s_sel[kMaxCells];
+  __shared__ int s_hist[256];
+  __shared__ int s_thr[2];
+  const int s = blockIdx.x;
+  const int cam0 = stream_cams[2 * s], ncam = stream_cams[2 * s + 1];
+  if (!frame->cam[cam0].active) return;
+  const int stream = cams[cam0].stream;
+  const int64_t id0 = cnt->next_id[stream];
+  int64_t next_id = id0;
+  const int step = ncam >= 2 ? 2 : 1;
+  for (int g = 0; g < ncam; g += step) {
+    const int lc = cam0 + g;
+    const CamDesc& L = cams[lc];
+    const FrameCam& fl = frame->cam[lc];
+    const int P = fl.parity, Q = P ^ 1;
+    const int ncells = L.ncells;
+    for (int i = threadIdx.x; i < ncells; i += kSelectThreads) s_occ[i] = 0;
+    for (int i = threadIdx.x; i < 256; i += kSelectThreads) s_hist[i] = 0;
+    __syncthreads();
+
+    // ---- left / mono camera: survivors and occupancy ----------------------
+    int n_rec = 0;
+    const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec);
+    __syncthreads();
+
+    // ---- candidates of unmasked cells, score histogram --------------------
+    const uint32_t* keys = L.keys[P];
+    for (int i = threadIdx.x; i < ncells; i += kSelectThreads) {
+      const uint32_t key = keys[i];
+      if (key && (int)s_occ[i] < tune.k) atomicAdd(&s_hist[key >> 24], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int room = max(0, L.cap - n_surv);
+      int total = 0;
+      for (int v = 0; v < 256; ++v) total += s_hist[v];
+      int thr = -1, rem = 0;
+      if (room == 0) {
+        thr = 256;
+      } else if (total > room) {
+        int acc = 0;
+        for (int v = 255; v >= 0; --v) {
+          if (acc + s_hist[v] >= room) {
+            thr = v;
+            rem = room - acc;
+            break;
+          }
+          acc += s_hist[v];
+        }
+      }
+      s_thr[0] = thr;
+      s_thr[1] = rem;
+    }
+    __syncthreads();
+    const int thr = s_thr[0], rem = s_thr[1];
+
+    // ---- selection in cell order, identifiers, DET_t records --------------
+    int n_new = 0, eq_base = 0;
+    for (int c0 = 0; c0 < ncells; c0 += kSelectThreads) {
+      const int cell = c0 + (int)threadIdx.x;
+      const uint32_t key = cell < ncells ? keys[cell] : 0u;
+      const bool cand = key && (int)s_occ[cell < ncells ? cell : 0] < tune.k;
+      const int score = (int)(key >> 24);
+      const bool is_eq = cand && score == thr;
+      int eq_tot, sel_tot;
+      const int eq_rank = eq_base + block_scan_flag(is_eq, sc, eq_tot);
+      const bool sel = cand && (score > thr || (is_eq && eq_rank < rem));
+      const int rank = n_new + block_scan_flag(sel, sc, sel_tot);
+      if (sel) {
+        const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
+        const float x = (float)(idx % L.w), y = (float)(idx / L.w);
+        const int64_t id = next_id + rank;
+        L.state[P][n_surv + rank] = make_kp(id, x, y, x, y, 0);
+        L.rec[n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
+        s_sel[rank] = (uint16_t)cell;
+      }
+      eq_base += eq_tot;
+      n_new += sel_tot;
+    }
+    if (threadIdx.x == 0) {
+      cnt->n_live[P][lc] = n_surv + n_new;
+      cnt->rec_count[lc] = n_rec + n_new;
+    }
+    for (int i = threadIdx.x; i < ncells; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
+    __syncthreads();
+
+    // ---- right camera of a pair: survivors, then accepted stereo matches ---
+    if (step == 2) {
+      const int rc = lc + 1;
+      const CamDesc& R = cams[rc];
+      const FrameCam& fr = frame->cam[rc];
+      const int PR = fr.parity;
+      int n_rec_r = 0;
+      const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r);
+      int m_base = 0;
+      for (int i0 = 0; i0 < n_new; i0 += kSelectThreads) {
+        const int i = i0 + (int)threadIdx.x;
+        const bool valid = i < n_new;
+        TrackRes sr{};
+        if (valid) sr = L.sres[s_sel[i]];
+        const bool matched = valid && sr.status == VIO_TRACKED;
+        int m_tot;
+        const int mrank = m_base + block_scan_flag(matched, sc, m_tot);
+        if (valid) {
+          const int64_t id = next_id + i;
+          const bool accepted = matched && n_surv_r + mrank < R.cap;
+          const int st = matched ? (accepted ? VIO_MATCHED : VIO_LOST_CAP) : sr.status;
+          R.rec[n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
+          if (accepted) R.state[PR][n_surv_r + mrank] = make_kp(id, sr.x, sr.y, sr.x, sr.y, 0);
+        }
+        m_base += m_tot;
+      }
+      if (threadIdx.x == 0) {
+        cnt->n_live[PR][rc] = n_surv_r + min(m_base, max(0, R.cap - n_surv_r));
+        cnt->rec_count[rc] = n_rec_r + n_new;
+      }
+      __syncthreads();
+    }
+    next_id += n_new;
+  }
+  if (threadIdx.x == 0) cnt->next_id[stream] = next_id;
+}
+
+}  // namespace
+
+hipError_t launch_select(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt, const int* d_stream_cams,
+                         int n_streams_launch, int /*cams_per_stream_max*/, Tuning tune, hipStream_t s) {
+  if (n_streams_launch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select, dim3(n_streams_launch), dim3(kSelectThreads), 0, s, d_cams, d_frame, d_cnt,
+                     d_stream_cams, tune);
+  return hipGetLastError();
+}
+
+}  // namespace vio
