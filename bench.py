@@ -54,6 +54,24 @@ def pyramid_bytes(width, height, levels, cams, copy_l0=True):
     return a0 * (2 if copy_l0 else 1) + p1
 
 
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed counter profile of this workload,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    k = prof.get("kernels", {}).get(kernel)
+    if not k or k.get("traffic_bytes") is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2609_30459_amd", "csrc", k["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != k["source_sha256_16"]:
+            return None
+    return k["traffic_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,7 +81,18 @@ def main():
     ap.add_argument("--seq", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the frontend's streams are "
               "independent and would shard across GPUs without communication", file=sys.stderr)
@@ -161,7 +190,7 @@ def main():
     kd = kernels[dom]
     roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd.get("achieved"), "peak": kd.get("peak"),
             "unit": kd.get("unit"), "frac": (kd["achieved"] / kd["peak"]) if kd.get("achieved") else None,
-            "traffic": None, "avg_ms": kd["avg_ms"]}
+            "traffic": measured_traffic(w.name, dom), "avg_ms": kd["avg_ms"]}
 
     # ---- CPU baseline: the oracle on a bounded sample of the same sequence ---
     cpu = None
