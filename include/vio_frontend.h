@@ -93,7 +93,11 @@ typedef struct vio_frontend_params {
   int32_t learned_levels; /* tracker budget when the learned guess is used */
   int32_t learned_iters;
   float learned_rho;      /* residual RMS above which a learned track falls back to the plain tracker */
+  uint32_t flags;         /* VIO_FLAG_* */
 } vio_frontend_params;
+
+/* vio_frontend_params.flags */
+#define VIO_FLAG_EAGER 1u /* launch the per-frame kernels one by one instead of replaying a captured hipGraph */
 
 /* Output record: one per previous keypoint of each camera (tracked or lost) and
  * one per new detection / stereo match, sorted by (camera, id). */
@@ -131,7 +135,8 @@ typedef struct vio_stats {
   int64_t frames;        /* frames processed by the handle */
   double last_gpu_ms;    /* device time of the last frame (first kernel to last) */
   double last_stage_ms[3]; /* HIP-event time of the last frame's pyramid+detector, tracker and
-                              selection kernels, on the stream they ran on */
+                              selection kernels, on the stream they ran on; -1 when the frame
+                              was replayed as a graph (VIO_FLAG_EAGER gives per-kernel times) */
   int32_t last_tracked;  /* VIO_TRACKED records of the last frame, all cameras */
   int32_t last_lost;     /* lost temporal records of the last frame */
   int32_t last_detected; /* VIO_DETECTED records */

@@ -27,7 +27,7 @@ def default_params() -> _n.vio_frontend_params:
 
 def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40, 20, 10, 5), edge_margin=8,
                 max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0, learned_levels=2,
-                learned_iters=3, learned_rho=0.0) -> _n.vio_frontend_params:
+                learned_iters=3, learned_rho=0.0, eager=False) -> _n.vio_frontend_params:
     p = default_params()
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
     p.n_thresholds = len(thresholds)
@@ -36,6 +36,7 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
     p.edge_margin, p.max_keypoints = edge_margin, max_keypoints
     p.fb_threshold, p.disparity0, p.init_mode = fb_threshold, disparity0, init_mode
     p.learned_levels, p.learned_iters, p.learned_rho = learned_levels, learned_iters, learned_rho
+    p.flags = _n.VIO_FLAG_EAGER if eager else 0
     return p
 
 

@@ -43,7 +43,11 @@ class vio_frontend_params(ctypes.Structure):
         ("thresholds", ctypes.c_int32 * 4), ("edge_margin", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
         ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float), ("init_mode", ctypes.c_int32),
         ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32), ("learned_rho", ctypes.c_float),
+        ("flags", ctypes.c_uint32),
     ]
+
+
+VIO_FLAG_EAGER = 1
 
 
 class vio_kp_prediction(ctypes.Structure):

@@ -13,7 +13,7 @@ constexpr int kMaxLevels = VIO_MAX_LEVELS;
 constexpr int kMaxCams = VIO_MAX_CAMERAS;
 constexpr int kPatch = 52;      // pattern points (Sec. III-E)
 constexpr int kTile = 64;       // level-0 output tile edge of the pyramid/detector kernel
-constexpr int kPyrThreads = 256;
+constexpr int kPyrThreads = 1024;
 constexpr int kTrackWaves = 4;  // waves (keypoints) per tracking block
 constexpr int kSelectThreads = 1024;
 
@@ -51,7 +51,8 @@ struct CamDesc {
   TrackRes* res;                     // temporal results [cap]
   uint32_t* keys[2];                 // per-cell packed winner keys, by frame parity [ncells]
   TrackRes* sres;                    // stereo match of every cell winner [ncells]
-  vio_track* rec;                    // output records [rec_cap]
+  vio_track* rec;                    // output records [rec_cap], in mapped pinned host memory
+  int32_t* rec_count_out;            // record count of the last frame, mapped pinned host memory
   int rec_cap;
 };
 

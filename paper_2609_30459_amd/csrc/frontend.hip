@@ -3,8 +3,9 @@
 // Device memory is one arena allocated at create (Sec. III-B: every resource
 // is allocated once and reused). Per frame the runtime fills a small frame
 // table in pinned memory, copies it (and the images, for a host push) to the
-// device, launches three kernels on one stream, copies the records back and
-// waits: the synchronous submit-and-fence of the paper's pipeline.
+// device, launches three kernels on one stream and waits: the synchronous
+// submit-and-fence of the paper's pipeline. The last kernel writes the
+// records into mapped pinned host memory, so nothing is copied back.
 //
 // Per camera and frame parity p the arena holds: pyramid levels, keypoint
 // state, per-cell winner keys; plus temporal and stereo results and records.
@@ -36,6 +37,7 @@ struct StreamInfo {
   int tile_begin = 0, n_tiles = 0;
   int seg_begin = 0, n_segs = 0, n_items = 0;
   size_t rec_off = 0, rec_n = 0;  // record range (in vio_track units) of the stream's cameras
+  hipGraphExec_t graph = nullptr;  // captured per-frame submit, replayed every frame
 };
 
 }  // namespace
@@ -56,11 +58,11 @@ struct vio_frontend {
   TrackSeg* d_segs = nullptr;
   int* d_stream_cams = nullptr;
   Prediction* d_pred = nullptr;
-  vio_track* d_rec = nullptr;
   int pred_cap = 0;
+  std::vector<size_t> rec_host_off;  // per camera, in records
   // pinned host
   FrameTable* h_frame = nullptr;
-  Counters* h_cnt = nullptr;
+  int32_t* h_rec_count = nullptr;
   vio_track* h_rec = nullptr;
   uint8_t* h_stage = nullptr;
   size_t stage_bytes = 0;
@@ -70,6 +72,7 @@ struct vio_frontend {
   int device = 0;
   bool poisoned = false;
   bool fault_device = false;
+  bool eager = false;  // graph capture off (flag) or unavailable
   std::string err;
   vio_stats stats{};
 };
@@ -140,9 +143,11 @@ void vio_frontend_default_params(vio_frontend_params* p) {
 void vio_frontend_destroy(vio_frontend* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto& si : h->streams)
+    if (si.graph) (void)hipGraphExecDestroy(si.graph);
   if (h->arena) (void)hipFree(h->arena);
   if (h->h_frame) (void)hipHostFree(h->h_frame);
-  if (h->h_cnt) (void)hipHostFree(h->h_cnt);
+  if (h->h_rec_count) (void)hipHostFree(h->h_rec_count);
   if (h->h_rec) (void)hipHostFree(h->h_rec);
   if (h->h_stage) (void)hipHostFree(h->h_stage);
   if (h->h_pred) (void)hipHostFree(h->h_pred);
@@ -244,7 +249,6 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   const size_t o_segs = take(sizeof(TrackSeg) * h->segs.size());
   const size_t o_sc = take(sizeof(int) * h->stream_cams.size());
   const size_t o_pred = take(sizeof(Prediction) * std::max(1, h->pred_cap));
-  const size_t o_rec = take(sizeof(vio_track) * rec_total);
   const size_t arena_bytes = off;
 
   // ---- device ---------------------------------------------------------------
@@ -284,22 +288,30 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->d_segs = reinterpret_cast<TrackSeg*>(base + o_segs);
   h->d_stream_cams = reinterpret_cast<int*>(base + o_sc);
   h->d_pred = reinterpret_cast<Prediction*>(base + o_pred);
-  h->d_rec = reinterpret_cast<vio_track*>(base + o_rec);
-  for (int c = 0; c < n_cams; ++c) h->cams[c].rec = h->d_rec + co[c].rec;
-  HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->d_segs, h->segs.data(), sizeof(TrackSeg) * h->segs.size(), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->d_stream_cams, h->stream_cams.data(), sizeof(int) * h->stream_cams.size(),
                          hipMemcpyHostToDevice));
-  // pinned host buffers
+  // pinned host buffers; records and their counts are written by the
+  // selection kernel through the device mapping of h_rec / h_rec_count
   h->stage_bytes = stage;
   if (hipHostMalloc((void**)&h->h_frame, sizeof(FrameTable)) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_cnt, sizeof(Counters)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_rec_count, sizeof(int32_t) * n_cams) != hipSuccess ||
       hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * rec_total) != hipSuccess ||
       hipHostMalloc((void**)&h->h_stage, stage) != hipSuccess ||
       hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * std::max(1, h->pred_cap)) != hipSuccess)
     return fail(h, VIO_ENOMEM, "pinned host buffers");
   std::memset(h->h_frame, 0, sizeof(FrameTable));
-  std::memset(h->h_cnt, 0, sizeof(Counters));
+  std::memset(h->h_rec_count, 0, sizeof(int32_t) * n_cams);
+  vio_track* rec_dev = nullptr;
+  int32_t* cnt_dev = nullptr;
+  HIP_CHECK(h, hipHostGetDevicePointer((void**)&rec_dev, h->h_rec, 0));
+  HIP_CHECK(h, hipHostGetDevicePointer((void**)&cnt_dev, h->h_rec_count, 0));
+  for (int c = 0; c < n_cams; ++c) {
+    h->cams[c].rec = rec_dev + co[c].rec;
+    h->cams[c].rec_count_out = cnt_dev + c;
+    h->rec_host_off.push_back(co[c].rec);
+  }
+  HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
   HIP_CHECK(h, hipStreamCreate(&h->stream));
   for (hipEvent_t& e : h->ev) HIP_CHECK(h, hipEventCreate(&e));
   return VIO_OK;
@@ -329,6 +341,7 @@ int vio_frontend_create(const vio_stream_desc* streams, int32_t n_streams, const
   auto* h = new (std::nothrow) vio_frontend();
   if (!h) return VIO_ENOMEM;
   h->P = *params;
+  h->eager = (params->flags & VIO_FLAG_EAGER) != 0;
   const int rc = create_impl(h, streams, n_streams);
   if (rc != VIO_OK) {
     vio_frontend_destroy(h);
@@ -352,29 +365,66 @@ static Tuning tuning(const vio_frontend* h) {
   return t;
 }
 
+// Enqueues one frame of stream s on `st`: frame table copy and the three
+// kernels, with a timing event between kernels when `timed` (eager launches).
+// The untimed sequence is what the stream's graph captures; nothing in it
+// changes between frames (per-frame inputs live in the frame table).
+static hipError_t enqueue_frame(vio_frontend* h, int s, hipStream_t st, bool timed) {
+  StreamInfo& si = h->streams[s];
+  const Tuning tune = tuning(h);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h->d_frame, h->h_frame, sizeof(FrameTable), hipMemcpyHostToDevice, st))) return e;
+  if (timed && (e = hipEventRecord(h->ev[0], st))) return e;
+  if ((e = launch_pyr_detect_range(h->d_cams, h->d_frame, si.first_cam, si.first_cam + si.n_cams, si.tile_begin,
+                                   si.n_tiles, tune.levels, tune.tmin, tune.margin, st)))
+    return e;
+  if (timed && (e = hipEventRecord(h->ev[1], st))) return e;
+  if ((e = launch_track(h->d_cams, h->d_frame, h->d_cnt, h->d_segs + si.seg_begin, si.n_segs, si.n_items,
+                        h->d_pred, tune, st)))
+    return e;
+  if (timed && (e = hipEventRecord(h->ev[2], st))) return e;
+  if ((e = launch_select(h->d_cams, h->d_frame, h->d_cnt, h->d_stream_cams + 2 * s, 1, si.n_cams, tune, st))) return e;
+  return timed ? hipEventRecord(h->ev[3], st) : hipSuccess;
+}
+
+// Captures the stream's frame into a graph on first use; a capture failure
+// switches the handle to eager launches for good.
+static void ensure_graph(vio_frontend* h, int s) {
+  StreamInfo& si = h->streams[s];
+  if (h->eager || si.graph) return;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (ok) {
+    const hipError_t e = enqueue_frame(h, s, h->stream, false);
+    ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && e == hipSuccess && g;
+  }
+  if (ok) ok = hipGraphInstantiate(&si.graph, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {
+    si.graph = nullptr;
+    h->eager = true;
+    (void)hipGetLastError();
+  }
+}
+
 // Runs one frame of stream s whose level-0 sources are already in h_frame.
 static int run_frame(vio_frontend* h, int s, hipStream_t st) {
   StreamInfo& si = h->streams[s];
-  const Tuning tune = tuning(h);
-  HIP_CHECK(h, hipMemcpyAsync(h->d_frame, h->h_frame, sizeof(FrameTable), hipMemcpyHostToDevice, st));
-  HIP_CHECK(h, hipEventRecord(h->ev[0], st));
-  HIP_CHECK(h, launch_pyr_detect_range(h->d_cams, h->d_frame, si.first_cam, si.first_cam + si.n_cams, si.tile_begin,
-                                       si.n_tiles, tune.levels, tune.tmin, tune.margin, st));
-  HIP_CHECK(h, hipEventRecord(h->ev[1], st));
-  HIP_CHECK(h, launch_track(h->d_cams, h->d_frame, h->d_cnt, h->d_segs + si.seg_begin, si.n_segs, si.n_items,
-                            h->d_pred, tune, st));
-  HIP_CHECK(h, hipEventRecord(h->ev[2], st));
-  HIP_CHECK(h, launch_select(h->d_cams, h->d_frame, h->d_cnt, h->d_stream_cams + 2 * s, 1, si.n_cams, tune, st));
-  HIP_CHECK(h, hipEventRecord(h->ev[3], st));
-  HIP_CHECK(h, hipMemcpyAsync(h->h_cnt, h->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(h, hipMemcpyAsync(h->h_rec + si.rec_off, h->d_rec + si.rec_off, sizeof(vio_track) * si.rec_n,
-                              hipMemcpyDeviceToHost, st));
+  ensure_graph(h, s);
+  if (si.graph) {
+    // events around the graph: the frame's device time (per-kernel times need eager launches)
+    HIP_CHECK(h, hipEventRecord(h->ev[0], st));
+    HIP_CHECK(h, hipGraphLaunch(si.graph, st));
+    HIP_CHECK(h, hipEventRecord(h->ev[3], st));
+  } else {
+    HIP_CHECK(h, enqueue_frame(h, s, st, true));
+  }
   HIP_CHECK(h, hipStreamSynchronize(st));
   float ms = 0.f;
   HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[3]));
   for (int k = 0; k < 3; ++k) {
-    float m = 0.f;
-    HIP_CHECK(h, hipEventElapsedTime(&m, h->ev[k], h->ev[k + 1]));
+    float m = -1.f;
+    if (!si.graph) HIP_CHECK(h, hipEventElapsedTime(&m, h->ev[k], h->ev[k + 1]));
     h->stats.last_stage_ms[k] = m;
   }
   si.frames += 1;
@@ -383,8 +433,8 @@ static int run_frame(vio_frontend* h, int s, hipStream_t st) {
   int tr = 0, lost = 0, det = 0, mat = 0;
   for (int k = 0; k < si.n_cams; ++k) {
     const CamDesc& c = h->cams[si.first_cam + k];
-    const int n = h->h_cnt->rec_count[si.first_cam + k];
-    const vio_track* r = h->h_rec + (c.rec - h->d_rec);
+    const int n = h->h_rec_count[si.first_cam + k];
+    const vio_track* r = h->h_rec + h->rec_host_off[si.first_cam + k];
     for (int i = 0; i < n; ++i) {
       switch (r[i].status) {
         case VIO_TRACKED: ++tr; break;
@@ -512,15 +562,14 @@ int vio_frontend_get_tracks(vio_frontend* h, int32_t s, vio_track* out, int32_t 
   const StreamInfo& si = h->streams[s];
   if (si.frames == 0) return fail(h, VIO_ESTATE, "no frame pushed yet");
   int n = 0;
-  for (int k = 0; k < si.n_cams; ++k) n += h->h_cnt->rec_count[si.first_cam + k];
+  for (int k = 0; k < si.n_cams; ++k) n += h->h_rec_count[si.first_cam + k];
   *n_out = n;
   if (capacity < n) return VIO_ETOOSMALL;
   if (n > 0 && !out) return VIO_EINVAL;
   int at = 0;
   for (int k = 0; k < si.n_cams; ++k) {
-    const CamDesc& c = h->cams[si.first_cam + k];
-    const int m = h->h_cnt->rec_count[si.first_cam + k];
-    std::memcpy(out + at, h->h_rec + (c.rec - h->d_rec), sizeof(vio_track) * m);
+    const int m = h->h_rec_count[si.first_cam + k];
+    std::memcpy(out + at, h->h_rec + h->rec_host_off[si.first_cam + k], sizeof(vio_track) * m);
     at += m;
   }
   return VIO_OK;

@@ -1,6 +1,6 @@
 // Fused pyramid + corner detector for gfx950.
 //
-// One 256-thread workgroup owns a 64x64 level-0 tile of one camera. It stages
+// One 1024-thread workgroup owns a 64x64 level-0 tile of one camera. It stages
 // the tile plus an apron in LDS with coalesced dword loads, then
 //  * computes the FAST-9 score (Sec. III-D) of the tile and a one-pixel ring,
 //    keeps strict 3x3 maxima with score >= the last threshold and folds each

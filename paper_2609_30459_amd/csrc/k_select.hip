@@ -1,6 +1,8 @@
 // Keypoint bookkeeping after tracking (Sec. III-B/III-D): cell mask, global
 // cap, new identifiers, stable compaction of the surviving tracks, acceptance
-// of stereo matches and the output records TR_t / DET_t.
+// of stereo matches and the output records TR_t / DET_t, written straight
+// into mapped pinned host memory (the host reads them after the frame's wait,
+// with no copy).
 //
 // One 1024-thread workgroup per stream; camera groups (mono camera or stereo
 // pair) are handled in order so identifiers are assigned in (group, cell)
@@ -212,6 +214,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     if (threadIdx.x == 0) {
       cnt->n_live[P][lc] = n_surv + n_new;
       cnt->rec_count[lc] = n_rec + n_new;
+      *L.rec_count_out = n_rec + n_new;
     }
     for (int i = threadIdx.x; i < ncells; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
     __syncthreads();
@@ -245,6 +248,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       if (threadIdx.x == 0) {
         cnt->n_live[PR][rc] = n_surv_r + min(m_base, max(0, R.cap - n_surv_r));
         cnt->rec_count[rc] = n_rec_r + n_new;
+        *R.rec_count_out = n_rec_r + n_new;
       }
       __syncthreads();
     }

@@ -4,15 +4,27 @@
 // One wave64 tracks one keypoint; lane i < 52 owns pattern point x_i (the 52
 // half-integer offsets of the radius-4 disk, rows v = -3.5..3.5 of 4, 6, 8, 8,
 // 8, 8, 6, 4 points), lanes 52..63 sit on an interior offset with weight 0 so
-// every lane runs the same code. Sums over the pattern use DPP inside each
-// 16-lane row plus four readlanes, a fixed tree that is identical in every
-// lane, so the result is deterministic and wave-uniform. Every branch is taken
-// on a wave vote, so a wave never diverges.
+// every lane runs the same code. Every branch is taken on a wave vote, so a
+// wave never diverges.
 //
-// Per iteration only four sums are needed: since
-//   delta = -sum_i G_i (I'_i / mean' - T_i) = c - (sum_i G_i I'_i) / mean'
-// with c = sum_i G_i T_i fixed per level, one fused reduction of
-// (sum I'_i, sum G_i I'_i) gives both the warped mean and the update.
+// A keypoint's time is its chain of dependent steps (2 passes x L levels x N
+// iterations), each a gather, a reduction and a little wave-uniform math, with
+// about one wave per SIMD at these sizes. The kernel is shaped for that chain:
+//  * sums over the pattern: DPP inside each 16-lane row, then row_bcast:15/31
+//    and one readlane of lane 63 -- a fixed tree, so results are deterministic;
+//  * per iteration one fused reduction of (sum I'_i, sum G_i I'_i), since
+//      delta = -sum_i G_i (I'_i / mean' - T_i) = c - (sum_i G_i I'_i) / mean'
+//    with c = sum_i G_i T_i fixed per level;
+//  * the templates of all levels of a pass are built together (they depend
+//    only on the source image and the keypoint), so their gathers and
+//    reductions overlap instead of sitting between the levels' iterations;
+//  * wave-uniform math uses the hardware reciprocal and sine/cosine, and a
+//    series for the SE(2) exponential;
+//  * gathers read the pyramid through the L1 cache (the patch's lines stay hot
+//    across a level's iterations).
+// Decisions (template fit, degeneracy, leaving the image) are taken in the
+// same order as a level-by-level pass, so the status is that of the paper's
+// procedure.
 //
 // The same launch also runs the stereo matching of every detected cell winner
 // (left camera -> right camera of the pair): those matches depend only on the
@@ -25,26 +37,30 @@ namespace {
 
 constexpr int kW = 64;
 
-template <int ctrl>
+template <int ctrl, int row_mask = 0xF>
 __device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, row_mask, 0xF, false));
 }
 
-__device__ __forceinline__ float lane_bcast(float v, int lane) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
-}
-
-// Sum over the 64 lanes, returned in every lane (wave-uniform).
+// Sum over the 64 lanes, returned as a wave-uniform value: each 16-lane row is
+// reduced with quad permutes and mirrors (every lane of a row then holds the
+// row sum), row_bcast:15 adds row 0 into row 1 and row 2 into row 3,
+// row_bcast:31 adds rows 0+1 into row 3; lane 63 holds (r2+r3)+(r0+r1).
 __device__ __forceinline__ float wave_sum(float v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
+  v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);       // row_half_mirror
+  v += dpp<0x140>(v);       // row_mirror
+  v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 __device__ __forceinline__ bool wave_all(bool p) { return __all(p); }
 __device__ __forceinline__ bool wave_any(bool p) { return __any(p); }
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ void pattern_of(int lane, float& u, float& v, float& w) {
   // rows v = -3.5 .. 3.5 hold 4, 6, 8, 8, 8, 8, 6, 4 points; row starts 0, 4,
@@ -76,7 +92,8 @@ __device__ __forceinline__ bool in_dom(const Level& I, float x, float y) {
   return x >= 0.f && x <= (float)(I.w - 1) && y >= 0.f && y <= (float)(I.h - 1);
 }
 
-// bilinear interpolation on [0, W-1] x [0, H-1]; the caller has checked the domain
+// bilinear interpolation on [0, W-1] x [0, H-1]: ix = min(floor(x), W-2),
+// fx = x - ix (likewise y); the caller has checked the domain
 __device__ __forceinline__ float bilinear(const Level& I, float x, float y) {
   const int ix = min((int)floorf(x), I.w - 2), iy = min((int)floorf(y), I.h - 2);
   const float fx = x - (float)ix, fy = y - (float)iy;
@@ -100,70 +117,116 @@ struct PassOut {
   float tx, ty, th, resid;
 };
 
+// SE(2) exponential of (d0, d1, phi): translation V(phi) (d0, d1) with
+// V = [[a, -b], [b, a]], a = sin(phi)/phi, b = (1 - cos(phi))/phi.
+__device__ __forceinline__ void se2_v(float phi, float& a, float& b) {
+  const float p2 = phi * phi;
+  if (fabsf(phi) < 0.25f) {  // series, error below 2e-9 here
+    a = 1.f - p2 * (1.f / 6.f - p2 * (1.f / 120.f - p2 * (1.f / 5040.f)));
+    b = phi * (0.5f - p2 * (1.f / 24.f - p2 * (1.f / 720.f - p2 * (1.f / 40320.f))));
+  } else {
+    const float ip = rcp(phi);
+    a = __sinf(phi) * ip;
+    b = (1.f - __cosf(phi)) * ip;
+  }
+}
+
 // One coarse-to-fine pass: template on `src` at (px, py), warp from (ix, iy,
 // ith), N Gauss-Newton iterations per level, levels L-1 .. 0, translation
 // doubled between levels, a level whose template does not fit is skipped.
+template <int L>
 __device__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px, float py,
-                            float ix, float iy, float ith, int L, int N, float u, float v, float wgt) {
+                            float ix, float iy, float ith, int N, float u, float v, float wgt) {
   PassOut o{VIO_TRACKED, 0.f, 0.f, 0.f, 0.f};
+  // ---- templates of all levels (Sec. III-E) ------------------------------
+  bool fits[L], valid[L];
+  float T[L], G0[L], G1[L], G2[L], k0[L], k1[L], k2[L];
+  float I0[L], gxr[L], gyr[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    const Level S = level_of(csrc, ssrc, l);
+    const float sc = 1.f / (float)(1 << l);
+    const float sx = px * sc + u, sy = py * sc + v;
+    fits[l] = wave_all(in_dom(S, sx - 1.f, sy) && in_dom(S, sx + 1.f, sy) && in_dom(S, sx, sy - 1.f) &&
+                       in_dom(S, sx, sy + 1.f));
+    I0[l] = gxr[l] = gyr[l] = 0.f;
+    if (fits[l]) {
+      I0[l] = bilinear(S, sx, sy);
+      gxr[l] = (bilinear(S, sx + 1.f, sy) - bilinear(S, sx - 1.f, sy)) * 0.5f;
+      gyr[l] = (bilinear(S, sx, sy + 1.f) - bilinear(S, sx, sy - 1.f)) * 0.5f;
+    }
+  }
+  float mean[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) mean[l] = wave_sum(wgt * I0[l]) * (1.f / 52.f);
+  float J0[L], J1[L], J2[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    const float im = rcp(mean[l]);
+    T[l] = I0[l] * im;
+    J0[l] = gxr[l] * im;
+    J1[l] = gyr[l] * im;
+    J2[l] = J1[l] * u - J0[l] * v;
+  }
+  float h00[L], h01[L], h02[L], h11[L], h12[L], h22[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    h00[l] = wave_sum(wgt * J0[l] * J0[l]);
+    h01[l] = wave_sum(wgt * J0[l] * J1[l]);
+    h02[l] = wave_sum(wgt * J0[l] * J2[l]);
+    h11[l] = wave_sum(wgt * J1[l] * J1[l]);
+    h12[l] = wave_sum(wgt * J1[l] * J2[l]);
+    h22[l] = wave_sum(wgt * J2[l] * J2[l]);
+  }
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    // 3x3 inverse by cofactors (H symmetric); degenerate when det <= 1e-6 (tr/3)^3
+    const float c00 = h11[l] * h22[l] - h12[l] * h12[l];
+    const float c01 = h12[l] * h02[l] - h01[l] * h22[l];
+    const float c02 = h01[l] * h12[l] - h11[l] * h02[l];
+    const float det = h00[l] * c00 + h01[l] * c01 + h02[l] * c02;
+    const float tr3 = (h00[l] + h11[l] + h22[l]) * (1.f / 3.f);
+    const float id = rcp(det);
+    const float i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
+    const float i11 = (h00[l] * h22[l] - h02[l] * h02[l]) * id;
+    const float i12 = (h02[l] * h01[l] - h00[l] * h12[l]) * id;
+    const float i22 = (h00[l] * h11[l] - h01[l] * h01[l]) * id;
+    // weight folded into the gains: lanes 52..63 contribute nothing
+    G0[l] = wgt * (i00 * J0[l] + i01 * J1[l] + i02 * J2[l]);
+    G1[l] = wgt * (i01 * J0[l] + i11 * J1[l] + i12 * J2[l]);
+    G2[l] = wgt * (i02 * J0[l] + i12 * J1[l] + i22 * J2[l]);
+    valid[l] = mean[l] > 0.f && det > 1e-6f * tr3 * tr3 * tr3 &&
+               wave_all(isfinite(G0[l]) && isfinite(G1[l]) && isfinite(G2[l]));
+  }
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    k0[l] = wave_sum(G0[l] * T[l]);
+    k1[l] = wave_sum(G1[l] * T[l]);
+    k2[l] = wave_sum(G2[l] * T[l]);
+  }
+  // ---- coarse-to-fine Gauss-Newton (eqs. 4-5) ------------------------------
   const float s0 = 1.f / (float)(1 << (L - 1));
   float tx = ix * s0, ty = iy * s0, th = ith;
+#pragma unroll
   for (int l = L - 1; l >= 0; --l) {
     if (l < L - 1) {
       tx = tx * 2.f;
       ty = ty * 2.f;
     }
-    const float sc = 1.f / (float)(1 << l);
-    const Level S = level_of(csrc, ssrc, l);
-    const float sx = px * sc + u, sy = py * sc + v;
-    const bool fits = in_dom(S, sx - 1.f, sy) && in_dom(S, sx + 1.f, sy) && in_dom(S, sx, sy - 1.f) &&
-                      in_dom(S, sx, sy + 1.f);
-    if (!wave_all(fits)) {
+    if (!fits[l]) {
       if (l == 0) {
         o.status = VIO_LOST_OOB;
         return o;
       }
       continue;
     }
-    // template (Sec. III-E): mean-normalised samples and gradients
-    const float I0 = bilinear(S, sx, sy);
-    const float gxr = (bilinear(S, sx + 1.f, sy) - bilinear(S, sx - 1.f, sy)) / 2.f;
-    const float gyr = (bilinear(S, sx, sy + 1.f) - bilinear(S, sx, sy - 1.f)) / 2.f;
-    const float mean = wave_sum(wgt * I0) / 52.f;
-    if (!(mean > 0.f)) {
+    if (!valid[l]) {
       o.status = VIO_LOST_DEGENERATE;
       return o;
     }
-    const float T = I0 / mean;
-    const float nx = gxr / mean, ny = gyr / mean;
-    const float J0 = nx, J1 = ny, J2 = ny * u - nx * v;
-    const float h00 = wave_sum(wgt * J0 * J0), h01 = wave_sum(wgt * J0 * J1), h02 = wave_sum(wgt * J0 * J2);
-    const float h11 = wave_sum(wgt * J1 * J1), h12 = wave_sum(wgt * J1 * J2), h22 = wave_sum(wgt * J2 * J2);
-    // 3x3 inverse by cofactors (H symmetric)
-    const float c00 = h11 * h22 - h12 * h12;
-    const float c01 = h12 * h02 - h01 * h22;
-    const float c02 = h01 * h12 - h11 * h02;
-    const float det = h00 * c00 + h01 * c01 + h02 * c02;
-    const float tr3 = (h00 + h11 + h22) / 3.f;
-    if (!(det > 1e-6f * tr3 * tr3 * tr3)) {
-      o.status = VIO_LOST_DEGENERATE;
-      return o;
-    }
-    const float id = 1.f / det;
-    const float i00 = c00 * id, i01 = (h02 * h12 - h01 * h22) * id, i02 = (h01 * h12 - h02 * h11) * id;
-    const float i10 = c01 * id, i11 = (h00 * h22 - h02 * h02) * id, i12 = (h02 * h01 - h00 * h12) * id;
-    const float i20 = c02 * id, i21 = (h01 * h02 - h00 * h12) * id, i22 = (h00 * h11 - h01 * h01) * id;
-    const float G0 = i00 * J0 + i01 * J1 + i02 * J2;
-    const float G1 = i10 * J0 + i11 * J1 + i12 * J2;
-    const float G2 = i20 * J0 + i21 * J1 + i22 * J2;
-    if (wave_any(!(isfinite(G0) && isfinite(G1) && isfinite(G2)))) {
-      o.status = VIO_LOST_DEGENERATE;
-      return o;
-    }
-    const float k0 = wave_sum(wgt * G0 * T), k1 = wave_sum(wgt * G1 * T), k2 = wave_sum(wgt * G2 * T);
     const Level D = level_of(cdst, sdst, l);
     for (int it = 0; it < N; ++it) {
-      const float cs = cosf(th), sn = sinf(th);
+      const float cs = __cosf(th), sn = __sinf(th);
       const float wx = (cs * u - sn * v) + tx, wy = (sn * u + cs * v) + ty;
       if (wave_any(!in_dom(D, wx, wy))) {
         o.status = VIO_LOST_OOB;
@@ -171,26 +234,20 @@ __device__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, 
       }
       const float Iw = bilinear(D, wx, wy);
       const float S0 = wave_sum(wgt * Iw);
-      const float S1 = wave_sum(wgt * G0 * Iw), S2 = wave_sum(wgt * G1 * Iw), S3 = wave_sum(wgt * G2 * Iw);
-      const float mw = S0 / 52.f;
+      const float S1 = wave_sum(G0[l] * Iw), S2 = wave_sum(G1[l] * Iw), S3 = wave_sum(G2[l] * Iw);
+      const float mw = S0 * (1.f / 52.f);
       if (!(mw > 0.f)) {
         o.status = VIO_LOST_OOB;
         return o;
       }
+      const float imw = rcp(mw);
       if (l == 0 && it == N - 1) {
-        const float e = Iw / mw - T;
-        o.resid = sqrtf(wave_sum(wgt * e * e) / 52.f);
+        const float e = Iw * imw - T[l];
+        o.resid = sqrtf(wave_sum(wgt * e * e) * (1.f / 52.f));
       }
-      const float d0 = k0 - S1 / mw, d1 = k1 - S2 / mw, d2 = k2 - S3 / mw;
-      // SE(2) exponential: translation V(phi) (d0, d1)
+      const float d0 = k0[l] - S1 * imw, d1 = k1[l] - S2 * imw, d2 = k2[l] - S3 * imw;
       float a, b;
-      if (fabsf(d2) < 1e-4f) {
-        a = 1.f - d2 * d2 / 6.f;
-        b = d2 / 2.f;
-      } else {
-        a = sinf(d2) / d2;
-        b = (1.f - cosf(d2)) / d2;
-      }
+      se2_v(d2, a, b);
       const float vx = a * d0 - b * d1, vy = b * d0 + a * d1;
       tx = tx + (cs * vx - sn * vy);
       ty = ty + (sn * vx + cs * vy);
@@ -203,8 +260,9 @@ __device__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, 
   return o;
 }
 
+template <int L>
 __device__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px, float py,
-                             float ix, float iy, int L, int N, float fb_thr, float u, float v, float wgt) {
+                             float ix, float iy, int N, float fb_thr, float u, float v, float wgt) {
   TrackRes r;
   r.x = ix;
   r.y = iy;
@@ -213,7 +271,7 @@ __device__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst,
   r.resid = 0.f;
   r.status = VIO_TRACKED;
   r.pad[0] = r.pad[1] = 0;
-  const PassOut f = klt_pass(csrc, ssrc, cdst, sdst, px, py, ix, iy, 0.f, L, N, u, v, wgt);
+  const PassOut f = klt_pass<L>(csrc, ssrc, cdst, sdst, px, py, ix, iy, 0.f, N, u, v, wgt);
   if (f.status != VIO_TRACKED) {
     r.status = f.status;
     return r;
@@ -222,7 +280,7 @@ __device__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst,
   r.y = f.ty;
   r.theta = f.th;
   r.resid = f.resid;
-  const PassOut b = klt_pass(cdst, sdst, csrc, ssrc, f.tx, f.ty, px, py, -f.th, L, N, u, v, wgt);
+  const PassOut b = klt_pass<L>(cdst, sdst, csrc, ssrc, f.tx, f.ty, px, py, -f.th, N, u, v, wgt);
   if (b.status != VIO_TRACKED) {
     r.status = b.status;
     return r;
@@ -233,6 +291,7 @@ __device__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst,
   return r;
 }
 
+template <int L>
 __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __restrict__ cams,
                                                           const FrameTable* __restrict__ frame,
                                                           const Counters* __restrict__ cnt,
@@ -272,18 +331,25 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
         else hi = mid - 1;
       }
     }
-    const TrackRes r =
-        track_fb(cd, P ^ 1, cd, P, kp.x, kp.y, ix, iy, tune.levels, tune.iters, tune.fb_threshold, u, v, wgt);
+    const TrackRes r = track_fb<L>(cd, P ^ 1, cd, P, kp.x, kp.y, ix, iy, tune.iters, tune.fb_threshold, u, v, wgt);
     if (lane == 0) cd.res[j] = r;
   } else {
     const uint32_t key = cd.keys[P][j];
     if (key == 0) return;
     const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
     const float x = (float)(idx % cd.w), y = (float)(idx / cd.w);
-    const TrackRes r = track_fb(cd, P, cams[cd.partner], P, x, y, x - tune.disparity0, y, tune.levels, tune.iters,
-                                tune.fb_threshold, u, v, wgt);
+    const TrackRes r = track_fb<L>(cd, P, cams[cd.partner], P, x, y, x - tune.disparity0, y, tune.iters,
+                                   tune.fb_threshold, u, v, wgt);
     if (lane == 0) cd.sres[j] = r;
   }
+}
+
+template <int L>
+hipError_t launch_L(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
+                    int n_segs, int blocks, const Prediction* d_pred, Tuning tune, hipStream_t s) {
+  hipLaunchKernelGGL(k_track<L>, dim3(blocks), dim3(kW * kTrackWaves), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
+                     d_pred, tune);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -292,9 +358,15 @@ hipError_t launch_track(const CamDesc* d_cams, const FrameTable* d_frame, Counte
                         int n_segs, int n_items, const Prediction* d_pred, Tuning tune, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   const int blocks = (n_items + kTrackWaves - 1) / kTrackWaves;
-  hipLaunchKernelGGL(k_track, dim3(blocks), dim3(kW * kTrackWaves), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
-                     d_pred, tune);
-  return hipGetLastError();
+  switch (tune.levels) {
+    case 1: return launch_L<1>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
+    case 2: return launch_L<2>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
+    case 3: return launch_L<3>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
+    case 4: return launch_L<4>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
+    case 5: return launch_L<5>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
+    case 6: return launch_L<6>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace vio

@@ -192,3 +192,17 @@ def test_abi_errors_on_device():
         # the handle is still usable after rejected calls
         fe.push_stereo_frame(0, 11, [seq.frames[1, 0]])
         assert len(fe.get_tracks(0)) > 0
+
+
+def test_graph_replay_equals_eager_launches():
+    """The captured per-frame graph and one-by-one launches give identical records."""
+    vf = _vf()
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=6, n_frames=5)
+    stream = (2, w.width, w.height, w.max_keypoints, w.cell_size)
+    with vf.Frontend([stream], vf.params_for(w)) as a, vf.Frontend([stream], vf.params_for(w, eager=True)) as b:
+        for t in range(5):
+            a.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            b.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            ra, rb = a.get_tracks(0), b.get_tracks(0)
+            assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), t
