@@ -43,6 +43,8 @@ class Params(ctypes.Structure):
         ("thresholds", ctypes.c_int32 * 4),
         ("edge_margin", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
         ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float),
+        ("init_mode", ctypes.c_int32), ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32),
+        ("learned_rho", ctypes.c_float),
     ]
 
 
@@ -75,6 +77,18 @@ def _lib_():
         lib.orc_fe_get_keypoints.argtypes = [vp, i32, i32, vp, vp, vp]
         lib.orc_fe_next_id.argtypes = [vp]
         lib.orc_fe_next_id.restype = ctypes.c_int64
+        lib.orc_fe_set_mlp.argtypes = [vp, vp, i32]
+        lib.orc_fe_last_fallback.argtypes = [vp]
+        lib.orc_mlp_nparam.restype = i32
+        lib.orc_bf16.argtypes = [ctypes.c_float]
+        lib.orc_bf16.restype = ctypes.c_float
+        lib.orc_features.argtypes = [i32, vp, vp, vp, vp, i32, i32, vp]
+        lib.orc_mlp_forward.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+        lib.orc_mlp_loss_grad.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+        lib.orc_mlp_loss_grad.restype = f64
+        lib.orc_adam.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float]
+        lib.orc_adam.restype = None
         _lib = lib
     return _lib
 
@@ -179,7 +193,8 @@ def inverse3(m):
 
 
 def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40, 20, 10, 5),
-                edge_margin=8, max_keypoints=300, fb_threshold=0.3, disparity0=32.5) -> Params:
+                edge_margin=8, max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0,
+                learned_levels=2, learned_iters=3, learned_rho=0.0) -> Params:
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
@@ -188,6 +203,8 @@ def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40
         p.thresholds[i] = t
     p.edge_margin, p.max_keypoints = edge_margin, max_keypoints
     p.fb_threshold, p.disparity0 = fb_threshold, disparity0
+    p.init_mode, p.learned_levels, p.learned_iters, p.learned_rho = init_mode, learned_levels, learned_iters, \
+        learned_rho
     return p
 
 
@@ -263,3 +280,77 @@ class Frontend:
     @property
     def next_id(self):
         return _lib_().orc_fe_next_id(self._h)
+
+    def set_mlp(self, params):
+        params = np.ascontiguousarray(params, np.float32)
+        assert _lib_().orc_fe_set_mlp(self._h, params.ctypes.data, len(params)) == 0
+
+    @property
+    def last_fallback(self):
+        return _lib_().orc_fe_last_fallback(self._h)
+
+
+# ---- learned initialisation ----------------------------------------------------
+MLP_IN, MLP_HIDDEN, MLP_OUT = 32, 128, 3
+MLP_NPARAM = 21123
+
+
+def bf16(x):
+    return np.float32(_lib_().orc_bf16(float(x)))
+
+
+def features(ids, xy, pxy, age, prev_img):
+    """[n, 32] features of live keypoints over the previous frame's level-0 image."""
+    ids = np.ascontiguousarray(ids, np.int64)
+    n = len(ids)
+    st = np.ascontiguousarray(np.concatenate([np.asarray(xy, np.float32).reshape(n, 2),
+                                              np.asarray(pxy, np.float32).reshape(n, 2)], 1))
+    age = np.ascontiguousarray(age, np.int32)
+    img = _u8(prev_img)
+    out = np.zeros((n, MLP_IN), np.float32)
+    _lib_().orc_features(n, ids.ctypes.data, st.ctypes.data, age.ctypes.data, img.ctypes.data, img.shape[1],
+                         img.shape[0], out.ctypes.data)
+    return out
+
+
+def mlp_forward(params, X, exact=False):
+    """(Y [n,3], H1 [n,128], H2 [n,128]); exact=True: double, no bf16 rounding."""
+    params = np.ascontiguousarray(params, np.float32)
+    X = np.ascontiguousarray(X, np.float32)
+    n = len(X)
+    Y, H1, H2 = np.zeros((n, 3)), np.zeros((n, MLP_HIDDEN)), np.zeros((n, MLP_HIDDEN))
+    _lib_().orc_mlp_forward(params.ctypes.data, X.ctypes.data, n, int(exact), Y.ctypes.data, H1.ctypes.data,
+                            H2.ctypes.data)
+    return Y, H1, H2
+
+
+def mlp_loss_grad(params, X, targets, exact=False):
+    """(loss, gradient [NPARAM], dY [n,3]) of a batch."""
+    params = np.ascontiguousarray(params, np.float32)
+    X = np.ascontiguousarray(X, np.float32)
+    T = np.ascontiguousarray(targets, np.float32)
+    G = np.zeros(MLP_NPARAM)
+    dY = np.zeros((len(X), 3))
+    L = _lib_().orc_mlp_loss_grad(params.ctypes.data, X.ctypes.data, T.ctypes.data, len(X), int(exact),
+                                  G.ctypes.data, dY.ctypes.data)
+    return L, G, dY
+
+
+def adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float32 arrays."""
+    for a in (params, m, v):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, np.float32)
+    _lib_().orc_adam(params.ctypes.data, g.ctypes.data, m.ctypes.data, v.ctypes.data, t, lr, b1, b2, eps)
+
+
+def mlp_init(seed=0):
+    """He-uniform weights, zero biases (float32)."""
+    rng = np.random.default_rng(seed)
+    P = np.zeros(MLP_NPARAM, np.float32)
+    o = 0
+    for fan_out, fan_in in ((MLP_HIDDEN, MLP_IN), (MLP_HIDDEN, MLP_HIDDEN), (MLP_OUT, MLP_HIDDEN)):
+        lim = np.sqrt(6.0 / fan_in)
+        P[o:o + fan_out * fan_in] = rng.uniform(-lim, lim, fan_out * fan_in)
+        o += fan_out * fan_in + fan_out
+    return P

@@ -420,6 +420,9 @@ struct Params {
   int32_t thresholds[4];
   int32_t edge_margin, max_keypoints;
   float fb_threshold, disparity0;
+  int32_t init_mode;  // 0 constant velocity, 1 learned
+  int32_t learned_levels, learned_iters;
+  float learned_rho;
 };
 
 struct Record {  // 40 bytes
@@ -437,6 +440,208 @@ struct Keypoint {
   int32_t age;
 };
 
+// ----------------------------------------------------------------------------
+// Learned initialisation (a project addition; the paper initialises from the
+// backend's prediction). An MLP maps 32 features of a keypoint to a
+// displacement guess and a confidence:
+//   features: the previous flows (x - px, y - py) / 16 of the 8 nearest other
+//             live keypoints of the camera that have a flow (age >= 1), by
+//             (squared distance, id), zero when fewer exist (16 values); and
+//             the 16x16-pixel patch of the previous frame's level 0 around
+//             round(p), mean-pooled over 4x4 cells: cell_mean / patch_mean - 1
+//             (16 values), pixels clamped to the image.
+//   network:  h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3,
+//             W1 128x32, W2 128x128, W3 3x128; guess (16 y0, 16 y1) px,
+//             confidence sigmoid(y2).
+//   precision: inputs, weights and the post-ReLU activations are rounded to
+//             bfloat16 (round to nearest even); sums in float; biases float.
+// ----------------------------------------------------------------------------
+constexpr int MI = 32, MH = 128, MO = 3;
+constexpr int OFF_W1 = 0, OFF_B1 = MH * MI, OFF_W2 = OFF_B1 + MH, OFF_B2 = OFF_W2 + MH * MH, OFF_W3 = OFF_B2 + MH,
+              OFF_B3 = OFF_W3 + MO * MH, NPARAM = OFF_B3 + MO;
+static_assert(NPARAM == 21123, "parameter count");
+
+static float bf16r(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u) return x;  // inf / nan unchanged
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
+
+// exact squared distance of two float positions (differences and squares are
+// exact in double, so the ordering is the same on every platform)
+static double dist2(float ax, float ay, float bx, float by) {
+  const double dx = (double)ax - (double)bx, dy = (double)ay - (double)by;
+  return dx * dx + dy * dy;
+}
+
+static void features_of(const std::vector<Keypoint>& live, const Img& prev0, float* out /* [n][32] */) {
+  const int n = (int)live.size();
+  for (int i = 0; i < n; ++i) {
+    float* f = out + (size_t)i * MI;
+    std::vector<std::pair<double, int64_t>> cand;
+    std::vector<int> idx;
+    for (int j = 0; j < n; ++j) {
+      if (j == i || live[j].age < 1) continue;
+      cand.push_back({dist2(live[j].x, live[j].y, live[i].x, live[i].y), live[j].id});
+      idx.push_back(j);
+    }
+    std::vector<int> order(cand.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return cand[a] < cand[b]; });
+    for (int k = 0; k < 8; ++k) {
+      if (k < (int)order.size()) {
+        const Keypoint& q = live[idx[order[k]]];
+        f[2 * k] = (q.x - q.px) * 0.0625f;
+        f[2 * k + 1] = (q.y - q.py) * 0.0625f;
+      } else {
+        f[2 * k] = f[2 * k + 1] = 0.f;
+      }
+    }
+    const int rx = (int)std::floor(live[i].x + 0.5f), ry = (int)std::floor(live[i].y + 0.5f);
+    int64_t cell[16] = {0}, total = 0;
+    for (int dy = 0; dy < 16; ++dy)
+      for (int dx = 0; dx < 16; ++dx) {
+        const int v = prev0.at(clampi(rx - 8 + dx, 0, prev0.w - 1), clampi(ry - 8 + dy, 0, prev0.h - 1));
+        cell[(dy / 4) * 4 + dx / 4] += v;
+        total += v;
+      }
+    for (int k = 0; k < 16; ++k)
+      f[16 + k] = total > 0 ? (float)(cell[k] * 16) / (float)total - 1.f : 0.f;
+  }
+}
+
+// Forward pass. bf16 = true: the GPU's rounding points; false: plain real R.
+// Keeps the (rounded) activations for the backward pass.
+template <class R>
+static void mlp_forward(const float* P, const float* X, int n, bool bf16, R* Y, R* H1, R* H2) {
+  auto wr = [&](float w) { return bf16 ? (R)bf16r(w) : (R)w; };
+  for (int i = 0; i < n; ++i) {
+    R x[MI], h1[MH], h2[MH];
+    for (int k = 0; k < MI; ++k) x[k] = bf16 ? (R)bf16r(X[(size_t)i * MI + k]) : (R)X[(size_t)i * MI + k];
+    for (int j = 0; j < MH; ++j) {
+      R acc = 0;
+      for (int k = 0; k < MI; ++k) acc += wr(P[OFF_W1 + j * MI + k]) * x[k];
+      R h = acc + (R)P[OFF_B1 + j];
+      h = h > 0 ? h : 0;
+      h1[j] = bf16 ? (R)bf16r((float)h) : h;
+    }
+    for (int j = 0; j < MH; ++j) {
+      R acc = 0;
+      for (int k = 0; k < MH; ++k) acc += wr(P[OFF_W2 + j * MH + k]) * h1[k];
+      R h = acc + (R)P[OFF_B2 + j];
+      h = h > 0 ? h : 0;
+      h2[j] = bf16 ? (R)bf16r((float)h) : h;
+    }
+    for (int c = 0; c < MO; ++c) {
+      R acc = 0;
+      for (int k = 0; k < MH; ++k) acc += wr(P[OFF_W3 + c * MH + k]) * h2[k];
+      Y[(size_t)i * MO + c] = acc + (R)P[OFF_B3 + c];
+    }
+    if (H1) std::copy(h1, h1 + MH, H1 + (size_t)i * MH);
+    if (H2) std::copy(h2, h2 + MH, H2 + (size_t)i * MH);
+  }
+}
+
+// Loss over a batch (mean over samples): Huber (delta 1 px) on the guess
+// (16 y0, 16 y1) against the target displacement, plus binary cross-entropy
+// of the confidence logit y2 against c = [|guess - target| <= 2 px]. dY gets
+// the gradient with respect to y.
+template <class R>
+static R mlp_loss(const R* Y, const float* tgt, int n, R* dY) {
+  R loss = 0;
+  for (int i = 0; i < n; ++i) {
+    const R gx = (R)16 * Y[i * MO], gy = (R)16 * Y[i * MO + 1], z = Y[i * MO + 2];
+    const R ex = gx - (R)tgt[2 * i], ey = gy - (R)tgt[2 * i + 1];
+    const R hx = std::fabs(ex) <= 1 ? (R)0.5 * ex * ex : std::fabs(ex) - (R)0.5;
+    const R hy = std::fabs(ey) <= 1 ? (R)0.5 * ey * ey : std::fabs(ey) - (R)0.5;
+    const R c = std::sqrt(ex * ex + ey * ey) <= 2 ? (R)1 : (R)0;
+    // softplus(z) - c z, written stably
+    const R bce = (z > 0 ? z + std::log1p(std::exp(-z)) : std::log1p(std::exp(z))) - c * z;
+    loss += hx + hy + bce;
+    if (dY) {
+      const R inv = (R)1 / (R)n;
+      dY[i * MO] = (R)16 * std::max((R)-1, std::min((R)1, ex)) * inv;
+      dY[i * MO + 1] = (R)16 * std::max((R)-1, std::min((R)1, ey)) * inv;
+      dY[i * MO + 2] = ((R)1 / ((R)1 + std::exp(-z)) - c) * inv;
+    }
+  }
+  return loss / (R)n;
+}
+
+// Backward pass from dY. bf16 = true: dY, dH2 and dH1 are rounded to bfloat16
+// where the GPU rounds them (the operands of its matrix products); gradients
+// of the biases sum the rounded values.
+template <class R>
+static void mlp_backward(const float* P, const float* X, const R* H1, const R* H2, const R* dYin, int n, bool bf16,
+                         R* G /* NPARAM */) {
+  auto rr = [&](R v) { return bf16 ? (R)bf16r((float)v) : v; };
+  auto wr = [&](float w) { return bf16 ? (R)bf16r(w) : (R)w; };
+  std::fill(G, G + NPARAM, (R)0);
+  std::vector<R> dH2((size_t)n * MH), dH1((size_t)n * MH), dY((size_t)n * MO);
+  for (size_t i = 0; i < dY.size(); ++i) dY[i] = rr(dYin[i]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < MH; ++j) {
+      R acc = 0;
+      for (int c = 0; c < MO; ++c) acc += dY[i * MO + c] * wr(P[OFF_W3 + c * MH + j]);
+      dH2[(size_t)i * MH + j] = rr(H2[(size_t)i * MH + j] > 0 ? acc : (R)0);
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < MH; ++j) {
+      R acc = 0;
+      for (int k = 0; k < MH; ++k) acc += dH2[(size_t)i * MH + k] * wr(P[OFF_W2 + k * MH + j]);
+      dH1[(size_t)i * MH + j] = rr(H1[(size_t)i * MH + j] > 0 ? acc : (R)0);
+    }
+  for (int c = 0; c < MO; ++c) {
+    for (int j = 0; j < MH; ++j) {
+      R acc = 0;
+      for (int i = 0; i < n; ++i) acc += dY[i * MO + c] * H2[(size_t)i * MH + j];
+      G[OFF_W3 + c * MH + j] = acc;
+    }
+    R acc = 0;
+    for (int i = 0; i < n; ++i) acc += dY[i * MO + c];
+    G[OFF_B3 + c] = acc;
+  }
+  for (int j = 0; j < MH; ++j) {
+    for (int k = 0; k < MH; ++k) {
+      R acc = 0;
+      for (int i = 0; i < n; ++i) acc += dH2[(size_t)i * MH + j] * H1[(size_t)i * MH + k];
+      G[OFF_W2 + j * MH + k] = acc;
+    }
+    R acc = 0;
+    for (int i = 0; i < n; ++i) acc += dH2[(size_t)i * MH + j];
+    G[OFF_B2 + j] = acc;
+  }
+  for (int j = 0; j < MH; ++j) {
+    for (int k = 0; k < MI; ++k) {
+      R acc = 0;
+      for (int i = 0; i < n; ++i) {
+        const R x = bf16 ? (R)bf16r(X[(size_t)i * MI + k]) : (R)X[(size_t)i * MI + k];
+        acc += dH1[(size_t)i * MH + j] * x;
+      }
+      G[OFF_W1 + j * MI + k] = acc;
+    }
+    R acc = 0;
+    for (int i = 0; i < n; ++i) acc += dH1[(size_t)i * MH + j];
+    G[OFF_B1 + j] = acc;
+  }
+}
+
+// Adam (Kingma & Ba) on the float master parameters, step t >= 1.
+static void adam(float* P, const float* G, float* m, float* v, int t, float lr, float b1, float b2, float eps) {
+  const float c1 = 1.f - std::pow(b1, (float)t), c2 = 1.f - std::pow(b2, (float)t);
+  for (int i = 0; i < NPARAM; ++i) {
+    m[i] = b1 * m[i] + (1.f - b1) * G[i];
+    v[i] = b2 * v[i] + (1.f - b2) * G[i] * G[i];
+    const float mh = m[i] / c1, vh = v[i] / c2;
+    P[i] -= lr * mh / (std::sqrt(vh) + eps);
+  }
+}
+
 struct Camera {
   int w, h;
   std::vector<Img> prev;
@@ -451,6 +656,8 @@ struct Frontend {
   std::vector<Camera> cams;
   int64_t next_id = 0;
   std::vector<Record> records;
+  std::vector<float> mlp;  // learned initialisation parameters (NPARAM)
+  int last_fallback = 0;
 };
 
 static Record make_record(int64_t id, int cam, int status, float x, float y, float th, float fb, float res,
@@ -492,6 +699,7 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     cur[c] = pyramid(l0, L);
   }
   F.records.clear();
+  F.last_fallback = 0;
   std::vector<std::vector<Record>> rec(F.n_cams);
   // temporal tracking with the constant-velocity initialisation; a camera with
   // no previous frame carries its keypoints over unchanged (nothing to track
@@ -500,15 +708,39 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     Camera& cam = F.cams[c];
     if (!cam.has_prev) continue;
     std::vector<Keypoint> surv;
+    // learned initialisation: one guess per keypoint from the previous frame
+    const bool learned = P.init_mode == 1;
+    std::vector<float> guess;
+    if (learned && !cam.live.empty()) {
+      std::vector<float> X(cam.live.size() * MI), Y(cam.live.size() * MO);
+      features_of(cam.live, cam.prev[0], X.data());
+      mlp_forward<float>(F.mlp.data(), X.data(), (int)cam.live.size(), true, Y.data(), (float*)nullptr,
+                         (float*)nullptr);
+      guess = Y;
+    }
     {
-      for (const Keypoint& k : cam.live) {
+      for (size_t ki = 0; ki < cam.live.size(); ++ki) {
+        const Keypoint& k = cam.live[ki];
         float ix = k.x + (k.x - k.px), iy = k.y + (k.y - k.py);
+        bool predicted = false;
         for (const Pred& q : preds)
           if (q.cam == c && q.id == k.id) {
             ix = q.x;
             iy = q.y;
+            predicted = true;
           }
-        const TrackOut<float> r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, L, N, P.fb_threshold);
+        TrackOut<float> r;
+        bool done = false;
+        if (learned && !predicted) {
+          // the tracker refines the guess on a smaller budget; a track that is
+          // not kept, or keeps a residual above rho, falls back to the plain
+          // budget from the constant-velocity initialisation
+          const float gx = k.x + 16.f * guess[ki * MO], gy = k.y + 16.f * guess[ki * MO + 1];
+          r = track<float>(cam.prev, cur[c], k.x, k.y, gx, gy, P.learned_levels, P.learned_iters, P.fb_threshold);
+          done = r.status == TRACKED && r.resid <= P.learned_rho;
+          if (!done) F.last_fallback++;
+        }
+        if (!done) r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, L, N, P.fb_threshold);
         if (r.status == TRACKED) {
           surv.push_back({k.id, r.x, r.y, k.x, k.y, k.age + 1});
           rec[c].push_back(make_record(k.id, c, TRACKED, r.x, r.y, r.th, r.fb, r.resid, k.age + 1, -1));
@@ -728,6 +960,7 @@ void orc_fe_destroy(void* h) { delete static_cast<Frontend*>(h); }
 
 int orc_fe_push(void* h, const uint8_t* const* imgs, const int32_t* strides) {
   if (!h || !imgs || !strides) return -1;
+  if (static_cast<Frontend*>(h)->P.init_mode == 1 && static_cast<Frontend*>(h)->mlp.empty()) return -5;
   push_frame(*static_cast<Frontend*>(h), imgs, strides, {});
   return 0;
 }
@@ -736,6 +969,7 @@ int orc_fe_push(void* h, const uint8_t* const* imgs, const int32_t* strides) {
 int orc_fe_push_pred(void* h, const uint8_t* const* imgs, const int32_t* strides, int n, const int64_t* pred_id,
                      const int32_t* pred_cam, const float* pred_xy) {
   if (!h || !imgs || !strides || n < 0) return -1;
+  if (static_cast<Frontend*>(h)->P.init_mode == 1 && static_cast<Frontend*>(h)->mlp.empty()) return -5;
   std::vector<Pred> v;
   for (int i = 0; i < n; ++i) v.push_back({pred_id[i], pred_cam[i], pred_xy[2 * i], pred_xy[2 * i + 1]});
   push_frame(*static_cast<Frontend*>(h), imgs, strides, v);
@@ -782,5 +1016,67 @@ int orc_fe_get_keypoints(void* h, int cam, int capacity, int64_t* id, float* xy_
 }
 
 int64_t orc_fe_next_id(void* h) { return static_cast<Frontend*>(h)->next_id; }
+
+int orc_fe_set_mlp(void* h, const float* params, int n) {
+  auto* F = static_cast<Frontend*>(h);
+  if (!F || !params || n != NPARAM) return -1;
+  F->mlp.assign(params, params + n);
+  return 0;
+}
+
+int orc_fe_last_fallback(void* h) { return static_cast<Frontend*>(h)->last_fallback; }
+
+// ---- learned initialisation ------------------------------------------------
+int orc_mlp_nparam() { return NPARAM; }
+
+float orc_bf16(float x) { return bf16r(x); }
+
+// Features of n live keypoints (id, x, y, px, py, age as in set_keypoints)
+// over the previous frame's level-0 image prev (w x h).
+int orc_features(int n, const int64_t* id, const float* xy_pxy, const int32_t* age, const uint8_t* prev, int w,
+                 int h, float* out) {
+  std::vector<Keypoint> live;
+  for (int i = 0; i < n; ++i)
+    live.push_back({id[i], xy_pxy[4 * i], xy_pxy[4 * i + 1], xy_pxy[4 * i + 2], xy_pxy[4 * i + 3], age[i]});
+  features_of(live, make_img(prev, w, h), out);
+  return 0;
+}
+
+// mode 0: float with bf16 rounding points; 1: double without rounding.
+int orc_mlp_forward(const float* P, const float* X, int n, int mode, double* Y, double* H1, double* H2) {
+  if (mode == 1) {
+    mlp_forward<double>(P, X, n, false, Y, H1, H2);
+    return 0;
+  }
+  std::vector<float> y((size_t)n * MO), h1((size_t)n * MH), h2((size_t)n * MH);
+  mlp_forward<float>(P, X, n, true, y.data(), h1.data(), h2.data());
+  std::copy(y.begin(), y.end(), Y);
+  if (H1) std::copy(h1.begin(), h1.end(), H1);
+  if (H2) std::copy(h2.begin(), h2.end(), H2);
+  return 0;
+}
+
+// Loss and parameter gradient of a batch. mode as above.
+double orc_mlp_loss_grad(const float* P, const float* X, const float* tgt, int n, int mode, double* G, double* dY_out) {
+  if (mode == 1) {
+    std::vector<double> y((size_t)n * MO), h1((size_t)n * MH), h2((size_t)n * MH), dy((size_t)n * MO);
+    mlp_forward<double>(P, X, n, false, y.data(), h1.data(), h2.data());
+    const double L = mlp_loss<double>(y.data(), tgt, n, dy.data());
+    if (G) mlp_backward<double>(P, X, h1.data(), h2.data(), dy.data(), n, false, G);
+    if (dY_out) std::copy(dy.begin(), dy.end(), dY_out);
+    return L;
+  }
+  std::vector<float> y((size_t)n * MO), h1((size_t)n * MH), h2((size_t)n * MH), dy((size_t)n * MO), g(NPARAM);
+  mlp_forward<float>(P, X, n, true, y.data(), h1.data(), h2.data());
+  const float L = mlp_loss<float>(y.data(), tgt, n, dy.data());
+  mlp_backward<float>(P, X, h1.data(), h2.data(), dy.data(), n, true, g.data());
+  if (G) std::copy(g.begin(), g.end(), G);
+  if (dY_out) std::copy(dy.begin(), dy.end(), dY_out);
+  return L;
+}
+
+void orc_adam(float* P, const float* G, float* m, float* v, int t, float lr, float b1, float b2, float eps) {
+  adam(P, G, m, v, t, lr, b1, b2, eps);
+}
 
 }  // extern "C"

@@ -2,9 +2,12 @@
 //
 // One 1024-thread workgroup owns a 64x64 level-0 tile of one camera. It stages
 // the tile plus an apron in LDS with coalesced dword loads, then
-//  * computes the FAST-9 score (Sec. III-D) of the tile and a one-pixel ring,
-//    keeps strict 3x3 maxima with score >= the last threshold and folds each
-//    into its cell's packed key with one atomicMax, and
+//  * computes the FAST-9 score (Sec. III-D) of the tile and a one-pixel ring
+//    (the paper's early rejection on ring pairs (0,8)/(4,12), then an exact
+//    run-of-9 bit-mask test at the last threshold, then the score only for
+//    pixels that pass), keeps strict 3x3 maxima with score >= the last
+//    threshold and folds each into its cell's packed key with one atomicMax,
+//    and
 //  * builds every coarser pyramid level of the tile (Sec. III-C, eqs. 2-3)
 //    from LDS, recomputing the apron instead of reading it back from HBM, so
 //    level 0 is read from HBM once per frame and the L-1 level-serial
@@ -44,11 +47,11 @@ constexpr int kScoreEdge = kTile + 2;
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// FAST-9 score of the pixel at LDS offset `o` (row pitch `sp`), or -1 when it
-// is below `tmin`. Bresenham circle of radius 3 from (0,-3) clockwise.
-__device__ __forceinline__ int fast_score_lds(const uint8_t* img, int o, int sp, int tmin) {
+// Signed differences of the 16 circle pixels to the centre (Bresenham circle
+// of radius 3 from (0,-3) clockwise), read from the LDS tile at offset `o`
+// with row pitch `sp`.
+__device__ __forceinline__ void ring_diffs(const uint8_t* img, int o, int sp, int d[16]) {
   const int c = img[o];
-  int d[16];
   d[0] = img[o - 3 * sp] - c;
   d[1] = img[o - 3 * sp + 1] - c;
   d[2] = img[o - 2 * sp + 2] - c;
@@ -65,10 +68,37 @@ __device__ __forceinline__ int fast_score_lds(const uint8_t* img, int o, int sp,
   d[13] = img[o - sp - 3] - c;
   d[14] = img[o - 2 * sp - 2] - c;
   d[15] = img[o - 3 * sp - 1] - c;
-  // every 9-arc holds one of {0, 8} and one of {4, 12}: exact early rejection
+}
+
+// Exact test of score >= tmin: the paper's early rejection on ring pairs
+// (0,8)/(4,12) (every 9-arc holds one of each pair), then whether the 16-bit
+// circular mask of pixels above (below) the threshold holds a run of 9
+// (rotate-and-AND on a doubled mask).
+__device__ __forceinline__ bool fast_candidate(const int d[16], int tmin) {
   const bool bright = (d[0] > tmin || d[8] > tmin) && (d[4] > tmin || d[12] > tmin);
   const bool dark = (d[0] < -tmin || d[8] < -tmin) && (d[4] < -tmin || d[12] < -tmin);
-  if (!bright && !dark) return -1;
+  if (!bright && !dark) return false;
+  uint32_t mb = 0, md = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    mb |= (uint32_t)(d[k] > tmin) << k;
+    md |= (uint32_t)(d[k] < -tmin) << k;
+  }
+  auto run9 = [](uint32_t m) {
+    const uint32_t x = m | (m << 16);
+    uint32_t a = x & (x >> 1);
+    a &= a >> 2;
+    a &= a >> 4;
+    a &= x >> 8;
+    return (a & 0xFFFFu) != 0;
+  };
+  return run9(mb) || run9(md);
+}
+
+// FAST-9 score (Sec. III-D): the largest tau with a 9-arc all brighter than
+// I(p)+tau or all darker than I(p)-tau, i.e. (max over polarity and arc of the
+// arc's minimum signed difference) - 1.
+__device__ __forceinline__ int fast_score(const int d[16]) {
   int best = -256;
 #pragma unroll
   for (int pol = 0; pol < 2; ++pol) {
@@ -86,8 +116,7 @@ __device__ __forceinline__ int fast_score_lds(const uint8_t* img, int o, int sp,
       best = max(best, m9);
     }
   }
-  const int score = max(best - 1, -1);
-  return score >= tmin ? score : -1;
+  return max(best - 1, -1);
 }
 
 template <int L>
@@ -97,6 +126,8 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __res
   using G = PyrGeom<L>;
   __shared__ __align__(16) uint8_t s_l0[G::sh0 * G::sw0];
   __shared__ uint8_t s_score[kScoreEdge * kScoreEdge];
+  __shared__ uint16_t s_queue[kScoreEdge * kScoreEdge];
+  __shared__ int s_nq;
   __shared__ uint16_t s_v[G::vbytes];
   __shared__ uint8_t s_lv[2][G::lvl_bytes];
 
@@ -153,15 +184,38 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __res
   }
 
   // ---- FAST-9 + strict NMS + per-cell key ---------------------------------
+  // Phase A tests every pixel of the tile and its one-pixel ring exactly for
+  // score >= tmin and queues the few that pass (wave ballot + one LDS atomic
+  // per wave); phase B scores only the queue, so waves stay dense.
   if (cd.detect) {
-    for (int i = tid; i < kScoreEdge * kScoreEdge; i += kPyrThreads) {
-      const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
-      int s8 = 0;
-      if (sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin) {
-        const int s = fast_score_lds(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, tmin);
-        s8 = s + 1;  // 0: below the last threshold
+    if (tid == 0) s_nq = 0;
+    __syncthreads();
+    for (int i0 = 0; i0 < kScoreEdge * kScoreEdge; i0 += kPyrThreads) {
+      const int i = i0 + tid;
+      bool cand = false;
+      if (i < kScoreEdge * kScoreEdge) {
+        const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
+        if (sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin) {
+          int d[16];
+          ring_diffs(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, d);
+          cand = fast_candidate(d, tmin);
+        }
+        s_score[i] = 0;  // 0: below the last threshold
       }
-      s_score[i] = (uint8_t)s8;
+      const unsigned long long m = __ballot(cand);
+      int base = 0;
+      if ((tid & 63) == 0 && m) base = atomicAdd(&s_nq, __popcll(m));
+      base = __shfl(base, 0);
+      if (cand) s_queue[base + __popcll(m & ((1ull << (tid & 63)) - 1ull))] = (uint16_t)i;
+    }
+    __syncthreads();
+    const int nq = s_nq;
+    for (int q = tid; q < nq; q += kPyrThreads) {
+      const int i = s_queue[q];
+      const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
+      int d[16];
+      ring_diffs(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, d);
+      s_score[i] = (uint8_t)(fast_score(d) + 1);
     }
     __syncthreads();
     uint32_t* keys = cd.keys[par];
