@@ -444,9 +444,11 @@ struct Keypoint {
 // Learned initialisation (a project addition; the paper initialises from the
 // backend's prediction). An MLP maps 32 features of a keypoint to a
 // displacement guess and a confidence:
-//   features: the previous flows (x - px, y - py) / 16 of the 8 nearest other
-//             live keypoints of the camera that have a flow (age >= 1), by
-//             (squared distance, id), zero when fewer exist (16 values); and
+//   features: the previous flows (x - px, y - py) / 16 of the 8 live tracks of
+//             the camera nearest to the keypoint that have a flow (age >= 1),
+//             by (squared distance, id) -- the keypoint's own track, at
+//             distance 0, is the nearest when it has a flow -- zero when fewer
+//             exist (16 values); and
 //             the 16x16-pixel patch of the previous frame's level 0 around
 //             round(p), mean-pooled over 4x4 cells: cell_mean / patch_mean - 1
 //             (16 values), pixels clamped to the image.
@@ -486,7 +488,7 @@ static void features_of(const std::vector<Keypoint>& live, const Img& prev0, flo
     std::vector<std::pair<double, int64_t>> cand;
     std::vector<int> idx;
     for (int j = 0; j < n; ++j) {
-      if (j == i || live[j].age < 1) continue;
+      if (live[j].age < 1) continue;
       cand.push_back({dist2(live[j].x, live[j].y, live[i].x, live[i].y), live[j].id});
       idx.push_back(j);
     }

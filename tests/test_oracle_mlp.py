@@ -111,13 +111,17 @@ def test_features_hand_built():
     pxy = xy - np.array([[1, 2], [-16, 8], [0.5, 0.25], [3, 3]], np.float32)
     age = np.array([1, 1, 0, 2])
     F = oracle.features(ids, xy, pxy, age, img)
-    # keypoint 0: neighbours with a flow are 1 (d^2 = 9) and 3 (d^2 = 800); 2 has age 0
-    assert np.allclose(F[0, :4], [-1.0, 0.5, 3 / 16, 3 / 16])
-    assert (F[0, 4:16] == 0).all()
+    # keypoint 0: tracks with a flow by distance: itself (0), 1 (d^2 = 9), 3 (800); 2 has age 0
+    assert np.allclose(F[0, :6], [1 / 16, 2 / 16, -1.0, 0.5, 3 / 16, 3 / 16])
+    assert (F[0, 6:16] == 0).all()
     # uniform image: every pooled cell equals the patch mean
     assert (F[:, 16:] == 0).all()
-    # keypoint 2 (age 0) still gets its neighbours' flows: 0 (d^2 = 36), 1 (45), 3
+    # keypoint 2 (age 0, no flow of its own) gets its neighbours' flows: 0 (d^2 = 36), 1 (45), 3
     assert np.allclose(F[2, :6], [1 / 16, 2 / 16, -1.0, 0.5, 3 / 16, 3 / 16])
+    # ties in distance go to the smaller id
+    xy_t = np.array([[10, 10], [13, 10], [7, 10]], np.float32)
+    F_t = oracle.features([5, 9, 2], xy_t, xy_t - 1, [0, 1, 1], img)
+    assert np.allclose(F_t[0, :4], [1 / 16] * 4)  # ids 2 then 9, both at d^2 = 9
     # a bright left half: cells in the two left columns of the patch are brighter
     img2 = img.copy()
     img2[:, :30] = 200
