@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the stereo VIO frontend on one MI355X.
 
-One step = one stereo frame through the whole frontend (pyramid, FAST grid
+One step = one frame through the whole frontend (pyramid, FAST grid
 detection, temporal tracking of every live keypoint with the forward-backward
-check, stereo matching of the new detections, records back on the host) on the
-752x480 stereo workload: a seeded synthetic 200-frame sequence with 4x texture
-density, smooth SE(2)+scale motion and a planar 5..60 px disparity, 4 pyramid
-levels, 5 Gauss-Newton iterations per level, <= 300 keypoints per camera.
+check, stereo matching of the new detections, records back on the host). The
+default workload is 752x480 stereo: a seeded synthetic 200-frame sequence with
+4x texture density, smooth SE(2)+scale motion and a planar 5..60 px disparity,
+4 pyramid levels, 5 Gauss-Newton iterations per level, <= 300 keypoints per
+camera.
 
-The sequence is resident in HBM before timing starts; each step pushes one
-frame's device images through the C ABI and reads the frame's records, as the
-synchronous submit-and-wait of the paper's pipeline. Prints one JSON line.
+The sequences are resident in HBM before timing starts. A single-stream step
+pushes one frame's device images through the C ABI and reads the frame's
+records (the synchronous submit-and-wait of the paper's pipeline); the batch16
+workload stages one frame of each of its sixteen streams and runs them as one
+batched step. The timed steps launch the kernels one by one, each with HIP
+start/stop events attached to its own dispatch, which gives the kernel
+durations behind the roofline figures; the same steps are then replayed as
+one captured graph per step and reported beside them (`graph_replay`, with a
+check that both give identical records). Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -75,13 +82,27 @@ def measured_traffic(workload, kernel):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=190)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 190, batch16 and rig4 100)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="stereo752")
+    ap.add_argument("--workload", default="stereo752", help="stereo752, stereo1280, rig4, mono320 or batch16")
     ap.add_argument("--seq", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eager", action="store_true", help="launch kernels one by one (per-kernel HIP events)")
+    ap.add_argument("--launch", choices=["eager", "graph"], default="eager",
+                    help="timed region: kernels launched one by one with HIP events attached to each dispatch "
+                         "(default; gives the kernel durations), or one captured graph per frame")
+    ap.add_argument("--no-graph-replay", action="store_true",
+                    help="skip the second timed region that replays the same steps as captured graphs")
+    ap.add_argument("--init", choices=["const_vel", "learned"], default="const_vel")
+    ap.add_argument("--weights", default=None, help="learned-init weights (default: the package's for the workload)")
+    ap.add_argument("--levels", type=int, default=None, help="override the pyramid levels")
+    ap.add_argument("--iters", type=int, default=None, help="override the Gauss-Newton iterations per level")
+    ap.add_argument("--learned-levels", type=int, default=2)
+    ap.add_argument("--learned-iters", type=int, default=3)
+    ap.add_argument("--waves-per-cu", type=int, default=None,
+                    help="tracker grid: 0 = one wave per keypoint, N = persistent N waves per CU "
+                         "(default: the autotuned choice, else 0)")
+    ap.add_argument("--block-waves", type=int, default=None, help="tracker waves per workgroup (1, 2, 4)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -103,44 +124,227 @@ def main():
 
     import paper_2609_30459_amd as vf
     import synthgen
+    from synthgen.workloads import BATCH16
 
-    w = synthgen.WORKLOADS[args.workload]
+    batched = args.workload == "batch16"
+    if args.steps is None:
+        args.steps = 100 if args.workload in ("batch16", "rig4") else 190
+    if batched:
+        ws = list(BATCH16)
+    else:
+        ws = [synthgen.WORKLOADS[args.workload]]
+    over = {}
+    if args.levels:
+        over["levels"] = args.levels
+    if args.iters:
+        over["gn_iters"] = args.iters
+    ws = [w.with_(**over) for w in ws]
+    w0 = ws[0]
     n_frames = args.warmup + args.steps
-    log(f"rendering {n_frames} frames of {w.name} ({w.n_cams} x {w.width}x{w.height})")
-    seq = synthgen.sequence(w, seq=args.seq, n_frames=n_frames)
-    dev = torch.from_numpy(seq.frames).cuda()
+    log(f"rendering {n_frames} frames of {args.workload}: {len(ws)} stream(s), "
+        f"{sum(w.n_cams * w.width * w.height for w in ws) / 1e6:.2f} MP per step")
+    seqs = [synthgen.sequence(w, seq=args.seq, stream=i, n_frames=n_frames) for i, w in enumerate(ws)]
+    devs = [torch.from_numpy(q.frames).cuda() for q in seqs]
     torch.cuda.synchronize()
-    stream = (w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size)
-    fe = vf.Frontend([stream], vf.params_for(w, eager=args.eager))
-    records = []
-    stage_ms = []
+    streams = [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in ws]
 
-    def step(t):
-        fe.push_stereo_frame_device(0, t + 1, [dev[t, c] for c in range(w.n_cams)])
-        return fe.get_tracks(0)
+    wpc, bw = args.waves_per_cu, args.block_waves
+    tuned = None
+    if wpc is None and bw is None:
+        from paper_2609_30459_amd import autotune
+        tuned = autotune.lookup(args.workload, args.init)
+        if tuned:
+            wpc, bw = tuned["track_waves_per_cu"], tuned["track_block_waves"]
+    wpc = wpc or 0
+    bw = bw or 4
+    extra = dict(track_waves_per_cu=wpc, track_block_waves=bw)
+    rho = None
+    if args.init == "learned":
+        from paper_2609_30459_amd.train_mlp import load_weights
+        path = args.weights or os.path.join(ROOT, "paper_2609_30459_amd", "weights", "mlp_stereo1280.bin")
+        mlp_params, rho, meta = load_weights(path)
+        log(f"learned init: {path} ({meta}), rho {rho:.4f}")
+        extra.update(init_mode=1, learned_levels=args.learned_levels, learned_iters=args.learned_iters,
+                     learned_rho=rho)
+    ids = list(range(len(ws)))
 
-    log(f"warmup {args.warmup} frames")
-    for t in range(args.warmup):
-        records.append(step(t))
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} frames")
-    t0 = time.perf_counter()
-    for t in range(args.warmup, n_frames):
-        records.append(step(t))
-        st = fe.stats()
-        stage_ms.append(st["last_stage_ms"] + [st["last_gpu_ms"]])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    fe.close()
-    fps = args.steps / elapsed
+    def timed_run(eager):
+        """Warmup, then the timed steps: (records per stream, wall s per step, stats per step, elapsed s)."""
+        # the streams share one parameter block; per-stream sizes and caps come with the stream
+        fe = vf.Frontend(streams, vf.params_for(w0, eager=eager, **extra))
+        if args.init == "learned":
+            fe.set_mlp(mlp_params, rho)
+        records = [[] for _ in ws]
+        wall, stats = [], []
+
+        def step(t):
+            if batched:
+                imgs = [devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)]
+                fe.stage_frames_device(ids, [t + 1] * len(ws), imgs)
+                fe.step()
+            else:
+                fe.push_stereo_frame_device(0, t + 1, [devs[0][t, c] for c in range(w0.n_cams)])
+            for i in ids:
+                records[i].append(fe.get_tracks(i))
+
+        log(f"warmup {args.warmup} steps ({'eager' if eager else 'graph'})")
+        for t in range(args.warmup):
+            step(t)
+        torch.cuda.synchronize()
+        log(f"timing {args.steps} steps")
+        t0 = time.perf_counter()
+        for t in range(args.warmup, n_frames):
+            ts = time.perf_counter()
+            step(t)
+            wall.append(time.perf_counter() - ts)
+            stats.append(fe.stats())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        fe.close()
+        return records, wall, stats, elapsed
+
+    records, wall, stats, elapsed = timed_run(args.launch == "eager")
+    steps_per_s = args.steps / elapsed
+    stage_ms = [s_["last_stage_ms"] + s_["last_learned_ms"] + [s_["last_gpu_ms"]] for s_ in stats]
+    fallbacks = [s_["last_fallback"] for s_ in stats]
+    replay = None
+    if args.launch == "eager" and not args.no_graph_replay:
+        rec2, wall2, stats2, elapsed2 = timed_run(False)
+        same = all(a.tobytes() == b.tobytes() for ra, rb in zip(records, rec2) for a, b in zip(ra, rb))
+        replay = {"value": args.steps * len(ws) / elapsed2, "ms_per_step": 1000.0 * elapsed2 / args.steps,
+                  "gpu_ms_per_step": float(np.mean([s_["last_gpu_ms"] for s_ in stats2])),
+                  "latency_p50_ms": float(np.percentile(np.array(wall2) * 1e3, 50)),
+                  "latency_p99_ms": float(np.percentile(np.array(wall2) * 1e3, 99)),
+                  "records_identical": bool(same)}
 
     # ---- tracked keypoints and accuracy against the synthetic ground truth ---
     TR, DET, MAT = vf.VIO_TRACKED, vf.VIO_DETECTED, vf.VIO_MATCHED
-    tracked = [int((r["status"] == TR).sum()) for r in records[args.warmup:]]
-    errs, serrs, lost = [], [], 0
-    for t in range(1, n_frames):
-        prev, cur = records[t - 1], records[t]
+    tracked = np.zeros(args.steps)
+    errs, serrs, n_tr, n_lost = [], [], 0, 0
+    n_temporal = np.zeros(args.steps)
+    n_stereo = np.zeros(args.steps)
+    for i, (w, seq) in enumerate(zip(ws, seqs)):
+        rec = records[i]
+        for k, t in enumerate(range(args.warmup, n_frames)):
+            tracked[k] += int((rec[t]["status"] == TR).sum())
+            prev = rec[t - 1] if t > 0 else rec[t][:0]
+            n_temporal[k] += int(np.isin(prev["status"], [TR, DET, MAT]).sum())
+            n_stereo[k] += int((rec[t]["status"] == DET).sum()) if w.stereo else 0
+        e, se, tr, lo = accuracy(w, seq, rec, TR, DET, MAT)
+        errs += e
+        serrs += se
+        n_tr += tr
+        n_lost += lo
+    err = np.concatenate(errs) if errs else np.zeros(1)
+    serr = np.concatenate(serrs) if serrs else np.zeros(1)
+    survival = n_tr / max(1, n_tr + n_lost)
+
+    # ---- roofline of the dominant kernel (HIP events on the launch stream) ----
+    # [steps, 6]: pyramid+detector, tracker, selection, features, network, whole frame
+    sm = np.array(stage_ms)
+    mean_ms = sm.mean(0)
+    mean_ms[3] = sm[:, 3].mean() if args.init == "learned" else -1.0
+    mean_ms[4] = sm[:, 4].mean() if args.init == "learned" else -1.0
+    have_times = bool((sm[:, :3] >= 0).all())
+    L, N = w0.levels, w0.gn_iters
+    fb = np.array(fallbacks, np.float64)
+    if args.init == "learned":
+        # every temporal track runs the short tracker; fallbacks rerun the full one
+        flops_step = (n_temporal * track_flops_per_call(args.learned_levels, args.learned_iters) +
+                      (fb + n_stereo) * track_flops_per_call(L, N))
+    else:
+        flops_step = (n_temporal + n_stereo) * track_flops_per_call(L, N)
+    pyr_b = sum(pyramid_bytes(w.width, w.height, L, w.n_cams) for w in ws)
+    total_rows = sum(w.max_keypoints * w.n_cams for w in ws)
+    kernels = {
+        "k_pyr_detect": {"bound": "hbm", "avg_ms": float(mean_ms[0]), "bytes_per_launch": pyr_b,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "achieved": pyr_b / (mean_ms[0] * 1e-3) / 1e9 if have_times else None},
+        "k_track": {"bound": "alu", "avg_ms": float(mean_ms[1]), "calls_per_launch": float((n_temporal + n_stereo).mean()),
+                    "flops_per_launch": float(flops_step.mean()), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "achieved": float(flops_step.mean()) / (mean_ms[1] * 1e-3) / 1e12 if have_times else None,
+                    },
+        "k_select": {"bound": "latency", "avg_ms": float(mean_ms[2])},
+    }
+    if args.init == "learned":
+        kernels["k_features"] = {"bound": "latency", "avg_ms": float(mean_ms[3])}
+        kernels["k_mlp_fwd"] = {"bound": "mfma", "avg_ms": float(mean_ms[4]),
+                                "flops_per_launch": 2 * (32 * 128 + 128 * 128 + 128 * 3) * total_rows}
+    roof = None
+    if have_times:
+        dom = ["k_pyr_detect", "k_track", "k_select"][int(np.argmax(mean_ms[:2]))]
+        kd = kernels[dom]
+        roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
+                "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"],
+                "traffic": measured_traffic(args.workload, dom) if args.init == "const_vel" else None,
+                "avg_ms": kd["avg_ms"]}
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same workload ---
+    cpu = None
+    if not args.no_cpu_baseline and args.init == "const_vel":
+        import oracle
+        log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s")
+        fos = [oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo, oracle.params_for(w))
+               for w in ws]
+        n, c0 = 0, time.perf_counter()
+        while n < n_frames and (time.perf_counter() - c0 < args.cpu_seconds or n < 3):
+            for fo, q in zip(fos, seqs):
+                fo.push(list(q.frames[n]))
+                fo.records()
+            n += 1
+        cpu_s = time.perf_counter() - c0
+        for fo in fos:
+            fo.close()
+        unit = "stream-frames/s" if batched else "frames/s"
+        cpu = {"value": n * len(ws) / cpu_s, "unit": unit, "cores": 1, "kind": "oracle",
+               "sample": f"first {n} frames of the same {args.workload} sequence(s), single-threaded C++ oracle "
+                         f"(-O2), {cpu_s:.1f} s"}
+
+    wall_ms = np.array(wall) * 1e3
+    value = steps_per_s * len(ws)
+    out = {
+        "metric": "stereo frames/s + tracked kpts/s, plain vs learned-init KLT at <=0.1px err",
+        "value": value,
+        "unit": "stream-frames/s" if batched else "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 / steps_per_s,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "streams": len(ws),
+                   "cameras": sum(w.n_cams for w in ws),
+                   "sizes": sorted({f"{w.width}x{w.height}x{w.n_cams}" for w in ws}),
+                   "levels": L, "gn_iters": N, "max_keypoints": sorted({w.max_keypoints for w in ws}),
+                   "init": args.init, "launch": args.launch, "track_waves_per_cu": wpc, "track_block_waves": bw,
+                   "autotuned": tuned is not None, "parallelism": "single_gpu",
+                   **({"learned_levels": args.learned_levels, "learned_iters": args.learned_iters, "rho": rho}
+                      if args.init == "learned" else {})},
+        "tracked_kpts_per_s": float(tracked.mean()) * steps_per_s,
+        "gpu_ms_per_step": float(mean_ms[5]),
+        "latency_ms": {"p50": float(np.percentile(wall_ms, 50)), "p99": float(np.percentile(wall_ms, 99)),
+                       "gpu_p50": float(np.percentile(sm[:, 5], 50)), "gpu_p99": float(np.percentile(sm[:, 5], 99))},
+        "accuracy": {"temporal_median_px": float(np.median(err)), "temporal_p90_px": float(np.percentile(err, 90)),
+                     "stereo_median_px": float(np.median(serr)), "survival": survival},
+        "fallback_per_step": float(fb.mean()) if args.init == "learned" else None,
+        "roofline": roof,
+        "graph_replay": replay,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def accuracy(w, seq, rec, TR, DET, MAT):
+    """Temporal and stereo errors against the ground truth, tracked and lost counts."""
+    errs, serrs, n_tr, lost = [], [], 0, 0
+    for t in range(1, len(rec)):
+        prev, cur = rec[t - 1], rec[t]
         live = np.isin(prev["status"], [TR, DET, MAT])
+        n_tr += int((cur["status"] == TR).sum())
         for c in range(w.n_cams):
             pc = prev[live & (prev["camera"] == c)]
             pos = {int(i): (x, y) for i, x, y in zip(pc["id"], pc["x"], pc["y"])}
@@ -161,81 +365,7 @@ def main():
                     ly = np.array([lpos[int(i)][1] for i in mr["id"]])
                     gx, gy = seq.gt_stereo(c, lx, ly)
                     serrs.append(np.hypot(mr["x"] - gx, mr["y"] - gy))
-    err = np.concatenate(errs) if errs else np.zeros(1)
-    serr = np.concatenate(serrs) if serrs else np.zeros(1)
-    survival = float(np.sum([int((r["status"] == TR).sum()) for r in records[1:]]) /
-                     max(1, np.sum([int((r["status"] == TR).sum()) for r in records[1:]]) + lost))
-
-    # ---- roofline of the dominant kernel (HIP events on the launch stream) ----
-    sm = np.array(stage_ms)  # [steps, 4]: pyramid+detector, tracker, selection, whole frame
-    mean_ms = sm.mean(0)
-    names = ["k_pyr_detect", "k_track", "k_select"]
-    calls = []
-    for t in range(args.warmup, n_frames):
-        prev = records[t - 1] if t > 0 else records[t][:0]
-        n_temporal = int(np.isin(prev["status"], [TR, DET, MAT]).sum())
-        n_stereo = int((records[t]["status"] == DET).sum()) if w.stereo else 0
-        calls.append(n_temporal + n_stereo)
-    calls = np.array(calls, np.float64)
-    flops_call = track_flops_per_call(w.levels, w.gn_iters)
-    pyr_b = pyramid_bytes(w.width, w.height, w.levels, w.n_cams)
-    kernels = {
-        "k_pyr_detect": {"bound": "hbm", "avg_ms": float(mean_ms[0]), "bytes_per_launch": pyr_b,
-                         "achieved": pyr_b / (mean_ms[0] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"},
-        "k_track": {"bound": "alu", "avg_ms": float(mean_ms[1]), "calls_per_launch": float(calls.mean()),
-                    "flops_per_call": flops_call,
-                    "achieved": flops_call * calls.mean() / (mean_ms[1] * 1e-3) / 1e12,
-                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"},
-        "k_select": {"bound": "alu", "avg_ms": float(mean_ms[2])},
-    }
-    dom = names[int(np.argmax(mean_ms[:3]))]
-    kd = kernels[dom]
-    roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd.get("achieved"), "peak": kd.get("peak"),
-            "unit": kd.get("unit"), "frac": (kd["achieved"] / kd["peak"]) if kd.get("achieved") else None,
-            "traffic": measured_traffic(w.name, dom), "avg_ms": kd["avg_ms"]}
-
-    # ---- CPU baseline: the oracle on a bounded sample of the same sequence ---
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s")
-        fo = oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo, oracle.params_for(w))
-        n, c0 = 0, time.perf_counter()
-        while n < n_frames and (time.perf_counter() - c0 < args.cpu_seconds or n < 3):
-            fo.push(list(seq.frames[n]))
-            fo.records()
-            n += 1
-        cpu_s = time.perf_counter() - c0
-        fo.close()
-        cpu = {"value": n / cpu_s, "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {n} frames of the same {w.name} sequence, single-threaded C++ oracle (-O2), "
-                         f"{cpu_s:.1f} s"}
-
-    out = {
-        "metric": "stereo frames/s + tracked kpts/s, plain vs learned-init KLT at <=0.1px err",
-        "value": fps,
-        "unit": "frames/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 / fps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "width": w.width, "height": w.height, "cameras": w.n_cams,
-                   "levels": w.levels, "gn_iters": w.gn_iters, "max_keypoints": w.max_keypoints,
-                   "cell_size": w.cell_size, "init": "const_vel", "parallelism": "single_gpu"},
-        "tracked_kpts_per_s": float(np.mean(tracked)) * fps,
-        "gpu_ms_per_frame": float(mean_ms[3]),
-        "accuracy": {"temporal_median_px": float(np.median(err)), "temporal_p90_px": float(np.percentile(err, 90)),
-                     "stereo_median_px": float(np.median(serr)), "survival": survival},
-        "roofline": roof,
-        "kernels": kernels,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    return errs, serrs, n_tr, lost
 
 
 if __name__ == "__main__":

@@ -94,10 +94,14 @@ typedef struct vio_frontend_params {
   int32_t learned_iters;
   float learned_rho;      /* residual RMS above which a learned track falls back to the plain tracker */
   uint32_t flags;         /* VIO_FLAG_* */
+  int32_t track_waves_per_cu; /* 0: one wave per tracking work item; > 0: a persistent tracking grid
+                                 of this many waves per compute unit over a shared work queue */
+  int32_t track_block_waves;  /* waves per tracking workgroup: 1, 2 or 4 (0 = 4) */
 } vio_frontend_params;
 
 /* vio_frontend_params.flags */
-#define VIO_FLAG_EAGER 1u /* launch the per-frame kernels one by one instead of replaying a captured hipGraph */
+#define VIO_FLAG_EAGER 1u /* launch the per-frame kernels one by one, each with dispatch timestamps, instead
+                             of replaying a captured hipGraph */
 
 /* Output record: one per previous keypoint of each camera (tracked or lost) and
  * one per new detection / stereo match, sorted by (camera, id). */
@@ -134,13 +138,16 @@ typedef struct vio_kp_prediction {
 typedef struct vio_stats {
   int64_t frames;        /* frames processed by the handle */
   double last_gpu_ms;    /* device time of the last frame (first kernel to last) */
-  double last_stage_ms[3]; /* HIP-event time of the last frame's pyramid+detector, tracker and
-                              selection kernels, on the stream they ran on; -1 when the frame
-                              was replayed as a graph (VIO_FLAG_EAGER gives per-kernel times) */
+  double last_stage_ms[3]; /* durations of the last frame's pyramid+detector, tracker and selection
+                              kernels from their own dispatch timestamps (HIP events attached to the
+                              launch); -1 unless launched one by one (VIO_FLAG_EAGER) */
+  double last_learned_ms[2]; /* the same for the learned initialisation's feature and network
+                                kernels; -1 otherwise */
   int32_t last_tracked;  /* VIO_TRACKED records of the last frame, all cameras */
   int32_t last_lost;     /* lost temporal records of the last frame */
   int32_t last_detected; /* VIO_DETECTED records */
   int32_t last_matched;  /* VIO_MATCHED records */
+  int32_t last_fallback; /* learned init: tracks that fell back to the plain tracker */
 } vio_stats;
 
 typedef struct vio_frontend vio_frontend;
@@ -175,6 +182,25 @@ int vio_frontend_push_stereo_frame(vio_frontend* h, int32_t stream, int64_t t_ns
  * handle's own stream) during this call only. The frame runs on that stream. */
 int vio_frontend_push_stereo_frame_device(vio_frontend* h, int32_t stream, int64_t t_ns,
                                           const void* const* d_images, const int32_t* pitches, void* hip_stream);
+
+/* Batched stepping: stage one frame for any number of streams, then run every
+ * staged stream in one submit (one pyramid/detector launch over all their
+ * cameras, one tracking launch over all their keypoints, one selection
+ * launch), replayed as one captured graph. The staging calls copy nothing:
+ * d_images must stay valid until vio_frontend_step returns; host images are
+ * copied into pinned staging at stage time. A stream staged twice keeps the
+ * last frame. vio_frontend_step is synchronous; afterwards each staged
+ * stream's records are read with vio_frontend_get_tracks. */
+int vio_frontend_stage_frame(vio_frontend* h, int32_t stream, int64_t t_ns, const uint8_t* const* images,
+                             const int32_t* strides);
+int vio_frontend_stage_frame_device(vio_frontend* h, int32_t stream, int64_t t_ns, const void* const* d_images,
+                                    const int32_t* pitches);
+int vio_frontend_step(vio_frontend* h);
+
+/* Stages device images for n streams at once: stream streams[i] at t_ns[i]
+ * takes the next n_cameras entries of d_images / pitches (in stream order). */
+int vio_frontend_stage_frames_device(vio_frontend* h, int32_t n, const int32_t* streams, const int64_t* t_ns,
+                                     const void* const* d_images, const int32_t* pitches);
 
 /* Copies the last frame's records of `stream` into out[0..capacity). *n_out
  * receives the record count; VIO_ETOOSMALL (nothing written) when capacity is

@@ -16,7 +16,9 @@ from . import _native as _n
 from ._native import (KEYPOINT_DTYPE, TRACK_DTYPE, VIO_DETECTED, VIO_LOST_CAP, VIO_LOST_DEGENERATE,  # noqa: F401
                       VIO_LOST_FB, VIO_LOST_OOB, VIO_MATCHED, VIO_TRACKED, VioError)
 
-__all__ = ["Frontend", "default_params", "make_params", "TRACK_DTYPE", "KEYPOINT_DTYPE", "VioError"]
+__all__ = ["Frontend", "Mlp", "default_params", "make_params", "TRACK_DTYPE", "KEYPOINT_DTYPE", "VioError"]
+
+MLP_NPARAM = _n.VIO_MLP_NPARAM
 
 
 def default_params() -> _n.vio_frontend_params:
@@ -27,7 +29,8 @@ def default_params() -> _n.vio_frontend_params:
 
 def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40, 20, 10, 5), edge_margin=8,
                 max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0, learned_levels=2,
-                learned_iters=3, learned_rho=0.0, eager=False) -> _n.vio_frontend_params:
+                learned_iters=3, learned_rho=0.0, eager=False, track_waves_per_cu=0,
+                track_block_waves=0) -> _n.vio_frontend_params:
     p = default_params()
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
     p.n_thresholds = len(thresholds)
@@ -37,6 +40,8 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
     p.fb_threshold, p.disparity0, p.init_mode = fb_threshold, disparity0, init_mode
     p.learned_levels, p.learned_iters, p.learned_rho = learned_levels, learned_iters, learned_rho
     p.flags = _n.VIO_FLAG_EAGER if eager else 0
+    p.track_waves_per_cu = track_waves_per_cu
+    p.track_block_waves = track_block_waves
     return p
 
 
@@ -113,6 +118,35 @@ class Frontend:
         rc = _n.lib.vio_frontend_push_stereo_frame_device(self._h, stream, int(t_ns), ptrs, pitches.ctypes.data, st)
         self._check(rc, "vio_frontend_push_stereo_frame_device")
 
+    def stage_frame(self, stream, t_ns, images):
+        """Stages host images (one uint8 HxW array per camera) for the next step()."""
+        imgs = [np.ascontiguousarray(im, np.uint8) for im in images]
+        ptrs = (ctypes.c_void_p * len(imgs))(*[im.ctypes.data for im in imgs])
+        strides = np.asarray([im.strides[0] for im in imgs], np.int32)
+        self._check(_n.lib.vio_frontend_stage_frame(self._h, stream, int(t_ns), ptrs, strides.ctypes.data),
+                    "vio_frontend_stage_frame")
+
+    def stage_frame_device(self, stream, t_ns, images):
+        """Stages device images (uint8 tensors, kept alive until step()) for the next step()."""
+        ptrs = (ctypes.c_void_p * len(images))(*[int(t.data_ptr()) for t in images])
+        pitches = np.asarray([int(t.stride(0)) * t.element_size() for t in images], np.int32)
+        self._check(_n.lib.vio_frontend_stage_frame_device(self._h, stream, int(t_ns), ptrs, pitches.ctypes.data),
+                    "vio_frontend_stage_frame_device")
+
+    def stage_frames_device(self, streams, t_ns, images):
+        """Stages device images of several streams in one call; images: all cameras, stream by stream."""
+        n = len(streams)
+        st = np.ascontiguousarray(streams, np.int32)
+        ts = np.ascontiguousarray(t_ns, np.int64)
+        ptrs = (ctypes.c_void_p * len(images))(*[int(t.data_ptr()) for t in images])
+        pitches = np.asarray([int(t.stride(0)) * t.element_size() for t in images], np.int32)
+        self._check(_n.lib.vio_frontend_stage_frames_device(self._h, n, st.ctypes.data, ts.ctypes.data, ptrs,
+                                                            pitches.ctypes.data), "vio_frontend_stage_frames_device")
+
+    def step(self):
+        """Runs every staged stream's frame in one submit (synchronous)."""
+        self._check(_n.lib.vio_frontend_step(self._h), "vio_frontend_step")
+
     def get_tracks(self, stream=0) -> np.ndarray:
         n = ctypes.c_int32()
         rc = _n.lib.vio_frontend_get_tracks(self._h, stream, None, 0, ctypes.byref(n))
@@ -163,5 +197,92 @@ class Frontend:
         s = _n.vio_stats()
         self._check(_n.lib.vio_frontend_get_stats(self._h, ctypes.byref(s)), "vio_frontend_get_stats")
         return {"frames": s.frames, "last_gpu_ms": s.last_gpu_ms, "last_stage_ms": list(s.last_stage_ms),
+                "last_learned_ms": list(s.last_learned_ms),
                 "last_tracked": s.last_tracked, "last_lost": s.last_lost, "last_detected": s.last_detected,
-                "last_matched": s.last_matched}
+                "last_matched": s.last_matched, "last_fallback": s.last_fallback}
+
+    def set_mlp(self, params, rho=-1.0):
+        """Installs learned-initialisation weights (VIO_MLP_NPARAM floats); rho >= 0 sets the fallback threshold."""
+        p = np.ascontiguousarray(params, np.float32)
+        self._check(_n.lib.vio_frontend_set_mlp(self._h, p.ctypes.data, len(p), float(rho)), "vio_frontend_set_mlp")
+
+
+    def get_features(self, stream, camera) -> np.ndarray:
+        """Network inputs of the camera's previous keypoints in the last frame (learned mode)."""
+        n = ctypes.c_int32()
+        rc = _n.lib.vio_frontend_get_features(self._h, stream, camera, None, 0, ctypes.byref(n))
+        if rc not in (0, _n.VIO_ETOOSMALL):
+            self._check(rc, "vio_frontend_get_features")
+        out = np.zeros((n.value, 32), np.float32)
+        rc = _n.lib.vio_frontend_get_features(self._h, stream, camera, out.ctypes.data, out.size, ctypes.byref(n))
+        self._check(rc, "vio_frontend_get_features")
+        return out
+
+
+def _stream_ptr(hip_stream):
+    if hip_stream is None:
+        return None
+    return ctypes.c_void_p(int(getattr(hip_stream, "cuda_stream", hip_stream)))
+
+
+class Mlp:
+    """The learned-initialisation network on the device (vio_mlp_create .. vio_mlp_destroy).
+
+    Device data are torch tensors (float32, contiguous, on the GPU).
+    """
+
+    def __init__(self, max_batch=1024):
+        h = ctypes.c_void_p()
+        rc = _n.lib.vio_mlp_create(int(max_batch), ctypes.byref(h))
+        if rc != 0:
+            raise VioError(rc, "vio_mlp_create")
+        self._h = h
+        self.max_batch = max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _n.lib.vio_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        rc = _n.lib.vio_mlp_set_params(self._h, p.ctypes.data, len(p))
+        if rc != 0:
+            raise VioError(rc, "vio_mlp_set_params")
+
+    def get_params(self):
+        p = np.zeros(MLP_NPARAM, np.float32)
+        rc = _n.lib.vio_mlp_get_params(self._h, p.ctypes.data, len(p))
+        if rc != 0:
+            raise VioError(rc, "vio_mlp_get_params")
+        return p
+
+    def forward(self, x, y, hip_stream=None):
+        rc = _n.lib.vio_mlp_forward(self._h, x.data_ptr(), x.shape[0], y.data_ptr(), _stream_ptr(hip_stream))
+        if rc != 0:
+            raise VioError(rc, "vio_mlp_forward")
+
+    def gradient(self, x, targets, grad, hip_stream=None):
+        loss = ctypes.c_float()
+        rc = _n.lib.vio_mlp_gradient(self._h, x.data_ptr(), targets.data_ptr(), x.shape[0], grad.data_ptr(),
+                                     ctypes.byref(loss), _stream_ptr(hip_stream))
+        if rc != 0:
+            raise VioError(rc, "vio_mlp_gradient")
+        return loss.value
+
+    def train_step(self, x, targets, lr=1e-3, want_loss=True, hip_stream=None):
+        loss = ctypes.c_float()
+        rc = _n.lib.vio_mlp_train_step(self._h, x.data_ptr(), targets.data_ptr(), x.shape[0], float(lr),
+                                       ctypes.byref(loss) if want_loss else None, _stream_ptr(hip_stream))
+        if rc != 0:
+            raise VioError(rc, "vio_mlp_train_step")
+        return loss.value if want_loss else None

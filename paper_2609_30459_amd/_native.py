@@ -19,6 +19,16 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_2609_30459_amd.build` "
         "(hipcc, gfx950) before using the frontend")
 
+# The PyTorch wheel ships its own HIP runtime under the same soname
+# (libamdhip64.so.7); whichever is loaded first serves the whole process. Load
+# torch's first so that one runtime owns the GPU for both torch and this
+# library (torch fails to start on a runtime other than its own), and torch
+# streams and allocations are valid handles here.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the C ABI works without torch
+    pass
+
 lib = ctypes.CDLL(LIB_PATH)
 
 VIO_OK, VIO_EINVAL, VIO_ENOMEM, VIO_EDEVICE, VIO_ETOOSMALL, VIO_ESTATE, VIO_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
@@ -43,7 +53,8 @@ class vio_frontend_params(ctypes.Structure):
         ("thresholds", ctypes.c_int32 * 4), ("edge_margin", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
         ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float), ("init_mode", ctypes.c_int32),
         ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32), ("learned_rho", ctypes.c_float),
-        ("flags", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("track_waves_per_cu", ctypes.c_int32),
+        ("track_block_waves", ctypes.c_int32),
     ]
 
 
@@ -56,9 +67,10 @@ class vio_kp_prediction(ctypes.Structure):
 
 class vio_stats(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_int64), ("last_gpu_ms", ctypes.c_double),
-                ("last_stage_ms", ctypes.c_double * 3), ("last_tracked", ctypes.c_int32),
+                ("last_stage_ms", ctypes.c_double * 3), ("last_learned_ms", ctypes.c_double * 2),
+                ("last_tracked", ctypes.c_int32),
                 ("last_lost", ctypes.c_int32), ("last_detected", ctypes.c_int32),
-                ("last_matched", ctypes.c_int32)]
+                ("last_matched", ctypes.c_int32), ("last_fallback", ctypes.c_int32)]
 
 
 TRACK_DTYPE = np.dtype([
@@ -87,9 +99,29 @@ lib.vio_frontend_get_cell_winners.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i3
 lib.vio_frontend_get_stats.argtypes = [_vp, _P(vio_stats)]
 lib.vio_frontend_last_error.argtypes = [_vp]
 lib.vio_frontend_last_error.restype = ctypes.c_char_p
+lib.vio_frontend_set_mlp.argtypes = [_vp, _vp, _i32, ctypes.c_float]
+lib.vio_frontend_stage_frame.argtypes = [_vp, _i32, _i64, _vp, _vp]
+lib.vio_frontend_stage_frame_device.argtypes = [_vp, _i32, _i64, _vp, _vp]
+lib.vio_frontend_step.argtypes = [_vp]
+lib.vio_frontend_stage_frames_device.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
+lib.vio_frontend_get_features.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
+# learned-initialisation network (vio_mlp.h)
+VIO_MLP_NPARAM = 21123
+lib.vio_mlp_create.argtypes = [_i32, _P(_vp)]
+lib.vio_mlp_destroy.argtypes = [_vp]
+lib.vio_mlp_destroy.restype = None
+lib.vio_mlp_set_params.argtypes = [_vp, _vp, _i32]
+lib.vio_mlp_get_params.argtypes = [_vp, _vp, _i32]
+lib.vio_mlp_forward.argtypes = [_vp, _vp, _i32, _vp, _vp]
+lib.vio_mlp_gradient.argtypes = [_vp, _vp, _vp, _i32, _vp, _P(ctypes.c_float), _vp]
+lib.vio_mlp_train_step.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_float, _P(ctypes.c_float), _vp]
 for _name in ("vio_frontend_create", "vio_frontend_push_stereo_frame", "vio_frontend_push_stereo_frame_device",
               "vio_frontend_get_tracks", "vio_frontend_set_keypoints", "vio_frontend_get_keypoints",
-              "vio_frontend_get_pyramid", "vio_frontend_get_cell_winners", "vio_frontend_get_stats"):
+              "vio_frontend_get_pyramid", "vio_frontend_get_cell_winners", "vio_frontend_get_stats",
+              "vio_frontend_set_mlp", "vio_frontend_get_features", "vio_frontend_stage_frame",
+              "vio_frontend_stage_frame_device", "vio_frontend_step", "vio_frontend_stage_frames_device",
+              "vio_mlp_create", "vio_mlp_set_params", "vio_mlp_get_params",
+              "vio_mlp_forward", "vio_mlp_gradient", "vio_mlp_train_step"):
     getattr(lib, _name).restype = ctypes.c_int
 
 

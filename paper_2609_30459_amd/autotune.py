@@ -1,0 +1,138 @@
+"""Picks the tracker's launch shape per workload and device by measurement.
+
+The tracker runs one wave64 per work item (a temporal track or a stereo
+match). Its launch shape is free: one wave per item in workgroups of 1, 2 or
+4 waves, or a persistent grid of 1..16 waves per compute unit popping items
+from a shared queue. Every shape gives the same records bit for bit; only the
+device time differs, and which is fastest depends on the item count, the
+levels and iterations, and the chip. Each candidate runs the same frames of
+the workload (device-resident, kernels launched one by one with HIP events
+attached to their dispatches) and is scored by the tracker kernel's mean
+duration; the winner goes into a JSON cache keyed by the device's
+architecture and compute-unit count, which the benchmark reads.
+
+    python -m paper_2609_30459_amd.autotune --workload batch16 --init const_vel
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned", "launch.json")
+
+# (waves_per_cu, block_waves); waves_per_cu 0 = one wave per item
+CANDIDATES = [(0, 1), (0, 2), (0, 4), (1, 4), (2, 4), (4, 4), (8, 4), (16, 4), (2, 1), (4, 2), (8, 2)]
+
+
+def device_key() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return f"{p.gcnArchName.split(':')[0]}_{p.multi_processor_count}cu"
+
+
+def _load_cache(path=CACHE):
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def lookup(workload: str, init: str, path=CACHE):
+    """The cached choice for this device, workload and init mode, or None."""
+    entry = _load_cache(path).get(device_key(), {}).get(f"{workload}:{init}")
+    return entry
+
+
+def _workloads(name):
+    import synthgen
+    from synthgen.workloads import BATCH16
+    return list(BATCH16) if name == "batch16" else [synthgen.WORKLOADS[name]]
+
+
+def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None, learned_levels=2,
+            learned_iters=3, log=print):
+    """Mean tracker-kernel and all-kernel durations (ms) of each launch shape."""
+    import torch
+
+    import paper_2609_30459_amd as vf
+    import synthgen
+    from paper_2609_30459_amd.train_mlp import load_weights
+
+    ws = _workloads(workload)
+    n = warmup + frames
+    seqs = [synthgen.sequence(w, seq=0, stream=i, n_frames=n) for i, w in enumerate(ws)]
+    devs = [torch.from_numpy(q.frames).cuda() for q in seqs]
+    streams = [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in ws]
+    extra = {}
+    if init == "learned":
+        params, rho, _ = load_weights(weights or os.path.join(HERE, "weights", "mlp_stereo1280.bin"))
+        extra = dict(init_mode=1, learned_levels=learned_levels, learned_iters=learned_iters, learned_rho=rho)
+    ids = list(range(len(ws)))
+    out = []
+    for wpc, bw in shapes:
+        p = vf.params_for(ws[0], eager=True, track_waves_per_cu=wpc, track_block_waves=bw, **extra)
+        track, total = [], []
+        with vf.Frontend(streams, p) as fe:
+            if init == "learned":
+                fe.set_mlp(params, rho)
+            for t in range(n):
+                imgs = [devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)]
+                fe.stage_frames_device(ids, [t + 1] * len(ws), imgs)
+                fe.step()
+                if t >= warmup:
+                    st = fe.stats()
+                    track.append(st["last_stage_ms"][1])
+                    total.append(sum(st["last_stage_ms"]) + sum(max(0.0, m) for m in st["last_learned_ms"]))
+        r = {"track_waves_per_cu": wpc, "track_block_waves": bw, "track_ms": float(np.mean(track)),
+             "kernels_ms": float(np.mean(total))}
+        log(f"  waves/CU {wpc:2d}  waves/block {bw}: tracker {r['track_ms'] * 1e3:7.1f} us, "
+            f"all kernels {r['kernels_ms'] * 1e3:7.1f} us")
+        out.append(r)
+    return out
+
+
+def tune(workload: str, init: str, frames=40, path=CACHE, log=print, **kw):
+    """Measures every candidate, stores the fastest in the cache and returns it."""
+    t0 = time.time()
+    res = measure(workload, init, CANDIDATES, frames=frames, log=log, **kw)
+    best = min(res, key=lambda r: r["track_ms"])
+    entry = {"track_waves_per_cu": best["track_waves_per_cu"], "track_block_waves": best["track_block_waves"],
+             "track_ms": best["track_ms"], "frames": frames, "candidates": res}
+    cache = _load_cache(path)
+    cache.setdefault(device_key(), {})[f"{workload}:{init}"] = entry
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path + ".tmp", "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(path + ".tmp", path)
+    log(f"{workload}:{init} -> waves/CU {entry['track_waves_per_cu']}, waves/block {entry['track_block_waves']} "
+        f"({time.time() - t0:.1f} s)")
+    return entry
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", action="append", help="repeatable; default stereo752, stereo1280, batch16")
+    ap.add_argument("--init", choices=["const_vel", "learned", "both"], default="both")
+    ap.add_argument("--frames", type=int, default=40)
+    ap.add_argument("--cache", default=CACHE)
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(HERE))
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    inits = ["const_vel", "learned"] if args.init == "both" else [args.init]
+    for wl in args.workload or ["stereo752", "stereo1280", "batch16"]:
+        for init in inits:
+            log(f"tuning {wl} ({init})")
+            tune(wl, init, frames=args.frames, path=args.cache, log=log)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,6 +1,7 @@
 // Device-side data layout of the frontend, shared by the kernels and the host
 // runtime of this library (not by anything outside it).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -14,7 +15,27 @@ constexpr int kMaxCams = VIO_MAX_CAMERAS;
 constexpr int kPatch = 52;      // pattern points (Sec. III-E)
 constexpr int kTile = 64;       // level-0 output tile edge of the pyramid/detector kernel
 constexpr int kPyrThreads = 1024;
-constexpr int kTrackWaves = 4;  // waves (keypoints) per tracking block
+// Kernel timing: while set, the frontend's kernel launches on this thread
+// attach these events to the dispatch itself (the kernel's own start and end
+// timestamps, without the gaps between launches); null for plain launches and
+// during graph capture.
+struct KernelTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelTiming tl_timing;
+
+template <class F, class... A>
+inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, A... args) {
+  if (tl_timing.start)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, tl_timing.start, tl_timing.stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
+// Word 3 of a raw buffer resource on the gfx9 family (32-bit data format,
+// byte-addressed range check).
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kTrackWaves = 4;  // most waves (keypoints) per tracking block
 constexpr int kSelectThreads = 1024;
 
 // Live keypoint, 32 bytes (same layout as vio_keypoint).
@@ -53,7 +74,9 @@ struct CamDesc {
   TrackRes* sres;                    // stereo match of every cell winner [ncells]
   vio_track* rec;                    // output records [rec_cap], in mapped pinned host memory
   int32_t* rec_count_out;            // record count of the last frame, mapped pinned host memory
+  int32_t* fallback_out;             // learned tracks that fell back to the plain tracker, mapped host memory
   int rec_cap;
+  int row_off;                       // first row of this camera in the learned-init feature/guess buffers
 };
 
 // Per-frame inputs, copied host -> device before every frame.
@@ -69,6 +92,8 @@ struct FrameCam {
 };
 
 struct FrameTable {
+  int queue_head;  // work-queue counter of the persistent tracker, zero at the start of every frame
+  int pad[3];
   FrameCam cam[kMaxCams];
 };
 
@@ -83,6 +108,21 @@ struct Tuning {
   int levels, iters;
   float fb_threshold, disparity0;
   int k, tmin, margin;
+  int learned;            // temporal tracks start from the learned guess
+  int llevels, liters;    // tracker budget from the guess
+  float rho;              // residual RMS above which a learned track falls back
+  const float* guess;     // [rows][3] network outputs (learned mode)
+};
+
+// Learned-initialisation network on the device (see vio_mlp.h).
+struct MlpDev {
+  float* P;        // master parameters [VIO_MLP_NPARAM]
+  float* m;        // Adam first moments
+  float* v;        // Adam second moments
+  uint16_t* W1b;   // bf16 [128][32]
+  uint16_t* W2b;   // bf16 [128][128]
+  uint16_t* W2tb;  // bf16 [128][128], transposed
+  uint16_t* W3b;   // bf16 [3][128]
 };
 
 // Work items of the tracking kernel: one segment per (camera, mode).
@@ -100,9 +140,24 @@ struct Prediction {
 hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end,
                                    int tile_base, int n_tiles, int levels, int tmin, int margin, hipStream_t s);
 size_t pyr_detect_lds_bytes(int levels);
-hipError_t launch_track(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt,
-                        const TrackSeg* d_segs, int n_segs, int n_items, const Prediction* d_pred,
-                        Tuning tune, hipStream_t s);
+// Tracking work items [item_base, item_base + n_items) over the segments
+// d_segs[0..n_segs) (segment begins are global item indices). waves_per_cu = 0
+// launches one wave per item; > 0 launches a persistent grid of that many
+// waves per compute unit that pops items from FrameTable::queue_head.
+// Launch shape of the tracker: waves_per_cu = 0 gives one wave per work item,
+// > 0 a persistent grid of waves_per_cu * n_cus waves; block_waves waves
+// (1, 2 or kTrackWaves) per workgroup.
+struct TrackShape {
+  int waves_per_cu, block_waves, n_cus;
+};
+hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
+                        int n_segs, int item_base, int n_items, const Prediction* d_pred, Tuning tune,
+                        TrackShape shape, hipStream_t s);
+// Features of cameras [cam_begin, cam_end); h_cams: host copy of the descriptors (caps).
+hipError_t launch_features(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt,
+                           const CamDesc* h_cams, int cam_begin, int cam_end, float* d_feat, hipStream_t s);
+hipError_t mlp_forward_launch(const MlpDev& M, const float* X, int K, float* Y, hipStream_t s);
+hipError_t mlp_pack_launch(const MlpDev& M, hipStream_t s);
 hipError_t launch_select(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt,
                          const int* d_stream_cams, int n_streams_launch, int cams_per_stream_max, Tuning tune,
                          hipStream_t s);

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "fe_common.h"
+#include "vio_mlp.h"
 
 using namespace vio;
 
@@ -30,20 +31,43 @@ constexpr int kMaxCellsAbi = 8192;  // matches the selection kernel's LDS tables
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Captured submit of a launch set: the whole frame as one graph.
+struct Graphs {
+  hipGraphExec_t whole = nullptr;
+  bool any() const { return whole != nullptr; }
+  void destroy() {
+    if (whole) (void)hipGraphExecDestroy(whole);
+    whole = nullptr;
+  }
+};
+
 struct StreamInfo {
   int first_cam, n_cams, w, h, cap, cell;
   int64_t frames = 0;
   int64_t last_t = 0;
   int tile_begin = 0, n_tiles = 0;
-  int seg_begin = 0, n_segs = 0, n_items = 0;
+  int seg_begin = 0, n_segs = 0, item_begin = 0, n_items = 0;
+  bool staged = false;     // a frame is staged for the next vio_frontend_step
+  int64_t staged_t = 0;
   size_t rec_off = 0, rec_n = 0;  // record range (in vio_track units) of the stream's cameras
-  hipGraphExec_t graph = nullptr;  // captured per-frame submit, replayed every frame
+  Graphs graph;                    // captured per-frame submit, replayed every frame
 };
 
 }  // namespace
 
+thread_local KernelTiming vio::tl_timing;
+
+// A set of cameras/streams launched together: one stream (push) or all (step).
+struct LaunchSet {
+  int cam_begin, cam_end, tile_begin, n_tiles, seg_begin, n_segs, item_begin, n_items, stream_begin, n_streams;
+};
+
+enum { kKernPyr, kKernFeatures, kKernMlp, kKernTrack, kKernSelect, kKernels };
+
 struct vio_frontend {
   vio_frontend_params P{};
+  int n_cus = 256;
+  Graphs graph_all;  // captured batched step
   std::vector<StreamInfo> streams;
   std::vector<CamDesc> cams;
   std::vector<TrackSeg> segs;
@@ -60,6 +84,12 @@ struct vio_frontend {
   Prediction* d_pred = nullptr;
   int pred_cap = 0;
   std::vector<size_t> rec_host_off;  // per camera, in records
+  // learned initialisation
+  bool learned = false, mlp_ready = false;
+  MlpDev mlp{};
+  float* d_feat = nullptr;   // [rows][32]
+  float* d_guess = nullptr;  // [rows][3]
+  int32_t* h_fallback = nullptr;
   // pinned host
   FrameTable* h_frame = nullptr;
   int32_t* h_rec_count = nullptr;
@@ -68,11 +98,14 @@ struct vio_frontend {
   size_t stage_bytes = 0;
   Prediction* h_pred = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};  // frame start and end on the launch stream
+  // eager launches: start/stop events attached to each kernel's dispatch
+  // (pyramid+detector, features, network, tracker, selection)
+  hipEvent_t kev[kKernels][2] = {};
   int device = 0;
   bool poisoned = false;
   bool fault_device = false;
-  bool eager = false;  // graph capture off (flag) or unavailable
+  bool eager = false;        // graph capture off (flag) or unavailable
   std::string err;
   vio_stats stats{};
 };
@@ -107,9 +140,19 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   for (int i = 0; i < p->n_thresholds; ++i)
     if (p->thresholds[i] < 0 || p->thresholds[i] > 254) return why = "threshold out of 0..254", VIO_EINVAL;
   if (p->edge_margin < 4) return why = "edge_margin below 4", VIO_EINVAL;
+  if (p->track_waves_per_cu < 0 || p->track_waves_per_cu > 64) return why = "track_waves_per_cu out of 0..64", VIO_EINVAL;
+  if (p->track_block_waves != 0 && p->track_block_waves != 1 && p->track_block_waves != 2 &&
+      p->track_block_waves != kTrackWaves)
+    return why = "track_block_waves must be 0, 1, 2 or 4", VIO_EINVAL;
+  if (p->flags & ~VIO_FLAG_EAGER) return why = "unknown flag bits", VIO_EINVAL;
   if (!(p->fb_threshold > 0.f)) return why = "fb_threshold must be positive", VIO_EINVAL;
   if (p->k_per_cell != 1) return why = "only k_per_cell = 1 is implemented", VIO_EUNSUPPORTED;
-  if (p->init_mode != VIO_INIT_CONST_VEL) return why = "learned init needs weights", VIO_EUNSUPPORTED;
+  if (p->init_mode != VIO_INIT_CONST_VEL && p->init_mode != VIO_INIT_LEARNED) return why = "init_mode", VIO_EINVAL;
+  if (p->init_mode == VIO_INIT_LEARNED) {
+    if (p->learned_levels < 1 || p->learned_levels > 3 || p->learned_levels > p->levels)
+      return why = "learned_levels out of 1..min(3, levels)", VIO_EINVAL;
+    if (p->learned_iters < 1 || p->learned_iters > 32) return why = "learned_iters out of 1..32", VIO_EINVAL;
+  }
   return VIO_OK;
 }
 
@@ -144,10 +187,12 @@ void vio_frontend_destroy(vio_frontend* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (auto& si : h->streams)
-    if (si.graph) (void)hipGraphExecDestroy(si.graph);
+    si.graph.destroy();
+  h->graph_all.destroy();
   if (h->arena) (void)hipFree(h->arena);
   if (h->h_frame) (void)hipHostFree(h->h_frame);
   if (h->h_rec_count) (void)hipHostFree(h->h_rec_count);
+  if (h->h_fallback) (void)hipHostFree(h->h_fallback);
   if (h->h_rec) (void)hipHostFree(h->h_rec);
   if (h->h_stage) (void)hipHostFree(h->h_stage);
   if (h->h_pred) (void)hipHostFree(h->h_pred);
@@ -173,7 +218,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     size_t lvl[2][kMaxLevels], state[2], res, keys[2], sres, rec;
   };
   std::vector<CamOffs> co(n_cams);
-  int cam = 0, tiles = 0;
+  int cam = 0, tiles = 0, rows_total = 0, items = 0;
   size_t rec_total = 0, stage = 0;
   for (int s = 0; s < n_streams; ++s) {
     StreamInfo si;
@@ -186,7 +231,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     si.tile_begin = tiles;
     si.rec_off = rec_total;
     si.seg_begin = (int)h->segs.size();
-    int items = 0;
+    si.item_begin = items;
     for (int k = 0; k < si.n_cams; ++k, ++cam) {
       CamDesc& c = h->cams[cam];
       std::memset(&c, 0, sizeof c);
@@ -217,6 +262,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
         co[cam].sres = take(sizeof(TrackRes) * c.ncells);
       }
       c.rec_cap = 2 * si.cap;
+      c.row_off = rows_total;
+      rows_total += si.cap;
       co[cam].rec = rec_total;
       rec_total += c.rec_cap;
       stage += (size_t)si.w * si.h;
@@ -232,7 +279,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       }
     }
     si.n_segs = (int)h->segs.size() - si.seg_begin;
-    si.n_items = items;
+    si.n_items = items - si.item_begin;
     si.n_tiles = tiles - si.tile_begin;
     si.rec_n = rec_total - si.rec_off;
     h->streams.push_back(si);
@@ -249,6 +296,17 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   const size_t o_segs = take(sizeof(TrackSeg) * h->segs.size());
   const size_t o_sc = take(sizeof(int) * h->stream_cams.size());
   const size_t o_pred = take(sizeof(Prediction) * std::max(1, h->pred_cap));
+  size_t o_feat = 0, o_guess = 0, o_P = 0, o_W1 = 0, o_W2 = 0, o_W2t = 0, o_W3 = 0;
+  if (h->learned) {
+    const int rows = (rows_total + 15) / 16 * 16;
+    o_feat = take(sizeof(float) * 32 * rows);
+    o_guess = take(sizeof(float) * 3 * rows);
+    o_P = take(sizeof(float) * VIO_MLP_NPARAM);
+    o_W1 = take(2 * 128 * 32);
+    o_W2 = take(2 * 128 * 128);
+    o_W2t = take(2 * 128 * 128);
+    o_W3 = take(2 * 3 * 128);
+  }
   const size_t arena_bytes = off;
 
   // ---- device ---------------------------------------------------------------
@@ -259,6 +317,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(h, VIO_EDEVICE, "no HIP device");
   HIP_CHECK(h, hipGetDevice(&h->device));
+  HIP_CHECK(h, hipDeviceGetAttribute(&h->n_cus, hipDeviceAttributeMultiprocessorCount, h->device));
   int lds_max = 0;
   HIP_CHECK(h, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
   const size_t lds_need = pyr_detect_lds_bytes(P.levels);
@@ -288,6 +347,15 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->d_segs = reinterpret_cast<TrackSeg*>(base + o_segs);
   h->d_stream_cams = reinterpret_cast<int*>(base + o_sc);
   h->d_pred = reinterpret_cast<Prediction*>(base + o_pred);
+  if (h->learned) {
+    h->d_feat = reinterpret_cast<float*>(base + o_feat);
+    h->d_guess = reinterpret_cast<float*>(base + o_guess);
+    h->mlp.P = reinterpret_cast<float*>(base + o_P);
+    h->mlp.W1b = reinterpret_cast<uint16_t*>(base + o_W1);
+    h->mlp.W2b = reinterpret_cast<uint16_t*>(base + o_W2);
+    h->mlp.W2tb = reinterpret_cast<uint16_t*>(base + o_W2t);
+    h->mlp.W3b = reinterpret_cast<uint16_t*>(base + o_W3);
+  }
   HIP_CHECK(h, hipMemcpy(h->d_segs, h->segs.data(), sizeof(TrackSeg) * h->segs.size(), hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->d_stream_cams, h->stream_cams.data(), sizeof(int) * h->stream_cams.size(),
                          hipMemcpyHostToDevice));
@@ -296,24 +364,30 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->stage_bytes = stage;
   if (hipHostMalloc((void**)&h->h_frame, sizeof(FrameTable)) != hipSuccess ||
       hipHostMalloc((void**)&h->h_rec_count, sizeof(int32_t) * n_cams) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_fallback, sizeof(int32_t) * n_cams) != hipSuccess ||
       hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * rec_total) != hipSuccess ||
       hipHostMalloc((void**)&h->h_stage, stage) != hipSuccess ||
       hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * std::max(1, h->pred_cap)) != hipSuccess)
     return fail(h, VIO_ENOMEM, "pinned host buffers");
   std::memset(h->h_frame, 0, sizeof(FrameTable));
   std::memset(h->h_rec_count, 0, sizeof(int32_t) * n_cams);
+  std::memset(h->h_fallback, 0, sizeof(int32_t) * n_cams);
   vio_track* rec_dev = nullptr;
-  int32_t* cnt_dev = nullptr;
+  int32_t *cnt_dev = nullptr, *fb_dev = nullptr;
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&rec_dev, h->h_rec, 0));
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&cnt_dev, h->h_rec_count, 0));
+  HIP_CHECK(h, hipHostGetDevicePointer((void**)&fb_dev, h->h_fallback, 0));
   for (int c = 0; c < n_cams; ++c) {
     h->cams[c].rec = rec_dev + co[c].rec;
     h->cams[c].rec_count_out = cnt_dev + c;
+    h->cams[c].fallback_out = fb_dev + c;
     h->rec_host_off.push_back(co[c].rec);
   }
   HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
   HIP_CHECK(h, hipStreamCreate(&h->stream));
   for (hipEvent_t& e : h->ev) HIP_CHECK(h, hipEventCreate(&e));
+  for (auto& pr : h->kev)
+    for (hipEvent_t& e : pr) HIP_CHECK(h, hipEventCreate(&e));
   return VIO_OK;
 }
 
@@ -342,6 +416,7 @@ int vio_frontend_create(const vio_stream_desc* streams, int32_t n_streams, const
   if (!h) return VIO_ENOMEM;
   h->P = *params;
   h->eager = (params->flags & VIO_FLAG_EAGER) != 0;
+  h->learned = params->init_mode == VIO_INIT_LEARNED;
   const int rc = create_impl(h, streams, n_streams);
   if (rc != VIO_OK) {
     vio_frontend_destroy(h);
@@ -362,99 +437,163 @@ static Tuning tuning(const vio_frontend* h) {
   t.k = h->P.k_per_cell;
   t.tmin = h->P.thresholds[h->P.n_thresholds - 1];
   t.margin = h->P.edge_margin;
+  t.learned = h->learned ? 1 : 0;
+  t.llevels = h->P.learned_levels;
+  t.liters = h->P.learned_iters;
+  t.rho = h->P.learned_rho;
+  t.guess = h->d_guess;
   return t;
 }
 
-// Enqueues one frame of stream s on `st`: frame table copy and the three
-// kernels, with a timing event between kernels when `timed` (eager launches).
-// The untimed sequence is what the stream's graph captures; nothing in it
-// changes between frames (per-frame inputs live in the frame table).
-static hipError_t enqueue_frame(vio_frontend* h, int s, hipStream_t st, bool timed) {
-  StreamInfo& si = h->streams[s];
-  const Tuning tune = tuning(h);
-  hipError_t e;
-  if ((e = hipMemcpyAsync(h->d_frame, h->h_frame, sizeof(FrameTable), hipMemcpyHostToDevice, st))) return e;
-  if (timed && (e = hipEventRecord(h->ev[0], st))) return e;
-  if ((e = launch_pyr_detect_range(h->d_cams, h->d_frame, si.first_cam, si.first_cam + si.n_cams, si.tile_begin,
-                                   si.n_tiles, tune.levels, tune.tmin, tune.margin, st)))
-    return e;
-  if (timed && (e = hipEventRecord(h->ev[1], st))) return e;
-  if ((e = launch_track(h->d_cams, h->d_frame, h->d_cnt, h->d_segs + si.seg_begin, si.n_segs, si.n_items,
-                        h->d_pred, tune, st)))
-    return e;
-  if (timed && (e = hipEventRecord(h->ev[2], st))) return e;
-  if ((e = launch_select(h->d_cams, h->d_frame, h->d_cnt, h->d_stream_cams + 2 * s, 1, si.n_cams, tune, st))) return e;
-  return timed ? hipEventRecord(h->ev[3], st) : hipSuccess;
+static LaunchSet stream_set(const vio_frontend* h, int s) {
+  const StreamInfo& si = h->streams[s];
+  return {si.first_cam, si.first_cam + si.n_cams, si.tile_begin, si.n_tiles, si.seg_begin, si.n_segs,
+          si.item_begin, si.n_items, s, 1};
 }
 
-// Captures the stream's frame into a graph on first use; a capture failure
-// switches the handle to eager launches for good.
-static void ensure_graph(vio_frontend* h, int s) {
-  StreamInfo& si = h->streams[s];
-  if (h->eager || si.graph) return;
+static LaunchSet all_set(const vio_frontend* h) {
+  const StreamInfo& last = h->streams.back();
+  return {0, (int)h->cams.size(), 0, h->total_tiles, 0, (int)h->segs.size(), 0, last.item_begin + last.n_items, 0,
+          (int)h->streams.size()};
+}
+
+// Enqueues one step of a frame of the launch set on `st`: 0 = frame table
+// copy, 1 = pyramid+detector, 2 = (learned mode: features and the network)
+// tracker, 3 = selection. Nothing enqueued changes between frames (per-frame
+// inputs live in the frame table), so the sequence can be captured once.
+// `timed` attaches each kernel's start/stop events to its dispatch.
+static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_t st, int stage, bool timed) {
+  const Tuning tune = tuning(h);
+  auto timing = [&](int k) { tl_timing = timed ? KernelTiming{h->kev[k][0], h->kev[k][1]} : KernelTiming{}; };
+  struct Reset {
+    ~Reset() { tl_timing = KernelTiming{}; }
+  } reset;
+  hipError_t e;
+  if (stage == 0) return hipMemcpyAsync(h->d_frame, h->h_frame, sizeof(FrameTable), hipMemcpyHostToDevice, st);
+  if (stage == 1) {
+    timing(kKernPyr);
+    return launch_pyr_detect_range(h->d_cams, h->d_frame, ls.cam_begin, ls.cam_end, ls.tile_begin, ls.n_tiles,
+                                   tune.levels, tune.tmin, tune.margin, st);
+  }
+  if (stage == 2) {
+    if (h->learned) {
+      // features of every previous keypoint, then one network pass over the
+      // set's rows; the tracker reads the guesses
+      const int row0 = h->cams[ls.cam_begin].row_off;
+      int rows = 0;
+      for (int c = ls.cam_begin; c < ls.cam_end; ++c) rows += h->cams[c].cap;
+      timing(kKernFeatures);
+      if ((e = launch_features(h->d_cams, h->d_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->d_feat,
+                               st)))
+        return e;
+      timing(kKernMlp);
+      if ((e = mlp_forward_launch(h->mlp, h->d_feat + (size_t)row0 * 32, rows, h->d_guess + (size_t)row0 * 3, st)))
+        return e;
+    }
+    timing(kKernTrack);
+    return launch_track(h->d_cams, h->d_frame, h->d_cnt, h->d_segs + ls.seg_begin, ls.n_segs, ls.item_begin,
+                        ls.n_items, h->d_pred, tune,
+                        TrackShape{h->P.track_waves_per_cu,
+                                   h->P.track_block_waves ? h->P.track_block_waves : kTrackWaves, h->n_cus},
+                        st);
+  }
+  timing(kKernSelect);
+  return launch_select(h->d_cams, h->d_frame, h->d_cnt, h->d_stream_cams + 2 * ls.stream_begin, ls.n_streams, 0,
+                       tune, st);
+}
+
+static hipError_t enqueue_frame(vio_frontend* h, const LaunchSet& ls, hipStream_t st, bool timed) {
+  for (int k = 0; k <= 3; ++k) {
+    const hipError_t e = enqueue_stage(h, ls, st, k, timed);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Captures a launch set into a graph on first use; a capture failure switches
+// the handle to eager launches for good.
+static void ensure_graph(vio_frontend* h, const LaunchSet& ls, Graphs* gr) {
+  if (h->eager || gr->any()) return;
   hipGraph_t g = nullptr;
   bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
   if (ok) {
-    const hipError_t e = enqueue_frame(h, s, h->stream, false);
+    const hipError_t e = enqueue_frame(h, ls, h->stream, false);
     ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && e == hipSuccess && g;
   }
-  if (ok) ok = hipGraphInstantiate(&si.graph, g, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) ok = hipGraphInstantiate(&gr->whole, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
   if (!ok) {
-    si.graph = nullptr;
+    gr->destroy();
     h->eager = true;
     (void)hipGetLastError();
   }
 }
 
-// Runs one frame of stream s whose level-0 sources are already in h_frame.
-static int run_frame(vio_frontend* h, int s, hipStream_t st) {
-  StreamInfo& si = h->streams[s];
-  ensure_graph(h, s);
-  if (si.graph) {
-    // events around the graph: the frame's device time (per-kernel times need eager launches)
-    HIP_CHECK(h, hipEventRecord(h->ev[0], st));
-    HIP_CHECK(h, hipGraphLaunch(si.graph, st));
-    HIP_CHECK(h, hipEventRecord(h->ev[3], st));
+// Runs one frame of a launch set whose inputs are in h_frame, waits, and
+// updates the statistics of the set's streams. Eager launches report each
+// kernel's duration from its dispatch timestamps; a graph replay reports the
+// frame's device time only.
+static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t st) {
+  ensure_graph(h, ls, gr);
+  HIP_CHECK(h, hipEventRecord(h->ev[0], st));
+  if (gr->whole) {
+    HIP_CHECK(h, hipGraphLaunch(gr->whole, st));
   } else {
-    HIP_CHECK(h, enqueue_frame(h, s, st, true));
+    HIP_CHECK(h, enqueue_frame(h, ls, st, true));
   }
+  HIP_CHECK(h, hipEventRecord(h->ev[1], st));
   HIP_CHECK(h, hipStreamSynchronize(st));
   float ms = 0.f;
-  HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[3]));
-  for (int k = 0; k < 3; ++k) {
-    float m = -1.f;
-    if (!si.graph) HIP_CHECK(h, hipEventElapsedTime(&m, h->ev[k], h->ev[k + 1]));
-    h->stats.last_stage_ms[k] = m;
+  HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+  float km[kKernels];
+  for (int k = 0; k < kKernels; ++k) {
+    km[k] = -1.f;
+    const bool ran = k == kKernPyr || k == kKernTrack || k == kKernSelect || h->learned;
+    if (!gr->whole && ran) HIP_CHECK(h, hipEventElapsedTime(&km[k], h->kev[k][0], h->kev[k][1]));
   }
-  si.frames += 1;
-  h->stats.frames += 1;
+  h->stats.last_stage_ms[0] = km[kKernPyr];
+  h->stats.last_stage_ms[1] = km[kKernTrack];
+  h->stats.last_stage_ms[2] = km[kKernSelect];
+  h->stats.last_learned_ms[0] = km[kKernFeatures];
+  h->stats.last_learned_ms[1] = km[kKernMlp];
   h->stats.last_gpu_ms = ms;
-  int tr = 0, lost = 0, det = 0, mat = 0;
-  for (int k = 0; k < si.n_cams; ++k) {
-    const CamDesc& c = h->cams[si.first_cam + k];
-    const int n = h->h_rec_count[si.first_cam + k];
-    const vio_track* r = h->h_rec + h->rec_host_off[si.first_cam + k];
+  h->stats.frames += 1;
+  int tr = 0, lost = 0, det = 0, mat = 0, fb = 0;
+  for (int c = ls.cam_begin; c < ls.cam_end; ++c) {
+    if (!h->h_frame->cam[c].active) continue;
+    const CamDesc& cd = h->cams[c];
+    const int n = h->h_rec_count[c];
+    const vio_track* r = h->h_rec + h->rec_host_off[c];
     for (int i = 0; i < n; ++i) {
       switch (r[i].status) {
         case VIO_TRACKED: ++tr; break;
         case VIO_DETECTED: ++det; break;
         case VIO_MATCHED: ++mat; break;
         default:
-          if (r[i].age > 0 || c.detect) ++lost;
+          if (r[i].age > 0 || cd.detect) ++lost;
       }
     }
+    if (h->learned) fb += h->h_fallback[c];
   }
+  h->stats.last_fallback = fb;
   h->stats.last_tracked = tr;
   h->stats.last_lost = lost;
   h->stats.last_detected = det;
   h->stats.last_matched = mat;
+  for (int s = ls.stream_begin; s < ls.stream_begin + ls.n_streams; ++s)
+    if (h->h_frame->cam[h->streams[s].first_cam].active) h->streams[s].frames += 1;
   return VIO_OK;
+}
+
+// Runs one frame of stream s whose level-0 sources are already in h_frame.
+static int run_frame(vio_frontend* h, int s, hipStream_t st) {
+  return run_set(h, stream_set(h, s), &h->streams[s].graph, st);
 }
 
 static int check_push(vio_frontend* h, int32_t s, int64_t t_ns) {
   if (!h) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (h->learned && !h->mlp_ready) return fail(h, VIO_ESTATE, "learned init: call vio_frontend_set_mlp first");
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (si.frames > 0 && t_ns <= si.last_t) return fail(h, VIO_ESTATE, "timestamps must increase");
@@ -462,10 +601,9 @@ static int check_push(vio_frontend* h, int32_t s, int64_t t_ns) {
   return VIO_OK;
 }
 
-static void fill_frame(vio_frontend* h, int s) {
+static void fill_stream(vio_frontend* h, int s) {
   const StreamInfo& si = h->streams[s];
   const int par = (int)(si.frames & 1);
-  for (int c = 0; c < (int)h->cams.size(); ++c) h->h_frame->cam[c].active = 0;
   for (int k = 0; k < si.n_cams; ++k) {
     FrameCam& f = h->h_frame->cam[si.first_cam + k];
     f.parity = par;
@@ -474,6 +612,38 @@ static void fill_frame(vio_frontend* h, int s) {
     f.n_pred = 0;
     f.pred_off = 0;
   }
+}
+
+static void fill_frame(vio_frontend* h, int s) {
+  for (int c = 0; c < (int)h->cams.size(); ++c) h->h_frame->cam[c].active = 0;
+  fill_stream(h, s);
+}
+
+static size_t stage_offset(const vio_frontend* h, int s) {
+  size_t so = 0;
+  for (int k = 0; k < h->streams[s].first_cam; ++k) so += (size_t)h->cams[k].w * h->cams[k].h;
+  return so;
+}
+
+// Copies host images of stream s into pinned staging and queues their upload
+// into the current pyramid slot's level 0.
+static int upload_host_images(vio_frontend* h, int s, const uint8_t* const* images, const int32_t* strides) {
+  const StreamInfo& si = h->streams[s];
+  const int par = (int)(si.frames & 1);
+  size_t so = stage_offset(h, s);
+  for (int k = 0; k < si.n_cams; ++k) {
+    const int c = si.first_cam + k;
+    const CamDesc& cd = h->cams[c];
+    uint8_t* stg = h->h_stage + so;
+    for (int y = 0; y < si.h; ++y) std::memcpy(stg + (size_t)y * si.w, images[k] + (size_t)y * strides[k], si.w);
+    HIP_CHECK(h, hipMemcpy2DAsync(cd.lvl[par][0], cd.pitch[0], stg, si.w, si.w, si.h, hipMemcpyHostToDevice, h->stream));
+    FrameCam& f = h->h_frame->cam[c];
+    f.src = cd.lvl[par][0];
+    f.src_pitch = cd.pitch[0];
+    f.copy_l0 = 0;
+    so += (size_t)si.w * si.h;
+  }
+  return VIO_OK;
 }
 
 static int upload_predictions(vio_frontend* h, int s, const vio_kp_prediction* pred, int32_t n_pred, hipStream_t st) {
@@ -512,21 +682,8 @@ int vio_frontend_push_stereo_frame(vio_frontend* h, int32_t s, int64_t t_ns, con
   fill_frame(h, s);
   rc = upload_predictions(h, s, pred, n_pred, h->stream);
   if (rc != VIO_OK) return rc;
-  const int par = (int)(si.frames & 1);
-  size_t so = 0;
-  for (int k = 0; k < si.first_cam; ++k) so += (size_t)h->cams[k].w * h->cams[k].h;
-  for (int k = 0; k < si.n_cams; ++k) {
-    const int c = si.first_cam + k;
-    const CamDesc& cd = h->cams[c];
-    uint8_t* stg = h->h_stage + so;
-    for (int y = 0; y < si.h; ++y) std::memcpy(stg + (size_t)y * si.w, images[k] + (size_t)y * strides[k], si.w);
-    HIP_CHECK(h, hipMemcpy2DAsync(cd.lvl[par][0], cd.pitch[0], stg, si.w, si.w, si.h, hipMemcpyHostToDevice, h->stream));
-    FrameCam& f = h->h_frame->cam[c];
-    f.src = cd.lvl[par][0];
-    f.src_pitch = cd.pitch[0];
-    f.copy_l0 = 0;
-    so += (size_t)si.w * si.h;
-  }
+  rc = upload_host_images(h, s, images, strides);
+  if (rc != VIO_OK) return rc;
   rc = run_frame(h, s, h->stream);
   if (rc != VIO_OK) return rc;
   si.last_t = t_ns;
@@ -552,6 +709,75 @@ int vio_frontend_push_stereo_frame_device(vio_frontend* h, int32_t s, int64_t t_
   rc = run_frame(h, s, st);
   if (rc != VIO_OK) return rc;
   si.last_t = t_ns;
+  return VIO_OK;
+}
+
+int vio_frontend_stage_frame(vio_frontend* h, int32_t s, int64_t t_ns, const uint8_t* const* images,
+                             const int32_t* strides) {
+  int rc = check_push(h, s, t_ns);
+  if (rc != VIO_OK) return rc;
+  StreamInfo& si = h->streams[s];
+  if (!images || !strides) return fail(h, VIO_EINVAL, "null images or strides");
+  for (int k = 0; k < si.n_cams; ++k)
+    if (!images[k] || strides[k] < si.w) return fail(h, VIO_EINVAL, "camera %d: null image or stride < width", k);
+  fill_stream(h, s);
+  rc = upload_host_images(h, s, images, strides);
+  if (rc != VIO_OK) return rc;
+  si.staged = true;
+  si.staged_t = t_ns;
+  return VIO_OK;
+}
+
+int vio_frontend_stage_frame_device(vio_frontend* h, int32_t s, int64_t t_ns, const void* const* d_images,
+                                    const int32_t* pitches) {
+  int rc = check_push(h, s, t_ns);
+  if (rc != VIO_OK) return rc;
+  StreamInfo& si = h->streams[s];
+  if (!d_images || !pitches) return fail(h, VIO_EINVAL, "null images or pitches");
+  for (int k = 0; k < si.n_cams; ++k)
+    if (!d_images[k] || pitches[k] < si.w) return fail(h, VIO_EINVAL, "camera %d: null image or pitch < width", k);
+  fill_stream(h, s);
+  for (int k = 0; k < si.n_cams; ++k) {
+    FrameCam& f = h->h_frame->cam[si.first_cam + k];
+    f.src = static_cast<const uint8_t*>(d_images[k]);
+    f.src_pitch = pitches[k];
+    f.copy_l0 = 1;
+  }
+  si.staged = true;
+  si.staged_t = t_ns;
+  return VIO_OK;
+}
+
+int vio_frontend_stage_frames_device(vio_frontend* h, int32_t n, const int32_t* streams, const int64_t* t_ns,
+                                     const void* const* d_images, const int32_t* pitches) {
+  if (!h || n < 0 || (n > 0 && (!streams || !t_ns || !d_images || !pitches))) return VIO_EINVAL;
+  int at = 0;
+  for (int i = 0; i < n; ++i) {
+    if (streams[i] < 0 || streams[i] >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream out of range");
+    const int rc = vio_frontend_stage_frame_device(h, streams[i], t_ns[i], d_images + at, pitches + at);
+    if (rc != VIO_OK) return rc;
+    at += h->streams[streams[i]].n_cams;
+  }
+  return VIO_OK;
+}
+
+int vio_frontend_step(vio_frontend* h) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (h->learned && !h->mlp_ready) return fail(h, VIO_ESTATE, "learned init: call vio_frontend_set_mlp first");
+  bool any = false;
+  for (auto& si : h->streams) {
+    any |= si.staged;
+    for (int k = 0; k < si.n_cams; ++k) h->h_frame->cam[si.first_cam + k].active = si.staged ? 1 : 0;
+  }
+  if (!any) return fail(h, VIO_ESTATE, "no frame staged");
+  const int rc = run_set(h, all_set(h), &h->graph_all, h->stream);
+  if (rc != VIO_OK) return rc;
+  for (auto& si : h->streams)
+    if (si.staged) {
+      si.last_t = si.staged_t;
+      si.staged = false;
+    }
   return VIO_OK;
 }
 
@@ -659,6 +885,49 @@ int vio_frontend_get_cell_winners(vio_frontend* h, int32_t s, int32_t camera, in
     out[3 * i] = idx % c.w;
     out[3 * i + 1] = idx / c.w;
     out[3 * i + 2] = (int)(keys[i] >> 24);
+  }
+  return VIO_OK;
+}
+
+int vio_frontend_set_mlp(vio_frontend* h, const float* params, int32_t n, float rho) {
+  if (!h || !params || n != VIO_MLP_NPARAM) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (!h->learned) return fail(h, VIO_ESTATE, "the frontend was not created with VIO_INIT_LEARNED");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream));
+  HIP_CHECK(h, hipMemcpy(h->mlp.P, params, sizeof(float) * VIO_MLP_NPARAM, hipMemcpyHostToDevice));
+  HIP_CHECK(h, mlp_pack_launch(h->mlp, h->stream));
+  HIP_CHECK(h, hipStreamSynchronize(h->stream));
+  if (rho >= 0.f) h->P.learned_rho = rho;
+  // the captured graphs hold the old threshold as a kernel argument
+  for (auto& si : h->streams)
+    if (si.graph.any()) {
+      si.graph.destroy();
+    }
+  h->graph_all.destroy();
+  h->mlp_ready = true;
+  return VIO_OK;
+}
+
+int vio_frontend_get_features(vio_frontend* h, int32_t s, int32_t camera, float* out, int32_t capacity,
+                              int32_t* n_out) {
+  if (!h || !n_out) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (!h->learned) return fail(h, VIO_ESTATE, "features exist in learned mode only");
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera out of range");
+  if (si.frames < 2) return fail(h, VIO_ESTATE, "features exist from the second frame on");
+  const int c = si.first_cam + camera;
+  // the temporal records of the last frame are the previous keypoints, in slot order
+  int32_t n = 0;
+  const int prev_slot = (int)(si.frames & 1);  // state slot the last frame read
+  HIP_CHECK(h, hipMemcpy(&n, &h->d_cnt->n_live[prev_slot][c], sizeof n, hipMemcpyDeviceToHost));
+  *n_out = n;
+  if (capacity < n * VIO_MLP_IN) return VIO_ETOOSMALL;
+  if (n > 0) {
+    if (!out) return VIO_EINVAL;
+    HIP_CHECK(h, hipMemcpy(out, h->d_feat + (size_t)h->cams[c].row_off * VIO_MLP_IN, sizeof(float) * VIO_MLP_IN * n,
+                           hipMemcpyDeviceToHost));
   }
   return VIO_OK;
 }

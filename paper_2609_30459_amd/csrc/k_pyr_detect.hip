@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __res
 template <int L>
 hipError_t launch_L(const CamDesc* cams, const FrameTable* frame, int cam_begin, int cam_end, int tile_base,
                     int n_tiles, int tmin, int margin, hipStream_t s) {
-  hipLaunchKernelGGL(k_pyr_detect<L>, dim3(n_tiles), dim3(kPyrThreads), 0, s, cams, frame, cam_begin, cam_end,
+  launch_kernel(k_pyr_detect<L>, dim3(n_tiles), dim3(kPyrThreads), 0, s, cams, frame, cam_begin, cam_end,
                      tile_base, tmin, margin);
   return hipGetLastError();
 }

@@ -88,9 +88,9 @@ __device__ __forceinline__ Kp make_kp(int64_t id, float x, float y, float px, fl
 // old order, with their records. Adds the survivors to `occ` when given.
 // Returns the survivor count; *n_rec receives the number of records written.
 __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev, unsigned* occ, ScanScratch& sc,
-                               int* n_rec) {
+                               int* n_rec, bool count_fallback) {
   const int P = fc.parity, Q = P ^ 1;
-  int base = 0;
+  int base = 0, n_fb = 0;
   for (int j0 = 0; j0 < n_prev; j0 += kSelectThreads) {
     const int j = j0 + (int)threadIdx.x;
     bool alive = false;
@@ -109,6 +109,11 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
     }
     int total;
     const int pos = base + block_scan_flag(alive, sc, total);
+    if (count_fallback) {
+      int fb_tot;
+      (void)block_scan_flag(j < n_prev && fc.has_prev && r.pad[0] != 0, sc, fb_tot);
+      n_fb += fb_tot;
+    }
     if (j < n_prev) {
       if (alive) {
         if (occ) {
@@ -124,6 +129,7 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
     base += total;
   }
   *n_rec = fc.has_prev ? n_prev : 0;
+  if (threadIdx.x == 0) *cd.fallback_out = n_fb;
   return base;
 }
 
@@ -154,7 +160,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
 
     // ---- left / mono camera: survivors and occupancy ----------------------
     int n_rec = 0;
-    const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec);
+    const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec, tune.learned != 0);
     __syncthreads();
 
     // ---- candidates of unmasked cells, score histogram --------------------
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       const FrameCam& fr = frame->cam[rc];
       const int PR = fr.parity;
       int n_rec_r = 0;
-      const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r);
+      const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, tune.learned != 0);
       int m_base = 0;
       for (int i0 = 0; i0 < n_new; i0 += kSelectThreads) {
         const int i = i0 + (int)threadIdx.x;
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
 hipError_t launch_select(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt, const int* d_stream_cams,
                          int n_streams_launch, int /*cams_per_stream_max*/, Tuning tune, hipStream_t s) {
   if (n_streams_launch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_select, dim3(n_streams_launch), dim3(kSelectThreads), 0, s, d_cams, d_frame, d_cnt,
+  launch_kernel(k_select, dim3(n_streams_launch), dim3(kSelectThreads), 0, s, d_cams, d_frame, d_cnt,
                      d_stream_cams, tune);
   return hipGetLastError();
 }

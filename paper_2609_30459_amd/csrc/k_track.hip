@@ -30,6 +30,8 @@
 // (left camera -> right camera of the pair): those matches depend only on the
 // current pyramids, so they run beside the temporal tracks instead of after the
 // selection, and the selection kernel picks the ones it keeps.
+#include <algorithm>
+
 #include "fe_common.h"
 
 namespace vio {
@@ -291,14 +293,35 @@ __device__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst,
   return r;
 }
 
-template <int L>
-__global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __restrict__ cams,
-                                                          const FrameTable* __restrict__ frame,
-                                                          const Counters* __restrict__ cnt,
-                                                          const TrackSeg* __restrict__ segs, int n_segs,
-                                                          const Prediction* __restrict__ pred, Tuning tune) {
-  const int lane = threadIdx.x & (kW - 1);
-  const int item = (int)blockIdx.x * kTrackWaves + (int)(threadIdx.x / kW);
+// Stores a wave-uniform 32-byte result without a branch on the lane id:
+// lanes 0..7 write one dword each through a buffer resource whose range is
+// exactly the record, and the hardware drops the other lanes' stores as out of
+// range. (A lane-id branch inside the persistent loop would let the compiler
+// split the wave across loop iterations; this keeps the loop body free of
+// lane-dependent control flow.)
+__device__ __forceinline__ void store_result(TrackRes* dst, const TrackRes& r, int lane) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)sizeof(TrackRes), kBufferWord3);
+  const uint32_t w[8] = {__builtin_bit_cast(uint32_t, r.x),     __builtin_bit_cast(uint32_t, r.y),
+                         __builtin_bit_cast(uint32_t, r.theta), __builtin_bit_cast(uint32_t, r.fb),
+                         __builtin_bit_cast(uint32_t, r.resid), (uint32_t)r.status,
+                         (uint32_t)r.pad[0],                    (uint32_t)r.pad[1]};
+  uint32_t val = w[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) val = lane == k ? w[k] : val;
+  __builtin_amdgcn_raw_buffer_store_b32(val, rs, lane * 4, 0, 0);
+}
+
+// One work item: a temporal track (camera c, slot j) or the stereo match of a
+// cell winner (camera c, cell j). LL > 0: learned initialisation -- temporal
+// tracks run LL levels from the network's guess and fall back to the plain
+// L-level tracker from the constant-velocity guess unless kept with a
+// residual RMS <= rho.
+template <int L, int LL>
+__device__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
+                             const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs, int n_segs,
+                             const Prediction* __restrict__ pred, const Tuning& tune, int item, int lane, float u,
+                             float v, float wgt) {
   int si = 0;
   while (si + 1 < n_segs && segs[si + 1].begin <= item) ++si;
   const TrackSeg sg = segs[si];
@@ -308,13 +331,12 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
   const CamDesc& cd = cams[c];
   const FrameCam& fc = frame->cam[c];
   if (!fc.active) return;
-  float u, v, wgt;
-  pattern_of(lane, u, v, wgt);
   const int P = fc.parity;
   if (sg.mode == kModeTemporal) {
     if (!fc.has_prev || j >= cnt->n_live[P ^ 1][c]) return;
     const Kp kp = cd.state[P ^ 1][j];
     float ix = kp.x + (kp.x - kp.px), iy = kp.y + (kp.y - kp.py);
+    bool predicted = false;
     const int np = fc.n_pred;
     if (np > 0) {  // caller predictions, ascending id: binary search
       const Prediction* pp = pred + fc.pred_off;
@@ -325,46 +347,127 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
         if (mid_id == kp.id) {
           ix = pp[mid].x;
           iy = pp[mid].y;
+          predicted = true;
           break;
         }
         if (mid_id < kp.id) lo = mid + 1;
         else hi = mid - 1;
       }
     }
-    const TrackRes r = track_fb<L>(cd, P ^ 1, cd, P, kp.x, kp.y, ix, iy, tune.iters, tune.fb_threshold, u, v, wgt);
-    if (lane == 0) cd.res[j] = r;
+    TrackRes r;
+    bool done = false;
+    if constexpr (LL > 0) {
+      if (!predicted) {
+        const float* gs = tune.guess + (size_t)(cd.row_off + j) * 3;
+        const float gx = kp.x + 16.f * gs[0], gy = kp.y + 16.f * gs[1];
+        r = track_fb<LL>(cd, P ^ 1, cd, P, kp.x, kp.y, gx, gy, tune.liters, tune.fb_threshold, u, v, wgt);
+        done = r.status == VIO_TRACKED && r.resid <= tune.rho;
+      }
+    }
+    if (!done) {
+      r = track_fb<L>(cd, P ^ 1, cd, P, kp.x, kp.y, ix, iy, tune.iters, tune.fb_threshold, u, v, wgt);
+      r.pad[0] = (LL > 0 && !predicted) ? 1 : 0;
+    }
+    store_result(cd.res + j, r, lane);
   } else {
     const uint32_t key = cd.keys[P][j];
     if (key == 0) return;
     const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
     const float x = (float)(idx % cd.w), y = (float)(idx / cd.w);
-    const TrackRes r = track_fb<L>(cd, P, cams[cd.partner], P, x, y, x - tune.disparity0, y, tune.iters,
-                                   tune.fb_threshold, u, v, wgt);
-    if (lane == 0) cd.sres[j] = r;
+    TrackRes r = track_fb<L>(cd, P, cams[cd.partner], P, x, y, x - tune.disparity0, y, tune.iters,
+                             tune.fb_threshold, u, v, wgt);
+    r.pad[0] = 0;
+    store_result(cd.sres + j, r, lane);
   }
 }
 
-template <int L>
-hipError_t launch_L(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
-                    int n_segs, int blocks, const Prediction* d_pred, Tuning tune, hipStream_t s) {
-  hipLaunchKernelGGL(k_track<L>, dim3(blocks), dim3(kW * kTrackWaves), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
-                     d_pred, tune);
+// One wave per work item.
+template <int L, int LL>
+__global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __restrict__ cams,
+                                                          const FrameTable* __restrict__ frame,
+                                                          const Counters* __restrict__ cnt,
+                                                          const TrackSeg* __restrict__ segs, int n_segs,
+                                                          int item_base, int n_items,
+                                                          const Prediction* __restrict__ pred, Tuning tune) {
+  const int lane = threadIdx.x & (kW - 1);
+  const int k = (int)blockIdx.x * (int)(blockDim.x / kW) + (int)(threadIdx.x / kW);
+  if (k >= n_items) return;
+  float u, v, wgt;
+  pattern_of(lane, u, v, wgt);
+  process_item<L, LL>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
+}
+
+// Persistent grid: every wave pops items from the frame's queue counter until
+// it runs past n_items (each pop advances the counter, so every wave exits).
+// The pop is branch-free: all lanes issue the atomic, lane 0 adding one and
+// the others zero, and the first lane's (lane 0's) old value is the item, so
+// no lane-dependent control flow enters the loop.
+template <int L, int LL>
+__global__ __launch_bounds__(kW* kTrackWaves) void k_track_persistent(const CamDesc* __restrict__ cams,
+                                                                     FrameTable* __restrict__ frame,
+                                                                     const Counters* __restrict__ cnt,
+                                                                     const TrackSeg* __restrict__ segs, int n_segs,
+                                                                     int item_base, int n_items,
+                                                                     const Prediction* __restrict__ pred,
+                                                                     Tuning tune) {
+  const int lane = threadIdx.x & (kW - 1);
+  float u, v, wgt;
+  pattern_of(lane, u, v, wgt);
+  for (;;) {
+    const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&frame->queue_head, lane == 0 ? 1 : 0));
+    if (k >= n_items) break;
+    process_item<L, LL>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
+  }
+}
+
+template <int L, int LL>
+hipError_t launch_L(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
+                    int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape sh, hipStream_t s) {
+  const int bw = sh.block_waves;
+  if (sh.waves_per_cu > 0) {
+    const int waves = std::min(n_items, sh.waves_per_cu * sh.n_cus);
+    const int blocks = (waves + bw - 1) / bw;
+    launch_kernel(k_track_persistent<L, LL>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs,
+                       n_segs, item_base, n_items, d_pred, tune);
+  } else {
+    const int blocks = (n_items + bw - 1) / bw;
+    launch_kernel(k_track<L, LL>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
+                       item_base, n_items, d_pred, tune);
+  }
   return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_LL(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
+                     int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape sh, hipStream_t s) {
+  const int ll = tune.learned ? tune.llevels : 0;
+  switch (ll) {
+    case 0: return launch_L<L, 0>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
+    case 1: return launch_L<L, 1>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
+    case 2: return launch_L<L, 2>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
+    case 3: return launch_L<L, 3>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_track(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
-                        int n_segs, int n_items, const Prediction* d_pred, Tuning tune, hipStream_t s) {
+hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
+                        int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape shape,
+                        hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  const int blocks = (n_items + kTrackWaves - 1) / kTrackWaves;
+  if (shape.block_waves < 1 || shape.block_waves > kTrackWaves || shape.n_cus < 1 || shape.waves_per_cu < 0)
+    return hipErrorInvalidValue;
   switch (tune.levels) {
-    case 1: return launch_L<1>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
-    case 2: return launch_L<2>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
-    case 3: return launch_L<3>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
-    case 4: return launch_L<4>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
-    case 5: return launch_L<5>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
-    case 6: return launch_L<6>(d_cams, d_frame, d_cnt, d_segs, n_segs, blocks, d_pred, tune, s);
+#define VIO_TRACK_CASE(LV) \
+  case LV: return launch_LL<LV>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, shape, s);
+    VIO_TRACK_CASE(1)
+    VIO_TRACK_CASE(2)
+    VIO_TRACK_CASE(3)
+    VIO_TRACK_CASE(4)
+    VIO_TRACK_CASE(5)
+    VIO_TRACK_CASE(6)
+#undef VIO_TRACK_CASE
     default: return hipErrorInvalidValue;
   }
 }

@@ -24,7 +24,7 @@ _lib = None
 
 def build() -> str:
     """Compile the renderer with g++ (host code only)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _LIB + ".tmp", _SRC]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -129,6 +130,21 @@ void render_canvas(Rng& rng, Canvas& cv, int w, int h, double density) {
     }
 }
 
+// Runs fn(y0, y1) over disjoint row bands on up to 16 threads; each pixel is
+// a pure function of its position, so the image does not depend on the split.
+template <class F>
+void for_rows(int H, F fn) {
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int n = std::min(nt, std::max(1, H / 32));
+  if (n == 1) {
+    fn(0, H);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int i = 0; i < n; ++i) pool.emplace_back(fn, H * i / n, H * (i + 1) / n);
+  for (auto& t : pool) t.join();
+}
+
 inline uint8_t quantise(double v) {
   double r = std::floor(v + 0.5);
   return (uint8_t)std::min(255.0, std::max(0.0, r));
@@ -241,14 +257,17 @@ int sg_render(const sg_params* p, uint8_t* frames, double* poses, double* planes
         uint8_t* img = frames + ((size_t)t * ncam + (size_t)k * per + side) * (size_t)W * H;
         if (p->warp_second && t == 1) continue;  // filled below
         const double a = planes[3 * k], b = planes[3 * k + 1], c = planes[3 * k + 2];
-        for (int y = 0; y < H; ++y)
-          for (int x = 0; x < W; ++x) {
-            const double xl = side ? x + a * x + b * y + c : (double)x;
-            const double dx = xl - cx, dy = y - cy;
-            const double X = Cx + s * (cr * dx - sr * dy) + ox;
-            const double Y = Cy + s * (sr * dx + cr * dy) + oy;
-            img[(size_t)y * W + x] = quantise(canv[k].sample(X, Y));
-          }
+        const Canvas& cv = canv[k];
+        for_rows(H, [&, img, side, a, b, c](int y0, int y1) {
+          for (int y = y0; y < y1; ++y)
+            for (int x = 0; x < W; ++x) {
+              const double xl = side ? x + a * x + b * y + c : (double)x;
+              const double dx = xl - cx, dy = y - cy;
+              const double X = Cx + s * (cr * dx - sr * dy) + ox;
+              const double Y = Cy + s * (sr * dx + cr * dy) + oy;
+              img[(size_t)y * W + x] = quantise(cv.sample(X, Y));
+            }
+        });
       }
     }
   }

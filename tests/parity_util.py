@@ -6,7 +6,9 @@ import numpy as np
 import oracle
 
 TOL_PX = 1e-3      # track positions, FP32 (the workloads' stated bound)
-TOL_THETA = 1e-4   # patch rotation, radians
+# patch rotation, radians: a rotation error d moves the pattern's outermost
+# point (radius sqrt(3.5^2 + 1.5^2) = 3.81 px) by 3.81 d, held to TOL_PX
+TOL_THETA = TOL_PX / 3.81
 MARGIN = 1e-3      # decisions closer than this to their threshold are reported, not failed
 
 

@@ -7,13 +7,15 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "vio_frontend.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("vio_frontend.h", "vio_mlp.h")]
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(vio_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for path in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names |= set(re.findall(r"\b(vio_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +70,8 @@ def test_create_rejects_bad_arguments_before_any_device_call(native):
     bad.struct_size = 12
     assert _create(native, [ok], bad) == native.VIO_EINVAL
     for field, value in (("levels", 0), ("levels", 7), ("gn_iters", 0), ("edge_margin", 3),
-                         ("n_thresholds", 0), ("fb_threshold", 0.0)):
+                         ("n_thresholds", 0), ("fb_threshold", 0.0), ("track_block_waves", 3),
+                         ("track_waves_per_cu", 65), ("flags", 4)):
         q = vf.default_params()
         setattr(q, field, value)
         assert _create(native, [ok], q) == native.VIO_EINVAL, field

@@ -1,0 +1,117 @@
+"""Batched stepping of many uneven streams (one submit, persistent tracking grid).
+
+Invariants: a batched step gives exactly the records of stepping each stream
+on its own, for the one-wave-per-item and the persistent tracking grids alike;
+and each stream of a batch matches its own CPU oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen
+from parity_util import compare_records
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+# small uneven mix: mono 320x240, stereo 752x480, stereo 400x300 with 5 levels' worth of size
+MIX = [
+    synthgen.Workload("b320", 3, 320, 240, n_frames=4, cell_size=16, max_keypoints=120),
+    synthgen.Workload("b752", 3, 752, 480, stereo=True, n_frames=4, cell_size=32, max_keypoints=300),
+    synthgen.Workload("b400", 3, 400, 304, stereo=True, n_frames=4, cell_size=24, max_keypoints=80),
+]
+
+
+def _seqs(n_frames):
+    return [synthgen.sequence(w, seq=20 + i, n_frames=n_frames) for i, w in enumerate(MIX)]
+
+
+def _streams():
+    return [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in MIX]
+
+
+@pytest.mark.parametrize("waves_per_cu,block_waves", [(0, 4), (0, 1), (4, 4), (2, 2)])
+def test_batched_step_equals_per_stream_push(waves_per_cu, block_waves):
+    import paper_2609_30459_amd as vf
+    seqs = _seqs(4)
+    params = vf.params_for(MIX[1], track_waves_per_cu=waves_per_cu, track_block_waves=block_waves)
+    with vf.Frontend(_streams(), params) as a, vf.Frontend(_streams(), vf.params_for(MIX[1])) as b:
+        for t in range(4):
+            for s, seq in enumerate(seqs):
+                a.stage_frame(s, t + 1, list(seq.frames[t]))
+            a.step()
+            for s, seq in enumerate(seqs):
+                b.push_stereo_frame(s, t + 1, list(seq.frames[t]))
+            for s in range(len(MIX)):
+                ra, rb = a.get_tracks(s), b.get_tracks(s)
+                assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), (t, s)
+
+
+def test_batched_streams_match_their_oracles():
+    import paper_2609_30459_amd as vf
+    seqs = _seqs(4)
+    orcs = [oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo,
+                            oracle.params_for(MIX[1], max_keypoints=w.max_keypoints, cell_size=w.cell_size))
+            for w in MIX]
+    with vf.Frontend(_streams(), vf.params_for(MIX[1], track_waves_per_cu=8)) as fe:
+        for t in range(4):
+            for s, seq in enumerate(seqs):
+                fe.stage_frame(s, t + 1, list(seq.frames[t]))
+                orcs[s].push(list(seq.frames[t]))
+            fe.step()
+            for s in range(len(MIX)):
+                exc = compare_records(fe.get_tracks(s), orcs[s].records(), MIX[1].fb_threshold,
+                                      where=f"batch stream {s} frame {t}")
+                assert len(exc) <= 1
+    for o in orcs:
+        o.close()
+
+
+def test_partial_staging_leaves_other_streams_alone():
+    import paper_2609_30459_amd as vf
+    seqs = _seqs(3)
+    with vf.Frontend(_streams(), vf.params_for(MIX[1], track_waves_per_cu=2)) as fe, \
+            vf.Frontend(_streams()[:1], vf.params_for(MIX[1])) as solo:
+        # stream 0 steps every time, stream 2 only in the first step
+        fe.stage_frame(0, 1, list(seqs[0].frames[0]))
+        fe.stage_frame(2, 1, list(seqs[2].frames[0]))
+        fe.step()
+        r2 = fe.get_tracks(2)
+        for t in range(1, 3):
+            fe.stage_frame(0, t + 1, list(seqs[0].frames[t]))
+            fe.step()
+        for t in range(3):
+            solo.push_stereo_frame(0, t + 1, list(seqs[0].frames[t]))
+        assert fe.get_tracks(0).tobytes() == solo.get_tracks(0).tobytes()
+        assert fe.get_tracks(2).tobytes() == r2.tobytes()
+        with pytest.raises(vf.VioError):
+            fe.step()  # nothing staged
+        with pytest.raises(vf.VioError):
+            fe.get_tracks(1)  # stream 1 never ran
+
+
+def test_multi_stream_staging_call_equals_single_stagings():
+    import torch
+
+    import paper_2609_30459_amd as vf
+    seqs = _seqs(3)
+    devs = [torch.from_numpy(q.frames).cuda() for q in seqs]
+    with vf.Frontend(_streams(), vf.params_for(MIX[1], eager=True)) as a, \
+            vf.Frontend(_streams(), vf.params_for(MIX[1])) as b:
+        for t in range(3):
+            imgs = [devs[s][t, c] for s, w in enumerate(MIX) for c in range(w.n_cams)]
+            a.stage_frames_device([0, 1, 2], [t + 1] * 3, imgs)
+            a.step()
+            for s, w in enumerate(MIX):
+                b.stage_frame_device(s, t + 1, [devs[s][t, c] for c in range(w.n_cams)])
+            b.step()
+            for s in range(3):
+                assert a.get_tracks(s).tobytes() == b.get_tracks(s).tobytes(), (t, s)
+            assert all(m > 0 for m in a.stats()["last_stage_ms"])

@@ -1,0 +1,130 @@
+"""GPU learned-initialisation part against the CPU oracle, through the C ABI.
+
+Network forward and gradient: the oracle emulates the GPU's bfloat16 rounding
+points; the remaining difference is the MFMA's summation order inside a
+32-wide step (a rare 1-ulp flip of a bf16 activation). Features: bit-exact.
+Learned pipeline: records parity with state injection.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen
+from parity_util import compare_records, inject
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 0.5, (n, 32)).astype(np.float32)
+    T = rng.normal(0, 2.0, (n, 2)).astype(np.float32)
+    return X, T
+
+
+@pytest.mark.parametrize("n", [1, 16, 37, 600, 1000])
+def test_forward_matches_oracle(n):
+    import torch
+    import paper_2609_30459_amd as vf
+    P = oracle.mlp_init(7)
+    P[-3:] = [0.05, -0.02, 0.1]
+    X, _ = _data(n, n)
+    want, _, _ = oracle.mlp_forward(P, X)
+    with vf.Mlp(1024) as net:
+        net.set_params(P)
+        y = torch.zeros((n, 3), dtype=torch.float32, device="cuda")
+        net.forward(torch.from_numpy(X).cuda(), y)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+    scale = np.abs(want).mean() + 1e-3
+    assert np.abs(got - want).max() <= 2e-2 * scale, (np.abs(got - want).max(), scale)
+    assert np.median(np.abs(got - want)) <= 1e-3 * scale
+
+
+@pytest.mark.parametrize("n", [32, 300, 1024])
+def test_gradient_matches_oracle(n):
+    import torch
+    import paper_2609_30459_amd as vf
+    P = oracle.mlp_init(9)
+    X, T = _data(n, 100 + n)
+    L_o, G_o, _ = oracle.mlp_loss_grad(P, X, T)
+    with vf.Mlp(1024) as net:
+        net.set_params(P)
+        g = torch.zeros(vf.MLP_NPARAM, dtype=torch.float32, device="cuda")
+        L_g = net.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), g)
+        G_g = g.cpu().numpy()
+    assert abs(L_g - L_o) <= 1e-3 * abs(L_o)
+    blocks = [(0, 4096), (4096, 4224), (4224, 20608), (20608, 20736), (20736, 21120), (21120, 21123)]
+    for a, b in blocks:
+        rel = np.linalg.norm(G_g[a:b] - G_o[a:b]) / max(np.linalg.norm(G_o[a:b]), 1e-12)
+        assert rel <= 1e-2, (a, b, rel)
+
+
+def test_adam_step_matches_oracle_and_training_reduces_loss():
+    import torch
+    import paper_2609_30459_amd as vf
+    P = oracle.mlp_init(11)
+    X, T = _data(1024, 5)
+    # one step: oracle gradient + oracle Adam against the GPU step
+    _, G_o, _ = oracle.mlp_loss_grad(P, X, T)
+    P_o, m, v = P.copy(), np.zeros_like(P), np.zeros_like(P)
+    oracle.adam(P_o, G_o.astype(np.float32), m, v, 1, lr=1e-3)
+    with vf.Mlp(1024) as net:
+        net.set_params(P)
+        dx, dt = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+        l0 = net.train_step(dx, dt, lr=1e-3)
+        P_g = net.get_params()
+        # Adam's first step moves each weight by about lr * sign(g): compare the moves
+        moved = np.abs(P_o - P) > 5e-4
+        assert (np.sign(P_g - P)[moved] == np.sign(P_o - P)[moved]).mean() > 0.99
+        assert np.abs((P_g - P) - (P_o - P)).max() <= 2e-3
+        losses = [net.train_step(dx, dt, lr=1e-3) for _ in range(200)]
+    assert losses[-1] < 0.5 * l0
+
+
+def _learned_params(w, rho, levels=2, iters=3):
+    return dict(init_mode=1, learned_levels=levels, learned_iters=iters, learned_rho=rho)
+
+
+@pytest.mark.parametrize("rho", [-1.0, 0.02, 1e9])
+def test_learned_pipeline_parity_and_features(rho):
+    import paper_2609_30459_amd as vf
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=7, n_frames=4)
+    P = oracle.mlp_init(13) * 0.05
+    P[-3:] = 0.0
+    po = _learned_params(w, rho)
+    fe_o = oracle.Frontend([w.width] * 2, [w.height] * 2, True, oracle.params_for(w, **po))
+    fe_o.set_mlp(P)
+    n_fb = 0
+    with vf.Frontend([(2, w.width, w.height, w.max_keypoints, w.cell_size)], vf.params_for(w, **po)) as fe_g:
+        fe_g.set_mlp(P)
+        for t in range(4):
+            if t > 0:
+                inject(fe_g, fe_o, 0, 2)
+                state = [fe_o.keypoints(c) for c in range(2)]
+            fe_o.push(list(seq.frames[t]))
+            fe_g.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            g, o = fe_g.get_tracks(0), fe_o.records()
+            exc = compare_records(g, o, w.fb_threshold, where=f"learned rho={rho} frame {t}")
+            assert len(exc) <= 1
+            if t > 0:
+                for c in range(2):
+                    ids, xy, pxy, age = state[c]
+                    want = oracle.features(ids, xy, pxy, age, seq.frames[t - 1, c])
+                    got = fe_g.get_features(0, c)
+                    assert got.shape == want.shape
+                    assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), c
+                st = fe_g.stats()
+                assert st["last_fallback"] == fe_o.last_fallback or abs(st["last_fallback"] - fe_o.last_fallback) <= 2
+                n_fb += st["last_fallback"]
+    fe_o.close()
+    if rho < 0:
+        assert n_fb > 0

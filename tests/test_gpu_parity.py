@@ -195,7 +195,8 @@ def test_abi_errors_on_device():
 
 
 def test_graph_replay_equals_eager_launches():
-    """The captured per-frame graph and one-by-one launches give identical records."""
+    """The captured per-frame graph and one-by-one launches give identical
+    records; eager launches report each kernel's duration."""
     vf = _vf()
     w = synthgen.WORKLOADS["stereo752"]
     seq = synthgen.sequence(w, seq=6, n_frames=5)
@@ -206,3 +207,9 @@ def test_graph_replay_equals_eager_launches():
             b.push_stereo_frame(0, t + 1, list(seq.frames[t]))
             ra, rb = a.get_tracks(0), b.get_tracks(0)
             assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), t
+            sa, sb = a.stats(), b.stats()
+            assert sa["last_stage_ms"] == [-1.0] * 3 and sa["last_gpu_ms"] > 0
+            assert all(m > 0 for m in sb["last_stage_ms"]), sb
+            assert sb["last_learned_ms"] == [-1.0] * 2
+            # kernel durations lie inside the frame's interval
+            assert sum(sb["last_stage_ms"]) <= sb["last_gpu_ms"] * 1.001 + 1e-3
