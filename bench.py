@@ -103,6 +103,7 @@ def main():
                     help="tracker grid: 0 = one wave per keypoint, N = persistent N waves per CU "
                          "(default: the autotuned choice, else 0)")
     ap.add_argument("--block-waves", type=int, default=None, help="tracker waves per workgroup (1, 2, 4)")
+    ap.add_argument("--tile", type=int, default=None, help="pyramid/detector tile edge (32, 64)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -148,16 +149,17 @@ def main():
     torch.cuda.synchronize()
     streams = [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in ws]
 
-    wpc, bw = args.waves_per_cu, args.block_waves
+    wpc, bw, tile = args.waves_per_cu, args.block_waves, args.tile
     tuned = None
-    if wpc is None and bw is None:
+    if wpc is None and bw is None and tile is None:
         from paper_2609_30459_amd import autotune
         tuned = autotune.lookup(args.workload, args.init)
         if tuned:
-            wpc, bw = tuned["track_waves_per_cu"], tuned["track_block_waves"]
+            wpc, bw, tile = tuned["track_waves_per_cu"], tuned["track_block_waves"], tuned.get("pyr_tile", 64)
     wpc = wpc or 0
     bw = bw or 4
-    extra = dict(track_waves_per_cu=wpc, track_block_waves=bw)
+    tile = tile or 64
+    extra = dict(track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile)
     rho = None
     if args.init == "learned":
         from paper_2609_30459_amd.train_mlp import load_weights
@@ -319,7 +321,7 @@ def main():
                    "cameras": sum(w.n_cams for w in ws),
                    "sizes": sorted({f"{w.width}x{w.height}x{w.n_cams}" for w in ws}),
                    "levels": L, "gn_iters": N, "max_keypoints": sorted({w.max_keypoints for w in ws}),
-                   "init": args.init, "launch": args.launch, "track_waves_per_cu": wpc, "track_block_waves": bw,
+                   "init": args.init, "launch": args.launch, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
                    "autotuned": tuned is not None, "parallelism": "single_gpu",
                    **({"learned_levels": args.learned_levels, "learned_iters": args.learned_iters, "rho": rho}
                       if args.init == "learned" else {})},

@@ -97,6 +97,8 @@ typedef struct vio_frontend_params {
   int32_t track_waves_per_cu; /* 0: one wave per tracking work item; > 0: a persistent tracking grid
                                  of this many waves per compute unit over a shared work queue */
   int32_t track_block_waves;  /* waves per tracking workgroup: 1, 2 or 4 (0 = 4) */
+  int32_t pyr_tile;           /* level-0 tile edge of the pyramid/detector kernel: 32 (256-thread workgroups)
+                                 or 64 (1024 threads); 0 = 64 */
 } vio_frontend_params;
 
 /* vio_frontend_params.flags */

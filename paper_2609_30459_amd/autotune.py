@@ -1,15 +1,19 @@
-"""Picks the tracker's launch shape per workload and device by measurement.
+"""Picks the kernels' launch shapes per workload and device by measurement.
 
-The tracker runs one wave64 per work item (a temporal track or a stereo
-match). Its launch shape is free: one wave per item in workgroups of 1, 2 or
-4 waves, or a persistent grid of 1..16 waves per compute unit popping items
-from a shared queue. Every shape gives the same records bit for bit; only the
-device time differs, and which is fastest depends on the item count, the
-levels and iterations, and the chip. Each candidate runs the same frames of
-the workload (device-resident, kernels launched one by one with HIP events
-attached to their dispatches) and is scored by the tracker kernel's mean
-duration; the winner goes into a JSON cache keyed by the device's
-architecture and compute-unit count, which the benchmark reads.
+Two choices are free and leave the records bit for bit the same:
+  * the pyramid/detector tile: 64x64 level-0 pixels per 1024-thread workgroup
+    or 32x32 per 256-thread workgroup (more, smaller workgroups, at the cost
+    of a larger share of recomputed apron);
+  * the tracker's launch shape: one wave64 per work item in workgroups of 1, 2
+    or 4 waves, or a persistent grid of 1..16 waves per compute unit popping
+    items from a shared queue.
+Which is fastest depends on the image sizes, the item count, the levels and
+iterations, and the chip. Each candidate runs the same frames of the workload
+(device-resident, kernels launched one by one with HIP events attached to
+their dispatches); the tile is scored by the pyramid/detector kernel's mean
+duration and the tracker shape by the tracker kernel's. The winners go into a
+JSON cache keyed by the device's architecture and compute-unit count, which
+the benchmark reads.
 
     python -m paper_2609_30459_amd.autotune --workload batch16 --init const_vel
 """
@@ -26,8 +30,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned", "launch.json")
 
-# (waves_per_cu, block_waves); waves_per_cu 0 = one wave per item
-CANDIDATES = [(0, 1), (0, 2), (0, 4), (1, 4), (2, 4), (4, 4), (8, 4), (16, 4), (2, 1), (4, 2), (8, 2)]
+# (waves_per_cu, block_waves, pyramid tile); waves_per_cu 0 = one wave per item
+CANDIDATES = [(0, 1, 64), (0, 2, 64), (0, 4, 64), (1, 4, 64), (2, 4, 64), (4, 4, 64), (8, 4, 64), (16, 4, 64),
+              (2, 1, 64), (4, 2, 64), (8, 2, 64), (0, 1, 32), (0, 4, 32)]
 
 
 def device_key() -> str:
@@ -57,7 +62,7 @@ def _workloads(name):
 
 def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None, learned_levels=2,
             learned_iters=3, log=print):
-    """Mean tracker-kernel and all-kernel durations (ms) of each launch shape."""
+    """Mean pyramid, tracker and all-kernel durations (ms) of each launch shape."""
     import torch
 
     import paper_2609_30459_amd as vf
@@ -75,9 +80,9 @@ def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None,
         extra = dict(init_mode=1, learned_levels=learned_levels, learned_iters=learned_iters, learned_rho=rho)
     ids = list(range(len(ws)))
     out = []
-    for wpc, bw in shapes:
-        p = vf.params_for(ws[0], eager=True, track_waves_per_cu=wpc, track_block_waves=bw, **extra)
-        track, total = [], []
+    for wpc, bw, tile in shapes:
+        p = vf.params_for(ws[0], eager=True, track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile, **extra)
+        pyr, track, total = [], [], []
         with vf.Frontend(streams, p) as fe:
             if init == "learned":
                 fe.set_mlp(params, rho)
@@ -87,12 +92,13 @@ def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None,
                 fe.step()
                 if t >= warmup:
                     st = fe.stats()
+                    pyr.append(st["last_stage_ms"][0])
                     track.append(st["last_stage_ms"][1])
                     total.append(sum(st["last_stage_ms"]) + sum(max(0.0, m) for m in st["last_learned_ms"]))
-        r = {"track_waves_per_cu": wpc, "track_block_waves": bw, "track_ms": float(np.mean(track)),
-             "kernels_ms": float(np.mean(total))}
-        log(f"  waves/CU {wpc:2d}  waves/block {bw}: tracker {r['track_ms'] * 1e3:7.1f} us, "
-            f"all kernels {r['kernels_ms'] * 1e3:7.1f} us")
+        r = {"track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile, "pyr_ms": float(np.mean(pyr)),
+             "track_ms": float(np.mean(track)), "kernels_ms": float(np.mean(total))}
+        log(f"  waves/CU {wpc:2d}  waves/block {bw}  tile {tile}: pyramid {r['pyr_ms'] * 1e3:7.1f} us, "
+            f"tracker {r['track_ms'] * 1e3:7.1f} us, all kernels {r['kernels_ms'] * 1e3:7.1f} us")
         out.append(r)
     return out
 
@@ -102,16 +108,21 @@ def tune(workload: str, init: str, frames=40, path=CACHE, log=print, **kw):
     t0 = time.time()
     res = measure(workload, init, CANDIDATES, frames=frames, log=log, **kw)
     best = min(res, key=lambda r: r["track_ms"])
+    by_tile = {}
+    for r in res:
+        by_tile.setdefault(r["pyr_tile"], []).append(r["pyr_ms"])
+    tile = min(by_tile, key=lambda t: float(np.mean(by_tile[t])))
     entry = {"track_waves_per_cu": best["track_waves_per_cu"], "track_block_waves": best["track_block_waves"],
-             "track_ms": best["track_ms"], "frames": frames, "candidates": res}
+             "track_ms": best["track_ms"], "pyr_tile": tile, "pyr_ms": float(np.mean(by_tile[tile])),
+             "frames": frames, "candidates": res}
     cache = _load_cache(path)
     cache.setdefault(device_key(), {})[f"{workload}:{init}"] = entry
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path + ".tmp", "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(path + ".tmp", path)
-    log(f"{workload}:{init} -> waves/CU {entry['track_waves_per_cu']}, waves/block {entry['track_block_waves']} "
-        f"({time.time() - t0:.1f} s)")
+    log(f"{workload}:{init} -> waves/CU {entry['track_waves_per_cu']}, waves/block {entry['track_block_waves']}, "
+        f"tile {entry['pyr_tile']} ({time.time() - t0:.1f} s)")
     return entry
 
 

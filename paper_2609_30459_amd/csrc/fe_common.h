@@ -13,8 +13,7 @@ namespace vio {
 constexpr int kMaxLevels = VIO_MAX_LEVELS;
 constexpr int kMaxCams = VIO_MAX_CAMERAS;
 constexpr int kPatch = 52;      // pattern points (Sec. III-E)
-constexpr int kTile = 64;       // level-0 output tile edge of the pyramid/detector kernel
-constexpr int kPyrThreads = 1024;
+constexpr int kTileDefault = 64;  // level-0 tile edge of the pyramid/detector kernel unless chosen
 // Kernel timing: while set, the frontend's kernel launches on this thread
 // attach these events to the dispatch itself (the kernel's own start and end
 // timestamps, without the gaps between launches); null for plain launches and
@@ -137,9 +136,12 @@ struct Prediction {
 };
 
 // ---- launchers (defined in the kernel translation units) ----
+// Pyramid + detector over tiles [tile_base, tile_base + n_tiles) of cameras
+// [cam_begin, cam_end); tile: the level-0 tile edge the cameras' tile grids use (32 or 64).
 hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end,
-                                   int tile_base, int n_tiles, int levels, int tmin, int margin, hipStream_t s);
-size_t pyr_detect_lds_bytes(int levels);
+                                   int tile_base, int n_tiles, int levels, int tile, int tmin, int margin,
+                                   hipStream_t s);
+size_t pyr_detect_lds_bytes(int levels, int tile);
 // Tracking work items [item_base, item_base + n_items) over the segments
 // d_segs[0..n_segs) (segment begins are global item indices). waves_per_cu = 0
 // launches one wave per item; > 0 launches a persistent grid of that many

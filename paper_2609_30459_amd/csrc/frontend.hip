@@ -60,6 +60,7 @@ thread_local KernelTiming vio::tl_timing;
 // A set of cameras/streams launched together: one stream (push) or all (step).
 struct LaunchSet {
   int cam_begin, cam_end, tile_begin, n_tiles, seg_begin, n_segs, item_begin, n_items, stream_begin, n_streams;
+  bool all;  // every stream: the batched item order (segs_all)
 };
 
 enum { kKernPyr, kKernFeatures, kKernMlp, kKernTrack, kKernSelect, kKernels };
@@ -67,10 +68,12 @@ enum { kKernPyr, kKernFeatures, kKernMlp, kKernTrack, kKernSelect, kKernels };
 struct vio_frontend {
   vio_frontend_params P{};
   int n_cus = 256;
+  int tile = kTileDefault;  // pyramid/detector tile edge
   Graphs graph_all;  // captured batched step
   std::vector<StreamInfo> streams;
   std::vector<CamDesc> cams;
-  std::vector<TrackSeg> segs;
+  std::vector<TrackSeg> segs;      // per stream: the stream's items are contiguous
+  std::vector<TrackSeg> segs_all;  // the same items in the batched step's order
   std::vector<int> stream_cams;
   int total_tiles = 0;
   size_t rec_total = 0;
@@ -80,6 +83,7 @@ struct vio_frontend {
   FrameTable* d_frame = nullptr;
   Counters* d_cnt = nullptr;
   TrackSeg* d_segs = nullptr;
+  TrackSeg* d_segs_all = nullptr;
   int* d_stream_cams = nullptr;
   Prediction* d_pred = nullptr;
   int pred_cap = 0;
@@ -145,6 +149,7 @@ int check_params(const vio_frontend_params* p, std::string& why) {
       p->track_block_waves != kTrackWaves)
     return why = "track_block_waves must be 0, 1, 2 or 4", VIO_EINVAL;
   if (p->flags & ~VIO_FLAG_EAGER) return why = "unknown flag bits", VIO_EINVAL;
+  if (p->pyr_tile != 0 && p->pyr_tile != 32 && p->pyr_tile != 64) return why = "pyr_tile must be 0, 32 or 64", VIO_EINVAL;
   if (!(p->fb_threshold > 0.f)) return why = "fb_threshold must be positive", VIO_EINVAL;
   if (p->k_per_cell != 1) return why = "only k_per_cell = 1 is implemented", VIO_EUNSUPPORTED;
   if (p->init_mode != VIO_INIT_CONST_VEL && p->init_mode != VIO_INIT_LEARNED) return why = "init_mode", VIO_EINVAL;
@@ -247,8 +252,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       c.partner = si.n_cams == 1 ? -1 : (k % 2 == 0 ? cam + 1 : cam - 1);
       c.stream = s;
       c.local = k;
-      c.tiles_x = (si.w + kTile - 1) / kTile;
-      c.tiles_y = (si.h + kTile - 1) / kTile;
+      c.tiles_x = (si.w + h->tile - 1) / h->tile;
+      c.tiles_y = (si.h + h->tile - 1) / h->tile;
       c.tile_begin = tiles;
       tiles += c.tiles_x * c.tiles_y;
       for (int l = 0; l < P.levels; ++l) {
@@ -267,16 +272,19 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       co[cam].rec = rec_total;
       rec_total += c.rec_cap;
       stage += (size_t)si.w * si.h;
-      // tracking work items: temporal for every camera, stereo for left cameras of pairs
-      h->segs.push_back({cam, kModeTemporal, items, si.cap});
-      items += si.cap;
     }
+    // tracking work items: stereo matches of the left cameras' cell winners
+    // first (they run the full budget), then the temporal tracks of every camera
     for (int k = 0; k < si.n_cams; ++k) {
       const int cc = si.first_cam + k;
       if (si.n_cams >= 2 && k % 2 == 0) {
         h->segs.push_back({cc, kModeStereo, items, h->cams[cc].ncells});
         items += h->cams[cc].ncells;
       }
+    }
+    for (int k = 0; k < si.n_cams; ++k) {
+      h->segs.push_back({si.first_cam + k, kModeTemporal, items, si.cap});
+      items += si.cap;
     }
     si.n_segs = (int)h->segs.size() - si.seg_begin;
     si.n_items = items - si.item_begin;
@@ -286,6 +294,16 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     h->stream_cams.push_back(si.first_cam);
     h->stream_cams.push_back(si.n_cams);
   }
+  // the batched step's order: every stream's stereo items, then every temporal item
+  {
+    int at = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (const TrackSeg& g : h->segs)
+        if ((g.mode == kModeStereo) == (pass == 0)) {
+          h->segs_all.push_back({g.cam, g.mode, at, g.count});
+          at += g.count;
+        }
+  }
   h->total_tiles = tiles;
   h->rec_total = rec_total;
   h->pred_cap = 0;
@@ -294,6 +312,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   const size_t o_frame = take(sizeof(FrameTable));
   const size_t o_cnt = take(sizeof(Counters));
   const size_t o_segs = take(sizeof(TrackSeg) * h->segs.size());
+  const size_t o_segs_all = take(sizeof(TrackSeg) * h->segs_all.size());
   const size_t o_sc = take(sizeof(int) * h->stream_cams.size());
   const size_t o_pred = take(sizeof(Prediction) * std::max(1, h->pred_cap));
   size_t o_feat = 0, o_guess = 0, o_P = 0, o_W1 = 0, o_W2 = 0, o_W2t = 0, o_W3 = 0;
@@ -320,10 +339,10 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   HIP_CHECK(h, hipDeviceGetAttribute(&h->n_cus, hipDeviceAttributeMultiprocessorCount, h->device));
   int lds_max = 0;
   HIP_CHECK(h, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
-  const size_t lds_need = pyr_detect_lds_bytes(P.levels);
+  const size_t lds_need = pyr_detect_lds_bytes(P.levels, h->tile);
   if (lds_need == 0 || lds_need > (size_t)lds_max)
-    return fail(h, VIO_EUNSUPPORTED, "%d levels need %zu bytes of LDS per workgroup, the device offers %d", P.levels,
-                lds_need, lds_max);
+    return fail(h, VIO_EUNSUPPORTED, "%d levels with %d-pixel tiles need %zu bytes of LDS per workgroup, the device "
+                "offers %d", P.levels, h->tile, lds_need, lds_max);
   if (hipMalloc(&h->arena, arena_bytes) != hipSuccess) {
     h->arena = nullptr;
     return fail(h, VIO_ENOMEM, "device arena of %zu bytes", arena_bytes);
@@ -345,6 +364,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->d_frame = reinterpret_cast<FrameTable*>(base + o_frame);
   h->d_cnt = reinterpret_cast<Counters*>(base + o_cnt);
   h->d_segs = reinterpret_cast<TrackSeg*>(base + o_segs);
+  h->d_segs_all = reinterpret_cast<TrackSeg*>(base + o_segs_all);
   h->d_stream_cams = reinterpret_cast<int*>(base + o_sc);
   h->d_pred = reinterpret_cast<Prediction*>(base + o_pred);
   if (h->learned) {
@@ -357,6 +377,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     h->mlp.W3b = reinterpret_cast<uint16_t*>(base + o_W3);
   }
   HIP_CHECK(h, hipMemcpy(h->d_segs, h->segs.data(), sizeof(TrackSeg) * h->segs.size(), hipMemcpyHostToDevice));
+  HIP_CHECK(h, hipMemcpy(h->d_segs_all, h->segs_all.data(), sizeof(TrackSeg) * h->segs_all.size(),
+                         hipMemcpyHostToDevice));
   HIP_CHECK(h, hipMemcpy(h->d_stream_cams, h->stream_cams.data(), sizeof(int) * h->stream_cams.size(),
                          hipMemcpyHostToDevice));
   // pinned host buffers; records and their counts are written by the
@@ -417,6 +439,7 @@ int vio_frontend_create(const vio_stream_desc* streams, int32_t n_streams, const
   h->P = *params;
   h->eager = (params->flags & VIO_FLAG_EAGER) != 0;
   h->learned = params->init_mode == VIO_INIT_LEARNED;
+  h->tile = params->pyr_tile ? params->pyr_tile : kTileDefault;
   const int rc = create_impl(h, streams, n_streams);
   if (rc != VIO_OK) {
     vio_frontend_destroy(h);
@@ -448,13 +471,13 @@ static Tuning tuning(const vio_frontend* h) {
 static LaunchSet stream_set(const vio_frontend* h, int s) {
   const StreamInfo& si = h->streams[s];
   return {si.first_cam, si.first_cam + si.n_cams, si.tile_begin, si.n_tiles, si.seg_begin, si.n_segs,
-          si.item_begin, si.n_items, s, 1};
+          si.item_begin, si.n_items, s, 1, false};
 }
 
 static LaunchSet all_set(const vio_frontend* h) {
   const StreamInfo& last = h->streams.back();
-  return {0, (int)h->cams.size(), 0, h->total_tiles, 0, (int)h->segs.size(), 0, last.item_begin + last.n_items, 0,
-          (int)h->streams.size()};
+  return {0, (int)h->cams.size(), 0, h->total_tiles, 0, (int)h->segs_all.size(), 0, last.item_begin + last.n_items, 0,
+          (int)h->streams.size(), true};
 }
 
 // Enqueues one step of a frame of the launch set on `st`: 0 = frame table
@@ -473,7 +496,7 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
   if (stage == 1) {
     timing(kKernPyr);
     return launch_pyr_detect_range(h->d_cams, h->d_frame, ls.cam_begin, ls.cam_end, ls.tile_begin, ls.n_tiles,
-                                   tune.levels, tune.tmin, tune.margin, st);
+                                   tune.levels, h->tile, tune.tmin, tune.margin, st);
   }
   if (stage == 2) {
     if (h->learned) {
@@ -491,7 +514,8 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
         return e;
     }
     timing(kKernTrack);
-    return launch_track(h->d_cams, h->d_frame, h->d_cnt, h->d_segs + ls.seg_begin, ls.n_segs, ls.item_begin,
+    return launch_track(h->d_cams, h->d_frame, h->d_cnt, (ls.all ? h->d_segs_all : h->d_segs) + ls.seg_begin,
+                        ls.n_segs, ls.item_begin,
                         ls.n_items, h->d_pred, tune,
                         TrackShape{h->P.track_waves_per_cu,
                                    h->P.track_block_waves ? h->P.track_block_waves : kTrackWaves, h->n_cus},

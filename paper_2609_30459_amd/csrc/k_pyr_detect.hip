@@ -1,6 +1,8 @@
 // Fused pyramid + corner detector for gfx950.
 //
-// One 1024-thread workgroup owns a 64x64 level-0 tile of one camera. It stages
+// One workgroup owns a TxT level-0 tile of one camera (T = 64 with 1024
+// threads, or T = 32 with 256 threads: more, smaller workgroups for small
+// images, chosen per workload at create). It stages
 // the tile plus an apron in LDS with coalesced dword loads, then
 //  * computes the FAST-9 score (Sec. III-D) of the tile and a one-pixel ring
 //    (the paper's early rejection on ring pairs (0,8)/(4,12), then an exact
@@ -27,23 +29,23 @@
 namespace vio {
 namespace {
 
-template <int L>
+template <int L, int T>
 struct PyrGeom {
+  static constexpr int threads = T == 64 ? 1024 : 256;
+  static constexpr int score_edge = T + 2;
   // apron of level l so that the tile of level L-1 can be computed: A[L-1] = 0,
   // A[l] = 2 A[l+1] + 2, i.e. A[l] = 2^(L-l) - 2
   static constexpr __host__ __device__ int apron(int l) { return (1 << (L - l)) - 2; }
-  static constexpr __host__ __device__ int tile(int l) { return kTile >> l; }
+  static constexpr __host__ __device__ int tile(int l) { return T >> l; }
   static constexpr __host__ __device__ int region(int l) { return tile(l) + 2 * apron(l); }
   // level-0 staging: apron at least 4 (FAST radius 3 plus the NMS ring)
   static constexpr int a0 = apron(0) > 4 ? apron(0) : 4;
   static constexpr int a0x = (a0 + 3) & ~3;  // left apron rounded to a dword
-  static constexpr int sw0 = ((kTile + a0x + a0) + 3) & ~3;
-  static constexpr int sh0 = kTile + 2 * a0;
+  static constexpr int sw0 = ((T + a0x + a0) + 3) & ~3;
+  static constexpr int sh0 = T + 2 * a0;
   static constexpr int vbytes = L > 1 ? (region(0) - 1) * region(1) : 1;
   static constexpr int lvl_bytes = L > 1 ? region(1) * region(1) : 1;
 };
-
-constexpr int kScoreEdge = kTile + 2;
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -119,11 +121,16 @@ __device__ __forceinline__ int fast_score(const int d[16]) {
   return max(best - 1, -1);
 }
 
-template <int L>
-__global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __restrict__ cams,
-                                                           const FrameTable* __restrict__ frame, int cam_begin,
-                                                           int cam_end, int tile_base, int tmin, int margin) {
-  using G = PyrGeom<L>;
+template <int L, int T>
+__global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDesc* __restrict__ cams,
+                                                                      const FrameTable* __restrict__ frame,
+                                                                      int cam_begin, int cam_end, int tile_base,
+                                                                      int tmin, int margin) {
+  using G = PyrGeom<L, T>;
+  static_assert(G::threads == (T == 64 ? 1024 : 256), "launch bounds");
+  constexpr int kTile = T;
+  constexpr int kPyrThreads = G::threads;
+  constexpr int kScoreEdge = G::score_edge;
   __shared__ __align__(16) uint8_t s_l0[G::sh0 * G::sw0];
   __shared__ uint8_t s_score[kScoreEdge * kScoreEdge];
   __shared__ uint16_t s_queue[kScoreEdge * kScoreEdge];
@@ -247,14 +254,16 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __res
       const int X0 = max(0, o_x), X1 = min(Wn - 1, o_x + S - 1);
       const int Y0 = max(0, o_y), Y1 = min(Hn - 1, o_y + S - 1);
       const int vy0 = max(0, 2 * o_y - 2), vy1 = min(Hc - 1, 2 * (o_y + S - 1) + 2);
-      const int ncol = X1 - X0 + 1;
+      // passes run over the full region width S (a compile-time constant, so
+      // the index split is a multiply-shift) and skip columns outside the image
       // block-uniform: a level with nothing inside the image ends the tile
       if (X0 > X1 || Y0 > Y1) break;
       {
         // eq. (2): horizontal pass over level-l rows vy0..vy1
-        const int nv = (vy1 - vy0 + 1) * ncol;
+        const int nv = (vy1 - vy0 + 1) * S;
         for (int i = tid; i < nv; i += kPyrThreads) {
-          const int r = i / ncol, X = X0 + i % ncol;
+          const int r = i / S, X = o_x + i % S;
+          if (X < X0 || X > X1) continue;
           const uint8_t* row = cur + (vy0 + r - cur_oy) * cur_p - cur_ox;
           const int xa = 2 * X;
           const uint32_t v = row[clampi(xa - 2, 0, Wc - 1)] + 4u * row[clampi(xa - 1, 0, Wc - 1)] +
@@ -267,9 +276,10 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __res
         uint8_t* gdst = cd.lvl[par][l + 1];
         const int gp = cd.pitch[l + 1];
         const int tx0 = x0 >> (l + 1), ty0 = y0 >> (l + 1), te = kTile >> (l + 1);
-        const int nn = (Y1 - Y0 + 1) * ncol;
+        const int nn = (Y1 - Y0 + 1) * S;
         for (int i = tid; i < nn; i += kPyrThreads) {
-          const int Y = Y0 + i / ncol, X = X0 + i % ncol;
+          const int Y = Y0 + i / S, X = o_x + i % S;
+          if (X < X0 || X > X1) continue;
           const uint16_t* col = s_v + (X - o_x);
           const int ya = 2 * Y;
           const uint32_t s = col[(clampi(ya - 2, 0, Hc - 1) - vy0) * S] + 4u * col[(clampi(ya - 1, 0, Hc - 1) - vy0) * S] +
@@ -289,44 +299,59 @@ __global__ __launch_bounds__(kPyrThreads) void k_pyr_detect(const CamDesc* __res
   }
 }
 
-template <int L>
-hipError_t launch_L(const CamDesc* cams, const FrameTable* frame, int cam_begin, int cam_end, int tile_base,
-                    int n_tiles, int tmin, int margin, hipStream_t s) {
-  launch_kernel(k_pyr_detect<L>, dim3(n_tiles), dim3(kPyrThreads), 0, s, cams, frame, cam_begin, cam_end,
-                     tile_base, tmin, margin);
+template <int L, int T>
+hipError_t launch_LT(const CamDesc* cams, const FrameTable* frame, int cam_begin, int cam_end, int tile_base,
+                     int n_tiles, int tmin, int margin, hipStream_t s) {
+  launch_kernel(k_pyr_detect<L, T>, dim3(n_tiles), dim3(PyrGeom<L, T>::threads), 0, s, cams, frame, cam_begin,
+                cam_end, tile_base, tmin, margin);
   return hipGetLastError();
 }
 
-}  // namespace
-
-// Static LDS bytes of the pyramid/detector kernel for `levels` (0 if unknown).
-size_t pyr_detect_lds_bytes(int levels) {
+template <int T>
+size_t lds_bytes_T(int levels) {
   hipFuncAttributes a{};
   hipError_t e = hipErrorInvalidValue;
   switch (levels) {
-    case 1: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<1>)); break;
-    case 2: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<2>)); break;
-    case 3: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<3>)); break;
-    case 4: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<4>)); break;
-    case 5: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<5>)); break;
-    case 6: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<6>)); break;
+    case 1: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<1, T>)); break;
+    case 2: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<2, T>)); break;
+    case 3: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<3, T>)); break;
+    case 4: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<4, T>)); break;
+    case 5: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<5, T>)); break;
+    case 6: e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_pyr_detect<6, T>)); break;
     default: break;
   }
   return e == hipSuccess ? a.sharedSizeBytes : 0;
 }
 
-hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end,
-                                   int tile_base, int n_tiles, int levels, int tmin, int margin, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
+template <int T>
+hipError_t launch_T(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end, int tile_base,
+                    int n_tiles, int levels, int tmin, int margin, hipStream_t s) {
   switch (levels) {
-    case 1: return launch_L<1>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 2: return launch_L<2>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 3: return launch_L<3>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 4: return launch_L<4>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 5: return launch_L<5>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 6: return launch_L<6>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 1: return launch_LT<1, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 2: return launch_LT<2, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 3: return launch_LT<3, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 4: return launch_LT<4, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 5: return launch_LT<5, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 6: return launch_LT<6, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+}  // namespace
+
+// Static LDS bytes of the pyramid/detector kernel for `levels` and tile edge
+// `tile` (0 if unknown).
+size_t pyr_detect_lds_bytes(int levels, int tile) {
+  return tile == 32 ? lds_bytes_T<32>(levels) : tile == 64 ? lds_bytes_T<64>(levels) : 0;
+}
+
+hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end,
+                                   int tile_base, int n_tiles, int levels, int tile, int tmin, int margin,
+                                   hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (tile == 32) return launch_T<32>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, levels, tmin, margin, s);
+  if (tile == 64) return launch_T<64>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, levels, tmin, margin, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace vio

@@ -322,9 +322,14 @@ __device__ void process_item(const CamDesc* __restrict__ cams, const FrameTable*
                              const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs, int n_segs,
                              const Prediction* __restrict__ pred, const Tuning& tune, int item, int lane, float u,
                              float v, float wgt) {
-  int si = 0;
-  while (si + 1 < n_segs && segs[si + 1].begin <= item) ++si;
-  const TrackSeg sg = segs[si];
+  // the last segment that begins at or before the item (begins ascend)
+  int lo = 0, hi = n_segs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].begin <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const TrackSeg sg = segs[lo];
   const int j = item - sg.begin;
   if (j < 0 || j >= sg.count) return;
   const int c = sg.cam;

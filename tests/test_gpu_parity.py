@@ -45,12 +45,13 @@ def _image(w, h, density, seed=5):
     return synthgen.render(seed, w, h, 1, density=density).frames[0, 0]
 
 
+@pytest.mark.parametrize("tile", [64, 32])
 @pytest.mark.parametrize("name,w,h,levels,cell,density", PYR_CASES, ids=[c[0] for c in PYR_CASES])
-def test_pyramid_and_cell_winners_bit_exact(name, w, h, levels, cell, density):
+def test_pyramid_and_cell_winners_bit_exact(name, w, h, levels, cell, density, tile):
     vf = _vf()
     img = _image(w, h, density)
-    print(f"case {name} {w}x{h} L={levels}", flush=True)
-    with vf.Frontend([(1, w, h, 50, cell)], vf.make_params(levels=levels, cell_size=cell)) as fe:
+    print(f"case {name} {w}x{h} L={levels} tile {tile}", flush=True)
+    with vf.Frontend([(1, w, h, 50, cell)], vf.make_params(levels=levels, cell_size=cell, pyr_tile=tile)) as fe:
         fe.push_stereo_frame(0, 1, [img])
         want = oracle.pyramid(img, levels)
         for l in range(levels):
