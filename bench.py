@@ -104,6 +104,7 @@ def main():
                          "(default: the autotuned choice, else 0)")
     ap.add_argument("--block-waves", type=int, default=None, help="tracker waves per workgroup (1, 2, 4)")
     ap.add_argument("--tile", type=int, default=None, help="pyramid/detector tile edge (32, 64)")
+    ap.add_argument("--stereo-mode", type=int, default=None, help="0 speculative, 1 deferred stereo matching")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -149,17 +150,19 @@ def main():
     torch.cuda.synchronize()
     streams = [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in ws]
 
-    wpc, bw, tile = args.waves_per_cu, args.block_waves, args.tile
+    wpc, bw, tile, smode = args.waves_per_cu, args.block_waves, args.tile, args.stereo_mode
     tuned = None
-    if wpc is None and bw is None and tile is None:
+    if wpc is None and bw is None and tile is None and smode is None:
         from paper_2609_30459_amd import autotune
         tuned = autotune.lookup(args.workload, args.init)
         if tuned:
-            wpc, bw, tile = tuned["track_waves_per_cu"], tuned["track_block_waves"], tuned.get("pyr_tile", 64)
+            wpc, bw = tuned["track_waves_per_cu"], tuned["track_block_waves"]
+            tile, smode = tuned.get("pyr_tile", 64), tuned.get("stereo_mode", 0)
     wpc = wpc or 0
     bw = bw or 4
     tile = tile or 64
-    extra = dict(track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile)
+    smode = smode or 0
+    extra = dict(track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile, stereo_mode=smode)
     rho = None
     if args.init == "learned":
         from paper_2609_30459_amd.train_mlp import load_weights
@@ -322,6 +325,7 @@ def main():
                    "sizes": sorted({f"{w.width}x{w.height}x{w.n_cams}" for w in ws}),
                    "levels": L, "gn_iters": N, "max_keypoints": sorted({w.max_keypoints for w in ws}),
                    "init": args.init, "launch": args.launch, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
+                   "stereo_mode": ["speculative", "deferred"][smode],
                    "autotuned": tuned is not None, "parallelism": "single_gpu",
                    **({"learned_levels": args.learned_levels, "learned_iters": args.learned_iters, "rho": rho}
                       if args.init == "learned" else {})},

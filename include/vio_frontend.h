@@ -99,7 +99,15 @@ typedef struct vio_frontend_params {
   int32_t track_block_waves;  /* waves per tracking workgroup: 1, 2 or 4 (0 = 4) */
   int32_t pyr_tile;           /* level-0 tile edge of the pyramid/detector kernel: 32 (256-thread workgroups)
                                  or 64 (1024 threads); 0 = 64 */
+  int32_t stereo_mode;        /* VIO_STEREO_SPECULATIVE: the tracking launch also matches every cell
+                                 winner left to right, selection keeps the selected ones' matches (fewest
+                                 dependent launches); VIO_STEREO_DEFERRED: only the selected detections are
+                                 matched, in a second tracking launch after selection (least work). The
+                                 records are the same either way. */
 } vio_frontend_params;
+
+#define VIO_STEREO_SPECULATIVE 0
+#define VIO_STEREO_DEFERRED 1
 
 /* vio_frontend_params.flags */
 #define VIO_FLAG_EAGER 1u /* launch the per-frame kernels one by one, each with dispatch timestamps, instead

@@ -54,11 +54,13 @@ class vio_frontend_params(ctypes.Structure):
         ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float), ("init_mode", ctypes.c_int32),
         ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32), ("learned_rho", ctypes.c_float),
         ("flags", ctypes.c_uint32), ("track_waves_per_cu", ctypes.c_int32),
-        ("track_block_waves", ctypes.c_int32), ("pyr_tile", ctypes.c_int32),
+        ("track_block_waves", ctypes.c_int32), ("pyr_tile", ctypes.c_int32), ("stereo_mode", ctypes.c_int32),
     ]
 
 
 VIO_FLAG_EAGER = 1
+VIO_STEREO_SPECULATIVE = 0
+VIO_STEREO_DEFERRED = 1
 
 
 class vio_kp_prediction(ctypes.Structure):

@@ -1,19 +1,23 @@
 """Picks the kernels' launch shapes per workload and device by measurement.
 
-Two choices are free and leave the records bit for bit the same:
+Three choices are free and leave the records bit for bit the same:
+  * the tracker's launch shape: one wave64 per work item in workgroups of 1, 2
+    or 4 waves, or a persistent grid of 1..16 waves per compute unit popping
+    items from a shared queue;
   * the pyramid/detector tile: 64x64 level-0 pixels per 1024-thread workgroup
     or 32x32 per 256-thread workgroup (more, smaller workgroups, at the cost
     of a larger share of recomputed apron);
-  * the tracker's launch shape: one wave64 per work item in workgroups of 1, 2
-    or 4 waves, or a persistent grid of 1..16 waves per compute unit popping
-    items from a shared queue.
+  * the stereo mode: match every cell winner speculatively in the tracking
+    launch (fewest dependent launches) or only the selected detections after
+    selection (least work).
 Which is fastest depends on the image sizes, the item count, the levels and
 iterations, and the chip. Each candidate runs the same frames of the workload
 (device-resident, kernels launched one by one with HIP events attached to
-their dispatches); the tile is scored by the pyramid/detector kernel's mean
-duration and the tracker shape by the tracker kernel's. The winners go into a
-JSON cache keyed by the device's architecture and compute-unit count, which
-the benchmark reads.
+their dispatches). The tracker shape is chosen first by the tracker kernel's
+mean duration, then the tile by the pyramid/detector kernel's, then the
+stereo mode by the frame's device time. The winners go into a JSON cache
+keyed by the device's architecture and compute-unit count, which the
+benchmark reads.
 
     python -m paper_2609_30459_amd.autotune --workload batch16 --init const_vel
 """
@@ -30,9 +34,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned", "launch.json")
 
-# (waves_per_cu, block_waves, pyramid tile); waves_per_cu 0 = one wave per item
-CANDIDATES = [(0, 1, 64), (0, 2, 64), (0, 4, 64), (1, 4, 64), (2, 4, 64), (4, 4, 64), (8, 4, 64), (16, 4, 64),
-              (2, 1, 64), (4, 2, 64), (8, 2, 64), (0, 1, 32), (0, 4, 32)]
+# tracker shapes (waves_per_cu, block_waves); waves_per_cu 0 = one wave per item
+SHAPES = [(0, 1), (0, 2), (0, 4), (1, 4), (2, 4), (4, 4), (8, 4), (16, 4), (2, 1), (4, 2), (8, 2)]
 
 
 def device_key() -> str:
@@ -62,7 +65,8 @@ def _workloads(name):
 
 def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None, learned_levels=2,
             learned_iters=3, log=print):
-    """Mean pyramid, tracker and all-kernel durations (ms) of each launch shape."""
+    """Mean pyramid, tracker, all-kernel and frame device times (ms) of each
+    (waves_per_cu, block_waves, tile, stereo_mode) candidate."""
     import torch
 
     import paper_2609_30459_amd as vf
@@ -80,9 +84,10 @@ def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None,
         extra = dict(init_mode=1, learned_levels=learned_levels, learned_iters=learned_iters, learned_rho=rho)
     ids = list(range(len(ws)))
     out = []
-    for wpc, bw, tile in shapes:
-        p = vf.params_for(ws[0], eager=True, track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile, **extra)
-        pyr, track, total = [], [], []
+    for wpc, bw, tile, smode in shapes:
+        p = vf.params_for(ws[0], eager=True, track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile,
+                          stereo_mode=smode, **extra)
+        pyr, track, total, frame = [], [], [], []
         with vf.Frontend(streams, p) as fe:
             if init == "learned":
                 fe.set_mlp(params, rho)
@@ -95,10 +100,13 @@ def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None,
                     pyr.append(st["last_stage_ms"][0])
                     track.append(st["last_stage_ms"][1])
                     total.append(sum(st["last_stage_ms"]) + sum(max(0.0, m) for m in st["last_learned_ms"]))
-        r = {"track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile, "pyr_ms": float(np.mean(pyr)),
-             "track_ms": float(np.mean(track)), "kernels_ms": float(np.mean(total))}
-        log(f"  waves/CU {wpc:2d}  waves/block {bw}  tile {tile}: pyramid {r['pyr_ms'] * 1e3:7.1f} us, "
-            f"tracker {r['track_ms'] * 1e3:7.1f} us, all kernels {r['kernels_ms'] * 1e3:7.1f} us")
+                    frame.append(st["last_gpu_ms"])
+        r = {"track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile, "stereo_mode": smode,
+             "pyr_ms": float(np.mean(pyr)), "track_ms": float(np.mean(track)), "kernels_ms": float(np.mean(total)),
+             "frame_ms": float(np.mean(frame))}
+        log(f"  waves/CU {wpc:2d}  waves/block {bw}  tile {tile}  stereo {smode}: pyramid {r['pyr_ms'] * 1e3:7.1f} "
+            f"us, tracker {r['track_ms'] * 1e3:7.1f} us, kernels {r['kernels_ms'] * 1e3:7.1f} us, frame "
+            f"{r['frame_ms'] * 1e3:7.1f} us")
         out.append(r)
     return out
 
@@ -106,14 +114,17 @@ def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None,
 def tune(workload: str, init: str, frames=40, path=CACHE, log=print, **kw):
     """Measures every candidate, stores the fastest in the cache and returns it."""
     t0 = time.time()
-    res = measure(workload, init, CANDIDATES, frames=frames, log=log, **kw)
+    res = measure(workload, init, [(w, b, 64, 0) for w, b in SHAPES], frames=frames, log=log, **kw)
     best = min(res, key=lambda r: r["track_ms"])
-    by_tile = {}
-    for r in res:
-        by_tile.setdefault(r["pyr_tile"], []).append(r["pyr_ms"])
-    tile = min(by_tile, key=lambda t: float(np.mean(by_tile[t])))
-    entry = {"track_waves_per_cu": best["track_waves_per_cu"], "track_block_waves": best["track_block_waves"],
-             "track_ms": best["track_ms"], "pyr_tile": tile, "pyr_ms": float(np.mean(by_tile[tile])),
+    wpc, bw = best["track_waves_per_cu"], best["track_block_waves"]
+    res += measure(workload, init, [(wpc, bw, 32, 0)], frames=frames, log=log, **kw)
+    tile = min((r for r in res if (r["track_waves_per_cu"], r["track_block_waves"]) == (wpc, bw)),
+               key=lambda r: r["pyr_ms"])["pyr_tile"]
+    res += measure(workload, init, [(wpc, bw, tile, 1)], frames=frames, log=log, **kw)
+    final = [r for r in res if (r["track_waves_per_cu"], r["track_block_waves"], r["pyr_tile"]) == (wpc, bw, tile)]
+    pick = min(final, key=lambda r: r["frame_ms"])
+    entry = {"track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile, "stereo_mode": pick["stereo_mode"],
+             "track_ms": best["track_ms"], "pyr_ms": pick["pyr_ms"], "frame_ms": pick["frame_ms"],
              "frames": frames, "candidates": res}
     cache = _load_cache(path)
     cache.setdefault(device_key(), {})[f"{workload}:{init}"] = entry
@@ -121,8 +132,8 @@ def tune(workload: str, init: str, frames=40, path=CACHE, log=print, **kw):
     with open(path + ".tmp", "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(path + ".tmp", path)
-    log(f"{workload}:{init} -> waves/CU {entry['track_waves_per_cu']}, waves/block {entry['track_block_waves']}, "
-        f"tile {entry['pyr_tile']} ({time.time() - t0:.1f} s)")
+    log(f"{workload}:{init} -> waves/CU {wpc}, waves/block {bw}, tile {tile}, stereo mode {entry['stereo_mode']} "
+        f"({time.time() - t0:.1f} s)")
     return entry
 
 

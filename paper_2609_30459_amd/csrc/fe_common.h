@@ -91,8 +91,10 @@ struct FrameCam {
 };
 
 struct FrameTable {
-  int queue_head;  // work-queue counter of the persistent tracker, zero at the start of every frame
-  int pad[3];
+  // work-queue counters of the persistent tracker, one per tracking launch
+  // of the frame (all items, or temporal then stereo items), zero at the
+  // start of every frame
+  int queue_head[4];
   FrameCam cam[kMaxCams];
 };
 
@@ -101,6 +103,11 @@ struct Counters {
   int32_t n_live[2][kMaxCams];
   int32_t rec_count[kMaxCams];
   int64_t next_id[kMaxCams];  // per stream (indexed by stream)
+  // deferred stereo matching: a left camera's new detections of the frame
+  // are state[P][sel_base .. sel_base + n_sel) (written by the first
+  // selection phase, matched by the second tracking launch)
+  int32_t sel_base[kMaxCams];
+  int32_t n_sel[kMaxCams];
 };
 
 struct Tuning {
@@ -111,6 +118,7 @@ struct Tuning {
   int llevels, liters;    // tracker budget from the guess
   float rho;              // residual RMS above which a learned track falls back
   const float* guess;     // [rows][3] network outputs (learned mode)
+  int deferred;           // stereo items match the selected detections (by rank), not every cell winner
 };
 
 // Learned-initialisation network on the device (see vio_mlp.h).
@@ -145,12 +153,13 @@ size_t pyr_detect_lds_bytes(int levels, int tile);
 // Tracking work items [item_base, item_base + n_items) over the segments
 // d_segs[0..n_segs) (segment begins are global item indices). waves_per_cu = 0
 // launches one wave per item; > 0 launches a persistent grid of that many
-// waves per compute unit that pops items from FrameTable::queue_head.
+// waves per compute unit that pops items from FrameTable::queue_head[shape.queue].
 // Launch shape of the tracker: waves_per_cu = 0 gives one wave per work item,
 // > 0 a persistent grid of waves_per_cu * n_cus waves; block_waves waves
 // (1, 2 or kTrackWaves) per workgroup.
 struct TrackShape {
   int waves_per_cu, block_waves, n_cus;
+  int queue;  // the frame's work-queue counter the persistent grid pops (one per tracking launch)
 };
 hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
                         int n_segs, int item_base, int n_items, const Prediction* d_pred, Tuning tune,
@@ -160,8 +169,12 @@ hipError_t launch_features(const CamDesc* d_cams, const FrameTable* d_frame, con
                            const CamDesc* h_cams, int cam_begin, int cam_end, float* d_feat, hipStream_t s);
 hipError_t mlp_forward_launch(const MlpDev& M, const float* X, int K, float* Y, hipStream_t s);
 hipError_t mlp_pack_launch(const MlpDev& M, hipStream_t s);
+// Selection phases: kSelectAll (speculative stereo: everything in one
+// launch), kSelectLeft (deferred: survivors of every camera, selection and
+// records of the left cameras; the right cameras' matches follow),
+// kSelectRight (deferred: acceptance of the matches into the right cameras).
+enum { kSelectAll = 0, kSelectLeft = 1, kSelectRight = 2 };
 hipError_t launch_select(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt,
-                         const int* d_stream_cams, int n_streams_launch, int cams_per_stream_max, Tuning tune,
-                         hipStream_t s);
+                         const int* d_stream_cams, int n_streams_launch, int phase, Tuning tune, hipStream_t s);
 
 }  // namespace vio

@@ -47,6 +47,7 @@ struct StreamInfo {
   int64_t last_t = 0;
   int tile_begin = 0, n_tiles = 0;
   int seg_begin = 0, n_segs = 0, item_begin = 0, n_items = 0;
+  int st_segs = 0, st_items = 0;  // the stream's stereo segments/items come first
   bool staged = false;     // a frame is staged for the next vio_frontend_step
   int64_t staged_t = 0;
   size_t rec_off = 0, rec_n = 0;  // record range (in vio_track units) of the stream's cameras
@@ -60,10 +61,11 @@ thread_local KernelTiming vio::tl_timing;
 // A set of cameras/streams launched together: one stream (push) or all (step).
 struct LaunchSet {
   int cam_begin, cam_end, tile_begin, n_tiles, seg_begin, n_segs, item_begin, n_items, stream_begin, n_streams;
-  bool all;  // every stream: the batched item order (segs_all)
+  bool all;               // every stream: the batched item order (segs_all)
+  int st_segs, st_items;  // the leading stereo segments/items of the range
 };
 
-enum { kKernPyr, kKernFeatures, kKernMlp, kKernTrack, kKernSelect, kKernels };
+enum { kKernPyr, kKernFeatures, kKernMlp, kKernTrack, kKernSelect, kKernTrackStereo, kKernSelectRight, kKernels };
 
 struct vio_frontend {
   vio_frontend_params P{};
@@ -102,10 +104,16 @@ struct vio_frontend {
   size_t stage_bytes = 0;
   Prediction* h_pred = nullptr;
   hipStream_t stream = nullptr;
+  // learned mode: the network's inputs are the previous frame's, so features
+  // and network run on a second stream beside the pyramid (fork after the
+  // frame-table copy, join before tracking)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};  // frame start and end on the launch stream
   // eager launches: start/stop events attached to each kernel's dispatch
   // (pyramid+detector, features, network, tracker, selection)
   hipEvent_t kev[kKernels][2] = {};
+  bool kran[kKernels] = {};  // kernels launched (and timed) in the last eager frame
   int device = 0;
   bool poisoned = false;
   bool fault_device = false;
@@ -150,6 +158,8 @@ int check_params(const vio_frontend_params* p, std::string& why) {
     return why = "track_block_waves must be 0, 1, 2 or 4", VIO_EINVAL;
   if (p->flags & ~VIO_FLAG_EAGER) return why = "unknown flag bits", VIO_EINVAL;
   if (p->pyr_tile != 0 && p->pyr_tile != 32 && p->pyr_tile != 64) return why = "pyr_tile must be 0, 32 or 64", VIO_EINVAL;
+  if (p->stereo_mode != VIO_STEREO_SPECULATIVE && p->stereo_mode != VIO_STEREO_DEFERRED)
+    return why = "stereo_mode must be VIO_STEREO_SPECULATIVE or VIO_STEREO_DEFERRED", VIO_EINVAL;
   if (!(p->fb_threshold > 0.f)) return why = "fb_threshold must be positive", VIO_EINVAL;
   if (p->k_per_cell != 1) return why = "only k_per_cell = 1 is implemented", VIO_EUNSUPPORTED;
   if (p->init_mode != VIO_INIT_CONST_VEL && p->init_mode != VIO_INIT_LEARNED) return why = "init_mode", VIO_EINVAL;
@@ -204,6 +214,9 @@ void vio_frontend_destroy(vio_frontend* h) {
   for (hipEvent_t& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   delete h;
 }
 
@@ -280,6 +293,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       if (si.n_cams >= 2 && k % 2 == 0) {
         h->segs.push_back({cc, kModeStereo, items, h->cams[cc].ncells});
         items += h->cams[cc].ncells;
+        si.st_segs += 1;
+        si.st_items += h->cams[cc].ncells;
       }
     }
     for (int k = 0; k < si.n_cams; ++k) {
@@ -407,6 +422,11 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   }
   HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
   HIP_CHECK(h, hipStreamCreate(&h->stream));
+  if (h->learned) {
+    HIP_CHECK(h, hipStreamCreate(&h->aux));
+    HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  }
   for (hipEvent_t& e : h->ev) HIP_CHECK(h, hipEventCreate(&e));
   for (auto& pr : h->kev)
     for (hipEvent_t& e : pr) HIP_CHECK(h, hipEventCreate(&e));
@@ -465,29 +485,49 @@ static Tuning tuning(const vio_frontend* h) {
   t.liters = h->P.learned_iters;
   t.rho = h->P.learned_rho;
   t.guess = h->d_guess;
+  t.deferred = h->P.stereo_mode == VIO_STEREO_DEFERRED;
   return t;
 }
 
 static LaunchSet stream_set(const vio_frontend* h, int s) {
   const StreamInfo& si = h->streams[s];
   return {si.first_cam, si.first_cam + si.n_cams, si.tile_begin, si.n_tiles, si.seg_begin, si.n_segs,
-          si.item_begin, si.n_items, s, 1, false};
+          si.item_begin, si.n_items, s, 1, false, si.st_segs, si.st_items};
 }
 
 static LaunchSet all_set(const vio_frontend* h) {
   const StreamInfo& last = h->streams.back();
+  int st_segs = 0, st_items = 0;
+  for (const StreamInfo& si : h->streams) st_segs += si.st_segs, st_items += si.st_items;
   return {0, (int)h->cams.size(), 0, h->total_tiles, 0, (int)h->segs_all.size(), 0, last.item_begin + last.n_items, 0,
-          (int)h->streams.size(), true};
+          (int)h->streams.size(), true, st_segs, st_items};
+}
+
+// Tracking launch over segments [seg_begin, seg_begin + n_segs) of the set's
+// table and items [item_begin, item_begin + n_items).
+// `queue`: the frame's work-queue counter this launch's persistent grid pops
+// (each tracking launch of a frame has its own).
+static hipError_t track_range(vio_frontend* h, const LaunchSet& ls, int seg_begin, int n_segs, int item_begin,
+                              int n_items, const Tuning& tune, int queue, hipStream_t st) {
+  return launch_track(h->d_cams, h->d_frame, h->d_cnt, (ls.all ? h->d_segs_all : h->d_segs) + seg_begin, n_segs,
+                      item_begin, n_items, h->d_pred, tune,
+                      TrackShape{h->P.track_waves_per_cu,
+                                 h->P.track_block_waves ? h->P.track_block_waves : kTrackWaves, h->n_cus, queue},
+                      st);
 }
 
 // Enqueues one step of a frame of the launch set on `st`: 0 = frame table
-// copy, 1 = pyramid+detector, 2 = (learned mode: features and the network)
-// tracker, 3 = selection. Nothing enqueued changes between frames (per-frame
-// inputs live in the frame table), so the sequence can be captured once.
+// copy, 1 = pyramid+detector, 2 = tracker, 3 = selection (deferred stereo:
+// selection, stereo tracker, selection), 4 = learned mode's features and
+// network. Nothing enqueued changes between frames (per-frame inputs live in
+// the frame table), so the sequence can be captured once.
 // `timed` attaches each kernel's start/stop events to its dispatch.
 static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_t st, int stage, bool timed) {
   const Tuning tune = tuning(h);
-  auto timing = [&](int k) { tl_timing = timed ? KernelTiming{h->kev[k][0], h->kev[k][1]} : KernelTiming{}; };
+  auto timing = [&](int k) {
+    tl_timing = timed ? KernelTiming{h->kev[k][0], h->kev[k][1]} : KernelTiming{};
+    if (timed) h->kran[k] = true;
+  };
   struct Reset {
     ~Reset() { tl_timing = KernelTiming{}; }
   } reset;
@@ -498,40 +538,56 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
     return launch_pyr_detect_range(h->d_cams, h->d_frame, ls.cam_begin, ls.cam_end, ls.tile_begin, ls.n_tiles,
                                    tune.levels, h->tile, tune.tmin, tune.margin, st);
   }
+  if (stage == 4) {
+    // features of every previous keypoint, then one network pass over the
+    // set's rows; the tracker reads the guesses
+    const int row0 = h->cams[ls.cam_begin].row_off;
+    int rows = 0;
+    for (int c = ls.cam_begin; c < ls.cam_end; ++c) rows += h->cams[c].cap;
+    timing(kKernFeatures);
+    if ((e = launch_features(h->d_cams, h->d_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->d_feat,
+                             st)))
+      return e;
+    timing(kKernMlp);
+    return mlp_forward_launch(h->mlp, h->d_feat + (size_t)row0 * 32, rows, h->d_guess + (size_t)row0 * 3, st);
+  }
   if (stage == 2) {
-    if (h->learned) {
-      // features of every previous keypoint, then one network pass over the
-      // set's rows; the tracker reads the guesses
-      const int row0 = h->cams[ls.cam_begin].row_off;
-      int rows = 0;
-      for (int c = ls.cam_begin; c < ls.cam_end; ++c) rows += h->cams[c].cap;
-      timing(kKernFeatures);
-      if ((e = launch_features(h->d_cams, h->d_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->d_feat,
-                               st)))
-        return e;
-      timing(kKernMlp);
-      if ((e = mlp_forward_launch(h->mlp, h->d_feat + (size_t)row0 * 32, rows, h->d_guess + (size_t)row0 * 3, st)))
-        return e;
-    }
+    // speculative: every item; deferred: the temporal items only (they follow the stereo ones)
     timing(kKernTrack);
-    return launch_track(h->d_cams, h->d_frame, h->d_cnt, (ls.all ? h->d_segs_all : h->d_segs) + ls.seg_begin,
-                        ls.n_segs, ls.item_begin,
-                        ls.n_items, h->d_pred, tune,
-                        TrackShape{h->P.track_waves_per_cu,
-                                   h->P.track_block_waves ? h->P.track_block_waves : kTrackWaves, h->n_cus},
-                        st);
+    const int s0 = tune.deferred ? ls.st_segs : 0, i0 = tune.deferred ? ls.st_items : 0;
+    return track_range(h, ls, ls.seg_begin + s0, ls.n_segs - s0, ls.item_begin + i0, ls.n_items - i0, tune, 0, st);
   }
   timing(kKernSelect);
-  return launch_select(h->d_cams, h->d_frame, h->d_cnt, h->d_stream_cams + 2 * ls.stream_begin, ls.n_streams, 0,
-                       tune, st);
+  const int* sc = h->d_stream_cams + 2 * ls.stream_begin;
+  if (!tune.deferred) return launch_select(h->d_cams, h->d_frame, h->d_cnt, sc, ls.n_streams, kSelectAll, tune, st);
+  // deferred stereo: select, match the selected detections, accept the matches
+  if ((e = launch_select(h->d_cams, h->d_frame, h->d_cnt, sc, ls.n_streams, kSelectLeft, tune, st))) return e;
+  if (ls.st_items > 0) {
+    timing(kKernTrackStereo);
+    if ((e = track_range(h, ls, ls.seg_begin, ls.st_segs, ls.item_begin, ls.st_items, tune, 1, st))) return e;
+  }
+  timing(kKernSelectRight);
+  return launch_select(h->d_cams, h->d_frame, h->d_cnt, sc, ls.n_streams, kSelectRight, tune, st);
 }
 
+// The frame's launches. Learned mode forks the features and the network onto
+// the second stream after the frame-table copy (their inputs are the previous
+// frame's keypoints and level 0) and joins before the tracker, so they run
+// beside the pyramid; a captured graph records the fork and join as
+// dependencies.
 static hipError_t enqueue_frame(vio_frontend* h, const LaunchSet& ls, hipStream_t st, bool timed) {
-  for (int k = 0; k <= 3; ++k) {
-    const hipError_t e = enqueue_stage(h, ls, st, k, timed);
-    if (e != hipSuccess) return e;
+  hipError_t e;
+  if ((e = enqueue_stage(h, ls, st, 0, timed))) return e;
+  if (h->learned) {
+    if ((e = hipEventRecord(h->ev_fork, st))) return e;
+    if ((e = hipStreamWaitEvent(h->aux, h->ev_fork, 0))) return e;
+    if ((e = enqueue_stage(h, ls, h->aux, 4, timed))) return e;
+    if ((e = hipEventRecord(h->ev_join, h->aux))) return e;
   }
-  return hipSuccess;
+  if ((e = enqueue_stage(h, ls, st, 1, timed))) return e;
+  if (h->learned && (e = hipStreamWaitEvent(st, h->ev_join, 0))) return e;
+  if ((e = enqueue_stage(h, ls, st, 2, timed))) return e;
+  return enqueue_stage(h, ls, st, 3, timed);
 }
 
 // Captures a launch set into a graph on first use; a capture failure switches
@@ -563,6 +619,7 @@ static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t
   if (gr->whole) {
     HIP_CHECK(h, hipGraphLaunch(gr->whole, st));
   } else {
+    for (bool& r : h->kran) r = false;
     HIP_CHECK(h, enqueue_frame(h, ls, st, true));
   }
   HIP_CHECK(h, hipEventRecord(h->ev[1], st));
@@ -572,12 +629,12 @@ static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t
   float km[kKernels];
   for (int k = 0; k < kKernels; ++k) {
     km[k] = -1.f;
-    const bool ran = k == kKernPyr || k == kKernTrack || k == kKernSelect || h->learned;
-    if (!gr->whole && ran) HIP_CHECK(h, hipEventElapsedTime(&km[k], h->kev[k][0], h->kev[k][1]));
+    if (!gr->whole && h->kran[k]) HIP_CHECK(h, hipEventElapsedTime(&km[k], h->kev[k][0], h->kev[k][1]));
   }
+  // deferred stereo matching: the tracker and selection run twice per frame
   h->stats.last_stage_ms[0] = km[kKernPyr];
-  h->stats.last_stage_ms[1] = km[kKernTrack];
-  h->stats.last_stage_ms[2] = km[kKernSelect];
+  h->stats.last_stage_ms[1] = km[kKernTrack] + (km[kKernTrackStereo] > 0.f ? km[kKernTrackStereo] : 0.f);
+  h->stats.last_stage_ms[2] = km[kKernSelect] + (km[kKernSelectRight] > 0.f ? km[kKernSelectRight] : 0.f);
   h->stats.last_learned_ms[0] = km[kKernFeatures];
   h->stats.last_learned_ms[1] = km[kKernMlp];
   h->stats.last_gpu_ms = ms;

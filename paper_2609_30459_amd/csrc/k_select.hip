@@ -17,6 +17,13 @@
 //    score histogram instead of a sort;
 //  * the kept ones get consecutive identifiers in cell order;
 //  * a stereo match is accepted while the right camera has room.
+//
+// Phases: kSelectAll reads the speculative stereo match of every selected
+// cell (indexed by cell). With deferred stereo matching the work splits in
+// two launches around the stereo tracking launch: kSelectLeft does
+// everything except the right cameras' matches and leaves the new detections'
+// place in the left state in sel_base / n_sel; kSelectRight accepts the
+// matches (indexed by selection rank) into the right cameras.
 #include "fe_common.h"
 
 namespace vio {
@@ -133,9 +140,47 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
   return base;
 }
 
+// Appends the accepted stereo matches of the n_new detections of left camera
+// L (ids from L's new keypoints state[P][sel_base + i]) to right camera R,
+// after its n_surv_r survivors and n_rec_r temporal records. sres(i): the
+// match of detection i.
+template <class SresOf>
+__device__ void accept_matches(const CamDesc& L, int P, int sel_base, const CamDesc& R, const FrameCam& fr,
+                               int rc, int n_new, int n_surv_r, int n_rec_r, SresOf sres, Counters* cnt,
+                               ScanScratch& sc) {
+  const int PR = fr.parity;
+  int m_base = 0;
+  for (int i0 = 0; i0 < n_new; i0 += kSelectThreads) {
+    const int i = i0 + (int)threadIdx.x;
+    const bool valid = i < n_new;
+    TrackRes sr{};
+    int64_t id = 0;
+    if (valid) {
+      sr = sres(i);
+      id = L.state[P][sel_base + i].id;
+    }
+    const bool matched = valid && sr.status == VIO_TRACKED;
+    int m_tot;
+    const int mrank = m_base + block_scan_flag(matched, sc, m_tot);
+    if (valid) {
+      const bool accepted = matched && n_surv_r + mrank < R.cap;
+      const int st = matched ? (accepted ? VIO_MATCHED : VIO_LOST_CAP) : sr.status;
+      R.rec[n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
+      if (accepted) R.state[PR][n_surv_r + mrank] = make_kp(id, sr.x, sr.y, sr.x, sr.y, 0);
+    }
+    m_base += m_tot;
+  }
+  if (threadIdx.x == 0) {
+    cnt->n_live[PR][rc] = n_surv_r + min(m_base, max(0, R.cap - n_surv_r));
+    cnt->rec_count[rc] = n_rec_r + n_new;
+    *R.rec_count_out = n_rec_r + n_new;
+  }
+}
+
 __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __restrict__ cams,
                                                           const FrameTable* __restrict__ frame, Counters* cnt,
-                                                          const int* __restrict__ stream_cams, Tuning tune) {
+                                                          const int* __restrict__ stream_cams, int phase,
+                                                          Tuning tune) {
   __shared__ ScanScratch sc;
   __shared__ unsigned s_occ[kMaxCells];
   __shared__ uint16_t s_sel[kMaxCells];
@@ -144,10 +189,23 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
   const int s = blockIdx.x;
   const int cam0 = stream_cams[2 * s], ncam = stream_cams[2 * s + 1];
   if (!frame->cam[cam0].active) return;
+  const int step = ncam >= 2 ? 2 : 1;
+  if (phase == kSelectRight) {
+    for (int g = 0; g + 1 < ncam; g += 2) {
+      const int lc = cam0 + g, rc = lc + 1;
+      const CamDesc& L = cams[lc];
+      const FrameCam& fr = frame->cam[rc];
+      const int P = frame->cam[lc].parity, PR = fr.parity;
+      const int n_rec_r = fr.has_prev ? cnt->n_live[PR ^ 1][rc] : 0;
+      accept_matches(L, P, cnt->sel_base[lc], cams[rc], fr, rc, cnt->n_sel[lc], cnt->n_live[PR][rc], n_rec_r,
+                     [&](int i) { return L.sres[i]; }, cnt, sc);
+      __syncthreads();
+    }
+    return;
+  }
   const int stream = cams[cam0].stream;
   const int64_t id0 = cnt->next_id[stream];
   int64_t next_id = id0;
-  const int step = ncam >= 2 ? 2 : 1;
   for (int g = 0; g < ncam; g += step) {
     const int lc = cam0 + g;
     const CamDesc& L = cams[lc];
@@ -233,28 +291,14 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       const int PR = fr.parity;
       int n_rec_r = 0;
       const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, tune.learned != 0);
-      int m_base = 0;
-      for (int i0 = 0; i0 < n_new; i0 += kSelectThreads) {
-        const int i = i0 + (int)threadIdx.x;
-        const bool valid = i < n_new;
-        TrackRes sr{};
-        if (valid) sr = L.sres[s_sel[i]];
-        const bool matched = valid && sr.status == VIO_TRACKED;
-        int m_tot;
-        const int mrank = m_base + block_scan_flag(matched, sc, m_tot);
-        if (valid) {
-          const int64_t id = next_id + i;
-          const bool accepted = matched && n_surv_r + mrank < R.cap;
-          const int st = matched ? (accepted ? VIO_MATCHED : VIO_LOST_CAP) : sr.status;
-          R.rec[n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
-          if (accepted) R.state[PR][n_surv_r + mrank] = make_kp(id, sr.x, sr.y, sr.x, sr.y, 0);
-        }
-        m_base += m_tot;
-      }
-      if (threadIdx.x == 0) {
-        cnt->n_live[PR][rc] = n_surv_r + min(m_base, max(0, R.cap - n_surv_r));
-        cnt->rec_count[rc] = n_rec_r + n_new;
-        *R.rec_count_out = n_rec_r + n_new;
+      if (phase == kSelectAll) {
+        accept_matches(L, P, n_surv, R, fr, rc, n_new, n_surv_r, n_rec_r, [&](int i) { return L.sres[s_sel[i]]; },
+                       cnt, sc);
+      } else if (threadIdx.x == 0) {
+        // the matches come from the stereo tracking launch; kSelectRight appends them
+        cnt->sel_base[lc] = n_surv;
+        cnt->n_sel[lc] = n_new;
+        cnt->n_live[PR][rc] = n_surv_r;
       }
       __syncthreads();
     }
@@ -266,10 +310,10 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
 }  // namespace
 
 hipError_t launch_select(const CamDesc* d_cams, const FrameTable* d_frame, Counters* d_cnt, const int* d_stream_cams,
-                         int n_streams_launch, int /*cams_per_stream_max*/, Tuning tune, hipStream_t s) {
+                         int n_streams_launch, int phase, Tuning tune, hipStream_t s) {
   if (n_streams_launch <= 0) return hipSuccess;
   launch_kernel(k_select, dim3(n_streams_launch), dim3(kSelectThreads), 0, s, d_cams, d_frame, d_cnt,
-                     d_stream_cams, tune);
+                d_stream_cams, phase, tune);
   return hipGetLastError();
 }
 

@@ -375,10 +375,21 @@ __device__ void process_item(const CamDesc* __restrict__ cams, const FrameTable*
     }
     store_result(cd.res + j, r, lane);
   } else {
-    const uint32_t key = cd.keys[P][j];
-    if (key == 0) return;
-    const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
-    const float x = (float)(idx % cd.w), y = (float)(idx / cd.w);
+    // stereo match of a detection: speculative (item j = cell j's winner) or
+    // deferred (item j = the frame's j-th selected detection)
+    float x, y;
+    if (tune.deferred) {
+      if (j >= cnt->n_sel[c]) return;
+      const Kp kp = cd.state[P][cnt->sel_base[c] + j];
+      x = kp.x;
+      y = kp.y;
+    } else {
+      const uint32_t key = cd.keys[P][j];
+      if (key == 0) return;
+      const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
+      x = (float)(idx % cd.w);
+      y = (float)(idx / cd.w);
+    }
     TrackRes r = track_fb<L>(cd, P, cams[cd.partner], P, x, y, x - tune.disparity0, y, tune.iters,
                              tune.fb_threshold, u, v, wgt);
     r.pad[0] = 0;
@@ -414,12 +425,12 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track_persistent(const CamD
                                                                      const TrackSeg* __restrict__ segs, int n_segs,
                                                                      int item_base, int n_items,
                                                                      const Prediction* __restrict__ pred,
-                                                                     Tuning tune) {
+                                                                     Tuning tune, int queue) {
   const int lane = threadIdx.x & (kW - 1);
   float u, v, wgt;
   pattern_of(lane, u, v, wgt);
   for (;;) {
-    const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&frame->queue_head, lane == 0 ? 1 : 0));
+    const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&frame->queue_head[queue], lane == 0 ? 1 : 0));
     if (k >= n_items) break;
     process_item<L, LL>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
   }
@@ -433,7 +444,7 @@ hipError_t launch_L(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt,
     const int waves = std::min(n_items, sh.waves_per_cu * sh.n_cus);
     const int blocks = (waves + bw - 1) / bw;
     launch_kernel(k_track_persistent<L, LL>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs,
-                       n_segs, item_base, n_items, d_pred, tune);
+                  n_segs, item_base, n_items, d_pred, tune, sh.queue);
   } else {
     const int blocks = (n_items + bw - 1) / bw;
     launch_kernel(k_track<L, LL>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
@@ -461,7 +472,8 @@ hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_
                         int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape shape,
                         hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (shape.block_waves < 1 || shape.block_waves > kTrackWaves || shape.n_cus < 1 || shape.waves_per_cu < 0)
+  if (shape.block_waves < 1 || shape.block_waves > kTrackWaves || shape.n_cus < 1 || shape.waves_per_cu < 0 ||
+      shape.queue < 0 || shape.queue >= 4)
     return hipErrorInvalidValue;
   switch (tune.levels) {
 #define VIO_TRACK_CASE(LV) \

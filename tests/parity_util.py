@@ -79,9 +79,11 @@ def compare_records(gpu, orc, fb_threshold, where=""):
 
 
 def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, stream_overrides=None,
-             push_device=False):
+             push_device=False, launch=None):
     """Runs the oracle and the GPU frontend over the first n_frames of `seq`.
 
+    params_overrides apply to both sides; launch: GPU-only launch parameters
+    (tiles, tracker shape, stereo mode), which must not change the records.
     Yields (t, gpu_records, oracle_records, excused) per frame.
     """
     import paper_2609_30459_amd as vf
@@ -91,7 +93,7 @@ def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, 
     stream = (workload.n_cams, workload.width, workload.height, workload.max_keypoints, workload.cell_size)
     if stream_overrides:
         stream = stream_overrides
-    fe_g = vf.Frontend([stream], vf.params_for(workload, **po))
+    fe_g = vf.Frontend([stream], vf.params_for(workload, **po, **(launch or {})))
     dev = None
     if push_device:
         import torch

@@ -37,11 +37,13 @@ def _streams():
     return [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in MIX]
 
 
-@pytest.mark.parametrize("waves_per_cu,block_waves,tile", [(0, 4, 64), (0, 1, 32), (4, 4, 64), (2, 2, 32)])
-def test_batched_step_equals_per_stream_push(waves_per_cu, block_waves, tile):
+@pytest.mark.parametrize("waves_per_cu,block_waves,tile,stereo_mode",
+                         [(0, 4, 64, 0), (0, 1, 32, 1), (4, 4, 64, 1), (2, 2, 32, 0)])
+def test_batched_step_equals_per_stream_push(waves_per_cu, block_waves, tile, stereo_mode):
     import paper_2609_30459_amd as vf
     seqs = _seqs(4)
-    params = vf.params_for(MIX[1], track_waves_per_cu=waves_per_cu, track_block_waves=block_waves, pyr_tile=tile)
+    params = vf.params_for(MIX[1], track_waves_per_cu=waves_per_cu, track_block_waves=block_waves, pyr_tile=tile,
+                           stereo_mode=stereo_mode)
     with vf.Frontend(_streams(), params) as a, vf.Frontend(_streams(), vf.params_for(MIX[1])) as b:
         for t in range(4):
             for s, seq in enumerate(seqs):

@@ -93,8 +93,9 @@ def _learned_params(w, rho, levels=2, iters=3):
     return dict(init_mode=1, learned_levels=levels, learned_iters=iters, learned_rho=rho)
 
 
-@pytest.mark.parametrize("rho", [-1.0, 0.02, 1e9])
-def test_learned_pipeline_parity_and_features(rho):
+@pytest.mark.parametrize("rho,launch", [(-1.0, {}), (0.02, {}), (1e9, {}), (0.02, {"eager": True}),
+                                        (0.02, {"stereo_mode": 1, "track_waves_per_cu": 4})])
+def test_learned_pipeline_parity_and_features(rho, launch):
     import paper_2609_30459_amd as vf
     w = synthgen.WORKLOADS["stereo752"]
     seq = synthgen.sequence(w, seq=7, n_frames=4)
@@ -104,7 +105,8 @@ def test_learned_pipeline_parity_and_features(rho):
     fe_o = oracle.Frontend([w.width] * 2, [w.height] * 2, True, oracle.params_for(w, **po))
     fe_o.set_mlp(P)
     n_fb = 0
-    with vf.Frontend([(2, w.width, w.height, w.max_keypoints, w.cell_size)], vf.params_for(w, **po)) as fe_g:
+    with vf.Frontend([(2, w.width, w.height, w.max_keypoints, w.cell_size)],
+                     vf.params_for(w, **po, **launch)) as fe_g:
         fe_g.set_mlp(P)
         for t in range(4):
             if t > 0:

@@ -103,6 +103,36 @@ def test_free_running_stereo_matches_oracle():
         assert not exc, (t, exc)
 
 
+def test_free_running_deferred_stereo_matches_oracle():
+    """Deferred stereo matching (selection first, then only the selected
+    detections are matched) keeps lockstep with the oracle."""
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=1, n_frames=8)
+    for t, g, o, exc, _, _ in run_pair(w, seq, 8, inject_state=False, launch={"stereo_mode": 1}):
+        assert not exc, (t, exc)
+
+
+@pytest.mark.parametrize("eager", [False, True])
+@pytest.mark.parametrize("name,n_cams", [("stereo", 2), ("two_pairs", 4)])
+def test_deferred_stereo_equals_speculative_bitwise(name, n_cams, eager):
+    vf = _vf()
+    w = synthgen.WORKLOADS["stereo752"].with_(n_canvases=n_cams // 2)
+    seq = synthgen.sequence(w, seq=9, n_frames=6)
+    stream = (n_cams, w.width, w.height, w.max_keypoints, w.cell_size)
+    matched = 0
+    with vf.Frontend([stream], vf.params_for(w, eager=eager)) as a, \
+            vf.Frontend([stream], vf.params_for(w, eager=eager, stereo_mode=1)) as b:
+        for t in range(6):
+            a.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            b.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            ra, rb = a.get_tracks(0), b.get_tracks(0)
+            matched += int((ra["status"] == vf.VIO_MATCHED).sum())
+            assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), t
+            if eager:
+                assert all(m > 0 for m in b.stats()["last_stage_ms"])
+    assert matched > 0
+
+
 def test_device_push_equals_host_push_bitwise():
     import torch
     vf = _vf()
