@@ -164,9 +164,24 @@ struct TrackShape {
 hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
                         int n_segs, int item_base, int n_items, const Prediction* d_pred, Tuning tune,
                         TrackShape shape, hipStream_t s);
-// Features of cameras [cam_begin, cam_end); h_cams: host copy of the descriptors (caps).
+// Neighbour grids of the learned init's features, per camera c: hdr[c] =
+// (cell edge px, cells x, cells y, 0), start[c][0 .. cells] the first slot of
+// each cell (row-major), pos/idx[row_off .. row_off + cap) the position and
+// state index of the tracks with a flow, by cell.
+constexpr int kFeatGridMax = 1024;
+struct FeatGrid {
+  int4* hdr;
+  int* start;  // [cameras][kFeatGridMax + 1]
+  float2* pos;
+  int* idx;
+};
+// Builds the grids of cameras [cam_begin, cam_end) from their previous keypoints.
+hipError_t launch_grid(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt, int cam_begin,
+                       int cam_end, const FeatGrid& fg, hipStream_t s);
+// Features of cameras [cam_begin, cam_end) from their grids; h_cams: host copy of the descriptors (caps).
 hipError_t launch_features(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt,
-                           const CamDesc* h_cams, int cam_begin, int cam_end, float* d_feat, hipStream_t s);
+                           const CamDesc* h_cams, int cam_begin, int cam_end, const FeatGrid& fg, float* d_feat,
+                           hipStream_t s);
 hipError_t mlp_forward_launch(const MlpDev& M, const float* X, int K, float* Y, hipStream_t s);
 hipError_t mlp_pack_launch(const MlpDev& M, hipStream_t s);
 // Selection phases: kSelectAll (speculative stereo: everything in one

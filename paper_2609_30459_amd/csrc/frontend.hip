@@ -65,7 +65,17 @@ struct LaunchSet {
   int st_segs, st_items;  // the leading stereo segments/items of the range
 };
 
-enum { kKernPyr, kKernFeatures, kKernMlp, kKernTrack, kKernSelect, kKernTrackStereo, kKernSelectRight, kKernels };
+enum {
+  kKernPyr,
+  kKernFeatures,
+  kKernMlp,
+  kKernTrack,
+  kKernSelect,
+  kKernTrackStereo,
+  kKernSelectRight,
+  kKernGrid,
+  kKernels
+};
 
 struct vio_frontend {
   vio_frontend_params P{};
@@ -94,6 +104,7 @@ struct vio_frontend {
   bool learned = false, mlp_ready = false;
   MlpDev mlp{};
   float* d_feat = nullptr;   // [rows][32]
+  FeatGrid grid{};           // neighbour grids of the features
   float* d_guess = nullptr;  // [rows][3]
   int32_t* h_fallback = nullptr;
   // pinned host
@@ -331,10 +342,15 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   const size_t o_sc = take(sizeof(int) * h->stream_cams.size());
   const size_t o_pred = take(sizeof(Prediction) * std::max(1, h->pred_cap));
   size_t o_feat = 0, o_guess = 0, o_P = 0, o_W1 = 0, o_W2 = 0, o_W2t = 0, o_W3 = 0;
+  size_t o_ghdr = 0, o_gstart = 0, o_gpos = 0, o_gidx = 0;
   if (h->learned) {
     const int rows = (rows_total + 15) / 16 * 16;
     o_feat = take(sizeof(float) * 32 * rows);
     o_guess = take(sizeof(float) * 3 * rows);
+    o_ghdr = take(sizeof(int4) * n_cams);
+    o_gstart = take(sizeof(int) * (kFeatGridMax + 1) * n_cams);
+    o_gpos = take(sizeof(float2) * rows);
+    o_gidx = take(sizeof(int) * rows);
     o_P = take(sizeof(float) * VIO_MLP_NPARAM);
     o_W1 = take(2 * 128 * 32);
     o_W2 = take(2 * 128 * 128);
@@ -385,6 +401,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   if (h->learned) {
     h->d_feat = reinterpret_cast<float*>(base + o_feat);
     h->d_guess = reinterpret_cast<float*>(base + o_guess);
+    h->grid = FeatGrid{reinterpret_cast<int4*>(base + o_ghdr), reinterpret_cast<int*>(base + o_gstart),
+                       reinterpret_cast<float2*>(base + o_gpos), reinterpret_cast<int*>(base + o_gidx)};
     h->mlp.P = reinterpret_cast<float*>(base + o_P);
     h->mlp.W1b = reinterpret_cast<uint16_t*>(base + o_W1);
     h->mlp.W2b = reinterpret_cast<uint16_t*>(base + o_W2);
@@ -544,9 +562,11 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
     const int row0 = h->cams[ls.cam_begin].row_off;
     int rows = 0;
     for (int c = ls.cam_begin; c < ls.cam_end; ++c) rows += h->cams[c].cap;
+    timing(kKernGrid);
+    if ((e = launch_grid(h->d_cams, h->d_frame, h->d_cnt, ls.cam_begin, ls.cam_end, h->grid, st))) return e;
     timing(kKernFeatures);
-    if ((e = launch_features(h->d_cams, h->d_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->d_feat,
-                             st)))
+    if ((e = launch_features(h->d_cams, h->d_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->grid,
+                             h->d_feat, st)))
       return e;
     timing(kKernMlp);
     return mlp_forward_launch(h->mlp, h->d_feat + (size_t)row0 * 32, rows, h->d_guess + (size_t)row0 * 3, st);
@@ -635,7 +655,7 @@ static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t
   h->stats.last_stage_ms[0] = km[kKernPyr];
   h->stats.last_stage_ms[1] = km[kKernTrack] + (km[kKernTrackStereo] > 0.f ? km[kKernTrackStereo] : 0.f);
   h->stats.last_stage_ms[2] = km[kKernSelect] + (km[kKernSelectRight] > 0.f ? km[kKernSelectRight] : 0.f);
-  h->stats.last_learned_ms[0] = km[kKernFeatures];
+  h->stats.last_learned_ms[0] = km[kKernFeatures] + (km[kKernGrid] > 0.f ? km[kKernGrid] : 0.f);
   h->stats.last_learned_ms[1] = km[kKernMlp];
   h->stats.last_gpu_ms = ms;
   h->stats.frames += 1;

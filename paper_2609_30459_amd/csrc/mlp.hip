@@ -150,6 +150,97 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpDev M, const floa
 }
 
 // ---------------------------------------------------------------------------
+// inference forward: the same MFMA sequence as k_mlp_fwd (so the same
+// results), with the workgroup's bf16 weights and the biases staged in LDS
+// once, and layer 2's eight output tiles held in registers so its output
+// reuses the wave's layer-1 tile in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kInferWaves = 4;
+__global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(MlpDev M, const float* __restrict__ X, int K,
+                                                               int Kpad, float* __restrict__ Y) {
+  __shared__ __align__(16) uint16_t sW1[MH * MI];
+  __shared__ __align__(16) uint16_t sW2[MH * MH];
+  __shared__ __align__(16) uint16_t sW3[16 * MH];  // rows 3..15 zero
+  __shared__ float sB[MH + MH + 16];
+  __shared__ __align__(16) uint16_t sH[kInferWaves][16][MH];
+  const int tid = (int)threadIdx.x;
+  // stage the weights: 16-byte copies
+  {
+    const uint4* w1 = reinterpret_cast<const uint4*>(M.W1b);
+    const uint4* w2 = reinterpret_cast<const uint4*>(M.W2b);
+    const uint4* w3 = reinterpret_cast<const uint4*>(M.W3b);
+    for (int i = tid; i < MH * MI / 8; i += 64 * kInferWaves) reinterpret_cast<uint4*>(sW1)[i] = w1[i];
+    for (int i = tid; i < MH * MH / 8; i += 64 * kInferWaves) reinterpret_cast<uint4*>(sW2)[i] = w2[i];
+    for (int i = tid; i < 16 * MH / 8; i += 64 * kInferWaves)
+      reinterpret_cast<uint4*>(sW3)[i] = i < MO * MH / 8 ? w3[i] : make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < MH + MH + 16; i += 64 * kInferWaves)
+      sB[i] = i < MH ? M.P[OFF_B1 + i] : i < 2 * MH ? M.P[OFF_B2 + i - MH] : i - 2 * MH < MO ? M.P[OFF_B3 + i - 2 * MH]
+                                                                                             : 0.f;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int i0 = ((int)blockIdx.x * kInferWaves + wv) * 16;
+  if (i0 >= Kpad) return;  // no barrier follows
+  const int r = lane & 15, g = lane >> 4;
+  uint16_t (*h)[MH] = sH[wv];
+  uint16_t xv[8];
+  {
+    const int i = i0 + r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xv[e] = i < K ? bf16_bits(X[(size_t)i * MI + 8 * g + e]) : (uint16_t)0;
+  }
+  const bf16x8 a = pack8(xv);
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  // layer 1
+#pragma unroll
+  for (int jt = 0; jt < MH / 16; ++jt) {
+    const int j = 16 * jt + r;
+    const f32x4 acc = mfma(a, load8(&sW1[j * MI + 8 * g]), zero);
+    const float b = sB[j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 4 * g + q;
+      h[row][j] = (i0 + row) < K ? bf16_bits(fmaxf(acc[q] + b, 0.f)) : (uint16_t)0;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // layer 2: all eight output tiles in registers, then written over h1
+  f32x4 acc2[MH / 16];
+#pragma unroll
+  for (int jt = 0; jt < MH / 16; ++jt) {
+    const int j = 16 * jt + r;
+    f32x4 acc = zero;
+#pragma unroll
+    for (int kc = 0; kc < MH / 32; ++kc) acc = mfma(load8(&h[r][32 * kc + 8 * g]), load8(&sW2[j * MH + 32 * kc + 8 * g]), acc);
+    acc2[jt] = acc;
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int jt = 0; jt < MH / 16; ++jt) {
+    const int j = 16 * jt + r;
+    const float b = sB[MH + j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = 4 * g + q;
+      h[row][j] = (i0 + row) < K ? bf16_bits(fmaxf(acc2[jt][q] + b, 0.f)) : (uint16_t)0;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // layer 3: 3 outputs padded to a 16-column tile (zero weight rows)
+  f32x4 acc = zero;
+#pragma unroll
+  for (int kc = 0; kc < MH / 32; ++kc) acc = mfma(load8(&h[r][32 * kc + 8 * g]), load8(&sW3[r * MH + 32 * kc + 8 * g]), acc);
+  if (r < MO) {
+    const float b = sB[2 * MH + r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + 4 * g + q;
+      if (i < K) Y[(size_t)i * MO + r] = acc[q] + b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // loss: Huber (1 px) on (16 y0, 16 y1) - target plus BCE of y2 against
 // [|guess - target| <= 2 px]; mean over the batch. One workgroup.
 // ---------------------------------------------------------------------------
@@ -354,9 +445,8 @@ hipError_t mlp_pack_launch(const MlpDev& M, hipStream_t s) {
 hipError_t mlp_forward_launch(const MlpDev& M, const float* X, int K, float* Y, hipStream_t s) {
   if (K <= 0) return hipSuccess;
   const int Kpad = (K + 15) / 16 * 16;
-  const int blocks = (Kpad / 16 + kMlpWaves - 1) / kMlpWaves;
-  MlpScratch none{};
-  launch_kernel(k_mlp_fwd<false>, dim3(blocks), dim3(64 * kMlpWaves), 0, s, M, X, K, Kpad, Y, none);
+  const int blocks = (Kpad / 16 + kInferWaves - 1) / kInferWaves;
+  launch_kernel(k_mlp_infer, dim3(blocks), dim3(64 * kInferWaves), 0, s, M, X, K, Kpad, Y);
   return hipGetLastError();
 }
 
