@@ -5,11 +5,10 @@
 // images, chosen per workload at create). It stages
 // the tile plus an apron in LDS with coalesced dword loads, then
 //  * computes the FAST-9 score (Sec. III-D) of the tile and a one-pixel ring
-//    (the paper's early rejection on ring pairs (0,8)/(4,12), then an exact
-//    run-of-9 bit-mask test at the last threshold, then the score only for
-//    pixels that pass), keeps strict 3x3 maxima with score >= the last
-//    threshold and folds each into its cell's packed key with one atomicMax,
-//    and
+//    (the paper's early rejection on ring pairs (0,8)/(4,12), then the score,
+//    both polarities at once in 16-bit halves), keeps strict 3x3 maxima with
+//    score >= the last threshold and folds each into its cell's packed key
+//    with one atomicMax, and
 //  * builds every coarser pyramid level of the tile (Sec. III-C, eqs. 2-3)
 //    from LDS, recomputing the apron instead of reading it back from HBM, so
 //    level 0 is read from HBM once per frame and the L-1 level-serial
@@ -72,53 +71,36 @@ __device__ __forceinline__ void ring_diffs(const uint8_t* img, int o, int sp, in
   d[15] = img[o - 3 * sp - 1] - c;
 }
 
-// Exact test of score >= tmin: the paper's early rejection on ring pairs
-// (0,8)/(4,12) (every 9-arc holds one of each pair), then whether the 16-bit
-// circular mask of pixels above (below) the threshold holds a run of 9
-// (rotate-and-AND on a doubled mask).
-__device__ __forceinline__ bool fast_candidate(const int d[16], int tmin) {
+// The paper's early rejection (Sec. III-D): every 9-arc holds one of the ring
+// positions 0 and 8 and one of 4 and 12, so a corner at threshold tmin needs
+// such a pair brighter than I(p) + tmin or darker than I(p) - tmin.
+__device__ __forceinline__ bool fast_may_pass(const int d[16], int tmin) {
   const bool bright = (d[0] > tmin || d[8] > tmin) && (d[4] > tmin || d[12] > tmin);
   const bool dark = (d[0] < -tmin || d[8] < -tmin) && (d[4] < -tmin || d[12] < -tmin);
-  if (!bright && !dark) return false;
-  uint32_t mb = 0, md = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    mb |= (uint32_t)(d[k] > tmin) << k;
-    md |= (uint32_t)(d[k] < -tmin) << k;
-  }
-  auto run9 = [](uint32_t m) {
-    const uint32_t x = m | (m << 16);
-    uint32_t a = x & (x >> 1);
-    a &= a >> 2;
-    a &= a >> 4;
-    a &= x >> 8;
-    return (a & 0xFFFFu) != 0;
-  };
-  return run9(mb) || run9(md);
+  return bright || dark;
 }
+
+typedef short short2v __attribute__((ext_vector_type(2)));
 
 // FAST-9 score (Sec. III-D): the largest tau with a 9-arc all brighter than
 // I(p)+tau or all darker than I(p)-tau, i.e. (max over polarity and arc of the
-// arc's minimum signed difference) - 1.
+// arc's minimum signed difference) - 1. Both polarities ride in the two
+// 16-bit halves of one register (differences lie in -255..255): sliding
+// minima of width 2, 4, then 9 over the circle, one maximum.
 __device__ __forceinline__ int fast_score(const int d[16]) {
-  int best = -256;
+  short2v e[16], m2[16], m4[16];
 #pragma unroll
-  for (int pol = 0; pol < 2; ++pol) {
-    int e[16];
+  for (int k = 0; k < 16; ++k) e[k] = short2v{(short)d[k], (short)-d[k]};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) e[k] = pol ? -d[k] : d[k];
-    int m2[16], m4[16];
+  for (int k = 0; k < 16; ++k) m2[k] = __builtin_elementwise_min(e[k], e[(k + 1) & 15]);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) m2[k] = min(e[k], e[(k + 1) & 15]);
+  for (int k = 0; k < 16; ++k) m4[k] = __builtin_elementwise_min(m2[k], m2[(k + 2) & 15]);
+  short2v best = __builtin_elementwise_min(__builtin_elementwise_min(m4[0], m4[4]), e[8]);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) m4[k] = min(m2[k], m2[(k + 2) & 15]);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int m9 = min(min(m4[k], m4[(k + 4) & 15]), e[(k + 8) & 15]);
-      best = max(best, m9);
-    }
-  }
-  return max(best - 1, -1);
+  for (int k = 1; k < 16; ++k)
+    best = __builtin_elementwise_max(
+        best, __builtin_elementwise_min(__builtin_elementwise_min(m4[k], m4[(k + 4) & 15]), e[(k + 8) & 15]));
+  return max(max((int)best.x, (int)best.y) - 1, -1);
 }
 
 template <int L, int T>
@@ -133,8 +115,6 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   constexpr int kScoreEdge = G::score_edge;
   __shared__ __align__(16) uint8_t s_l0[G::sh0 * G::sw0];
   __shared__ uint8_t s_score[kScoreEdge * kScoreEdge];
-  __shared__ uint16_t s_queue[kScoreEdge * kScoreEdge];
-  __shared__ int s_nq;
   __shared__ uint16_t s_v[G::vbytes];
   __shared__ uint8_t s_lv[2][G::lvl_bytes];
 
@@ -191,38 +171,20 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   }
 
   // ---- FAST-9 + strict NMS + per-cell key ---------------------------------
-  // Phase A tests every pixel of the tile and its one-pixel ring exactly for
-  // score >= tmin and queues the few that pass (wave ballot + one LDS atomic
-  // per wave); phase B scores only the queue, so waves stay dense.
+  // Scores of the tile and its one-pixel ring (0: below the last threshold).
   if (cd.detect) {
-    if (tid == 0) s_nq = 0;
-    __syncthreads();
-    for (int i0 = 0; i0 < kScoreEdge * kScoreEdge; i0 += kPyrThreads) {
-      const int i = i0 + tid;
-      bool cand = false;
-      if (i < kScoreEdge * kScoreEdge) {
-        const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
-        if (sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin) {
-          int d[16];
-          ring_diffs(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, d);
-          cand = fast_candidate(d, tmin);
-        }
-        s_score[i] = 0;  // 0: below the last threshold
-      }
-      const unsigned long long m = __ballot(cand);
-      int base = 0;
-      if ((tid & 63) == 0 && m) base = atomicAdd(&s_nq, __popcll(m));
-      base = __shfl(base, 0);
-      if (cand) s_queue[base + __popcll(m & ((1ull << (tid & 63)) - 1ull))] = (uint16_t)i;
-    }
-    __syncthreads();
-    const int nq = s_nq;
-    for (int q = tid; q < nq; q += kPyrThreads) {
-      const int i = s_queue[q];
+    for (int i = tid; i < kScoreEdge * kScoreEdge; i += kPyrThreads) {
       const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
-      int d[16];
-      ring_diffs(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, d);
-      s_score[i] = (uint8_t)(fast_score(d) + 1);
+      int sc = 0;
+      if (sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin) {
+        int d[16];
+        ring_diffs(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, d);
+        if (fast_may_pass(d, tmin)) {
+          const int score = fast_score(d);
+          sc = score >= tmin ? score + 1 : 0;
+        }
+      }
+      s_score[i] = (uint8_t)sc;
     }
     __syncthreads();
     uint32_t* keys = cd.keys[par];
