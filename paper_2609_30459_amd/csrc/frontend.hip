@@ -282,7 +282,10 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       tiles += c.tiles_x * c.tiles_y;
       for (int l = 0; l < P.levels; ++l) {
         c.pitch[l] = (int)round_up((size_t)(si.w >> l), 64);
-        for (int par = 0; par < 2; ++par) co[cam].lvl[par][l] = take((size_t)c.pitch[l] * (size_t)(si.h >> l));
+        // one guard row: the tracker's template window reads up to one row and
+        // one column past a level (with weight 0)
+        for (int par = 0; par < 2; ++par)
+          co[cam].lvl[par][l] = take((size_t)c.pitch[l] * (size_t)((si.h >> l) + 1));
       }
       for (int par = 0; par < 2; ++par) co[cam].state[par] = take(sizeof(Kp) * si.cap);
       co[cam].res = take(sizeof(TrackRes) * si.cap);

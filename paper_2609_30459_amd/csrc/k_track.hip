@@ -10,18 +10,31 @@
 // A keypoint's time is its chain of dependent steps (2 passes x L levels x N
 // iterations), each a gather, a reduction and a little wave-uniform math, with
 // about one wave per SIMD at these sizes. The kernel is shaped for that chain:
-//  * sums over the pattern: DPP inside each 16-lane row, then row_bcast:15/31
-//    and one readlane of lane 63 -- a fixed tree, so results are deterministic;
+//  * one copy of the alignment code per kernel: the learned attempt and the
+//    plain one, and the forward and backward passes, run it in a loop with the
+//    level count as an argument, so it is inlined and every descriptor field,
+//    pyramid base pointer and warp parameter stays a scalar (SGPR) value;
+//  * sums over the pattern are taken several at once: inside each 16-lane
+//    row, four exchange stages (lane ^ 1, ^ 2 by quad permutes, rotations by 4
+//    and 8) each halve the values a lane carries -- a lane keeps the half its
+//    lane bit selects and adds its partner's copy of it -- until lane j of a
+//    row holds sum j of that row; two row swaps (permlane32, permlane16) add
+//    the four rows, and sum j is read from lane j. A fixed tree, so results
+//    are deterministic, at about half the instructions of one reduction per
+//    value;
 //  * per iteration one fused reduction of (sum I'_i, sum G_i I'_i), since
 //      delta = -sum_i G_i (I'_i / mean' - T_i) = c - (sum_i G_i I'_i) / mean'
 //    with c = sum_i G_i T_i fixed per level;
 //  * the templates of all levels of a pass are built together (they depend
-//    only on the source image and the keypoint), so their gathers and
-//    reductions overlap instead of sitting between the levels' iterations;
+//    only on the source image and the keypoint), so their loads and reductions
+//    overlap; a point's five template samples (centre and the four neighbours
+//    of the central difference) share one 4x4 pixel window, read as four
+//    unaligned 32-bit rows;
 //  * wave-uniform math uses the hardware reciprocal and sine/cosine, and a
 //    series for the SE(2) exponential;
-//  * gathers read the pyramid through the L1 cache (the patch's lines stay hot
-//    across a level's iterations).
+//  * gathers are global loads at a 32-bit offset from the level's scalar base,
+//    through the L1 cache (the patch's lines stay hot across a level's
+//    iterations).
 // Decisions (template fit, degeneracy, leaving the image) are taken in the
 // same order as a level-by-level pass, so the status is that of the paper's
 // procedure.
@@ -39,24 +52,97 @@ namespace {
 
 constexpr int kW = 64;
 
-template <int ctrl, int row_mask = 0xF>
-__device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(float,
-                            __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, row_mask, 0xF, false));
+typedef const __attribute__((address_space(1))) uint8_t* gbytes;
+struct __attribute__((packed)) U16 {
+  uint16_t v;
+};
+struct __attribute__((packed)) U32 {
+  uint32_t v;
+};
+
+// unaligned 16- and 32-bit global loads at a 32-bit byte offset
+__device__ __forceinline__ uint32_t ld16(gbytes p, uint32_t off) {
+  return ((const __attribute__((address_space(1))) U16*)(p + off))->v;
+}
+__device__ __forceinline__ uint32_t ld32(gbytes p, uint32_t off) {
+  return ((const __attribute__((address_space(1))) U32*)(p + off))->v;
 }
 
-// Sum over the 64 lanes, returned as a wave-uniform value: each 16-lane row is
-// reduced with quad permutes and mirrors (every lane of a row then holds the
-// row sum), row_bcast:15 adds row 0 into row 1 and row 2 into row 3,
-// row_bcast:31 adds rows 0+1 into row 3; lane 63 holds (r2+r3)+(r0+r1).
-__device__ __forceinline__ float wave_sum(float v) {
-  v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);       // row_half_mirror
-  v += dpp<0x140>(v);       // row_mirror
-  v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
-  v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+template <int ctrl>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+}
+
+// One exchange stage inside the 16-lane rows: the partner of a lane differs
+// from it in lane bit BIT and agrees below it (CTRL: quad_perm [1,0,3,2] for
+// bit 0, quad_perm [2,3,0,1] for bit 1, row_ror:4 for bit 2, row_ror:8 for
+// bit 3). With N > 1 values, value pair (2i, 2i+1) becomes value i: a lane
+// keeps the member its bit selects and adds the partner's copy of it (the
+// partner, with the other bit, sends exactly that member).
+template <int CTRL, int BIT, int N>
+__device__ __forceinline__ void xstage(float* v, int lane) {
+  if constexpr (N == 1) {
+    v[0] += dpp<CTRL>(v[0]);
+  } else {
+    const bool b = (lane >> BIT) & 1;
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      const float keep = b ? v[2 * i + 1] : v[2 * i];
+      const float send = b ? v[2 * i] : v[2 * i + 1];
+      v[i] = keep + dpp<CTRL>(send);
+    }
+  }
+}
+
+// Sum of a row with its partner row: permlane32 swaps lanes 32..63 of one copy
+// with lanes 0..31 of the other (rows 0,1 <-> 2,3), permlane16 the odd rows of
+// one copy with the even rows of the other (rows 0 <-> 1, 2 <-> 3); the two
+// results, added, give every lane its value plus the partner row's value in
+// the same position.
+__device__ __forceinline__ float rowswap_sum32(float x) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
+                                                  false, false);
+  const unsigned a = p[0], b = p[1];  // (a bit cast of p[1] itself would read p[0])
+  return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+__device__ __forceinline__ float rowswap_sum16(float x) {
+  const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
+                                                  false, false);
+  const unsigned a = p[0], b = p[1];  // (a bit cast of p[1] itself would read p[0])
+  return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+
+// v[i] <- sum of v[i] over the 64 lanes, i < N (N = 1, 2, 4, 8 or 16), as
+// wave-uniform values.
+template <int N>
+__device__ __forceinline__ void wave_sums_pow2(float* v, int lane) {
+  static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "power of two up to 16");
+  float w[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = v[i];
+  xstage<0xB1, 0, N>(w, lane);
+  xstage<0x4E, 1, (N > 2 ? N / 2 : 1)>(w, lane);
+  xstage<0x124, 2, (N > 4 ? N / 4 : 1)>(w, lane);
+  xstage<0x128, 3, (N > 8 ? N / 8 : 1)>(w, lane);
+  // lane j of every row holds sum j (j = lane mod N) of its row
+  const float x = rowswap_sum16(rowswap_sum32(w[0]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
+}
+
+// v[i] <- wave sum of v[i] for i < M, in chunks of 16, 8, 4, 2, 1
+template <int M>
+__device__ __forceinline__ void wave_sums(float* v, int lane) {
+  if constexpr (M > 0) {
+    constexpr int C = M >= 16 ? 16 : M >= 8 ? 8 : M >= 4 ? 4 : M >= 2 ? 2 : 1;
+    wave_sums_pow2<C>(v, lane);
+    wave_sums<M - C>(v + C, lane);
+  }
+}
+
+__device__ __forceinline__ float wave_sum(float x, int lane) {
+  wave_sums_pow2<1>(&x, lane);
+  return x;
 }
 
 __device__ __forceinline__ bool wave_all(bool p) { return __all(p); }
@@ -86,12 +172,13 @@ __device__ __forceinline__ void pattern_of(int lane, float& u, float& v, float& 
 }
 
 struct Level {
-  const uint8_t* p;
+  gbytes p;
   int pitch, w, h;
 };
 
+// x in [0, W-1] and y in [0, H-1], without short-circuit branches
 __device__ __forceinline__ bool in_dom(const Level& I, float x, float y) {
-  return x >= 0.f && x <= (float)(I.w - 1) && y >= 0.f && y <= (float)(I.h - 1);
+  return (x >= 0.f) & (x <= (float)(I.w - 1)) & (y >= 0.f) & (y <= (float)(I.h - 1));
 }
 
 // bilinear interpolation on [0, W-1] x [0, H-1]: ix = min(floor(x), W-2),
@@ -99,15 +186,43 @@ __device__ __forceinline__ bool in_dom(const Level& I, float x, float y) {
 __device__ __forceinline__ float bilinear(const Level& I, float x, float y) {
   const int ix = min((int)floorf(x), I.w - 2), iy = min((int)floorf(y), I.h - 2);
   const float fx = x - (float)ix, fy = y - (float)iy;
-  const uint8_t* q = I.p + (size_t)iy * I.pitch + ix;
-  const float a = q[0], b = q[1], c = q[I.pitch], d = q[I.pitch + 1];
+  const uint32_t o = (uint32_t)(iy * I.pitch + ix);
+  const uint32_t r0 = ld16(I.p, o), r1 = ld16(I.p, o + (uint32_t)I.pitch);
+  const float a = (float)(r0 & 0xFFu), b = (float)(r0 >> 8), c = (float)(r1 & 0xFFu), d = (float)(r1 >> 8);
   return (1.f - fy) * ((1.f - fx) * a + fx * b) + fy * ((1.f - fx) * c + fx * d);
+}
+
+// Template samples at (x, y): I(x, y) and the central differences
+// (I(x+1, y) - I(x-1, y)) / 2, (I(x, y+1) - I(x, y-1)) / 2, all bilinear as
+// above. The caller has checked that x +- 1 and y +- 1 lie in the domain, so
+// floor(x) - 1 >= 0 and floor(y) - 1 >= 0. The five samples share the 4x4
+// window from (floor(x) - 1, floor(y) - 1) and the fractions of (x, y). At
+// x = W-2 exactly the right sample's clamped form (ix = W-2, fx = 1) equals
+// this one (ix = W-1, fx = 0), and the window's last column (x = W) enters
+// with weight 0; likewise y = H-2 and the window's last row (y = H): each
+// level buffer has a guard row, so these reads stay inside it.
+__device__ __forceinline__ void template_samples(const Level& I, float x, float y, float& i0, float& gx, float& gy) {
+  const int fxi = (int)floorf(x), fyi = (int)floorf(y);
+  const float fx = x - (float)fxi, fy = y - (float)fyi;
+  const uint32_t o = (uint32_t)((fyi - 1) * I.pitch + (fxi - 1));
+  const uint32_t pt = (uint32_t)I.pitch;
+  const uint32_t w0 = ld32(I.p, o), w1 = ld32(I.p, o + pt), w2 = ld32(I.p, o + 2u * pt), w3 = ld32(I.p, o + 3u * pt);
+  const float gfx = 1.f - fx, gfy = 1.f - fy;
+  auto px = [](uint32_t w, int c) { return (float)((w >> (8 * c)) & 0xFFu); };
+  auto h = [&](uint32_t w, int c) { return gfx * px(w, c) + fx * px(w, c + 1); };
+  const float h01 = h(w0, 1), h10 = h(w1, 0), h11 = h(w1, 1), h12 = h(w1, 2);
+  const float h20 = h(w2, 0), h21 = h(w2, 1), h22 = h(w2, 2), h31 = h(w3, 1);
+  i0 = gfy * h11 + fy * h21;
+  const float ixp = gfy * h12 + fy * h22, ixm = gfy * h10 + fy * h20;
+  const float iyp = gfy * h21 + fy * h31, iym = gfy * h01 + fy * h11;
+  gx = (ixp - ixm) * 0.5f;
+  gy = (iyp - iym) * 0.5f;
 }
 
 // level l of pyramid slot `slot` of camera `cd` (scalar loads from the descriptor)
 __device__ __forceinline__ Level level_of(const CamDesc& cd, int slot, int l) {
   Level L;
-  L.p = cd.lvl[slot][l];
+  L.p = (gbytes)cd.lvl[slot][l];
   L.pitch = cd.pitch[l];
   L.w = cd.w >> l;
   L.h = cd.h >> l;
@@ -133,85 +248,85 @@ __device__ __forceinline__ void se2_v(float phi, float& a, float& b) {
   }
 }
 
-// One coarse-to-fine pass: template on `src` at (px, py), warp from (ix, iy,
-// ith), N Gauss-Newton iterations per level, levels L-1 .. 0, translation
-// doubled between levels, a level whose template does not fit is skipped.
+// One coarse-to-fine pass over the first nl <= L levels: template on `src` at
+// (px, py), warp from (ix, iy, ith) (level-0 pixels), N Gauss-Newton
+// iterations per level, levels nl-1 .. 0, translation doubled between levels,
+// a level whose template does not fit is skipped.
 template <int L>
-__device__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px, float py,
-                            float ix, float iy, float ith, int N, float u, float v, float wgt) {
+__device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px,
+                                            float py, float ix, float iy, float ith, int nl, int N, float u, float v,
+                                            float wgt, int lane) {
   PassOut o{VIO_TRACKED, 0.f, 0.f, 0.f, 0.f};
   // ---- templates of all levels (Sec. III-E) ------------------------------
   bool fits[L], valid[L];
-  float T[L], G0[L], G1[L], G2[L], k0[L], k1[L], k2[L];
+  float T[L], G0[L], G1[L], G2[L], k[3 * L];
   float I0[L], gxr[L], gyr[L];
 #pragma unroll
   for (int l = 0; l < L; ++l) {
-    const Level S = level_of(csrc, ssrc, l);
-    const float sc = 1.f / (float)(1 << l);
-    const float sx = px * sc + u, sy = py * sc + v;
-    fits[l] = wave_all(in_dom(S, sx - 1.f, sy) && in_dom(S, sx + 1.f, sy) && in_dom(S, sx, sy - 1.f) &&
-                       in_dom(S, sx, sy + 1.f));
+    fits[l] = false;
     I0[l] = gxr[l] = gyr[l] = 0.f;
-    if (fits[l]) {
-      I0[l] = bilinear(S, sx, sy);
-      gxr[l] = (bilinear(S, sx + 1.f, sy) - bilinear(S, sx - 1.f, sy)) * 0.5f;
-      gyr[l] = (bilinear(S, sx, sy + 1.f) - bilinear(S, sx, sy - 1.f)) * 0.5f;
+    if (l < nl) {
+      const Level S = level_of(csrc, ssrc, l);
+      const float sc = 1.f / (float)(1 << l);
+      const float sx = px * sc + u, sy = py * sc + v;
+      fits[l] = wave_all(in_dom(S, sx - 1.f, sy) & in_dom(S, sx + 1.f, sy) & in_dom(S, sx, sy - 1.f) &
+                         in_dom(S, sx, sy + 1.f));
+      if (fits[l]) template_samples(S, sx, sy, I0[l], gxr[l], gyr[l]);
     }
   }
   float mean[L];
 #pragma unroll
-  for (int l = 0; l < L; ++l) mean[l] = wave_sum(wgt * I0[l]) * (1.f / 52.f);
-  float J0[L], J1[L], J2[L];
+  for (int l = 0; l < L; ++l) mean[l] = wgt * I0[l];
+  wave_sums<L>(mean, lane);
+  float J0[L], J1[L], J2[L], hs[6 * L];
 #pragma unroll
   for (int l = 0; l < L; ++l) {
+    mean[l] *= 1.f / 52.f;
     const float im = rcp(mean[l]);
     T[l] = I0[l] * im;
     J0[l] = gxr[l] * im;
     J1[l] = gyr[l] * im;
     J2[l] = J1[l] * u - J0[l] * v;
+    hs[6 * l + 0] = wgt * J0[l] * J0[l];
+    hs[6 * l + 1] = wgt * J0[l] * J1[l];
+    hs[6 * l + 2] = wgt * J0[l] * J2[l];
+    hs[6 * l + 3] = wgt * J1[l] * J1[l];
+    hs[6 * l + 4] = wgt * J1[l] * J2[l];
+    hs[6 * l + 5] = wgt * J2[l] * J2[l];
   }
-  float h00[L], h01[L], h02[L], h11[L], h12[L], h22[L];
+  wave_sums<6 * L>(hs, lane);
 #pragma unroll
   for (int l = 0; l < L; ++l) {
-    h00[l] = wave_sum(wgt * J0[l] * J0[l]);
-    h01[l] = wave_sum(wgt * J0[l] * J1[l]);
-    h02[l] = wave_sum(wgt * J0[l] * J2[l]);
-    h11[l] = wave_sum(wgt * J1[l] * J1[l]);
-    h12[l] = wave_sum(wgt * J1[l] * J2[l]);
-    h22[l] = wave_sum(wgt * J2[l] * J2[l]);
-  }
-#pragma unroll
-  for (int l = 0; l < L; ++l) {
+    const float h00 = hs[6 * l + 0], h01 = hs[6 * l + 1], h02 = hs[6 * l + 2];
+    const float h11 = hs[6 * l + 3], h12 = hs[6 * l + 4], h22 = hs[6 * l + 5];
     // 3x3 inverse by cofactors (H symmetric); degenerate when det <= 1e-6 (tr/3)^3
-    const float c00 = h11[l] * h22[l] - h12[l] * h12[l];
-    const float c01 = h12[l] * h02[l] - h01[l] * h22[l];
-    const float c02 = h01[l] * h12[l] - h11[l] * h02[l];
-    const float det = h00[l] * c00 + h01[l] * c01 + h02[l] * c02;
-    const float tr3 = (h00[l] + h11[l] + h22[l]) * (1.f / 3.f);
+    const float c00 = h11 * h22 - h12 * h12;
+    const float c01 = h12 * h02 - h01 * h22;
+    const float c02 = h01 * h12 - h11 * h02;
+    const float det = h00 * c00 + h01 * c01 + h02 * c02;
+    const float tr3 = (h00 + h11 + h22) * (1.f / 3.f);
     const float id = rcp(det);
     const float i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
-    const float i11 = (h00[l] * h22[l] - h02[l] * h02[l]) * id;
-    const float i12 = (h02[l] * h01[l] - h00[l] * h12[l]) * id;
-    const float i22 = (h00[l] * h11[l] - h01[l] * h01[l]) * id;
+    const float i11 = (h00 * h22 - h02 * h02) * id;
+    const float i12 = (h02 * h01 - h00 * h12) * id;
+    const float i22 = (h00 * h11 - h01 * h01) * id;
     // weight folded into the gains: lanes 52..63 contribute nothing
     G0[l] = wgt * (i00 * J0[l] + i01 * J1[l] + i02 * J2[l]);
     G1[l] = wgt * (i01 * J0[l] + i11 * J1[l] + i12 * J2[l]);
     G2[l] = wgt * (i02 * J0[l] + i12 * J1[l] + i22 * J2[l]);
     valid[l] = mean[l] > 0.f && det > 1e-6f * tr3 * tr3 * tr3 &&
-               wave_all(isfinite(G0[l]) && isfinite(G1[l]) && isfinite(G2[l]));
+               wave_all(isfinite(G0[l]) & isfinite(G1[l]) & isfinite(G2[l]));
+    k[3 * l + 0] = G0[l] * T[l];
+    k[3 * l + 1] = G1[l] * T[l];
+    k[3 * l + 2] = G2[l] * T[l];
   }
-#pragma unroll
-  for (int l = 0; l < L; ++l) {
-    k0[l] = wave_sum(G0[l] * T[l]);
-    k1[l] = wave_sum(G1[l] * T[l]);
-    k2[l] = wave_sum(G2[l] * T[l]);
-  }
+  wave_sums<3 * L>(k, lane);
   // ---- coarse-to-fine Gauss-Newton (eqs. 4-5) ------------------------------
-  const float s0 = 1.f / (float)(1 << (L - 1));
-  float tx = ix * s0, ty = iy * s0, th = ith;
+  float tx = ldexpf(ix, 1 - nl), ty = ldexpf(iy, 1 - nl), th = ith;
 #pragma unroll
   for (int l = L - 1; l >= 0; --l) {
-    if (l < L - 1) {
+    if (l >= nl) continue;
+    if (l < nl - 1) {
       tx = tx * 2.f;
       ty = ty * 2.f;
     }
@@ -235,9 +350,9 @@ __device__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, 
         return o;
       }
       const float Iw = bilinear(D, wx, wy);
-      const float S0 = wave_sum(wgt * Iw);
-      const float S1 = wave_sum(G0[l] * Iw), S2 = wave_sum(G1[l] * Iw), S3 = wave_sum(G2[l] * Iw);
-      const float mw = S0 * (1.f / 52.f);
+      float S[4] = {wgt * Iw, G0[l] * Iw, G1[l] * Iw, G2[l] * Iw};
+      wave_sums<4>(S, lane);
+      const float mw = S[0] * (1.f / 52.f);
       if (!(mw > 0.f)) {
         o.status = VIO_LOST_OOB;
         return o;
@@ -245,9 +360,9 @@ __device__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, 
       const float imw = rcp(mw);
       if (l == 0 && it == N - 1) {
         const float e = Iw * imw - T[l];
-        o.resid = sqrtf(wave_sum(wgt * e * e) * (1.f / 52.f));
+        o.resid = sqrtf(wave_sum(wgt * e * e, lane) * (1.f / 52.f));
       }
-      const float d0 = k0[l] - S1 * imw, d1 = k1[l] - S2 * imw, d2 = k2[l] - S3 * imw;
+      const float d0 = k[3 * l + 0] - S[1] * imw, d1 = k[3 * l + 1] - S[2] * imw, d2 = k[3 * l + 2] - S[3] * imw;
       float a, b;
       se2_v(d2, a, b);
       const float vx = a * d0 - b * d1, vy = b * d0 + a * d1;
@@ -262,9 +377,13 @@ __device__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, 
   return o;
 }
 
+// Forward pass src -> dst from (ix, iy), then the backward pass dst -> src
+// from the keypoint's own position, over nl levels with N iterations; both
+// passes run the one inlined copy of the alignment code.
 template <int L>
-__device__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px, float py,
-                             float ix, float iy, int N, float fb_thr, float u, float v, float wgt) {
+__device__ __forceinline__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px,
+                                             float py, float ix, float iy, int nl, int N, float fb_thr, float u,
+                                             float v, float wgt, int lane) {
   TrackRes r;
   r.x = ix;
   r.y = iy;
@@ -273,23 +392,39 @@ __device__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst,
   r.resid = 0.f;
   r.status = VIO_TRACKED;
   r.pad[0] = r.pad[1] = 0;
-  const PassOut f = klt_pass<L>(csrc, ssrc, cdst, sdst, px, py, ix, iy, 0.f, N, u, v, wgt);
-  if (f.status != VIO_TRACKED) {
-    r.status = f.status;
-    return r;
+  const CamDesc* A = &csrc;
+  const CamDesc* B = &cdst;
+  int sa = ssrc, sb = sdst;
+  float qx = px, qy = py, gx = ix, gy = iy, gth = 0.f;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    const PassOut o = klt_pass<L>(*A, sa, *B, sb, qx, qy, gx, gy, gth, nl, N, u, v, wgt, lane);
+    if (o.status != VIO_TRACKED) {
+      r.status = o.status;
+      break;
+    }
+    if (pass == 0) {
+      r.x = o.tx;
+      r.y = o.ty;
+      r.theta = o.th;
+      r.resid = o.resid;
+      const CamDesc* t = A;
+      A = B;
+      B = t;
+      const int st = sa;
+      sa = sb;
+      sb = st;
+      qx = o.tx;
+      qy = o.ty;
+      gx = px;
+      gy = py;
+      gth = -o.th;
+    } else {
+      const float dx = o.tx - px, dy = o.ty - py;
+      r.fb = sqrtf(dx * dx + dy * dy);
+      r.status = r.fb > fb_thr ? VIO_LOST_FB : VIO_TRACKED;
+    }
   }
-  r.x = f.tx;
-  r.y = f.ty;
-  r.theta = f.th;
-  r.resid = f.resid;
-  const PassOut b = klt_pass<L>(cdst, sdst, csrc, ssrc, f.tx, f.ty, px, py, -f.th, N, u, v, wgt);
-  if (b.status != VIO_TRACKED) {
-    r.status = b.status;
-    return r;
-  }
-  const float dx = b.tx - px, dy = b.ty - py;
-  r.fb = sqrtf(dx * dx + dy * dy);
-  r.status = r.fb > fb_thr ? VIO_LOST_FB : VIO_TRACKED;
   return r;
 }
 
@@ -313,15 +448,17 @@ __device__ __forceinline__ void store_result(TrackRes* dst, const TrackRes& r, i
 }
 
 // One work item: a temporal track (camera c, slot j) or the stereo match of a
-// cell winner (camera c, cell j). LL > 0: learned initialisation -- temporal
-// tracks run LL levels from the network's guess and fall back to the plain
-// L-level tracker from the constant-velocity guess unless kept with a
-// residual RMS <= rho.
-template <int L, int LL>
-__device__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
-                             const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs, int n_segs,
-                             const Prediction* __restrict__ pred, const Tuning& tune, int item, int lane, float u,
-                             float v, float wgt) {
+// detection (camera c, item j). With learned initialisation (tune.learned), a
+// temporal track without a caller prediction first runs tune.llevels levels
+// with tune.liters iterations from the network's guess and is kept when it
+// passes the forward-backward check with a residual RMS <= rho; otherwise the
+// plain tracker runs from the constant-velocity guess (pad[0] = 1 marks that
+// fallback).
+template <int L>
+__device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
+                                             const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
+                                             int n_segs, const Prediction* __restrict__ pred, const Tuning& tune,
+                                             int item, int lane, float u, float v, float wgt) {
   // the last segment that begins at or before the item (begins ascend)
   int lo = 0, hi = n_segs - 1;
   while (lo < hi) {
@@ -337,10 +474,19 @@ __device__ void process_item(const CamDesc* __restrict__ cams, const FrameTable*
   const FrameCam& fc = frame->cam[c];
   if (!fc.active) return;
   const int P = fc.parity;
+  const CamDesc* src = &cd;
+  const CamDesc* dst;
+  int ssrc, sdst;
+  float px, py, ix, iy, gx = 0.f, gy = 0.f;
+  bool try_learned = false;
+  TrackRes* out;
   if (sg.mode == kModeTemporal) {
     if (!fc.has_prev || j >= cnt->n_live[P ^ 1][c]) return;
     const Kp kp = cd.state[P ^ 1][j];
-    float ix = kp.x + (kp.x - kp.px), iy = kp.y + (kp.y - kp.py);
+    px = kp.x;
+    py = kp.y;
+    ix = kp.x + (kp.x - kp.px);
+    iy = kp.y + (kp.y - kp.py);
     bool predicted = false;
     const int np = fc.n_pred;
     if (np > 0) {  // caller predictions, ascending id: binary search
@@ -359,46 +505,57 @@ __device__ void process_item(const CamDesc* __restrict__ cams, const FrameTable*
         else hi = mid - 1;
       }
     }
-    TrackRes r;
-    bool done = false;
-    if constexpr (LL > 0) {
-      if (!predicted) {
-        const float* gs = tune.guess + (size_t)(cd.row_off + j) * 3;
-        const float gx = kp.x + 16.f * gs[0], gy = kp.y + 16.f * gs[1];
-        r = track_fb<LL>(cd, P ^ 1, cd, P, kp.x, kp.y, gx, gy, tune.liters, tune.fb_threshold, u, v, wgt);
-        done = r.status == VIO_TRACKED && r.resid <= tune.rho;
-      }
+    if (tune.learned && !predicted) {
+      const float* gs = tune.guess + (size_t)(cd.row_off + j) * 3;
+      gx = kp.x + 16.f * gs[0];
+      gy = kp.y + 16.f * gs[1];
+      try_learned = true;
     }
-    if (!done) {
-      r = track_fb<L>(cd, P ^ 1, cd, P, kp.x, kp.y, ix, iy, tune.iters, tune.fb_threshold, u, v, wgt);
-      r.pad[0] = (LL > 0 && !predicted) ? 1 : 0;
-    }
-    store_result(cd.res + j, r, lane);
+    dst = &cd;
+    ssrc = P ^ 1;
+    sdst = P;
+    out = cd.res + j;
   } else {
     // stereo match of a detection: speculative (item j = cell j's winner) or
     // deferred (item j = the frame's j-th selected detection)
-    float x, y;
     if (tune.deferred) {
       if (j >= cnt->n_sel[c]) return;
       const Kp kp = cd.state[P][cnt->sel_base[c] + j];
-      x = kp.x;
-      y = kp.y;
+      px = kp.x;
+      py = kp.y;
     } else {
       const uint32_t key = cd.keys[P][j];
       if (key == 0) return;
       const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
-      x = (float)(idx % cd.w);
-      y = (float)(idx / cd.w);
+      px = (float)(idx % cd.w);
+      py = (float)(idx / cd.w);
     }
-    TrackRes r = track_fb<L>(cd, P, cams[cd.partner], P, x, y, x - tune.disparity0, y, tune.iters,
-                             tune.fb_threshold, u, v, wgt);
-    r.pad[0] = 0;
-    store_result(cd.sres + j, r, lane);
+    ix = px - tune.disparity0;
+    iy = py;
+    dst = &cams[cd.partner];
+    ssrc = P;
+    sdst = P;
+    out = cd.sres + j;
   }
+  TrackRes r;
+  int fell_back = 0;
+#pragma unroll 1
+  for (int a = try_learned ? 0 : 1; a < 2; ++a) {
+    const bool short_run = a == 0;
+    r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy,
+                    short_run ? tune.llevels : tune.levels, short_run ? tune.liters : tune.iters, tune.fb_threshold,
+                    u, v, wgt, lane);
+    if (short_run) {
+      if (r.status == VIO_TRACKED && r.resid <= tune.rho) break;
+      fell_back = 1;
+    }
+  }
+  r.pad[0] = fell_back;
+  store_result(out, r, lane);
 }
 
 // One wave per work item.
-template <int L, int LL>
+template <int L>
 __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __restrict__ cams,
                                                           const FrameTable* __restrict__ frame,
                                                           const Counters* __restrict__ cnt,
@@ -410,7 +567,7 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
   if (k >= n_items) return;
   float u, v, wgt;
   pattern_of(lane, u, v, wgt);
-  process_item<L, LL>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
+  process_item<L>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
 }
 
 // Persistent grid: every wave pops items from the frame's queue counter until
@@ -418,7 +575,7 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
 // The pop is branch-free: all lanes issue the atomic, lane 0 adding one and
 // the others zero, and the first lane's (lane 0's) old value is the item, so
 // no lane-dependent control flow enters the loop.
-template <int L, int LL>
+template <int L>
 __global__ __launch_bounds__(kW* kTrackWaves) void k_track_persistent(const CamDesc* __restrict__ cams,
                                                                      FrameTable* __restrict__ frame,
                                                                      const Counters* __restrict__ cnt,
@@ -432,38 +589,25 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track_persistent(const CamD
   for (;;) {
     const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&frame->queue_head[queue], lane == 0 ? 1 : 0));
     if (k >= n_items) break;
-    process_item<L, LL>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
+    process_item<L>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
   }
 }
 
-template <int L, int LL>
+template <int L>
 hipError_t launch_L(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
                     int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape sh, hipStream_t s) {
   const int bw = sh.block_waves;
   if (sh.waves_per_cu > 0) {
     const int waves = std::min(n_items, sh.waves_per_cu * sh.n_cus);
     const int blocks = (waves + bw - 1) / bw;
-    launch_kernel(k_track_persistent<L, LL>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs,
-                  n_segs, item_base, n_items, d_pred, tune, sh.queue);
+    launch_kernel(k_track_persistent<L>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
+                  item_base, n_items, d_pred, tune, sh.queue);
   } else {
     const int blocks = (n_items + bw - 1) / bw;
-    launch_kernel(k_track<L, LL>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
-                       item_base, n_items, d_pred, tune);
+    launch_kernel(k_track<L>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs, item_base,
+                  n_items, d_pred, tune);
   }
   return hipGetLastError();
-}
-
-template <int L>
-hipError_t launch_LL(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
-                     int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape sh, hipStream_t s) {
-  const int ll = tune.learned ? tune.llevels : 0;
-  switch (ll) {
-    case 0: return launch_L<L, 0>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
-    case 1: return launch_L<L, 1>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
-    case 2: return launch_L<L, 2>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
-    case 3: return launch_L<L, 3>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 }  // namespace
@@ -475,9 +619,11 @@ hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_
   if (shape.block_waves < 1 || shape.block_waves > kTrackWaves || shape.n_cus < 1 || shape.waves_per_cu < 0 ||
       shape.queue < 0 || shape.queue >= 4)
     return hipErrorInvalidValue;
+  // the short tracker of learned initialisation runs within the full one's levels
+  if (tune.learned && (tune.llevels < 1 || tune.llevels > tune.levels || tune.liters < 1)) return hipErrorInvalidValue;
   switch (tune.levels) {
 #define VIO_TRACK_CASE(LV) \
-  case LV: return launch_LL<LV>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, shape, s);
+  case LV: return launch_L<LV>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, shape, s);
     VIO_TRACK_CASE(1)
     VIO_TRACK_CASE(2)
     VIO_TRACK_CASE(3)
