@@ -5,7 +5,8 @@
 // images, chosen per workload at create). It stages
 // the tile plus an apron in LDS with coalesced dword loads, then
 //  * computes the FAST-9 score (Sec. III-D) of the tile and a one-pixel ring
-//    (the paper's early rejection on ring pairs (0,8)/(4,12), then the score,
+//    (the paper's early rejection on ring pairs (0,8)/(4,12) over every pixel,
+//    the survivors compacted into an LDS list, then the score over the list,
 //    both polarities at once in 16-bit halves), keeps strict 3x3 maxima with
 //    score >= the last threshold and folds each into its cell's packed key
 //    with one atomicMax, and
@@ -43,6 +44,14 @@ struct PyrGeom {
   static constexpr int sw0 = ((T + a0x + a0) + 3) & ~3;
   static constexpr int sh0 = T + 2 * a0;
   static constexpr int vbytes = L > 1 ? (region(0) - 1) * region(1) : 1;
+  // the paired horizontal pass reads three dwords from byte 4q of a level-0
+  // row: bytes up to 2 region(1) + 7 stay inside the staged row
+  static_assert(L == 1 || 2 * region(1) + 8 <= sw0, "staged level-0 row too short for the paired pass");
+  // byte offset of input column 2 o_x - 2 (o_x: level-1 region origin) in
+  // its dword of a staged level-0 row; above level 0 the region origins nest
+  // and the offset is 0
+  static constexpr int h_shift0 = a0x - apron(0);
+  static_assert(L == 1 || (h_shift0 >= 0 && h_shift0 < 4), "paired pass byte shift");
   static constexpr int lvl_bytes = L > 1 ? region(1) * region(1) : 1;
 };
 
@@ -73,10 +82,13 @@ __device__ __forceinline__ void ring_diffs(const uint8_t* img, int o, int sp, in
 
 // The paper's early rejection (Sec. III-D): every 9-arc holds one of the ring
 // positions 0 and 8 and one of 4 and 12, so a corner at threshold tmin needs
-// such a pair brighter than I(p) + tmin or darker than I(p) - tmin.
-__device__ __forceinline__ bool fast_may_pass(const int d[16], int tmin) {
-  const bool bright = (d[0] > tmin || d[8] > tmin) && (d[4] > tmin || d[12] > tmin);
-  const bool dark = (d[0] < -tmin || d[8] < -tmin) && (d[4] < -tmin || d[12] < -tmin);
+// such a pair brighter than I(p) + tmin or darker than I(p) - tmin. Reads the
+// centre and the four ring positions 0, 4, 8, 12 only.
+__device__ __forceinline__ bool fast_may_pass(const uint8_t* img, int o, int sp, int tmin) {
+  const int c = img[o];
+  const int d0 = img[o - 3 * sp] - c, d4 = img[o + 3] - c, d8 = img[o + 3 * sp] - c, d12 = img[o - 3] - c;
+  const bool bright = (d0 > tmin || d8 > tmin) && (d4 > tmin || d12 > tmin);
+  const bool dark = (d0 < -tmin || d8 < -tmin) && (d4 < -tmin || d12 < -tmin);
   return bright || dark;
 }
 
@@ -103,6 +115,38 @@ __device__ __forceinline__ int fast_score(const int d[16]) {
   return max(max((int)best.x, (int)best.y) - 1, -1);
 }
 
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t* s_v32(uint16_t* p) { return reinterpret_cast<uint32_t*>(p); }
+
+// eq. (2) for two adjacent outputs: with input bytes x0..x6 (x_k = byte k of
+// a, then b), out = (x0 + 4 x1 + 6 x2 + 4 x3 + x4, x2 + 4 x3 + 6 x4 + 4 x5 + x6)
+// in the low and high 16-bit halves (each at most 16 * 255).
+__device__ __forceinline__ uint32_t pyr_h_pair(uint32_t a, uint32_t b) {
+  // v_perm_b32 selectors over (b:a): bytes 0..3 of a are 0..3, of b 4..7; 0x0C gives zero
+  const ushort2v p0 = __builtin_bit_cast(ushort2v, __builtin_amdgcn_perm(b, a, 0x0C020C00u));  // x0, x2
+  const ushort2v p1 = __builtin_bit_cast(ushort2v, __builtin_amdgcn_perm(b, a, 0x0C030C01u));  // x1, x3
+  const ushort2v p2 = __builtin_bit_cast(ushort2v, __builtin_amdgcn_perm(b, a, 0x0C040C02u));  // x2, x4
+  const ushort2v p3 = __builtin_bit_cast(ushort2v, __builtin_amdgcn_perm(b, a, 0x0C050C03u));  // x3, x5
+  const ushort2v p4 = __builtin_bit_cast(ushort2v, __builtin_amdgcn_perm(b, a, 0x0C060C04u));  // x4, x6
+  const ushort2v four = {4, 4}, six = {6, 6};
+  const ushort2v s = (p0 + p4) + four * (p1 + p3) + six * p2;
+  return __builtin_bit_cast(uint32_t, s);
+}
+
+// eq. (3) for two adjacent columns: five rows of packed horizontal sums,
+// (r0 + 4 r1 + 6 r2 + 4 r3 + r4 + 128) >> 8 per half (at most 16 * 4080 + 128,
+// which fits 16 bits), returned as two bytes in the low 16 bits.
+__device__ __forceinline__ uint32_t pyr_v_pair(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t r4) {
+  const ushort2v v0 = __builtin_bit_cast(ushort2v, r0), v1 = __builtin_bit_cast(ushort2v, r1);
+  const ushort2v v2 = __builtin_bit_cast(ushort2v, r2), v3 = __builtin_bit_cast(ushort2v, r3);
+  const ushort2v v4 = __builtin_bit_cast(ushort2v, r4);
+  const ushort2v four = {4, 4}, six = {6, 6}, half = {128, 128}, eight = {8, 8};
+  const ushort2v s = ((v0 + v4) + four * (v1 + v3) + six * v2 + half) >> eight;
+  const uint32_t w = __builtin_bit_cast(uint32_t, s);
+  return (w & 0xFFu) | ((w >> 8) & 0xFF00u);
+}
+
 template <int L, int T>
 __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDesc* __restrict__ cams,
                                                                       const FrameTable* __restrict__ frame,
@@ -115,8 +159,10 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   constexpr int kScoreEdge = G::score_edge;
   __shared__ __align__(16) uint8_t s_l0[G::sh0 * G::sw0];
   __shared__ uint8_t s_score[kScoreEdge * kScoreEdge];
-  __shared__ uint16_t s_v[G::vbytes];
-  __shared__ uint8_t s_lv[2][G::lvl_bytes];
+  __shared__ uint16_t s_cand[kScoreEdge * kScoreEdge];  // pixels past the early rejection
+  __shared__ int s_ncand;
+  __shared__ __align__(16) uint16_t s_v[G::vbytes];
+  __shared__ __align__(16) uint8_t s_lv[2][G::lvl_bytes];
 
   const int gtile = tile_base + (int)blockIdx.x;
   int c = cam_begin;
@@ -151,6 +197,7 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
     }
     *reinterpret_cast<uint32_t*>(&s_l0[r * G::sw0 + 4 * q]) = v;
   }
+  if (tid == 0) s_ncand = 0;
   __syncthreads();
 
   // ---- copy level 0 into the own pyramid when it came from outside --------
@@ -172,27 +219,48 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
 
   // ---- FAST-9 + strict NMS + per-cell key ---------------------------------
   // Scores of the tile and its one-pixel ring (0: below the last threshold).
+  // The early rejection runs over every pixel and appends the survivors (about
+  // a quarter of a textured image) to a list; the full score then runs over
+  // the list, so a wave scores 64 survivors at a time instead of running the
+  // score for every wave that holds one.
   if (cd.detect) {
+    const int lane = tid & 63;
     for (int i = tid; i < kScoreEdge * kScoreEdge; i += kPyrThreads) {
       const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
-      int sc = 0;
-      if (sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin) {
-        int d[16];
-        ring_diffs(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, d);
-        if (fast_may_pass(d, tmin)) {
-          const int score = fast_score(d);
-          sc = score >= tmin ? score + 1 : 0;
-        }
+      const bool cand = sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin &&
+                        fast_may_pass(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, tmin);
+      s_score[i] = 0;
+      // one LDS atomic per wave reserves the wave's slots
+      const uint64_t m = __ballot(cand);
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&s_ncand, __popcll(m));
+        base = __builtin_amdgcn_readlane(base, leader);
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (cand) s_cand[base + below] = (uint16_t)i;
       }
-      s_score[i] = (uint8_t)sc;
     }
     __syncthreads();
+    const int ncand = s_ncand;
+    for (int j = tid; j < ncand; j += kPyrThreads) {
+      const int i = s_cand[j];
+      const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
+      int d[16];
+      ring_diffs(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, d);
+      const int score = fast_score(d);
+      s_score[i] = (uint8_t)(score >= tmin ? score + 1 : 0);
+    }
+    __syncthreads();
+    // strict 3x3 maxima: only listed pixels can hold a nonzero score
     uint32_t* keys = cd.keys[par];
-    for (int i = tid; i < kTile * kTile; i += kPyrThreads) {
-      const int ly = i / kTile, lx = i % kTile;
+    for (int j = tid; j < ncand; j += kPyrThreads) {
+      const int i = s_cand[j];
+      const int ly = i / kScoreEdge - 1, lx = i % kScoreEdge - 1;
+      if (lx < 0 || lx >= kTile || ly < 0 || ly >= kTile) continue;  // the ring around the tile
       const int x = x0 + lx, y = y0 + ly;
       if (x < margin || x > W - 1 - margin || y < margin || y > H - 1 - margin) continue;
-      const uint8_t* sc = &s_score[(ly + 1) * kScoreEdge + lx + 1];
+      const uint8_t* sc = &s_score[i];
       const int s = sc[0];
       if (!s) continue;
       const bool peak = s > sc[-kScoreEdge - 1] && s > sc[-kScoreEdge] && s > sc[-kScoreEdge + 1] && s > sc[-1] &&
@@ -220,7 +288,46 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
       // the index split is a multiply-shift) and skip columns outside the image
       // block-uniform: a level with nothing inside the image ends the tile
       if (X0 > X1 || Y0 > Y1) break;
-      {
+      // a region wholly inside the image with every filter tap inside level l
+      // (no clamping) runs two outputs per thread in packed 16-bit halves
+      const bool paired = G::region(l) % 4 == 0 && S % 4 == 0 && (kTile >> (l + 1)) % 2 == 0 && X0 == o_x &&
+                          X1 == o_x + S - 1 && 2 * o_x - 2 >= 0 &&
+                          2 * X1 + 2 <= Wc - 1 && 2 * Y0 - 2 >= 0 && 2 * Y1 + 2 <= Hc - 1;
+      if (paired) {
+        const int shift = l == 0 ? G::h_shift0 : 0;
+        const int npair = S / 2;
+        // eq. (2): outputs X, X+1 from input bytes 2X-2 .. 2X+4
+        const int nv = (vy1 - vy0 + 1) * npair;
+        for (int i = tid; i < nv; i += kPyrThreads) {
+          const int r = i / npair, q = i - r * npair;
+          const uint32_t* w = reinterpret_cast<const uint32_t*>(cur + (vy0 + r - cur_oy) * cur_p) + q;
+          const uint32_t d0 = w[0], d1 = w[1], d2 = shift != 0 ? w[2] : 0u;
+          const uint32_t a = __builtin_amdgcn_alignbyte(d1, d0, shift);  // bytes 0..3 of the window
+          const uint32_t b = __builtin_amdgcn_alignbyte(d2, d1, shift);  // bytes 4..7
+          s_v32(s_v)[r * npair + q] = pyr_h_pair(a, b);
+        }
+        __syncthreads();
+        // eq. (3): +128 then >> 8, two columns per thread
+        uint8_t* nxt = s_lv[l & 1];
+        uint8_t* gdst = cd.lvl[par][l + 1];
+        const int gp = cd.pitch[l + 1];
+        const int tx0 = x0 >> (l + 1), ty0 = y0 >> (l + 1), te = kTile >> (l + 1);
+        const int nn = (Y1 - Y0 + 1) * npair;
+        for (int i = tid; i < nn; i += kPyrThreads) {
+          const int Y = Y0 + i / npair, q = i % npair;
+          const uint32_t* col = s_v32(s_v) + (2 * Y - 2 - vy0) * npair + q;
+          const uint32_t v2 = pyr_v_pair(col[0], col[npair], col[2 * npair], col[3 * npair], col[4 * npair]);
+          const int X = o_x + 2 * q;
+          *reinterpret_cast<uint16_t*>(&nxt[(Y - o_y) * S + 2 * q]) = (uint16_t)v2;
+          if (X >= tx0 && X < tx0 + te && Y >= ty0 && Y < ty0 + te)
+            *reinterpret_cast<uint16_t*>(&gdst[(size_t)Y * gp + X]) = (uint16_t)v2;
+        }
+        __syncthreads();
+        cur = nxt;
+        cur_ox = o_x;
+        cur_oy = o_y;
+        cur_p = S;
+      } else {
         // eq. (2): horizontal pass over level-l rows vy0..vy1
         const int nv = (vy1 - vy0 + 1) * S;
         for (int i = tid; i < nv; i += kPyrThreads) {
