@@ -35,31 +35,51 @@ namespace {
 constexpr int kWaves = kSelectThreads / 64;
 
 struct ScanScratch {
-  int wave_tot[kWaves];
-  int wave_off[kWaves + 1];
+  int wave_tot[2][kWaves];
+};
+
+// A thread's handle on the block's scan scratch. Every thread makes the same
+// sequence of scan calls, so `tog` agrees across the block.
+struct Scan {
+  ScanScratch* sh;
+  int tog;
 };
 
 // Exclusive prefix count of `flag` over the block's threads in thread order;
 // returns the thread's offset and sets `total`. All threads must call it.
-__device__ __forceinline__ int block_scan_flag(bool flag, ScanScratch& sc, int& total) {
+// One barrier per call: the wave totals alternate between two buffers, and a
+// buffer is rewritten two calls later, which a thread reaches only after the
+// next call's barrier, i.e. after every thread has read this call's totals.
+__device__ __forceinline__ int block_scan_flag(bool flag, Scan& sc, int& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long m = __ballot(flag);
   const int below = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) sc.wave_tot[wave] = __popcll(m);
+  int* tot = sc.sh->wave_tot[sc.tog];
+  sc.tog ^= 1;
+  if (lane == 0) tot[wave] = __popcll(m);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      sc.wave_off[w] = acc;
-      acc += sc.wave_tot[w];
-    }
-    sc.wave_off[kWaves] = acc;
+  int off = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int t = tot[w];
+    off += w < wave ? t : 0;
+    all += t;
   }
-  __syncthreads();
-  const int r = sc.wave_off[wave] + below;
-  total = sc.wave_off[kWaves];
-  __syncthreads();
-  return r;
+  total = all;
+  return off + below;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
+// inside each 16-lane row, then row_bcast:15 and row_bcast:31 carry the row
+// totals forward (lanes without a source add the old value 0).
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+  return x;
 }
 
 __device__ __forceinline__ vio_track make_rec(int64_t id, int cam, int status, float x, float y, float th, float fb,
@@ -94,7 +114,7 @@ __device__ __forceinline__ Kp make_kp(int64_t id, float x, float y, float px, fl
 // of temporal tracking (all of them when there was no previous frame) in their
 // old order, with their records. Adds the survivors to `occ` when given.
 // Returns the survivor count; *n_rec receives the number of records written.
-__device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev, unsigned* occ, ScanScratch& sc,
+__device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev, unsigned* occ, Scan& sc,
                                int* n_rec, bool count_fallback) {
   const int P = fc.parity, Q = P ^ 1;
   int base = 0, n_fb = 0;
@@ -147,7 +167,7 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
 template <class SresOf>
 __device__ void accept_matches(const CamDesc& L, int P, int sel_base, const CamDesc& R, const FrameCam& fr,
                                int rc, int n_new, int n_surv_r, int n_rec_r, SresOf sres, Counters* cnt,
-                               ScanScratch& sc) {
+                               Scan& sc) {
   const int PR = fr.parity;
   int m_base = 0;
   for (int i0 = 0; i0 < n_new; i0 += kSelectThreads) {
@@ -181,7 +201,9 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
                                                           const FrameTable* __restrict__ frame, Counters* cnt,
                                                           const int* __restrict__ stream_cams, int phase,
                                                           Tuning tune) {
-  __shared__ ScanScratch sc;
+  __shared__ ScanScratch s_scan;
+  __shared__ int s_hsum[4];
+  Scan sc{&s_scan, 0};
   __shared__ unsigned s_occ[kMaxCells];
   __shared__ uint16_t s_sel[kMaxCells];
   __shared__ int s_hist[256];
@@ -228,28 +250,41 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       if (key && (int)s_occ[i] < tune.k) atomicAdd(&s_hist[key >> 24], 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // Score threshold of the best `room` candidates: thread t < 256 holds bin
+    // v = 255 - t, so a scan in thread order gives cum(v) = #candidates
+    // scoring >= v. With more candidates than room, thr is the bin where cum
+    // first reaches room and rem the number taken from it; thr = 256 takes
+    // none (no room), thr = -1 takes all.
+    {
       const int room = max(0, L.cap - n_surv);
-      int total = 0;
-      for (int v = 0; v < 256; ++v) total += s_hist[v];
-      int thr = -1, rem = 0;
-      if (room == 0) {
-        thr = 256;
-      } else if (total > room) {
-        int acc = 0;
-        for (int v = 255; v >= 0; --v) {
-          if (acc + s_hist[v] >= room) {
-            thr = v;
-            rem = room - acc;
-            break;
-          }
-          acc += s_hist[v];
+      int hv = 0, incl = 0;
+      if (threadIdx.x < 256) {
+        hv = s_hist[255 - threadIdx.x];
+        incl = wave_incl_scan(hv);
+        if ((threadIdx.x & 63) == 63) s_hsum[threadIdx.x >> 6] = incl;
+      }
+      __syncthreads();
+      if (threadIdx.x < 256) {
+        const int w = threadIdx.x >> 6;
+        int before = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int t = s_hsum[k];
+          before += k < w ? t : 0;
+          total += t;
+        }
+        const int cum = before + incl;
+        if (room > 0 && total > room && cum >= room && cum - hv < room) {
+          s_thr[0] = 255 - (int)threadIdx.x;
+          s_thr[1] = room - (cum - hv);
+        }
+        if (threadIdx.x == 0 && (room == 0 || total <= room)) {
+          s_thr[0] = room == 0 ? 256 : -1;
+          s_thr[1] = 0;
         }
       }
-      s_thr[0] = thr;
-      s_thr[1] = rem;
+      __syncthreads();
     }
-    __syncthreads();
     const int thr = s_thr[0], rem = s_thr[1];
 
     // ---- selection in cell order, identifiers, DET_t records --------------
