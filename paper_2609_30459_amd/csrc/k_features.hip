@@ -11,20 +11,23 @@
 //    division).
 //
 // Two launches. k_grid (one workgroup per camera) buckets the camera's tracks
-// that have a flow into a uniform grid of integer cells of about twice the
-// expected distance to the 8th neighbour: counts in LDS, a workgroup scan,
-// and a scatter of (position, index) into the camera's grid arrays.
-// k_features (one wave64 per keypoint) scans the (2R+1)^2 cells around its
-// keypoint -- every lane keeping a sorted top-8 of (squared distance, index)
-// over its share of the window's tracks -- and merges the lanes' heads in
-// eight wave-wide minimum rounds. A window is accepted when its 8th distance
-// is below the distance to the window's nearest open side (no track outside
-// can be as close) or it covers the grid, else R grows. The live set is
-// sorted by id, so index order is id order; squared distances are taken in
+// that have a flow into a uniform grid of integer cells of 2.5 mean track
+// spacings (about 6 tracks a cell, and well beyond the expected distance to
+// the 8th neighbour): counts in LDS, a workgroup scan, and a scatter of
+// (position, index) into the camera's grid arrays. k_features (one wave64 per
+// keypoint) gives every track of the (2R+1)^2 cells around its keypoint an
+// exact key (squared distance, index), one per lane, and sorts the keys over
+// the wave with a bitonic network (lane exchanges by DPP, swizzle and
+// permlane, no LDS); windows with more than 64 tracks go in chunks, the best
+// eight riding along in lanes 0..7. A window is accepted when its 8th
+// distance is below the distance to the window's nearest open side (no track
+// outside can be as close) or it covers the grid, else R grows. The live set
+// is sorted by id, so index order is id order; squared distances are taken in
 // double, where differences and squares of float positions are exact, so the
 // neighbour order is reproducible bit for bit. The same wave then pools the
 // patch.
 #include "fe_common.h"
+#include "wave_ops.h"
 
 namespace vio {
 namespace {
@@ -34,14 +37,10 @@ constexpr int kFeatWaves = 4;
 constexpr int kNone = 0x7FFFFFFF;
 static_assert(kFeatGridMax <= kGridThreads, "one cell per thread in the scan");
 
-__device__ __forceinline__ bool less_di(double da, int ia, double db, int ib) {
-  return da < db || (da == db && ia < ib);
-}
-
 // Cell edge (px) and grid size for n tracks on a w x h image: about
-// 1.9 sqrt(area / n), at most kFeatGridMax cells.
+// 2.5 sqrt(area / n), at most kFeatGridMax cells.
 __device__ __forceinline__ void grid_geometry(int w, int h, int n, int& cs, int& gx, int& gy) {
-  cs = max(8, (int)ceilf(1.9f * sqrtf((float)w * (float)h / (float)max(n, 1))));
+  cs = max(8, (int)ceilf(2.5f * sqrtf((float)w * (float)h / (float)max(n, 1))));
   gx = (w + cs - 1) / cs;
   gy = (h + cs - 1) / cs;
   while (gx * gy > kFeatGridMax) {
@@ -113,21 +112,63 @@ __global__ __launch_bounds__(kGridThreads) void k_grid(const CamDesc* __restrict
   }
 }
 
-// Inserts (dd, qi) into the lane's ascending top-8 (a NaN distance never enters).
-__device__ __forceinline__ void top8_insert(double (&d)[8], int (&ix)[8], double dd, int qi) {
-  if (!less_di(dd, qi, d[7], ix[7])) return;
-  d[7] = dd;
-  ix[7] = qi;
-#pragma unroll
-  for (int k = 7; k > 0; --k) {
-    const bool sw = less_di(d[k], ix[k], d[k - 1], ix[k - 1]);
-    const double td = d[k];
-    const int ti = ix[k];
-    d[k] = sw ? d[k - 1] : d[k];
-    ix[k] = sw ? ix[k - 1] : ix[k];
-    d[k - 1] = sw ? td : d[k - 1];
-    ix[k - 1] = sw ? ti : ix[k - 1];
+// Exact neighbour key: the squared distance as the bits of a non-negative
+// double (their unsigned order is the numeric order), then the index.
+struct NKey {
+  uint64_t d;
+  int ix;
+};
+
+__device__ __forceinline__ bool nkey_less(const NKey& a, const NKey& b) {
+  return a.d < b.d || (a.d == b.d && a.ix < b.ix);
+}
+
+// The value of lane (lane ^ J) (every lane active). J = 1, 2 by quad
+// permutes, 8 by a rotation of the 16-lane row by 8, 4 and 16 by swizzles
+// inside 32-lane halves, 32 by a permlane32 swap.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int lane) {
+  if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+  if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+  if constexpr (J == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+  if constexpr (J == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+  if constexpr (J == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+  if constexpr (J == 32) {
+    // swap(v, v): the first result holds lanes 0..31 twice, the second 32..63
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    const uint32_t lo = p[0], hi = p[1];
+    return lane < 32 ? hi : lo;
   }
+  return v;
+}
+
+// One compare-exchange stage of a bitonic sort over the 64 lanes: partner
+// lane ^ J; in blocks of K lanes sorted ascending when (lane & K) == 0, the
+// lower lane of a pair keeps the smaller key.
+template <int K, int J>
+__device__ __forceinline__ void bitonic_stage(NKey& k, int lane) {
+  NKey p;
+  const uint32_t lo = xor_lane<J>((uint32_t)k.d, lane), hi = xor_lane<J>((uint32_t)(k.d >> 32), lane);
+  p.d = ((uint64_t)hi << 32) | lo;
+  p.ix = (int)xor_lane<J>((uint32_t)k.ix, lane);
+  const bool want_min = ((lane & J) == 0) == ((lane & K) == 0);
+  const bool take = want_min ? nkey_less(p, k) : nkey_less(k, p);
+  // field by field: a select of the whole struct goes through private memory
+  k.d = take ? p.d : k.d;
+  k.ix = take ? p.ix : k.ix;
+}
+
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge(NKey& k, int lane) {
+  bitonic_stage<K, J>(k, lane);
+  if constexpr (J > 1) bitonic_merge<K, J / 2>(k, lane);
+}
+
+// Sorts the 64 lanes' keys ascending by lane (21 compare-exchange stages).
+template <int K = 2>
+__device__ __forceinline__ void bitonic_sort64(NKey& k, int lane) {
+  bitonic_merge<K, K / 2>(k, lane);
+  if constexpr (K < 64) bitonic_sort64<K * 2>(k, lane);
 }
 
 __global__ __launch_bounds__(64 * kFeatWaves) void k_features(const CamDesc* __restrict__ cams,
@@ -160,54 +201,41 @@ __global__ __launch_bounds__(64 * kFeatWaves) void k_features(const CamDesc* __r
   const int* idx = fg.idx + cd.row_off;
 
   // ---- the 8 nearest tracks with a flow: growing windows of cells --------
+  // Every candidate of the window gets an exact key; lanes 0..7 keep the best
+  // eight so far, and each chunk of candidates (64, then 56 at a time in
+  // lanes 8..63) is merged in by a bitonic sort over the wave.
   const int mcx = min(max((int)floorf(me.x) / cs, 0), gx - 1);
   const int mcy = min(max((int)floorf(me.y) / cs, 0), gy - 1);
-  float nfx = 0.f, nfy = 0.f;  // lane r keeps the r-th neighbour's flow
+  const NKey none{0x7FF0000000000000ull, kNone};  // +inf, no track
+  NKey best = none;
   for (int R = 1;; ++R) {
     const int ax = max(0, mcx - R), bx = min(gx - 1, mcx + R);
     const int ay = max(0, mcy - R), by = min(gy - 1, mcy + R);
-    double d[8];
-    int ix[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) d[k] = INFINITY, ix[k] = kNone;
-    for (int row = ay; row <= by; ++row) {
-      // the cells of a row are contiguous in the sorted order
-      const int hi = start[row * gx + bx + 1];
-      for (int q = start[row * gx + ax] + lane; q < hi; q += 64) {
+    // the cells of a window row are contiguous in the sorted order
+    int total = 0;
+    for (int row = ay; row <= by; ++row) total += start[row * gx + bx + 1] - start[row * gx + ax];
+    best = none;
+    for (int t0 = 0; t0 == 0 || t0 < total; t0 += t0 == 0 ? 64 : 56) {
+      // after the first chunk, lanes 0..7 carry the best eight so far
+      const int t = t0 == 0 ? lane : (lane < 8 ? -1 : t0 + lane - 8);
+      const bool carry = t0 != 0 && lane < 8;
+      NKey k;
+      k.d = carry ? best.d : none.d;
+      k.ix = carry ? best.ix : none.ix;
+      if (t >= 0 && t < total) {
+        int q = 0, acc = 0;
+        for (int row = ay; row <= by; ++row) {
+          const int rb = start[row * gx + ax], n = start[row * gx + bx + 1] - rb;
+          q = (t >= acc && t < acc + n) ? rb + (t - acc) : q;
+          acc += n;
+        }
         const float2 p = pos[q];
         const double dx = (double)p.x - mx, dy = (double)p.y - my;
-        top8_insert(d, ix, dx * dx + dy * dy, idx[q]);
+        k.d = (uint64_t)__double_as_longlong(dx * dx + dy * dy);
+        k.ix = idx[q];
       }
-    }
-    // merge: eight rounds of the wave-wide minimum of the lanes' heads
-    int found = 0;
-    double dlast = 0.0;
-    nfx = nfy = 0.f;
-    for (int r = 0; r < 8; ++r) {
-      double bd = d[0];
-      int bi = ix[0];
-#pragma unroll
-      for (int msk = 1; msk < 64; msk <<= 1) {
-        const double od = __shfl_xor(bd, msk);
-        const int oi = __shfl_xor(bi, msk);
-        const bool take = less_di(od, oi, bd, bi);
-        bd = take ? od : bd;
-        bi = take ? oi : bi;
-      }
-      if (bi == kNone) break;  // wave-uniform
-      const bool pop = ix[0] == bi;  // the lane holding the winner drops it
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        d[k] = pop ? d[k + 1] : d[k];
-        ix[k] = pop ? ix[k + 1] : ix[k];
-      }
-      d[7] = pop ? INFINITY : d[7];
-      ix[7] = pop ? kNone : ix[7];
-      const Kp o = live[bi];
-      nfx = lane == r ? (o.x - o.px) * 0.0625f : nfx;
-      nfy = lane == r ? (o.y - o.py) * 0.0625f : nfy;
-      found = r + 1;
-      dlast = bd;
+      bitonic_sort64(k, lane);
+      best = k;
     }
     if (ax == 0 && bx == gx - 1 && ay == 0 && by == gy - 1) break;
     // no track outside the window lies closer than its nearest open side
@@ -216,12 +244,22 @@ __global__ __launch_bounds__(64 * kFeatWaves) void k_features(const CamDesc* __r
     if (bx < gx - 1) bnd = fmin(bnd, (double)((bx + 1) * cs) - mx);
     if (ay > 0) bnd = fmin(bnd, my - (double)(ay * cs));
     if (by < gy - 1) bnd = fmin(bnd, (double)((by + 1) * cs) - my);
-    if (found == 8 && dlast < bnd * bnd) break;
+    const int ix7 = __builtin_amdgcn_readlane(best.ix, 7);
+    const uint32_t d7lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)best.d, 7);
+    const uint32_t d7hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(best.d >> 32), 7);
+    const double d7 = __longlong_as_double((long long)(((uint64_t)d7hi << 32) | d7lo));
+    if (ix7 != kNone && d7 < bnd * bnd) break;
   }
   float* f = feat + (size_t)(cd.row_off + j) * 32;
   {
-    const float fx = __shfl(nfx, (lane >> 1) & 7), fy = __shfl(nfy, (lane >> 1) & 7);
-    if (lane < 16) f[lane] = (lane & 1) ? fy : fx;
+    // lane r < 8 holds the r-th neighbour (nearest first)
+    float fx = 0.f, fy = 0.f;
+    if (lane < 8 && best.ix != kNone) {
+      const Kp o = live[best.ix];
+      fx = (o.x - o.px) * 0.0625f;
+      fy = (o.y - o.py) * 0.0625f;
+    }
+    if (lane < 8) reinterpret_cast<float2*>(f)[lane] = make_float2(fx, fy);
   }
 
   // ---- pooled patch of the previous frame --------------------------------
@@ -233,11 +271,11 @@ __global__ __launch_bounds__(64 * kFeatWaves) void k_features(const CamDesc* __r
   int ps = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) ps += img[(size_t)yy * pitch + min(max(rx - 8 + col4 + k, 0), cd.w - 1)];
-  // cell (row / 4, lane & 3): lanes differing in bits 2 and 3 share a cell
-  const int csum = ps + __shfl_xor(ps, 4) + __shfl_xor(ps, 8) + __shfl_xor(ps, 12);
-  int tot = ps;
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) tot += __shfl_xor(tot, m);
+  // cell (row / 4, lane & 3): the four lanes of a 16-lane row that agree in
+  // bits 0..1 share a cell (rotations by 8 and 4 sum them)
+  int csum = ps + dpp_i<0x128>(ps);
+  csum += dpp_i<0x124>(csum);
+  const int tot = wave_total_i(ps);
   if (((lane >> 2) & 3) == 0) {
     const int cell = (prow >> 2) * 4 + (lane & 3);
     f[16 + cell] = tot > 0 ? (float)(csum * 16) / (float)tot - 1.f : 0.f;

@@ -46,6 +46,7 @@
 #include <algorithm>
 
 #include "fe_common.h"
+#include "wave_ops.h"
 
 namespace vio {
 namespace {
@@ -66,83 +67,6 @@ __device__ __forceinline__ uint32_t ld16(gbytes p, uint32_t off) {
 }
 __device__ __forceinline__ uint32_t ld32(gbytes p, uint32_t off) {
   return ((const __attribute__((address_space(1))) U32*)(p + off))->v;
-}
-
-template <int ctrl>
-__device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
-}
-
-// One exchange stage inside the 16-lane rows: the partner of a lane differs
-// from it in lane bit BIT and agrees below it (CTRL: quad_perm [1,0,3,2] for
-// bit 0, quad_perm [2,3,0,1] for bit 1, row_ror:4 for bit 2, row_ror:8 for
-// bit 3). With N > 1 values, value pair (2i, 2i+1) becomes value i: a lane
-// keeps the member its bit selects and adds the partner's copy of it (the
-// partner, with the other bit, sends exactly that member).
-template <int CTRL, int BIT, int N>
-__device__ __forceinline__ void xstage(float* v, int lane) {
-  if constexpr (N == 1) {
-    v[0] += dpp<CTRL>(v[0]);
-  } else {
-    const bool b = (lane >> BIT) & 1;
-#pragma unroll
-    for (int i = 0; i < N / 2; ++i) {
-      const float keep = b ? v[2 * i + 1] : v[2 * i];
-      const float send = b ? v[2 * i] : v[2 * i + 1];
-      v[i] = keep + dpp<CTRL>(send);
-    }
-  }
-}
-
-// Sum of a row with its partner row: permlane32 swaps lanes 32..63 of one copy
-// with lanes 0..31 of the other (rows 0,1 <-> 2,3), permlane16 the odd rows of
-// one copy with the even rows of the other (rows 0 <-> 1, 2 <-> 3); the two
-// results, added, give every lane its value plus the partner row's value in
-// the same position.
-__device__ __forceinline__ float rowswap_sum32(float x) {
-  const auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
-                                                  false, false);
-  const unsigned a = p[0], b = p[1];  // (a bit cast of p[1] itself would read p[0])
-  return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
-}
-__device__ __forceinline__ float rowswap_sum16(float x) {
-  const auto p = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, x),
-                                                  false, false);
-  const unsigned a = p[0], b = p[1];  // (a bit cast of p[1] itself would read p[0])
-  return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
-}
-
-// v[i] <- sum of v[i] over the 64 lanes, i < N (N = 1, 2, 4, 8 or 16), as
-// wave-uniform values.
-template <int N>
-__device__ __forceinline__ void wave_sums_pow2(float* v, int lane) {
-  static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "power of two up to 16");
-  float w[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) w[i] = v[i];
-  xstage<0xB1, 0, N>(w, lane);
-  xstage<0x4E, 1, (N > 2 ? N / 2 : 1)>(w, lane);
-  xstage<0x124, 2, (N > 4 ? N / 4 : 1)>(w, lane);
-  xstage<0x128, 3, (N > 8 ? N / 8 : 1)>(w, lane);
-  // lane j of every row holds sum j (j = lane mod N) of its row
-  const float x = rowswap_sum16(rowswap_sum32(w[0]));
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
-}
-
-// v[i] <- wave sum of v[i] for i < M, in chunks of 16, 8, 4, 2, 1
-template <int M>
-__device__ __forceinline__ void wave_sums(float* v, int lane) {
-  if constexpr (M > 0) {
-    constexpr int C = M >= 16 ? 16 : M >= 8 ? 8 : M >= 4 ? 4 : M >= 2 ? 2 : 1;
-    wave_sums_pow2<C>(v, lane);
-    wave_sums<M - C>(v + C, lane);
-  }
-}
-
-__device__ __forceinline__ float wave_sum(float x, int lane) {
-  wave_sums_pow2<1>(&x, lane);
-  return x;
 }
 
 __device__ __forceinline__ bool wave_all(bool p) { return __all(p); }

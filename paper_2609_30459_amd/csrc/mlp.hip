@@ -151,33 +151,17 @@ __global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_fwd(MlpDev M, const floa
 
 // ---------------------------------------------------------------------------
 // inference forward: the same MFMA sequence as k_mlp_fwd (so the same
-// results), with the workgroup's bf16 weights and the biases staged in LDS
-// once, and layer 2's eight output tiles held in registers so its output
-// reuses the wave's layer-1 tile in LDS.
+// results). The bf16 weights and the biases (42 KB, L2-resident) are read
+// straight from global memory as MFMA operands, so a workgroup holds only its
+// waves' 4 KB activation tiles in LDS and fits beside the pyramid kernel's
+// workgroups when both run at once; layer 2's eight output tiles stay in
+// registers so its output reuses the wave's layer-1 tile.
 // ---------------------------------------------------------------------------
 constexpr int kInferWaves = 4;
 __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(MlpDev M, const float* __restrict__ X, int K,
                                                                int Kpad, float* __restrict__ Y) {
-  __shared__ __align__(16) uint16_t sW1[MH * MI];
-  __shared__ __align__(16) uint16_t sW2[MH * MH];
-  __shared__ __align__(16) uint16_t sW3[16 * MH];  // rows 3..15 zero
-  __shared__ float sB[MH + MH + 16];
   __shared__ __align__(16) uint16_t sH[kInferWaves][16][MH];
   const int tid = (int)threadIdx.x;
-  // stage the weights: 16-byte copies
-  {
-    const uint4* w1 = reinterpret_cast<const uint4*>(M.W1b);
-    const uint4* w2 = reinterpret_cast<const uint4*>(M.W2b);
-    const uint4* w3 = reinterpret_cast<const uint4*>(M.W3b);
-    for (int i = tid; i < MH * MI / 8; i += 64 * kInferWaves) reinterpret_cast<uint4*>(sW1)[i] = w1[i];
-    for (int i = tid; i < MH * MH / 8; i += 64 * kInferWaves) reinterpret_cast<uint4*>(sW2)[i] = w2[i];
-    for (int i = tid; i < 16 * MH / 8; i += 64 * kInferWaves)
-      reinterpret_cast<uint4*>(sW3)[i] = i < MO * MH / 8 ? w3[i] : make_uint4(0u, 0u, 0u, 0u);
-    for (int i = tid; i < MH + MH + 16; i += 64 * kInferWaves)
-      sB[i] = i < MH ? M.P[OFF_B1 + i] : i < 2 * MH ? M.P[OFF_B2 + i - MH] : i - 2 * MH < MO ? M.P[OFF_B3 + i - 2 * MH]
-                                                                                             : 0.f;
-  }
-  __syncthreads();
   const int lane = tid & 63, wv = tid >> 6;
   const int i0 = ((int)blockIdx.x * kInferWaves + wv) * 16;
   if (i0 >= Kpad) return;  // no barrier follows
@@ -195,8 +179,8 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(MlpDev M, const 
 #pragma unroll
   for (int jt = 0; jt < MH / 16; ++jt) {
     const int j = 16 * jt + r;
-    const f32x4 acc = mfma(a, load8(&sW1[j * MI + 8 * g]), zero);
-    const float b = sB[j];
+    const f32x4 acc = mfma(a, load8(&M.W1b[j * MI + 8 * g]), zero);
+    const float b = M.P[OFF_B1 + j];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = 4 * g + q;
@@ -211,14 +195,15 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(MlpDev M, const 
     const int j = 16 * jt + r;
     f32x4 acc = zero;
 #pragma unroll
-    for (int kc = 0; kc < MH / 32; ++kc) acc = mfma(load8(&h[r][32 * kc + 8 * g]), load8(&sW2[j * MH + 32 * kc + 8 * g]), acc);
+    for (int kc = 0; kc < MH / 32; ++kc)
+      acc = mfma(load8(&h[r][32 * kc + 8 * g]), load8(&M.W2b[j * MH + 32 * kc + 8 * g]), acc);
     acc2[jt] = acc;
   }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int jt = 0; jt < MH / 16; ++jt) {
     const int j = 16 * jt + r;
-    const float b = sB[MH + j];
+    const float b = M.P[OFF_B2 + j];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = 4 * g + q;
@@ -229,9 +214,13 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(MlpDev M, const 
   // layer 3: 3 outputs padded to a 16-column tile (zero weight rows)
   f32x4 acc = zero;
 #pragma unroll
-  for (int kc = 0; kc < MH / 32; ++kc) acc = mfma(load8(&h[r][32 * kc + 8 * g]), load8(&sW3[r * MH + 32 * kc + 8 * g]), acc);
+  for (int kc = 0; kc < MH / 32; ++kc) {
+    // output columns 3..15 are zero weight rows
+    const bf16x8 w = r < MO ? load8(&M.W3b[r * MH + 32 * kc + 8 * g]) : __builtin_bit_cast(bf16x8, make_uint4(0u, 0u, 0u, 0u));
+    acc = mfma(load8(&h[r][32 * kc + 8 * g]), w, acc);
+  }
   if (r < MO) {
-    const float b = sB[2 * MH + r];
+    const float b = M.P[OFF_B3 + r];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = i0 + 4 * g + q;
