@@ -143,14 +143,29 @@ __device__ __forceinline__ void template_samples(const Level& I, float x, float 
   gy = (iyp - iym) * 0.5f;
 }
 
-// level l of pyramid slot `slot` of camera `cd` (scalar loads from the descriptor)
-__device__ __forceinline__ Level level_of(const CamDesc& cd, int slot, int l) {
+// Camera descriptors are read-only while the tracker runs: read through the
+// constant address space, a wave-uniform descriptor's fields come in with
+// scalar loads.
+typedef const __attribute__((address_space(4))) CamDesc* cdesc_k;
+
+// level l of pyramid slot `slot` of camera `cd`
+__device__ __forceinline__ Level level_of(cdesc_k cd, int slot, int l) {
   Level L;
-  L.p = (gbytes)cd.lvl[slot][l];
-  L.pitch = cd.pitch[l];
-  L.w = cd.w >> l;
-  L.h = cd.h >> l;
+  L.p = (gbytes)cd->lvl[slot][l];
+  L.pitch = cd->pitch[l];
+  L.w = cd->w >> l;
+  L.h = cd->h >> l;
   return L;
+}
+
+// A pointer every lane holds the same value of, marked so for the compiler
+// (its loads then go through the scalar cache into scalar registers).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
 struct PassOut {
@@ -177,9 +192,13 @@ __device__ __forceinline__ void se2_v(float phi, float& a, float& b) {
 // iterations per level, levels nl-1 .. 0, translation doubled between levels,
 // a level whose template does not fit is skipped.
 template <int L>
-__device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px,
-                                            float py, float ix, float iy, float ith, int nl, int N, float u, float v,
-                                            float wgt, int lane) {
+__device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc_in, int ssrc_in, const CamDesc& cdst_in, int sdst_in,
+                                            float px, float py, float ix, float iy, float ith, int nl, int N, float u,
+                                            float v, float wgt, int lane) {
+  // the pass's cameras and slots are the wave's (the passes swap them)
+  const cdesc_k csrc = (cdesc_k)uniform_ptr(&csrc_in);
+  const cdesc_k cdst = (cdesc_k)uniform_ptr(&cdst_in);
+  const int ssrc = __builtin_amdgcn_readfirstlane(ssrc_in), sdst = __builtin_amdgcn_readfirstlane(sdst_in);
   PassOut o{VIO_TRACKED, 0.f, 0.f, 0.f, 0.f};
   // ---- templates of all levels (Sec. III-E) ------------------------------
   bool fits[L], valid[L];
@@ -487,7 +506,10 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
                                                           int item_base, int n_items,
                                                           const Prediction* __restrict__ pred, Tuning tune) {
   const int lane = threadIdx.x & (kW - 1);
-  const int k = (int)blockIdx.x * (int)(blockDim.x / kW) + (int)(threadIdx.x / kW);
+  // the wave's item: uniform across the wave (readfirstlane tells the compiler
+  // so, which keeps the item's descriptors and pyramid bases in scalar
+  // registers, loaded through the scalar cache)
+  const int k = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (int)(blockDim.x / kW) + (int)(threadIdx.x / kW));
   if (k >= n_items) return;
   float u, v, wgt;
   pattern_of(lane, u, v, wgt);
