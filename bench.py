@@ -173,6 +173,9 @@ def main():
         extra.update(init_mode=1, learned_levels=args.learned_levels, learned_iters=args.learned_iters,
                      learned_rho=rho)
     ids = list(range(len(ws)))
+    # each frame's device images (views into the resident sequences), all
+    # cameras stream by stream, made once before any timed region
+    frame_imgs = [[devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)] for t in range(n_frames)]
 
     def timed_run(eager):
         """Warmup, then the timed steps: (records per stream, wall s per step, stats per step, elapsed s)."""
@@ -185,11 +188,10 @@ def main():
 
         def step(t):
             if batched:
-                imgs = [devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)]
-                fe.stage_frames_device(ids, [t + 1] * len(ws), imgs)
+                fe.stage_frames_device(ids, [t + 1] * len(ws), frame_imgs[t])
                 fe.step()
             else:
-                fe.push_stereo_frame_device(0, t + 1, [devs[0][t, c] for c in range(w0.n_cams)])
+                fe.push_stereo_frame_device(0, t + 1, frame_imgs[t])
             for i in ids:
                 records[i].append(fe.get_tracks(i))
 

@@ -69,6 +69,7 @@ class Frontend:
             d.n_cameras, d.width, d.height, d.max_keypoints, d.cell_size = s
         self.streams = [tuple(s) for s in streams]
         self.params = params
+        self._rec_hint = {}  # per stream: record buffer size for get_tracks
         h = ctypes.c_void_p()
         rc = _n.lib.vio_frontend_create(descs, len(streams), ctypes.byref(params), ctypes.byref(h))
         if rc != 0:
@@ -150,14 +151,18 @@ class Frontend:
         self._check(_n.lib.vio_frontend_step(self._h), "vio_frontend_step")
 
     def get_tracks(self, stream=0) -> np.ndarray:
+        """The last frame's records of the stream (one C call while the buffer guess holds)."""
         n = ctypes.c_int32()
-        rc = _n.lib.vio_frontend_get_tracks(self._h, stream, None, 0, ctypes.byref(n))
-        if rc not in (0, _n.VIO_ETOOSMALL):
-            self._check(rc, "vio_frontend_get_tracks")
-        out = np.zeros(n.value, TRACK_DTYPE)
-        rc = _n.lib.vio_frontend_get_tracks(self._h, stream, out.ctypes.data, n.value, ctypes.byref(n))
+        cap = self._rec_hint.get(stream, 256)
+        out = np.empty(cap, TRACK_DTYPE)
+        rc = _n.lib.vio_frontend_get_tracks(self._h, stream, out.ctypes.data, cap, ctypes.byref(n))
+        if rc == _n.VIO_ETOOSMALL:
+            cap = n.value + n.value // 4
+            out = np.empty(cap, TRACK_DTYPE)
+            rc = _n.lib.vio_frontend_get_tracks(self._h, stream, out.ctypes.data, cap, ctypes.byref(n))
         self._check(rc, "vio_frontend_get_tracks")
-        return out
+        self._rec_hint[stream] = cap
+        return out[:n.value]
 
     # -- keypoint state ----------------------------------------------------
     def set_keypoints(self, stream, camera, kps: np.ndarray):

@@ -73,9 +73,20 @@ struct CamDesc {
   TrackRes* sres;                    // stereo match of every cell winner [ncells]
   vio_track* rec;                    // output records [rec_cap], in mapped pinned host memory
   int32_t* rec_count_out;            // record count of the last frame, mapped pinned host memory
-  int32_t* fallback_out;             // learned tracks that fell back to the plain tracker, mapped host memory
+  int32_t* stats_out;                // [kCamStats] counts of the last frame (CamStat), mapped host memory
   int rec_cap;
   int row_off;                       // first row of this camera in the learned-init feature/guess buffers
+};
+
+// Per-camera counts of a frame, written by the selection kernel into mapped
+// host memory (CamDesc::stats_out).
+enum CamStat : int {
+  kStatFallback = 0,  // learned tracks that fell back to the plain tracker
+  kStatTracked,       // temporal records with VIO_TRACKED
+  kStatLost,          // temporal records without VIO_TRACKED
+  kStatDetected,      // VIO_DETECTED records
+  kStatMatched,       // VIO_MATCHED records
+  kCamStats
 };
 
 // Per-frame inputs, copied host -> device before every frame.

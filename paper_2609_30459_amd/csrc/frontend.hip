@@ -106,7 +106,7 @@ struct vio_frontend {
   float* d_feat = nullptr;   // [rows][32]
   FeatGrid grid{};           // neighbour grids of the features
   float* d_guess = nullptr;  // [rows][3]
-  int32_t* h_fallback = nullptr;
+  int32_t* h_camstats = nullptr;  // [cameras][kCamStats], written by the selection kernel
   // pinned host
   FrameTable* h_frame = nullptr;
   int32_t* h_rec_count = nullptr;
@@ -218,7 +218,7 @@ void vio_frontend_destroy(vio_frontend* h) {
   if (h->arena) (void)hipFree(h->arena);
   if (h->h_frame) (void)hipHostFree(h->h_frame);
   if (h->h_rec_count) (void)hipHostFree(h->h_rec_count);
-  if (h->h_fallback) (void)hipHostFree(h->h_fallback);
+  if (h->h_camstats) (void)hipHostFree(h->h_camstats);
   if (h->h_rec) (void)hipHostFree(h->h_rec);
   if (h->h_stage) (void)hipHostFree(h->h_stage);
   if (h->h_pred) (void)hipHostFree(h->h_pred);
@@ -422,23 +422,23 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->stage_bytes = stage;
   if (hipHostMalloc((void**)&h->h_frame, sizeof(FrameTable)) != hipSuccess ||
       hipHostMalloc((void**)&h->h_rec_count, sizeof(int32_t) * n_cams) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_fallback, sizeof(int32_t) * n_cams) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_camstats, sizeof(int32_t) * kCamStats * n_cams) != hipSuccess ||
       hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * rec_total) != hipSuccess ||
       hipHostMalloc((void**)&h->h_stage, stage) != hipSuccess ||
       hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * std::max(1, h->pred_cap)) != hipSuccess)
     return fail(h, VIO_ENOMEM, "pinned host buffers");
   std::memset(h->h_frame, 0, sizeof(FrameTable));
   std::memset(h->h_rec_count, 0, sizeof(int32_t) * n_cams);
-  std::memset(h->h_fallback, 0, sizeof(int32_t) * n_cams);
+  std::memset(h->h_camstats, 0, sizeof(int32_t) * kCamStats * n_cams);
   vio_track* rec_dev = nullptr;
-  int32_t *cnt_dev = nullptr, *fb_dev = nullptr;
+  int32_t *cnt_dev = nullptr, *stats_dev = nullptr;
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&rec_dev, h->h_rec, 0));
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&cnt_dev, h->h_rec_count, 0));
-  HIP_CHECK(h, hipHostGetDevicePointer((void**)&fb_dev, h->h_fallback, 0));
+  HIP_CHECK(h, hipHostGetDevicePointer((void**)&stats_dev, h->h_camstats, 0));
   for (int c = 0; c < n_cams; ++c) {
     h->cams[c].rec = rec_dev + co[c].rec;
     h->cams[c].rec_count_out = cnt_dev + c;
-    h->cams[c].fallback_out = fb_dev + c;
+    h->cams[c].stats_out = stats_dev + (size_t)kCamStats * c;
     h->rec_host_off.push_back(co[c].rec);
   }
   HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
@@ -662,22 +662,16 @@ static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t
   h->stats.last_learned_ms[1] = km[kKernMlp];
   h->stats.last_gpu_ms = ms;
   h->stats.frames += 1;
+  // the selection kernel's per-camera counts (no pass over the records)
   int tr = 0, lost = 0, det = 0, mat = 0, fb = 0;
   for (int c = ls.cam_begin; c < ls.cam_end; ++c) {
     if (!h->h_frame->cam[c].active) continue;
-    const CamDesc& cd = h->cams[c];
-    const int n = h->h_rec_count[c];
-    const vio_track* r = h->h_rec + h->rec_host_off[c];
-    for (int i = 0; i < n; ++i) {
-      switch (r[i].status) {
-        case VIO_TRACKED: ++tr; break;
-        case VIO_DETECTED: ++det; break;
-        case VIO_MATCHED: ++mat; break;
-        default:
-          if (r[i].age > 0 || cd.detect) ++lost;
-      }
-    }
-    if (h->learned) fb += h->h_fallback[c];
+    const int32_t* st = h->h_camstats + (size_t)kCamStats * c;
+    tr += st[kStatTracked];
+    lost += st[kStatLost];
+    det += st[kStatDetected];
+    mat += st[kStatMatched];
+    if (h->learned) fb += st[kStatFallback];
   }
   h->stats.last_fallback = fb;
   h->stats.last_tracked = tr;

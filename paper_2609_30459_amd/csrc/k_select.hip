@@ -156,7 +156,14 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
     base += total;
   }
   *n_rec = fc.has_prev ? n_prev : 0;
-  if (threadIdx.x == 0) *cd.fallback_out = n_fb;
+  if (threadIdx.x == 0) {
+    int32_t* st = cd.stats_out;
+    st[kStatFallback] = n_fb;
+    st[kStatTracked] = fc.has_prev ? base : 0;
+    st[kStatLost] = fc.has_prev ? n_prev - base : 0;
+    st[kStatDetected] = 0;
+    st[kStatMatched] = 0;
+  }
   return base;
 }
 
@@ -191,9 +198,11 @@ __device__ void accept_matches(const CamDesc& L, int P, int sel_base, const CamD
     m_base += m_tot;
   }
   if (threadIdx.x == 0) {
-    cnt->n_live[PR][rc] = n_surv_r + min(m_base, max(0, R.cap - n_surv_r));
+    const int accepted = min(m_base, max(0, R.cap - n_surv_r));
+    cnt->n_live[PR][rc] = n_surv_r + accepted;
     cnt->rec_count[rc] = n_rec_r + n_new;
     *R.rec_count_out = n_rec_r + n_new;
+    R.stats_out[kStatMatched] = accepted;
   }
 }
 
@@ -314,6 +323,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       cnt->n_live[P][lc] = n_surv + n_new;
       cnt->rec_count[lc] = n_rec + n_new;
       *L.rec_count_out = n_rec + n_new;
+      L.stats_out[kStatDetected] = n_new;
     }
     for (int i = threadIdx.x; i < ncells; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
     __syncthreads();

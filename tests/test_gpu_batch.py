@@ -117,3 +117,27 @@ def test_multi_stream_staging_call_equals_single_stagings():
             for s in range(3):
                 assert a.get_tracks(s).tobytes() == b.get_tracks(s).tobytes(), (t, s)
             assert all(m > 0 for m in a.stats()["last_stage_ms"])
+
+
+@pytest.mark.parametrize("stereo_mode", [0, 1])
+def test_step_counts_equal_the_records(stereo_mode):
+    """The per-frame counts the selection kernel reports (vio_stats) agree with
+    the records: tracked, detected and matched records by status, and lost =
+    the previous frame's live keypoints that were not tracked."""
+    import paper_2609_30459_amd as vf
+    TR, DET, MAT = vf.VIO_TRACKED, vf.VIO_DETECTED, vf.VIO_MATCHED
+    seqs = _seqs(5)
+    with vf.Frontend(_streams(), vf.params_for(MIX[1], stereo_mode=stereo_mode)) as fe:
+        prev_live = None
+        for t in range(5):
+            for s, seq in enumerate(seqs):
+                fe.stage_frame(s, t + 1, list(seq.frames[t]))
+            fe.step()
+            recs = np.concatenate([fe.get_tracks(s) for s in range(len(MIX))])
+            st = fe.stats()
+            n_tr = int((recs["status"] == TR).sum())
+            assert st["last_tracked"] == n_tr, t
+            assert st["last_detected"] == int((recs["status"] == DET).sum()), t
+            assert st["last_matched"] == int((recs["status"] == MAT).sum()), t
+            assert st["last_lost"] == (prev_live - n_tr if prev_live is not None else 0), t
+            prev_live = int(np.isin(recs["status"], [TR, DET, MAT]).sum())
