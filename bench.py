@@ -167,7 +167,10 @@ def main():
     rho = None
     if args.init == "learned":
         from paper_2609_30459_amd.train_mlp import load_weights
-        path = args.weights or os.path.join(ROOT, "paper_2609_30459_amd", "weights", "mlp_stereo1280.bin")
+        # the workload's own trained network when there is one, else the stereo1280 one
+        wdir = os.path.join(ROOT, "paper_2609_30459_amd", "weights")
+        own = os.path.join(wdir, f"mlp_{args.workload}.bin")
+        path = args.weights or (own if os.path.exists(own) else os.path.join(wdir, "mlp_stereo1280.bin"))
         mlp_params, rho, meta = load_weights(path)
         log(f"learned init: {path} ({meta}), rho {rho:.4f}")
         extra.update(init_mode=1, learned_levels=args.learned_levels, learned_iters=args.learned_iters,
