@@ -25,6 +25,7 @@
 // key = score << 24 | (2^24 - 1 - (y * W + x)), i.e. highest score, then
 // smallest y, then smallest x.
 #include "fe_common.h"
+#include "wave_ops.h"
 
 namespace vio {
 namespace {
@@ -41,7 +42,13 @@ struct PyrGeom {
   // level-0 staging: apron at least 4 (FAST radius 3 plus the NMS ring)
   static constexpr int a0 = apron(0) > 4 ? apron(0) : 4;
   static constexpr int a0x = (a0 + 3) & ~3;  // left apron rounded to a dword
-  static constexpr int sw0 = ((T + a0x + a0) + 3) & ~3;
+  // the early rejection tests four pixels at a time: group g holds score-region
+  // columns 4g-3 .. 4g (dword-aligned in LDS), and reads the dwords on either
+  // side of its middle row
+  static constexpr int fast_groups = (score_edge + 2) / 4 + 1;
+  static constexpr int sw0_min = ((T + a0x + a0) + 3) & ~3;
+  static constexpr int sw0 = sw0_min > 4 * fast_groups + a0x ? sw0_min : 4 * fast_groups + a0x;
+  static constexpr int score_bytes = (score_edge * score_edge + 3) & ~3;
   static constexpr int sh0 = T + 2 * a0;
   static constexpr int vbytes = L > 1 ? (region(0) - 1) * region(1) : 1;
   // the paired horizontal pass reads three dwords from byte 4q of a level-0
@@ -80,19 +87,35 @@ __device__ __forceinline__ void ring_diffs(const uint8_t* img, int o, int sp, in
   d[15] = img[o - 3 * sp - 1] - c;
 }
 
+typedef short short2v __attribute__((ext_vector_type(2)));
+
 // The paper's early rejection (Sec. III-D): every 9-arc holds one of the ring
 // positions 0 and 8 and one of 4 and 12, so a corner at threshold tmin needs
-// such a pair brighter than I(p) + tmin or darker than I(p) - tmin. Reads the
-// centre and the four ring positions 0, 4, 8, 12 only.
-__device__ __forceinline__ bool fast_may_pass(const uint8_t* img, int o, int sp, int tmin) {
-  const int c = img[o];
-  const int d0 = img[o - 3 * sp] - c, d4 = img[o + 3] - c, d8 = img[o + 3 * sp] - c, d12 = img[o - 3] - c;
-  const bool bright = (d0 > tmin || d8 > tmin) && (d4 > tmin || d12 > tmin);
-  const bool dark = (d0 < -tmin || d8 < -tmin) && (d4 < -tmin || d12 < -tmin);
-  return bright || dark;
+// such a pair brighter than I(p) + tmin or darker than I(p) - tmin, i.e.
+//   min(max(p0, p8), max(p4, p12)) - I(p) > tmin   (bright) or
+//   I(p) - max(min(p0, p8), min(p4, p12)) > tmin   (dark).
+// Four horizontally adjacent pixels at once: byte k of c is pixel k, of p0,
+// p4, p8, p12 its ring pixels 0 (above), 4 (right), 8 (below), 12 (left);
+// bytes 0, 2 and then 1, 3 ride in 16-bit halves. Bit k of the result is set
+// when pixel k passes.
+__device__ __forceinline__ uint32_t fast_may_pass4(uint32_t p0, uint32_t p4, uint32_t p8, uint32_t p12, uint32_t c,
+                                                   int tmin) {
+  const short2v tm = {(short)tmin, (short)tmin};
+  uint32_t res = 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    auto pair = [h](uint32_t w) { return __builtin_bit_cast(short2v, (w >> (8 * h)) & 0x00FF00FFu); };
+    const short2v a = pair(p0), b = pair(p8), r = pair(p4), l = pair(p12), cc = pair(c);
+    const short2v hi = __builtin_elementwise_min(__builtin_elementwise_max(a, b), __builtin_elementwise_max(r, l));
+    const short2v lo = __builtin_elementwise_max(__builtin_elementwise_min(a, b), __builtin_elementwise_min(r, l));
+    // sign bit set where tmin - margin < 0, i.e. the margin exceeds tmin
+    const uint32_t e = __builtin_bit_cast(uint32_t, (short2v)(tm - (hi - cc))) |
+                       __builtin_bit_cast(uint32_t, (short2v)(tm - (cc - lo)));
+    res |= ((e >> 15) & 1u) << h;        // byte h
+    res |= ((e >> 31) & 1u) << (2 + h);  // byte h + 2
+  }
+  return res;
 }
-
-typedef short short2v __attribute__((ext_vector_type(2)));
 
 // FAST-9 score (Sec. III-D): the largest tau with a 9-arc all brighter than
 // I(p)+tau or all darker than I(p)-tau, i.e. (max over polarity and arc of the
@@ -158,7 +181,7 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   constexpr int kPyrThreads = G::threads;
   constexpr int kScoreEdge = G::score_edge;
   __shared__ __align__(16) uint8_t s_l0[G::sh0 * G::sw0];
-  __shared__ uint8_t s_score[kScoreEdge * kScoreEdge];
+  __shared__ __align__(4) uint8_t s_score[G::score_bytes];
   __shared__ uint16_t s_cand[kScoreEdge * kScoreEdge];  // pixels past the early rejection
   __shared__ int s_ncand;
   __shared__ __align__(16) uint16_t s_v[G::vbytes];
@@ -225,20 +248,46 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   // score for every wave that holds one.
   if (cd.detect) {
     const int lane = tid & 63;
-    for (int i = tid; i < kScoreEdge * kScoreEdge; i += kPyrThreads) {
-      const int sy = y0 - 1 + i / kScoreEdge, sx = x0 - 1 + i % kScoreEdge;
-      const bool cand = sx >= margin - 1 && sx <= W - margin && sy >= margin - 1 && sy <= H - margin &&
-                        fast_may_pass(s_l0, (sy - oy0) * G::sw0 + (sx - ox0), G::sw0, tmin);
-      s_score[i] = 0;
-      // one LDS atomic per wave reserves the wave's slots
-      const uint64_t m = __ballot(cand);
-      if (m) {
-        const int leader = __ffsll((unsigned long long)m) - 1;
+    for (int i = tid; i < G::score_bytes / 4; i += kPyrThreads) reinterpret_cast<uint32_t*>(s_score)[i] = 0u;
+    // four pixels per thread: the score-region row cy, columns 4g-3 .. 4g
+    constexpr int kGroups = G::fast_groups, kItems = kScoreEdge * kGroups;
+    for (int i0 = 0; i0 < kItems; i0 += kPyrThreads) {  // the same trip count for every thread
+      const int it = i0 + tid;
+      const int cy = it / kGroups, g = it - cy * kGroups;
+      const int cx0 = 4 * g - 3;
+      const int sy = y0 - 1 + cy, sx0 = x0 - 1 + cx0;
+      // bytes k of the group that are score-region pixels inside the margins
+      const int klo = max(max(0, -cx0), margin - 1 - sx0);
+      const int khi = min(min(3, kScoreEdge - 1 - cx0), W - margin - sx0);
+      const bool rows_ok = it < kItems && sy >= margin - 1 && sy <= H - margin && klo <= khi;
+      uint32_t m = 0;
+      if (rows_ok) {
+        const int lx = 4 * g + G::a0x - 4;
+        const uint8_t* row = s_l0 + (cy + G::a0 - 1) * G::sw0;
+        const uint32_t up = *reinterpret_cast<const uint32_t*>(row - 3 * G::sw0 + lx);
+        const uint32_t dn = *reinterpret_cast<const uint32_t*>(row + 3 * G::sw0 + lx);
+        // (at lx = 0 the left dword is not needed: only byte 3 is a pixel then)
+        const uint32_t w0 = *reinterpret_cast<const uint32_t*>(row + max(lx - 4, 0));
+        const uint32_t c = *reinterpret_cast<const uint32_t*>(row + lx);
+        const uint32_t w2 = *reinterpret_cast<const uint32_t*>(row + lx + 4);
+        const uint32_t lt = __builtin_amdgcn_alignbyte(c, w0, 1), rt = __builtin_amdgcn_alignbyte(w2, c, 3);
+        m = fast_may_pass4(up, rt, dn, lt, c, tmin) & ((2u << khi) - (1u << klo));
+      }
+      // the wave's candidates go to consecutive slots: a scan of the counts,
+      // one LDS atomic per wave
+      const int n = __popc(m);
+      const int incl = wave_incl_scan(n);
+      const int tot = __builtin_amdgcn_readlane(incl, 63);
+      if (tot) {
         int base = 0;
-        if (lane == leader) base = atomicAdd(&s_ncand, __popcll(m));
-        base = __builtin_amdgcn_readlane(base, leader);
-        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (cand) s_cand[base + below] = (uint16_t)i;
+        if (lane == 0) base = atomicAdd(&s_ncand, tot);
+        int at = __builtin_amdgcn_readlane(base, 0) + incl - n;
+        const int i_row = cy * kScoreEdge + cx0;
+        while (m) {
+          const int k = __ffs(m) - 1;
+          m &= m - 1;
+          s_cand[at++] = (uint16_t)(i_row + k);
+        }
       }
     }
     __syncthreads();

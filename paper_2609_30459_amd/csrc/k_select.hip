@@ -25,6 +25,7 @@
 // place in the left state in sel_base / n_sel; kSelectRight accepts the
 // matches (indexed by selection rank) into the right cameras.
 #include "fe_common.h"
+#include "wave_ops.h"
 
 namespace vio {
 
@@ -69,18 +70,7 @@ __device__ __forceinline__ int block_scan_flag(bool flag, Scan& sc, int& total) 
   return off + below;
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
-// inside each 16-lane row, then row_bcast:15 and row_bcast:31 carry the row
-// totals forward (lanes without a source add the old value 0).
-__device__ __forceinline__ int wave_incl_scan(int x) {
-  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
-  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
-  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
-  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
-  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
-  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
-  return x;
-}
+
 
 __device__ __forceinline__ vio_track make_rec(int64_t id, int cam, int status, float x, float y, float th, float fb,
                                               float res, int age, int score) {
