@@ -204,6 +204,14 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   const int sp = fc.src_pitch;
   const bool aligned = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)sp) & 3) == 0;
   constexpr int qrow = G::sw0 / 4;
+  if (aligned && ox0 >= 0 && oy0 >= 0 && ox0 + G::sw0 <= W && oy0 + G::sh0 <= H) {
+    // the whole staged region inside the image (the workgroup's choice): plain dword copies
+    for (int i = tid; i < G::sh0 * qrow; i += kPyrThreads) {
+      const int r = i / qrow, q = i - r * qrow;
+      *reinterpret_cast<uint32_t*>(&s_l0[r * G::sw0 + 4 * q]) =
+          *reinterpret_cast<const uint32_t*>(src + (size_t)(oy0 + r) * sp + ox0 + 4 * q);
+    }
+  } else
   for (int i = tid; i < G::sh0 * qrow; i += kPyrThreads) {
     const int r = i / qrow, q = i - r * qrow;
     const int y = oy0 + r, x = ox0 + 4 * q;
@@ -306,18 +314,21 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
     for (int j = tid; j < ncand; j += kPyrThreads) {
       const int i = s_cand[j];
       const int ly = i / kScoreEdge - 1, lx = i % kScoreEdge - 1;
-      if (lx < 0 || lx >= kTile || ly < 0 || ly >= kTile) continue;  // the ring around the tile
       const int x = x0 + lx, y = y0 + ly;
-      if (x < margin || x > W - 1 - margin || y < margin || y > H - 1 - margin) continue;
-      const uint8_t* sc = &s_score[i];
+      // branch-free test: tile pixels inside the margins (the ring around the
+      // tile and margin pixels read an interior slot instead, and fail)
+      const bool inside = (unsigned)lx < (unsigned)kTile && (unsigned)ly < (unsigned)kTile && x >= margin &&
+                          x <= W - 1 - margin && y >= margin && y <= H - 1 - margin;
+      const uint8_t* sc = &s_score[inside ? i : kScoreEdge + 1];
       const int s = sc[0];
-      if (!s) continue;
-      const bool peak = s > sc[-kScoreEdge - 1] && s > sc[-kScoreEdge] && s > sc[-kScoreEdge + 1] && s > sc[-1] &&
-                        s > sc[1] && s > sc[kScoreEdge - 1] && s > sc[kScoreEdge] && s > sc[kScoreEdge + 1];
-      if (!peak) continue;
-      const uint32_t key = ((uint32_t)(s - 1) << 24) | (0xFFFFFFu - (uint32_t)(y * W + x));
-      const int cell = (y / cd.cell) * cd.ncx + x / cd.cell;
-      atomicMax(&keys[cell], key);
+      const bool peak = inside & (s != 0) & (s > sc[-kScoreEdge - 1]) & (s > sc[-kScoreEdge]) &
+                        (s > sc[-kScoreEdge + 1]) & (s > sc[-1]) & (s > sc[1]) & (s > sc[kScoreEdge - 1]) &
+                        (s > sc[kScoreEdge]) & (s > sc[kScoreEdge + 1]);
+      if (peak) {
+        const uint32_t key = ((uint32_t)(s - 1) << 24) | (0xFFFFFFu - (uint32_t)(y * W + x));
+        const int cell = (y / cd.cell) * cd.ncx + x / cd.cell;
+        atomicMax(&keys[cell], key);
+      }
     }
   }
 
