@@ -168,6 +168,23 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
+// Sums of K values per level (level-major v[K*l + k]) over the first nl of L
+// levels: all L levels in one call when all are used (the plain budget), else
+// two levels at a time behind wave-uniform tests, so a short learned budget
+// does not reduce the levels it never visits.
+template <int L, int K, int l = 0>
+__device__ __forceinline__ void level_pair_sums(float* v, int nl, int lane) {
+  if constexpr (l < L) {
+    if (l < nl) wave_sums<(l + 1 < L ? 2 : 1) * K>(v + K * l, lane);
+    level_pair_sums<L, K, l + 2>(v, nl, lane);
+  }
+}
+template <int L, int K>
+__device__ __forceinline__ void level_sums(float* v, int nl, int lane) {
+  if (nl >= L) wave_sums<K * L>(v, lane);
+  else level_pair_sums<L, K>(v, nl, lane);
+}
+
 struct PassOut {
   int status;
   float tx, ty, th, resid;
@@ -220,7 +237,7 @@ __device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc_in, int ssrc_in,
   float mean[L];
 #pragma unroll
   for (int l = 0; l < L; ++l) mean[l] = wgt * I0[l];
-  wave_sums<L>(mean, lane);
+  level_sums<L, 1>(mean, nl, lane);
   float J0[L], J1[L], J2[L], hs[6 * L];
 #pragma unroll
   for (int l = 0; l < L; ++l) {
@@ -237,9 +254,13 @@ __device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc_in, int ssrc_in,
     hs[6 * l + 4] = wgt * J1[l] * J2[l];
     hs[6 * l + 5] = wgt * J2[l] * J2[l];
   }
-  wave_sums<6 * L>(hs, lane);
+  level_sums<L, 6>(hs, nl, lane);
 #pragma unroll
   for (int l = 0; l < L; ++l) {
+    valid[l] = false;
+    k[3 * l + 0] = k[3 * l + 1] = k[3 * l + 2] = 0.f;
+    G0[l] = G1[l] = G2[l] = 0.f;
+    if (l >= nl) continue;  // a level the pass does not visit
     const float h00 = hs[6 * l + 0], h01 = hs[6 * l + 1], h02 = hs[6 * l + 2];
     const float h11 = hs[6 * l + 3], h12 = hs[6 * l + 4], h22 = hs[6 * l + 5];
     // 3x3 inverse by cofactors (H symmetric); degenerate when det <= 1e-6 (tr/3)^3
@@ -263,7 +284,7 @@ __device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc_in, int ssrc_in,
     k[3 * l + 1] = G1[l] * T[l];
     k[3 * l + 2] = G2[l] * T[l];
   }
-  wave_sums<3 * L>(k, lane);
+  level_sums<L, 3>(k, nl, lane);
   // ---- coarse-to-fine Gauss-Newton (eqs. 4-5) ------------------------------
   float tx = ldexpf(ix, 1 - nl), ty = ldexpf(iy, 1 - nl), th = ith;
 #pragma unroll
