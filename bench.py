@@ -42,6 +42,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model_name():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def track_flops_per_call(levels, iters):
     """Algorithmic FP32 operations of one forward-backward track.
 
@@ -301,9 +312,17 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and args.init == "const_vel":
         import oracle
-        log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s")
-        fos = [oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo, oracle.params_for(w))
-               for w in ws]
+        nproc = os.cpu_count() or 1
+        model = cpu_model_name()
+        unit = "stream-frames/s" if batched else "frames/s"
+
+        def new_oracles():
+            return [oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo, oracle.params_for(w))
+                    for w in ws]
+
+        # (i) one thread, stream after stream, frame by frame
+        log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s (one thread)")
+        fos = new_oracles()
         n, c0 = 0, time.perf_counter()
         while n < n_frames and (time.perf_counter() - c0 < args.cpu_seconds or n < 3):
             for fo, q in zip(fos, seqs):
@@ -313,10 +332,29 @@ def main():
         cpu_s = time.perf_counter() - c0
         for fo in fos:
             fo.close()
-        unit = "stream-frames/s" if batched else "frames/s"
         cpu = {"value": n * len(ws) / cpu_s, "unit": unit, "cores": 1, "kind": "oracle",
                "sample": f"first {n} frames of the same {args.workload} sequence(s), single-threaded C++ oracle "
-                         f"(-O2), {cpu_s:.1f} s"}
+                         f"(-O2), {cpu_s:.1f} s", "nproc": nproc, "cpu_model": model}
+        if batched:
+            # (ii) one thread per stream (the oracle's calls release the GIL), the same frames
+            from concurrent.futures import ThreadPoolExecutor
+            threads = min(len(ws), nproc)
+            log(f"cpu baseline: oracle, one thread per stream ({threads} threads), {n} frames")
+            fos = new_oracles()
+
+            def run_stream(i):
+                for t in range(n):
+                    fos[i].push(list(seqs[i].frames[t]))
+                    fos[i].records()
+
+            c0 = time.perf_counter()
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                list(ex.map(run_stream, range(len(ws))))
+            thr_s = time.perf_counter() - c0
+            for fo in fos:
+                fo.close()
+            cpu["threaded"] = {"value": n * len(ws) / thr_s, "unit": unit, "threads": threads,
+                               "sample": f"the same {n} frames, one thread per stream, {thr_s:.1f} s"}
 
     wall_ms = np.array(wall) * 1e3
     value = steps_per_s * len(ws)
