@@ -109,6 +109,9 @@ def main():
     ap.add_argument("--weights", default=None, help="learned-init weights (default: the package's for the workload)")
     ap.add_argument("--levels", type=int, default=None, help="override the pyramid levels")
     ap.add_argument("--iters", type=int, default=None, help="override the Gauss-Newton iterations per level")
+    ap.add_argument("--k-per-cell", type=int, default=None, help="keypoints per detection cell (default 1)")
+    ap.add_argument("--preset", choices=["standard", "lite"], default="standard",
+                    help="lite: minimum FAST threshold 20, cells of 82 px, 3 Gauss-Newton iterations (Sec. V)")
     ap.add_argument("--learned-levels", type=int, default=2)
     ap.add_argument("--learned-iters", type=int, default=3)
     ap.add_argument("--waves-per-cu", type=int, default=None,
@@ -148,6 +151,10 @@ def main():
     else:
         ws = [synthgen.WORKLOADS[args.workload]]
     over = {}
+    if args.preset == "lite":
+        over.update(thresholds=(40, 20), cell_size=82, gn_iters=3)
+    if args.k_per_cell:
+        over["k_per_cell"] = args.k_per_cell
     if args.levels:
         over["levels"] = args.levels
     if args.iters:
@@ -375,6 +382,8 @@ def main():
                    "cameras": sum(w.n_cams for w in ws),
                    "sizes": sorted({f"{w.width}x{w.height}x{w.n_cams}" for w in ws}),
                    "levels": L, "gn_iters": N, "max_keypoints": sorted({w.max_keypoints for w in ws}),
+                   "preset": args.preset, "k_per_cell": w0.k_per_cell,
+                   "cell_size": sorted({w.cell_size for w in ws}), "thresholds": list(w0.thresholds),
                    "init": args.init, "launch": args.launch, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
                    "stereo_mode": ["speculative", "deferred"][smode],
                    "autotuned": tuned is not None, "parallelism": "single_gpu",

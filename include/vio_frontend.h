@@ -82,9 +82,9 @@ typedef struct vio_frontend_params {
   int32_t levels;         /* pyramid levels L including level 0, 1..VIO_MAX_LEVELS (Sec. III-C) */
   int32_t gn_iters;       /* Gauss-Newton iterations per level N, 1..32 (Sec. III-E) */
   int32_t cell_size;      /* default cell edge C in px (Sec. III-D) */
-  int32_t k_per_cell;     /* keypoints per cell; this build implements k = 1 (Sec. III-D) */
+  int32_t k_per_cell;     /* keypoints per cell k, 1..8 (Sec. III-D) */
   int32_t n_thresholds;   /* 1..4 */
-  int32_t thresholds[4];  /* FAST threshold walk, e.g. 40, 20, 10, 5 (Sec. III-D) */
+  int32_t thresholds[4];  /* FAST threshold walk, strictly decreasing, e.g. 40, 20, 10, 5 (Sec. III-D) */
   int32_t edge_margin;    /* detections keep this distance to the border, >= 4 px */
   int32_t max_keypoints;  /* default per-camera keypoint cap */
   float fb_threshold;     /* forward-backward distance limit in px (Sec. III-E) */
@@ -171,7 +171,7 @@ void vio_frontend_default_params(vio_frontend_params* p);
  * Allocates every device buffer and the pinned host staging here; nothing is
  * allocated per frame. On success *out receives the handle (caller frees it
  * with vio_frontend_destroy). Errors: VIO_EINVAL, VIO_ENOMEM, VIO_EDEVICE,
- * VIO_EUNSUPPORTED (k_per_cell != 1, learned init without weights). */
+ * VIO_EUNSUPPORTED (a pyramid depth whose tile does not fit in LDS). */
 int vio_frontend_create(const vio_stream_desc* streams, int32_t n_streams, const vio_frontend_params* params,
                         vio_frontend** out);
 
@@ -234,8 +234,9 @@ int vio_frontend_get_pyramid(vio_frontend* h, int32_t stream, int32_t camera, in
                              size_t capacity);
 
 /* Diagnostics: per-cell detector winners of the last frame of a detecting
- * camera (mono or left), before masking and the cap: out[3*cell + {0,1,2}] =
- * x, y, score, or -1, -1, -1 for a cell without a corner. *n_out = cells. */
+ * camera (mono or left), before masking and the cap, k per cell in rank order
+ * (score desc, y asc, x asc): out[3*(cell*k + rank) + {0,1,2}] = x, y, score,
+ * or -1, -1, -1 for an empty rank. *n_out = cells * k. */
 int vio_frontend_get_cell_winners(vio_frontend* h, int32_t stream, int32_t camera, int32_t* out,
                                   int32_t capacity, int32_t* n_out);
 

@@ -210,7 +210,7 @@ def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40
 
 def params_for(workload, **overrides) -> Params:
     kw = dict(levels=workload.levels, gn_iters=workload.gn_iters, cell_size=workload.cell_size,
-              thresholds=workload.thresholds, edge_margin=workload.edge_margin,
+              k_per_cell=workload.k_per_cell, thresholds=workload.thresholds, edge_margin=workload.edge_margin,
               max_keypoints=workload.max_keypoints, fb_threshold=workload.fb_threshold,
               disparity0=workload.disparity0)
     kw.update(overrides)

@@ -60,6 +60,7 @@ struct CamDesc {
   int w, h, levels;
   int cap;             // keypoint capacity of the state buffers
   int cell, ncx, ncy, ncells;
+  int kcell, nslots;   // keypoints per cell k; winner key slots ncells * k (cell-major)
   int detect;          // 1: mono camera or left camera of a pair
   int partner;         // right camera of a left camera, left camera of a right one, else -1
   int stream;
@@ -69,8 +70,8 @@ struct CamDesc {
   uint8_t* lvl[2][kMaxLevels];       // two pyramid slots (frame parity)
   Kp* state[2];                      // keypoint state, double-buffered by frame parity
   TrackRes* res;                     // temporal results [cap]
-  uint32_t* keys[2];                 // per-cell packed winner keys, by frame parity [ncells]
-  TrackRes* sres;                    // stereo match of every cell winner [ncells]
+  uint32_t* keys[2];                 // packed winner keys, slot cell * k + rank, by frame parity [nslots]
+  TrackRes* sres;                    // stereo match of every winner slot [nslots]
   vio_track* rec;                    // output records [rec_cap], in mapped pinned host memory
   int32_t* rec_count_out;            // record count of the last frame, mapped pinned host memory
   int32_t* stats_out;                // [kCamStats] counts of the last frame (CamStat), mapped host memory
@@ -124,7 +125,7 @@ struct Counters {
 struct Tuning {
   int levels, iters;
   float fb_threshold, disparity0;
-  int k, tmin, margin;
+  int tmin, margin;
   int learned;            // temporal tracks start from the learned guess
   int llevels, liters;    // tracker budget from the guess
   float rho;              // residual RMS above which a learned track falls back

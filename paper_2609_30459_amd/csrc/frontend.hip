@@ -28,6 +28,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxCellsAbi = 8192;  // matches the selection kernel's LDS tables
+constexpr int kMaxPerCell = 8;
+static_assert(kMaxCellsAbi * kMaxPerCell <= 65536, "the selection kernel keeps key slot indices in 16 bits");
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -162,6 +164,8 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   if (p->n_thresholds < 1 || p->n_thresholds > 4) return why = "n_thresholds out of 1..4", VIO_EINVAL;
   for (int i = 0; i < p->n_thresholds; ++i)
     if (p->thresholds[i] < 0 || p->thresholds[i] > 254) return why = "threshold out of 0..254", VIO_EINVAL;
+  for (int i = 1; i < p->n_thresholds; ++i)
+    if (p->thresholds[i] >= p->thresholds[i - 1]) return why = "thresholds must decrease", VIO_EINVAL;
   if (p->edge_margin < 4) return why = "edge_margin below 4", VIO_EINVAL;
   if (p->track_waves_per_cu < 0 || p->track_waves_per_cu > 64) return why = "track_waves_per_cu out of 0..64", VIO_EINVAL;
   if (p->track_block_waves != 0 && p->track_block_waves != 1 && p->track_block_waves != 2 &&
@@ -172,7 +176,7 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   if (p->stereo_mode != VIO_STEREO_SPECULATIVE && p->stereo_mode != VIO_STEREO_DEFERRED)
     return why = "stereo_mode must be VIO_STEREO_SPECULATIVE or VIO_STEREO_DEFERRED", VIO_EINVAL;
   if (!(p->fb_threshold > 0.f)) return why = "fb_threshold must be positive", VIO_EINVAL;
-  if (p->k_per_cell != 1) return why = "only k_per_cell = 1 is implemented", VIO_EUNSUPPORTED;
+  if (p->k_per_cell < 1 || p->k_per_cell > kMaxPerCell) return why = "k_per_cell out of 1..8", VIO_EINVAL;
   if (p->init_mode != VIO_INIT_CONST_VEL && p->init_mode != VIO_INIT_LEARNED) return why = "init_mode", VIO_EINVAL;
   if (p->init_mode == VIO_INIT_LEARNED) {
     if (p->learned_levels < 1 || p->learned_levels > 3 || p->learned_levels > p->levels)
@@ -272,6 +276,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       c.ncx = (si.w + si.cell - 1) / si.cell;
       c.ncy = (si.h + si.cell - 1) / si.cell;
       c.ncells = c.ncx * c.ncy;
+      c.kcell = P.k_per_cell;
+      c.nslots = c.ncells * c.kcell;
       c.detect = (si.n_cams == 1 || k % 2 == 0) ? 1 : 0;
       c.partner = si.n_cams == 1 ? -1 : (k % 2 == 0 ? cam + 1 : cam - 1);
       c.stream = s;
@@ -290,8 +296,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       for (int par = 0; par < 2; ++par) co[cam].state[par] = take(sizeof(Kp) * si.cap);
       co[cam].res = take(sizeof(TrackRes) * si.cap);
       if (c.detect) {
-        for (int par = 0; par < 2; ++par) co[cam].keys[par] = take(sizeof(uint32_t) * c.ncells);
-        co[cam].sres = take(sizeof(TrackRes) * c.ncells);
+        for (int par = 0; par < 2; ++par) co[cam].keys[par] = take(sizeof(uint32_t) * c.nslots);
+        co[cam].sres = take(sizeof(TrackRes) * c.nslots);
       }
       c.rec_cap = 2 * si.cap;
       c.row_off = rows_total;
@@ -301,14 +307,15 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       stage += (size_t)si.w * si.h;
     }
     // tracking work items: stereo matches of the left cameras' cell winners
-    // first (they run the full budget), then the temporal tracks of every camera
+    // (one per key slot) first (they run the full budget), then the temporal
+    // tracks of every camera
     for (int k = 0; k < si.n_cams; ++k) {
       const int cc = si.first_cam + k;
       if (si.n_cams >= 2 && k % 2 == 0) {
-        h->segs.push_back({cc, kModeStereo, items, h->cams[cc].ncells});
-        items += h->cams[cc].ncells;
+        h->segs.push_back({cc, kModeStereo, items, h->cams[cc].nslots});
+        items += h->cams[cc].nslots;
         si.st_segs += 1;
-        si.st_items += h->cams[cc].ncells;
+        si.st_items += h->cams[cc].nslots;
       }
     }
     for (int k = 0; k < si.n_cams; ++k) {
@@ -498,7 +505,6 @@ static Tuning tuning(const vio_frontend* h) {
   t.iters = h->P.gn_iters;
   t.fb_threshold = h->P.fb_threshold;
   t.disparity0 = h->P.disparity0;
-  t.k = h->P.k_per_cell;
   t.tmin = h->P.thresholds[h->P.n_thresholds - 1];
   t.margin = h->P.edge_margin;
   t.learned = h->learned ? 1 : 0;
@@ -968,13 +974,13 @@ int vio_frontend_get_cell_winners(vio_frontend* h, int32_t s, int32_t camera, in
   const CamDesc& c = h->cams[si.first_cam + camera];
   if (!c.detect) return fail(h, VIO_EINVAL, "camera %d does not detect", camera);
   if (si.frames == 0) return fail(h, VIO_ESTATE, "no frame pushed yet");
-  *n_out = c.ncells;
-  if (capacity < 3 * c.ncells) return VIO_ETOOSMALL;
+  *n_out = c.nslots;
+  if (capacity < 3 * c.nslots) return VIO_ETOOSMALL;
   if (!out) return VIO_EINVAL;
-  std::vector<uint32_t> keys(c.ncells);
+  std::vector<uint32_t> keys(c.nslots);
   const int par = (int)((si.frames - 1) & 1);
-  HIP_CHECK(h, hipMemcpy(keys.data(), c.keys[par], sizeof(uint32_t) * c.ncells, hipMemcpyDeviceToHost));
-  for (int i = 0; i < c.ncells; ++i) {
+  HIP_CHECK(h, hipMemcpy(keys.data(), c.keys[par], sizeof(uint32_t) * c.nslots, hipMemcpyDeviceToHost));
+  for (int i = 0; i < c.nslots; ++i) {
     if (!keys[i]) {
       out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = -1;
       continue;

@@ -8,8 +8,8 @@
 //    (the paper's early rejection on ring pairs (0,8)/(4,12) over every pixel,
 //    the survivors compacted into an LDS list, then the score over the list,
 //    both polarities at once in 16-bit halves), keeps strict 3x3 maxima with
-//    score >= the last threshold and folds each into its cell's packed key
-//    with one atomicMax, and
+//    score >= the last threshold and folds each into its cell's packed
+//    winner keys with atomicMax, and
 //  * builds every coarser pyramid level of the tile (Sec. III-C, eqs. 2-3)
 //    from LDS, recomputing the apron instead of reading it back from HBM, so
 //    level 0 is read from HBM once per frame and the L-1 level-serial
@@ -17,13 +17,16 @@
 // All arithmetic is integer, so the result is bit-identical to a level-serial
 // build.
 //
-// Threshold walk (Sec. III-D): with one keypoint per cell, walking the
-// thresholds 40, 20, 10, 5 and stopping at the first non-empty level picks the
-// same corner as one pass at the last threshold, because a strict local
-// maximum does not depend on the threshold (a neighbour below it scores less
-// than the candidate anyway). The cell winner is the maximum of
+// Threshold walk (Sec. III-D): walking the decreasing thresholds 40, 20, 10, 5
+// and stopping at the first level with k survivors in the cell keeps the same
+// top k as one pass at the last threshold. A strict local maximum does not
+// depend on the threshold (a neighbour below it scores less than the candidate
+// anyway), so the survivor sets of the levels are nested, and whenever some
+// level holds k of them its top k are the top k of the last level's set. The
+// cell's winners are its largest keys
 // key = score << 24 | (2^24 - 1 - (y * W + x)), i.e. highest score, then
-// smallest y, then smallest x.
+// smallest y, then smallest x: one atomicMax per survivor for k = 1, a chain
+// of k max-exchange slots otherwise.
 #include "fe_common.h"
 #include "wave_ops.h"
 
@@ -327,7 +330,18 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
       if (peak) {
         const uint32_t key = ((uint32_t)(s - 1) << 24) | (0xFFFFFFu - (uint32_t)(y * W + x));
         const int cell = (y / cd.cell) * cd.ncx + x / cd.cell;
-        atomicMax(&keys[cell], key);
+        if (cd.kcell == 1) {
+          atomicMax(&keys[cell], key);
+        } else {
+          // k > 1: the cell's k slots keep its best keys in descending order.
+          // Each slot keeps the larger of its value and the incoming key and
+          // passes the smaller one on, so slot values plus keys in flight
+          // always form the same multiset; once every insert has finished,
+          // slot r holds the (r+1)-th largest key (0 = none).
+          uint32_t* slot = keys + cell * cd.kcell;
+          uint32_t v = key;
+          for (int r = 0; r < cd.kcell && v != 0u; ++r) v = min(v, atomicMax(&slot[r], v));
+        }
       }
     }
   }

@@ -12,14 +12,15 @@
 //
 // Rules (all on integers):
 //  * a cell is masked when it holds at least k surviving tracks of the camera;
-//  * the candidates are the winners of the unmasked cells; the best
-//    (score desc, cell asc) up to cap - live are kept, found with a 256-bin
-//    score histogram instead of a sort;
-//  * the kept ones get consecutive identifiers in cell order;
+//  * the candidates are the (up to k) winners of the unmasked cells, in key
+//    slots cell * k + rank; the best (score desc, cell asc, rank asc) up to
+//    cap - live are kept, found with a 256-bin score histogram instead of a
+//    sort (equal scores are taken in slot order);
+//  * the kept ones get consecutive identifiers in slot (cell, rank) order;
 //  * a stereo match is accepted while the right camera has room.
 //
 // Phases: kSelectAll reads the speculative stereo match of every selected
-// cell (indexed by cell). With deferred stereo matching the work splits in
+// winner (indexed by key slot). With deferred stereo matching the work splits in
 // two launches around the stereo tracking launch: kSelectLeft does
 // everything except the right cameras' matches and leaves the new detections'
 // place in the left state in sel_base / n_sel; kSelectRight accepts the
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
   __shared__ int s_hsum[4];
   Scan sc{&s_scan, 0};
   __shared__ unsigned s_occ[kMaxCells];
-  __shared__ uint16_t s_sel[kMaxCells];
+  __shared__ uint16_t s_sel[kMaxCells];  // key slot of selection rank i (rank < cap <= kMaxCells, slot < 2^16)
   __shared__ int s_hist[256];
   __shared__ int s_thr[2];
   const int s = blockIdx.x;
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     const CamDesc& L = cams[lc];
     const FrameCam& fl = frame->cam[lc];
     const int P = fl.parity, Q = P ^ 1;
-    const int ncells = L.ncells;
+    const int ncells = L.ncells, kc = L.kcell, nslots = L.nslots;
     for (int i = threadIdx.x; i < ncells; i += kSelectThreads) s_occ[i] = 0;
     for (int i = threadIdx.x; i < 256; i += kSelectThreads) s_hist[i] = 0;
     __syncthreads();
@@ -244,9 +245,9 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
 
     // ---- candidates of unmasked cells, score histogram --------------------
     const uint32_t* keys = L.keys[P];
-    for (int i = threadIdx.x; i < ncells; i += kSelectThreads) {
+    for (int i = threadIdx.x; i < nslots; i += kSelectThreads) {
       const uint32_t key = keys[i];
-      if (key && (int)s_occ[i] < tune.k) atomicAdd(&s_hist[key >> 24], 1);
+      if (key && (int)s_occ[i / kc] < kc) atomicAdd(&s_hist[key >> 24], 1);
     }
     __syncthreads();
     // Score threshold of the best `room` candidates: thread t < 256 holds bin
@@ -286,12 +287,12 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     }
     const int thr = s_thr[0], rem = s_thr[1];
 
-    // ---- selection in cell order, identifiers, DET_t records --------------
+    // ---- selection in slot order, identifiers, DET_t records --------------
     int n_new = 0, eq_base = 0;
-    for (int c0 = 0; c0 < ncells; c0 += kSelectThreads) {
-      const int cell = c0 + (int)threadIdx.x;
-      const uint32_t key = cell < ncells ? keys[cell] : 0u;
-      const bool cand = key && (int)s_occ[cell < ncells ? cell : 0] < tune.k;
+    for (int i0 = 0; i0 < nslots; i0 += kSelectThreads) {
+      const int slot = i0 + (int)threadIdx.x;
+      const uint32_t key = slot < nslots ? keys[slot] : 0u;
+      const bool cand = key && (int)s_occ[slot < nslots ? slot / kc : 0] < kc;
       const int score = (int)(key >> 24);
       const bool is_eq = cand && score == thr;
       int eq_tot, sel_tot;
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         const int64_t id = next_id + rank;
         L.state[P][n_surv + rank] = make_kp(id, x, y, x, y, 0);
         L.rec[n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
-        s_sel[rank] = (uint16_t)cell;
+        s_sel[rank] = (uint16_t)slot;
       }
       eq_base += eq_tot;
       n_new += sel_tot;
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       *L.rec_count_out = n_rec + n_new;
       L.stats_out[kStatDetected] = n_new;
     }
-    for (int i = threadIdx.x; i < ncells; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
+    for (int i = threadIdx.x; i < nslots; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
     __syncthreads();
 
     // ---- right camera of a pair: survivors, then accepted stereo matches ---

@@ -480,8 +480,8 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
     sdst = P;
     out = cd.res + j;
   } else {
-    // stereo match of a detection: speculative (item j = cell j's winner) or
-    // deferred (item j = the frame's j-th selected detection)
+    // stereo match of a detection: speculative (item j = the winner in key
+    // slot j) or deferred (item j = the frame's j-th selected detection)
     if (tune.deferred) {
       if (j >= cnt->n_sel[c]) return;
       const Kp kp = cd.state[P][cnt->sel_base[c] + j];

@@ -59,6 +59,7 @@ class Workload:
     levels: int = 4
     gn_iters: int = 5
     cell_size: int = 32
+    k_per_cell: int = 1
     max_keypoints: int = 300
     fb_threshold: float = 0.3
     thresholds: tuple = (40, 20, 10, 5)

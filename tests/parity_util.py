@@ -27,7 +27,7 @@ def inject(fe_gpu, fe_orc, stream, n_cams):
         fe_gpu.set_keypoints(stream, c, oracle_state(fe_orc, c))
 
 
-def compare_records(gpu, orc, fb_threshold, where=""):
+def compare_records(gpu, orc, fb_threshold, where="", referee=None):
     """Element-by-element comparison; returns the list of excused margin cases.
 
     Identifiers, cameras and statuses must agree, tracked and matched positions
@@ -37,6 +37,14 @@ def compare_records(gpu, orc, fb_threshold, where=""):
     differently, returned to the caller), or when both sides lost the track and
     only the reason differs because the backward pass diverged (one left the
     image, the other returned more than 1 px away).
+
+    Positions and forward-backward distances within TOL_PX and rotations
+    within TOL_THETA, or, for a track
+    that is barely observable (a weak corner or an edge, where the Gauss-Newton
+    system is near singular and the FP32 summation order moves its fixed
+    point), no further from the FP64 track than the FP32 oracle is, plus the
+    same tolerance. referee(indices) returns the FP64 (x, y, theta, fb) of
+    the given records.
     """
     assert len(gpu) == len(orc), f"{where}: {len(gpu)} GPU records vs {len(orc)} oracle records"
     assert (gpu["camera"] == orc["camera"]).all(), where
@@ -63,19 +71,45 @@ def compare_records(gpu, orc, fb_threshold, where=""):
     same = gpu["status"] == orc["status"]
     pos = same & np.isin(orc["status"], [oracle.TRACKED, oracle.MATCHED])
     if pos.any():
-        dx = np.abs(gpu["x"][pos].astype(np.float64) - orc["x"][pos])
-        dy = np.abs(gpu["y"][pos].astype(np.float64) - orc["y"][pos])
-        worst = int(np.argmax(np.maximum(dx, dy)))
-        assert max(dx.max(), dy.max()) <= TOL_PX, \
-            f"{where}: position error {max(dx.max(), dy.max()):.2e} px at id {int(gpu['id'][pos][worst])}"
-        dth = np.abs(gpu["theta"][pos].astype(np.float64) - orc["theta"][pos])
-        assert dth.max() <= TOL_THETA, f"{where}: theta error {dth.max():.2e}"
-        dfb = np.abs(gpu["fb_err"][pos].astype(np.float64) - orc["fb_err"][pos])
-        assert dfb.max() <= TOL_PX, f"{where}: fb error {dfb.max():.2e}"
+        fields, tols = ("x", "y", "theta", "fb_err"), np.array([TOL_PX, TOL_PX, TOL_THETA, TOL_PX])
+        d = np.stack([np.abs(gpu[f][pos].astype(np.float64) - orc[f][pos]) for f in fields], 1)
+        off = np.nonzero(pos)[0][(d > tols).any(1)]
+        if len(off):
+            worst = off[int(np.argmax((d[(d > tols).any(1)] / tols).max(1)))]
+            msg = (f"{where}: id {int(gpu['id'][worst])} differs by "
+                   f"{[float(abs(gpu[f][worst] - orc[f][worst])) for f in fields]} (x, y, theta, fb)")
+            assert referee is not None, msg
+            ref = referee(off)
+            eg = np.stack([np.abs(gpu[f][off].astype(np.float64) - ref[:, j]) for j, f in enumerate(fields)], 1)
+            eo = np.stack([np.abs(orc[f][off].astype(np.float64) - ref[:, j]) for j, f in enumerate(fields)], 1)
+            bad_ref = (eg > eo + tols).any(1)
+            assert not bad_ref.any(), \
+                f"{msg}; against FP64 the GPU is off by {eg[bad_ref][0].tolist()}, the oracle by {eo[bad_ref][0].tolist()}"
     det = orc["status"] == oracle.DETECTED
     assert (gpu["x"][det] == orc["x"][det]).all() and (gpu["y"][det] == orc["y"][det]).all(), where
     assert (gpu["score"][det] == orc["score"][det]).all(), where
     return excused
+
+
+def _track_fp64(frames, t, orc, prev, idx, L, N, fb, d0):
+    """FP64 (x, y, theta, fb) of the tracked/matched records `idx` of frame t: temporal
+    tracks from the previous state with the constant-velocity start, stereo
+    matches from the same frame's detection in the left camera."""
+    out = np.zeros((len(idx), 4))
+    for n, i in enumerate(idx):
+        c, kid = int(orc["camera"][i]), int(orc["id"][i])
+        if orc["status"][i] == oracle.TRACKED:
+            kp = prev[c][prev[c]["id"] == kid][0]
+            src, dst = frames[t - 1][c], frames[t][c]
+            pt, init = (kp["x"], kp["y"]), (2.0 * kp["x"] - kp["px"], 2.0 * kp["y"] - kp["py"])
+        else:
+            det = orc[(orc["camera"] == c - 1) & (orc["id"] == kid) & (orc["status"] == oracle.DETECTED)][0]
+            src, dst = frames[t][c - 1], frames[t][c]
+            pt, init = (det["x"], det["y"]), (det["x"] - d0, det["y"])
+        r, _ = oracle.track(src, dst, np.array([pt], np.float64), np.array([init], np.float64), L, N, fb,
+                            double=True)
+        out[n] = r[0, :4]
+    return out
 
 
 def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, stream_overrides=None,
@@ -98,17 +132,26 @@ def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, 
     if push_device:
         import torch
         dev = torch.from_numpy(seq.frames[:n_frames]).cuda()
+    L, N = po.get("levels", workload.levels), po.get("gn_iters", workload.gn_iters)
+    fb, d0 = po.get("fb_threshold", workload.fb_threshold), po.get("disparity0", workload.disparity0)
     try:
         for t in range(n_frames):
             if inject_state and t > 0:
                 inject(fe_g, fe_o, 0, workload.n_cams)
+            prev = [oracle_state(fe_o, c) for c in range(workload.n_cams)]
             fe_o.push(list(seq.frames[t]))
             if push_device:
                 fe_g.push_stereo_frame_device(0, t + 1, [dev[t, c] for c in range(workload.n_cams)])
             else:
                 fe_g.push_stereo_frame(0, t + 1, list(seq.frames[t]))
             g, o = fe_g.get_tracks(0), fe_o.records()
-            exc = compare_records(g, o, workload.fb_threshold, where=f"{workload.name} frame {t}")
+
+            def referee(idx, t=t, o=o, prev=prev):
+                return _track_fp64(seq.frames, t, o, prev, idx, L, N, fb, d0)
+
+            learned = po.get("init_mode", 0) != 0
+            exc = compare_records(g, o, workload.fb_threshold, where=f"{workload.name} frame {t}",
+                                  referee=None if learned else referee)
             yield t, g, o, exc, fe_g, fe_o
     finally:
         fe_g.close()

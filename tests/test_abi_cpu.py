@@ -75,9 +75,21 @@ def test_create_rejects_bad_arguments_before_any_device_call(native):
         q = vf.default_params()
         setattr(q, field, value)
         assert _create(native, [ok], q) == native.VIO_EINVAL, field
+    for k in (0, 9):
+        q = vf.default_params()
+        q.k_per_cell = k
+        assert _create(native, [ok], q) == native.VIO_EINVAL, k
+    # the largest grid (8192 cells) takes the largest k
     q = vf.default_params()
-    q.k_per_cell = 2
-    assert _create(native, [ok], q) == native.VIO_EUNSUPPORTED
+    q.k_per_cell = 8
+    assert _create(native, [(1, 1024, 512, 300, 8)], q) != native.VIO_EINVAL
+    # the threshold walk goes down
+    for thr in ((20, 40), (40, 40), (40, 20, 20, 5)):
+        q = vf.default_params()
+        q.n_thresholds = len(thr)
+        for i, t in enumerate(thr):
+            q.thresholds[i] = t
+        assert _create(native, [ok], q) == native.VIO_EINVAL, thr
     for s in ((3, 752, 480, 300, 32), (2, 8, 480, 300, 32), (2, 5000, 480, 300, 32), (2, 4096, 4096, 300, 32),
               (1, 64, 64, 300, 2), (1, 4000, 4000, 300, 32)):
         assert _create(native, [s], p) == native.VIO_EINVAL, s
