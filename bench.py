@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--iters", type=int, default=None, help="override the Gauss-Newton iterations per level")
     ap.add_argument("--k-per-cell", type=int, default=None, help="keypoints per detection cell (default 1)")
     ap.add_argument("--preset", choices=["standard", "lite"], default="standard",
-                    help="lite: minimum FAST threshold 20, cells of 82 px, 3 Gauss-Newton iterations (Sec. V)")
+                    help="lite: minimum FAST threshold 20, cells of 82 px, 3 Gauss-Newton iterations (Sec. IV-D)")
     ap.add_argument("--learned-levels", type=int, default=2)
     ap.add_argument("--learned-iters", type=int, default=3)
     ap.add_argument("--waves-per-cu", type=int, default=None,
