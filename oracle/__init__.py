@@ -78,6 +78,8 @@ def _lib_():
         lib.orc_fe_next_id.argtypes = [vp]
         lib.orc_fe_next_id.restype = ctypes.c_int64
         lib.orc_fe_set_mlp.argtypes = [vp, vp, i32]
+        lib.orc_fe_set_motion.argtypes = [vp, i32, vp, vp, vp, f64, i32, vp, vp]
+        lib.orc_motion_start.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
         lib.orc_fe_last_fallback.argtypes = [vp]
         lib.orc_mlp_nparam.restype = i32
         lib.orc_bf16.argtypes = [ctypes.c_float]
@@ -147,6 +149,27 @@ def track(src, dst, pts, init, levels, iters, fb_threshold=0.3, double=False):
                              px.ctypes.data, py.ctypes.data, ix.ctypes.data, iy.ctypes.data, int(double),
                              out.ctypes.data, st.ctypes.data) == 0
     return out, st
+
+
+def _f64(a, n):
+    a = np.ascontiguousarray(a, np.float64).reshape(-1)
+    assert len(a) == n
+    return a
+
+
+def motion_start(K, R, t, pts, rho):
+    """Camera-model start of the warp (Sec. III-E) for keypoints pts [n, 2] at
+    inverse depths rho [n]: (start [n, 3] = x, y, theta, ok [n])."""
+    pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
+    n = len(pts)
+    x, y = np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1])
+    rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, np.float64), (n,)))
+    out = np.zeros((n, 3), np.float64)
+    ok = np.zeros(n, np.int32)
+    K, R, t = _f64(K, 4), _f64(R, 9), _f64(t, 3)
+    assert _lib_().orc_motion_start(K.ctypes.data, R.ctypes.data, t.ctypes.data, n, x.ctypes.data, y.ctypes.data,
+                                    rho.ctypes.data, out.ctypes.data, ok.ctypes.data) == 0
+    return out, ok.astype(bool)
 
 
 def klt_pass(src, dst, pts, init, levels, iters, theta0=None):
@@ -251,6 +274,17 @@ class Frontend:
         pxy = np.ascontiguousarray([[float(p[2]), float(p[3])] for p in predictions], np.float32)
         assert _lib_().orc_fe_push_pred(self._h, ptrs, strides.ctypes.data, len(pid), pid.ctypes.data,
                                         pcam.ctypes.data, pxy.ctypes.data) == 0
+
+    def set_motion(self, cam, K, R, t, rho, depths=None):
+        """Camera model K = (fx, fy, cx, cy) and predicted motion (X_new = R X_prev + t)
+        of camera `cam` for the next frame only; rho: inverse depth of keypoints
+        without their own; depths: iterable of (id, inverse depth)."""
+        K, R, t = _f64(K, 4), _f64(R, 9), _f64(t, 3)
+        depths = list(depths or [])
+        ids = np.ascontiguousarray([int(d[0]) for d in depths], np.int64)
+        rhos = np.ascontiguousarray([float(d[1]) for d in depths], np.float64)
+        assert _lib_().orc_fe_set_motion(self._h, cam, K.ctypes.data, R.ctypes.data, t.ctypes.data, float(rho),
+                                         len(ids), ids.ctypes.data, rhos.ctypes.data) == 0
 
     def records(self):
         n = ctypes.c_int()

@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <vector>
 
 namespace orc {
@@ -386,9 +387,9 @@ struct TrackOut {
 // the returned position is farther than fb_thr from p.
 template <class R>
 static TrackOut<R> track(const std::vector<Img>& src, const std::vector<Img>& dst, R px, R py, R ix, R iy, int L,
-                         int N, R fb_thr) {
+                         int N, R fb_thr, R ith = R(0)) {
   TrackOut<R> r{TRACKED, ix, iy, 0, 0, 0};
-  const PassOut<R> f = klt_pass<R>(src, dst, px, py, {ix, iy, R(0)}, L, N);
+  const PassOut<R> f = klt_pass<R>(src, dst, px, py, {ix, iy, ith}, L, N);
   if (f.status != TRACKED) {
     r.status = f.status;
     return r;
@@ -644,6 +645,45 @@ static void adam(float* P, const float* G, float* m, float* v, int t, float lr, 
   }
 }
 
+// ----------------------------------------------------------------------------
+// Camera-model initialisation, Sec. III-E: the forward warp starts from the
+// pattern projected into the new image through the camera model, using the
+// predicted pose and the keypoint's inverse depth.
+//
+// Pinhole camera with focal lengths (fx, fy) and principal point (cx, cy). The
+// pixel p at inverse depth rho is the point X = ((px-cx)/fx, (py-cy)/fy, 1)/rho
+// of the previous camera frame; the new camera frame holds X' = R X + t, seen
+// at the pixel (fx X'x/X'z + cx, fy X'y/X'z + cy). A point must lie in front
+// of the new camera: rho X'z > 1e-6 (else the keypoint keeps its usual start).
+// The start of the SE(2) warp is the projection of p, with the rotation of the
+// image x axis under the same mapping: the angle of proj(p + (1, 0)) - proj(p),
+// both at the keypoint's inverse depth.
+// ----------------------------------------------------------------------------
+struct Motion {
+  bool on = false;
+  double fx = 0, fy = 0, cx = 0, cy = 0;
+  double R[9] = {}, t[3] = {};
+  double rho = 0;                   // inverse depth of keypoints without their own
+  std::map<int64_t, double> depth;  // per-keypoint inverse depth, by id
+};
+
+static bool project_pixel(const Motion& m, double rho, double x, double y, double& ox, double& oy) {
+  const double X[3] = {(x - m.cx) / m.fx / rho, (y - m.cy) / m.fy / rho, 1.0 / rho};
+  double Xn[3];
+  for (int i = 0; i < 3; ++i) Xn[i] = m.R[3 * i] * X[0] + m.R[3 * i + 1] * X[1] + m.R[3 * i + 2] * X[2] + m.t[i];
+  if (!(rho * Xn[2] > 1e-6)) return false;
+  ox = m.fx * Xn[0] / Xn[2] + m.cx;
+  oy = m.fy * Xn[1] / Xn[2] + m.cy;
+  return true;
+}
+
+static bool motion_start(const Motion& m, double rho, double x, double y, double& ix, double& iy, double& ith) {
+  double x1, y1;
+  if (!project_pixel(m, rho, x, y, ix, iy) || !project_pixel(m, rho, x + 1.0, y, x1, y1)) return false;
+  ith = std::atan2(y1 - iy, x1 - ix);
+  return true;
+}
+
 struct Camera {
   int w, h;
   std::vector<Img> prev;
@@ -660,6 +700,7 @@ struct Frontend {
   std::vector<Record> records;
   std::vector<float> mlp;  // learned initialisation parameters (NPARAM)
   int last_fallback = 0;
+  std::vector<Motion> motion;  // per camera, for the next frame only
 };
 
 static Record make_record(int64_t id, int cam, int status, float x, float y, float th, float fb, float res,
@@ -723,7 +764,7 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     {
       for (size_t ki = 0; ki < cam.live.size(); ++ki) {
         const Keypoint& k = cam.live[ki];
-        float ix = k.x + (k.x - k.px), iy = k.y + (k.y - k.py);
+        float ix = k.x + (k.x - k.px), iy = k.y + (k.y - k.py), ith = 0.f;
         bool predicted = false;
         for (const Pred& q : preds)
           if (q.cam == c && q.id == k.id) {
@@ -731,6 +772,17 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
             iy = q.y;
             predicted = true;
           }
+        const Motion& mo = F.motion[c];
+        if (!predicted && mo.on) {
+          const auto it = mo.depth.find(k.id);
+          double mx, my, mth;
+          if (motion_start(mo, it != mo.depth.end() ? it->second : mo.rho, k.x, k.y, mx, my, mth)) {
+            ix = (float)mx;
+            iy = (float)my;
+            ith = (float)mth;
+            predicted = true;
+          }
+        }
         TrackOut<float> r;
         bool done = false;
         if (learned && !predicted) {
@@ -742,7 +794,7 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
           done = r.status == TRACKED && r.resid <= P.learned_rho;
           if (!done) F.last_fallback++;
         }
-        if (!done) r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, L, N, P.fb_threshold);
+        if (!done) r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, L, N, P.fb_threshold, ith);
         if (r.status == TRACKED) {
           surv.push_back({k.id, r.x, r.y, k.x, k.y, k.age + 1});
           rec[c].push_back(make_record(k.id, c, TRACKED, r.x, r.y, r.th, r.fb, r.resid, k.age + 1, -1));
@@ -811,6 +863,7 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     F.cams[c].prev = cur[c];
     F.cams[c].has_prev = true;
     F.records.insert(F.records.end(), rec[c].begin(), rec[c].end());
+    F.motion[c] = Motion();
   }
 }
 
@@ -951,6 +1004,7 @@ void* orc_fe_create(int n_cams, const int32_t* widths, const int32_t* heights, i
   F->n_cams = n_cams;
   F->stereo = stereo != 0;
   F->cams.resize(n_cams);
+  F->motion.resize(n_cams);
   for (int c = 0; c < n_cams; ++c) {
     F->cams[c].w = widths[c];
     F->cams[c].h = heights[c];
@@ -975,6 +1029,53 @@ int orc_fe_push_pred(void* h, const uint8_t* const* imgs, const int32_t* strides
   std::vector<Pred> v;
   for (int i = 0; i < n; ++i) v.push_back({pred_id[i], pred_cam[i], pred_xy[2 * i], pred_xy[2 * i + 1]});
   push_frame(*static_cast<Frontend*>(h), imgs, strides, v);
+  return 0;
+}
+
+// Camera model and predicted motion of camera `cam` for the next frame only:
+// K = (fx, fy, cx, cy), R row-major and t with X_new = R X_prev + t, rho the
+// inverse depth of keypoints not among the n (ids[i], rhos[i]).
+int orc_fe_set_motion(void* h, int cam, const double* K, const double* R, const double* t, double rho, int n,
+                      const int64_t* ids, const double* rhos) {
+  auto* F = static_cast<Frontend*>(h);
+  if (!F || cam < 0 || cam >= F->n_cams || !K || !R || !t || n < 0 || !(rho > 0)) return -1;
+  if (!(K[0] > 0) || !(K[1] > 0)) return -1;
+  Motion m;
+  m.on = true;
+  m.fx = K[0];
+  m.fy = K[1];
+  m.cx = K[2];
+  m.cy = K[3];
+  for (int i = 0; i < 9; ++i) m.R[i] = R[i];
+  for (int i = 0; i < 3; ++i) m.t[i] = t[i];
+  m.rho = rho;
+  for (int i = 0; i < n; ++i) {
+    if (!(rhos[i] > 0)) return -1;
+    m.depth[ids[i]] = rhos[i];
+  }
+  F->motion[cam] = m;
+  return 0;
+}
+
+// The camera-model start of n keypoints: out[3i..3i+2] = x, y, theta and
+// ok[i] = 1, or ok[i] = 0 when the point does not land in front of the camera.
+int orc_motion_start(const double* K, const double* R, const double* t, int n, const double* x, const double* y,
+                     const double* rho, double* out, int32_t* ok) {
+  if (!K || !R || !t || n < 0) return -1;
+  Motion m;
+  m.fx = K[0];
+  m.fy = K[1];
+  m.cx = K[2];
+  m.cy = K[3];
+  for (int i = 0; i < 9; ++i) m.R[i] = R[i];
+  for (int i = 0; i < 3; ++i) m.t[i] = t[i];
+  for (int i = 0; i < n; ++i) {
+    double ix = 0, iy = 0, ith = 0;
+    ok[i] = motion_start(m, rho[i], x[i], y[i], ix, iy, ith) ? 1 : 0;
+    out[3 * i] = ix;
+    out[3 * i + 1] = iy;
+    out[3 * i + 2] = ith;
+  }
   return 0;
 }
 

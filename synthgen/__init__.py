@@ -132,6 +132,31 @@ class Sequence:
             x1, y1 = self.left_to_right(cam, x1, y1)
         return x1, y1
 
+    def camera_motion(self, t, f, rho):
+        """The image motion of a left (or mono) camera from frame t to t+1 as a
+        pinhole camera moving over a fronto-parallel scene: intrinsics
+        K = (f, f, cx, cy) at the image centre, scene at inverse depth rho, and
+        the rigid motion (R, tr) with X_new = R X_prev + tr. The frame-to-frame
+        map is a similarity about the centre, p' - c = sigma Rot(alpha) (p - c) + d,
+        which is what a roll by alpha, a move along the axis to depth Z / sigma
+        and a sideways move of d Z / (sigma f) produce (Z = 1 / rho). Returns
+        (K [4], R [9] row-major, tr [3]), float64."""
+        cx, cy, _, _ = self._centres()
+        if self.warp_second:
+            tx, ty, alpha = self.warp
+            sigma, d = 1.0, np.array([tx, ty])
+        else:
+            s0, phi0, ox0, oy0 = self.poses[t]
+            s1, phi1, ox1, oy1 = self.poses[t + 1]
+            sigma, alpha = s0 / s1, phi0 - phi1
+            c1, n1 = np.cos(phi1), np.sin(phi1)
+            d = np.array([c1 * (ox0 - ox1) + n1 * (oy0 - oy1), -n1 * (ox0 - ox1) + c1 * (oy0 - oy1)]) / s1
+        Z = 1.0 / rho
+        ca, sa = np.cos(alpha), np.sin(alpha)
+        R = np.array([ca, -sa, 0.0, sa, ca, 0.0, 0.0, 0.0, 1.0])
+        tr = np.array([d[0] * Z / (sigma * f), d[1] * Z / (sigma * f), Z * (1.0 / sigma - 1.0)])
+        return np.array([f, f, cx, cy]), R, tr
+
     def gt_stereo(self, cam_left, x, y):
         """Right-camera position of the left point (x, y)."""
         return self.left_to_right(cam_left, np.asarray(x, np.float64), np.asarray(y, np.float64))

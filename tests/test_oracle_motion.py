@@ -1,0 +1,159 @@
+"""Pins of the oracle's camera-model start (Sec. III-E: the forward warp starts
+from the pattern projected through the camera model with the predicted pose
+and the keypoint's inverse depth), against closed forms and an independent
+statement through 3D points, and of its wiring into the frame pipeline."""
+import numpy as np
+import pytest
+
+import oracle
+import synthgen
+
+K = np.array([460.0, 460.0, 375.5, 239.5])
+
+
+def _rot(axis, ang):
+    a = np.asarray(axis, np.float64) / np.linalg.norm(axis)
+    x = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + np.sin(ang) * x + (1 - np.cos(ang)) * (x @ x)
+
+
+def _pts(n=50, seed=0):
+    r = np.random.default_rng(seed)
+    return np.stack([r.uniform(0, 751, n), r.uniform(0, 479, n)], 1)
+
+
+def test_identity_motion_starts_at_the_keypoint():
+    p = _pts()
+    out, ok = oracle.motion_start(K, np.eye(3), np.zeros(3), p, np.linspace(0.1, 3.0, len(p)))
+    assert ok.all()
+    assert np.abs(out[:, :2] - p).max() < 1e-9 and np.abs(out[:, 2]).max() < 1e-12
+
+
+def test_roll_rotates_about_the_principal_point():
+    a = 0.07
+    p = _pts()
+    out, ok = oracle.motion_start(K, _rot([0, 0, 1], a), np.zeros(3), p, 0.5)
+    c, s = np.cos(a), np.sin(a)
+    d = p - K[2:]
+    want = K[2:] + np.stack([c * d[:, 0] - s * d[:, 1], s * d[:, 0] + c * d[:, 1]], 1)
+    assert ok.all() and np.abs(out[:, :2] - want).max() < 1e-9
+    assert np.abs(out[:, 2] - a).max() < 1e-12
+
+
+def test_sideways_and_forward_translation():
+    p = _pts()
+    rho = 0.25
+    out, _ = oracle.motion_start(K, np.eye(3), [0.1, -0.2, 0.0], p, rho)
+    assert np.abs(out[:, 0] - (p[:, 0] + K[0] * 0.1 * rho)).max() < 1e-9
+    assert np.abs(out[:, 1] - (p[:, 1] - K[1] * 0.2 * rho)).max() < 1e-9
+    # moving back by tz scales about the principal point by 1 / (1 + tz rho)
+    out, _ = oracle.motion_start(K, np.eye(3), [0.0, 0.0, 0.8], p, rho)
+    want = K[2:] + (p - K[2:]) / (1 + 0.8 * rho)
+    assert np.abs(out[:, :2] - want).max() < 1e-9 and np.abs(out[:, 2]).max() < 1e-12
+
+
+def test_general_motion_against_3d_points():
+    """Independent statement: scene points in 3D, projected before and after
+    the rigid motion; the rotation is that of the image of the point one
+    pixel to the right (one pixel = Z / fx in X at depth Z)."""
+    r = np.random.default_rng(3)
+    Kx = np.array([410.0, 395.0, 300.2, 210.7])
+    R = _rot(r.normal(size=3), 0.3)
+    t = np.array([0.3, -0.1, 0.2])
+    P = np.stack([r.uniform(-2, 2, 40), r.uniform(-1.5, 1.5, 40), r.uniform(2, 8, 40)], 1)
+
+    def proj(Q):
+        return np.stack([Kx[0] * Q[:, 0] / Q[:, 2] + Kx[2], Kx[1] * Q[:, 1] / Q[:, 2] + Kx[3]], 1)
+
+    p = proj(P)
+    Pn = P @ R.T + t
+    P1 = P + np.stack([P[:, 2] / Kx[0], np.zeros(40), np.zeros(40)], 1)
+    d = proj(P1 @ R.T + t) - proj(Pn)
+    out, ok = oracle.motion_start(Kx, R, t, p, 1.0 / P[:, 2])
+    assert ok.all()
+    assert np.abs(out[:, :2] - proj(Pn)).max() < 1e-8
+    assert np.abs(out[:, 2] - np.arctan2(d[:, 1], d[:, 0])).max() < 1e-10
+
+
+def test_point_behind_the_new_camera_is_rejected():
+    p = _pts(4)
+    rho = 0.5  # depth 2: moving 3 forward puts the scene behind the camera
+    _, ok = oracle.motion_start(K, np.eye(3), [0, 0, -3.0], p, rho)
+    assert not ok.any()
+    _, ok = oracle.motion_start(K, np.eye(3), [0, 0, -1.0], p, rho)
+    assert ok.all()
+
+
+@pytest.mark.parametrize("name", ["stereo752", "mono320"])
+def test_synthetic_motion_as_a_camera_predicts_the_ground_truth(name):
+    w = synthgen.WORKLOADS[name]
+    seq = synthgen.sequence(w, n_frames=2)
+    p = _pts(30, seed=5) * [w.width / 752, w.height / 480]
+    for f, rho in ((300.0, 0.2), (900.0, 1.7)):
+        Km, R, t = seq.camera_motion(0, f, rho)
+        out, ok = oracle.motion_start(Km, R, t, p, rho)
+        gx, gy = seq.gt_temporal(0, 0, p[:, 0], p[:, 1])
+        assert ok.all() and max(np.abs(out[:, 0] - gx).max(), np.abs(out[:, 1] - gy).max()) < 1e-9
+
+
+def _pipeline(motion=None, preds=None, frames=4, at=2):
+    """Runs the oracle, setting `motion` / `preds` before frame `at` only
+    (not frame 1: new keypoints have no velocity yet, so constant velocity
+    starts them at the keypoint as well)."""
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=6, n_frames=frames)
+    fe = oracle.Frontend([w.width] * 2, [w.height] * 2, True, oracle.params_for(w))
+    out = []
+    try:
+        for t in range(frames):
+            if t == at and motion:
+                motion(fe)
+            fe.push(list(seq.frames[t]), predictions=preds(fe) if t == at and preds else None)
+            out.append(fe.records())
+    finally:
+        fe.close()
+    return out
+
+
+def test_pipeline_identity_motion_equals_predictions_at_the_keypoints():
+    """R = I, t = 0 starts every temporal track at its keypoint with no
+    rotation, as a caller prediction at the keypoint does; only the camera
+    given the motion is affected, and only for one frame."""
+    def motion(fe):
+        fe.set_motion(1, K, np.eye(3), np.zeros(3), 0.5)
+
+    def preds(fe):
+        ids, xy, _, _ = fe.keypoints(1)
+        return [(int(i), 1, float(x), float(y)) for i, (x, y) in zip(ids, xy)]
+
+    a, b, plain = _pipeline(motion), _pipeline(preds=preds), _pipeline()
+    for t in range(4):
+        assert a[t].tobytes() == b[t].tobytes(), t
+    # camera 0 is untouched by camera 1's motion
+    cam0 = a[2]["camera"] == 0
+    assert a[2][cam0].tobytes() == plain[2][cam0].tobytes()
+    assert a[2].tobytes() != plain[2].tobytes()
+
+
+def test_pipeline_per_keypoint_depth_behind_the_camera_keeps_constant_velocity():
+    """A keypoint whose own inverse depth puts it behind the new camera keeps
+    the constant-velocity start; the others take the camera-model start."""
+    state = {}
+
+    def motion(fe):
+        ids, _, _, _ = fe.keypoints(0)
+        state["ids"] = ids
+        # every keypoint at depth 0.5 (behind after moving 1 forward) except those with their own depth 0.1
+        fe.set_motion(0, K, np.eye(3), [0, 0, -1.0], 2.0, depths=[(int(i), 0.1) for i in ids[::2]])
+
+    a, plain = _pipeline(motion), _pipeline()
+    ids = state["ids"]
+    def temporal(rec, sel):
+        m = (rec["camera"] == 0) & (rec["status"] != oracle.DETECTED) & np.isin(rec["id"], sel)
+        return rec[m]
+
+    behind, own = ids[1::2], ids[::2]
+    assert len(behind) > 10 and len(own) > 10
+    assert temporal(a[2], behind).tobytes() == temporal(plain[2], behind).tobytes()
+    ra, rp = temporal(a[2], own), temporal(plain[2], own)
+    assert len(ra) == len(own) and (ra["x"] != rp["x"]).mean() > 0.5
