@@ -145,6 +145,28 @@ typedef struct vio_kp_prediction {
   float x, y;
 } vio_kp_prediction;
 
+/* Pinhole camera model: focal lengths and principal point in pixels. */
+typedef struct vio_pinhole {
+  float fx, fy, cx, cy;
+} vio_pinhole;  /* 16 bytes */
+
+/* Predicted rigid motion of one camera from its previous frame to the next
+ * one: a point X of the previous camera frame is R X + t in the new one (R
+ * row-major, t in the units of 1 / inv_depth). */
+typedef struct vio_camera_motion {
+  int32_t camera;    /* camera index within the stream */
+  float R[9];
+  float t[3];
+  float inv_depth;   /* inverse depth of the camera's keypoints without their own entry, > 0 */
+} vio_camera_motion;  /* 56 bytes */
+
+/* Inverse depth of one keypoint (its landmark, as the backend estimates it). */
+typedef struct vio_kp_depth {
+  int64_t id;
+  int32_t camera;
+  float inv_depth;   /* > 0 */
+} vio_kp_depth;  /* 16 bytes */
+
 typedef struct vio_stats {
   int64_t frames;        /* frames processed by the handle */
   double last_gpu_ms;    /* device time of the last frame (first kernel to last) */
@@ -211,6 +233,30 @@ int vio_frontend_step(vio_frontend* h);
  * takes the next n_cameras entries of d_images / pitches (in stream order). */
 int vio_frontend_stage_frames_device(vio_frontend* h, int32_t n, const int32_t* streams, const int64_t* t_ns,
                                      const void* const* d_images, const int32_t* pitches);
+
+/* Sets (K != NULL) or clears (K == NULL) the pinhole model of one camera of a
+ * stream; fx, fy > 0. Needed before vio_frontend_set_motion names the camera.
+ * Errors: VIO_EINVAL. */
+int vio_frontend_set_camera_model(vio_frontend* h, int32_t stream, int32_t camera, const vio_pinhole* K);
+
+/* Camera-model initialisation (Sec. III-E: the forward warp starts from the
+ * pattern projected into the new image through the camera model, with the
+ * predicted pose and the keypoint's inverse depth), for the stream's next frame
+ * only (the next push or stage of the stream consumes it; a second call before
+ * that replaces the first). For every camera named in m[0..n_m), each temporal
+ * track without a caller prediction (vio_kp_prediction, which takes
+ * precedence) starts at the projection of its keypoint p: back-projected at the
+ * keypoint's inverse depth rho (its depths[] entry, else the camera's
+ * inv_depth) to X = ((p - c) / f, 1) / rho, moved to R X + t and projected
+ * through the same pinhole model, with the start rotation of the image x axis
+ * under that mapping. A keypoint whose point would not lie in front of the new
+ * camera keeps its usual start. Learned mode skips the network for such
+ * tracks. Host arrays are read during the call. Errors (nothing is kept):
+ * VIO_EINVAL for a camera out of range or without a model, a repeated camera,
+ * a non-finite value, inv_depth <= 0, a repeated (camera, id) depth, more
+ * depths for a camera than its keypoint cap. */
+int vio_frontend_set_motion(vio_frontend* h, int32_t stream, const vio_camera_motion* m, int32_t n_m,
+                            const vio_kp_depth* depths, int32_t n_depths);
 
 /* Copies the last frame's records of `stream` into out[0..capacity). *n_out
  * receives the record count; VIO_ETOOSMALL (nothing written) when capacity is

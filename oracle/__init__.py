@@ -58,7 +58,7 @@ def _lib_():
         lib.orc_pyramid.argtypes = [vp, i32, i32, i32, vp]
         lib.orc_fast_scores.argtypes = [vp, i32, i32, vp]
         lib.orc_detect.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, vp]
-        lib.orc_track.argtypes = [vp, vp, i32, i32, i32, i32, f64, i32, vp, vp, vp, vp, i32, vp, vp]
+        lib.orc_track.argtypes = [vp, vp, i32, i32, i32, i32, f64, i32, vp, vp, vp, vp, vp, i32, vp, vp]
         lib.orc_klt_pass.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         lib.orc_template.argtypes = [vp, i32, i32, f64, f64, vp]
         lib.orc_pattern.argtypes = [vp, vp]
@@ -134,8 +134,9 @@ def detect(img, cell, k=1, thresholds=(40, 20, 10, 5), margin=8, single_pass=Fal
     return out
 
 
-def track(src, dst, pts, init, levels, iters, fb_threshold=0.3, double=False):
-    """Forward-backward tracking; returns (xy_theta_fb_resid [n,5], status [n])."""
+def track(src, dst, pts, init, levels, iters, fb_threshold=0.3, double=False, theta0=None):
+    """Forward-backward tracking from the start `init` (and start rotations
+    theta0, default 0); returns (xy_theta_fb_resid [n,5], status [n])."""
     src, dst = _u8(src), _u8(dst)
     h, w = src.shape
     pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
@@ -145,8 +146,10 @@ def track(src, dst, pts, init, levels, iters, fb_threshold=0.3, double=False):
     ix, iy = np.ascontiguousarray(init[:, 0]), np.ascontiguousarray(init[:, 1])
     out = np.zeros((n, 5), np.float64)
     st = np.zeros(n, np.int32)
+    th = None if theta0 is None else np.ascontiguousarray(np.broadcast_to(np.asarray(theta0, np.float64), (n,)))
     assert _lib_().orc_track(src.ctypes.data, dst.ctypes.data, w, h, levels, iters, fb_threshold, n,
-                             px.ctypes.data, py.ctypes.data, ix.ctypes.data, iy.ctypes.data, int(double),
+                             px.ctypes.data, py.ctypes.data, ix.ctypes.data, iy.ctypes.data,
+                             None if th is None else th.ctypes.data, int(double),
                              out.ctypes.data, st.ctypes.data) == 0
     return out, st
 

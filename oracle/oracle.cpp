@@ -926,20 +926,22 @@ int orc_detect(const uint8_t* img, int w, int h, int C, int k, const int32_t* th
 // Forward-backward tracking of n keypoints from the pyramid of `src` to that of
 // `dst` (both level-0 images w x h). double_prec selects the FP64 instantiation.
 // out_f[i*5 + {0..4}] = x, y, theta, fb, resid; out_status[i].
+// ith: the forward pass's start rotation per keypoint (NULL: 0).
 int orc_track(const uint8_t* src, const uint8_t* dst, int w, int h, int L, int N, double fb_thr, int n,
-              const double* px, const double* py, const double* ix, const double* iy, int double_prec,
-              double* out_f, int32_t* out_status) {
+              const double* px, const double* py, const double* ix, const double* iy, const double* ith,
+              int double_prec, double* out_f, int32_t* out_status) {
   if (!src || !dst || L < 1 || N < 0 || n < 0) return -1;
   const auto S = pyramid(make_img(src, w, h), L), D = pyramid(make_img(dst, w, h), L);
   for (int i = 0; i < n; ++i) {
+    const double th0 = ith ? ith[i] : 0.0;
     if (double_prec) {
-      const auto r = track<double>(S, D, px[i], py[i], ix[i], iy[i], L, N, fb_thr);
+      const auto r = track<double>(S, D, px[i], py[i], ix[i], iy[i], L, N, fb_thr, th0);
       out_status[i] = r.status;
       const double v[5] = {r.x, r.y, r.th, r.fb, r.resid};
       std::memcpy(out_f + 5 * i, v, sizeof v);
     } else {
       const auto r = track<float>(S, D, (float)px[i], (float)py[i], (float)ix[i], (float)iy[i], L, N,
-                                  (float)fb_thr);
+                                  (float)fb_thr, (float)th0);
       out_status[i] = r.status;
       const double v[5] = {r.x, r.y, r.th, r.fb, r.resid};
       std::memcpy(out_f + 5 * i, v, sizeof v);

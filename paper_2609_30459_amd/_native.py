@@ -67,6 +67,19 @@ class vio_kp_prediction(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("camera", ctypes.c_int32), ("x", ctypes.c_float), ("y", ctypes.c_float)]
 
 
+class vio_pinhole(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class vio_camera_motion(ctypes.Structure):
+    _fields_ = [("camera", ctypes.c_int32), ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3),
+                ("inv_depth", ctypes.c_float)]
+
+
+class vio_kp_depth(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("camera", ctypes.c_int32), ("inv_depth", ctypes.c_float)]
+
+
 class vio_stats(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_int64), ("last_gpu_ms", ctypes.c_double),
                 ("last_stage_ms", ctypes.c_double * 3), ("last_learned_ms", ctypes.c_double * 2),
@@ -107,6 +120,8 @@ lib.vio_frontend_stage_frame_device.argtypes = [_vp, _i32, _i64, _vp, _vp]
 lib.vio_frontend_step.argtypes = [_vp]
 lib.vio_frontend_stage_frames_device.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
 lib.vio_frontend_get_features.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
+lib.vio_frontend_set_camera_model.argtypes = [_vp, _i32, _i32, _P(vio_pinhole)]
+lib.vio_frontend_set_motion.argtypes = [_vp, _i32, _vp, _i32, _vp, _i32]
 # learned-initialisation network (vio_mlp.h)
 VIO_MLP_NPARAM = 21123
 lib.vio_mlp_create.argtypes = [_i32, _P(_vp)]

@@ -100,6 +100,13 @@ struct FrameCam {
   int active;          // camera takes part in this frame
   int n_pred;          // caller predictions for this camera (ascending id)
   int pred_off;        // their offset in the prediction buffer
+  // camera-model start of the temporal tracks (Sec. III-E), this frame only
+  int has_motion;
+  int n_depth;         // per-keypoint inverse depths (ascending id) at depth_off in Tuning::depths
+  int depth_off;
+  float K[4];          // fx, fy, cx, cy
+  float R[9], t[3];    // X_new = R X_prev + t
+  float rho;           // inverse depth of keypoints without their own
 };
 
 struct FrameTable {
@@ -122,6 +129,13 @@ struct Counters {
   int32_t n_sel[kMaxCams];
 };
 
+// Per-keypoint inverse depth of the camera-model start, 16 bytes.
+struct KpDepth {
+  int64_t id;
+  float rho;
+  int32_t pad;
+};
+
 struct Tuning {
   int levels, iters;
   float fb_threshold, disparity0;
@@ -131,6 +145,7 @@ struct Tuning {
   float rho;              // residual RMS above which a learned track falls back
   const float* guess;     // [rows][3] network outputs (learned mode)
   int deferred;           // stereo items match the selected detections (by rank), not every cell winner
+  const KpDepth* depths;  // per-keypoint inverse depths of the camera-model start (FrameCam ranges)
 };
 
 // Learned-initialisation network on the device (see vio_mlp.h).

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -54,6 +56,9 @@ struct StreamInfo {
   int64_t staged_t = 0;
   size_t rec_off = 0, rec_n = 0;  // record range (in vio_track units) of the stream's cameras
   Graphs graph;                    // captured per-frame submit, replayed every frame
+  // camera-model start for the next frame (vio_frontend_set_motion)
+  std::vector<vio_camera_motion> motion;  // at most one per camera
+  std::vector<vio_kp_depth> depths;       // sorted by (camera, id)
 };
 
 }  // namespace
@@ -101,6 +106,8 @@ struct vio_frontend {
   int* d_stream_cams = nullptr;
   Prediction* d_pred = nullptr;
   int pred_cap = 0;
+  KpDepth* d_depth = nullptr;  // per camera at CamDesc::row_off, up to its cap
+  std::vector<vio_pinhole> K;  // per camera; fx == 0: no model
   std::vector<size_t> rec_host_off;  // per camera, in records
   // learned initialisation
   bool learned = false, mlp_ready = false;
@@ -116,6 +123,7 @@ struct vio_frontend {
   uint8_t* h_stage = nullptr;
   size_t stage_bytes = 0;
   Prediction* h_pred = nullptr;
+  KpDepth* h_depth = nullptr;
   hipStream_t stream = nullptr;
   // learned mode: the network's inputs are the previous frame's, so features
   // and network run on a second stream beside the pyramid (fork after the
@@ -226,6 +234,7 @@ void vio_frontend_destroy(vio_frontend* h) {
   if (h->h_rec) (void)hipHostFree(h->h_rec);
   if (h->h_stage) (void)hipHostFree(h->h_stage);
   if (h->h_pred) (void)hipHostFree(h->h_pred);
+  if (h->h_depth) (void)hipHostFree(h->h_depth);
   for (hipEvent_t& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   if (h->stream) (void)hipStreamDestroy(h->stream);
@@ -351,6 +360,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   const size_t o_segs_all = take(sizeof(TrackSeg) * h->segs_all.size());
   const size_t o_sc = take(sizeof(int) * h->stream_cams.size());
   const size_t o_pred = take(sizeof(Prediction) * std::max(1, h->pred_cap));
+  const size_t o_depth = take(sizeof(KpDepth) * std::max(1, h->pred_cap));
   size_t o_feat = 0, o_guess = 0, o_P = 0, o_W1 = 0, o_W2 = 0, o_W2t = 0, o_W3 = 0;
   size_t o_ghdr = 0, o_gstart = 0, o_gpos = 0, o_gidx = 0;
   if (h->learned) {
@@ -408,6 +418,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->d_segs_all = reinterpret_cast<TrackSeg*>(base + o_segs_all);
   h->d_stream_cams = reinterpret_cast<int*>(base + o_sc);
   h->d_pred = reinterpret_cast<Prediction*>(base + o_pred);
+  h->d_depth = reinterpret_cast<KpDepth*>(base + o_depth);
+  h->K.assign(n_cams, vio_pinhole{0.f, 0.f, 0.f, 0.f});
   if (h->learned) {
     h->d_feat = reinterpret_cast<float*>(base + o_feat);
     h->d_guess = reinterpret_cast<float*>(base + o_guess);
@@ -432,7 +444,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       hipHostMalloc((void**)&h->h_camstats, sizeof(int32_t) * kCamStats * n_cams) != hipSuccess ||
       hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * rec_total) != hipSuccess ||
       hipHostMalloc((void**)&h->h_stage, stage) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * std::max(1, h->pred_cap)) != hipSuccess)
+      hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * std::max(1, h->pred_cap)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_depth, sizeof(KpDepth) * std::max(1, h->pred_cap)) != hipSuccess)
     return fail(h, VIO_ENOMEM, "pinned host buffers");
   std::memset(h->h_frame, 0, sizeof(FrameTable));
   std::memset(h->h_rec_count, 0, sizeof(int32_t) * n_cams);
@@ -513,6 +526,7 @@ static Tuning tuning(const vio_frontend* h) {
   t.rho = h->P.learned_rho;
   t.guess = h->d_guess;
   t.deferred = h->P.stereo_mode == VIO_STEREO_DEFERRED;
+  t.depths = h->d_depth;
   return t;
 }
 
@@ -559,7 +573,9 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
     ~Reset() { tl_timing = KernelTiming{}; }
   } reset;
   hipError_t e;
-  if (stage == 0) return hipMemcpyAsync(h->d_frame, h->h_frame, sizeof(FrameTable), hipMemcpyHostToDevice, st);
+  if (stage == 0)
+    return hipMemcpyAsync(h->d_frame, h->h_frame, offsetof(FrameTable, cam) + sizeof(FrameCam) * h->cams.size(),
+                          hipMemcpyHostToDevice, st);
   if (stage == 1) {
     timing(kKernPyr);
     return launch_pyr_detect_range(h->d_cams, h->d_frame, ls.cam_begin, ls.cam_end, ls.tile_begin, ls.n_tiles,
@@ -715,7 +731,44 @@ static void fill_stream(vio_frontend* h, int s) {
     f.active = 1;
     f.n_pred = 0;
     f.pred_off = 0;
+    f.has_motion = 0;
+    f.n_depth = 0;
+    f.depth_off = 0;
   }
+}
+
+// Moves the stream's pending camera motion (vio_frontend_set_motion) into
+// its cameras' frame-table entries and queues the per-keypoint inverse depths'
+// upload on `st` (each camera's list at its row offset); the pending motion is
+// consumed by this frame.
+static int stage_motion(vio_frontend* h, int s, hipStream_t st) {
+  StreamInfo& si = h->streams[s];
+  if (si.motion.empty()) return VIO_OK;
+  for (const vio_camera_motion& m : si.motion) {
+    const int c = si.first_cam + m.camera;
+    FrameCam& f = h->h_frame->cam[c];
+    const CamDesc& cd = h->cams[c];
+    const vio_pinhole& K = h->K[c];
+    f.has_motion = 1;
+    f.K[0] = K.fx;
+    f.K[1] = K.fy;
+    f.K[2] = K.cx;
+    f.K[3] = K.cy;
+    for (int i = 0; i < 9; ++i) f.R[i] = m.R[i];
+    for (int i = 0; i < 3; ++i) f.t[i] = m.t[i];
+    f.rho = m.inv_depth;
+    f.depth_off = cd.row_off;
+    int n = 0;
+    for (const vio_kp_depth& d : si.depths)
+      if (d.camera == m.camera) h->h_depth[cd.row_off + n++] = KpDepth{d.id, d.inv_depth, 0};
+    f.n_depth = n;
+    if (n > 0)
+      HIP_CHECK(h, hipMemcpyAsync(h->d_depth + cd.row_off, h->h_depth + cd.row_off, sizeof(KpDepth) * n,
+                                  hipMemcpyHostToDevice, st));
+  }
+  si.motion.clear();
+  si.depths.clear();
+  return VIO_OK;
 }
 
 static void fill_frame(vio_frontend* h, int s) {
@@ -786,6 +839,8 @@ int vio_frontend_push_stereo_frame(vio_frontend* h, int32_t s, int64_t t_ns, con
   fill_frame(h, s);
   rc = upload_predictions(h, s, pred, n_pred, h->stream);
   if (rc != VIO_OK) return rc;
+  rc = stage_motion(h, s, h->stream);
+  if (rc != VIO_OK) return rc;
   rc = upload_host_images(h, s, images, strides);
   if (rc != VIO_OK) return rc;
   rc = run_frame(h, s, h->stream);
@@ -810,6 +865,8 @@ int vio_frontend_push_stereo_frame_device(vio_frontend* h, int32_t s, int64_t t_
     f.copy_l0 = 1;
   }
   hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : h->stream;
+  rc = stage_motion(h, s, st);
+  if (rc != VIO_OK) return rc;
   rc = run_frame(h, s, st);
   if (rc != VIO_OK) return rc;
   si.last_t = t_ns;
@@ -826,6 +883,8 @@ int vio_frontend_stage_frame(vio_frontend* h, int32_t s, int64_t t_ns, const uin
     if (!images[k] || strides[k] < si.w) return fail(h, VIO_EINVAL, "camera %d: null image or stride < width", k);
   fill_stream(h, s);
   rc = upload_host_images(h, s, images, strides);
+  if (rc != VIO_OK) return rc;
+  rc = stage_motion(h, s, h->stream);
   if (rc != VIO_OK) return rc;
   si.staged = true;
   si.staged_t = t_ns;
@@ -847,6 +906,8 @@ int vio_frontend_stage_frame_device(vio_frontend* h, int32_t s, int64_t t_ns, co
     f.src_pitch = pitches[k];
     f.copy_l0 = 1;
   }
+  rc = stage_motion(h, s, h->stream);
+  if (rc != VIO_OK) return rc;
   si.staged = true;
   si.staged_t = t_ns;
   return VIO_OK;
@@ -882,6 +943,57 @@ int vio_frontend_step(vio_frontend* h) {
       si.last_t = si.staged_t;
       si.staged = false;
     }
+  return VIO_OK;
+}
+
+int vio_frontend_set_camera_model(vio_frontend* h, int32_t s, int32_t camera, const vio_pinhole* K) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera %d out of range", camera);
+  if (K && !(std::isfinite(K->fx) && std::isfinite(K->fy) && std::isfinite(K->cx) && std::isfinite(K->cy) &&
+             K->fx > 0.f && K->fy > 0.f))
+    return fail(h, VIO_EINVAL, "camera model needs finite values and fx, fy > 0");
+  h->K[si.first_cam + camera] = K ? *K : vio_pinhole{0.f, 0.f, 0.f, 0.f};
+  return VIO_OK;
+}
+
+int vio_frontend_set_motion(vio_frontend* h, int32_t s, const vio_camera_motion* m, int32_t n_m,
+                            const vio_kp_depth* depths, int32_t n_depths) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  StreamInfo& si = h->streams[s];
+  if (n_m < 0 || n_depths < 0 || (n_m > 0 && !m) || (n_depths > 0 && !depths))
+    return fail(h, VIO_EINVAL, "bad motion or depth list");
+  std::vector<vio_camera_motion> mv(m, m + n_m);
+  std::vector<int> seen(si.n_cams, 0);
+  for (const vio_camera_motion& q : mv) {
+    if (q.camera < 0 || q.camera >= si.n_cams) return fail(h, VIO_EINVAL, "motion camera %d out of range", q.camera);
+    if (seen[q.camera]++) return fail(h, VIO_EINVAL, "camera %d given two motions", q.camera);
+    if (!(h->K[si.first_cam + q.camera].fx > 0.f))
+      return fail(h, VIO_EINVAL, "camera %d has no camera model", q.camera);
+    bool finite = std::isfinite(q.inv_depth);
+    for (float v : q.R) finite &= std::isfinite(v);
+    for (float v : q.t) finite &= std::isfinite(v);
+    if (!finite || !(q.inv_depth > 0.f)) return fail(h, VIO_EINVAL, "motion needs finite values and inv_depth > 0");
+  }
+  std::vector<vio_kp_depth> dv(depths, depths + n_depths);
+  std::vector<int> per_cam(si.n_cams, 0);
+  for (const vio_kp_depth& d : dv) {
+    if (d.camera < 0 || d.camera >= si.n_cams || !seen[d.camera])
+      return fail(h, VIO_EINVAL, "depth for camera %d, which has no motion", d.camera);
+    if (!std::isfinite(d.inv_depth) || !(d.inv_depth > 0.f)) return fail(h, VIO_EINVAL, "inv_depth must be > 0");
+    if (++per_cam[d.camera] > si.cap) return fail(h, VIO_EINVAL, "more depths than keypoint capacity");
+  }
+  std::stable_sort(dv.begin(), dv.end(), [](const vio_kp_depth& a, const vio_kp_depth& b) {
+    return a.camera != b.camera ? a.camera < b.camera : a.id < b.id;
+  });
+  for (size_t i = 1; i < dv.size(); ++i)
+    if (dv[i].camera == dv[i - 1].camera && dv[i].id == dv[i - 1].id) return fail(h, VIO_EINVAL, "repeated depth");
+  si.motion = std::move(mv);
+  si.depths = std::move(dv);
   return VIO_OK;
 }
 

@@ -346,8 +346,8 @@ __device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc_in, int ssrc_in,
 // passes run the one inlined copy of the alignment code.
 template <int L>
 __device__ __forceinline__ TrackRes track_fb(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px,
-                                             float py, float ix, float iy, int nl, int N, float fb_thr, float u,
-                                             float v, float wgt, int lane) {
+                                             float py, float ix, float iy, float ith, int nl, int N, float fb_thr,
+                                             float u, float v, float wgt, int lane) {
   TrackRes r;
   r.x = ix;
   r.y = iy;
@@ -359,7 +359,7 @@ __device__ __forceinline__ TrackRes track_fb(const CamDesc& csrc, int ssrc, cons
   const CamDesc* A = &csrc;
   const CamDesc* B = &cdst;
   int sa = ssrc, sb = sdst;
-  float qx = px, qy = py, gx = ix, gy = iy, gth = 0.f;
+  float qx = px, qy = py, gx = ix, gy = iy, gth = ith;
 #pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {
     const PassOut o = klt_pass<L>(*A, sa, *B, sb, qx, qy, gx, gy, gth, nl, N, u, v, wgt, lane);
@@ -441,7 +441,7 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   const CamDesc* src = &cd;
   const CamDesc* dst;
   int ssrc, sdst;
-  float px, py, ix, iy, gx = 0.f, gy = 0.f;
+  float px, py, ix, iy, ith = 0.f, gx = 0.f, gy = 0.f;
   bool try_learned = false;
   TrackRes* out;
   if (sg.mode == kModeTemporal) {
@@ -467,6 +467,42 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
         }
         if (mid_id < kp.id) lo = mid + 1;
         else hi = mid - 1;
+      }
+    }
+    if (!predicted && fc.has_motion) {
+      // camera-model start (Sec. III-E): back-project at inverse depth rho,
+      // move by (R, t), project. With (a, b) = ((p - c) / f), rho X' =
+      // R (a, b, 1) + rho t; the start rotation is the angle of
+      // proj(p + (1, 0)) - proj(p), which in the same terms is
+      // atan2((fy / fx) (R3 Z - R6 Y), R0 Z - R6 X) when both points lie in
+      // front (Z, Z + R6 / fx > 0), without subtracting two projections.
+      float rho = fc.rho;
+      const int nd = fc.n_depth;
+      if (nd > 0) {  // per-keypoint inverse depths, ascending id
+        const KpDepth* dp = tune.depths + fc.depth_off;
+        int lo = 0, hi = nd - 1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          const int64_t mid_id = dp[mid].id;
+          if (mid_id == kp.id) {
+            rho = dp[mid].rho;
+            break;
+          }
+          if (mid_id < kp.id) lo = mid + 1;
+          else hi = mid - 1;
+        }
+      }
+      const float* R = fc.R;
+      const float fx = fc.K[0], fy = fc.K[1];
+      const float a = (kp.x - fc.K[2]) / fx, b = (kp.y - fc.K[3]) / fy;
+      const float X = R[0] * a + R[1] * b + R[2] + rho * fc.t[0];
+      const float Y = R[3] * a + R[4] * b + R[5] + rho * fc.t[1];
+      const float Z = R[6] * a + R[7] * b + R[8] + rho * fc.t[2];
+      if (Z > 1e-6f && Z + R[6] / fx > 1e-6f) {
+        ix = fx * (X / Z) + fc.K[2];
+        iy = fy * (Y / Z) + fc.K[3];
+        ith = atan2f((fy / fx) * (R[3] * Z - R[6] * Y), R[0] * Z - R[6] * X);
+        predicted = true;
       }
     }
     if (tune.learned && !predicted) {
@@ -506,7 +542,7 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
 #pragma unroll 1
   for (int a = try_learned ? 0 : 1; a < 2; ++a) {
     const bool short_run = a == 0;
-    r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy,
+    r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy, short_run ? 0.f : ith,
                     short_run ? tune.llevels : tune.levels, short_run ? tune.liters : tune.iters, tune.fb_threshold,
                     u, v, wgt, lane);
     if (short_run) {

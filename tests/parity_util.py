@@ -91,10 +91,11 @@ def compare_records(gpu, orc, fb_threshold, where="", referee=None):
     return excused
 
 
-def _track_fp64(frames, t, orc, prev, idx, L, N, fb, d0):
+def _track_fp64(frames, t, orc, prev, idx, L, N, fb, d0, motion=None):
     """FP64 (x, y, theta, fb) of the tracked/matched records `idx` of frame t: temporal
-    tracks from the previous state with the constant-velocity start, stereo
-    matches from the same frame's detection in the left camera."""
+    tracks from the previous state with the constant-velocity start (or the
+    camera-model start where motion[camera] = (K, R, t, rho, {id: rho}) is
+    given), stereo matches from the same frame's detection in the left camera."""
     out = np.zeros((len(idx), 4))
     for n, i in enumerate(idx):
         c, kid = int(orc["camera"][i]), int(orc["id"][i])
@@ -102,22 +103,32 @@ def _track_fp64(frames, t, orc, prev, idx, L, N, fb, d0):
             kp = prev[c][prev[c]["id"] == kid][0]
             src, dst = frames[t - 1][c], frames[t][c]
             pt, init = (kp["x"], kp["y"]), (2.0 * kp["x"] - kp["px"], 2.0 * kp["y"] - kp["py"])
+            th0 = 0.0
+            if motion and c in motion:
+                K, R, tr, rho, own = motion[c]
+                st, ok = oracle.motion_start(K, R, tr, np.array([pt], np.float64), own.get(kid, rho))
+                if ok[0]:
+                    init, th0 = (st[0, 0], st[0, 1]), st[0, 2]
         else:
+            th0 = 0.0
             det = orc[(orc["camera"] == c - 1) & (orc["id"] == kid) & (orc["status"] == oracle.DETECTED)][0]
             src, dst = frames[t][c - 1], frames[t][c]
             pt, init = (det["x"], det["y"]), (det["x"] - d0, det["y"])
         r, _ = oracle.track(src, dst, np.array([pt], np.float64), np.array([init], np.float64), L, N, fb,
-                            double=True)
+                            double=True, theta0=th0)
         out[n] = r[0, :4]
     return out
 
 
 def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, stream_overrides=None,
-             push_device=False, launch=None):
+             push_device=False, launch=None, before_push=None):
     """Runs the oracle and the GPU frontend over the first n_frames of `seq`.
 
     params_overrides apply to both sides; launch: GPU-only launch parameters
-    (tiles, tracker shape, stereo mode), which must not change the records.
+    (tiles, tracker shape, stereo mode), which must not change the records;
+    before_push(t, fe_gpu, fe_oracle) runs before each frame's push and
+    returns the camera motions it set ({camera: (K, R, t, rho, {id: rho})}) or
+    None.
     Yields (t, gpu_records, oracle_records, excused) per frame.
     """
     import paper_2609_30459_amd as vf
@@ -139,6 +150,7 @@ def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, 
             if inject_state and t > 0:
                 inject(fe_g, fe_o, 0, workload.n_cams)
             prev = [oracle_state(fe_o, c) for c in range(workload.n_cams)]
+            motion = before_push(t, fe_g, fe_o) if before_push else None
             fe_o.push(list(seq.frames[t]))
             if push_device:
                 fe_g.push_stereo_frame_device(0, t + 1, [dev[t, c] for c in range(workload.n_cams)])
@@ -146,9 +158,10 @@ def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, 
                 fe_g.push_stereo_frame(0, t + 1, list(seq.frames[t]))
             g, o = fe_g.get_tracks(0), fe_o.records()
 
-            def referee(idx, t=t, o=o, prev=prev):
-                return _track_fp64(seq.frames, t, o, prev, idx, L, N, fb, d0)
+            def referee(idx, t=t, o=o, prev=prev, motion=motion):
+                return _track_fp64(seq.frames, t, o, prev, idx, L, N, fb, d0, motion)
 
+            # the FP64 referee rebuilds constant-velocity and camera-model starts
             learned = po.get("init_mode", 0) != 0
             exc = compare_records(g, o, workload.fb_threshold, where=f"{workload.name} frame {t}",
                                   referee=None if learned else referee)

@@ -41,6 +41,9 @@ def test_struct_layouts_match_header(native):
     assert native.TRACK_DTYPE.itemsize == 40
     assert native.KEYPOINT_DTYPE.itemsize == 32
     assert ctypes.sizeof(native.vio_kp_prediction) == 24
+    assert ctypes.sizeof(native.vio_pinhole) == 16
+    assert ctypes.sizeof(native.vio_camera_motion) == 56
+    assert ctypes.sizeof(native.vio_kp_depth) == 16
 
 
 def test_default_params_are_the_standard_configuration():
