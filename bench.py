@@ -23,6 +23,7 @@ check that both give identical records). Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -112,6 +113,17 @@ def main():
     ap.add_argument("--k-per-cell", type=int, default=None, help="keypoints per detection cell (default 1)")
     ap.add_argument("--preset", choices=["standard", "lite"], default="standard",
                     help="lite: minimum FAST threshold 20, cells of 82 px, 3 Gauss-Newton iterations (Sec. IV-D)")
+    ap.add_argument("--motion", choices=["none", "truth"], default="none",
+                    help="truth: each frame's synthetic camera motion as the predicted pose of the camera-model "
+                         "start (Sec. III-E), pinhole model of focal --focal over a scene at inverse depth 0.5")
+    ap.add_argument("--motion-noise", type=float, default=0.0, metavar="PX",
+                    help="Gaussian error (px, per axis) added to the predicted image translation")
+    ap.add_argument("--focal", type=float, default=450.0)
+    ap.add_argument("--pred-levels", type=int, default=0,
+                    help="short budget (levels) of tracks with a camera-model start; 0 = the full budget")
+    ap.add_argument("--pred-iters", type=int, default=3)
+    ap.add_argument("--pred-rho", type=float, default=None,
+                    help="residual RMS above which a short predicted track falls back (default: none)")
     ap.add_argument("--learned-levels", type=int, default=2)
     ap.add_argument("--learned-iters", type=int, default=3)
     ap.add_argument("--waves-per-cu", type=int, default=None,
@@ -182,6 +194,12 @@ def main():
     tile = tile or 64
     smode = smode or 0
     extra = dict(track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile, stereo_mode=smode)
+    short_pred = args.motion != "none" and args.pred_levels > 0
+    profiled_config = (args.init == "const_vel" and args.motion == "none" and args.preset == "standard" and
+                       not args.k_per_cell and not args.levels and not args.iters)
+    if short_pred:
+        extra.update(pred_levels=args.pred_levels, pred_iters=args.pred_iters,
+                     pred_rho=args.pred_rho if args.pred_rho is not None else 3.0e38)
     rho = None
     if args.init == "learned":
         from paper_2609_30459_amd.train_mlp import load_weights
@@ -197,6 +215,21 @@ def main():
     # each frame's device images (views into the resident sequences), all
     # cameras stream by stream, made once before any timed region
     frame_imgs = [[devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)] for t in range(n_frames)]
+    # camera-model start: the motion of frame t-1 -> t per stream (every camera of a stream takes its
+    # first camera's motion), made before any timed region
+    motions, K_of = None, None
+    if args.motion == "truth":
+        inv_depth = 0.5
+        rng = np.random.default_rng(1234)
+        K_of = [seqs[i].camera_motion(0, args.focal, inv_depth)[0] for i in ids]
+        motions = [[None] * n_frames for _ in ws]
+        for i, w in enumerate(ws):
+            for t in range(1, n_frames):
+                _, R, tr = seqs[i].camera_motion(t - 1, args.focal, inv_depth)
+                if args.motion_noise > 0:
+                    tr = tr.copy()
+                    tr[:2] += rng.normal(0.0, args.motion_noise, 2) / (args.focal * inv_depth)
+                motions[i][t] = [(c, R, tr, inv_depth) for c in range(w.n_cams)]
 
     def timed_run(eager):
         """Warmup, then the timed steps: (records per stream, wall s per step, stats per step, elapsed s)."""
@@ -204,10 +237,17 @@ def main():
         fe = vf.Frontend(streams, vf.params_for(w0, eager=eager, **extra))
         if args.init == "learned":
             fe.set_mlp(mlp_params, rho)
+        if motions is not None:
+            for i, w in enumerate(ws):
+                for c in range(w.n_cams):
+                    fe.set_camera_model(i, c, K_of[i])
         records = [[] for _ in ws]
         wall, stats = [], []
 
         def step(t):
+            if motions is not None and t > 0:
+                for i in ids:
+                    fe.set_motion(i, motions[i][t])
             if batched:
                 fe.stage_frames_device(ids, [t + 1] * len(ws), frame_imgs[t])
                 fe.step()
@@ -221,6 +261,9 @@ def main():
             step(t)
         torch.cuda.synchronize()
         log(f"timing {args.steps} steps")
+        # no garbage-collector pause inside the timed steps
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         for t in range(args.warmup, n_frames):
             ts = time.perf_counter()
@@ -229,6 +272,7 @@ def main():
             stats.append(fe.stats())
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        gc.enable()
         fe.close()
         return records, wall, stats, elapsed
 
@@ -284,10 +328,11 @@ def main():
     have_times = bool((sm[:, :3] >= 0).all())
     L, N = w0.levels, w0.gn_iters
     fb = np.array(fallbacks, np.float64)
-    if args.init == "learned":
+    if args.init == "learned" or short_pred:
         # every temporal track runs the short tracker; fallbacks rerun the full one
-        flops_step = (n_temporal * track_flops_per_call(args.learned_levels, args.learned_iters) +
-                      (fb + n_stereo) * track_flops_per_call(L, N))
+        sl, si = (args.learned_levels, args.learned_iters) if args.init == "learned" else (args.pred_levels,
+                                                                                          args.pred_iters)
+        flops_step = n_temporal * track_flops_per_call(sl, si) + (fb + n_stereo) * track_flops_per_call(L, N)
     else:
         flops_step = (n_temporal + n_stereo) * track_flops_per_call(L, N)
     pyr_b = sum(pyramid_bytes(w.width, w.height, L, w.n_cams) for w in ws)
@@ -312,7 +357,8 @@ def main():
         kd = kernels[dom]
         roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
                 "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"],
-                "traffic": measured_traffic(args.workload, dom) if args.init == "const_vel" else None,
+                # counters were taken on the default configuration only
+                "traffic": measured_traffic(args.workload, dom) if profiled_config else None,
                 "avg_ms": kd["avg_ms"]}
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ---
@@ -383,6 +429,10 @@ def main():
                    "sizes": sorted({f"{w.width}x{w.height}x{w.n_cams}" for w in ws}),
                    "levels": L, "gn_iters": N, "max_keypoints": sorted({w.max_keypoints for w in ws}),
                    "preset": args.preset, "k_per_cell": w0.k_per_cell,
+                   "motion": args.motion, **({"motion_noise_px": args.motion_noise, "focal": args.focal}
+                                             if args.motion != "none" else {}),
+                   **({"pred_levels": args.pred_levels, "pred_iters": args.pred_iters, "pred_rho": args.pred_rho}
+                      if short_pred else {}),
                    "cell_size": sorted({w.cell_size for w in ws}), "thresholds": list(w0.thresholds),
                    "init": args.init, "launch": args.launch, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
                    "stereo_mode": ["speculative", "deferred"][smode],
@@ -395,7 +445,7 @@ def main():
                        "gpu_p50": float(np.percentile(sm[:, 5], 50)), "gpu_p99": float(np.percentile(sm[:, 5], 99))},
         "accuracy": {"temporal_median_px": float(np.median(err)), "temporal_p90_px": float(np.percentile(err, 90)),
                      "stereo_median_px": float(np.median(serr)), "survival": survival},
-        "fallback_per_step": float(fb.mean()) if args.init == "learned" else None,
+        "fallback_per_step": float(fb.mean()) if args.init == "learned" or short_pred else None,
         "roofline": roof,
         "second_launch": second,
         "kernels": kernels,

@@ -104,6 +104,12 @@ typedef struct vio_frontend_params {
                                  dependent launches); VIO_STEREO_DEFERRED: only the selected detections are
                                  matched, in a second tracking launch after selection (least work). The
                                  records are the same either way. */
+  int32_t pred_levels;        /* tracker budget of a predicted temporal track (caller prediction or camera-model
+                                 start): 0 = the full budget; 1..levels = this many levels and pred_iters
+                                 iterations first, the full budget from the same start when the track is not
+                                 kept or its residual RMS exceeds pred_rho (counted as a fallback) */
+  int32_t pred_iters;
+  float pred_rho;
 } vio_frontend_params;
 
 #define VIO_STEREO_SPECULATIVE 0

@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
         ("edge_margin", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
         ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float),
         ("init_mode", ctypes.c_int32), ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32),
-        ("learned_rho", ctypes.c_float),
+        ("learned_rho", ctypes.c_float), ("pred_levels", ctypes.c_int32), ("pred_iters", ctypes.c_int32),
+        ("pred_rho", ctypes.c_float),
     ]
 
 
@@ -220,7 +221,8 @@ def inverse3(m):
 
 def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40, 20, 10, 5),
                 edge_margin=8, max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0,
-                learned_levels=2, learned_iters=3, learned_rho=0.0) -> Params:
+                learned_levels=2, learned_iters=3, learned_rho=0.0, pred_levels=0, pred_iters=0,
+                pred_rho=0.0) -> Params:
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
@@ -231,6 +233,7 @@ def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40
     p.fb_threshold, p.disparity0 = fb_threshold, disparity0
     p.init_mode, p.learned_levels, p.learned_iters, p.learned_rho = init_mode, learned_levels, learned_iters, \
         learned_rho
+    p.pred_levels, p.pred_iters, p.pred_rho = pred_levels, pred_iters, pred_rho
     return p
 
 

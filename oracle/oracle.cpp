@@ -424,6 +424,11 @@ struct Params {
   int32_t init_mode;  // 0 constant velocity, 1 learned
   int32_t learned_levels, learned_iters;
   float learned_rho;
+  // predicted tracks (caller prediction or camera-model start): 0 levels = the
+  // full budget; else this budget first, the full one from the same start when
+  // the track is not kept or its residual RMS exceeds pred_rho
+  int32_t pred_levels, pred_iters;
+  float pred_rho;
 };
 
 struct Record {  // 40 bytes
@@ -794,6 +799,13 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
           done = r.status == TRACKED && r.resid <= P.learned_rho;
           if (!done) F.last_fallback++;
         }
+        if (predicted && P.pred_levels > 0) {
+          // a predicted start needs a smaller search range: the short budget
+          // first, the full one (from the same start) when it does not hold
+          r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, P.pred_levels, P.pred_iters, P.fb_threshold, ith);
+          done = r.status == TRACKED && r.resid <= P.pred_rho;
+          if (!done) F.last_fallback++;
+        }
         if (!done) r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, L, N, P.fb_threshold, ith);
         if (r.status == TRACKED) {
           surv.push_back({k.id, r.x, r.y, k.x, k.y, k.age + 1});
@@ -1001,6 +1013,7 @@ double orc_inverse3(const double* m, double* inv) {
 // ---- frontend --------------------------------------------------------------
 void* orc_fe_create(int n_cams, const int32_t* widths, const int32_t* heights, int stereo, const Params* p) {
   if (!p || p->struct_size != sizeof(Params) || n_cams < 1 || (stereo && n_cams % 2)) return nullptr;
+  if (p->pred_levels < 0 || p->pred_levels > p->levels || (p->pred_levels > 0 && p->pred_iters < 1)) return nullptr;
   auto* F = new Frontend();
   F->P = *p;
   F->n_cams = n_cams;

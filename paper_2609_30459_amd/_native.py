@@ -55,6 +55,7 @@ class vio_frontend_params(ctypes.Structure):
         ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32), ("learned_rho", ctypes.c_float),
         ("flags", ctypes.c_uint32), ("track_waves_per_cu", ctypes.c_int32),
         ("track_block_waves", ctypes.c_int32), ("pyr_tile", ctypes.c_int32), ("stereo_mode", ctypes.c_int32),
+        ("pred_levels", ctypes.c_int32), ("pred_iters", ctypes.c_int32), ("pred_rho", ctypes.c_float),
     ]
 
 

@@ -146,6 +146,8 @@ struct Tuning {
   const float* guess;     // [rows][3] network outputs (learned mode)
   int deferred;           // stereo items match the selected detections (by rank), not every cell winner
   const KpDepth* depths;  // per-keypoint inverse depths of the camera-model start (FrameCam ranges)
+  int plevels, piters;    // short budget of predicted tracks (plevels 0: none)
+  float prho;             // residual RMS above which a predicted short track falls back
 };
 
 // Learned-initialisation network on the device (see vio_mlp.h).

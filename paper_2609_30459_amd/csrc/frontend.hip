@@ -191,6 +191,10 @@ int check_params(const vio_frontend_params* p, std::string& why) {
       return why = "learned_levels out of 1..min(3, levels)", VIO_EINVAL;
     if (p->learned_iters < 1 || p->learned_iters > 32) return why = "learned_iters out of 1..32", VIO_EINVAL;
   }
+  if (p->pred_levels < 0 || p->pred_levels > p->levels) return why = "pred_levels out of 0..levels", VIO_EINVAL;
+  if (p->pred_levels > 0 && (p->pred_iters < 1 || p->pred_iters > 32))
+    return why = "pred_iters out of 1..32", VIO_EINVAL;
+  if (std::isnan(p->pred_rho)) return why = "pred_rho is NaN", VIO_EINVAL;
   return VIO_OK;
 }
 
@@ -527,6 +531,9 @@ static Tuning tuning(const vio_frontend* h) {
   t.guess = h->d_guess;
   t.deferred = h->P.stereo_mode == VIO_STEREO_DEFERRED;
   t.depths = h->d_depth;
+  t.plevels = h->P.pred_levels;
+  t.piters = h->P.pred_iters;
+  t.prho = h->P.pred_rho;
   return t;
 }
 
@@ -693,7 +700,7 @@ static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t
     lost += st[kStatLost];
     det += st[kStatDetected];
     mat += st[kStatMatched];
-    if (h->learned) fb += st[kStatFallback];
+    fb += st[kStatFallback];
   }
   h->stats.last_fallback = fb;
   h->stats.last_tracked = tr;

@@ -240,7 +240,8 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
 
     // ---- left / mono camera: survivors and occupancy ----------------------
     int n_rec = 0;
-    const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec, tune.learned != 0);
+    const bool count_fb = tune.learned != 0 || tune.plevels > 0;
+    const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec, count_fb);
     __syncthreads();
 
     // ---- candidates of unmasked cells, score histogram --------------------
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       const FrameCam& fr = frame->cam[rc];
       const int PR = fr.parity;
       int n_rec_r = 0;
-      const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, tune.learned != 0);
+      const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, count_fb);
       if (phase == kSelectAll) {
         accept_matches(L, P, n_surv, R, fr, rc, n_new, n_surv_r, n_rec_r, [&](int i) { return L.sres[s_sel[i]]; },
                        cnt, sc);

@@ -412,12 +412,16 @@ __device__ __forceinline__ void store_result(TrackRes* dst, const TrackRes& r, i
 }
 
 // One work item: a temporal track (camera c, slot j) or the stereo match of a
-// detection (camera c, item j). With learned initialisation (tune.learned), a
-// temporal track without a caller prediction first runs tune.llevels levels
-// with tune.liters iterations from the network's guess and is kept when it
-// passes the forward-backward check with a residual RMS <= rho; otherwise the
-// plain tracker runs from the constant-velocity guess (pad[0] = 1 marks that
-// fallback).
+// detection (camera c, item j). A temporal track starts from the caller's
+// prediction, else from the camera-model projection when the frame carries a
+// motion for the camera, else from the constant-velocity guess. Two tracks
+// first try a short budget and are kept when they pass the forward-backward
+// check with a residual RMS within a limit: with learned initialisation
+// (tune.learned), an unpredicted track runs tune.llevels levels with
+// tune.liters iterations from the network's guess, and a predicted one runs
+// tune.plevels x tune.piters from its prediction when tune.plevels > 0.
+// Otherwise, and whenever the short attempt does not hold, the full budget
+// runs from the track's start (pad[0] = 1 marks such a fallback).
 template <int L>
 __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
                                              const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
@@ -441,8 +445,11 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   const CamDesc* src = &cd;
   const CamDesc* dst;
   int ssrc, sdst;
-  float px, py, ix, iy, ith = 0.f, gx = 0.f, gy = 0.f;
-  bool try_learned = false;
+  // the short attempt: start (gx, gy, gth), budget (sl, si), kept when
+  // tracked with a residual RMS <= srho, else the full budget from (ix, iy, ith)
+  float px, py, ix, iy, ith = 0.f, gx = 0.f, gy = 0.f, gth = 0.f, srho = 0.f;
+  int sl = 0, si = 0;
+  bool try_short = false;
   TrackRes* out;
   if (sg.mode == kModeTemporal) {
     if (!fc.has_prev || j >= cnt->n_live[P ^ 1][c]) return;
@@ -509,7 +516,21 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       const float* gs = tune.guess + (size_t)(cd.row_off + j) * 3;
       gx = kp.x + 16.f * gs[0];
       gy = kp.y + 16.f * gs[1];
-      try_learned = true;
+      sl = tune.llevels;
+      si = tune.liters;
+      srho = tune.rho;
+      try_short = true;
+    }
+    if (predicted && tune.plevels > 0) {
+      // a predicted start needs a smaller search range: the short budget
+      // first, the full one from the same start when it does not hold
+      gx = ix;
+      gy = iy;
+      gth = ith;
+      sl = tune.plevels;
+      si = tune.piters;
+      srho = tune.prho;
+      try_short = true;
     }
     dst = &cd;
     ssrc = P ^ 1;
@@ -540,13 +561,12 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   TrackRes r;
   int fell_back = 0;
 #pragma unroll 1
-  for (int a = try_learned ? 0 : 1; a < 2; ++a) {
+  for (int a = try_short ? 0 : 1; a < 2; ++a) {
     const bool short_run = a == 0;
-    r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy, short_run ? 0.f : ith,
-                    short_run ? tune.llevels : tune.levels, short_run ? tune.liters : tune.iters, tune.fb_threshold,
-                    u, v, wgt, lane);
+    r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy, short_run ? gth : ith,
+                    short_run ? sl : tune.levels, short_run ? si : tune.iters, tune.fb_threshold, u, v, wgt, lane);
     if (short_run) {
-      if (r.status == VIO_TRACKED && r.resid <= tune.rho) break;
+      if (r.status == VIO_TRACKED && r.resid <= srho) break;
       fell_back = 1;
     }
   }

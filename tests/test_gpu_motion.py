@@ -164,3 +164,21 @@ def test_staged_batch_with_motion_equals_single_pushes():
             batch.step()
             for s in range(3):
                 assert batch.get_tracks(s).tobytes() == single.get_tracks(s).tobytes(), (t, s)
+
+
+@pytest.mark.parametrize("pred_rho", [3.0e38, 0.03])
+def test_short_budget_of_predicted_tracks_parity(pred_rho):
+    """Predicted tracks first run 2 levels x 3 iterations; rho = 0.03 makes a
+    part of them fall back to the full budget. Records and fallback counts
+    equal the oracle's."""
+    w = synthgen.WORKLOADS["rig4"]
+    seq = synthgen.sequence(w, seq=3, n_frames=4)
+    over = dict(pred_levels=2, pred_iters=3, pred_rho=pred_rho)
+    n_fb = []
+    for t, g, o, exc, fe_g, fe_o in run_pair(w, seq, 4, params_overrides=over,
+                                              before_push=_motion_hook(w, seq, per_keypoint=False)):
+        assert len(exc) <= 1, (t, exc)
+        assert fe_g.stats()["last_fallback"] == fe_o.last_fallback, t
+        n_fb.append(fe_o.last_fallback)
+    if pred_rho < 1.0:
+        assert n_fb[3] > 0, n_fb

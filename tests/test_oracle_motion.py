@@ -157,3 +157,51 @@ def test_pipeline_per_keypoint_depth_behind_the_camera_keeps_constant_velocity()
     assert temporal(a[2], behind).tobytes() == temporal(plain[2], behind).tobytes()
     ra, rp = temporal(a[2], own), temporal(plain[2], own)
     assert len(ra) == len(own) and (ra["x"] != rp["x"]).mean() > 0.5
+
+
+def _motion_run(params_over, frames=4):
+    """stereo752 with the synthetic camera motion from frame 2 on; returns
+    every frame's records, the oracle's fallback counts and the number of
+    live keypoints (temporal tracks) before each frame."""
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=6, n_frames=frames)
+    fe = oracle.Frontend([w.width] * 2, [w.height] * 2, True, oracle.params_for(w, **params_over))
+    out, fb, live = [], [], []
+    try:
+        for t in range(frames):
+            live.append(sum(len(fe.keypoints(c)[0]) for c in range(2)))
+            if t >= 2:
+                K, R, tr = seq.camera_motion(t - 1, 420.0, 0.4)
+                for c in range(2):
+                    fe.set_motion(c, K, R, tr, 0.4)
+            fe.push(list(seq.frames[t]))
+            out.append(fe.records())
+            fb.append(fe.last_fallback)
+    finally:
+        fe.close()
+    return out, fb, live
+
+
+def test_short_budget_for_predicted_tracks_reduces_to_the_full_one():
+    """The predicted tracks' short budget: equal to the full budget it is the
+    full run (no fallback); with a residual limit below every residual each
+    predicted track falls back to the full run from the same start. Either way
+    the records equal those of the full budget alone."""
+    w = synthgen.WORKLOADS["stereo752"]
+    full, fb0, live = _motion_run({})
+    same, fb1, _ = _motion_run(dict(pred_levels=w.levels, pred_iters=w.gn_iters, pred_rho=1e9))
+    back, fb2, _ = _motion_run(dict(pred_levels=2, pred_iters=3, pred_rho=-1.0))
+    for t in range(4):
+        assert same[t].tobytes() == full[t].tobytes(), t
+        assert back[t].tobytes() == full[t].tobytes(), t
+    assert fb0 == [0] * 4 and fb1 == [0] * 4
+    # every temporal track of frames 2 and 3 had a camera-model start and fell back
+    assert fb2[:2] == [0, 0] and fb2[2:] == live[2:] and live[2] > 100
+
+
+def test_short_budget_keeps_the_predicted_tracks():
+    """With the exact motion a 2-level, 3-iteration budget keeps nearly every
+    predicted track without falling back."""
+    short, fb, _ = _motion_run(dict(pred_levels=2, pred_iters=3, pred_rho=1e9))
+    n_tr = int((short[3]["status"] == oracle.TRACKED).sum())
+    assert n_tr > 200 and fb[3] < 0.02 * n_tr, (n_tr, fb)
