@@ -229,7 +229,7 @@ def main():
                 if args.motion_noise > 0:
                     tr = tr.copy()
                     tr[:2] += rng.normal(0.0, args.motion_noise, 2) / (args.focal * inv_depth)
-                motions[i][t] = [(c, R, tr, inv_depth) for c in range(w.n_cams)]
+                motions[i][t] = vf.Frontend.motion_array([(c, R, tr, inv_depth) for c in range(w.n_cams)])
 
     def timed_run(eager):
         """Warmup, then the timed steps: (records per stream, wall s per step, stats per step, elapsed s)."""

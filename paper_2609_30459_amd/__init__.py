@@ -121,21 +121,31 @@ class Frontend:
         rc = _n.lib.vio_frontend_set_camera_model(self._h, stream, camera, ctypes.byref(k) if k is not None else None)
         self._check(rc, "vio_frontend_set_camera_model")
 
-    def set_motion(self, stream, motions, depths=None):
-        """Camera-model start for the stream's next frame. motions: iterable of
-        (camera, R [9 or 3x3], t [3], inv_depth); depths: iterable of
-        (id, camera, inv_depth)."""
+    @staticmethod
+    def motion_array(motions):
+        """ctypes array of vio_camera_motion from (camera, R [9 or 3x3], t [3],
+        inv_depth) tuples; set_motion takes it as is (no per-call conversion)."""
         motions = list(motions)
-        depths = list(depths or [])
         m = (_n.vio_camera_motion * max(1, len(motions)))()
         for q, (cam, R, t, rho) in zip(m, motions):
             q.camera, q.inv_depth = int(cam), float(rho)
             q.R[:] = [float(v) for v in np.asarray(R, np.float64).reshape(9)]
             q.t[:] = [float(v) for v in np.asarray(t, np.float64).reshape(3)]
-        d = (_n.vio_kp_depth * max(1, len(depths)))()
-        for q, (kid, cam, rho) in zip(d, depths):
-            q.id, q.camera, q.inv_depth = int(kid), int(cam), float(rho)
-        rc = _n.lib.vio_frontend_set_motion(self._h, stream, m, len(motions), d, len(depths))
+        return m, len(motions)
+
+    def set_motion(self, stream, motions, depths=None):
+        """Camera-model start for the stream's next frame. motions: iterable of
+        (camera, R [9 or 3x3], t [3], inv_depth), or the result of
+        motion_array; depths: iterable of (id, camera, inv_depth)."""
+        prebuilt = isinstance(motions, tuple) and len(motions) == 2 and isinstance(motions[1], int)
+        m, n_m = motions if prebuilt else self.motion_array(motions)
+        depths = list(depths or [])
+        d = None
+        if depths:
+            d = (_n.vio_kp_depth * len(depths))()
+            for q, (kid, cam, rho) in zip(d, depths):
+                q.id, q.camera, q.inv_depth = int(kid), int(cam), float(rho)
+        rc = _n.lib.vio_frontend_set_motion(self._h, stream, m, n_m, d, len(depths))
         self._check(rc, "vio_frontend_set_motion")
 
     def push_stereo_frame_device(self, stream, t_ns, images, hip_stream=None):
