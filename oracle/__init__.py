@@ -58,7 +58,8 @@ def _lib_():
         vp, i32, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         lib.orc_pyramid.argtypes = [vp, i32, i32, i32, vp]
         lib.orc_fast_scores.argtypes = [vp, i32, i32, vp]
-        lib.orc_detect.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, vp]
+        lib.orc_detect.argtypes = [vp, i32, i32, i32, i32, vp, i32, i32, i32, vp, vp]
+        lib.orc_fe_set_mask.argtypes = [vp, i32, vp]
         lib.orc_track.argtypes = [vp, vp, i32, i32, i32, i32, f64, i32, vp, vp, vp, vp, vp, i32, vp, vp]
         lib.orc_klt_pass.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         lib.orc_template.argtypes = [vp, i32, i32, f64, f64, vp]
@@ -123,15 +124,18 @@ def fast_scores(img):
     return out
 
 
-def detect(img, cell, k=1, thresholds=(40, 20, 10, 5), margin=8, single_pass=False):
-    """Per-cell winners [n_cells, k, 3] = (x, y, score), -1 where none."""
+def detect(img, cell, k=1, thresholds=(40, 20, 10, 5), margin=8, single_pass=False, mask=None):
+    """Per-cell winners [n_cells, k, 3] = (x, y, score), -1 where none; mask:
+    uint8 HxW, nonzero pixels hold no detection."""
     img = _u8(img)
     h, w = img.shape
     ncells = ((w + cell - 1) // cell) * ((h + cell - 1) // cell)
     thr = np.asarray(thresholds, np.int32)
     out = np.zeros((ncells, k, 3), np.int32)
+    m = None if mask is None else _u8(mask)
+    assert m is None or m.shape == img.shape
     assert _lib_().orc_detect(img.ctypes.data, w, h, cell, k, thr.ctypes.data, len(thr), margin,
-                              int(single_pass), out.ctypes.data) == 0
+                              int(single_pass), None if m is None else m.ctypes.data, out.ctypes.data) == 0
     return out
 
 
@@ -291,6 +295,11 @@ class Frontend:
         rhos = np.ascontiguousarray([float(d[1]) for d in depths], np.float64)
         assert _lib_().orc_fe_set_motion(self._h, cam, K.ctypes.data, R.ctypes.data, t.ctypes.data, float(rho),
                                          len(ids), ids.ctypes.data, rhos.ctypes.data) == 0
+
+    def set_mask(self, cam, mask):
+        """Detection mask of a camera (uint8 HxW, nonzero = no detections), None to remove."""
+        m = None if mask is None else _u8(mask)
+        assert _lib_().orc_fe_set_mask(self._h, cam, None if m is None else m.ctypes.data) == 0
 
     def records(self):
         n = ctypes.c_int()

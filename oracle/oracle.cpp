@@ -133,9 +133,12 @@ static bool corner_before(const Corner& a, const Corner& b) {
   return a.x < b.x;
 }
 
-// winners[cell] = up to k corners in rank order
+// winners[cell] = up to k corners in rank order. mask (w*h bytes, or NULL):
+// the caller's detection mask (the mask buffer of Fig. 2); a corner on a
+// nonzero mask pixel is dropped after non-maximum suppression, so it still
+// suppresses its neighbours but never becomes a winner.
 std::vector<std::vector<Corner>> detect_cells(const Img& I, int C, int k, const int* thr, int nthr, int E,
-                                              bool single_pass) {
+                                              bool single_pass, const uint8_t* mask = nullptr) {
   const std::vector<int> S = score_map(I);
   const int ncx = (I.w + C - 1) / C, ncy = (I.h + C - 1) / C;
   std::vector<std::vector<Corner>> win((size_t)ncx * ncy);
@@ -149,7 +152,8 @@ std::vector<std::vector<Corner>> detect_cells(const Img& I, int C, int k, const 
         for (int y = y0; y <= y1; ++y)
           for (int x = x0; x <= x1; ++x) {
             const int s = S[(size_t)y * I.w + x];
-            if (s >= thr[ti] && nms_survivor(S, I.w, x, y)) surv.push_back({x, y, s});
+            if (s >= thr[ti] && nms_survivor(S, I.w, x, y) && !(mask && mask[(size_t)y * I.w + x]))
+              surv.push_back({x, y, s});
           }
         std::sort(surv.begin(), surv.end(), corner_before);
         if ((int)surv.size() > k) surv.resize(k);
@@ -706,6 +710,7 @@ struct Frontend {
   std::vector<float> mlp;  // learned initialisation parameters (NPARAM)
   int last_fallback = 0;
   std::vector<Motion> motion;  // per camera, for the next frame only
+  std::vector<std::vector<uint8_t>> mask;  // per camera detection mask (empty: none)
 };
 
 static Record make_record(int64_t id, int cam, int status, float x, float y, float th, float fb, float res,
@@ -823,7 +828,8 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     Camera& left = F.cams[g];
     const Img& I0 = cur[g][0];
     const int C = P.cell_size, k = P.k_per_cell;
-    const auto win = detect_cells(I0, C, k, P.thresholds, P.n_thresholds, P.edge_margin, false);
+    const auto win = detect_cells(I0, C, k, P.thresholds, P.n_thresholds, P.edge_margin, false,
+                                  F.mask[g].empty() ? nullptr : F.mask[g].data());
     const int ncx = (I0.w + C - 1) / C, ncy = (I0.h + C - 1) / C;
     std::vector<int> occ((size_t)ncx * ncy, 0);
     for (const Keypoint& kp : left.live) {
@@ -918,9 +924,9 @@ int orc_fast_scores(const uint8_t* img, int w, int h, int32_t* out) {
 
 // Per-cell winners: out[(cell * k + r) * 3 + {0,1,2}] = x, y, score (-1 = none).
 int orc_detect(const uint8_t* img, int w, int h, int C, int k, const int32_t* thr, int nthr, int E,
-               int single_pass, int32_t* out) {
+               int single_pass, const uint8_t* mask, int32_t* out) {
   if (!img || !out || !thr || C < 1 || k < 1 || nthr < 1) return -1;
-  const auto win = detect_cells(make_img(img, w, h), C, k, thr, nthr, E, single_pass != 0);
+  const auto win = detect_cells(make_img(img, w, h), C, k, thr, nthr, E, single_pass != 0, mask);
   for (size_t cell = 0; cell < win.size(); ++cell)
     for (int r = 0; r < k; ++r) {
       int32_t* o = out + (cell * k + r) * 3;
@@ -1020,6 +1026,7 @@ void* orc_fe_create(int n_cams, const int32_t* widths, const int32_t* heights, i
   F->stereo = stereo != 0;
   F->cams.resize(n_cams);
   F->motion.resize(n_cams);
+  F->mask.resize(n_cams);
   for (int c = 0; c < n_cams; ++c) {
     F->cams[c].w = widths[c];
     F->cams[c].h = heights[c];
@@ -1091,6 +1098,17 @@ int orc_motion_start(const double* K, const double* R, const double* t, int n, c
     out[3 * i + 1] = iy;
     out[3 * i + 2] = ith;
   }
+  return 0;
+}
+
+// Detection mask of camera `cam` (w*h bytes, row-major, nonzero = no
+// detections there) for every following frame; NULL removes it.
+int orc_fe_set_mask(void* h, int cam, const uint8_t* mask) {
+  auto* F = static_cast<Frontend*>(h);
+  if (!F || cam < 0 || cam >= F->n_cams) return -1;
+  const Camera& C = F->cams[cam];
+  if (mask) F->mask[cam].assign(mask, mask + (size_t)C.w * C.h);
+  else F->mask[cam].clear();
   return 0;
 }
 
