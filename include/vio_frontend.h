@@ -240,6 +240,18 @@ int vio_frontend_step(vio_frontend* h);
 int vio_frontend_stage_frames_device(vio_frontend* h, int32_t n, const int32_t* streams, const int64_t* t_ns,
                                      const void* const* d_images, const int32_t* pitches);
 
+/* Detection mask of a detecting camera (mono or left; the mask buffer the
+ * host uploads with the frames, Fig. 2): mask points to width x height bytes
+ * with row pitch `pitch` >= width (host memory, copied during the call); a
+ * nonzero byte means no new keypoint at that pixel. A masked corner is dropped
+ * after non-maximum suppression, so it still suppresses its neighbours, and
+ * the cell's next strongest corners compete for its k places (Sec. III-D).
+ * Stays in effect for every following frame; mask == NULL removes it. Tracked
+ * keypoints are not affected. Errors: VIO_EINVAL (stream or camera out of
+ * range, a camera that does not detect, pitch < width), VIO_EDEVICE. */
+int vio_frontend_set_detection_mask(vio_frontend* h, int32_t stream, int32_t camera, const uint8_t* mask,
+                                    int32_t pitch);
+
 /* Sets (K != NULL) or clears (K == NULL) the pinhole model of one camera of a
  * stream; fx, fy > 0. Needed before vio_frontend_set_motion names the camera.
  * Errors: VIO_EINVAL. */

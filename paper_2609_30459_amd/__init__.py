@@ -113,6 +113,18 @@ class Frontend:
                                                    pred_arr, n_pred)
         self._check(rc, "vio_frontend_push_stereo_frame")
 
+    def set_detection_mask(self, stream, camera, mask):
+        """Detection mask of a detecting camera (uint8 HxW, nonzero = no new keypoint), None to remove."""
+        if mask is None:
+            rc = _n.lib.vio_frontend_set_detection_mask(self._h, stream, camera, None, 0)
+        else:
+            m = np.ascontiguousarray(mask, np.uint8)
+            _, w, h = self.streams[stream][:3] if 0 <= stream < len(self.streams) else (0, 0, 0)
+            if w and m.shape != (h, w):
+                raise ValueError(f"mask shape {m.shape}, stream images are {(h, w)}")
+            rc = _n.lib.vio_frontend_set_detection_mask(self._h, stream, camera, m.ctypes.data, m.strides[0])
+        self._check(rc, "vio_frontend_set_detection_mask")
+
     def set_camera_model(self, stream, camera, K):
         """Pinhole model K = (fx, fy, cx, cy) of a camera, or None to clear it."""
         k = None

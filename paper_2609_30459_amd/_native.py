@@ -122,6 +122,7 @@ lib.vio_frontend_step.argtypes = [_vp]
 lib.vio_frontend_stage_frames_device.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
 lib.vio_frontend_get_features.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
 lib.vio_frontend_set_camera_model.argtypes = [_vp, _i32, _i32, _P(vio_pinhole)]
+lib.vio_frontend_set_detection_mask.argtypes = [_vp, _i32, _i32, _vp, _i32]
 lib.vio_frontend_set_motion.argtypes = [_vp, _i32, _vp, _i32, _vp, _i32]
 # learned-initialisation network (vio_mlp.h)
 VIO_MLP_NPARAM = 21123

@@ -61,6 +61,7 @@ struct CamDesc {
   int cap;             // keypoint capacity of the state buffers
   int cell, ncx, ncy, ncells;
   int kcell, nslots;   // keypoints per cell k; winner key slots ncells * k (cell-major)
+  int has_mask;        // detection mask in use (nonzero mask byte: no detection at that pixel)
   int detect;          // 1: mono camera or left camera of a pair
   int partner;         // right camera of a left camera, left camera of a right one, else -1
   int stream;
@@ -72,6 +73,7 @@ struct CamDesc {
   TrackRes* res;                     // temporal results [cap]
   uint32_t* keys[2];                 // packed winner keys, slot cell * k + rank, by frame parity [nslots]
   TrackRes* sres;                    // stereo match of every winner slot [nslots]
+  const uint8_t* mask;               // detection mask [h][w] (detecting cameras)
   vio_track* rec;                    // output records [rec_cap], in mapped pinned host memory
   int32_t* rec_count_out;            // record count of the last frame, mapped pinned host memory
   int32_t* stats_out;                // [kCamStats] counts of the last frame (CamStat), mapped host memory

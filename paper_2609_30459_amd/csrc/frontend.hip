@@ -261,7 +261,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     return o;
   };
   struct CamOffs {
-    size_t lvl[2][kMaxLevels], state[2], res, keys[2], sres, rec;
+    size_t lvl[2][kMaxLevels], state[2], res, keys[2], sres, rec, mask;
   };
   std::vector<CamOffs> co(n_cams);
   int cam = 0, tiles = 0, rows_total = 0, items = 0;
@@ -311,6 +311,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       if (c.detect) {
         for (int par = 0; par < 2; ++par) co[cam].keys[par] = take(sizeof(uint32_t) * c.nslots);
         co[cam].sres = take(sizeof(TrackRes) * c.nslots);
+        co[cam].mask = take((size_t)si.w * si.h);
       }
       c.rec_cap = 2 * si.cap;
       c.row_off = rows_total;
@@ -413,6 +414,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     if (d.detect) {
       for (int par = 0; par < 2; ++par) d.keys[par] = reinterpret_cast<uint32_t*>(base + co[c].keys[par]);
       d.sres = reinterpret_cast<TrackRes*>(base + co[c].sres);
+      d.mask = reinterpret_cast<const uint8_t*>(base + co[c].mask);
     }
   }
   h->d_cams = reinterpret_cast<CamDesc*>(base + o_cams);
@@ -963,6 +965,25 @@ int vio_frontend_set_camera_model(vio_frontend* h, int32_t s, int32_t camera, co
              K->fx > 0.f && K->fy > 0.f))
     return fail(h, VIO_EINVAL, "camera model needs finite values and fx, fy > 0");
   h->K[si.first_cam + camera] = K ? *K : vio_pinhole{0.f, 0.f, 0.f, 0.f};
+  return VIO_OK;
+}
+
+int vio_frontend_set_detection_mask(vio_frontend* h, int32_t s, int32_t camera, const uint8_t* mask,
+                                    int32_t pitch) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera %d out of range", camera);
+  const int c = si.first_cam + camera;
+  CamDesc& cd = h->cams[c];
+  if (!cd.detect) return fail(h, VIO_EINVAL, "camera %d does not detect", camera);
+  if (mask && pitch < cd.w) return fail(h, VIO_EINVAL, "mask pitch below the width");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream));
+  if (mask)
+    HIP_CHECK(h, hipMemcpy2D(const_cast<uint8_t*>(cd.mask), cd.w, mask, pitch, cd.w, cd.h, hipMemcpyHostToDevice));
+  cd.has_mask = mask ? 1 : 0;
+  HIP_CHECK(h, hipMemcpy(h->d_cams + c, &cd, sizeof(CamDesc), hipMemcpyHostToDevice));
   return VIO_OK;
 }
 

@@ -327,7 +327,9 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
       const bool peak = inside & (s != 0) & (s > sc[-kScoreEdge - 1]) & (s > sc[-kScoreEdge]) &
                         (s > sc[-kScoreEdge + 1]) & (s > sc[-1]) & (s > sc[1]) & (s > sc[kScoreEdge - 1]) &
                         (s > sc[kScoreEdge]) & (s > sc[kScoreEdge + 1]);
-      if (peak) {
+      // the caller's detection mask drops a corner after the maximum test, so
+      // a masked maximum still suppresses its neighbours
+      if (peak && (!cd.has_mask || cd.mask[y * W + x] == 0)) {
         const uint32_t key = ((uint32_t)(s - 1) << 24) | (0xFFFFFFu - (uint32_t)(y * W + x));
         const int cell = (y / cd.cell) * cd.ncx + x / cd.cell;
         if (cd.kcell == 1) {
