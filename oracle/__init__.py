@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("fb_threshold", ctypes.c_float), ("disparity0", ctypes.c_float),
         ("init_mode", ctypes.c_int32), ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32),
         ("learned_rho", ctypes.c_float), ("pred_levels", ctypes.c_int32), ("pred_iters", ctypes.c_int32),
-        ("pred_rho", ctypes.c_float),
+        ("pred_rho", ctypes.c_float), ("topology", ctypes.c_int32),
     ]
 
 
@@ -226,7 +226,7 @@ def inverse3(m):
 def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40, 20, 10, 5),
                 edge_margin=8, max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0,
                 learned_levels=2, learned_iters=3, learned_rho=0.0, pred_levels=0, pred_iters=0,
-                pred_rho=0.0) -> Params:
+                pred_rho=0.0, topology=0) -> Params:
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
@@ -238,6 +238,7 @@ def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40
     p.init_mode, p.learned_levels, p.learned_iters, p.learned_rho = init_mode, learned_levels, learned_iters, \
         learned_rho
     p.pred_levels, p.pred_iters, p.pred_rho = pred_levels, pred_iters, pred_rho
+    p.topology = topology
     return p
 
 
@@ -245,7 +246,7 @@ def params_for(workload, **overrides) -> Params:
     kw = dict(levels=workload.levels, gn_iters=workload.gn_iters, cell_size=workload.cell_size,
               k_per_cell=workload.k_per_cell, thresholds=workload.thresholds, edge_margin=workload.edge_margin,
               max_keypoints=workload.max_keypoints, fb_threshold=workload.fb_threshold,
-              disparity0=workload.disparity0)
+              disparity0=workload.disparity0, topology=1 if workload.star else 0)
     kw.update(overrides)
     return make_params(**kw)
 

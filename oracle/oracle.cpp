@@ -433,6 +433,10 @@ struct Params {
   // the track is not kept or its residual RMS exceeds pred_rho
   int32_t pred_levels, pred_iters;
   float pred_rho;
+  // cameras of a stereo frontend with 4k cameras: 0 = pairs (0,1), (2,3); 1 =
+  // a star (0 -> 1, 2, 3): detection in the first camera of each group of
+  // four, its new keypoints matched into the other three
+  int32_t topology;
 };
 
 struct Record {  // 40 bytes
@@ -822,8 +826,9 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     }
     cam.live = surv;
   }
-  // detection, selection and stereo matching per mono camera / stereo pair
-  const int group = F.stereo ? 2 : 1;
+  // detection, selection and stereo matching per mono camera, stereo pair or
+  // star group (the first camera detects, the others receive its matches)
+  const int group = !F.stereo ? 1 : (P.topology == 1 && F.n_cams % 4 == 0 ? 4 : 2);
   for (int g = 0; g < F.n_cams; g += group) {
     Camera& left = F.cams[g];
     const Img& I0 = cur[g][0];
@@ -865,15 +870,15 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
       left.live.push_back(kp);
       rec[g].push_back(make_record(kp.id, g, DETECTED, kp.x, kp.y, 0, 0, 0, 0, cd.c.score));
     }
-    if (F.stereo) {
-      Camera& right = F.cams[g + 1];
+    for (int tc = g + 1; tc < g + group; ++tc) {
+      Camera& right = F.cams[tc];
       for (const Keypoint& kp : fresh) {
         const float ix = kp.x - P.disparity0, iy = kp.y;
-        const TrackOut<float> r = track<float>(cur[g], cur[g + 1], kp.x, kp.y, ix, iy, L, N, P.fb_threshold);
+        const TrackOut<float> r = track<float>(cur[g], cur[tc], kp.x, kp.y, ix, iy, L, N, P.fb_threshold);
         int st = r.status == TRACKED ? MATCHED : r.status;
         if (st == MATCHED && (int)right.live.size() >= P.max_keypoints) st = LOST_CAP;
         if (st == MATCHED) right.live.push_back({kp.id, r.x, r.y, r.x, r.y, 0});
-        rec[g + 1].push_back(make_record(kp.id, g + 1, st, r.x, r.y, r.th, r.fb, r.resid, 0, -1));
+        rec[tc].push_back(make_record(kp.id, tc, st, r.x, r.y, r.th, r.fb, r.resid, 0, -1));
       }
     }
   }
@@ -1020,6 +1025,7 @@ double orc_inverse3(const double* m, double* inv) {
 void* orc_fe_create(int n_cams, const int32_t* widths, const int32_t* heights, int stereo, const Params* p) {
   if (!p || p->struct_size != sizeof(Params) || n_cams < 1 || (stereo && n_cams % 2)) return nullptr;
   if (p->pred_levels < 0 || p->pred_levels > p->levels || (p->pred_levels > 0 && p->pred_iters < 1)) return nullptr;
+  if (p->topology != 0 && p->topology != 1) return nullptr;
   auto* F = new Frontend();
   F->P = *p;
   F->n_cams = n_cams;

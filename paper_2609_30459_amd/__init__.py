@@ -53,7 +53,7 @@ def params_for(workload, **overrides) -> _n.vio_frontend_params:
     kw = dict(levels=workload.levels, gn_iters=workload.gn_iters, cell_size=workload.cell_size,
               k_per_cell=workload.k_per_cell, thresholds=workload.thresholds, edge_margin=workload.edge_margin,
               max_keypoints=workload.max_keypoints, fb_threshold=workload.fb_threshold,
-              disparity0=workload.disparity0)
+              disparity0=workload.disparity0, topology=1 if workload.star else 0)
     kw.update(overrides)
     return make_params(**kw)
 

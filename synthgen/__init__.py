@@ -106,12 +106,23 @@ class Sequence:
         c, sn = np.cos(phi), np.sin(phi)
         return cx + c * dx + sn * dy, cy - sn * dx + c * dy
 
+    @property
+    def views(self):
+        """Cameras per canvas: 1 mono, 2 a stereo pair, 4 a star rig."""
+        return self.frames.shape[1] // self.planes.shape[0]
+
+    def _plane(self, cam):
+        v = cam % self.views
+        return self.planes[cam // self.views][max(v, 1) - 1]
+
     def right_to_left(self, cam, x, y):
-        a, b, c = self.planes[cam // 2]
+        """Reference-view position of the point seen at (x, y) by view `cam`."""
+        a, b, c = self._plane(cam)
         return x + a * x + b * y + c, y
 
     def left_to_right(self, cam, x, y):
-        a, b, c = self.planes[cam // 2]
+        """Position in view `cam` of the reference-view point (x, y)."""
+        a, b, c = self._plane(cam)
         return (x - b * y - c) / (1.0 + a), y
 
     def gt_temporal(self, t, cam, x, y):
@@ -123,7 +134,7 @@ class Sequence:
             cx, cy, _, _ = self._centres()
             c, s = np.cos(th), np.sin(th)
             return cx + c * (x - cx) - s * (y - cy) + tx, cy + s * (x - cx) + c * (y - cy) + ty
-        right = self.stereo and cam % 2 == 1
+        right = self.views > 1 and cam % self.views != 0
         if right:
             x, y = self.right_to_left(cam, x, y)
         X, Y = self._to_canvas(t, x, y)
@@ -157,22 +168,26 @@ class Sequence:
         tr = np.array([d[0] * Z / (sigma * f), d[1] * Z / (sigma * f), Z * (1.0 / sigma - 1.0)])
         return np.array([f, f, cx, cy]), R, tr
 
-    def gt_stereo(self, cam_left, x, y):
-        """Right-camera position of the left point (x, y)."""
-        return self.left_to_right(cam_left, np.asarray(x, np.float64), np.asarray(y, np.float64))
+    def gt_stereo(self, cam_left, x, y, cam_target=None):
+        """Position in camera cam_target (default: the next camera) of the point
+        (x, y) of reference camera cam_left."""
+        tgt = cam_left + 1 if cam_target is None else cam_target
+        return self.left_to_right(tgt, np.asarray(x, np.float64), np.asarray(y, np.float64))
 
 
 def render(seed: int, width: int, height: int, n_frames: int, n_canvases: int = 1,
            stereo: bool = False, warp_second: bool = False, density: float = 1.0,
            max_t: float = 3.0, max_rot_deg: float = 2.0, max_scale: float = 0.0,
-           smooth: float = 0.8) -> Sequence:
+           smooth: float = 0.8, views: int | None = None) -> Sequence:
+    """views: cameras per canvas (1, 2, 4); default 2 with stereo, else 1."""
     lib = _load()
-    p = _Params(seed, width, height, n_frames, n_canvases, int(stereo), int(warp_second),
+    views = views or (2 if stereo else 1)
+    p = _Params(seed, width, height, n_frames, n_canvases, views - 1, int(warp_second),
                 density, max_t, max_rot_deg, max_scale, smooth)
-    n_cams = n_canvases * (2 if stereo else 1)
+    n_cams = n_canvases * views
     frames = np.zeros((n_frames, n_cams, height, width), np.uint8)
     poses = np.zeros((n_frames, 4), np.float64)
-    planes = np.zeros((n_canvases, 3), np.float64)
+    planes = np.zeros((n_canvases, max(1, views - 1), 3), np.float64)
     warp = np.zeros(3, np.float64)
     rc = lib.sg_render(ctypes.byref(p), frames.ctypes.data, poses.ctypes.data,
                        planes.ctypes.data, warp.ctypes.data)
@@ -188,4 +203,5 @@ def sequence(workload: Workload, seq: int = 0, stream: int = 0, n_frames: int | 
     if seed is None:
         seed = eval_seed(w.cfg_index, seq, stream)
     return render(seed, w.width, w.height, n_frames or w.n_frames, w.n_canvases, w.stereo,
-                  w.warp_second, w.density, w.max_t, w.max_rot_deg, w.max_scale, w.smooth)
+                  w.warp_second, w.density, w.max_t, w.max_rot_deg, w.max_scale, w.smooth,
+                  views=4 if w.star else None)

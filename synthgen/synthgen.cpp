@@ -159,7 +159,8 @@ typedef struct {
   int32_t width, height;
   int32_t n_frames;
   int32_t n_canvases;   // one per mono camera or stereo pair
-  int32_t stereo;       // 1: each canvas gives a left and a right camera
+  int32_t stereo;       // extra views per canvas: 0 mono, 1 a stereo pair (left, right), 3 a star rig
+                        // (a reference view and three views through their own disparity planes)
   int32_t warp_second;  // 1: two frames, the second is the bilinear warp of the first
   double density;       // 1.0 = 64 blobs + 32 rectangles per 320x240 area
   double max_t;         // per-frame translation bound (px)
@@ -168,24 +169,27 @@ typedef struct {
   double smooth;        // AR(1) coefficient of the per-frame motion increments
 } sg_params;
 
-// frames: [n_frames][n_cams][height][width] u8, n_cams = n_canvases * (stereo ? 2 : 1)
+// frames: [n_frames][n_cams][height][width] u8, n_cams = n_canvases * (1 + stereo)
 // poses:  [n_frames][4] = (s, phi, ox, oy): canvas X = C + s R(phi) (x - c) + o
-// planes: [n_canvases][3] = (a, b, c): right(x, y) = left(x + a x + b y + c, y)
+// planes: [n_canvases][max(1, stereo)][3] = (a, b, c): view v >= 1 of a canvas is
+//         view(x, y) = reference(x + a x + b y + c, y) with plane v - 1
 // warp:   [3] = (tx, ty, theta) of the second frame (warp_second mode only)
 // Returns 0 on success, -1 on bad arguments.
 int sg_render(const sg_params* p, uint8_t* frames, double* poses, double* planes, double* warp) {
   if (!p || !frames || !poses || !planes || !warp) return -1;
   const int W = p->width, H = p->height, T = p->n_frames;
   if (W < 16 || H < 16 || T < 1 || p->n_canvases < 1 || p->n_canvases > 8) return -1;
+  if (p->stereo != 0 && p->stereo != 1 && p->stereo != 3) return -1;
   if (p->warp_second && (T != 2 || p->stereo)) return -1;
   Rng rng(p->seed);
   const int ncan = p->n_canvases;
-  const int per = p->stereo ? 2 : 1;
+  const int per = 1 + p->stereo;
+  const int npl = p->stereo ? p->stereo : 1;  // planes per canvas
   const int ncam = ncan * per;
   const int CW = 3 * W, CH = 3 * H;
   std::vector<Canvas> canv(ncan);
   for (int k = 0; k < ncan; ++k) render_canvas(rng, canv[k], CW, CH, p->density);
-  for (int k = 0; k < ncan; ++k) {
+  for (int k = 0; k < ncan * npl; ++k) {
     double a = 0, b = 0, c = 32.5;
     if (p->stereo) {
       for (;;) {
@@ -256,7 +260,8 @@ int sg_render(const sg_params* p, uint8_t* frames, double* poses, double* planes
       for (int side = 0; side < per; ++side) {
         uint8_t* img = frames + ((size_t)t * ncam + (size_t)k * per + side) * (size_t)W * H;
         if (p->warp_second && t == 1) continue;  // filled below
-        const double a = planes[3 * k], b = planes[3 * k + 1], c = planes[3 * k + 2];
+        const double* pl = planes + 3 * ((size_t)k * npl + (side ? side - 1 : 0));
+        const double a = pl[0], b = pl[1], c = pl[2];
         const Canvas& cv = canv[k];
         for_rows(H, [&, img, side, a, b, c](int y0, int y1) {
           for (int y = y0; y < y1; ++y)

@@ -48,6 +48,7 @@ class Workload:
     height: int
     n_canvases: int = 1
     stereo: bool = False
+    star: bool = False      # four cameras per canvas: detection in the first, matched into the other three
     n_frames: int = 200
     warp_second: bool = False
     density: float = 4.0
@@ -69,7 +70,7 @@ class Workload:
 
     @property
     def n_cams(self) -> int:
-        return self.n_canvases * (2 if self.stereo else 1)
+        return self.n_canvases * (4 if self.star else 2 if self.stereo else 1)
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
