@@ -97,7 +97,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 190, batch16 and rig4 100)")
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="stereo752", help="stereo752, stereo1280, rig4, mono320 or batch16")
+    ap.add_argument("--workload", default="stereo752",
+                    help="stereo752, stereo1280, rig4, star752, mono320 or batch16")
     ap.add_argument("--seq", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -309,7 +310,8 @@ def main():
             tracked[k] += int((rec[t]["status"] == TR).sum())
             prev = rec[t - 1] if t > 0 else rec[t][:0]
             n_temporal[k] += int(np.isin(prev["status"], [TR, DET, MAT]).sum())
-            n_stereo[k] += int((rec[t]["status"] == DET).sum()) if w.stereo else 0
+            # each detection is matched into the pair's right camera, or a star's three other cameras
+            n_stereo[k] += int((rec[t]["status"] == DET).sum()) * (3 if w.star else 1) if w.stereo else 0
         e, se, tr, lo = accuracy(w, seq, rec, TR, DET, MAT)
         errs += e
         serrs += se
@@ -472,15 +474,18 @@ def accuracy(w, seq, rec, TR, DET, MAT):
                 errs.append(np.hypot(cc["x"] - gx, cc["y"] - gy))
             lost += int(((cur["camera"] == c) & (cur["age"] > 0) & ~np.isin(cur["status"], [TR, DET, MAT])).sum())
         if w.stereo:
-            for c in range(0, w.n_cams, 2):
+            # groups: stereo pairs, or a star rig whose first camera's detections go to the other three
+            group = 4 if w.star else 2
+            for c in range(0, w.n_cams, group):
                 dl = cur[(cur["camera"] == c) & (cur["status"] == DET)]
-                mr = cur[(cur["camera"] == c + 1) & (cur["status"] == MAT)]
                 lpos = {int(i): (x, y) for i, x, y in zip(dl["id"], dl["x"], dl["y"])}
-                if len(mr):
-                    lx = np.array([lpos[int(i)][0] for i in mr["id"]])
-                    ly = np.array([lpos[int(i)][1] for i in mr["id"]])
-                    gx, gy = seq.gt_stereo(c, lx, ly)
-                    serrs.append(np.hypot(mr["x"] - gx, mr["y"] - gy))
+                for tc in range(c + 1, c + group):
+                    mr = cur[(cur["camera"] == tc) & (cur["status"] == MAT)]
+                    if len(mr):
+                        lx = np.array([lpos[int(i)][0] for i in mr["id"]])
+                        ly = np.array([lpos[int(i)][1] for i in mr["id"]])
+                        gx, gy = seq.gt_stereo(c, lx, ly, tc)
+                        serrs.append(np.hypot(mr["x"] - gx, mr["y"] - gy))
     return errs, serrs, n_tr, lost
 
 

@@ -66,8 +66,10 @@ typedef enum vio_init_mode {
   VIO_INIT_LEARNED = 1    /* learned displacement guess refined by the tracker */
 } vio_init_mode;
 
-/* One input stream: a mono camera, a stereo pair (cameras 0,1), or two stereo
- * pairs (0,1) and (2,3). All cameras of a stream share the image size. */
+/* One input stream: a mono camera, a stereo pair (cameras 0,1), or four
+ * cameras: two stereo pairs (0,1) and (2,3), or a star rig (0 -> 1, 2, 3) with
+ * vio_frontend_params.topology = VIO_TOPOLOGY_STAR. All cameras of a stream
+ * share the image size. */
 typedef struct vio_stream_desc {
   int32_t n_cameras;     /* 1, 2 or 4 */
   int32_t width, height; /* level-0 size in pixels, 16..4096 each, width*height < 2^24 */
@@ -110,10 +112,15 @@ typedef struct vio_frontend_params {
                                  kept or its residual RMS exceeds pred_rho (counted as a fallback) */
   int32_t pred_iters;
   float pred_rho;
+  int32_t topology;           /* four-camera streams: VIO_TOPOLOGY_PAIRS (pairs (0,1) and (2,3), each left
+                                 camera detects) or VIO_TOPOLOGY_STAR (camera 0 detects, its new keypoints
+                                 are matched into cameras 1, 2 and 3, each with its own keypoint cap) */
 } vio_frontend_params;
 
 #define VIO_STEREO_SPECULATIVE 0
 #define VIO_STEREO_DEFERRED 1
+#define VIO_TOPOLOGY_PAIRS 0
+#define VIO_TOPOLOGY_STAR 1
 
 /* vio_frontend_params.flags */
 #define VIO_FLAG_EAGER 1u /* launch the per-frame kernels one by one, each with dispatch timestamps, instead

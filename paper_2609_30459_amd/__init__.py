@@ -31,7 +31,7 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
                 max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0, learned_levels=2,
                 learned_iters=3, learned_rho=0.0, eager=False, track_waves_per_cu=0,
                 track_block_waves=0, pyr_tile=0, stereo_mode=0, pred_levels=0, pred_iters=0,
-                pred_rho=0.0) -> _n.vio_frontend_params:
+                pred_rho=0.0, topology=0) -> _n.vio_frontend_params:
     p = default_params()
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
     p.n_thresholds = len(thresholds)
@@ -46,6 +46,7 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
     p.pyr_tile = pyr_tile
     p.stereo_mode = stereo_mode
     p.pred_levels, p.pred_iters, p.pred_rho = pred_levels, pred_iters, pred_rho
+    p.topology = topology
     return p
 
 

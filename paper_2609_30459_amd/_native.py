@@ -56,12 +56,15 @@ class vio_frontend_params(ctypes.Structure):
         ("flags", ctypes.c_uint32), ("track_waves_per_cu", ctypes.c_int32),
         ("track_block_waves", ctypes.c_int32), ("pyr_tile", ctypes.c_int32), ("stereo_mode", ctypes.c_int32),
         ("pred_levels", ctypes.c_int32), ("pred_iters", ctypes.c_int32), ("pred_rho", ctypes.c_float),
+        ("topology", ctypes.c_int32),
     ]
 
 
 VIO_FLAG_EAGER = 1
 VIO_STEREO_SPECULATIVE = 0
 VIO_STEREO_DEFERRED = 1
+VIO_TOPOLOGY_PAIRS = 0
+VIO_TOPOLOGY_STAR = 1
 
 
 class vio_kp_prediction(ctypes.Structure):

@@ -63,7 +63,8 @@ struct CamDesc {
   int kcell, nslots;   // keypoints per cell k; winner key slots ncells * k (cell-major)
   int has_mask;        // detection mask in use (nonzero mask byte: no detection at that pixel)
   int detect;          // 1: mono camera or left camera of a pair
-  int partner;         // right camera of a left camera, left camera of a right one, else -1
+  int n_targets;       // detecting camera: cameras c+1 .. c+n_targets receive its new keypoints' matches
+                       // (1: a stereo pair's right camera, 3: a star rig's other cameras)
   int stream;
   int local;           // camera index within its stream
   int tiles_x, tiles_y, tile_begin;  // pyramid/detector tiles of this camera
@@ -72,7 +73,7 @@ struct CamDesc {
   Kp* state[2];                      // keypoint state, double-buffered by frame parity
   TrackRes* res;                     // temporal results [cap]
   uint32_t* keys[2];                 // packed winner keys, slot cell * k + rank, by frame parity [nslots]
-  TrackRes* sres;                    // stereo match of every winner slot [nslots]
+  TrackRes* sres;                    // stereo matches [n_targets][nslots], by key slot or selection rank
   const uint8_t* mask;               // detection mask [h][w] (detecting cameras)
   vio_track* rec;                    // output records [rec_cap], in mapped pinned host memory
   int32_t* rec_count_out;            // record count of the last frame, mapped pinned host memory

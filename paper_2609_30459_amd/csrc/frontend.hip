@@ -192,6 +192,8 @@ int check_params(const vio_frontend_params* p, std::string& why) {
     if (p->learned_iters < 1 || p->learned_iters > 32) return why = "learned_iters out of 1..32", VIO_EINVAL;
   }
   if (p->pred_levels < 0 || p->pred_levels > p->levels) return why = "pred_levels out of 0..levels", VIO_EINVAL;
+  if (p->topology != VIO_TOPOLOGY_PAIRS && p->topology != VIO_TOPOLOGY_STAR)
+    return why = "topology must be VIO_TOPOLOGY_PAIRS or VIO_TOPOLOGY_STAR", VIO_EINVAL;
   if (p->pred_levels > 0 && (p->pred_iters < 1 || p->pred_iters > 32))
     return why = "pred_iters out of 1..32", VIO_EINVAL;
   if (std::isnan(p->pred_rho)) return why = "pred_rho is NaN", VIO_EINVAL;
@@ -291,8 +293,11 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       c.ncells = c.ncx * c.ncy;
       c.kcell = P.k_per_cell;
       c.nslots = c.ncells * c.kcell;
-      c.detect = (si.n_cams == 1 || k % 2 == 0) ? 1 : 0;
-      c.partner = si.n_cams == 1 ? -1 : (k % 2 == 0 ? cam + 1 : cam - 1);
+      // groups: mono, stereo pairs (0,1), (2,3), or a star rig 0 -> 1, 2, 3
+      const bool star = si.n_cams == 4 && P.topology == VIO_TOPOLOGY_STAR;
+      const int group = si.n_cams == 1 ? 1 : (star ? 4 : 2);
+      c.detect = k % group == 0 ? 1 : 0;
+      c.n_targets = c.detect ? group - 1 : 0;
       c.stream = s;
       c.local = k;
       c.tiles_x = (si.w + h->tile - 1) / h->tile;
@@ -310,7 +315,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       co[cam].res = take(sizeof(TrackRes) * si.cap);
       if (c.detect) {
         for (int par = 0; par < 2; ++par) co[cam].keys[par] = take(sizeof(uint32_t) * c.nslots);
-        co[cam].sres = take(sizeof(TrackRes) * c.nslots);
+        co[cam].sres = take(sizeof(TrackRes) * c.nslots * std::max(1, c.n_targets));
         co[cam].mask = take((size_t)si.w * si.h);
       }
       c.rec_cap = 2 * si.cap;
@@ -325,11 +330,13 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     // tracks of every camera
     for (int k = 0; k < si.n_cams; ++k) {
       const int cc = si.first_cam + k;
-      if (si.n_cams >= 2 && k % 2 == 0) {
-        h->segs.push_back({cc, kModeStereo, items, h->cams[cc].nslots});
-        items += h->cams[cc].nslots;
+      const CamDesc& cd = h->cams[cc];
+      if (cd.n_targets > 0) {
+        const int n = cd.nslots * cd.n_targets;
+        h->segs.push_back({cc, kModeStereo, items, n});
+        items += n;
         si.st_segs += 1;
-        si.st_items += h->cams[cc].nslots;
+        si.st_items += n;
       }
     }
     for (int k = 0; k < si.n_cams; ++k) {

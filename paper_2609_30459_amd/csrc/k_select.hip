@@ -211,24 +211,30 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
   const int s = blockIdx.x;
   const int cam0 = stream_cams[2 * s], ncam = stream_cams[2 * s + 1];
   if (!frame->cam[cam0].active) return;
-  const int step = ncam >= 2 ? 2 : 1;
+  // camera groups: a detecting camera followed by the n_targets cameras that
+  // receive its matches (mono: none, stereo pair: one, star rig: three)
   if (phase == kSelectRight) {
-    for (int g = 0; g + 1 < ncam; g += 2) {
-      const int lc = cam0 + g, rc = lc + 1;
+    for (int g = 0; g < ncam; g += 1 + cams[cam0 + g].n_targets) {
+      const int lc = cam0 + g;
       const CamDesc& L = cams[lc];
-      const FrameCam& fr = frame->cam[rc];
-      const int P = frame->cam[lc].parity, PR = fr.parity;
-      const int n_rec_r = fr.has_prev ? cnt->n_live[PR ^ 1][rc] : 0;
-      accept_matches(L, P, cnt->sel_base[lc], cams[rc], fr, rc, cnt->n_sel[lc], cnt->n_live[PR][rc], n_rec_r,
-                     [&](int i) { return L.sres[i]; }, cnt, sc);
-      __syncthreads();
+      const int P = frame->cam[lc].parity;
+      for (int t = 0; t < L.n_targets; ++t) {
+        const int rc = lc + 1 + t;
+        const FrameCam& fr = frame->cam[rc];
+        const int PR = fr.parity;
+        const int n_rec_r = fr.has_prev ? cnt->n_live[PR ^ 1][rc] : 0;
+        const TrackRes* sr = L.sres + (size_t)t * L.nslots;
+        accept_matches(L, P, cnt->sel_base[lc], cams[rc], fr, rc, cnt->n_sel[lc], cnt->n_live[PR][rc], n_rec_r,
+                       [&](int i) { return sr[i]; }, cnt, sc);
+        __syncthreads();
+      }
     }
     return;
   }
   const int stream = cams[cam0].stream;
   const int64_t id0 = cnt->next_id[stream];
   int64_t next_id = id0;
-  for (int g = 0; g < ncam; g += step) {
+  for (int g = 0; g < ncam; g += 1 + cams[cam0 + g].n_targets) {
     const int lc = cam0 + g;
     const CamDesc& L = cams[lc];
     const FrameCam& fl = frame->cam[lc];
@@ -320,16 +326,18 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     for (int i = threadIdx.x; i < nslots; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
     __syncthreads();
 
-    // ---- right camera of a pair: survivors, then accepted stereo matches ---
-    if (step == 2) {
-      const int rc = lc + 1;
+    // ---- target cameras (a pair's right camera, a star's other three):
+    //      survivors, then accepted stereo matches
+    for (int t = 0; t < L.n_targets; ++t) {
+      const int rc = lc + 1 + t;
       const CamDesc& R = cams[rc];
       const FrameCam& fr = frame->cam[rc];
       const int PR = fr.parity;
       int n_rec_r = 0;
       const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, count_fb);
       if (phase == kSelectAll) {
-        accept_matches(L, P, n_surv, R, fr, rc, n_new, n_surv_r, n_rec_r, [&](int i) { return L.sres[s_sel[i]]; },
+        const TrackRes* sr = L.sres + (size_t)t * nslots;
+        accept_matches(L, P, n_surv, R, fr, rc, n_new, n_surv_r, n_rec_r, [&](int i) { return sr[s_sel[i]]; },
                        cnt, sc);
       } else if (threadIdx.x == 0) {
         // the matches come from the stereo tracking launch; kSelectRight appends them

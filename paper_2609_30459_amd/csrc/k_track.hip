@@ -537,15 +537,18 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
     sdst = P;
     out = cd.res + j;
   } else {
-    // stereo match of a detection: speculative (item j = the winner in key
-    // slot j) or deferred (item j = the frame's j-th selected detection)
+    // stereo match of a detection into target camera c + 1 + t (item j =
+    // t * nslots + i): speculative (i = the winner's key slot) or deferred
+    // (i = the frame's i-th selected detection)
+    const int t = cd.n_targets > 1 ? j / cd.nslots : 0;
+    const int i = j - t * cd.nslots;
     if (tune.deferred) {
-      if (j >= cnt->n_sel[c]) return;
-      const Kp kp = cd.state[P][cnt->sel_base[c] + j];
+      if (i >= cnt->n_sel[c]) return;
+      const Kp kp = cd.state[P][cnt->sel_base[c] + i];
       px = kp.x;
       py = kp.y;
     } else {
-      const uint32_t key = cd.keys[P][j];
+      const uint32_t key = cd.keys[P][i];
       if (key == 0) return;
       const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
       px = (float)(idx % cd.w);
@@ -553,7 +556,7 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
     }
     ix = px - tune.disparity0;
     iy = py;
-    dst = &cams[cd.partner];
+    dst = &cams[c + 1 + t];
     ssrc = P;
     sdst = P;
     out = cd.sres + j;

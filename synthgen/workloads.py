@@ -81,6 +81,7 @@ WORKLOADS = {
                         max_scale=0.0, levels=3, cell_size=16, max_keypoints=200),
     "stereo752": Workload("stereo752", 1, 752, 480, stereo=True),
     "stereo1280": Workload("stereo1280", 2, 1280, 720, stereo=True, cell_size=48),
+    "star752": Workload("star752", 5, 752, 480, stereo=True, star=True),
     "rig4": Workload("rig4", 4, 1920, 1200, n_canvases=2, stereo=True, n_frames=500,
                      max_t=25.0, max_rot_deg=8.0, levels=5, cell_size=32, max_keypoints=1500),
 }
