@@ -254,8 +254,11 @@ def main():
                 fe.step()
             else:
                 fe.push_stereo_frame_device(0, t + 1, frame_imgs[t])
-            for i in ids:
-                records[i].append(fe.get_tracks(i))
+            if batched:
+                for i, r in enumerate(fe.get_tracks_many(ids)):
+                    records[i].append(r)
+            else:
+                records[0].append(fe.get_tracks(0))
 
         log(f"warmup {args.warmup} steps ({'eager' if eager else 'graph'})")
         for t in range(args.warmup):

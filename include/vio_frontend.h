@@ -288,6 +288,14 @@ int vio_frontend_set_motion(vio_frontend* h, int32_t stream, const vio_camera_mo
  * smaller. VIO_ESTATE before the stream's first push. */
 int vio_frontend_get_tracks(vio_frontend* h, int32_t stream, vio_track* out, int32_t capacity, int32_t* n_out);
 
+/* The last frame's records of n streams in one call: those of streams[i]
+ * follow those of streams[0..i), each stream's as vio_frontend_get_tracks
+ * orders them; counts[i] receives stream i's record count and *n_out the
+ * total. VIO_ETOOSMALL (nothing written to out, counts and *n_out set) when
+ * capacity is smaller; VIO_EINVAL / VIO_ESTATE as vio_frontend_get_tracks. */
+int vio_frontend_get_tracks_streams(vio_frontend* h, int32_t n, const int32_t* streams, vio_track* out,
+                                    int32_t capacity, int32_t* counts, int32_t* n_out);
+
 /* Replaces camera `camera`'s live keypoints of `stream` with kps[0..n) (ids
  * strictly ascending, n <= the camera's keypoint cap): the host upload of
  * KP_{t-1} (Sec. III-B, Fig. 2). New identifiers continue above the largest id

@@ -214,6 +214,26 @@ class Frontend:
         self._rec_hint[stream] = cap
         return out[:n.value]
 
+    def get_tracks_many(self, streams) -> list:
+        """The last frame's records of several streams with one C call: a list of
+        arrays (views into one buffer), one per stream in the given order."""
+        key = tuple(int(s) for s in streams)
+        ids = np.asarray(key, np.int32)
+        counts = np.zeros(len(key), np.int32)
+        n = ctypes.c_int32()
+        cap = self._rec_hint.get(key, 1024)
+        out = np.empty(cap, TRACK_DTYPE)
+        rc = _n.lib.vio_frontend_get_tracks_streams(self._h, len(key), ids.ctypes.data, out.ctypes.data, cap,
+                                                    counts.ctypes.data, ctypes.byref(n))
+        if rc == _n.VIO_ETOOSMALL:
+            cap = n.value + n.value // 4
+            out = np.empty(cap, TRACK_DTYPE)
+            rc = _n.lib.vio_frontend_get_tracks_streams(self._h, len(key), ids.ctypes.data, out.ctypes.data, cap,
+                                                        counts.ctypes.data, ctypes.byref(n))
+        self._check(rc, "vio_frontend_get_tracks_streams")
+        self._rec_hint[key] = cap
+        return np.split(out[:n.value], np.cumsum(counts)[:-1])
+
     # -- keypoint state ----------------------------------------------------
     def set_keypoints(self, stream, camera, kps: np.ndarray):
         kps = np.ascontiguousarray(kps, KEYPOINT_DTYPE)

@@ -111,6 +111,7 @@ lib.vio_frontend_destroy.restype = None
 lib.vio_frontend_push_stereo_frame.argtypes = [_vp, _i32, _i64, _vp, _vp, _vp, _i32]
 lib.vio_frontend_push_stereo_frame_device.argtypes = [_vp, _i32, _i64, _vp, _vp, _vp]
 lib.vio_frontend_get_tracks.argtypes = [_vp, _i32, _vp, _i32, _P(_i32)]
+lib.vio_frontend_get_tracks_streams.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _P(_i32)]
 lib.vio_frontend_set_keypoints.argtypes = [_vp, _i32, _i32, _vp, _i32]
 lib.vio_frontend_get_keypoints.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
 lib.vio_frontend_get_pyramid.argtypes = [_vp, _i32, _i32, _i32, _vp, _sz]

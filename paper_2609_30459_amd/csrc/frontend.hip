@@ -1052,6 +1052,36 @@ int vio_frontend_get_tracks(vio_frontend* h, int32_t s, vio_track* out, int32_t 
   return VIO_OK;
 }
 
+int vio_frontend_get_tracks_streams(vio_frontend* h, int32_t n, const int32_t* streams, vio_track* out,
+                                    int32_t capacity, int32_t* counts, int32_t* n_out) {
+  if (!h || !n_out || n < 0 || (n > 0 && (!streams || !counts))) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  int total = 0;
+  for (int i = 0; i < n; ++i) {
+    const int s = streams[i];
+    if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+    const StreamInfo& si = h->streams[s];
+    if (si.frames == 0) return fail(h, VIO_ESTATE, "stream %d: no frame pushed yet", s);
+    int m = 0;
+    for (int k = 0; k < si.n_cams; ++k) m += h->h_rec_count[si.first_cam + k];
+    counts[i] = m;
+    total += m;
+  }
+  *n_out = total;
+  if (capacity < total) return VIO_ETOOSMALL;
+  if (total > 0 && !out) return VIO_EINVAL;
+  int at = 0;
+  for (int i = 0; i < n; ++i) {
+    const StreamInfo& si = h->streams[streams[i]];
+    for (int k = 0; k < si.n_cams; ++k) {
+      const int m = h->h_rec_count[si.first_cam + k];
+      std::memcpy(out + at, h->h_rec + h->rec_host_off[si.first_cam + k], sizeof(vio_track) * m);
+      at += m;
+    }
+  }
+  return VIO_OK;
+}
+
 static int state_slot(const StreamInfo& si) { return (int)((si.frames & 1) ^ 1); }
 
 int vio_frontend_set_keypoints(vio_frontend* h, int32_t s, int32_t camera, const vio_keypoint* kps, int32_t n) {

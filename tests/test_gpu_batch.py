@@ -117,6 +117,12 @@ def test_multi_stream_staging_call_equals_single_stagings():
             for s in range(3):
                 assert a.get_tracks(s).tobytes() == b.get_tracks(s).tobytes(), (t, s)
             assert all(m > 0 for m in a.stats()["last_stage_ms"])
+            # one readback call for several streams, in any order
+            for order in ([0, 1, 2], [2, 0], [1]):
+                many = a.get_tracks_many(order)
+                assert len(many) == len(order)
+                for s, r in zip(order, many):
+                    assert r.tobytes() == a.get_tracks(s).tobytes(), (t, order, s)
 
 
 @pytest.mark.parametrize("stereo_mode", [0, 1])
