@@ -216,6 +216,8 @@ def main():
     # each frame's device images (views into the resident sequences), all
     # cameras stream by stream, made once before any timed region
     frame_imgs = [[devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)] for t in range(n_frames)]
+    # the push/staging call's pointer and pitch arrays, built once per frame
+    frame_imgs = [vf.Frontend.device_images(f) for f in frame_imgs]
     # camera-model start: the motion of frame t-1 -> t per stream (every camera of a stream takes its
     # first camera's motion), made before any timed region
     motions, K_of = None, None

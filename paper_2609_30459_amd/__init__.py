@@ -59,6 +59,11 @@ def params_for(workload, **overrides) -> _n.vio_frontend_params:
     return make_params(**kw)
 
 
+def _prebuilt(images):
+    """True for the (pointer array, pitch array) pair that Frontend.device_images returns."""
+    return isinstance(images, tuple) and len(images) == 2 and isinstance(images[0], ctypes.Array)
+
+
 class Frontend:
     """A frontend handle (vio_frontend_create .. vio_frontend_destroy).
 
@@ -162,9 +167,9 @@ class Frontend:
         self._check(rc, "vio_frontend_set_motion")
 
     def push_stereo_frame_device(self, stream, t_ns, images, hip_stream=None):
-        """images: one device uint8 tensor (HxW, row-contiguous) per camera."""
-        ptrs = (ctypes.c_void_p * len(images))(*[int(t.data_ptr()) for t in images])
-        pitches = np.asarray([int(t.stride(0)) * t.element_size() for t in images], np.int32)
+        """images: one device uint8 tensor (HxW, row-contiguous) per camera, or the
+        result of device_images."""
+        ptrs, pitches = images if _prebuilt(images) else self.device_images(images)
         st = None
         if hip_stream is not None:
             st = ctypes.c_void_p(int(getattr(hip_stream, "cuda_stream", hip_stream)))
@@ -186,13 +191,21 @@ class Frontend:
         self._check(_n.lib.vio_frontend_stage_frame_device(self._h, stream, int(t_ns), ptrs, pitches.ctypes.data),
                     "vio_frontend_stage_frame_device")
 
+    @staticmethod
+    def device_images(images):
+        """(pointer array, pitch array) of device image tensors, as stage_frames_device
+        takes them; build it once per frame's images to skip the per-call conversion."""
+        ptrs = (ctypes.c_void_p * len(images))(*[int(t.data_ptr()) for t in images])
+        pitches = np.asarray([int(t.stride(0)) * t.element_size() for t in images], np.int32)
+        return ptrs, pitches
+
     def stage_frames_device(self, streams, t_ns, images):
-        """Stages device images of several streams in one call; images: all cameras, stream by stream."""
+        """Stages device images of several streams in one call; images: all cameras, stream by
+        stream, as tensors or as the result of device_images."""
         n = len(streams)
         st = np.ascontiguousarray(streams, np.int32)
         ts = np.ascontiguousarray(t_ns, np.int64)
-        ptrs = (ctypes.c_void_p * len(images))(*[int(t.data_ptr()) for t in images])
-        pitches = np.asarray([int(t.stride(0)) * t.element_size() for t in images], np.int32)
+        ptrs, pitches = images if _prebuilt(images) else self.device_images(images)
         self._check(_n.lib.vio_frontend_stage_frames_device(self._h, n, st.ctypes.data, ts.ctypes.data, ptrs,
                                                             pitches.ctypes.data), "vio_frontend_stage_frames_device")
 
@@ -232,7 +245,11 @@ class Frontend:
                                                         counts.ctypes.data, ctypes.byref(n))
         self._check(rc, "vio_frontend_get_tracks_streams")
         self._rec_hint[key] = cap
-        return np.split(out[:n.value], np.cumsum(counts)[:-1])
+        views, at = [], 0
+        for m in counts.tolist():
+            views.append(out[at:at + m])
+            at += m
+        return views
 
     # -- keypoint state ----------------------------------------------------
     def set_keypoints(self, stream, camera, kps: np.ndarray):
