@@ -115,6 +115,15 @@ typedef struct vio_frontend_params {
   int32_t topology;           /* four-camera streams: VIO_TOPOLOGY_PAIRS (pairs (0,1) and (2,3), each left
                                  camera detects) or VIO_TOPOLOGY_STAR (camera 0 detects, its new keypoints
                                  are matched into cameras 1, 2 and 3, each with its own keypoint cap) */
+  /* Optional device allocator for the handle's one device arena (every device
+   * buffer of the handle lives in it; allocated once in vio_frontend_create,
+   * released in vio_frontend_destroy, Sec. III-B). dev_alloc(bytes, ctx)
+   * returns device memory of the handle's device aligned to 256 bytes, or NULL
+   * (create then fails with VIO_ENOMEM); dev_free(ptr, ctx) releases it. Set
+   * both or neither (NULL: hipMalloc / hipFree). */
+  void* (*dev_alloc)(size_t bytes, void* ctx);
+  void (*dev_free)(void* ptr, void* ctx);
+  void* alloc_ctx;
 } vio_frontend_params;
 
 #define VIO_STEREO_SPECULATIVE 0

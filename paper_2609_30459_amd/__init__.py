@@ -68,14 +68,24 @@ class Frontend:
     """A frontend handle (vio_frontend_create .. vio_frontend_destroy).
 
     streams: list of (n_cameras, width, height[, max_keypoints[, cell_size]]).
+    allocator: optional (alloc(nbytes) -> device pointer as int, free(pointer)),
+    used for the handle's one device arena (e.g. torch's caching allocator).
     """
 
-    def __init__(self, streams, params: _n.vio_frontend_params):
+    def __init__(self, streams, params: _n.vio_frontend_params, allocator=None):
         descs = (_n.vio_stream_desc * len(streams))()
         for d, s in zip(descs, streams):
             s = tuple(s) + (0,) * (5 - len(s))
             d.n_cameras, d.width, d.height, d.max_keypoints, d.cell_size = s
         self.streams = [tuple(s) for s in streams]
+        self._alloc_cb = None
+        if allocator is not None:
+            alloc, free = allocator
+            params = _n.vio_frontend_params.from_buffer_copy(params)
+            self._alloc_cb = (_n.DEV_ALLOC(lambda nbytes, ctx: int(alloc(int(nbytes))) or None),
+                              _n.DEV_FREE(lambda ptr, ctx: free(int(ptr))))
+            params.dev_alloc = ctypes.cast(self._alloc_cb[0], ctypes.c_void_p)
+            params.dev_free = ctypes.cast(self._alloc_cb[1], ctypes.c_void_p)
         self.params = params
         self._rec_hint = {}  # per stream: record buffer size for get_tracks
         h = ctypes.c_void_p()

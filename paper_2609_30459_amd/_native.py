@@ -57,7 +57,12 @@ class vio_frontend_params(ctypes.Structure):
         ("track_block_waves", ctypes.c_int32), ("pyr_tile", ctypes.c_int32), ("stereo_mode", ctypes.c_int32),
         ("pred_levels", ctypes.c_int32), ("pred_iters", ctypes.c_int32), ("pred_rho", ctypes.c_float),
         ("topology", ctypes.c_int32),
+        ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
     ]
+
+# the optional device allocator of vio_frontend_params
+DEV_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEV_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 VIO_FLAG_EAGER = 1

@@ -192,6 +192,7 @@ int check_params(const vio_frontend_params* p, std::string& why) {
     if (p->learned_iters < 1 || p->learned_iters > 32) return why = "learned_iters out of 1..32", VIO_EINVAL;
   }
   if (p->pred_levels < 0 || p->pred_levels > p->levels) return why = "pred_levels out of 0..levels", VIO_EINVAL;
+  if ((p->dev_alloc == nullptr) != (p->dev_free == nullptr)) return why = "set both dev_alloc and dev_free or neither", VIO_EINVAL;
   if (p->topology != VIO_TOPOLOGY_PAIRS && p->topology != VIO_TOPOLOGY_STAR)
     return why = "topology must be VIO_TOPOLOGY_PAIRS or VIO_TOPOLOGY_STAR", VIO_EINVAL;
   if (p->pred_levels > 0 && (p->pred_iters < 1 || p->pred_iters > 32))
@@ -233,7 +234,10 @@ void vio_frontend_destroy(vio_frontend* h) {
   for (auto& si : h->streams)
     si.graph.destroy();
   h->graph_all.destroy();
-  if (h->arena) (void)hipFree(h->arena);
+  if (h->arena) {
+    if (h->P.dev_free) h->P.dev_free(h->arena, h->P.alloc_ctx);
+    else (void)hipFree(h->arena);
+  }
   if (h->h_frame) (void)hipHostFree(h->h_frame);
   if (h->h_rec_count) (void)hipHostFree(h->h_rec_count);
   if (h->h_camstats) (void)hipHostFree(h->h_camstats);
@@ -406,7 +410,15 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   if (lds_need == 0 || lds_need > (size_t)lds_max)
     return fail(h, VIO_EUNSUPPORTED, "%d levels with %d-pixel tiles need %zu bytes of LDS per workgroup, the device "
                 "offers %d", P.levels, h->tile, lds_need, lds_max);
-  if (hipMalloc(&h->arena, arena_bytes) != hipSuccess) {
+  if (P.dev_alloc) {
+    h->arena = P.dev_alloc(arena_bytes, P.alloc_ctx);
+    if (!h->arena) return fail(h, VIO_ENOMEM, "caller's allocator: device arena of %zu bytes", arena_bytes);
+    if (reinterpret_cast<uintptr_t>(h->arena) % kAlign != 0) {
+      P.dev_free(h->arena, P.alloc_ctx);
+      h->arena = nullptr;
+      return fail(h, VIO_EINVAL, "caller's allocator returned memory not aligned to %zu bytes", kAlign);
+    }
+  } else if (hipMalloc(&h->arena, arena_bytes) != hipSuccess) {
     h->arena = nullptr;
     return fail(h, VIO_ENOMEM, "device arena of %zu bytes", arena_bytes);
   }

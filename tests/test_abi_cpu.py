@@ -82,6 +82,11 @@ def test_create_rejects_bad_arguments_before_any_device_call(native):
         q = vf.default_params()
         q.k_per_cell = k
         assert _create(native, [ok], q) == native.VIO_EINVAL, k
+    # a device allocator needs both callbacks
+    cb = native.DEV_ALLOC(lambda n, ctx: None)
+    q = vf.default_params()
+    q.dev_alloc = ctypes.cast(cb, ctypes.c_void_p)
+    assert _create(native, [ok], q) == native.VIO_EINVAL
     # the largest grid (8192 cells) takes the largest k
     q = vf.default_params()
     q.k_per_cell = 8
