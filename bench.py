@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--launch", choices=["eager", "graph"], default="graph",
                     help="first timed region (`value`): one captured graph per frame (default), or the kernels "
                          "launched one by one with HIP events attached to each dispatch (gives kernel durations)")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="graph launches one frame at a time (no frame submitted before the last one's records are read)")
     ap.add_argument("--no-second-launch", "--no-graph-replay", dest="no_second", action="store_true",
                     help="skip the second timed region, which runs the same steps with the other launch mode")
     ap.add_argument("--init", choices=["const_vel", "learned"], default="const_vel")
@@ -247,24 +249,40 @@ def main():
         records = [[] for _ in ws]
         wall, stats = [], []
 
-        def step(t):
+        pipelined = not eager and not args.no_pipeline
+        t_sub = {}
+
+        def submit(t):
             if motions is not None and t > 0:
                 for i in ids:
                     fe.set_motion(i, motions[i][t])
-            if batched:
+            t_sub[t] = time.perf_counter()
+            if pipelined:
+                fe.stage_frames_device(ids, [t + 1] * len(ws), frame_imgs[t])
+                fe.step_async()
+            elif batched:
                 fe.stage_frames_device(ids, [t + 1] * len(ws), frame_imgs[t])
                 fe.step()
             else:
                 fe.push_stereo_frame_device(0, t + 1, frame_imgs[t])
-            if batched:
+
+        def collect(t):
+            if pipelined:
+                fe.wait()
+            if batched or pipelined:
                 for i, r in enumerate(fe.get_tracks_many(ids)):
                     records[i].append(r)
             else:
                 records[0].append(fe.get_tracks(0))
+            return time.perf_counter() - t_sub.pop(t)
 
-        log(f"warmup {args.warmup} steps ({'eager' if eager else 'graph'})")
+        # pipelined (graph launches): frame t is submitted before frame t-1's
+        # records are read, so the host's work overlaps the device's; the
+        # latency of a frame runs from its submission to its records
+        log(f"warmup {args.warmup} steps ({'eager' if eager else 'graph'}{', pipelined' if pipelined else ''})")
         for t in range(args.warmup):
-            step(t)
+            submit(t)
+            collect(t)
         torch.cuda.synchronize()
         log(f"timing {args.steps} steps")
         # no garbage-collector pause inside the timed steps
@@ -272,9 +290,16 @@ def main():
         gc.disable()
         t0 = time.perf_counter()
         for t in range(args.warmup, n_frames):
-            ts = time.perf_counter()
-            step(t)
-            wall.append(time.perf_counter() - ts)
+            submit(t)
+            if pipelined:
+                if t > args.warmup:
+                    wall.append(collect(t - 1))
+                    stats.append(fe.stats())
+            else:
+                wall.append(collect(t))
+                stats.append(fe.stats())
+        if pipelined:
+            wall.append(collect(n_frames - 1))
             stats.append(fe.stats())
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -441,7 +466,8 @@ def main():
                    **({"pred_levels": args.pred_levels, "pred_iters": args.pred_iters, "pred_rho": args.pred_rho}
                       if short_pred else {}),
                    "cell_size": sorted({w.cell_size for w in ws}), "thresholds": list(w0.thresholds),
-                   "init": args.init, "launch": args.launch, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
+                   "init": args.init, "launch": args.launch,
+                   "pipelined": args.launch == "graph" and not args.no_pipeline, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
                    "stereo_mode": ["speculative", "deferred"][smode],
                    "autotuned": tuned is not None, "parallelism": "single_gpu",
                    **({"learned_levels": args.learned_levels, "learned_iters": args.learned_iters, "rho": rho}

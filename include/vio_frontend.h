@@ -251,6 +251,21 @@ int vio_frontend_stage_frame_device(vio_frontend* h, int32_t stream, int64_t t_n
                                     const int32_t* pitches);
 int vio_frontend_step(vio_frontend* h);
 
+/* Pipelined stepping: vio_frontend_step_async submits the staged streams'
+ * frames like vio_frontend_step but returns without waiting; while it runs
+ * the host may stage the next frames and submit them too (at most two frames
+ * in flight: staging, pushing or submitting a third returns VIO_ESTATE).
+ * vio_frontend_wait waits for the oldest frame in flight (VIO_ESTATE when
+ * none); afterwards vio_frontend_get_tracks returns its records, while the
+ * next frame may still run (records are double-buffered by frame parity).
+ * Every other call (pushes, keypoint and diagnostic calls) first waits for
+ * all frames in flight. Device images staged for a frame must stay valid
+ * until that frame is waited for. vio_frontend_in_flight returns the number
+ * of frames in flight (0 for NULL). */
+int vio_frontend_step_async(vio_frontend* h);
+int vio_frontend_wait(vio_frontend* h);
+int vio_frontend_in_flight(const vio_frontend* h);
+
 /* Stages device images for n streams at once: stream streams[i] at t_ns[i]
  * takes the next n_cameras entries of d_images / pitches (in stream order). */
 int vio_frontend_stage_frames_device(vio_frontend* h, int32_t n, const int32_t* streams, const int64_t* t_ns,

@@ -223,6 +223,18 @@ class Frontend:
         """Runs every staged stream's frame in one submit (synchronous)."""
         self._check(_n.lib.vio_frontend_step(self._h), "vio_frontend_step")
 
+    def step_async(self):
+        """Submits every staged stream's frame without waiting (at most two frames in flight)."""
+        self._check(_n.lib.vio_frontend_step_async(self._h), "vio_frontend_step_async")
+
+    def wait(self):
+        """Waits for the oldest frame in flight; its records are then readable."""
+        self._check(_n.lib.vio_frontend_wait(self._h), "vio_frontend_wait")
+
+    @property
+    def in_flight(self) -> int:
+        return _n.lib.vio_frontend_in_flight(self._h)
+
     def get_tracks(self, stream=0) -> np.ndarray:
         """The last frame's records of the stream (one C call while the buffer guess holds)."""
         n = ctypes.c_int32()

@@ -128,6 +128,9 @@ lib.vio_frontend_set_mlp.argtypes = [_vp, _vp, _i32, ctypes.c_float]
 lib.vio_frontend_stage_frame.argtypes = [_vp, _i32, _i64, _vp, _vp]
 lib.vio_frontend_stage_frame_device.argtypes = [_vp, _i32, _i64, _vp, _vp]
 lib.vio_frontend_step.argtypes = [_vp]
+lib.vio_frontend_step_async.argtypes = [_vp]
+lib.vio_frontend_wait.argtypes = [_vp]
+lib.vio_frontend_in_flight.argtypes = [_vp]
 lib.vio_frontend_stage_frames_device.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
 lib.vio_frontend_get_features.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
 lib.vio_frontend_set_camera_model.argtypes = [_vp, _i32, _i32, _P(vio_pinhole)]

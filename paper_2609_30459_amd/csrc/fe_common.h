@@ -75,9 +75,11 @@ struct CamDesc {
   uint32_t* keys[2];                 // packed winner keys, slot cell * k + rank, by frame parity [nslots]
   TrackRes* sres;                    // stereo matches [n_targets][nslots], by key slot or selection rank
   const uint8_t* mask;               // detection mask [h][w] (detecting cameras)
-  vio_track* rec;                    // output records [rec_cap], in mapped pinned host memory
-  int32_t* rec_count_out;            // record count of the last frame, mapped pinned host memory
-  int32_t* stats_out;                // [kCamStats] counts of the last frame (CamStat), mapped host memory
+  // outputs in mapped pinned host memory, by frame parity (the host reads one
+  // frame's while the next frame runs)
+  vio_track* rec[2];                 // records [rec_cap]
+  int32_t* rec_count_out[2];         // record count
+  int32_t* stats_out[2];             // [kCamStats] counts (CamStat)
   int rec_cap;
   int row_off;                       // first row of this camera in the learned-init feature/guess buffers
 };

@@ -52,10 +52,11 @@ struct StreamInfo {
   int tile_begin = 0, n_tiles = 0;
   int seg_begin = 0, n_segs = 0, item_begin = 0, n_items = 0;
   int st_segs = 0, st_items = 0;  // the stream's stereo segments/items come first
+  int64_t done = 0;        // frames whose records are ready (frames - done are in flight)
   bool staged = false;     // a frame is staged for the next vio_frontend_step
   int64_t staged_t = 0;
   size_t rec_off = 0, rec_n = 0;  // record range (in vio_track units) of the stream's cameras
-  Graphs graph;                    // captured per-frame submit, replayed every frame
+  Graphs graph[2];                 // captured per-frame submit by submission slot, replayed every frame
   // camera-model start for the next frame (vio_frontend_set_motion)
   std::vector<vio_camera_motion> motion;  // at most one per camera
   std::vector<vio_kp_depth> depths;       // sorted by (camera, id)
@@ -88,7 +89,7 @@ struct vio_frontend {
   vio_frontend_params P{};
   int n_cus = 256;
   int tile = kTileDefault;  // pyramid/detector tile edge
-  Graphs graph_all;  // captured batched step
+  Graphs graph_all[2];  // captured batched step by submission slot
   std::vector<StreamInfo> streams;
   std::vector<CamDesc> cams;
   std::vector<TrackSeg> segs;      // per stream: the stream's items are contiguous
@@ -115,22 +116,36 @@ struct vio_frontend {
   float* d_feat = nullptr;   // [rows][32]
   FeatGrid grid{};           // neighbour grids of the features
   float* d_guess = nullptr;  // [rows][3]
-  int32_t* h_camstats = nullptr;  // [cameras][kCamStats], written by the selection kernel
+  int32_t* h_camstats = nullptr;  // [parity][cameras][kCamStats], written by the selection kernel
   // pinned host
-  FrameTable* h_frame = nullptr;
-  int32_t* h_rec_count = nullptr;
-  vio_track* h_rec = nullptr;
-  uint8_t* h_stage = nullptr;
+  // Submissions alternate between two slots: the frame table, the host image
+  // staging and the prediction / depth lists being filled belong to slot
+  // sub & 1, so the next frame can be staged while the previous one runs.
+  // Records, their counts and the per-camera counts are double-buffered by
+  // each camera's frame parity instead.
+  FrameTable* h_frames[2] = {nullptr, nullptr};
+  FrameTable* h_frame = nullptr;  // h_frames[sub & 1]
+  int64_t sub = 0;                // submissions so far
+  struct Pending {
+    LaunchSet ls;
+    bool graphed;
+    int slot;
+  };
+  Pending pend[2];
+  int n_pend = 0, pend_head = 0;  // submitted, not yet completed (oldest first)
+  int32_t* h_rec_count = nullptr; // [parity][cameras]
+  vio_track* h_rec = nullptr;     // [parity][rec_total]
+  uint8_t* h_stage = nullptr;     // [slot][stage_bytes]
   size_t stage_bytes = 0;
-  Prediction* h_pred = nullptr;
-  KpDepth* h_depth = nullptr;
+  Prediction* h_pred = nullptr;  // [slot][pred_cap]
+  KpDepth* h_depth = nullptr;    // [slot][pred_cap]
   hipStream_t stream = nullptr;
   // learned mode: the network's inputs are the previous frame's, so features
   // and network run on a second stream beside the pyramid (fork after the
   // frame-table copy, join before tracking)
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};  // frame start and end on the launch stream
+  hipEvent_t ev[2][2] = {};  // per submission slot: frame start and end on the launch stream
   // eager launches: start/stop events attached to each kernel's dispatch
   // (pyramid+detector, features, network, tracker, selection)
   hipEvent_t kev[kKernels][2] = {};
@@ -232,21 +247,23 @@ void vio_frontend_destroy(vio_frontend* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (auto& si : h->streams)
-    si.graph.destroy();
-  h->graph_all.destroy();
+    for (Graphs& g : si.graph) g.destroy();
+  for (Graphs& g : h->graph_all) g.destroy();
   if (h->arena) {
     if (h->P.dev_free) h->P.dev_free(h->arena, h->P.alloc_ctx);
     else (void)hipFree(h->arena);
   }
-  if (h->h_frame) (void)hipHostFree(h->h_frame);
+  for (FrameTable* f : h->h_frames)
+    if (f) (void)hipHostFree(f);
   if (h->h_rec_count) (void)hipHostFree(h->h_rec_count);
   if (h->h_camstats) (void)hipHostFree(h->h_camstats);
   if (h->h_rec) (void)hipHostFree(h->h_rec);
   if (h->h_stage) (void)hipHostFree(h->h_stage);
   if (h->h_pred) (void)hipHostFree(h->h_pred);
   if (h->h_depth) (void)hipHostFree(h->h_depth);
-  for (hipEvent_t& e : h->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& pr : h->ev)
+    for (hipEvent_t& e : pr)
+      if (e) (void)hipEventDestroy(e);
   if (h->stream) (void)hipStreamDestroy(h->stream);
   if (h->aux) (void)hipStreamDestroy(h->aux);
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -464,26 +481,30 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   // pinned host buffers; records and their counts are written by the
   // selection kernel through the device mapping of h_rec / h_rec_count
   h->stage_bytes = stage;
-  if (hipHostMalloc((void**)&h->h_frame, sizeof(FrameTable)) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_rec_count, sizeof(int32_t) * n_cams) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_camstats, sizeof(int32_t) * kCamStats * n_cams) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * rec_total) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_stage, stage) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * std::max(1, h->pred_cap)) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_depth, sizeof(KpDepth) * std::max(1, h->pred_cap)) != hipSuccess)
+  if (hipHostMalloc((void**)&h->h_frames[0], sizeof(FrameTable)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_frames[1], sizeof(FrameTable)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_rec_count, sizeof(int32_t) * 2 * n_cams) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_camstats, sizeof(int32_t) * kCamStats * 2 * n_cams) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * 2 * rec_total) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_stage, 2 * stage) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * 2 * std::max(1, h->pred_cap)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_depth, sizeof(KpDepth) * 2 * std::max(1, h->pred_cap)) != hipSuccess)
     return fail(h, VIO_ENOMEM, "pinned host buffers");
-  std::memset(h->h_frame, 0, sizeof(FrameTable));
-  std::memset(h->h_rec_count, 0, sizeof(int32_t) * n_cams);
-  std::memset(h->h_camstats, 0, sizeof(int32_t) * kCamStats * n_cams);
+  for (FrameTable* f : h->h_frames) std::memset(f, 0, sizeof(FrameTable));
+  h->h_frame = h->h_frames[0];
+  std::memset(h->h_rec_count, 0, sizeof(int32_t) * 2 * n_cams);
+  std::memset(h->h_camstats, 0, sizeof(int32_t) * kCamStats * 2 * n_cams);
   vio_track* rec_dev = nullptr;
   int32_t *cnt_dev = nullptr, *stats_dev = nullptr;
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&rec_dev, h->h_rec, 0));
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&cnt_dev, h->h_rec_count, 0));
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&stats_dev, h->h_camstats, 0));
   for (int c = 0; c < n_cams; ++c) {
-    h->cams[c].rec = rec_dev + co[c].rec;
-    h->cams[c].rec_count_out = cnt_dev + c;
-    h->cams[c].stats_out = stats_dev + (size_t)kCamStats * c;
+    for (int par = 0; par < 2; ++par) {
+      h->cams[c].rec[par] = rec_dev + par * rec_total + co[c].rec;
+      h->cams[c].rec_count_out[par] = cnt_dev + par * n_cams + c;
+      h->cams[c].stats_out[par] = stats_dev + (size_t)kCamStats * (par * n_cams + c);
+    }
     h->rec_host_off.push_back(co[c].rec);
   }
   HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
@@ -493,7 +514,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
   }
-  for (hipEvent_t& e : h->ev) HIP_CHECK(h, hipEventCreate(&e));
+  for (auto& pr : h->ev)
+    for (hipEvent_t& e : pr) HIP_CHECK(h, hipEventCreate(&e));
   for (auto& pr : h->kev)
     for (hipEvent_t& e : pr) HIP_CHECK(h, hipEventCreate(&e));
   return VIO_OK;
@@ -682,27 +704,55 @@ static void ensure_graph(vio_frontend* h, const LaunchSet& ls, Graphs* gr) {
   }
 }
 
-// Runs one frame of a launch set whose inputs are in h_frame, waits, and
-// updates the statistics of the set's streams. Eager launches report each
-// kernel's duration from its dispatch timestamps; a graph replay reports the
-// frame's device time only.
-static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t st) {
-  ensure_graph(h, ls, gr);
-  HIP_CHECK(h, hipEventRecord(h->ev[0], st));
-  if (gr->whole) {
-    HIP_CHECK(h, hipGraphLaunch(gr->whole, st));
+static int complete_all(vio_frontend* h);
+
+// Submits one frame of a launch set whose inputs are in the current slot's
+// frame table (h_frame) without waiting: the slot's captured graph, or eager
+// launches with per-kernel timing. The next slot becomes the staging slot.
+// At most two submissions are outstanding; eager ones are completed before
+// the next submission (their kernel timing events are shared).
+static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t st) {
+  if (h->n_pend == 2) return fail(h, VIO_ESTATE, "two frames in flight: call vio_frontend_wait first");
+  const int slot = (int)(h->sub & 1);
+  ensure_graph(h, ls, &gr[slot]);
+  const bool graphed = gr[slot].whole != nullptr;
+  if (!graphed && h->n_pend > 0) {
+    const int rc = complete_all(h);
+    if (rc != VIO_OK) return rc;
+  }
+  HIP_CHECK(h, hipEventRecord(h->ev[slot][0], st));
+  if (graphed) {
+    HIP_CHECK(h, hipGraphLaunch(gr[slot].whole, st));
   } else {
     for (bool& r : h->kran) r = false;
     HIP_CHECK(h, enqueue_frame(h, ls, st, true));
   }
-  HIP_CHECK(h, hipEventRecord(h->ev[1], st));
-  HIP_CHECK(h, hipStreamSynchronize(st));
+  HIP_CHECK(h, hipEventRecord(h->ev[slot][1], st));
+  for (int s = ls.stream_begin; s < ls.stream_begin + ls.n_streams; ++s)
+    if (h->h_frame->cam[h->streams[s].first_cam].active) h->streams[s].frames += 1;
+  h->pend[(h->pend_head + h->n_pend) & 1] = vio_frontend::Pending{ls, graphed, slot};
+  h->n_pend += 1;
+  h->sub += 1;
+  h->h_frame = h->h_frames[h->sub & 1];
+  return VIO_OK;
+}
+
+// Waits for the oldest outstanding submission and takes its statistics: the
+// frame's device time, eager launches' kernel times, and the selection
+// kernel's per-camera counts (no pass over the records).
+static int complete_oldest(vio_frontend* h) {
+  if (h->n_pend == 0) return fail(h, VIO_ESTATE, "no frame in flight");
+  const vio_frontend::Pending p = h->pend[h->pend_head];
+  h->pend_head ^= 1;
+  h->n_pend -= 1;
+  HIP_CHECK(h, hipEventSynchronize(h->ev[p.slot][1]));
+  const FrameTable* ft = h->h_frames[p.slot];
   float ms = 0.f;
-  HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+  HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[p.slot][0], h->ev[p.slot][1]));
   float km[kKernels];
   for (int k = 0; k < kKernels; ++k) {
     km[k] = -1.f;
-    if (!gr->whole && h->kran[k]) HIP_CHECK(h, hipEventElapsedTime(&km[k], h->kev[k][0], h->kev[k][1]));
+    if (!p.graphed && h->kran[k]) HIP_CHECK(h, hipEventElapsedTime(&km[k], h->kev[k][0], h->kev[k][1]));
   }
   // deferred stereo matching: the tracker and selection run twice per frame
   h->stats.last_stage_ms[0] = km[kKernPyr];
@@ -712,11 +762,11 @@ static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t
   h->stats.last_learned_ms[1] = km[kKernMlp];
   h->stats.last_gpu_ms = ms;
   h->stats.frames += 1;
-  // the selection kernel's per-camera counts (no pass over the records)
+  const int n_cams = (int)h->cams.size();
   int tr = 0, lost = 0, det = 0, mat = 0, fb = 0;
-  for (int c = ls.cam_begin; c < ls.cam_end; ++c) {
-    if (!h->h_frame->cam[c].active) continue;
-    const int32_t* st = h->h_camstats + (size_t)kCamStats * c;
+  for (int c = p.ls.cam_begin; c < p.ls.cam_end; ++c) {
+    if (!ft->cam[c].active) continue;
+    const int32_t* st = h->h_camstats + (size_t)kCamStats * (ft->cam[c].parity * n_cams + c);
     tr += st[kStatTracked];
     lost += st[kStatLost];
     det += st[kStatDetected];
@@ -728,14 +778,31 @@ static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t
   h->stats.last_lost = lost;
   h->stats.last_detected = det;
   h->stats.last_matched = mat;
-  for (int s = ls.stream_begin; s < ls.stream_begin + ls.n_streams; ++s)
-    if (h->h_frame->cam[h->streams[s].first_cam].active) h->streams[s].frames += 1;
+  for (int s = p.ls.stream_begin; s < p.ls.stream_begin + p.ls.n_streams; ++s)
+    if (ft->cam[h->streams[s].first_cam].active) h->streams[s].done += 1;
   return VIO_OK;
+}
+
+static int complete_all(vio_frontend* h) {
+  while (h->n_pend > 0) {
+    const int rc = complete_oldest(h);
+    if (rc != VIO_OK) return rc;
+  }
+  return VIO_OK;
+}
+
+// Runs one frame of a launch set and waits for it (and for anything submitted
+// before it).
+static int run_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t st) {
+  int rc = complete_all(h);
+  if (rc == VIO_OK) rc = submit_set(h, ls, gr, st);
+  if (rc == VIO_OK) rc = complete_all(h);
+  return rc;
 }
 
 // Runs one frame of stream s whose level-0 sources are already in h_frame.
 static int run_frame(vio_frontend* h, int s, hipStream_t st) {
-  return run_set(h, stream_set(h, s), &h->streams[s].graph, st);
+  return run_set(h, stream_set(h, s), h->streams[s].graph, st);
 }
 
 static int check_push(vio_frontend* h, int32_t s, int64_t t_ns) {
@@ -745,6 +812,7 @@ static int check_push(vio_frontend* h, int32_t s, int64_t t_ns) {
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (si.frames > 0 && t_ns <= si.last_t) return fail(h, VIO_ESTATE, "timestamps must increase");
+  if (h->n_pend == 2) return fail(h, VIO_ESTATE, "two frames in flight: call vio_frontend_wait first");
   if (h->fault_device) return fail(h, VIO_EDEVICE, "injected device failure");
   return VIO_OK;
 }
@@ -786,12 +854,13 @@ static int stage_motion(vio_frontend* h, int s, hipStream_t st) {
     for (int i = 0; i < 3; ++i) f.t[i] = m.t[i];
     f.rho = m.inv_depth;
     f.depth_off = cd.row_off;
+    KpDepth* hd = h->h_depth + (h->sub & 1) * std::max(1, h->pred_cap);  // the staging slot's lists
     int n = 0;
     for (const vio_kp_depth& d : si.depths)
-      if (d.camera == m.camera) h->h_depth[cd.row_off + n++] = KpDepth{d.id, d.inv_depth, 0};
+      if (d.camera == m.camera) hd[cd.row_off + n++] = KpDepth{d.id, d.inv_depth, 0};
     f.n_depth = n;
     if (n > 0)
-      HIP_CHECK(h, hipMemcpyAsync(h->d_depth + cd.row_off, h->h_depth + cd.row_off, sizeof(KpDepth) * n,
+      HIP_CHECK(h, hipMemcpyAsync(h->d_depth + cd.row_off, hd + cd.row_off, sizeof(KpDepth) * n,
                                   hipMemcpyHostToDevice, st));
   }
   si.motion.clear();
@@ -819,7 +888,7 @@ static int upload_host_images(vio_frontend* h, int s, const uint8_t* const* imag
   for (int k = 0; k < si.n_cams; ++k) {
     const int c = si.first_cam + k;
     const CamDesc& cd = h->cams[c];
-    uint8_t* stg = h->h_stage + so;
+    uint8_t* stg = h->h_stage + (h->sub & 1) * h->stage_bytes + so;
     for (int y = 0; y < si.h; ++y) std::memcpy(stg + (size_t)y * si.w, images[k] + (size_t)y * strides[k], si.w);
     HIP_CHECK(h, hipMemcpy2DAsync(cd.lvl[par][0], cd.pitch[0], stg, si.w, si.w, si.h, hipMemcpyHostToDevice, h->stream));
     FrameCam& f = h->h_frame->cam[c];
@@ -844,15 +913,16 @@ static int upload_predictions(vio_frontend* h, int s, const vio_kp_prediction* p
   for (size_t i = 1; i < v.size(); ++i)
     if (v[i].camera == v[i - 1].camera && v[i].id == v[i - 1].id) return fail(h, VIO_EINVAL, "duplicate prediction");
   if (n_pred > h->pred_cap) return fail(h, VIO_EINVAL, "more predictions than keypoint capacity");
+  Prediction* hp = h->h_pred + (h->sub & 1) * std::max(1, h->pred_cap);  // the staging slot's list
   int at = 0;
   for (int k = 0; k < si.n_cams; ++k) {
     FrameCam& f = h->h_frame->cam[si.first_cam + k];
     f.pred_off = at;
     for (const auto& q : v)
-      if (q.camera == k) h->h_pred[at++] = Prediction{q.id, q.x, q.y};
+      if (q.camera == k) hp[at++] = Prediction{q.id, q.x, q.y};
     f.n_pred = at - f.pred_off;
   }
-  HIP_CHECK(h, hipMemcpyAsync(h->d_pred, h->h_pred, sizeof(Prediction) * at, hipMemcpyHostToDevice, st));
+  HIP_CHECK(h, hipMemcpyAsync(h->d_pred, hp, sizeof(Prediction) * at, hipMemcpyHostToDevice, st));
   return VIO_OK;
 }
 
@@ -954,7 +1024,8 @@ int vio_frontend_stage_frames_device(vio_frontend* h, int32_t n, const int32_t* 
   return VIO_OK;
 }
 
-int vio_frontend_step(vio_frontend* h) {
+// Submits every staged stream's frame as one batched launch set.
+static int submit_staged(vio_frontend* h) {
   if (!h) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
   if (h->learned && !h->mlp_ready) return fail(h, VIO_ESTATE, "learned init: call vio_frontend_set_mlp first");
@@ -964,7 +1035,7 @@ int vio_frontend_step(vio_frontend* h) {
     for (int k = 0; k < si.n_cams; ++k) h->h_frame->cam[si.first_cam + k].active = si.staged ? 1 : 0;
   }
   if (!any) return fail(h, VIO_ESTATE, "no frame staged");
-  const int rc = run_set(h, all_set(h), &h->graph_all, h->stream);
+  const int rc = submit_set(h, all_set(h), h->graph_all, h->stream);
   if (rc != VIO_OK) return rc;
   for (auto& si : h->streams)
     if (si.staged) {
@@ -973,6 +1044,22 @@ int vio_frontend_step(vio_frontend* h) {
     }
   return VIO_OK;
 }
+
+int vio_frontend_step(vio_frontend* h) {
+  int rc = submit_staged(h);
+  if (rc == VIO_OK) rc = complete_all(h);
+  return rc;
+}
+
+int vio_frontend_step_async(vio_frontend* h) { return submit_staged(h); }
+
+int vio_frontend_wait(vio_frontend* h) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  return complete_oldest(h);
+}
+
+int vio_frontend_in_flight(const vio_frontend* h) { return h ? h->n_pend : 0; }
 
 int vio_frontend_set_camera_model(vio_frontend* h, int32_t s, int32_t camera, const vio_pinhole* K) {
   if (!h) return VIO_EINVAL;
@@ -991,6 +1078,7 @@ int vio_frontend_set_detection_mask(vio_frontend* h, int32_t s, int32_t camera, 
                                     int32_t pitch) {
   if (!h) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera %d out of range", camera);
@@ -1044,21 +1132,33 @@ int vio_frontend_set_motion(vio_frontend* h, int32_t s, const vio_camera_motion*
   return VIO_OK;
 }
 
+// The record count and records of camera c's last completed frame (records
+// are double-buffered by frame parity).
+static int rec_count(const vio_frontend* h, const StreamInfo& si, int c) {
+  const int par = (int)((si.done - 1) & 1);
+  return h->h_rec_count[par * (int)h->cams.size() + c];
+}
+
+static const vio_track* rec_ptr(const vio_frontend* h, const StreamInfo& si, int c) {
+  const int par = (int)((si.done - 1) & 1);
+  return h->h_rec + (size_t)par * h->rec_total + h->rec_host_off[c];
+}
+
 int vio_frontend_get_tracks(vio_frontend* h, int32_t s, vio_track* out, int32_t capacity, int32_t* n_out) {
   if (!h || !n_out) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
-  if (si.frames == 0) return fail(h, VIO_ESTATE, "no frame pushed yet");
+  if (si.done == 0) return fail(h, VIO_ESTATE, "no frame completed yet");
   int n = 0;
-  for (int k = 0; k < si.n_cams; ++k) n += h->h_rec_count[si.first_cam + k];
+  for (int k = 0; k < si.n_cams; ++k) n += rec_count(h, si, si.first_cam + k);
   *n_out = n;
   if (capacity < n) return VIO_ETOOSMALL;
   if (n > 0 && !out) return VIO_EINVAL;
   int at = 0;
   for (int k = 0; k < si.n_cams; ++k) {
-    const int m = h->h_rec_count[si.first_cam + k];
-    std::memcpy(out + at, h->h_rec + h->rec_host_off[si.first_cam + k], sizeof(vio_track) * m);
+    const int m = rec_count(h, si, si.first_cam + k);
+    std::memcpy(out + at, rec_ptr(h, si, si.first_cam + k), sizeof(vio_track) * m);
     at += m;
   }
   return VIO_OK;
@@ -1073,9 +1173,9 @@ int vio_frontend_get_tracks_streams(vio_frontend* h, int32_t n, const int32_t* s
     const int s = streams[i];
     if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
     const StreamInfo& si = h->streams[s];
-    if (si.frames == 0) return fail(h, VIO_ESTATE, "stream %d: no frame pushed yet", s);
+    if (si.done == 0) return fail(h, VIO_ESTATE, "stream %d: no frame completed yet", s);
     int m = 0;
-    for (int k = 0; k < si.n_cams; ++k) m += h->h_rec_count[si.first_cam + k];
+    for (int k = 0; k < si.n_cams; ++k) m += rec_count(h, si, si.first_cam + k);
     counts[i] = m;
     total += m;
   }
@@ -1086,8 +1186,8 @@ int vio_frontend_get_tracks_streams(vio_frontend* h, int32_t n, const int32_t* s
   for (int i = 0; i < n; ++i) {
     const StreamInfo& si = h->streams[streams[i]];
     for (int k = 0; k < si.n_cams; ++k) {
-      const int m = h->h_rec_count[si.first_cam + k];
-      std::memcpy(out + at, h->h_rec + h->rec_host_off[si.first_cam + k], sizeof(vio_track) * m);
+      const int m = rec_count(h, si, si.first_cam + k);
+      std::memcpy(out + at, rec_ptr(h, si, si.first_cam + k), sizeof(vio_track) * m);
       at += m;
     }
   }
@@ -1099,6 +1199,7 @@ static int state_slot(const StreamInfo& si) { return (int)((si.frames & 1) ^ 1);
 int vio_frontend_set_keypoints(vio_frontend* h, int32_t s, int32_t camera, const vio_keypoint* kps, int32_t n) {
   if (!h) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera out of range");
@@ -1124,6 +1225,7 @@ int vio_frontend_get_keypoints(vio_frontend* h, int32_t s, int32_t camera, vio_k
                                int32_t* n_out) {
   if (!h || !n_out) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera out of range");
@@ -1141,6 +1243,7 @@ int vio_frontend_get_pyramid(vio_frontend* h, int32_t s, int32_t camera, int32_t
                              size_t capacity) {
   if (!h || !out) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (camera < 0 || camera >= si.n_cams || level < 0 || level >= h->P.levels) return fail(h, VIO_EINVAL, "bad camera/level");
@@ -1157,6 +1260,7 @@ int vio_frontend_get_cell_winners(vio_frontend* h, int32_t s, int32_t camera, in
                                   int32_t* n_out) {
   if (!h || !n_out) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera out of range");
@@ -1185,6 +1289,7 @@ int vio_frontend_get_cell_winners(vio_frontend* h, int32_t s, int32_t camera, in
 int vio_frontend_set_mlp(vio_frontend* h, const float* params, int32_t n, float rho) {
   if (!h || !params || n != VIO_MLP_NPARAM) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
   if (!h->learned) return fail(h, VIO_ESTATE, "the frontend was not created with VIO_INIT_LEARNED");
   HIP_CHECK(h, hipStreamSynchronize(h->stream));
   HIP_CHECK(h, hipMemcpy(h->mlp.P, params, sizeof(float) * VIO_MLP_NPARAM, hipMemcpyHostToDevice));
@@ -1193,10 +1298,8 @@ int vio_frontend_set_mlp(vio_frontend* h, const float* params, int32_t n, float 
   if (rho >= 0.f) h->P.learned_rho = rho;
   // the captured graphs hold the old threshold as a kernel argument
   for (auto& si : h->streams)
-    if (si.graph.any()) {
-      si.graph.destroy();
-    }
-  h->graph_all.destroy();
+    for (Graphs& g : si.graph) g.destroy();
+  for (Graphs& g : h->graph_all) g.destroy();
   h->mlp_ready = true;
   return VIO_OK;
 }
@@ -1205,6 +1308,7 @@ int vio_frontend_get_features(vio_frontend* h, int32_t s, int32_t camera, float*
                               int32_t* n_out) {
   if (!h || !n_out) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
   if (!h->learned) return fail(h, VIO_ESTATE, "features exist in learned mode only");
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];

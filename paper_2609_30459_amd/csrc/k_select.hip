@@ -141,14 +141,14 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
         cd.state[P][pos] = fc.has_prev ? make_kp(kp.id, r.x, r.y, kp.x, kp.y, kp.age + 1) : kp;
       }
       if (fc.has_prev)
-        cd.rec[j] = make_rec(kp.id, cd.local, r.status, r.x, r.y, r.theta, r.fb, r.resid,
+        cd.rec[P][j] = make_rec(kp.id, cd.local, r.status, r.x, r.y, r.theta, r.fb, r.resid,
                              alive ? kp.age + 1 : kp.age, -1);
     }
     base += total;
   }
   *n_rec = fc.has_prev ? n_prev : 0;
   if (threadIdx.x == 0) {
-    int32_t* st = cd.stats_out;
+    int32_t* st = cd.stats_out[P];
     st[kStatFallback] = n_fb;
     st[kStatTracked] = fc.has_prev ? base : 0;
     st[kStatLost] = fc.has_prev ? n_prev - base : 0;
@@ -183,7 +183,7 @@ __device__ void accept_matches(const CamDesc& L, int P, int sel_base, const CamD
     if (valid) {
       const bool accepted = matched && n_surv_r + mrank < R.cap;
       const int st = matched ? (accepted ? VIO_MATCHED : VIO_LOST_CAP) : sr.status;
-      R.rec[n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
+      R.rec[PR][n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
       if (accepted) R.state[PR][n_surv_r + mrank] = make_kp(id, sr.x, sr.y, sr.x, sr.y, 0);
     }
     m_base += m_tot;
@@ -192,8 +192,8 @@ __device__ void accept_matches(const CamDesc& L, int P, int sel_base, const CamD
     const int accepted = min(m_base, max(0, R.cap - n_surv_r));
     cnt->n_live[PR][rc] = n_surv_r + accepted;
     cnt->rec_count[rc] = n_rec_r + n_new;
-    *R.rec_count_out = n_rec_r + n_new;
-    R.stats_out[kStatMatched] = accepted;
+    *R.rec_count_out[PR] = n_rec_r + n_new;
+    R.stats_out[PR][kStatMatched] = accepted;
   }
 }
 
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         const float x = (float)(idx % L.w), y = (float)(idx / L.w);
         const int64_t id = next_id + rank;
         L.state[P][n_surv + rank] = make_kp(id, x, y, x, y, 0);
-        L.rec[n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
+        L.rec[P][n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
         s_sel[rank] = (uint16_t)slot;
       }
       eq_base += eq_tot;
@@ -320,8 +320,8 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     if (threadIdx.x == 0) {
       cnt->n_live[P][lc] = n_surv + n_new;
       cnt->rec_count[lc] = n_rec + n_new;
-      *L.rec_count_out = n_rec + n_new;
-      L.stats_out[kStatDetected] = n_new;
+      *L.rec_count_out[P] = n_rec + n_new;
+      L.stats_out[P][kStatDetected] = n_new;
     }
     for (int i = threadIdx.x; i < nslots; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
     __syncthreads();

@@ -147,3 +147,81 @@ def test_step_counts_equal_the_records(stereo_mode):
             assert st["last_matched"] == int((recs["status"] == MAT).sum()), t
             assert st["last_lost"] == (prev_live - n_tr if prev_live is not None else 0), t
             prev_live = int(np.isin(recs["status"], [TR, DET, MAT]).sum())
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_pipelined_steps_equal_synchronous_steps(learned):
+    """Frame t+1 submitted before frame t's records are read (two frames in
+    flight, device images, host images staged from the second slot, a stream
+    left out of some steps): every frame's records equal synchronous steps'."""
+    import torch
+
+    import paper_2609_30459_amd as vf
+    n = 6
+    seqs = _seqs(n)
+    devs = [torch.from_numpy(q.frames).cuda() for q in seqs]
+    extra = {}
+    if learned:
+        import os
+        from paper_2609_30459_amd.train_mlp import load_weights
+        params, rho, _ = load_weights(os.path.join(os.path.dirname(vf.__file__), "weights", "mlp_stereo1280.bin"))
+        extra = dict(init_mode=1, learned_levels=2, learned_iters=3, learned_rho=rho)
+
+    def staged(t):
+        return [s for s in range(3) if not (s == 2 and t % 3 == 1)]  # stream 2 skips some frames
+
+    def stage(fe, t):
+        for s in staged(t):
+            imgs = [devs[s][t, c] for c in range(MIX[s].n_cams)]
+            if s == 0:
+                fe.stage_frame(s, t + 1, [q.cpu().numpy() for q in imgs])  # host images
+            else:
+                fe.stage_frame_device(s, t + 1, imgs)
+
+    with vf.Frontend(_streams(), vf.params_for(MIX[1], **extra)) as a, \
+            vf.Frontend(_streams(), vf.params_for(MIX[1], **extra)) as b:
+        if learned:
+            a.set_mlp(params, rho)
+            b.set_mlp(params, rho)
+        want = []
+        for t in range(n):
+            stage(b, t)
+            b.step()
+            want.append({s: b.get_tracks(s).tobytes() for s in staged(t)})
+        got = []
+        stage(a, 0)
+        a.step_async()
+        for t in range(1, n + 1):
+            if t < n:
+                stage(a, t)
+                a.step_async()
+                assert a.in_flight == 2
+                with pytest.raises(vf.VioError):
+                    a.stage_frame_device(1, 1000 + t, [devs[1][t, c] for c in range(2)])  # a third frame
+            a.wait()
+            got.append({s: a.get_tracks(s).tobytes() for s in staged(t - 1)})
+        assert a.in_flight == 0
+        with pytest.raises(vf.VioError):
+            a.wait()
+        for t in range(n):
+            assert got[t] == want[t], t
+            assert all(len(r) > 0 for r in got[t].values())
+
+
+def test_calls_during_a_frame_in_flight_wait_for_it():
+    import torch
+
+    import paper_2609_30459_amd as vf
+    seqs = _seqs(3)
+    devs = [torch.from_numpy(q.frames).cuda() for q in seqs]
+    with vf.Frontend(_streams(), vf.params_for(MIX[1])) as a, vf.Frontend(_streams(), vf.params_for(MIX[1])) as b:
+        for t in range(3):
+            for fe in (a, b):
+                for s in range(3):
+                    fe.stage_frame_device(s, t + 1, [devs[s][t, c] for c in range(MIX[s].n_cams)])
+            a.step_async()
+            b.step()
+            # a keypoint read drains the frame in flight
+            assert a.get_keypoints(1, 0).tobytes() == b.get_keypoints(1, 0).tobytes()
+            assert a.in_flight == 0
+            assert a.get_tracks(1).tobytes() == b.get_tracks(1).tobytes()

@@ -38,6 +38,7 @@ PYR_CASES = [
     ("hd1280", 1280, 720, 4, 48, 4.0),
     ("rig1920x1200_L5", 1920, 1200, 5, 32, 4.0),
     ("wide2000x70_L6", 2000, 140, 6, 20, 4.0),
+    ("min16x16_L1", 16, 16, 1, 8, 4.0),
 ]
 
 
@@ -62,6 +63,43 @@ def test_pyramid_and_cell_winners_bit_exact(name, w, h, levels, cell, density, t
         ref = oracle.detect(img, cell)[:, 0]
         assert (win == ref).all(), f"{(win != ref).any(1).sum()} cells differ"
         assert (ref[:, 2] >= 0).sum() > 0 or w < 64
+
+
+def test_largest_image_winners_and_pyramid_bit_exact():
+    """The largest image the boundary takes (width * height < 2^24: 4096 x 4095),
+    six levels, 64-px cells (4096 cells): a rendered 1024 x 1024 texture tiled
+    with flips, so the tiles' seams are textured too."""
+    vf = _vf()
+    base = _image(1024, 1024, 4.0, seed=17)
+    row = np.concatenate([base, base[:, ::-1], base, base[:, ::-1]], 1)
+    img = np.ascontiguousarray(np.concatenate([row, row[::-1], row, row[::-1]], 0)[:4095])
+    w, h, L, cell = 4096, 4095, 6, 64
+    print(f"case max {w}x{h} L={L}", flush=True)
+    with vf.Frontend([(1, w, h, 2000, cell)], vf.make_params(levels=L, cell_size=cell, max_keypoints=2000)) as fe:
+        fe.push_stereo_frame(0, 1, [img])
+        want = oracle.pyramid(img, L)
+        for l in range(L):
+            assert (fe.get_pyramid(0, 0, l) == want[l]).all(), l
+        win = fe.get_cell_winners(0, 0)
+        rec = fe.get_tracks(0)
+    ref = oracle.detect(img, cell)[:, 0]
+    assert (win == ref).all(), f"{(win != ref).any(1).sum()} cells differ"
+    assert (rec["status"] == oracle.DETECTED).sum() == min(2000, (ref[:, 2] >= 0).sum())
+
+
+@pytest.mark.parametrize("value", [0, 128, 255])
+def test_uniform_images_give_no_keypoints(value):
+    """A uniform image has no corner (every FAST difference is 0), so nothing
+    is detected, matched or tracked, on every frame."""
+    vf = _vf()
+    w = synthgen.WORKLOADS["stereo752"]
+    img = np.full((w.height, w.width), value, np.uint8)
+    with vf.Frontend([(2, w.width, w.height, 300, 32)], vf.params_for(w)) as fe:
+        for t in range(3):
+            fe.push_stereo_frame(0, t + 1, [img, img])
+            assert len(fe.get_tracks(0)) == 0
+            assert (fe.get_cell_winners(0, 0) == -1).all()
+    assert (oracle.detect(img, 32) == -1).all()
 
 
 def test_device_push_with_unaligned_pitch_matches_oracle():
