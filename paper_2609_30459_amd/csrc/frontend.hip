@@ -733,7 +733,15 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
   h->pend[(h->pend_head + h->n_pend) & 1] = vio_frontend::Pending{ls, graphed, slot};
   h->n_pend += 1;
   h->sub += 1;
-  h->h_frame = h->h_frames[h->sub & 1];
+  // a stream staged for a later step but not in this submission keeps its
+  // staged inputs in the next slot's table
+  FrameTable* next = h->h_frames[h->sub & 1];
+  for (int s = 0; s < (int)h->streams.size(); ++s) {
+    const StreamInfo& si = h->streams[s];
+    if (!si.staged || (s >= ls.stream_begin && s < ls.stream_begin + ls.n_streams)) continue;
+    for (int k = 0; k < si.n_cams; ++k) next->cam[si.first_cam + k] = h->h_frame->cam[si.first_cam + k];
+  }
+  h->h_frame = next;
   return VIO_OK;
 }
 

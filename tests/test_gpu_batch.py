@@ -225,3 +225,21 @@ def test_calls_during_a_frame_in_flight_wait_for_it():
             assert a.get_keypoints(1, 0).tobytes() == b.get_keypoints(1, 0).tobytes()
             assert a.in_flight == 0
             assert a.get_tracks(1).tobytes() == b.get_tracks(1).tobytes()
+
+
+def test_push_between_staging_and_step_keeps_the_staged_frame():
+    """Stream 1 is staged, stream 0 is pushed on its own, then the step runs
+    stream 1: its records equal a handle where nothing came in between."""
+    import paper_2609_30459_amd as vf
+    seqs = _seqs(3)
+    with vf.Frontend(_streams(), vf.params_for(MIX[1])) as a, vf.Frontend(_streams(), vf.params_for(MIX[1])) as b:
+        for t in range(3):
+            a.stage_frame(1, t + 1, list(seqs[1].frames[t]))
+            a.push_stereo_frame(0, t + 1, list(seqs[0].frames[t]))
+            a.step()
+            b.stage_frame(1, t + 1, list(seqs[1].frames[t]))
+            b.step()
+            b.push_stereo_frame(0, t + 1, list(seqs[0].frames[t]))
+            for s in (0, 1):
+                ra = a.get_tracks(s)
+                assert len(ra) > 0 and ra.tobytes() == b.get_tracks(s).tobytes(), (t, s)
