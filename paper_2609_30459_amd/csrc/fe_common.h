@@ -69,10 +69,11 @@ struct CamDesc {
   int local;           // camera index within its stream
   int tiles_x, tiles_y, tile_begin;  // pyramid/detector tiles of this camera
   int pitch[kMaxLevels];
-  uint8_t* lvl[2][kMaxLevels];       // two pyramid slots (frame parity)
+  uint8_t* lvl[3][kMaxLevels];       // three pyramid slots (frame index mod 3: the next frame's pyramid
+                                     // is built while the last two frames' are still read)
   Kp* state[2];                      // keypoint state, double-buffered by frame parity
   TrackRes* res;                     // temporal results [cap]
-  uint32_t* keys[2];                 // packed winner keys, slot cell * k + rank, by frame parity [nslots]
+  uint32_t* keys[3];                 // packed winner keys, slot cell * k + rank, by pyramid slot [nslots]
   TrackRes* sres;                    // stereo matches [n_targets][nslots], by key slot or selection rank
   const uint8_t* mask;               // detection mask [h][w] (detecting cameras)
   // outputs in mapped pinned host memory, by frame parity (the host reads one
@@ -100,7 +101,8 @@ struct FrameCam {
   const uint8_t* src;  // level-0 image to read (own level 0 or the caller's)
   int src_pitch;
   int copy_l0;         // 1: write src into the own level-0 buffer
-  int parity;          // current slot; the previous frame is parity ^ 1
+  int parity;          // keypoint state and record slot; the previous frame's is parity ^ 1
+  int pyr, pyr_prev;   // pyramid and key slots (frame index mod 3) of this and the previous frame
   int has_prev;        // a previous frame exists (temporal tracking runs)
   int active;          // camera takes part in this frame
   int n_pred;          // caller predictions for this camera (ascending id)

@@ -36,12 +36,19 @@ static_assert(kMaxCellsAbi * kMaxPerCell <= 65536, "the selection kernel keeps k
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Captured submit of a launch set: the whole frame as one graph.
+// Captured launches of one submission slot: the learned stage (features and
+// network) and the tracking part (tracker and selection) of a frame. The
+// frame-table copy and the pyramid/detector run as plain launches on the
+// pyramid stream.
 struct Graphs {
-  hipGraphExec_t whole = nullptr;
-  bool any() const { return whole != nullptr; }
+  hipGraphExec_t learn = nullptr, trk = nullptr;
+  bool captured = false;
+  bool any() const { return captured; }
   void destroy() {
-    if (whole) (void)hipGraphExecDestroy(whole);
-    whole = nullptr;
+    if (learn) (void)hipGraphExecDestroy(learn);
+    if (trk) (void)hipGraphExecDestroy(trk);
+    learn = trk = nullptr;
+    captured = false;
   }
 };
 
@@ -100,7 +107,8 @@ struct vio_frontend {
   // device
   void* arena = nullptr;
   CamDesc* d_cams = nullptr;
-  FrameTable* d_frame = nullptr;
+  FrameTable* d_frames[2] = {nullptr, nullptr};  // by submission slot
+  FrameTable* d_frame = nullptr;                 // the slot being launched
   Counters* d_cnt = nullptr;
   TrackSeg* d_segs = nullptr;
   TrackSeg* d_segs_all = nullptr;
@@ -139,12 +147,9 @@ struct vio_frontend {
   size_t stage_bytes = 0;
   Prediction* h_pred = nullptr;  // [slot][pred_cap]
   KpDepth* h_depth = nullptr;    // [slot][pred_cap]
-  hipStream_t stream = nullptr;
-  // learned mode: the network's inputs are the previous frame's, so features
-  // and network run on a second stream beside the pyramid (fork after the
-  // frame-table copy, join before tracking)
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t stream = nullptr;   // the launch stream: learned stage, tracking, selection
+  hipStream_t pstream = nullptr;  // frame-table copies and pyramids/detections
+  hipEvent_t ev_copy[2] = {}, ev_pyr[2] = {}, ev_in = nullptr;  // per slot: copy and pyramid done
   hipEvent_t ev[2][2] = {};  // per submission slot: frame start and end on the launch stream
   // eager launches: start/stop events attached to each kernel's dispatch
   // (pyramid+detector, features, network, tracker, selection)
@@ -246,6 +251,7 @@ void vio_frontend_default_params(vio_frontend_params* p) {
 void vio_frontend_destroy(vio_frontend* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->pstream) (void)hipStreamSynchronize(h->pstream);
   for (auto& si : h->streams)
     for (Graphs& g : si.graph) g.destroy();
   for (Graphs& g : h->graph_all) g.destroy();
@@ -264,10 +270,13 @@ void vio_frontend_destroy(vio_frontend* h) {
   for (auto& pr : h->ev)
     for (hipEvent_t& e : pr)
       if (e) (void)hipEventDestroy(e);
+  for (int slot = 0; slot < 2; ++slot) {
+    if (h->ev_copy[slot]) (void)hipEventDestroy(h->ev_copy[slot]);
+    if (h->ev_pyr[slot]) (void)hipEventDestroy(h->ev_pyr[slot]);
+  }
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->stream) (void)hipStreamDestroy(h->stream);
-  if (h->aux) (void)hipStreamDestroy(h->aux);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->pstream) (void)hipStreamDestroy(h->pstream);
   delete h;
 }
 
@@ -284,7 +293,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     return o;
   };
   struct CamOffs {
-    size_t lvl[2][kMaxLevels], state[2], res, keys[2], sres, rec, mask;
+    size_t lvl[3][kMaxLevels], state[2], res, keys[3], sres, rec, mask;
   };
   std::vector<CamOffs> co(n_cams);
   int cam = 0, tiles = 0, rows_total = 0, items = 0;
@@ -329,13 +338,13 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
         c.pitch[l] = (int)round_up((size_t)(si.w >> l), 64);
         // one guard row: the tracker's template window reads up to one row and
         // one column past a level (with weight 0)
-        for (int par = 0; par < 2; ++par)
-          co[cam].lvl[par][l] = take((size_t)c.pitch[l] * (size_t)((si.h >> l) + 1));
+        for (int ps = 0; ps < 3; ++ps)
+          co[cam].lvl[ps][l] = take((size_t)c.pitch[l] * (size_t)((si.h >> l) + 1));
       }
       for (int par = 0; par < 2; ++par) co[cam].state[par] = take(sizeof(Kp) * si.cap);
       co[cam].res = take(sizeof(TrackRes) * si.cap);
       if (c.detect) {
-        for (int par = 0; par < 2; ++par) co[cam].keys[par] = take(sizeof(uint32_t) * c.nslots);
+        for (int ps = 0; ps < 3; ++ps) co[cam].keys[ps] = take(sizeof(uint32_t) * c.nslots);
         co[cam].sres = take(sizeof(TrackRes) * c.nslots * std::max(1, c.n_targets));
         co[cam].mask = take((size_t)si.w * si.h);
       }
@@ -387,7 +396,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->pred_cap = 0;
   for (auto& c : h->cams) h->pred_cap += c.cap;
   const size_t o_cams = take(sizeof(CamDesc) * n_cams);
-  const size_t o_frame = take(sizeof(FrameTable));
+  const size_t o_frame = take(2 * sizeof(FrameTable));
   const size_t o_cnt = take(sizeof(Counters));
   const size_t o_segs = take(sizeof(TrackSeg) * h->segs.size());
   const size_t o_segs_all = take(sizeof(TrackSeg) * h->segs_all.size());
@@ -444,17 +453,18 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   for (int c = 0; c < n_cams; ++c) {
     CamDesc& d = h->cams[c];
     for (int l = 0; l < P.levels; ++l)
-      for (int par = 0; par < 2; ++par) d.lvl[par][l] = base + co[c].lvl[par][l];
+      for (int ps = 0; ps < 3; ++ps) d.lvl[ps][l] = base + co[c].lvl[ps][l];
     for (int par = 0; par < 2; ++par) d.state[par] = reinterpret_cast<Kp*>(base + co[c].state[par]);
     d.res = reinterpret_cast<TrackRes*>(base + co[c].res);
     if (d.detect) {
-      for (int par = 0; par < 2; ++par) d.keys[par] = reinterpret_cast<uint32_t*>(base + co[c].keys[par]);
+      for (int ps = 0; ps < 3; ++ps) d.keys[ps] = reinterpret_cast<uint32_t*>(base + co[c].keys[ps]);
       d.sres = reinterpret_cast<TrackRes*>(base + co[c].sres);
       d.mask = reinterpret_cast<const uint8_t*>(base + co[c].mask);
     }
   }
   h->d_cams = reinterpret_cast<CamDesc*>(base + o_cams);
-  h->d_frame = reinterpret_cast<FrameTable*>(base + o_frame);
+  for (int slot = 0; slot < 2; ++slot) h->d_frames[slot] = reinterpret_cast<FrameTable*>(base + o_frame) + slot;
+  h->d_frame = h->d_frames[0];
   h->d_cnt = reinterpret_cast<Counters*>(base + o_cnt);
   h->d_segs = reinterpret_cast<TrackSeg*>(base + o_segs);
   h->d_segs_all = reinterpret_cast<TrackSeg*>(base + o_segs_all);
@@ -509,11 +519,12 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   }
   HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
   HIP_CHECK(h, hipStreamCreate(&h->stream));
-  if (h->learned) {
-    HIP_CHECK(h, hipStreamCreate(&h->aux));
-    HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-    HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  HIP_CHECK(h, hipStreamCreate(&h->pstream));
+  for (int slot = 0; slot < 2; ++slot) {
+    HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_copy[slot], hipEventDisableTiming));
+    HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_pyr[slot], hipEventDisableTiming));
   }
+  HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
   for (auto& pr : h->ev)
     for (hipEvent_t& e : pr) HIP_CHECK(h, hipEventCreate(&e));
   for (auto& pr : h->kev)
@@ -665,38 +676,46 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
   return launch_select(h->d_cams, h->d_frame, h->d_cnt, sc, ls.n_streams, kSelectRight, tune, st);
 }
 
-// The frame's launches. Learned mode forks the features and the network onto
-// the second stream after the frame-table copy (their inputs are the previous
-// frame's keypoints and level 0) and joins before the tracker, so they run
-// beside the pyramid; a captured graph records the fork and join as
-// dependencies.
-static hipError_t enqueue_frame(vio_frontend* h, const LaunchSet& ls, hipStream_t st, bool timed) {
+// A frame runs on two streams. The pyramid stream copies the slot's frame
+// table and builds the pyramid and detections; the launch stream, after the
+// copy, runs the learned stage (its inputs are the previous frame's
+// keypoints and level 0, so it runs beside the pyramid) and, after the
+// pyramid, the tracker and the selection. The pyramid slots rotate over
+// three frames, so the next frame's pyramid can run beside this frame's
+// tracking.
+static hipError_t enqueue_pyr_part(vio_frontend* h, const LaunchSet& ls, int slot, bool timed) {
   hipError_t e;
-  if ((e = enqueue_stage(h, ls, st, 0, timed))) return e;
-  if (h->learned) {
-    if ((e = hipEventRecord(h->ev_fork, st))) return e;
-    if ((e = hipStreamWaitEvent(h->aux, h->ev_fork, 0))) return e;
-    if ((e = enqueue_stage(h, ls, h->aux, 4, timed))) return e;
-    if ((e = hipEventRecord(h->ev_join, h->aux))) return e;
-  }
-  if ((e = enqueue_stage(h, ls, st, 1, timed))) return e;
-  if (h->learned && (e = hipStreamWaitEvent(st, h->ev_join, 0))) return e;
+  if ((e = enqueue_stage(h, ls, h->pstream, 0, timed))) return e;
+  if ((e = hipEventRecord(h->ev_copy[slot], h->pstream))) return e;
+  if ((e = enqueue_stage(h, ls, h->pstream, 1, timed))) return e;
+  return hipEventRecord(h->ev_pyr[slot], h->pstream);
+}
+
+static hipError_t enqueue_track_part(vio_frontend* h, const LaunchSet& ls, hipStream_t st, bool timed) {
+  hipError_t e;
   if ((e = enqueue_stage(h, ls, st, 2, timed))) return e;
   return enqueue_stage(h, ls, st, 3, timed);
 }
 
-// Captures a launch set into a graph on first use; a capture failure switches
-// the handle to eager launches for good.
+// Captures a slot's learned stage and tracking part on first use; a capture
+// failure switches the handle to eager launches for good.
 static void ensure_graph(vio_frontend* h, const LaunchSet& ls, Graphs* gr) {
   if (h->eager || gr->any()) return;
-  hipGraph_t g = nullptr;
-  bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
-  if (ok) {
-    const hipError_t e = enqueue_frame(h, ls, h->stream, false);
-    ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && e == hipSuccess && g;
-  }
-  if (ok) ok = hipGraphInstantiate(&gr->whole, g, nullptr, nullptr, 0) == hipSuccess;
-  if (g) (void)hipGraphDestroy(g);
+  auto capture = [&](hipGraphExec_t* out, bool learned_stage) {
+    hipGraph_t g = nullptr;
+    bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      const hipError_t e = learned_stage ? enqueue_stage(h, ls, h->stream, 4, false)
+                                         : enqueue_track_part(h, ls, h->stream, false);
+      ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && e == hipSuccess && g;
+    }
+    if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    return ok;
+  };
+  bool ok = capture(&gr->trk, false);
+  if (ok && h->learned) ok = capture(&gr->learn, true);
+  gr->captured = ok;
   if (!ok) {
     gr->destroy();
     h->eager = true;
@@ -714,19 +733,30 @@ static int complete_all(vio_frontend* h);
 static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t st) {
   if (h->n_pend == 2) return fail(h, VIO_ESTATE, "two frames in flight: call vio_frontend_wait first");
   const int slot = (int)(h->sub & 1);
+  h->d_frame = h->d_frames[slot];
   ensure_graph(h, ls, &gr[slot]);
-  const bool graphed = gr[slot].whole != nullptr;
+  const bool graphed = gr[slot].any();
   if (!graphed && h->n_pend > 0) {
     const int rc = complete_all(h);
     if (rc != VIO_OK) return rc;
   }
-  HIP_CHECK(h, hipEventRecord(h->ev[slot][0], st));
-  if (graphed) {
-    HIP_CHECK(h, hipGraphLaunch(gr[slot].whole, st));
-  } else {
+  if (!graphed)
     for (bool& r : h->kran) r = false;
-    HIP_CHECK(h, enqueue_frame(h, ls, st, true));
+  if (st != h->stream) {
+    // a caller's stream: the pyramid reads images produced there
+    HIP_CHECK(h, hipEventRecord(h->ev_in, st));
+    HIP_CHECK(h, hipStreamWaitEvent(h->pstream, h->ev_in, 0));
   }
+  HIP_CHECK(h, hipEventRecord(h->ev[slot][0], h->pstream));
+  HIP_CHECK(h, enqueue_pyr_part(h, ls, slot, !graphed));
+  HIP_CHECK(h, hipStreamWaitEvent(st, h->ev_copy[slot], 0));
+  if (h->learned) {
+    if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].learn, st));
+    else HIP_CHECK(h, enqueue_stage(h, ls, st, 4, true));
+  }
+  HIP_CHECK(h, hipStreamWaitEvent(st, h->ev_pyr[slot], 0));
+  if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].trk, st));
+  else HIP_CHECK(h, enqueue_track_part(h, ls, st, true));
   HIP_CHECK(h, hipEventRecord(h->ev[slot][1], st));
   for (int s = ls.stream_begin; s < ls.stream_begin + ls.n_streams; ++s)
     if (h->h_frame->cam[h->streams[s].first_cam].active) h->streams[s].frames += 1;
@@ -831,6 +861,8 @@ static void fill_stream(vio_frontend* h, int s) {
   for (int k = 0; k < si.n_cams; ++k) {
     FrameCam& f = h->h_frame->cam[si.first_cam + k];
     f.parity = par;
+    f.pyr = (int)(si.frames % 3);
+    f.pyr_prev = (int)((si.frames + 2) % 3);
     f.has_prev = si.frames > 0;
     f.active = 1;
     f.n_pred = 0;
@@ -891,16 +923,17 @@ static size_t stage_offset(const vio_frontend* h, int s) {
 // into the current pyramid slot's level 0.
 static int upload_host_images(vio_frontend* h, int s, const uint8_t* const* images, const int32_t* strides) {
   const StreamInfo& si = h->streams[s];
-  const int par = (int)(si.frames & 1);
+  const int ps = (int)(si.frames % 3);
   size_t so = stage_offset(h, s);
   for (int k = 0; k < si.n_cams; ++k) {
     const int c = si.first_cam + k;
     const CamDesc& cd = h->cams[c];
     uint8_t* stg = h->h_stage + (h->sub & 1) * h->stage_bytes + so;
     for (int y = 0; y < si.h; ++y) std::memcpy(stg + (size_t)y * si.w, images[k] + (size_t)y * strides[k], si.w);
-    HIP_CHECK(h, hipMemcpy2DAsync(cd.lvl[par][0], cd.pitch[0], stg, si.w, si.w, si.h, hipMemcpyHostToDevice, h->stream));
+    HIP_CHECK(h, hipMemcpy2DAsync(cd.lvl[ps][0], cd.pitch[0], stg, si.w, si.w, si.h, hipMemcpyHostToDevice,
+                                  h->pstream));
     FrameCam& f = h->h_frame->cam[c];
-    f.src = cd.lvl[par][0];
+    f.src = cd.lvl[ps][0];
     f.src_pitch = cd.pitch[0];
     f.copy_l0 = 0;
     so += (size_t)si.w * si.h;
@@ -1259,8 +1292,8 @@ int vio_frontend_get_pyramid(vio_frontend* h, int32_t s, int32_t camera, int32_t
   const CamDesc& c = h->cams[si.first_cam + camera];
   const int w = c.w >> level, hh = c.h >> level;
   if (capacity < (size_t)w * hh) return VIO_ETOOSMALL;
-  const int par = (int)((si.frames - 1) & 1);
-  HIP_CHECK(h, hipMemcpy2D(out, w, c.lvl[par][level], c.pitch[level], w, hh, hipMemcpyDeviceToHost));
+  const int ps = (int)((si.frames - 1) % 3);
+  HIP_CHECK(h, hipMemcpy2D(out, w, c.lvl[ps][level], c.pitch[level], w, hh, hipMemcpyDeviceToHost));
   return VIO_OK;
 }
 
@@ -1279,8 +1312,8 @@ int vio_frontend_get_cell_winners(vio_frontend* h, int32_t s, int32_t camera, in
   if (capacity < 3 * c.nslots) return VIO_ETOOSMALL;
   if (!out) return VIO_EINVAL;
   std::vector<uint32_t> keys(c.nslots);
-  const int par = (int)((si.frames - 1) & 1);
-  HIP_CHECK(h, hipMemcpy(keys.data(), c.keys[par], sizeof(uint32_t) * c.nslots, hipMemcpyDeviceToHost));
+  const int ps = (int)((si.frames - 1) % 3);
+  HIP_CHECK(h, hipMemcpy(keys.data(), c.keys[ps], sizeof(uint32_t) * c.nslots, hipMemcpyDeviceToHost));
   for (int i = 0; i < c.nslots; ++i) {
     if (!keys[i]) {
       out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = -1;

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64 * kFeatWaves) void k_features(const CamDesc* __r
 
   // ---- pooled patch of the previous frame --------------------------------
   const int rx = (int)floorf(me.x + 0.5f), ry = (int)floorf(me.y + 0.5f);
-  const uint8_t* img = cd.lvl[Q][0];
+  const uint8_t* img = cd.lvl[fc.pyr_prev][0];
   const int pitch = cd.pitch[0];
   const int prow = lane >> 2, col4 = (lane & 3) * 4;
   const int yy = min(max(ry - 8 + prow, 0), cd.h - 1);

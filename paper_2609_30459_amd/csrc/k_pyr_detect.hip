@@ -198,7 +198,7 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   if (!fc.active) return;
   const int t = gtile - cd.tile_begin;
   const int x0 = (t % cd.tiles_x) * kTile, y0 = (t / cd.tiles_x) * kTile;
-  const int W = cd.w, H = cd.h, par = fc.parity;
+  const int W = cd.w, H = cd.h, par = fc.pyr;
   const int tid = threadIdx.x;
 
   // ---- stage level 0 (tile + apron) -------------------------------------

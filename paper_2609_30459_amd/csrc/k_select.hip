@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     __syncthreads();
 
     // ---- candidates of unmasked cells, score histogram --------------------
-    const uint32_t* keys = L.keys[P];
+    const uint32_t* keys = L.keys[fl.pyr];
     for (int i = threadIdx.x; i < nslots; i += kSelectThreads) {
       const uint32_t key = keys[i];
       if (key && (int)s_occ[i / kc] < kc) atomicAdd(&s_hist[key >> 24], 1);
@@ -323,7 +323,10 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       *L.rec_count_out[P] = n_rec + n_new;
       L.stats_out[P][kStatDetected] = n_new;
     }
-    for (int i = threadIdx.x; i < nslots; i += kSelectThreads) L.keys[Q][i] = 0u;  // next frame's buffer
+    // the key buffer of the frame after next (the next frame's was cleared a
+    // frame ago, and its detector may already run beside this selection)
+    uint32_t* next_keys = L.keys[fl.pyr == 0 ? 2 : fl.pyr - 1];
+    for (int i = threadIdx.x; i < nslots; i += kSelectThreads) next_keys[i] = 0u;
     __syncthreads();
 
     // ---- target cameras (a pair's right camera, a star's other three):

@@ -533,8 +533,8 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       try_short = true;
     }
     dst = &cd;
-    ssrc = P ^ 1;
-    sdst = P;
+    ssrc = fc.pyr_prev;
+    sdst = fc.pyr;
     out = cd.res + j;
   } else {
     // stereo match of a detection into target camera c + 1 + t (item j =
@@ -548,7 +548,7 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       px = kp.x;
       py = kp.y;
     } else {
-      const uint32_t key = cd.keys[P][i];
+      const uint32_t key = cd.keys[fc.pyr][i];
       if (key == 0) return;
       const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
       px = (float)(idx % cd.w);
@@ -557,8 +557,8 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
     ix = px - tune.disparity0;
     iy = py;
     dst = &cams[c + 1 + t];
-    ssrc = P;
-    sdst = P;
+    ssrc = fc.pyr;
+    sdst = fc.pyr;
     out = cd.sres + j;
   }
   TrackRes r;
