@@ -134,6 +134,8 @@ typedef struct vio_frontend_params {
 /* vio_frontend_params.flags */
 #define VIO_FLAG_EAGER 1u /* launch the per-frame kernels one by one, each with dispatch timestamps, instead
                              of replaying a captured hipGraph */
+#define VIO_FLAG_PLAIN 2u /* launch the per-frame kernels one by one without timestamps (fewer host calls
+                             than a graph launch for small frames); excludes VIO_FLAG_EAGER */
 
 /* Output record: one per previous keypoint of each camera (tracked or lost) and
  * one per new detection / stereo match, sorted by (camera, id). */

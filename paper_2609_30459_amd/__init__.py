@@ -31,7 +31,7 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
                 max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0, learned_levels=2,
                 learned_iters=3, learned_rho=0.0, eager=False, track_waves_per_cu=0,
                 track_block_waves=0, pyr_tile=0, stereo_mode=0, pred_levels=0, pred_iters=0,
-                pred_rho=0.0, topology=0) -> _n.vio_frontend_params:
+                pred_rho=0.0, topology=0, plain=False) -> _n.vio_frontend_params:
     p = default_params()
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
     p.n_thresholds = len(thresholds)
@@ -40,7 +40,7 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
     p.edge_margin, p.max_keypoints = edge_margin, max_keypoints
     p.fb_threshold, p.disparity0, p.init_mode = fb_threshold, disparity0, init_mode
     p.learned_levels, p.learned_iters, p.learned_rho = learned_levels, learned_iters, learned_rho
-    p.flags = _n.VIO_FLAG_EAGER if eager else 0
+    p.flags = (_n.VIO_FLAG_EAGER if eager else 0) | (_n.VIO_FLAG_PLAIN if plain else 0)
     p.track_waves_per_cu = track_waves_per_cu
     p.track_block_waves = track_block_waves
     p.pyr_tile = pyr_tile

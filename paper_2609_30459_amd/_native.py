@@ -66,6 +66,7 @@ DEV_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 VIO_FLAG_EAGER = 1
+VIO_FLAG_PLAIN = 2
 VIO_STEREO_SPECULATIVE = 0
 VIO_STEREO_DEFERRED = 1
 VIO_TOPOLOGY_PAIRS = 0

@@ -39,15 +39,16 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Captured launches of one submission slot: the learned stage (features and
 // network) and the tracking part (tracker and selection) of a frame. The
 // frame-table copy and the pyramid/detector run as plain launches on the
-// pyramid stream.
+// pyramid stream (a captured copy-and-kernel graph launched slower).
 struct Graphs {
   hipGraphExec_t learn = nullptr, trk = nullptr;
   bool captured = false;
   bool any() const { return captured; }
   void destroy() {
-    if (learn) (void)hipGraphExecDestroy(learn);
-    if (trk) (void)hipGraphExecDestroy(trk);
-    learn = trk = nullptr;
+    for (hipGraphExec_t* g : {&learn, &trk}) {
+      if (*g) (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
     captured = false;
   }
 };
@@ -159,6 +160,7 @@ struct vio_frontend {
   bool poisoned = false;
   bool fault_device = false;
   bool eager = false;        // graph capture off (flag) or unavailable
+  bool plain = false;        // plain launches: no graphs, no per-kernel timing
   std::string err;
   vio_stats stats{};
 };
@@ -199,7 +201,9 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   if (p->track_block_waves != 0 && p->track_block_waves != 1 && p->track_block_waves != 2 &&
       p->track_block_waves != kTrackWaves)
     return why = "track_block_waves must be 0, 1, 2 or 4", VIO_EINVAL;
-  if (p->flags & ~VIO_FLAG_EAGER) return why = "unknown flag bits", VIO_EINVAL;
+  if (p->flags & ~(VIO_FLAG_EAGER | VIO_FLAG_PLAIN)) return why = "unknown flag bits", VIO_EINVAL;
+  if ((p->flags & VIO_FLAG_EAGER) && (p->flags & VIO_FLAG_PLAIN))
+    return why = "VIO_FLAG_EAGER and VIO_FLAG_PLAIN exclude each other", VIO_EINVAL;
   if (p->pyr_tile != 0 && p->pyr_tile != 32 && p->pyr_tile != 64) return why = "pyr_tile must be 0, 32 or 64", VIO_EINVAL;
   if (p->stereo_mode != VIO_STEREO_SPECULATIVE && p->stereo_mode != VIO_STEREO_DEFERRED)
     return why = "stereo_mode must be VIO_STEREO_SPECULATIVE or VIO_STEREO_DEFERRED", VIO_EINVAL;
@@ -557,6 +561,7 @@ int vio_frontend_create(const vio_stream_desc* streams, int32_t n_streams, const
   if (!h) return VIO_ENOMEM;
   h->P = *params;
   h->eager = (params->flags & VIO_FLAG_EAGER) != 0;
+  h->plain = (params->flags & VIO_FLAG_PLAIN) != 0;
   h->learned = params->init_mode == VIO_INIT_LEARNED;
   h->tile = params->pyr_tile ? params->pyr_tile : kTileDefault;
   const int rc = create_impl(h, streams, n_streams);
@@ -700,21 +705,22 @@ static hipError_t enqueue_track_part(vio_frontend* h, const LaunchSet& ls, hipSt
 // Captures a slot's learned stage and tracking part on first use; a capture
 // failure switches the handle to eager launches for good.
 static void ensure_graph(vio_frontend* h, const LaunchSet& ls, Graphs* gr) {
-  if (h->eager || gr->any()) return;
-  auto capture = [&](hipGraphExec_t* out, bool learned_stage) {
+  if (h->eager || h->plain || gr->any()) return;
+  // part 1: learned stage, 2: tracking part
+  auto capture = [&](hipGraphExec_t* out, int part) {
+    hipStream_t cs = h->stream;
     hipGraph_t g = nullptr;
-    bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
-      const hipError_t e = learned_stage ? enqueue_stage(h, ls, h->stream, 4, false)
-                                         : enqueue_track_part(h, ls, h->stream, false);
-      ok = hipStreamEndCapture(h->stream, &g) == hipSuccess && e == hipSuccess && g;
+      const hipError_t e = part == 1 ? enqueue_stage(h, ls, cs, 4, false) : enqueue_track_part(h, ls, cs, false);
+      ok = hipStreamEndCapture(cs, &g) == hipSuccess && e == hipSuccess && g;
     }
     if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
     if (g) (void)hipGraphDestroy(g);
     return ok;
   };
-  bool ok = capture(&gr->trk, false);
-  if (ok && h->learned) ok = capture(&gr->learn, true);
+  bool ok = capture(&gr->trk, 2);
+  if (ok && h->learned) ok = capture(&gr->learn, 1);
   gr->captured = ok;
   if (!ok) {
     gr->destroy();
@@ -736,11 +742,13 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
   h->d_frame = h->d_frames[slot];
   ensure_graph(h, ls, &gr[slot]);
   const bool graphed = gr[slot].any();
-  if (!graphed && h->n_pend > 0) {
+  // eager launches time each kernel with shared events: one frame at a time
+  const bool timed = !graphed && !h->plain;
+  if (timed && h->n_pend > 0) {
     const int rc = complete_all(h);
     if (rc != VIO_OK) return rc;
   }
-  if (!graphed)
+  if (timed)
     for (bool& r : h->kran) r = false;
   if (st != h->stream) {
     // a caller's stream: the pyramid reads images produced there
@@ -748,15 +756,15 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
     HIP_CHECK(h, hipStreamWaitEvent(h->pstream, h->ev_in, 0));
   }
   HIP_CHECK(h, hipEventRecord(h->ev[slot][0], h->pstream));
-  HIP_CHECK(h, enqueue_pyr_part(h, ls, slot, !graphed));
-  HIP_CHECK(h, hipStreamWaitEvent(st, h->ev_copy[slot], 0));
+  HIP_CHECK(h, enqueue_pyr_part(h, ls, slot, timed));
   if (h->learned) {
+    HIP_CHECK(h, hipStreamWaitEvent(st, h->ev_copy[slot], 0));
     if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].learn, st));
-    else HIP_CHECK(h, enqueue_stage(h, ls, st, 4, true));
+    else HIP_CHECK(h, enqueue_stage(h, ls, st, 4, timed));
   }
   HIP_CHECK(h, hipStreamWaitEvent(st, h->ev_pyr[slot], 0));
   if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].trk, st));
-  else HIP_CHECK(h, enqueue_track_part(h, ls, st, true));
+  else HIP_CHECK(h, enqueue_track_part(h, ls, st, timed));
   HIP_CHECK(h, hipEventRecord(h->ev[slot][1], st));
   for (int s = ls.stream_begin; s < ls.stream_begin + ls.n_streams; ++s)
     if (h->h_frame->cam[h->streams[s].first_cam].active) h->streams[s].frames += 1;

@@ -270,12 +270,16 @@ def test_graph_replay_equals_eager_launches():
     w = synthgen.WORKLOADS["stereo752"]
     seq = synthgen.sequence(w, seq=6, n_frames=5)
     stream = (2, w.width, w.height, w.max_keypoints, w.cell_size)
-    with vf.Frontend([stream], vf.params_for(w)) as a, vf.Frontend([stream], vf.params_for(w, eager=True)) as b:
+    with vf.Frontend([stream], vf.params_for(w)) as a, vf.Frontend([stream], vf.params_for(w, eager=True)) as b, \
+            vf.Frontend([stream], vf.params_for(w, plain=True)) as c:
         for t in range(5):
             a.push_stereo_frame(0, t + 1, list(seq.frames[t]))
             b.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            c.push_stereo_frame(0, t + 1, list(seq.frames[t]))
             ra, rb = a.get_tracks(0), b.get_tracks(0)
             assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), t
+            assert ra.tobytes() == c.get_tracks(0).tobytes(), t  # plain launches, no timing
+            assert c.stats()["last_stage_ms"] == [-1.0] * 3
             sa, sb = a.stats(), b.stats()
             assert sa["last_stage_ms"] == [-1.0] * 3 and sa["last_gpu_ms"] > 0
             assert all(m > 0 for m in sb["last_stage_ms"]), sb
