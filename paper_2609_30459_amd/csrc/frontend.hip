@@ -691,7 +691,8 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
 static hipError_t enqueue_pyr_part(vio_frontend* h, const LaunchSet& ls, int slot, bool timed) {
   hipError_t e;
   if ((e = enqueue_stage(h, ls, h->pstream, 0, timed))) return e;
-  if ((e = hipEventRecord(h->ev_copy[slot], h->pstream))) return e;
+  // the learned stage starts after the copy (beside the pyramid)
+  if (h->learned && (e = hipEventRecord(h->ev_copy[slot], h->pstream))) return e;
   if ((e = enqueue_stage(h, ls, h->pstream, 1, timed))) return e;
   return hipEventRecord(h->ev_pyr[slot], h->pstream);
 }
