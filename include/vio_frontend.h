@@ -193,7 +193,8 @@ typedef struct vio_kp_depth {
 
 typedef struct vio_stats {
   int64_t frames;        /* frames processed by the handle */
-  double last_gpu_ms;    /* device time of the last frame (first kernel to last) */
+  double last_gpu_ms;    /* device time of the last completed frame, from its frame-table copy to its
+                            selection (with frames in flight it overlaps the neighbouring frames') */
   double last_stage_ms[3]; /* durations of the last frame's pyramid+detector, tracker and selection
                               kernels from their own dispatch timestamps (HIP events attached to the
                               launch); -1 unless launched one by one (VIO_FLAG_EAGER) */
@@ -203,7 +204,8 @@ typedef struct vio_stats {
   int32_t last_lost;     /* lost temporal records of the last frame */
   int32_t last_detected; /* VIO_DETECTED records */
   int32_t last_matched;  /* VIO_MATCHED records */
-  int32_t last_fallback; /* learned init: tracks that fell back to the plain tracker */
+  int32_t last_fallback; /* tracks whose short attempt (learned or predicted start) fell back to the
+                            full budget */
 } vio_stats;
 
 typedef struct vio_frontend vio_frontend;
