@@ -186,6 +186,29 @@ def test_device_push_equals_host_push_bitwise():
             assert ra.tobytes() == rb.tobytes(), t
 
 
+def test_device_push_on_a_caller_stream_waits_for_its_images():
+    """Images written on the caller's stream right before the push (a copy
+    into a reused buffer), then read by the frontend on that stream: the
+    pyramid, on its own stream, starts after the caller's work."""
+    import torch
+    vf = _vf()
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=3, n_frames=5)
+    src = torch.from_numpy(seq.frames).cuda()
+    buf = torch.empty_like(src[0])
+    torch.cuda.synchronize()
+    cs = torch.cuda.Stream()  # default priority
+    stream = (2, w.width, w.height, w.max_keypoints, w.cell_size)
+    with vf.Frontend([stream], vf.params_for(w)) as a, vf.Frontend([stream], vf.params_for(w)) as b:
+        for t in range(5):
+            a.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            with torch.cuda.stream(cs):
+                buf.copy_(src[t])
+            b.push_stereo_frame_device(0, t + 1, [buf[0], buf[1]], hip_stream=cs)
+            ra, rb = a.get_tracks(0), b.get_tracks(0)
+            assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), t
+
+
 def test_runs_are_deterministic():
     vf = _vf()
     w = synthgen.WORKLOADS["stereo752"]
