@@ -9,16 +9,18 @@ default workload is 752x480 stereo: a seeded synthetic 200-frame sequence with
 4 pyramid levels, 5 Gauss-Newton iterations per level, <= 300 keypoints per
 camera.
 
-The sequences are resident in HBM before timing starts. A single-stream step
-pushes one frame's device images through the C ABI and reads the frame's
-records (the synchronous submit-and-wait of the paper's pipeline); the batch16
-workload stages one frame of each of its sixteen streams and runs them as one
-batched step. The timed steps replay one captured graph per step (the
-frontend's production path; `value`). A second timed region runs the same
-steps with the kernels launched one by one, each with HIP start/stop events
-attached to its own dispatch: it gives the kernel durations behind the
-roofline figures and is reported beside the first (`second_launch`, with a
-check that both give identical records). Prints one JSON line.
+The sequences are resident in HBM before timing starts. A step stages one
+frame's device images of every stream of the workload through the C ABI,
+submits it, and reads the records back. The first timed region is the
+production path and gives `value`: pipelined submission (frame t is submitted
+before frame t-1's records are waited for and read, two frames in flight) with
+the kernels launched one by one without timestamps (`--launch graph`:
+captured graphs; `--no-pipeline`: one frame at a time, the paper's
+submit-and-wait). A second timed region runs the same steps one frame at a
+time with each kernel's HIP start/stop events attached to its own dispatch: it
+gives the kernel durations behind the roofline figures and is reported beside
+the first (`second_launch`, with a check that both give identical records).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -102,9 +104,10 @@ def main():
     ap.add_argument("--seq", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", choices=["eager", "graph"], default="graph",
-                    help="first timed region (`value`): one captured graph per frame (default), or the kernels "
-                         "launched one by one with HIP events attached to each dispatch (gives kernel durations)")
+    ap.add_argument("--launch", choices=["plain", "graph", "eager"], default="plain",
+                    help="first timed region (`value`): the kernels launched one by one without timestamps "
+                         "(default; the fewest host calls per pipelined frame), captured graphs, or one by one "
+                         "with HIP events attached to each dispatch (gives kernel durations)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="graph launches one frame at a time (no frame submitted before the last one's records are read)")
     ap.add_argument("--no-second-launch", "--no-graph-replay", dest="no_second", action="store_true",
@@ -239,7 +242,7 @@ def main():
     def timed_run(eager):
         """Warmup, then the timed steps: (records per stream, wall s per step, stats per step, elapsed s)."""
         # the streams share one parameter block; per-stream sizes and caps come with the stream
-        fe = vf.Frontend(streams, vf.params_for(w0, eager=eager, **extra))
+        fe = vf.Frontend(streams, vf.params_for(w0, eager=eager, plain=args.launch == "plain" and not eager, **extra))
         if args.init == "learned":
             fe.set_mlp(mlp_params, rho)
         if motions is not None:
@@ -467,7 +470,7 @@ def main():
                       if short_pred else {}),
                    "cell_size": sorted({w.cell_size for w in ws}), "thresholds": list(w0.thresholds),
                    "init": args.init, "launch": args.launch,
-                   "pipelined": args.launch == "graph" and not args.no_pipeline, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
+                   "pipelined": args.launch != "eager" and not args.no_pipeline, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
                    "stereo_mode": ["speculative", "deferred"][smode],
                    "autotuned": tuned is not None, "parallelism": "single_gpu",
                    **({"learned_levels": args.learned_levels, "learned_iters": args.learned_iters, "rho": rho}
