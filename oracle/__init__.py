@@ -81,7 +81,8 @@ def _lib_():
         lib.orc_fe_next_id.restype = ctypes.c_int64
         lib.orc_fe_set_mlp.argtypes = [vp, vp, i32]
         lib.orc_fe_set_motion.argtypes = [vp, i32, vp, vp, vp, f64, i32, vp, vp]
-        lib.orc_motion_start.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        lib.orc_motion_start.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+        lib.orc_fe_set_stereo.argtypes = [vp, i32, vp, vp, vp, vp, f64]
         lib.orc_fe_last_fallback.argtypes = [vp]
         lib.orc_mlp_nparam.restype = i32
         lib.orc_bf16.argtypes = [ctypes.c_float]
@@ -165,9 +166,10 @@ def _f64(a, n):
     return a
 
 
-def motion_start(K, R, t, pts, rho):
+def motion_start(K, R, t, pts, rho, Kq=None):
     """Camera-model start of the warp (Sec. III-E) for keypoints pts [n, 2] at
-    inverse depths rho [n]: (start [n, 3] = x, y, theta, ok [n])."""
+    inverse depths rho [n], projected into a camera of intrinsics Kq (default
+    K): (start [n, 3] = x, y, theta, ok [n])."""
     pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
     n = len(pts)
     x, y = np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1])
@@ -175,8 +177,10 @@ def motion_start(K, R, t, pts, rho):
     out = np.zeros((n, 3), np.float64)
     ok = np.zeros(n, np.int32)
     K, R, t = _f64(K, 4), _f64(R, 9), _f64(t, 3)
+    Kq = None if Kq is None else _f64(Kq, 4)
     assert _lib_().orc_motion_start(K.ctypes.data, R.ctypes.data, t.ctypes.data, n, x.ctypes.data, y.ctypes.data,
-                                    rho.ctypes.data, out.ctypes.data, ok.ctypes.data) == 0
+                                    rho.ctypes.data, out.ctypes.data, ok.ctypes.data,
+                                    None if Kq is None else Kq.ctypes.data) == 0
     return out, ok.astype(bool)
 
 
@@ -301,6 +305,17 @@ class Frontend:
         """Detection mask of a camera (uint8 HxW, nonzero = no detections), None to remove."""
         m = None if mask is None else _u8(mask)
         assert _lib_().orc_fe_set_mask(self._h, cam, None if m is None else m.ctypes.data) == 0
+
+    def set_stereo(self, cam, Ks=None, Kt=None, R=None, t=None, rho=0.0):
+        """Stereo extrinsics of target camera `cam` (X_target = R X + t, keypoints at
+        inverse depth rho, intrinsics Ks of the detecting and Kt of the target
+        camera); R None: the disparity prior again."""
+        if R is None:
+            assert _lib_().orc_fe_set_stereo(self._h, cam, None, None, None, None, 0.0) == 0
+            return
+        Ks, Kt, R, t = _f64(Ks, 4), _f64(Kt, 4), _f64(R, 9), _f64(t, 3)
+        assert _lib_().orc_fe_set_stereo(self._h, cam, Ks.ctypes.data, Kt.ctypes.data, R.ctypes.data, t.ctypes.data,
+                                         float(rho)) == 0
 
     def records(self):
         n = ctypes.c_int()

@@ -674,7 +674,8 @@ static void adam(float* P, const float* G, float* m, float* v, int t, float lr, 
 // ----------------------------------------------------------------------------
 struct Motion {
   bool on = false;
-  double fx = 0, fy = 0, cx = 0, cy = 0;
+  double fx = 0, fy = 0, cx = 0, cy = 0;      // back-projecting camera
+  double qfx = 0, qfy = 0, qcx = 0, qcy = 0;  // projecting camera (the same one for a temporal motion)
   double R[9] = {}, t[3] = {};
   double rho = 0;                   // inverse depth of keypoints without their own
   std::map<int64_t, double> depth;  // per-keypoint inverse depth, by id
@@ -685,8 +686,8 @@ static bool project_pixel(const Motion& m, double rho, double x, double y, doubl
   double Xn[3];
   for (int i = 0; i < 3; ++i) Xn[i] = m.R[3 * i] * X[0] + m.R[3 * i + 1] * X[1] + m.R[3 * i + 2] * X[2] + m.t[i];
   if (!(rho * Xn[2] > 1e-6)) return false;
-  ox = m.fx * Xn[0] / Xn[2] + m.cx;
-  oy = m.fy * Xn[1] / Xn[2] + m.cy;
+  ox = m.qfx * Xn[0] / Xn[2] + m.qcx;
+  oy = m.qfy * Xn[1] / Xn[2] + m.qcy;
   return true;
 }
 
@@ -715,6 +716,7 @@ struct Frontend {
   int last_fallback = 0;
   std::vector<Motion> motion;  // per camera, for the next frame only
   std::vector<std::vector<uint8_t>> mask;  // per camera detection mask (empty: none)
+  std::vector<Motion> stereo_ext;          // per target camera: the stereo matches' camera-model start
 };
 
 static Record make_record(int64_t id, int cam, int status, float x, float y, float th, float fb, float res,
@@ -872,9 +874,17 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     }
     for (int tc = g + 1; tc < g + group; ++tc) {
       Camera& right = F.cams[tc];
+      const Motion& ext = F.stereo_ext[tc];
       for (const Keypoint& kp : fresh) {
-        const float ix = kp.x - P.disparity0, iy = kp.y;
-        const TrackOut<float> r = track<float>(cur[g], cur[tc], kp.x, kp.y, ix, iy, L, N, P.fb_threshold);
+        // the disparity prior, or the projection through the rig's extrinsics (Sec. III-E)
+        float ix = kp.x - P.disparity0, iy = kp.y, ith = 0.f;
+        double mx, my, mth;
+        if (ext.on && motion_start(ext, ext.rho, kp.x, kp.y, mx, my, mth)) {
+          ix = (float)mx;
+          iy = (float)my;
+          ith = (float)mth;
+        }
+        const TrackOut<float> r = track<float>(cur[g], cur[tc], kp.x, kp.y, ix, iy, L, N, P.fb_threshold, ith);
         int st = r.status == TRACKED ? MATCHED : r.status;
         if (st == MATCHED && (int)right.live.size() >= P.max_keypoints) st = LOST_CAP;
         if (st == MATCHED) right.live.push_back({kp.id, r.x, r.y, r.x, r.y, 0});
@@ -1033,6 +1043,7 @@ void* orc_fe_create(int n_cams, const int32_t* widths, const int32_t* heights, i
   F->cams.resize(n_cams);
   F->motion.resize(n_cams);
   F->mask.resize(n_cams);
+  F->stereo_ext.resize(n_cams);
   for (int c = 0; c < n_cams; ++c) {
     F->cams[c].w = widths[c];
     F->cams[c].h = heights[c];
@@ -1070,10 +1081,10 @@ int orc_fe_set_motion(void* h, int cam, const double* K, const double* R, const 
   if (!(K[0] > 0) || !(K[1] > 0)) return -1;
   Motion m;
   m.on = true;
-  m.fx = K[0];
-  m.fy = K[1];
-  m.cx = K[2];
-  m.cy = K[3];
+  m.fx = m.qfx = K[0];
+  m.fy = m.qfy = K[1];
+  m.cx = m.qcx = K[2];
+  m.cy = m.qcy = K[3];
   for (int i = 0; i < 9; ++i) m.R[i] = R[i];
   for (int i = 0; i < 3; ++i) m.t[i] = t[i];
   m.rho = rho;
@@ -1087,14 +1098,20 @@ int orc_fe_set_motion(void* h, int cam, const double* K, const double* R, const 
 
 // The camera-model start of n keypoints: out[3i..3i+2] = x, y, theta and
 // ok[i] = 1, or ok[i] = 0 when the point does not land in front of the camera.
+// Kq: intrinsics of the camera projected into (NULL: K, the same camera).
 int orc_motion_start(const double* K, const double* R, const double* t, int n, const double* x, const double* y,
-                     const double* rho, double* out, int32_t* ok) {
+                     const double* rho, double* out, int32_t* ok, const double* Kq) {
   if (!K || !R || !t || n < 0) return -1;
+  if (!Kq) Kq = K;
   Motion m;
   m.fx = K[0];
   m.fy = K[1];
   m.cx = K[2];
   m.cy = K[3];
+  m.qfx = Kq[0];
+  m.qfy = Kq[1];
+  m.qcx = Kq[2];
+  m.qcy = Kq[3];
   for (int i = 0; i < 9; ++i) m.R[i] = R[i];
   for (int i = 0; i < 3; ++i) m.t[i] = t[i];
   for (int i = 0; i < n; ++i) {
@@ -1115,6 +1132,37 @@ int orc_fe_set_mask(void* h, int cam, const uint8_t* mask) {
   const Camera& C = F->cams[cam];
   if (mask) F->mask[cam].assign(mask, mask + (size_t)C.w * C.h);
   else F->mask[cam].clear();
+  return 0;
+}
+
+// Stereo extrinsics of target camera `cam` (a pair's right camera or a star's
+// other camera), kept for every following frame: its matches of the detecting
+// camera's new keypoints start at the projection of the keypoint at inverse
+// depth rho, back-projected through Ks (the detecting camera), moved by
+// X_target = R X + t and projected through Kt. R == NULL: the disparity prior.
+int orc_fe_set_stereo(void* h, int cam, const double* Ks, const double* Kt, const double* R, const double* t,
+                      double rho) {
+  auto* F = static_cast<Frontend*>(h);
+  if (!F || cam < 0 || cam >= F->n_cams) return -1;
+  if (!R) {
+    F->stereo_ext[cam] = Motion();
+    return 0;
+  }
+  if (!Ks || !Kt || !t || !(rho > 0) || !(Ks[0] > 0) || !(Ks[1] > 0) || !(Kt[0] > 0) || !(Kt[1] > 0)) return -1;
+  Motion m;
+  m.on = true;
+  m.fx = Ks[0];
+  m.fy = Ks[1];
+  m.cx = Ks[2];
+  m.cy = Ks[3];
+  m.qfx = Kt[0];
+  m.qfy = Kt[1];
+  m.qcx = Kt[2];
+  m.qcy = Kt[3];
+  for (int i = 0; i < 9; ++i) m.R[i] = R[i];
+  for (int i = 0; i < 3; ++i) m.t[i] = t[i];
+  m.rho = rho;
+  F->stereo_ext[cam] = m;
   return 0;
 }
 

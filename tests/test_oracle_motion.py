@@ -205,3 +205,76 @@ def test_short_budget_keeps_the_predicted_tracks():
     short, fb, _ = _motion_run(dict(pred_levels=2, pred_iters=3, pred_rho=1e9))
     n_tr = int((short[3]["status"] == oracle.TRACKED).sum())
     assert n_tr > 200 and fb[3] < 0.02 * n_tr, (n_tr, fb)
+
+
+def test_projection_into_another_camera():
+    """Identity motion between two cameras of different intrinsics maps p to
+    Kt Ks^-1 p (a pure change of pixel coordinates, no rotation)."""
+    Ks = np.array([400.0, 380.0, 300.0, 200.0])
+    Kt = np.array([800.0, 760.0, 350.5, 240.25])
+    p = _pts(30, seed=9)
+    out, ok = oracle.motion_start(Ks, np.eye(3), np.zeros(3), p, 0.7, Kq=Kt)
+    want = np.stack([Kt[2] + Kt[0] * (p[:, 0] - Ks[2]) / Ks[0], Kt[3] + Kt[1] * (p[:, 1] - Ks[3]) / Ks[1]], 1)
+    assert ok.all() and np.abs(out[:, :2] - want).max() < 1e-9
+    assert np.abs(out[:, 2]).max() < 1e-12
+
+
+def _stereo_run(set_ext, frames=3):
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=8, n_frames=frames)
+    fe = oracle.Frontend([w.width] * 2, [w.height] * 2, True, oracle.params_for(w))
+    out = []
+    try:
+        set_ext(fe, seq)
+        for t in range(frames):
+            fe.push(list(seq.frames[t]))
+            out.append(fe.records())
+    finally:
+        fe.close()
+    return out, seq
+
+
+def test_stereo_extrinsics_that_equal_the_disparity_prior():
+    """A sideways baseline of d0 / (f rho) with equal intrinsics starts every
+    match at p - (d0, 0), as the disparity prior does."""
+    w = synthgen.WORKLOADS["stereo752"]
+    rho, f = 0.5, 450.0
+    Kc = np.array([f, f, 375.5, 239.5])
+
+    def ext(fe, seq):
+        fe.set_stereo(1, Kc, Kc, np.eye(3), [-w.disparity0 / (f * rho), 0.0, 0.0], rho)
+
+    a, _ = _stereo_run(ext)
+    b, _ = _stereo_run(lambda fe, seq: None)
+    for ra, rb in zip(a, b):
+        assert len(ra) == len(rb) and (ra["status"] == rb["status"]).all() and (ra["id"] == rb["id"]).all()
+        assert np.abs(ra["x"] - rb["x"]).max() < 1e-4 and np.abs(ra["y"] - rb["y"]).max() < 1e-4
+
+
+def test_stereo_extrinsics_from_the_rig_land_on_the_ground_truth():
+    """Baselines from each synthetic rig's disparity plane (its constant term)
+    start the matches closer than the fixed prior; they still land on the
+    ground truth, and the cleared extrinsics give the prior's records back."""
+    rho, f = 0.5, 450.0
+    Kc = np.array([f, f, 375.5, 239.5])
+
+    def ext(fe, seq):
+        c = seq.planes[0][0][2]
+        fe.set_stereo(1, Kc, Kc, np.eye(3), [-c / (f * rho), 0.0, 0.0], rho)
+
+    out, seq = _stereo_run(ext, frames=1)
+    rec = out[0]
+    det = rec[(rec["camera"] == 0) & (rec["status"] == oracle.DETECTED)]
+    m = rec[(rec["camera"] == 1) & (rec["status"] == oracle.MATCHED)]
+    pos = {int(i): (x, y) for i, x, y in zip(det["id"], det["x"], det["y"])}
+    src = np.array([pos[int(i)] for i in m["id"]])
+    gx, gy = seq.gt_stereo(0, src[:, 0], src[:, 1])
+    assert len(m) > 0.8 * len(det) and np.median(np.hypot(m["x"] - gx, m["y"] - gy)) < 0.1
+
+    def cleared(fe, seq):
+        ext(fe, seq)
+        fe.set_stereo(1)
+
+    a, _ = _stereo_run(cleared, frames=2)
+    b, _ = _stereo_run(lambda fe, seq: None, frames=2)
+    assert all(x.tobytes() == y.tobytes() for x, y in zip(a, b))
