@@ -292,6 +292,20 @@ int vio_frontend_set_detection_mask(vio_frontend* h, int32_t stream, int32_t cam
  * Errors: VIO_EINVAL. */
 int vio_frontend_set_camera_model(vio_frontend* h, int32_t stream, int32_t camera, const vio_pinhole* K);
 
+/* Stereo extrinsics of a camera that receives matches (a pair's right camera
+ * or a star rig's cameras 1-3): its matches of the detecting camera's new
+ * keypoints start at the projection of the keypoint, back-projected through
+ * the detecting camera's pinhole model at inverse depth inv_depth, moved by
+ * X_this = R X_detecting + t (R row-major) and projected through this camera's
+ * model, instead of the disparity prior p - (disparity0, 0) (Sec. III-E starts
+ * every warp from the camera model). Both cameras' models must be set first
+ * (they are copied now). Stays in effect for every following frame; R == NULL
+ * returns to the disparity prior. A point not in front of this camera keeps
+ * the prior. Errors: VIO_EINVAL (camera out of range or detecting, models
+ * missing, a non-finite value, inv_depth <= 0), VIO_EDEVICE. */
+int vio_frontend_set_stereo_extrinsics(vio_frontend* h, int32_t stream, int32_t camera, const float* R,
+                                       const float* t, float inv_depth);
+
 /* Camera-model initialisation (Sec. III-E: the forward warp starts from the
  * pattern projected into the new image through the camera model, with the
  * predicted pose and the keypoint's inverse depth), for the stream's next frame

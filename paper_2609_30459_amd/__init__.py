@@ -141,6 +141,18 @@ class Frontend:
             rc = _n.lib.vio_frontend_set_detection_mask(self._h, stream, camera, m.ctypes.data, m.strides[0])
         self._check(rc, "vio_frontend_set_detection_mask")
 
+    def set_stereo_extrinsics(self, stream, camera, R=None, t=None, inv_depth=1.0):
+        """Stereo matches into `camera` start from the rig's extrinsics (X_camera = R X_detecting + t,
+        keypoints at inverse depth inv_depth); R None: the disparity prior again."""
+        if R is None:
+            rc = _n.lib.vio_frontend_set_stereo_extrinsics(self._h, stream, camera, None, None, 1.0)
+        else:
+            r = np.ascontiguousarray(np.asarray(R, np.float32).reshape(9))
+            tt = np.ascontiguousarray(np.asarray(t, np.float32).reshape(3))
+            rc = _n.lib.vio_frontend_set_stereo_extrinsics(self._h, stream, camera, r.ctypes.data, tt.ctypes.data,
+                                                           float(inv_depth))
+        self._check(rc, "vio_frontend_set_stereo_extrinsics")
+
     def set_camera_model(self, stream, camera, K):
         """Pinhole model K = (fx, fy, cx, cy) of a camera, or None to clear it."""
         k = None

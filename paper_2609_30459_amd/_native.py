@@ -136,6 +136,7 @@ lib.vio_frontend_stage_frames_device.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
 lib.vio_frontend_get_features.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
 lib.vio_frontend_set_camera_model.argtypes = [_vp, _i32, _i32, _P(vio_pinhole)]
 lib.vio_frontend_set_detection_mask.argtypes = [_vp, _i32, _i32, _vp, _i32]
+lib.vio_frontend_set_stereo_extrinsics.argtypes = [_vp, _i32, _i32, _vp, _vp, ctypes.c_float]
 lib.vio_frontend_set_motion.argtypes = [_vp, _i32, _vp, _i32, _vp, _i32]
 # learned-initialisation network (vio_mlp.h)
 VIO_MLP_NPARAM = 21123

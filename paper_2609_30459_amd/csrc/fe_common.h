@@ -62,6 +62,11 @@ struct CamDesc {
   int cell, ncx, ncy, ncells;
   int kcell, nslots;   // keypoints per cell k; winner key slots ncells * k (cell-major)
   int has_mask;        // detection mask in use (nonzero mask byte: no detection at that pixel)
+  // target camera of stereo matches: start from the rig's extrinsics instead of
+  // the disparity prior (X_target = R X_detecting + t, keypoints at inverse
+  // depth ext_rho, intrinsics ext_Ks of the detecting and ext_Kt of this camera)
+  int has_ext;
+  float ext_Ks[4], ext_Kt[4], ext_R[9], ext_t[3], ext_rho;
   int detect;          // 1: mono camera or left camera of a pair
   int n_targets;       // detecting camera: cameras c+1 .. c+n_targets receive its new keypoints' matches
                        // (1: a stereo pair's right camera, 3: a star rig's other cameras)

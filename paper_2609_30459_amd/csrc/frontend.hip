@@ -1144,6 +1144,46 @@ int vio_frontend_set_detection_mask(vio_frontend* h, int32_t s, int32_t camera, 
   return VIO_OK;
 }
 
+int vio_frontend_set_stereo_extrinsics(vio_frontend* h, int32_t s, int32_t camera, const float* R, const float* t,
+                                       float inv_depth) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera %d out of range", camera);
+  const int c = si.first_cam + camera;
+  CamDesc& cd = h->cams[c];
+  if (cd.detect) return fail(h, VIO_EINVAL, "camera %d detects; extrinsics belong to a camera receiving matches", camera);
+  int src = c - 1;  // the detecting camera whose matches this camera receives
+  while (!h->cams[src].detect) --src;
+  if (R) {
+    if (!t) return fail(h, VIO_EINVAL, "null translation");
+    if (!(h->K[c].fx > 0.f) || !(h->K[src].fx > 0.f))
+      return fail(h, VIO_EINVAL, "set the camera models of both cameras first");
+    bool finite = std::isfinite(inv_depth);
+    for (int i = 0; i < 9; ++i) finite &= std::isfinite(R[i]);
+    for (int i = 0; i < 3; ++i) finite &= std::isfinite(t[i]);
+    if (!finite || !(inv_depth > 0.f)) return fail(h, VIO_EINVAL, "extrinsics need finite values and inv_depth > 0");
+  }
+  if (const int rc = complete_all(h)) return rc;  // frames in flight finish first
+  cd.has_ext = R ? 1 : 0;
+  if (R) {
+    const vio_pinhole& Ks = h->K[src];
+    const vio_pinhole& Kt = h->K[c];
+    const float ks[4] = {Ks.fx, Ks.fy, Ks.cx, Ks.cy}, kt[4] = {Kt.fx, Kt.fy, Kt.cx, Kt.cy};
+    for (int i = 0; i < 4; ++i) {
+      cd.ext_Ks[i] = ks[i];
+      cd.ext_Kt[i] = kt[i];
+    }
+    for (int i = 0; i < 9; ++i) cd.ext_R[i] = R[i];
+    for (int i = 0; i < 3; ++i) cd.ext_t[i] = t[i];
+    cd.ext_rho = inv_depth;
+  }
+  HIP_CHECK(h, hipStreamSynchronize(h->stream));
+  HIP_CHECK(h, hipMemcpy(h->d_cams + c, &cd, sizeof(CamDesc), hipMemcpyHostToDevice));
+  return VIO_OK;
+}
+
 int vio_frontend_set_motion(vio_frontend* h, int32_t s, const vio_camera_motion* m, int32_t n_m,
                             const vio_kp_depth* depths, int32_t n_depths) {
   if (!h) return VIO_EINVAL;

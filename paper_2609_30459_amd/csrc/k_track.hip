@@ -554,9 +554,28 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       px = (float)(idx % cd.w);
       py = (float)(idx / cd.w);
     }
+    dst = &cams[c + 1 + t];
     ix = px - tune.disparity0;
     iy = py;
-    dst = &cams[c + 1 + t];
+    if (dst->has_ext) {
+      // the rig's extrinsics (Sec. III-E's camera-model start): back-project
+      // through the detecting camera at the default inverse depth, move,
+      // project through the target camera; the rotation in closed form as for
+      // the temporal start, with the two cameras' focal lengths
+      const float* R = dst->ext_R;
+      const float* Ks = dst->ext_Ks;
+      const float* Kt = dst->ext_Kt;
+      const float rho = dst->ext_rho;
+      const float a = (px - Ks[2]) / Ks[0], b = (py - Ks[3]) / Ks[1];
+      const float X = R[0] * a + R[1] * b + R[2] + rho * dst->ext_t[0];
+      const float Y = R[3] * a + R[4] * b + R[5] + rho * dst->ext_t[1];
+      const float Z = R[6] * a + R[7] * b + R[8] + rho * dst->ext_t[2];
+      if (Z > 1e-6f && Z + R[6] / Ks[0] > 1e-6f) {
+        ix = Kt[0] * (X / Z) + Kt[2];
+        iy = Kt[1] * (Y / Z) + Kt[3];
+        ith = atan2f(Kt[1] * (R[3] * Z - R[6] * Y), Kt[0] * (R[0] * Z - R[6] * X));
+      }
+    }
     ssrc = fc.pyr;
     sdst = fc.pyr;
     out = cd.sres + j;

@@ -182,3 +182,62 @@ def test_short_budget_of_predicted_tracks_parity(pred_rho):
         n_fb.append(fe_o.last_fallback)
     if pred_rho < 1.0:
         assert n_fb[3] > 0, n_fb
+
+
+def _ext_hook(w, seq, f=450.0, rho=0.5, clear_at=None):
+    """Both sides: every target camera's matches start from extrinsics built
+    from its synthetic disparity plane (a sideways baseline of c / (f rho)),
+    the two cameras with different principal points."""
+    Ks = np.array([f, f, 375.5, 239.5], np.float32)
+    Kt = np.array([f, f, 371.0, 241.0], np.float32)
+    views = seq.views
+
+    def hook(t, fe_g, fe_o):
+        if t == 0:
+            for c in range(w.n_cams):
+                fe_g.set_camera_model(0, c, Ks if c % views == 0 else Kt)
+            for c in range(w.n_cams):
+                if c % views == 0:
+                    continue
+                cc = float(seq._plane(c)[2])
+                # x_t = cx_t + f (a + rho tx) = x_s - c  =>  tx = (cx_s - cx_t - c) / (f rho)
+                tr = np.array([(Ks[2] - Kt[2] - cc) / (f * rho), (Ks[3] - Kt[3]) / (f * rho), 0.0], np.float32)
+                fe_g.set_stereo_extrinsics(0, c, np.eye(3), tr, rho)
+                fe_o.set_stereo(c, Ks.astype(np.float64), Kt.astype(np.float64), np.eye(3),
+                                tr.astype(np.float64), float(np.float32(rho)))
+        if clear_at is not None and t == clear_at:
+            for c in range(w.n_cams):
+                if c % views:
+                    fe_g.set_stereo_extrinsics(0, c, None)
+                    fe_o.set_stereo(c)
+        return None
+
+    return hook
+
+
+@pytest.mark.parametrize("name", ["stereo752", "star752"])
+def test_stereo_extrinsics_start_parity(name):
+    w = synthgen.WORKLOADS[name]
+    seq = synthgen.sequence(w, seq=4, n_frames=4)
+    print(f"case {name}", flush=True)
+    matched = 0
+    for t, g, o, exc, _, _ in run_pair(w, seq, 4, before_push=_ext_hook(w, seq, clear_at=3)):
+        assert len(exc) <= 1, (t, exc)
+        matched += int((o["status"] == oracle.MATCHED).sum())
+    assert matched > 100
+
+
+def test_stereo_extrinsics_arguments():
+    import paper_2609_30459_amd as vf
+    w = synthgen.WORKLOADS["stereo752"]
+    with vf.Frontend([(2, w.width, w.height, 300, 32)], vf.params_for(w)) as fe:
+        with pytest.raises(vf.VioError):
+            fe.set_stereo_extrinsics(0, 1, np.eye(3), [0.1, 0, 0], 0.5)  # no camera models yet
+        fe.set_camera_model(0, 0, (450.0, 450.0, 375.5, 239.5))
+        fe.set_camera_model(0, 1, (450.0, 450.0, 375.5, 239.5))
+        with pytest.raises(vf.VioError):
+            fe.set_stereo_extrinsics(0, 0, np.eye(3), [0.1, 0, 0], 0.5)  # camera 0 detects
+        with pytest.raises(vf.VioError):
+            fe.set_stereo_extrinsics(0, 1, np.eye(3), [0.1, 0, 0], 0.0)  # inverse depth 0
+        fe.set_stereo_extrinsics(0, 1, np.eye(3), [0.1, 0, 0], 0.5)
+        fe.set_stereo_extrinsics(0, 1, None)
