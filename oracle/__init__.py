@@ -83,6 +83,8 @@ def _lib_():
         lib.orc_fe_set_motion.argtypes = [vp, i32, vp, vp, vp, f64, i32, vp, vp]
         lib.orc_motion_start.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp]
         lib.orc_fe_set_stereo.argtypes = [vp, i32, vp, vp, vp, vp, f64]
+        lib.orc_camera_roundtrip.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        lib.orc_camera_project.argtypes = [vp, i32, vp, vp, vp]
         lib.orc_fe_last_fallback.argtypes = [vp]
         lib.orc_mlp_nparam.restype = i32
         lib.orc_bf16.argtypes = [ctypes.c_float]
@@ -166,6 +168,42 @@ def _f64(a, n):
     return a
 
 
+def _cam(K):
+    """A camera model in the oracle's C form: K = (fx, fy, cx, cy) is the
+    pinhole model, K = (fx, fy, cx, cy, k1, k2, k3, k4) the Kannala-Brandt
+    equidistant fisheye model (KB4)."""
+    K = np.asarray(K, np.float64).reshape(-1)
+    assert len(K) in (4, 8), "a camera model has 4 (pinhole) or 8 (KB4) values"
+    out = np.zeros(9, np.float64)
+    out[:4] = K[:4]
+    if len(K) == 8:
+        out[4] = 1.0
+        out[5:] = K[4:]
+    return out
+
+
+def camera_roundtrip(K, pts):
+    """Unprojects pixels pts [n, 2] through camera model K (see _cam) at
+    inverse depth 1 and projects them again: (pixels [n, 2], points [n, 3], ok [n])."""
+    K = _cam(K)
+    pts = np.ascontiguousarray(pts, np.float64).reshape(-1, 2)
+    n = len(pts)
+    x, y = np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1])
+    out, rays, ok = np.zeros((n, 2)), np.zeros((n, 3)), np.zeros(n, np.int32)
+    assert _lib_().orc_camera_roundtrip(K.ctypes.data, n, x.ctypes.data, y.ctypes.data, out.ctypes.data,
+                                        rays.ctypes.data, ok.ctypes.data) == 0
+    return out, rays, ok.astype(bool)
+
+
+def camera_project(K, X):
+    """Pixels of camera-frame points X [n, 3] through camera model K: (pixels [n, 2], ok [n])."""
+    K = _cam(K)
+    X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
+    out, ok = np.zeros((len(X), 2)), np.zeros(len(X), np.int32)
+    assert _lib_().orc_camera_project(K.ctypes.data, len(X), X.ctypes.data, out.ctypes.data, ok.ctypes.data) == 0
+    return out, ok.astype(bool)
+
+
 def motion_start(K, R, t, pts, rho, Kq=None):
     """Camera-model start of the warp (Sec. III-E) for keypoints pts [n, 2] at
     inverse depths rho [n], projected into a camera of intrinsics Kq (default
@@ -176,8 +214,8 @@ def motion_start(K, R, t, pts, rho, Kq=None):
     rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, np.float64), (n,)))
     out = np.zeros((n, 3), np.float64)
     ok = np.zeros(n, np.int32)
-    K, R, t = _f64(K, 4), _f64(R, 9), _f64(t, 3)
-    Kq = None if Kq is None else _f64(Kq, 4)
+    K, R, t = _cam(K), _f64(R, 9), _f64(t, 3)
+    Kq = None if Kq is None else _cam(Kq)
     assert _lib_().orc_motion_start(K.ctypes.data, R.ctypes.data, t.ctypes.data, n, x.ctypes.data, y.ctypes.data,
                                     rho.ctypes.data, out.ctypes.data, ok.ctypes.data,
                                     None if Kq is None else Kq.ctypes.data) == 0
@@ -291,10 +329,11 @@ class Frontend:
                                         pcam.ctypes.data, pxy.ctypes.data) == 0
 
     def set_motion(self, cam, K, R, t, rho, depths=None):
-        """Camera model K = (fx, fy, cx, cy) and predicted motion (X_new = R X_prev + t)
-        of camera `cam` for the next frame only; rho: inverse depth of keypoints
-        without their own; depths: iterable of (id, inverse depth)."""
-        K, R, t = _f64(K, 4), _f64(R, 9), _f64(t, 3)
+        """Camera model K (pinhole (fx, fy, cx, cy) or KB4 (fx, fy, cx, cy, k1..k4))
+        and predicted motion (X_new = R X_prev + t) of camera `cam` for the next
+        frame only; rho: inverse depth of keypoints without their own; depths:
+        iterable of (id, inverse depth)."""
+        K, R, t = _cam(K), _f64(R, 9), _f64(t, 3)
         depths = list(depths or [])
         ids = np.ascontiguousarray([int(d[0]) for d in depths], np.int64)
         rhos = np.ascontiguousarray([float(d[1]) for d in depths], np.float64)
@@ -313,7 +352,7 @@ class Frontend:
         if R is None:
             assert _lib_().orc_fe_set_stereo(self._h, cam, None, None, None, None, 0.0) == 0
             return
-        Ks, Kt, R, t = _f64(Ks, 4), _f64(Kt, 4), _f64(R, 9), _f64(t, 3)
+        Ks, Kt, R, t = _cam(Ks), _cam(Kt), _f64(R, 9), _f64(t, 3)
         assert _lib_().orc_fe_set_stereo(self._h, cam, Ks.ctypes.data, Kt.ctypes.data, R.ctypes.data, t.ctypes.data,
                                          float(rho)) == 0
 

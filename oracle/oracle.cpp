@@ -672,23 +672,94 @@ static void adam(float* P, const float* G, float* m, float* v, int t, float lr, 
 // image x axis under the same mapping: the angle of proj(p + (1, 0)) - proj(p),
 // both at the keypoint's inverse depth.
 // ----------------------------------------------------------------------------
+// A camera's projection model: pinhole (u = fx X/Z + cx, v = fy Y/Z + cy), or
+// the equidistant fisheye model of Kannala and Brandt with four coefficients
+// (KB4), which maps the angle theta between a ray and the optical axis to the
+// radius theta_d = theta (1 + k1 theta^2 + k2 theta^4 + k3 theta^6 + k4
+// theta^8) on the normalised image plane. Sec. III-E names only "the camera
+// model"; pinhole and KB4 cover the calibrations of the paper's datasets.
+struct CamModel {
+  int kb4 = 0;
+  double fx = 0, fy = 0, cx = 0, cy = 0;
+  double k[4] = {};
+};
+
 struct Motion {
   bool on = false;
-  double fx = 0, fy = 0, cx = 0, cy = 0;      // back-projecting camera
-  double qfx = 0, qfy = 0, qcx = 0, qcy = 0;  // projecting camera (the same one for a temporal motion)
+  CamModel src, dst;                // back-projecting and projecting camera (the same one for a temporal motion)
   double R[9] = {}, t[3] = {};
   double rho = 0;                   // inverse depth of keypoints without their own
   std::map<int64_t, double> depth;  // per-keypoint inverse depth, by id
 };
 
-static bool project_pixel(const Motion& m, double rho, double x, double y, double& ox, double& oy) {
-  const double X[3] = {(x - m.cx) / m.fx / rho, (y - m.cy) / m.fy / rho, 1.0 / rho};
-  double Xn[3];
-  for (int i = 0; i < 3; ++i) Xn[i] = m.R[3 * i] * X[0] + m.R[3 * i + 1] * X[1] + m.R[3 * i + 2] * X[2] + m.t[i];
-  if (!(rho * Xn[2] > 1e-6)) return false;
-  ox = m.qfx * Xn[0] / Xn[2] + m.qcx;
-  oy = m.qfy * Xn[1] / Xn[2] + m.qcy;
+// KB4 radius polynomial and its derivative at theta
+static double kb4_radius(const CamModel& m, double th, double* deriv) {
+  const double t2 = th * th;
+  const double poly = 1 + t2 * (m.k[0] + t2 * (m.k[1] + t2 * (m.k[2] + t2 * m.k[3])));
+  if (deriv) *deriv = 1 + t2 * (3 * m.k[0] + t2 * (5 * m.k[1] + t2 * (7 * m.k[2] + t2 * 9 * m.k[3])));
+  return th * poly;
+}
+
+// The point at inverse depth rho on the ray of pixel (x, y): for the pinhole
+// model at depth Z = 1 / rho, for KB4 at distance 1 / rho along the unit ray
+// (a fisheye ray may leave the half-space Z > 0). KB4 inverts the radius
+// polynomial by Newton's method from theta = theta_d; false when it does not
+// converge to a root with a positive slope below pi.
+static bool unproject(const CamModel& m, double rho, double x, double y, double X[3]) {
+  const double a = (x - m.cx) / m.fx, b = (y - m.cy) / m.fy;
+  if (!m.kb4) {
+    X[0] = a / rho;
+    X[1] = b / rho;
+    X[2] = 1.0 / rho;
+    return true;
+  }
+  const double td = std::sqrt(a * a + b * b);
+  double th = td, d = 1;
+  bool conv = false;
+  for (int it = 0; it < 100 && !conv; ++it) {
+    const double f = kb4_radius(m, th, &d) - td;
+    if (!(d > 0)) return false;
+    const double step = f / d;
+    th -= step;
+    conv = std::fabs(step) <= 1e-15 * (1 + th);
+  }
+  kb4_radius(m, th, &d);
+  if (!conv || !(th >= 0) || !(th < M_PI) || !(d > 0)) return false;
+  const double s = td > 0 ? std::sin(th) / td : 1.0;  // sin(theta) / theta_d -> 1 on the axis
+  X[0] = s * a / rho;
+  X[1] = s * b / rho;
+  X[2] = std::cos(th) / rho;
   return true;
+}
+
+// Pixel of camera-frame point X; false for a pinhole point not in front of
+// the camera (rho Z <= 1e-6, rho the inverse depth it was built at) and for a
+// KB4 point on the optical axis behind the camera or at the centre.
+static bool project(const CamModel& m, double rho, const double X[3], double& u, double& v) {
+  if (!m.kb4) {
+    if (!(rho * X[2] > 1e-6)) return false;
+    u = m.fx * X[0] / X[2] + m.cx;
+    v = m.fy * X[1] / X[2] + m.cy;
+    return true;
+  }
+  const double r = std::sqrt(X[0] * X[0] + X[1] * X[1]);
+  if (!(r > 0)) {
+    if (!(X[2] > 0)) return false;
+    u = m.cx;
+    v = m.cy;
+    return true;
+  }
+  const double rd = kb4_radius(m, std::atan2(r, X[2]), nullptr) / r;
+  u = m.fx * rd * X[0] + m.cx;
+  v = m.fy * rd * X[1] + m.cy;
+  return true;
+}
+
+static bool project_pixel(const Motion& m, double rho, double x, double y, double& ox, double& oy) {
+  double X[3], Xn[3];
+  if (!unproject(m.src, rho, x, y, X)) return false;
+  for (int i = 0; i < 3; ++i) Xn[i] = m.R[3 * i] * X[0] + m.R[3 * i + 1] * X[1] + m.R[3 * i + 2] * X[2] + m.t[i];
+  return project(m.dst, rho, Xn, ox, oy);
 }
 
 static bool motion_start(const Motion& m, double rho, double x, double y, double& ix, double& iy, double& ith) {
@@ -1074,17 +1145,30 @@ int orc_fe_push_pred(void* h, const uint8_t* const* imgs, const int32_t* strides
 // Camera model and predicted motion of camera `cam` for the next frame only:
 // K = (fx, fy, cx, cy), R row-major and t with X_new = R X_prev + t, rho the
 // inverse depth of keypoints not among the n (ids[i], rhos[i]).
+// A camera model from its C form: K[0..3] = fx, fy, cx, cy, K[4] = 0 for the
+// pinhole model or 1 for KB4 with coefficients K[5..8].
+static bool cam_model(const double* K, CamModel& m) {
+  if (!K || !(K[0] > 0) || !(K[1] > 0) || !(K[4] == 0 || K[4] == 1)) return false;
+  m.fx = K[0];
+  m.fy = K[1];
+  m.cx = K[2];
+  m.cy = K[3];
+  m.kb4 = K[4] == 1;
+  for (int i = 0; i < 4; ++i) {
+    m.k[i] = m.kb4 ? K[5 + i] : 0.0;
+    if (!std::isfinite(m.k[i])) return false;
+  }
+  return true;
+}
+
 int orc_fe_set_motion(void* h, int cam, const double* K, const double* R, const double* t, double rho, int n,
                       const int64_t* ids, const double* rhos) {
   auto* F = static_cast<Frontend*>(h);
-  if (!F || cam < 0 || cam >= F->n_cams || !K || !R || !t || n < 0 || !(rho > 0)) return -1;
-  if (!(K[0] > 0) || !(K[1] > 0)) return -1;
+  if (!F || cam < 0 || cam >= F->n_cams || !R || !t || n < 0 || !(rho > 0)) return -1;
   Motion m;
+  if (!cam_model(K, m.src)) return -1;
   m.on = true;
-  m.fx = m.qfx = K[0];
-  m.fy = m.qfy = K[1];
-  m.cx = m.qcx = K[2];
-  m.cy = m.qcy = K[3];
+  m.dst = m.src;
   for (int i = 0; i < 9; ++i) m.R[i] = R[i];
   for (int i = 0; i < 3; ++i) m.t[i] = t[i];
   m.rho = rho;
@@ -1097,21 +1181,14 @@ int orc_fe_set_motion(void* h, int cam, const double* K, const double* R, const 
 }
 
 // The camera-model start of n keypoints: out[3i..3i+2] = x, y, theta and
-// ok[i] = 1, or ok[i] = 0 when the point does not land in front of the camera.
-// Kq: intrinsics of the camera projected into (NULL: K, the same camera).
+// ok[i] = 1, or ok[i] = 0 when a projection is undefined (see project()).
+// K, Kq: camera models (9 values each, as cam_model) of the back-projecting
+// camera and of the camera projected into (NULL: K, the same camera).
 int orc_motion_start(const double* K, const double* R, const double* t, int n, const double* x, const double* y,
                      const double* rho, double* out, int32_t* ok, const double* Kq) {
-  if (!K || !R || !t || n < 0) return -1;
-  if (!Kq) Kq = K;
+  if (!R || !t || n < 0) return -1;
   Motion m;
-  m.fx = K[0];
-  m.fy = K[1];
-  m.cx = K[2];
-  m.cy = K[3];
-  m.qfx = Kq[0];
-  m.qfy = Kq[1];
-  m.qcx = Kq[2];
-  m.qcy = Kq[3];
+  if (!cam_model(K, m.src) || !cam_model(Kq ? Kq : K, m.dst)) return -1;
   for (int i = 0; i < 9; ++i) m.R[i] = R[i];
   for (int i = 0; i < 3; ++i) m.t[i] = t[i];
   for (int i = 0; i < n; ++i) {
@@ -1120,6 +1197,38 @@ int orc_motion_start(const double* K, const double* R, const double* t, int n, c
     out[3 * i] = ix;
     out[3 * i + 1] = iy;
     out[3 * i + 2] = ith;
+  }
+  return 0;
+}
+
+// Unprojection then projection through one camera model (9 values, as
+// cam_model) of n pixels at inverse depth 1: out[2i..2i+1] = the pixel again,
+// ok[i] = both steps defined; rays[3i..3i+2] (may be NULL) = the point.
+int orc_camera_roundtrip(const double* K, int n, const double* x, const double* y, double* out, double* rays,
+                         int32_t* ok) {
+  CamModel m;
+  if (!cam_model(K, m) || n < 0) return -1;
+  for (int i = 0; i < n; ++i) {
+    double X[3] = {0, 0, 0}, u = 0, v = 0;
+    ok[i] = unproject(m, 1.0, x[i], y[i], X) && project(m, 1.0, X, u, v);
+    out[2 * i] = u;
+    out[2 * i + 1] = v;
+    if (rays)
+      for (int j = 0; j < 3; ++j) rays[3 * i + j] = X[j];
+  }
+  return 0;
+}
+
+// Projection of n camera-frame points through one camera model (9 values):
+// out[2i..2i+1], ok[i] (the pinhole check at inverse depth 1).
+int orc_camera_project(const double* K, int n, const double* X, double* out, int32_t* ok) {
+  CamModel m;
+  if (!cam_model(K, m) || n < 0) return -1;
+  for (int i = 0; i < n; ++i) {
+    double u = 0, v = 0;
+    ok[i] = project(m, 1.0, X + 3 * i, u, v);
+    out[2 * i] = u;
+    out[2 * i + 1] = v;
   }
   return 0;
 }
@@ -1148,17 +1257,9 @@ int orc_fe_set_stereo(void* h, int cam, const double* Ks, const double* Kt, cons
     F->stereo_ext[cam] = Motion();
     return 0;
   }
-  if (!Ks || !Kt || !t || !(rho > 0) || !(Ks[0] > 0) || !(Ks[1] > 0) || !(Kt[0] > 0) || !(Kt[1] > 0)) return -1;
   Motion m;
+  if (!t || !(rho > 0) || !cam_model(Ks, m.src) || !cam_model(Kt, m.dst)) return -1;
   m.on = true;
-  m.fx = Ks[0];
-  m.fy = Ks[1];
-  m.cx = Ks[2];
-  m.cy = Ks[3];
-  m.qfx = Kt[0];
-  m.qfy = Kt[1];
-  m.qcx = Kt[2];
-  m.qcy = Kt[3];
   for (int i = 0; i < 9; ++i) m.R[i] = R[i];
   for (int i = 0; i < 3; ++i) m.t[i] = t[i];
   m.rho = rho;
