@@ -174,6 +174,18 @@ typedef struct vio_pinhole {
   float fx, fy, cx, cy;
 } vio_pinhole;  /* 16 bytes */
 
+/* Kannala-Brandt equidistant fisheye model with four coefficients (KB4, the
+ * calibration model of wide-angle datasets; Sec. III-E only names "the camera
+ * model"): a ray at angle theta to the optical axis, azimuth phi, lands at
+ * pixel (fx r cos phi + cx, fy r sin phi + cy) with r = theta (1 + k[0]
+ * theta^2 + k[1] theta^4 + k[2] theta^6 + k[3] theta^8). A keypoint's inverse
+ * depth under this model is the inverse of its distance along the ray (the
+ * pinhole model's is that of its depth along the optical axis). */
+typedef struct vio_kb4 {
+  float fx, fy, cx, cy;
+  float k[4];
+} vio_kb4;  /* 32 bytes */
+
 /* Predicted rigid motion of one camera from its previous frame to the next
  * one: a point X of the previous camera frame is R X + t in the new one (R
  * row-major, t in the units of 1 / inv_depth). */
@@ -291,6 +303,19 @@ int vio_frontend_set_detection_mask(vio_frontend* h, int32_t stream, int32_t cam
  * stream; fx, fy > 0. Needed before vio_frontend_set_motion names the camera.
  * Errors: VIO_EINVAL. */
 int vio_frontend_set_camera_model(vio_frontend* h, int32_t stream, int32_t camera, const vio_pinhole* K);
+
+/* Sets a camera's model to the KB4 fisheye model K (replacing a pinhole model
+ * or an earlier KB4 one; vio_frontend_set_camera_model switches it back). Every
+ * use of the camera model (the temporal start of vio_frontend_set_motion and
+ * the stereo extrinsics start) then back-projects a pixel by inverting the
+ * radius polynomial with Newton's method (the ray is undefined where it has no
+ * root with a positive slope below pi: such a keypoint keeps the start it
+ * would have without the model) and projects through the same model. The
+ * start rotation is the angle of the image of the pixel step (1, 0), as for
+ * the pinhole model. Stereo extrinsics copy both cameras' models when they are
+ * set: set the models first. VIO_EINVAL for a null K, non-finite values,
+ * fx <= 0 or fy <= 0, or a stream or camera out of range. */
+int vio_frontend_set_camera_kb4(vio_frontend* h, int32_t stream, int32_t camera, const vio_kb4* K);
 
 /* Stereo extrinsics of a camera that receives matches (a pair's right camera
  * or a star rig's cameras 1-3): its matches of the detecting camera's new

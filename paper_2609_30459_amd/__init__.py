@@ -154,9 +154,17 @@ class Frontend:
         self._check(rc, "vio_frontend_set_stereo_extrinsics")
 
     def set_camera_model(self, stream, camera, K):
-        """Pinhole model K = (fx, fy, cx, cy) of a camera, or None to clear it."""
+        """Camera model of a camera: pinhole K = (fx, fy, cx, cy), the KB4
+        fisheye K = (fx, fy, cx, cy, k1, k2, k3, k4), or None to clear it."""
+        if K is not None and len(K) == 8:
+            k = _n.vio_kb4(*[float(v) for v in K[:4]], (ctypes.c_float * 4)(*[float(v) for v in K[4:]]))
+            self._check(_n.lib.vio_frontend_set_camera_kb4(self._h, stream, camera, ctypes.byref(k)),
+                        "vio_frontend_set_camera_kb4")
+            return
         k = None
         if K is not None:
+            if len(K) != 4:
+                raise ValueError("a camera model has 4 (pinhole) or 8 (KB4) values")
             k = _n.vio_pinhole(*[float(v) for v in K])
         rc = _n.lib.vio_frontend_set_camera_model(self._h, stream, camera, ctypes.byref(k) if k is not None else None)
         self._check(rc, "vio_frontend_set_camera_model")

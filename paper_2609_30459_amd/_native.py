@@ -81,6 +81,11 @@ class vio_pinhole(ctypes.Structure):
     _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
 
 
+class vio_kb4(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("k", ctypes.c_float * 4)]
+
+
 class vio_camera_motion(ctypes.Structure):
     _fields_ = [("camera", ctypes.c_int32), ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3),
                 ("inv_depth", ctypes.c_float)]
@@ -135,6 +140,7 @@ lib.vio_frontend_in_flight.argtypes = [_vp]
 lib.vio_frontend_stage_frames_device.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
 lib.vio_frontend_get_features.argtypes = [_vp, _i32, _i32, _vp, _i32, _P(_i32)]
 lib.vio_frontend_set_camera_model.argtypes = [_vp, _i32, _i32, _P(vio_pinhole)]
+lib.vio_frontend_set_camera_kb4.argtypes = [_vp, _i32, _i32, _P(vio_kb4)]
 lib.vio_frontend_set_detection_mask.argtypes = [_vp, _i32, _i32, _vp, _i32]
 lib.vio_frontend_set_stereo_extrinsics.argtypes = [_vp, _i32, _i32, _vp, _vp, ctypes.c_float]
 lib.vio_frontend_set_motion.argtypes = [_vp, _i32, _vp, _i32, _vp, _i32]

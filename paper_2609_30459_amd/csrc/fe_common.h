@@ -64,9 +64,12 @@ struct CamDesc {
   int has_mask;        // detection mask in use (nonzero mask byte: no detection at that pixel)
   // target camera of stereo matches: start from the rig's extrinsics instead of
   // the disparity prior (X_target = R X_detecting + t, keypoints at inverse
-  // depth ext_rho, intrinsics ext_Ks of the detecting and ext_Kt of this camera)
+  // depth ext_rho, intrinsics ext_Ks of the detecting and ext_Kt of this camera;
+  // ext_kbs / ext_kbt: that camera is a KB4 fisheye with coefficients ext_ks / ext_kt)
   int has_ext;
   float ext_Ks[4], ext_Kt[4], ext_R[9], ext_t[3], ext_rho;
+  int ext_kbs, ext_kbt;
+  float ext_ks[4], ext_kt[4];
   int detect;          // 1: mono camera or left camera of a pair
   int n_targets;       // detecting camera: cameras c+1 .. c+n_targets receive its new keypoints' matches
                        // (1: a stereo pair's right camera, 3: a star rig's other cameras)
@@ -117,6 +120,8 @@ struct FrameCam {
   int n_depth;         // per-keypoint inverse depths (ascending id) at depth_off in Tuning::depths
   int depth_off;
   float K[4];          // fx, fy, cx, cy
+  int kb4;             // 1: KB4 fisheye model with coefficients kk (else pinhole)
+  float kk[4];
   float R[9], t[3];    // X_new = R X_prev + t
   float rho;           // inverse depth of keypoints without their own
 };

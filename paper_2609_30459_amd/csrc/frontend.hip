@@ -118,6 +118,8 @@ struct vio_frontend {
   int pred_cap = 0;
   KpDepth* d_depth = nullptr;  // per camera at CamDesc::row_off, up to its cap
   std::vector<vio_pinhole> K;  // per camera; fx == 0: no model
+  std::vector<vio_kb4> kb;     // per camera: the KB4 coefficients when kb4[c]
+  std::vector<int> kb4;
   std::vector<size_t> rec_host_off;  // per camera, in records
   // learned initialisation
   bool learned = false, mlp_ready = false;
@@ -476,6 +478,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->d_pred = reinterpret_cast<Prediction*>(base + o_pred);
   h->d_depth = reinterpret_cast<KpDepth*>(base + o_depth);
   h->K.assign(n_cams, vio_pinhole{0.f, 0.f, 0.f, 0.f});
+  h->kb.assign(n_cams, vio_kb4{});
+  h->kb4.assign(n_cams, 0);
   if (h->learned) {
     h->d_feat = reinterpret_cast<float*>(base + o_feat);
     h->d_guess = reinterpret_cast<float*>(base + o_guess);
@@ -899,6 +903,8 @@ static int stage_motion(vio_frontend* h, int s, hipStream_t st) {
     f.K[1] = K.fy;
     f.K[2] = K.cx;
     f.K[3] = K.cy;
+    f.kb4 = h->kb4[c];
+    for (int i = 0; i < 4; ++i) f.kk[i] = h->kb[c].k[i];
     for (int i = 0; i < 9; ++i) f.R[i] = m.R[i];
     for (int i = 0; i < 3; ++i) f.t[i] = m.t[i];
     f.rho = m.inv_depth;
@@ -1121,6 +1127,25 @@ int vio_frontend_set_camera_model(vio_frontend* h, int32_t s, int32_t camera, co
              K->fx > 0.f && K->fy > 0.f))
     return fail(h, VIO_EINVAL, "camera model needs finite values and fx, fy > 0");
   h->K[si.first_cam + camera] = K ? *K : vio_pinhole{0.f, 0.f, 0.f, 0.f};
+  h->kb4[si.first_cam + camera] = 0;
+  return VIO_OK;
+}
+
+int vio_frontend_set_camera_kb4(vio_frontend* h, int32_t s, int32_t camera, const vio_kb4* K) {
+  if (!h) return VIO_EINVAL;
+  if (h->poisoned) return VIO_EDEVICE;
+  if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
+  const StreamInfo& si = h->streams[s];
+  if (camera < 0 || camera >= si.n_cams) return fail(h, VIO_EINVAL, "camera %d out of range", camera);
+  if (!K) return fail(h, VIO_EINVAL, "null camera model");
+  bool finite = std::isfinite(K->fx) && std::isfinite(K->fy) && std::isfinite(K->cx) && std::isfinite(K->cy);
+  for (float v : K->k) finite &= std::isfinite(v);
+  if (!finite || !(K->fx > 0.f) || !(K->fy > 0.f))
+    return fail(h, VIO_EINVAL, "camera model needs finite values and fx, fy > 0");
+  const int c = si.first_cam + camera;
+  h->K[c] = vio_pinhole{K->fx, K->fy, K->cx, K->cy};
+  h->kb[c] = *K;
+  h->kb4[c] = 1;
   return VIO_OK;
 }
 
@@ -1174,7 +1199,11 @@ int vio_frontend_set_stereo_extrinsics(vio_frontend* h, int32_t s, int32_t camer
     for (int i = 0; i < 4; ++i) {
       cd.ext_Ks[i] = ks[i];
       cd.ext_Kt[i] = kt[i];
+      cd.ext_ks[i] = h->kb[src].k[i];
+      cd.ext_kt[i] = h->kb[c].k[i];
     }
+    cd.ext_kbs = h->kb4[src];
+    cd.ext_kbt = h->kb4[c];
     for (int i = 0; i < 9; ++i) cd.ext_R[i] = R[i];
     for (int i = 0; i < 3; ++i) cd.ext_t[i] = t[i];
     cd.ext_rho = inv_depth;

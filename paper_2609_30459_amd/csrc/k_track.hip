@@ -341,6 +341,98 @@ __device__ __forceinline__ PassOut klt_pass(const CamDesc& csrc_in, int ssrc_in,
   return o;
 }
 
+// ---- camera models of the camera-model start (Sec. III-E) ------------------
+// A model is K = (fx, fy, cx, cy) plus, for the Kannala-Brandt equidistant
+// fisheye (kb4 != 0), the coefficients k of its radius polynomial
+// theta (1 + k0 theta^2 + k1 theta^4 + k2 theta^6 + k3 theta^8).
+struct Model {
+  const float* K;
+  const float* k;
+  int kb4;
+};
+
+__device__ __forceinline__ float kb4_radius(const float* k, float th, float& slope) {
+  const float t2 = th * th;
+  slope = 1.f + t2 * (3.f * k[0] + t2 * (5.f * k[1] + t2 * (7.f * k[2] + t2 * 9.f * k[3])));
+  return th * (1.f + t2 * (k[0] + t2 * (k[1] + t2 * (k[2] + t2 * k[3]))));
+}
+
+// rho times the point at inverse depth rho on pixel (x, y)'s ray: (a, b, 1)
+// for the pinhole model, the unit ray for KB4 (the polynomial inverted by
+// Newton's method from theta = theta_d; false without a root of positive
+// slope in [0, pi))
+__device__ __forceinline__ bool model_ray(const Model& m, float x, float y, float X[3]) {
+  const float a = (x - m.K[2]) / m.K[0], b = (y - m.K[3]) / m.K[1];
+  if (!m.kb4) {
+    X[0] = a;
+    X[1] = b;
+    X[2] = 1.f;
+    return true;
+  }
+  const float td = sqrtf(a * a + b * b);
+  float th = td, slope = 1.f;
+  bool ok = true;
+#pragma unroll 1
+  for (int it = 0; it < 12; ++it) {
+    const float f = kb4_radius(m.k, th, slope) - td;
+    ok &= slope > 0.f;
+    th -= ok ? f / slope : 0.f;
+  }
+  const float res = kb4_radius(m.k, th, slope) - td;
+  if (!ok || !(slope > 0.f) || !(th >= 0.f) || !(th < 3.14159265f) || !(fabsf(res) <= 1e-4f * (1.f + td)))
+    return false;
+  const float sc = td > 0.f ? sinf(th) / td : 1.f;
+  X[0] = sc * a;
+  X[1] = sc * b;
+  X[2] = cosf(th);
+  return true;
+}
+
+// pixel of rho X (scaled as model_ray's); false for a pinhole point with
+// rho Z <= 1e-6 and for a KB4 point on the axis behind the camera
+__device__ __forceinline__ bool model_project(const Model& m, const float X[3], float& u, float& v) {
+  if (!m.kb4) {
+    if (!(X[2] > 1e-6f)) return false;
+    u = m.K[0] * (X[0] / X[2]) + m.K[2];
+    v = m.K[1] * (X[1] / X[2]) + m.K[3];
+    return true;
+  }
+  const float r = sqrtf(X[0] * X[0] + X[1] * X[1]);
+  if (!(r > 0.f)) {
+    if (!(X[2] > 0.f)) return false;
+    u = m.K[2];
+    v = m.K[3];
+    return true;
+  }
+  float slope;
+  const float rd = kb4_radius(m.k, atan2f(r, X[2]), slope) / r;
+  u = m.K[0] * (rd * X[0]) + m.K[2];
+  v = m.K[1] * (rd * X[1]) + m.K[3];
+  return true;
+}
+
+// (x, y) back-projected through `s` at inverse depth rho, moved by
+// X' = R X + t, projected through `d`
+__device__ __forceinline__ bool model_map(const Model& s, const Model& d, const float* R, const float* t, float rho,
+                                          float x, float y, float& u, float& v) {
+  float X[3], Y[3];
+  if (!model_ray(s, x, y, X)) return false;
+  for (int i = 0; i < 3; ++i) Y[i] = R[3 * i] * X[0] + R[3 * i + 1] * X[1] + R[3 * i + 2] * X[2] + rho * t[i];
+  return model_project(d, Y, u, v);
+}
+
+// The start through any pair of models: the mapped pixel, and the angle of
+// the mapped pixel step (1, 0) as the start rotation.
+__device__ __forceinline__ bool model_start(const Model& s, const Model& d, const float* R, const float* t, float rho,
+                                            float x, float y, float& ix, float& iy, float& ith) {
+  float u0, v0, u1, v1;
+  if (!model_map(s, d, R, t, rho, x, y, u0, v0) || !model_map(s, d, R, t, rho, x + 1.f, y, u1, v1)) return false;
+  ix = u0;
+  iy = v0;
+  ith = atan2f(v1 - v0, u1 - u0);
+  return true;
+}
+
 // Forward pass src -> dst from (ix, iy), then the backward pass dst -> src
 // from the keypoint's own position, over nl levels with N iterations; both
 // passes run the one inlined copy of the alignment code.
@@ -505,7 +597,10 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       const float X = R[0] * a + R[1] * b + R[2] + rho * fc.t[0];
       const float Y = R[3] * a + R[4] * b + R[5] + rho * fc.t[1];
       const float Z = R[6] * a + R[7] * b + R[8] + rho * fc.t[2];
-      if (Z > 1e-6f && Z + R[6] / fx > 1e-6f) {
+      if (fc.kb4) {
+        const Model m{fc.K, fc.kk, 1};
+        predicted = model_start(m, m, R, fc.t, rho, kp.x, kp.y, ix, iy, ith);
+      } else if (Z > 1e-6f && Z + R[6] / fx > 1e-6f) {
         ix = fx * (X / Z) + fc.K[2];
         iy = fy * (Y / Z) + fc.K[3];
         ith = atan2f((fy / fx) * (R[3] * Z - R[6] * Y), R[0] * Z - R[6] * X);
@@ -570,7 +665,15 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       const float X = R[0] * a + R[1] * b + R[2] + rho * dst->ext_t[0];
       const float Y = R[3] * a + R[4] * b + R[5] + rho * dst->ext_t[1];
       const float Z = R[6] * a + R[7] * b + R[8] + rho * dst->ext_t[2];
-      if (Z > 1e-6f && Z + R[6] / Ks[0] > 1e-6f) {
+      if (dst->ext_kbs || dst->ext_kbt) {
+        const Model ms{Ks, dst->ext_ks, dst->ext_kbs}, mt{Kt, dst->ext_kt, dst->ext_kbt};
+        float sx, sy, sth;
+        if (model_start(ms, mt, R, dst->ext_t, rho, px, py, sx, sy, sth)) {
+          ix = sx;
+          iy = sy;
+          ith = sth;
+        }
+      } else if (Z > 1e-6f && Z + R[6] / Ks[0] > 1e-6f) {
         ix = Kt[0] * (X / Z) + Kt[2];
         iy = Kt[1] * (Y / Z) + Kt[3];
         ith = atan2f(Kt[1] * (R[3] * Z - R[6] * Y), Kt[0] * (R[0] * Z - R[6] * X));

@@ -95,7 +95,9 @@ def _track_fp64(frames, t, orc, prev, idx, L, N, fb, d0, motion=None):
     """FP64 (x, y, theta, fb) of the tracked/matched records `idx` of frame t: temporal
     tracks from the previous state with the constant-velocity start (or the
     camera-model start where motion[camera] = (K, R, t, rho, {id: rho}) is
-    given), stereo matches from the same frame's detection in the left camera."""
+    given), stereo matches from the same frame's detection in the detecting
+    camera (with the extrinsics start where motion[("ext", camera)] =
+    (Ks, Kt, R, t, rho) is given)."""
     out = np.zeros((len(idx), 4))
     for n, i in enumerate(idx):
         c, kid = int(orc["camera"][i]), int(orc["id"][i])
@@ -111,9 +113,15 @@ def _track_fp64(frames, t, orc, prev, idx, L, N, fb, d0, motion=None):
                     init, th0 = (st[0, 0], st[0, 1]), st[0, 2]
         else:
             th0 = 0.0
-            det = orc[(orc["camera"] == c - 1) & (orc["id"] == kid) & (orc["status"] == oracle.DETECTED)][0]
-            src, dst = frames[t][c - 1], frames[t][c]
+            # the keypoint's detection, in the camera whose matches this one receives
+            det = orc[(orc["id"] == kid) & (orc["status"] == oracle.DETECTED)][0]
+            src, dst = frames[t][int(det["camera"])], frames[t][c]
             pt, init = (det["x"], det["y"]), (det["x"] - d0, det["y"])
+            if motion and ("ext", c) in motion:
+                Ks, Kt, R, tr, rho = motion[("ext", c)]
+                st, ok = oracle.motion_start(Ks, R, tr, np.array([pt], np.float64), rho, Kq=Kt)
+                if ok[0]:
+                    init, th0 = (st[0, 0], st[0, 1]), st[0, 2]
         r, _ = oracle.track(src, dst, np.array([pt], np.float64), np.array([init], np.float64), L, N, fb,
                             double=True, theta0=th0)
         out[n] = r[0, :4]

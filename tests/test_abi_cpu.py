@@ -42,6 +42,7 @@ def test_struct_layouts_match_header(native):
     assert native.KEYPOINT_DTYPE.itemsize == 32
     assert ctypes.sizeof(native.vio_kp_prediction) == 24
     assert ctypes.sizeof(native.vio_pinhole) == 16
+    assert ctypes.sizeof(native.vio_kb4) == 32
     assert ctypes.sizeof(native.vio_camera_motion) == 56
     assert ctypes.sizeof(native.vio_kp_depth) == 16
 
