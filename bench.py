@@ -125,6 +125,10 @@ def main():
     ap.add_argument("--motion-noise", type=float, default=0.0, metavar="PX",
                     help="Gaussian error (px, per axis) added to the predicted image translation")
     ap.add_argument("--focal", type=float, default=450.0)
+    ap.add_argument("--camera", choices=["pinhole", "kb4"], default="pinhole",
+                    help="camera model of --motion truth: kb4 = the Kannala-Brandt fisheye model with the first "
+                         "four Taylor coefficients of tan (within a fraction of a pixel of the rendered pinhole "
+                         "scene near the centre), which takes the fisheye start path")
     ap.add_argument("--pred-levels", type=int, default=0,
                     help="short budget (levels) of tracks with a camera-model start; 0 = the full budget")
     ap.add_argument("--pred-iters", type=int, default=3)
@@ -230,6 +234,8 @@ def main():
         inv_depth = 0.5
         rng = np.random.default_rng(1234)
         K_of = [seqs[i].camera_motion(0, args.focal, inv_depth)[0] for i in ids]
+        if args.camera == "kb4":
+            K_of = [(*K, 1 / 3, 2 / 15, 17 / 315, 62 / 2835) for K in K_of]
         motions = [[None] * n_frames for _ in ws]
         for i, w in enumerate(ws):
             for t in range(1, n_frames):
@@ -464,8 +470,8 @@ def main():
                    "sizes": sorted({f"{w.width}x{w.height}x{w.n_cams}" for w in ws}),
                    "levels": L, "gn_iters": N, "max_keypoints": sorted({w.max_keypoints for w in ws}),
                    "preset": args.preset, "k_per_cell": w0.k_per_cell,
-                   "motion": args.motion, **({"motion_noise_px": args.motion_noise, "focal": args.focal}
-                                             if args.motion != "none" else {}),
+                   "motion": args.motion, **({"motion_noise_px": args.motion_noise, "focal": args.focal,
+                                              "camera": args.camera} if args.motion != "none" else {}),
                    **({"pred_levels": args.pred_levels, "pred_iters": args.pred_iters, "pred_rho": args.pred_rho}
                       if short_pred else {}),
                    "cell_size": sorted({w.cell_size for w in ws}), "thresholds": list(w0.thresholds),
