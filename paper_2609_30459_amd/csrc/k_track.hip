@@ -372,11 +372,16 @@ __device__ __forceinline__ bool model_ray(const Model& m, float x, float y, floa
   const float td = sqrtf(a * a + b * b);
   float th = td, slope = 1.f;
   bool ok = true;
+  // at most 12 steps; a step below 1e-6 (1 + theta) leaves an error of its
+  // square's order, beneath FP32 resolution, so the loop ends there (every
+  // lane holds the item's values, so the exit is wave-uniform)
 #pragma unroll 1
   for (int it = 0; it < 12; ++it) {
     const float f = kb4_radius(m.k, th, slope) - td;
     ok &= slope > 0.f;
-    th -= ok ? f / slope : 0.f;
+    const float step = ok ? f / slope : 0.f;
+    th -= step;
+    if (!(fabsf(step) > 1e-6f * (1.f + th))) break;
   }
   const float res = kb4_radius(m.k, th, slope) - td;
   if (!ok || !(slope > 0.f) || !(th >= 0.f) || !(th < 3.14159265f) || !(fabsf(res) <= 1e-4f * (1.f + td)))
