@@ -74,6 +74,67 @@ def test_gradient_against_fp64_central_differences():
     assert np.median(rel) < 1e-6
 
 
+def _one_path_net(paths, b3=(0.0, 0.0, 0.0)):
+    """Parameters of a network whose output c is one chain input i -> h1 unit
+    j -> h2 unit j -> y c: paths = [(i, j, c, w1, b1, w2, b2, w3)]."""
+    P = np.zeros(oracle.MLP_NPARAM, np.float32)
+    W1, B1 = 0, 128 * 32
+    W2, B2 = B1 + 128, B1 + 128 + 128 * 128
+    W3, B3 = B2 + 128, B2 + 128 + 3 * 128
+    for i, j, c, w1, b1, w2, b2, w3 in paths:
+        P[W1 + j * 32 + i], P[B1 + j] = w1, b1
+        P[W2 + j * 128 + j], P[B2 + j] = w2, b2
+        P[W3 + c * 128 + j] = w3
+    P[B3:B3 + 3] = b3
+    return P
+
+
+def test_bf16_rounding_points_hand_derived():
+    """The GPU's rounding points, one at a time, on hand-built one-path
+    networks; every expected value below is worked out by hand from the
+    bfloat16 grid (8 significant bits: next to 1 the spacing is 2^-7, and
+    1 + 2^-8 is the tie between 1 and 1 + 2^-7, which goes to the even 1).
+
+    Network A (weights and activations):
+      w1 = 1 + 2^-9 rounds to 1; x = 1; b1 = 3 * 2^-10: 1 + 3 * 2^-10 lies
+      below the tie 1 + 2^-8, so h1 = 1. Same for layer 2: h2 = 1. w3 = 1 +
+      2^-9 rounds to 1; y0 = 1 + b3[0] with b3[0] = 2^-12 + 2^-21 kept in
+      float (bfloat16 would drop the 2^-21), and y is not rounded.
+      Slips: unrounded weights give h1 = bf16(1 + 2^-9 + 3 * 2^-10) = 1 + 2^-7;
+      an unrounded h1 makes h2 = bf16(1 + 6 * 2^-10) = 1 + 2^-7; an unrounded
+      h2 gives y0 = 1 + 3 * 2^-10 + ...; a rounded y gives 1.
+    Network B (inputs and biases):
+      path 0: x0 = 1 + 2^-9 rounds to 1, + b1 = 3 * 2^-10 -> h1 = 1 -> y0 = 1
+      (an unrounded input gives 1 + 5 * 2^-10, above the tie: 1 + 2^-7);
+      path 1: x1 = 1, b1 = 2^-8 + 2^-20 (float): 1 + 2^-8 + 2^-20 lies above
+      the tie -> 1 + 2^-7 = y1 (a bias rounded to 2^-8 lands on the tie: 1);
+      path 2: x2 = 0.75, h1 = 0.75, w2 = -1, b2 = 0.5: relu(-0.25) = 0, so
+      y2 = b3[2] = 0.1 in float (rounding the pre-activation first would not
+      change it; dropping the ReLU gives -0.25 + 0.1)."""
+    A = _one_path_net([(0, 0, 0, 1 + 2 ** -9, 3 * 2 ** -10, 1.0, 3 * 2 ** -10, 1 + 2 ** -9)],
+                      b3=(2 ** -12 + 2 ** -21, 0.1, -0.3))
+    X = np.zeros((1, 32), np.float32)
+    X[0, 0] = 1.0
+    Y, H1, H2 = oracle.mlp_forward(A, X)
+    assert H1[0, 0] == 1.0 and H2[0, 0] == 1.0
+    assert Y[0, 0] == np.float32(1 + 2 ** -12 + 2 ** -21)
+    assert Y[0, 1] == np.float32(0.1) and Y[0, 2] == np.float32(-0.3)
+    B = _one_path_net([(0, 0, 0, 1.0, 3 * 2 ** -10, 1.0, 0.0, 1.0),
+                       (1, 1, 1, 1.0, 2 ** -8 + 2 ** -20, 1.0, 0.0, 1.0),
+                       (2, 2, 2, 1.0, 0.0, -1.0, 0.5, 1.0)], b3=(0.0, 0.0, 0.1))
+    X = np.zeros((1, 32), np.float32)
+    X[0, :3] = [1 + 2 ** -9, 1.0, 0.75]
+    Y, H1, H2 = oracle.mlp_forward(B, X)
+    assert H1[0, :3].tolist() == [1.0, 1 + 2 ** -7, 0.75]
+    assert H2[0, :3].tolist() == [1.0, 1 + 2 ** -7, 0.0]
+    assert Y[0].tolist() == [1.0, 1 + 2 ** -7, float(np.float32(0.1))]
+    # the exact mode rounds nothing
+    Ye, _, _ = oracle.mlp_forward(A, np.eye(1, 32, dtype=np.float32), exact=True)
+    w = float(np.float32(1 + 2 ** -9))
+    # (w2 = 1): y0 = w3 (w1 + b1 + b2) + b3
+    assert abs(Ye[0, 0] - (w * (w + 6 * 2 ** -10) + float(np.float32(2 ** -12 + 2 ** -21)))) < 1e-12
+
+
 def test_bf16_mode_tracks_the_exact_gradient():
     P = oracle.mlp_init(5)
     X, T = _batch(256, 6)

@@ -424,6 +424,98 @@ def test_klt_lands_on_brute_force_ssd_minimum():
     assert out[0, 4] < 1e-4  # the last step is small once converged
 
 
+# Level schedule and image domain (Sec. III-E; the paper is silent on borders).
+# Reading: a coarse level whose template does not fit is skipped, with t still
+# doubled through it; the template fits when every sample and its +-1 px
+# gradient neighbours lie in the closed domain [0, W-1] x [0, H-1]; a warped
+# sample outside that domain, or a template that does not fit at level 0, is
+# LOST_OOB.
+
+
+def test_coarse_level_that_does_not_fit_is_skipped():
+    tex = np.round(_smooth_texture(128, 128, 4)).astype(np.uint8)
+    dx, dy = 4, -8
+    dst = np.roll(tex, (dy, dx), axis=(0, 1))
+    # x = 8.98: level 1 holds the keypoint at 4.49, where the pattern's
+    # leftmost gradient tap (4.49 - 3.5 - 1) falls outside the image; level 0
+    # (8.98 - 4.5 >= 0) fits. Skipping the coarse levels leaves t = init at
+    # level 0, so the 2- and 3-level passes equal the 1-level pass bit for bit.
+    p = np.array([[8.98, 64.0]])
+    init = p + [dx + 0.3, dy - 0.2]
+    one = oracle.klt_pass(tex, dst, p, init, 1, 10)
+    assert one[0, 5] == oracle.TRACKED
+    assert abs(one[0, 0] - (p[0, 0] + dx)) < 1e-2 and abs(one[0, 1] - (p[0, 1] + dy)) < 1e-2
+    for L in (2, 3):
+        out = oracle.klt_pass(tex, dst, p, init, L, 10)
+        assert out[0, 5] == oracle.TRACKED, L
+        assert (out[0, :5] == one[0, :5]).all(), (L, out[0], one[0])
+    # x = 9.0: level 1 (4.5) fits and is used, so the 2-level pass differs
+    q = np.array([[9.0, 64.0]])
+    two = oracle.klt_pass(tex, dst, q, q + [dx + 0.3, dy - 0.2], 2, 10)
+    lone = oracle.klt_pass(tex, dst, q, q + [dx + 0.3, dy - 0.2], 1, 10)
+    assert two[0, 5] == oracle.TRACKED and (two[0, :3] != lone[0, :3]).any()
+    # the full forward-backward tracker keeps the near-border keypoint
+    out, st = oracle.track(tex, dst, p, init, 3, 5)
+    assert st[0] == oracle.TRACKED and abs(out[0, 0] - (p[0, 0] + dx)) < 5e-2
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_template_fit_boundary(axis):
+    """The template fits iff the outermost gradient tap (3.5 + 1 px from the
+    keypoint) lies in [0, W-1]: at level 0 alone a misfit is LOST_OOB."""
+    tex = np.round(_smooth_texture(96, 128, 6)).astype(np.uint8)  # H 96, W 128
+    size = tex.shape[1 - axis]
+    for c, fits in ((4.5, True), (4.49, False), (size - 1 - 4.5, True), (size - 1 - 4.49, False)):
+        p = np.array([[c, 48.0]] if axis == 0 else [[64.0, c]])
+        out = oracle.klt_pass(tex, tex, p, p, 1, 1)
+        assert out[0, 5] == (oracle.TRACKED if fits else oracle.LOST_OOB), (c, out[0])
+        _, st = oracle.track(tex, tex, p, p, 1, 1)
+        assert st[0] == (oracle.TRACKED if fits else oracle.LOST_OOB), c
+
+
+def test_warp_leaving_the_image_is_lost_oob():
+    tex = np.round(_smooth_texture(128, 128, 8)).astype(np.uint8)
+    p = np.array([[64.0, 64.0]])
+    # first iteration's warp at the start: the pattern reaches 3.5 px from it;
+    # the closed domain admits a sample exactly on the first or last column
+    for sx, ok in ((3.5, True), (3.49, False), (127 - 3.5, True), (127 - 3.49, False)):
+        out = oracle.klt_pass(tex, tex, p, [[sx, 64.0]], 1, 1)
+        assert out[0, 5] == (oracle.TRACKED if ok else oracle.LOST_OOB), (sx, out[0])
+        out = oracle.klt_pass(tex, tex, p, [[64.0, sx]], 1, 1)
+        assert out[0, 5] == (oracle.TRACKED if ok else oracle.LOST_OOB), (sx, out[0])
+    # a keypoint whose true match lies past the border: src is dst shifted so
+    # that the match of x = 12 sits at x = 1, and the converging warp leaves
+    # the image; clamped addressing would return a position instead
+    dst = np.ascontiguousarray(np.concatenate([tex[:, 11:], tex[:, :11]], 1))
+    q = np.array([[12.0, 64.0]])
+    out = oracle.klt_pass(tex, dst, q, q - [8.0, 0.0], 1, 20)
+    assert out[0, 5] == oracle.LOST_OOB, out[0]
+    _, st = oracle.track(tex, dst, q, q - [8.0, 0.0], 1, 20)
+    assert st[0] == oracle.LOST_OOB
+
+
+def test_backward_pass_starts_from_the_inverse_of_the_forward_motion():
+    """Fig. 4: the backward pass rebuilds the template on the target at the
+    forward result p' and starts from the inverse motion, position p and
+    rotation -theta_fwd. When the forward pass starts at the true motion (a
+    20 degree rotation about the image centre plus a shift), that start is
+    already the backward solution, so a single Gauss-Newton iteration per pass
+    returns to p: the forward-backward distance stays at the interpolation
+    level. A start at +theta_fwd (40 degrees off) or at p' (a full re-track)
+    cannot get back in one iteration."""
+    tex = _smooth_texture(160, 160, 11, sigma=2.0)
+    th, d, c = math.radians(20.0), (2.0, -1.5), (80.0, 80.0)
+    src = np.round(tex).astype(np.uint8)
+    dst = np.clip(np.round(_warp(tex, d[0], d[1], th, c)), 0, 255).astype(np.uint8)
+    pts = np.random.default_rng(3).uniform(50, 110, (20, 2))
+    gx = c[0] + math.cos(th) * (pts[:, 0] - c[0]) - math.sin(th) * (pts[:, 1] - c[1]) + d[0]
+    gy = c[1] + math.sin(th) * (pts[:, 0] - c[0]) + math.cos(th) * (pts[:, 1] - c[1]) + d[1]
+    for dbl in (False, True):
+        out, st = oracle.track(src, dst, pts, np.stack([gx, gy], 1), 1, 1, fb_threshold=0.3, double=dbl, theta0=th)
+        assert (st == oracle.TRACKED).all(), st
+        assert np.median(out[:, 3]) < 0.05 and out[:, 3].max() < 0.1, np.sort(out[:, 3])
+
+
 def test_float_and_double_trackers_agree():
     seq = synthgen.sequence(synthgen.WORKLOADS["mono320"])
     d = oracle.detect(seq.frames[0, 0], 16)[:, 0]
