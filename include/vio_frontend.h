@@ -309,8 +309,9 @@ int vio_frontend_set_camera_model(vio_frontend* h, int32_t stream, int32_t camer
  * use of the camera model (the temporal start of vio_frontend_set_motion and
  * the stereo extrinsics start) then back-projects a pixel by inverting the
  * radius polynomial with Newton's method (the ray is undefined where it has no
- * root with a positive slope below pi: such a keypoint keeps the start it
- * would have without the model) and projects through the same model. The
+ * root below pi at which the radius rises with slope >= 0.05, i.e. at and near
+ * the polynomial's fold: such a keypoint keeps the start it would have
+ * without the model) and projects through the same model. The
  * start rotation is the angle of the image of the pixel step (1, 0), as for
  * the pinhole model. Stereo extrinsics copy both cameras' models when they are
  * set: set the models first. VIO_EINVAL for a null K, non-finite values,
@@ -320,7 +321,7 @@ int vio_frontend_set_camera_kb4(vio_frontend* h, int32_t stream, int32_t camera,
 /* Stereo extrinsics of a camera that receives matches (a pair's right camera
  * or a star rig's cameras 1-3): its matches of the detecting camera's new
  * keypoints start at the projection of the keypoint, back-projected through
- * the detecting camera's pinhole model at inverse depth inv_depth, moved by
+ * the detecting camera's model (pinhole or KB4) at inverse depth inv_depth, moved by
  * X_this = R X_detecting + t (R row-major) and projected through this camera's
  * model, instead of the disparity prior p - (disparity0, 0) (Sec. III-E starts
  * every warp from the camera model). Both cameras' models must be set first

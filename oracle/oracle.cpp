@@ -704,7 +704,11 @@ static double kb4_radius(const CamModel& m, double th, double* deriv) {
 // model at depth Z = 1 / rho, for KB4 at distance 1 / rho along the unit ray
 // (a fisheye ray may leave the half-space Z > 0). KB4 inverts the radius
 // polynomial by Newton's method from theta = theta_d; false when it does not
-// converge to a root with a positive slope below pi.
+// converge to a root below pi where the radius rises with slope at least
+// KB4_MIN_SLOPE (near the fold of the polynomial a pixel step turns the ray
+// by 1 / slope times as much as on the axis: the ray is ill-conditioned and
+// the keypoint keeps its usual start).
+constexpr double KB4_MIN_SLOPE = 0.05;
 static bool unproject(const CamModel& m, double rho, double x, double y, double X[3]) {
   const double a = (x - m.cx) / m.fx, b = (y - m.cy) / m.fy;
   if (!m.kb4) {
@@ -724,7 +728,7 @@ static bool unproject(const CamModel& m, double rho, double x, double y, double 
     conv = std::fabs(step) <= 1e-15 * (1 + th);
   }
   kb4_radius(m, th, &d);
-  if (!conv || !(th >= 0) || !(th < M_PI) || !(d > 0)) return false;
+  if (!conv || !(th >= 0) || !(th < M_PI) || !(d >= KB4_MIN_SLOPE)) return false;
   const double s = td > 0 ? std::sin(th) / td : 1.0;  // sin(theta) / theta_d -> 1 on the axis
   X[0] = s * a / rho;
   X[1] = s * b / rho;

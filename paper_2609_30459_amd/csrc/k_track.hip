@@ -359,8 +359,11 @@ __device__ __forceinline__ float kb4_radius(const float* k, float th, float& slo
 
 // rho times the point at inverse depth rho on pixel (x, y)'s ray: (a, b, 1)
 // for the pinhole model, the unit ray for KB4 (the polynomial inverted by
-// Newton's method from theta = theta_d; false without a root of positive
-// slope in [0, pi))
+// Newton's method from theta = theta_d; false without a root in [0, pi) where
+// the radius rises with slope >= kKb4MinSlope: nearer the polynomial's fold
+// the ray is ill-conditioned, and Newton's steps in FP32 stall at the root's
+// resolution)
+constexpr float kKb4MinSlope = 0.05f;
 __device__ __forceinline__ bool model_ray(const Model& m, float x, float y, float X[3]) {
   const float a = (x - m.K[2]) / m.K[0], b = (y - m.K[3]) / m.K[1];
   if (!m.kb4) {
@@ -372,9 +375,10 @@ __device__ __forceinline__ bool model_ray(const Model& m, float x, float y, floa
   const float td = sqrtf(a * a + b * b);
   float th = td, slope = 1.f;
   bool ok = true;
-  // at most 12 steps; a step below 1e-6 (1 + theta) leaves an error of its
-  // square's order, beneath FP32 resolution, so the loop ends there (every
-  // lane holds the item's values, so the exit is wave-uniform)
+  // at most 12 steps (from theta_d, a root of slope >= kKb4MinSlope takes at
+  // most 7); a step below 1e-6 (1 + theta) leaves an error of its square's
+  // order, beneath FP32 resolution, so the loop ends there (every lane holds
+  // the item's values, so the exit is wave-uniform)
 #pragma unroll 1
   for (int it = 0; it < 12; ++it) {
     const float f = kb4_radius(m.k, th, slope) - td;
@@ -384,7 +388,8 @@ __device__ __forceinline__ bool model_ray(const Model& m, float x, float y, floa
     if (!(fabsf(step) > 1e-6f * (1.f + th))) break;
   }
   const float res = kb4_radius(m.k, th, slope) - td;
-  if (!ok || !(slope > 0.f) || !(th >= 0.f) || !(th < 3.14159265f) || !(fabsf(res) <= 1e-4f * (1.f + td)))
+  // the residual of a converged root is at FP32 resolution: a few ulps of td
+  if (!ok || !(slope >= kKb4MinSlope) || !(th >= 0.f) || !(th < 3.14159265f) || !(fabsf(res) <= 4e-6f * (1.f + td)))
     return false;
   const float sc = td > 0.f ? sinf(th) / td : 1.f;
   X[0] = sc * a;

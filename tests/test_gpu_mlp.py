@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synthgen
-from parity_util import compare_records, inject
+from parity_util import Tally, compare_records, inject
 
 pytestmark = pytest.mark.gpu
 
@@ -48,8 +48,35 @@ def test_forward_matches_oracle(n):
     assert np.median(np.abs(got - want)) <= 1e-3 * scale
 
 
+def _term_magnitudes(P, X, T):
+    """A[p] = sum over the batch of |a| |b| for the two operands of every
+    weight-gradient product (dW = dH^T H_prev, db = sum dH): the most that
+    one-ulp bfloat16 differences in all operands can move dW is 2^-8 A for
+    each operand. Built from the oracle's forward and loss; the backward
+    operands are propagated here only to size the tolerance."""
+    bf = np.vectorize(oracle.bf16, otypes=[np.float32])
+    Y, H1, H2 = oracle.mlp_forward(P, X)
+    _, _, dY = oracle.mlp_loss_grad(P, X, T)
+    W2 = bf(P[4224:20608].reshape(128, 128)).astype(np.float64)
+    W3 = bf(P[20736:21120].reshape(3, 128)).astype(np.float64)
+    dH2 = np.abs(dY) @ np.abs(W3) * (H2 > 0)
+    dH1 = dH2 @ np.abs(W2) * (H1 > 0)
+    Xb = np.abs(bf(X).astype(np.float64))
+    A = np.zeros(oracle.MLP_NPARAM)
+    A[0:4096] = (dH1.T @ Xb).ravel()
+    A[4096:4224] = dH1.sum(0)
+    A[4224:20608] = (dH2.T @ np.abs(H1)).ravel()
+    A[20608:20736] = dH2.sum(0)
+    A[20736:21120] = (np.abs(dY).T @ np.abs(H2)).ravel()
+    A[21120:21123] = np.abs(dY).sum(0)
+    return A
+
+
 @pytest.mark.parametrize("n", [32, 300, 1024])
 def test_gradient_matches_oracle(n):
+    """dW element by element: within 1e-2 of the oracle's value plus 2^-7 of
+    the element's term magnitude (one-ulp bfloat16 differences of both
+    operands, from the MFMA's summation order flipping a rounding)."""
     import torch
     import paper_2609_30459_amd as vf
     P = oracle.mlp_init(9)
@@ -59,74 +86,118 @@ def test_gradient_matches_oracle(n):
         net.set_params(P)
         g = torch.zeros(vf.MLP_NPARAM, dtype=torch.float32, device="cuda")
         L_g = net.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), g)
-        G_g = g.cpu().numpy()
+        G_g = g.cpu().numpy().astype(np.float64)
     assert abs(L_g - L_o) <= 1e-3 * abs(L_o)
-    blocks = [(0, 4096), (4096, 4224), (4224, 20608), (20608, 20736), (20736, 21120), (21120, 21123)]
-    for a, b in blocks:
-        rel = np.linalg.norm(G_g[a:b] - G_o[a:b]) / max(np.linalg.norm(G_o[a:b]), 1e-12)
-        assert rel <= 1e-2, (a, b, rel)
+    A = _term_magnitudes(P, X, T)
+    err = np.abs(G_g - G_o)
+    tol = 1e-2 * np.abs(G_o) + 2.0 ** -7 * A
+    bad = np.nonzero(err > tol)[0]
+    assert not len(bad), (f"{len(bad)} gradient entries outside tolerance, first {bad[:5].tolist()}: "
+                          f"gpu {G_g[bad[:5]].tolist()} oracle {G_o[bad[:5]].tolist()} A {A[bad[:5]].tolist()}")
+    # most entries agree far inside the bound (a flip is rare)
+    rel = err / np.maximum(np.abs(G_o), 1e-30)
+    assert np.median(rel[np.abs(G_o) > 1e-6]) < 1e-4
 
 
 def test_adam_step_matches_oracle_and_training_reduces_loss():
+    """The GPU's Adam step against the oracle's Adam applied to the GPU's own
+    gradient of the same batch (the gradient kernels are deterministic): each
+    weight's move within 1e-2 of the expected move (first and second step;
+    a wrong learning rate, epsilon or bias correction fails)."""
     import torch
     import paper_2609_30459_amd as vf
     P = oracle.mlp_init(11)
     X, T = _data(1024, 5)
-    # one step: oracle gradient + oracle Adam against the GPU step
-    _, G_o, _ = oracle.mlp_loss_grad(P, X, T)
-    P_o, m, v = P.copy(), np.zeros_like(P), np.zeros_like(P)
-    oracle.adam(P_o, G_o.astype(np.float32), m, v, 1, lr=1e-3)
     with vf.Mlp(1024) as net:
         net.set_params(P)
         dx, dt = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
-        l0 = net.train_step(dx, dt, lr=1e-3)
-        P_g = net.get_params()
-        # Adam's first step moves each weight by about lr * sign(g): compare the moves
-        moved = np.abs(P_o - P) > 5e-4
-        assert (np.sign(P_g - P)[moved] == np.sign(P_o - P)[moved]).mean() > 0.99
-        assert np.abs((P_g - P) - (P_o - P)).max() <= 2e-3
+        g = torch.zeros(vf.MLP_NPARAM, dtype=torch.float32, device="cuda")
+        P_o, m, v = P.copy(), np.zeros_like(P), np.zeros_like(P)
+        for step in (1, 2):
+            before = net.get_params()
+            net.gradient(dx, dt, g)
+            G = g.cpu().numpy()
+            oracle.adam(P_o, G, m, v, step, lr=1e-3)
+            loss = net.train_step(dx, dt, lr=1e-3)
+            P_g = net.get_params()
+            want = P_o.astype(np.float64) - before
+            got = P_g.astype(np.float64) - before
+            # float rounding of the parameter itself: 2 ulps of |P|
+            tol = 1e-2 * np.abs(want) + 2.0 ** -22 * np.abs(before)
+            bad = np.nonzero(np.abs(got - want) > tol)[0]
+            assert not len(bad), (step, len(bad), got[bad[:5]].tolist(), want[bad[:5]].tolist())
+            assert np.median(np.abs(want)) > 5e-4  # the steps are about lr in size
+            P_o = P_g.copy()  # the next step starts from the GPU's parameters
+            if step == 1:
+                loss0 = loss
         losses = [net.train_step(dx, dt, lr=1e-3) for _ in range(200)]
-    assert losses[-1] < 0.5 * l0
+    assert losses[-1] < 0.5 * loss0
 
 
 def _learned_params(w, rho, levels=2, iters=3):
     return dict(init_mode=1, learned_levels=levels, learned_iters=iters, learned_rho=rho)
 
 
-@pytest.mark.parametrize("rho,launch", [(-1.0, {}), (0.02, {}), (1e9, {}), (0.02, {"eager": True}),
-                                        (0.02, {"stereo_mode": 1, "track_waves_per_cu": 4})])
-def test_learned_pipeline_parity_and_features(rho, launch):
+def _learned_run(w, seq, P, rho, launch, frames, where):
+    """Learned-init GPU frontend against the oracle with state injection: records,
+    features (bit-exact) and fallback counts (exact) per frame; returns the
+    total fallbacks."""
     import paper_2609_30459_amd as vf
-    w = synthgen.WORKLOADS["stereo752"]
-    seq = synthgen.sequence(w, seq=7, n_frames=4)
-    P = oracle.mlp_init(13) * 0.05
-    P[-3:] = 0.0
     po = _learned_params(w, rho)
-    fe_o = oracle.Frontend([w.width] * 2, [w.height] * 2, True, oracle.params_for(w, **po))
+    fe_o = oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo, oracle.params_for(w, **po))
     fe_o.set_mlp(P)
     n_fb = 0
-    with vf.Frontend([(2, w.width, w.height, w.max_keypoints, w.cell_size)],
+    tally = Tally(where)
+    with vf.Frontend([(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size)],
                      vf.params_for(w, **po, **launch)) as fe_g:
         fe_g.set_mlp(P)
-        for t in range(4):
+        for t in range(frames):
             if t > 0:
-                inject(fe_g, fe_o, 0, 2)
-                state = [fe_o.keypoints(c) for c in range(2)]
+                inject(fe_g, fe_o, 0, w.n_cams)
+                state = [fe_o.keypoints(c) for c in range(w.n_cams)]
             fe_o.push(list(seq.frames[t]))
             fe_g.push_stereo_frame(0, t + 1, list(seq.frames[t]))
             g, o = fe_g.get_tracks(0), fe_o.records()
-            exc = compare_records(g, o, w.fb_threshold, where=f"learned rho={rho} frame {t}")
-            assert len(exc) <= 1
+            compare_records(g, o, w.fb_threshold, where=f"{where} frame {t}", tally=tally)
             if t > 0:
-                for c in range(2):
+                for c in range(w.n_cams):
                     ids, xy, pxy, age = state[c]
                     want = oracle.features(ids, xy, pxy, age, seq.frames[t - 1, c])
                     got = fe_g.get_features(0, c)
                     assert got.shape == want.shape
                     assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), c
                 st = fe_g.stats()
-                assert st["last_fallback"] == fe_o.last_fallback or abs(st["last_fallback"] - fe_o.last_fallback) <= 2
+                assert st["last_fallback"] == fe_o.last_fallback, (t, st["last_fallback"], fe_o.last_fallback)
                 n_fb += st["last_fallback"]
     fe_o.close()
+    print(tally.line(), f"fallbacks {n_fb}", flush=True)
+    tally.check(1)
+    return n_fb
+
+
+@pytest.mark.parametrize("rho,launch", [(-1.0, {}), (0.02, {}), (1e9, {}), (0.02, {"eager": True}),
+                                        (0.02, {"stereo_mode": 1, "track_waves_per_cu": 4})])
+def test_learned_pipeline_parity_and_features(rho, launch):
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=7, n_frames=4)
+    P = oracle.mlp_init(13) * 0.05
+    P[-3:] = 0.0
+    n_fb = _learned_run(w, seq, P, rho, launch, 4, f"learned stereo752 rho={rho} {launch}")
     if rho < 0:
         assert n_fb > 0
+
+
+def test_learned_pipeline_parity_trained_weights_stereo1280():
+    """The committed trained network on its own workload (1280x720 stereo, held-out
+    sequence): the learned guesses, short budget and fallbacks as in the
+    benchmark, against the oracle."""
+    from paper_2609_30459_amd.train_mlp import load_weights
+    import os
+    import paper_2609_30459_amd as vf
+    P, rho, _ = load_weights(os.path.join(os.path.dirname(vf.__file__), "weights", "mlp_stereo1280.bin"))
+    w = synthgen.WORKLOADS["stereo1280"]
+    seq = synthgen.sequence(w, seq=3, n_frames=5)
+    n_fb = _learned_run(w, seq, P, rho, {}, 5, "learned stereo1280 trained weights")
+    assert n_fb > 0  # the fallback path is exercised
+
+

@@ -72,6 +72,29 @@ def test_unprojection_inverts_the_projection(k):
     np.testing.assert_allclose(rad, rn, atol=1e-9)
 
 
+def test_back_projection_near_the_fold_of_the_radius_polynomial():
+    """k = (-0.3, 0, 0, 0): r(theta) = theta - 0.3 theta^3 rises to its fold at
+    theta = 1/sqrt(0.9) (r = 0.70273) with slope r' = 1 - 0.9 theta^2. A pixel
+    whose root has slope >= 0.05 has a ray (the root of the cubic, from
+    numpy's polynomial roots); at slope 0.04, at the fold and beyond it (no
+    root at all) the back-projection is refused."""
+    K = (F, F, CX, CY, -0.3, 0.0, 0.0, 0.0)
+    for slope, want in ((0.5, True), (0.06, True), (0.04, False), (0.0, False)):
+        th = np.sqrt((1 - slope) / 0.9)
+        td = th - 0.3 * th ** 3
+        px = [[CX + F * td * np.cos(0.7), CY + F * td * np.sin(0.7)]]
+        out, rays, ok = oracle.camera_roundtrip(K, px)
+        assert ok[0] == want, (slope, ok[0])
+        if want:
+            roots = np.roots([-0.3, 0.0, 1.0, -td])
+            root = min(r.real for r in roots if abs(r.imag) < 1e-12 and r.real >= 0)
+            assert abs(np.arccos(rays[0, 2] / np.linalg.norm(rays[0])) - root) < 1e-9
+            np.testing.assert_allclose(out[0], px[0], atol=1e-7)
+    # beyond the fold (r > 0.70273 has no root)
+    _, _, ok = oracle.camera_roundtrip(K, [[CX + F * 0.71, CY]])
+    assert not ok[0]
+
+
 def test_roll_about_the_optical_axis_rotates_the_pixels():
     """KB4 is symmetric about the optical axis: a roll by phi (R = Rz(phi),
     t = 0, fx = fy) rotates every pixel by phi about the principal point and
