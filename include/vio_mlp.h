@@ -60,6 +60,23 @@ int vio_mlp_forward(vio_mlp* m, const float* d_x, int32_t k, float* d_y, void* h
 int vio_mlp_gradient(vio_mlp* m, const float* d_x, const float* d_targets, int32_t k, float* d_grad, float* loss,
                      void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results as vio_mlp_gradient (bit for bit), with the training scratch (the
+ * transposed bfloat16 operands, the output and loss gradients, the loss) in a
+ * device array the library holds, one per GPU, for the life of the process
+ * (VIO_MLP_NOALLOC_MAX_ROWS rows, about 4.4 MB), instead of the handle's
+ * buffers; k may exceed the handle's max_batch up to that maximum. Allocates
+ * nothing (no hipMalloc, hipFree or allocating library call); the first call
+ * on a device looks the array's address up. Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (on different streams or
+ * threads) race and must be serialised by the caller. Waits for the result
+ * like vio_mlp_gradient. Errors: VIO_EINVAL for a null pointer, k < 1 or
+ * k > VIO_MLP_NOALLOC_MAX_ROWS; VIO_EDEVICE. */
+#define VIO_MLP_NOALLOC_MAX_ROWS 4096
+int vio_mlp_gradient_noalloc(vio_mlp* m, const float* d_x, const float* d_targets, int32_t k, float* d_grad,
+                             float* loss, void* hip_stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch's gradient;
  * *loss (host, may be NULL) receives the batch loss before the step. Waits
  * when loss is not NULL. */

@@ -154,13 +154,15 @@ lib.vio_mlp_get_params.argtypes = [_vp, _vp, _i32]
 lib.vio_mlp_forward.argtypes = [_vp, _vp, _i32, _vp, _vp]
 lib.vio_mlp_gradient.argtypes = [_vp, _vp, _vp, _i32, _vp, _P(ctypes.c_float), _vp]
 lib.vio_mlp_train_step.argtypes = [_vp, _vp, _vp, _i32, ctypes.c_float, _P(ctypes.c_float), _vp]
+lib.vio_mlp_gradient_noalloc.argtypes = [_vp, _vp, _vp, _i32, _vp, _P(ctypes.c_float), _vp]
+VIO_MLP_NOALLOC_MAX_ROWS = 4096
 for _name in ("vio_frontend_create", "vio_frontend_push_stereo_frame", "vio_frontend_push_stereo_frame_device",
               "vio_frontend_get_tracks", "vio_frontend_set_keypoints", "vio_frontend_get_keypoints",
               "vio_frontend_get_pyramid", "vio_frontend_get_cell_winners", "vio_frontend_get_stats",
               "vio_frontend_set_mlp", "vio_frontend_get_features", "vio_frontend_stage_frame",
               "vio_frontend_stage_frame_device", "vio_frontend_step", "vio_frontend_stage_frames_device",
               "vio_mlp_create", "vio_mlp_set_params", "vio_mlp_get_params",
-              "vio_mlp_forward", "vio_mlp_gradient", "vio_mlp_train_step"):
+              "vio_mlp_forward", "vio_mlp_gradient", "vio_mlp_train_step", "vio_mlp_gradient_noalloc"):
     getattr(lib, _name).restype = ctypes.c_int
 
 

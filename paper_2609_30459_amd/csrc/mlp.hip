@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "fe_common.h"
@@ -431,6 +432,74 @@ hipError_t mlp_pack_launch(const MlpDev& M, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Library-held training scratch of vio_mlp_gradient_noalloc: one array per
+// GPU, held until the process ends, for batches of up to
+// VIO_MLP_NOALLOC_MAX_ROWS rows. Host code reaches it only through the
+// device address hipGetSymbolAddress returns (per device, at the first call on
+// that device); the array's name itself is not a device address on the host.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t up256c(size_t v) { return (v + 255) / 256 * 256; }
+// bytes of the scratch for a padded batch of kp rows (kp a multiple of 32)
+constexpr size_t noalloc_bytes(size_t kp) {
+  return up256c(2 * (size_t)MI * kp) + 4 * up256c(2 * (size_t)MH * kp) + up256c(2 * (size_t)MO * kp) +
+         2 * up256c(4 * (size_t)MO * kp) + up256c(4);
+}
+constexpr size_t kNoallocBytes = noalloc_bytes(VIO_MLP_NOALLOC_MAX_ROWS);
+static_assert(VIO_MLP_NOALLOC_MAX_ROWS % 32 == 0, "row maximum is a whole number of MFMA batch steps");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};  // per device ordinal
+
+// the current device's scratch address (looked up once per device, with that
+// device current); nullptr on a HIP error
+void* noalloc_scratch(int* dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  *dev_out = dev;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// The training scratch laid out in `base` for a padded batch of kp rows: the
+// same sub-buffers as a handle's arena, with the batch as leading dimension.
+struct NoallocLayout {
+  MlpScratch S;
+  float* y;
+};
+NoallocLayout noalloc_layout(unsigned char* base, int kp) {
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    unsigned char* p = base + off;
+    off = up256c(off + b);
+    return p;
+  };
+  NoallocLayout L{};
+  L.S.ldt = kp;
+  L.S.Xt = reinterpret_cast<uint16_t*>(take(2 * (size_t)MI * kp));
+  L.S.H1t = reinterpret_cast<uint16_t*>(take(2 * (size_t)MH * kp));
+  L.S.H2t = reinterpret_cast<uint16_t*>(take(2 * (size_t)MH * kp));
+  L.S.dYt = reinterpret_cast<uint16_t*>(take(2 * (size_t)MO * kp));
+  L.S.dH2t = reinterpret_cast<uint16_t*>(take(2 * (size_t)MH * kp));
+  L.S.dH1t = reinterpret_cast<uint16_t*>(take(2 * (size_t)MH * kp));
+  L.S.dY = reinterpret_cast<float*>(take(4 * (size_t)MO * kp));
+  L.y = reinterpret_cast<float*>(take(4 * (size_t)MO * kp));
+  L.S.loss = reinterpret_cast<float*>(take(4));
+  return L;
+}
+}  // namespace
+
 hipError_t mlp_forward_launch(const MlpDev& M, const float* X, int K, float* Y, hipStream_t s) {
   if (K <= 0) return hipSuccess;
   const int Kpad = (K + 15) / 16 * 16;
@@ -545,14 +614,18 @@ int vio_mlp_forward(vio_mlp* m, const float* d_x, int32_t k, float* d_y, void* h
                                                                                                   : VIO_EDEVICE;
 }
 
-static int gradient_impl(vio_mlp* m, const float* d_x, const float* d_t, int k, float* d_grad, hipStream_t s) {
+// Forward, loss, backward and weight gradients of a batch through the
+// training scratch S (every scratch row the kernels read, padding rows
+// included, is written earlier in the same sequence) and forward output y.
+static int gradient_impl(vio_mlp* m, const float* d_x, const float* d_t, int k, float* d_grad, const MlpScratch& S,
+                         float* y, hipStream_t s) {
   const int Kpad = (k + 31) / 32 * 32;
   const int blocks = (Kpad / 16 + kMlpWaves - 1) / kMlpWaves;
-  hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(blocks), dim3(64 * kMlpWaves), 0, s, m->M, d_x, k, Kpad, m->d_y, m->S);
-  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(1024), 0, s, (const float*)m->d_y, d_t, k, Kpad, m->S);
-  hipLaunchKernelGGL(k_mlp_bwd_data, dim3(blocks), dim3(64 * kMlpWaves), 0, s, m->M, Kpad, m->S);
+  hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(blocks), dim3(64 * kMlpWaves), 0, s, m->M, d_x, k, Kpad, y, S);
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(1024), 0, s, (const float*)y, d_t, k, Kpad, S);
+  hipLaunchKernelGGL(k_mlp_bwd_data, dim3(blocks), dim3(64 * kMlpWaves), 0, s, m->M, Kpad, S);
   hipLaunchKernelGGL(k_mlp_wgrad, dim3((m->n_tiles + kMlpWaves - 1) / kMlpWaves), dim3(64 * kMlpWaves), 0, s,
-                     m->n_tiles, Kpad, m->S, d_grad);
+                     m->n_tiles, Kpad, S, d_grad);
   return hipGetLastError() == hipSuccess ? VIO_OK : VIO_EDEVICE;
 }
 
@@ -560,9 +633,26 @@ int vio_mlp_gradient(vio_mlp* m, const float* d_x, const float* d_targets, int32
                      void* hip_stream) {
   if (!m || !d_x || !d_targets || !d_grad || k < 1 || k > m->max_batch) return VIO_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int rc = gradient_impl(m, d_x, d_targets, k, d_grad, s);
+  int rc = gradient_impl(m, d_x, d_targets, k, d_grad, m->S, m->d_y, s);
   if (rc != VIO_OK) return rc;
   if (hipMemcpyAsync(m->h_loss, m->S.loss, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return VIO_EDEVICE;
+  if (loss) *loss = *m->h_loss;
+  return VIO_OK;
+}
+
+int vio_mlp_gradient_noalloc(vio_mlp* m, const float* d_x, const float* d_targets, int32_t k, float* d_grad,
+                             float* loss, void* hip_stream) {
+  if (!m || !d_x || !d_targets || !d_grad || k < 1 || k > VIO_MLP_NOALLOC_MAX_ROWS) return VIO_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  void* base = noalloc_scratch(&dev);
+  if (!base) return VIO_EDEVICE;
+  const NoallocLayout L = noalloc_layout(static_cast<unsigned char*>(base), (k + 31) / 32 * 32);
+  int rc = gradient_impl(m, d_x, d_targets, k, d_grad, L.S, L.y, s);
+  if (rc != VIO_OK) return rc;
+  if (hipMemcpyAsync(m->h_loss, L.S.loss, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return VIO_EDEVICE;
   if (loss) *loss = *m->h_loss;
@@ -573,7 +663,7 @@ int vio_mlp_train_step(vio_mlp* m, const float* d_x, const float* d_targets, int
                        void* hip_stream) {
   if (!m || !d_x || !d_targets || k < 1 || k > m->max_batch || !(lr > 0.f)) return VIO_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int rc = gradient_impl(m, d_x, d_targets, k, m->d_g, s);
+  int rc = gradient_impl(m, d_x, d_targets, k, m->d_g, m->S, m->d_y, s);
   if (rc != VIO_OK) return rc;
   m->step += 1;
   const float b1 = 0.9f, b2 = 0.999f;
