@@ -4,23 +4,31 @@
 One step = one frame through the whole frontend (pyramid, FAST grid
 detection, temporal tracking of every live keypoint with the forward-backward
 check, stereo matching of the new detections, records back on the host). The
-default workload is 752x480 stereo: a seeded synthetic 200-frame sequence with
-4x texture density, smooth SE(2)+scale motion and a planar 5..60 px disparity,
-4 pyramid levels, 5 Gauss-Newton iterations per level, <= 300 keypoints per
-camera.
+default workload is the learned-initialisation comparison's: 1280x720 stereo,
+a seeded synthetic 200-frame sequence with 4x texture density, smooth
+SE(2)+scale motion and a planar 5..60 px disparity, <= 300 keypoints per
+camera, run twice:
 
-The sequences are resident in HBM before timing starts. A step stages one
-frame's device images of every stream of the workload through the C ABI,
-submits it, and reads the records back. The first timed region is the
-production path and gives `value`: pipelined submission (frame t is submitted
-before frame t-1's records are waited for and read, two frames in flight) with
-the kernels launched one by one without timestamps (`--launch graph`:
-captured graphs; `--no-pipeline`: one frame at a time, the paper's
-submit-and-wait). A second timed region runs the same steps one frame at a
-time with each kernel's HIP start/stop events attached to its own dispatch: it
-gives the kernel durations behind the roofline figures and is reported beside
-the first (`second_launch`, with a check that both give identical records).
-Prints one JSON line.
+* plain: 4 pyramid levels, 5 Gauss-Newton iterations per level from the
+  constant-velocity start (the paper's standard configuration);
+* learned: the trained network's guess refined with 2 levels and 3
+  iterations, falling back to the plain tracker when the short track is not
+  kept or its residual is above the network's threshold.
+
+Each leg's sequence is resident in HBM before timing starts. A step stages
+one frame's device images of every stream through the C ABI, submits it and
+reads the records back. The first timed region of a leg is the production
+path: pipelined submission (frame t is submitted before frame t-1's records
+are waited for and read, two frames in flight) with the kernels launched one
+by one (`--launch graph`: captured graphs; `--no-pipeline`: one frame at a
+time). A second region runs the same steps one frame at a time with each
+kernel's HIP start/stop events attached to its own dispatch: it gives the
+kernel durations behind the roofline figures, with a check that both regions
+give identical records. A host-image leg pushes the frames from host memory
+one at a time (upload, kernels, fence, readback: the paper's frontend time).
+`value` is the frames/s of the faster leg that meets the accuracy bar (median
+per-step error against the synthetic ground truth <= 0.1 px, survival within
+0.5 points of plain). Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -38,7 +46,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-PATTERN = 52
+# Algorithmic FP32 work of the tracker, per level and pass of one keypoint:
+# the template (52 samples, gradients, normalisation, J, H, its inverse, G,
+# c) about 4.6 kFLOP, one Gauss-Newton iteration (warp, bilinear samples,
+# the sums, the update) about 1.25 kFLOP.
+F_TEMPLATE = 4600.0
+F_ITERATION = 1250.0
+MLP_FLOP_PER_ROW = 2 * (32 * 128 + 128 * 128 + 128 * 3)
 
 
 def log(msg):
@@ -57,23 +71,19 @@ def cpu_model_name():
 
 
 def track_flops_per_call(levels, iters):
-    """Algorithmic FP32 operations of one forward-backward track.
-
-    Counting convention (per pattern point, multiply and add counted
-    separately): template per level 122 (5 bilinear samples at 13, sample
-    positions 4, gradients 4, normalisation 7, Hessian 18, gains 15, c 9);
-    iteration 32 (warp 8, bilinear 13, the four sums 11). Wave-uniform scalar
-    work (3x3 inverse, SE(2) exponential) is not counted.
-    """
-    return 2 * levels * PATTERN * (122 + 32 * iters)
+    """Algorithmic FP32 operations of one forward-backward track: two passes of
+    `levels` levels, each a template and `iters` iterations (L = 4, N = 5:
+    86.8 kFLOP)."""
+    return 2 * levels * (F_TEMPLATE + iters * F_ITERATION)
 
 
-def pyramid_bytes(width, height, levels, cams, copy_l0=True):
-    """Algorithmic HBM bytes of the pyramid+detector launch: level 0 read once,
-    written once into the own pyramid (device push), levels 1..L-1 written."""
+def pyramid_bytes(width, height, levels, cams):
+    """Algorithmic HBM bytes of the pyramid+detector launch: level 0 read once
+    and levels 1..L-1 written once (the device push's copy of level 0 into the
+    frontend's own pyramid is not counted)."""
     a0 = width * height * cams
     p1 = sum((width >> l) * (height >> l) for l in range(1, levels)) * cams
-    return a0 * (2 if copy_l0 else 1) + p1
+    return a0 + p1
 
 
 def measured_traffic(workload, kernel):
@@ -97,22 +107,23 @@ def measured_traffic(workload, kernel):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 190, batch16 and rig4 100)")
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="stereo752",
-                    help="stereo752, stereo1280, rig4, star752, mono320 or batch16")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps per leg (default 150, batch16 and rig4 80)")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed steps before each leg's timed steps (at least 10)")
+    ap.add_argument("--workload", default="stereo1280",
+                    help="stereo1280 (default), stereo752, rig4, star752, mono320 or batch16")
     ap.add_argument("--seq", type=int, default=0)
+    ap.add_argument("--init", choices=["both", "const_vel", "learned"], default="both",
+                    help="legs to run: the plain tracker (const_vel), the learned initialisation, or both")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-host-leg", action="store_true", help="skip the host-image leg")
     ap.add_argument("--launch", choices=["plain", "graph", "eager"], default="plain",
-                    help="first timed region (`value`): the kernels launched one by one without timestamps "
-                         "(default; the fewest host calls per pipelined frame), captured graphs, or one by one "
-                         "with HIP events attached to each dispatch (gives kernel durations)")
+                    help="first timed region: kernels launched one by one without timestamps (default), captured "
+                         "graphs, or one by one with HIP events attached to each dispatch")
     ap.add_argument("--no-pipeline", action="store_true",
-                    help="graph launches one frame at a time (no frame submitted before the last one's records are read)")
+                    help="one frame at a time (no frame submitted before the last one's records are read)")
     ap.add_argument("--no-second-launch", "--no-graph-replay", dest="no_second", action="store_true",
-                    help="skip the second timed region, which runs the same steps with the other launch mode")
-    ap.add_argument("--init", choices=["const_vel", "learned"], default="const_vel")
+                    help="skip the second timed region (one frame at a time with per-kernel events)")
     ap.add_argument("--weights", default=None, help="learned-init weights (default: the package's for the workload)")
     ap.add_argument("--levels", type=int, default=None, help="override the pyramid levels")
     ap.add_argument("--iters", type=int, default=None, help="override the Gauss-Newton iterations per level")
@@ -136,6 +147,14 @@ def main():
                     help="residual RMS above which a short predicted track falls back (default: none)")
     ap.add_argument("--learned-levels", type=int, default=2)
     ap.add_argument("--learned-iters", type=int, default=3)
+    ap.add_argument("--learned-fb-levels", type=int, default=2,
+                    help="learned leg: budget of the fallback from the constant-velocity start (0 = the full one)")
+    ap.add_argument("--learned-fb-iters", type=int, default=5)
+    ap.add_argument("--learned-stereo", choices=["prior", "neighbour"], default="neighbour",
+                    help="learned leg: stereo matches start from the nearest paired keypoint's offset (neighbour) "
+                         "or from the disparity prior")
+    ap.add_argument("--stereo-levels", type=int, default=2, help="budget of neighbour-started stereo matches")
+    ap.add_argument("--stereo-iters", type=int, default=3)
     ap.add_argument("--waves-per-cu", type=int, default=None,
                     help="tracker grid: 0 = one wave per keypoint, N = persistent N waves per CU "
                          "(default: the autotuned choice, else 0)")
@@ -167,7 +186,8 @@ def main():
 
     batched = args.workload == "batch16"
     if args.steps is None:
-        args.steps = 100 if args.workload in ("batch16", "rig4") else 190
+        args.steps = 80 if args.workload in ("batch16", "rig4") else 150
+    warmup = max(args.warmup, 10)
     if batched:
         ws = list(BATCH16)
     else:
@@ -183,49 +203,47 @@ def main():
         over["gn_iters"] = args.iters
     ws = [w.with_(**over) for w in ws]
     w0 = ws[0]
-    n_frames = args.warmup + args.steps
+    n_frames = warmup + args.steps
     log(f"rendering {n_frames} frames of {args.workload}: {len(ws)} stream(s), "
         f"{sum(w.n_cams * w.width * w.height for w in ws) / 1e6:.2f} MP per step")
     seqs = [synthgen.sequence(w, seq=args.seq, stream=i, n_frames=n_frames) for i, w in enumerate(ws)]
     devs = [torch.from_numpy(q.frames).cuda() for q in seqs]
     torch.cuda.synchronize()
     streams = [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in ws]
-
-    wpc, bw, tile, smode = args.waves_per_cu, args.block_waves, args.tile, args.stereo_mode
-    tuned = None
-    if wpc is None and bw is None and tile is None and smode is None:
-        from paper_2609_30459_amd import autotune
-        tuned = autotune.lookup(args.workload, args.init)
-        if tuned:
-            wpc, bw = tuned["track_waves_per_cu"], tuned["track_block_waves"]
-            tile, smode = tuned.get("pyr_tile", 64), tuned.get("stereo_mode", 0)
-    wpc = wpc or 0
-    bw = bw or 4
-    tile = tile or 64
-    smode = smode or 0
-    extra = dict(track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile, stereo_mode=smode)
+    inits = ["const_vel", "learned"] if args.init == "both" else [args.init]
     short_pred = args.motion != "none" and args.pred_levels > 0
-    profiled_config = (args.init == "const_vel" and args.motion == "none" and args.preset == "standard" and
-                       not args.k_per_cell and not args.levels and not args.iters)
-    if short_pred:
-        extra.update(pred_levels=args.pred_levels, pred_iters=args.pred_iters,
-                     pred_rho=args.pred_rho if args.pred_rho is not None else 3.0e38)
-    rho = None
-    if args.init == "learned":
+    profiled_config = (args.motion == "none" and args.preset == "standard" and not args.k_per_cell and
+                       not args.levels and not args.iters)
+
+    def launch_choice(init):
+        """Launch parameters (never change the records): explicit flags, else the autotuned choice."""
+        wpc, bw, tile, smode = args.waves_per_cu, args.block_waves, args.tile, args.stereo_mode
+        tuned = None
+        if wpc is None and bw is None and tile is None and smode is None:
+            from paper_2609_30459_amd import autotune
+            tuned = autotune.lookup(args.workload, init)
+            if tuned:
+                wpc, bw = tuned["track_waves_per_cu"], tuned["track_block_waves"]
+                tile, smode = tuned.get("pyr_tile", 64), tuned.get("stereo_mode", 0)
+        return dict(track_waves_per_cu=wpc or 0, track_block_waves=bw or 4, pyr_tile=tile or 64,
+                    stereo_mode=smode or 0), tuned is not None
+
+    mlp = None
+    if "learned" in inits:
         from paper_2609_30459_amd.train_mlp import load_weights
         # the workload's own trained network when there is one, else the stereo1280 one
         wdir = os.path.join(ROOT, "paper_2609_30459_amd", "weights")
         own = os.path.join(wdir, f"mlp_{args.workload}.bin")
         path = args.weights or (own if os.path.exists(own) else os.path.join(wdir, "mlp_stereo1280.bin"))
-        mlp_params, rho, meta = load_weights(path)
-        log(f"learned init: {path} ({meta}), rho {rho:.4f}")
-        extra.update(init_mode=1, learned_levels=args.learned_levels, learned_iters=args.learned_iters,
-                     learned_rho=rho)
+        params_, rho_, meta = load_weights(path)
+        mlp = (params_, rho_, os.path.basename(path))
+        log(f"learned init: {path} ({meta}), rho {rho_:.4f}")
+
     ids = list(range(len(ws)))
     # each frame's device images (views into the resident sequences), all
     # cameras stream by stream, made once before any timed region
     frame_imgs = [[devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)] for t in range(n_frames)]
-    # the push/staging call's pointer and pitch arrays, built once per frame
+    # the push/staging call's pointer and pipelined arrays, built once per frame
     frame_imgs = [vf.Frontend.device_images(f) for f in frame_imgs]
     # camera-model start: the motion of frame t-1 -> t per stream (every camera of a stream takes its
     # first camera's motion), made before any timed region
@@ -245,19 +263,36 @@ def main():
                     tr[:2] += rng.normal(0.0, args.motion_noise, 2) / (args.focal * inv_depth)
                 motions[i][t] = vf.Frontend.motion_array([(c, R, tr, inv_depth) for c in range(w.n_cams)])
 
-    def timed_run(eager):
-        """Warmup, then the timed steps: (records per stream, wall s per step, stats per step, elapsed s)."""
+    def leg_params(init):
+        extra, tuned = launch_choice(init)
+        if short_pred:
+            extra.update(pred_levels=args.pred_levels, pred_iters=args.pred_iters,
+                         pred_rho=args.pred_rho if args.pred_rho is not None else 3.0e38)
+        if init == "learned":
+            extra.update(init_mode=1, learned_levels=args.learned_levels, learned_iters=args.learned_iters,
+                         learned_rho=mlp[1], learned_fb_levels=args.learned_fb_levels,
+                         learned_fb_iters=args.learned_fb_iters)
+            if args.learned_stereo == "neighbour":
+                extra.update(stereo_init=1, stereo_levels=args.stereo_levels, stereo_iters=args.stereo_iters)
+        return extra, tuned
+
+    def new_frontend(init, eager=False, plain=False):
+        extra, _ = leg_params(init)
         # the streams share one parameter block; per-stream sizes and caps come with the stream
-        fe = vf.Frontend(streams, vf.params_for(w0, eager=eager, plain=args.launch == "plain" and not eager, **extra))
-        if args.init == "learned":
-            fe.set_mlp(mlp_params, rho)
+        fe = vf.Frontend(streams, vf.params_for(w0, eager=eager, plain=plain, **extra))
+        if init == "learned":
+            fe.set_mlp(mlp[0], mlp[1])
         if motions is not None:
             for i, w in enumerate(ws):
                 for c in range(w.n_cams):
                     fe.set_camera_model(i, c, K_of[i])
+        return fe
+
+    def timed_run(init, eager):
+        """Warmup, then the timed steps: (records per stream, wall s per step, stats per step, elapsed s)."""
+        fe = new_frontend(init, eager=eager, plain=args.launch == "plain" and not eager)
         records = [[] for _ in ws]
         wall, stats = [], []
-
         pipelined = not eager and not args.no_pipeline
         t_sub = {}
 
@@ -285,23 +320,19 @@ def main():
                 records[0].append(fe.get_tracks(0))
             return time.perf_counter() - t_sub.pop(t)
 
-        # pipelined (graph launches): frame t is submitted before frame t-1's
-        # records are read, so the host's work overlaps the device's; the
-        # latency of a frame runs from its submission to its records
-        log(f"warmup {args.warmup} steps ({'eager' if eager else 'graph'}{', pipelined' if pipelined else ''})")
-        for t in range(args.warmup):
+        log(f"{init}: warmup {warmup} steps ({'eager' if eager else args.launch}{', pipelined' if pipelined else ''})")
+        for t in range(warmup):
             submit(t)
             collect(t)
         torch.cuda.synchronize()
-        log(f"timing {args.steps} steps")
-        # no garbage-collector pause inside the timed steps
+        log(f"{init}: timing {args.steps} steps")
         gc.collect()
-        gc.disable()
+        gc.disable()  # no garbage-collector pause inside the timed steps
         t0 = time.perf_counter()
-        for t in range(args.warmup, n_frames):
+        for t in range(warmup, n_frames):
             submit(t)
             if pipelined:
-                if t > args.warmup:
+                if t > warmup:
                     wall.append(collect(t - 1))
                     stats.append(fe.stats())
             else:
@@ -316,95 +347,170 @@ def main():
         fe.close()
         return records, wall, stats, elapsed
 
-    first_eager = args.launch == "eager"
-    records, wall, stats, elapsed = timed_run(first_eager)
-    steps_per_s = args.steps / elapsed
-    fallbacks = [s_["last_fallback"] for s_ in stats]
-    second, eager_stats = None, stats if first_eager else None
-    if not args.no_second:
-        rec2, wall2, stats2, elapsed2 = timed_run(not first_eager)
-        same = all(a.tobytes() == b.tobytes() for ra, rb in zip(records, rec2) for a, b in zip(ra, rb))
-        second = {"launch": "graph" if first_eager else "eager",
-                  "value": args.steps * len(ws) / elapsed2, "ms_per_step": 1000.0 * elapsed2 / args.steps,
-                  "gpu_ms_per_step": float(np.mean([s_["last_gpu_ms"] for s_ in stats2])),
-                  "latency_p50_ms": float(np.percentile(np.array(wall2) * 1e3, 50)),
-                  "latency_p99_ms": float(np.percentile(np.array(wall2) * 1e3, 99)),
-                  "records_identical": bool(same)}
-        if not first_eager:
-            eager_stats = stats2
-    # kernel durations from the eager pass (a graph replay gives the frame's device time only);
-    # the whole-frame device time from the first timed region
-    kstats = eager_stats if eager_stats is not None else stats
-    stage_ms = [s_["last_stage_ms"] + s_["last_learned_ms"] + [f_["last_gpu_ms"]] for s_, f_ in zip(kstats, stats)]
+    def host_run(init):
+        """The paper's frontend time: host images pushed one frame at a time (H2D upload, kernels, fence,
+        records back), host wall clock per frame."""
+        fe = new_frontend(init)
+        host = [q.frames for q in seqs]
+        wall = []
+        log(f"{init}: host-image leg, {warmup} + {args.steps} frames")
+        for t in range(n_frames):
+            if motions is not None and t > 0:
+                for i in ids:
+                    fe.set_motion(i, motions[i][t])
+            t0 = time.perf_counter()
+            if batched:
+                for i, w in enumerate(ws):
+                    fe.stage_frame(i, t + 1, list(host[i][t]))
+                fe.step()
+                fe.get_tracks_many(ids)
+            else:
+                fe.push_stereo_frame(0, t + 1, list(host[0][t]))
+                fe.get_tracks(0)
+            if t >= warmup:
+                wall.append(time.perf_counter() - t0)
+        fe.close()
+        ms = np.array(wall) * 1e3
+        return {"value": len(ws) * 1e3 / ms.mean(), "unit": "stream-frames/s" if batched else "frames/s",
+                "ms_per_frame": float(ms.mean()), "p50_ms": float(np.percentile(ms, 50)),
+                "p99_ms": float(np.percentile(ms, 99)),
+                "h2d_bytes_per_frame": sum(w.n_cams * w.width * w.height for w in ws)}
 
-    # ---- tracked keypoints and accuracy against the synthetic ground truth ---
     TR, DET, MAT = vf.VIO_TRACKED, vf.VIO_DETECTED, vf.VIO_MATCHED
-    tracked = np.zeros(args.steps)
-    errs, serrs, n_tr, n_lost = [], [], 0, 0
-    n_temporal = np.zeros(args.steps)
-    n_stereo = np.zeros(args.steps)
-    for i, (w, seq) in enumerate(zip(ws, seqs)):
-        rec = records[i]
-        for k, t in enumerate(range(args.warmup, n_frames)):
-            tracked[k] += int((rec[t]["status"] == TR).sum())
-            prev = rec[t - 1] if t > 0 else rec[t][:0]
-            n_temporal[k] += int(np.isin(prev["status"], [TR, DET, MAT]).sum())
-            # each detection is matched into the pair's right camera, or a star's three other cameras
-            n_stereo[k] += int((rec[t]["status"] == DET).sum()) * (3 if w.star else 1) if w.stereo else 0
-        e, se, tr, lo = accuracy(w, seq, rec, TR, DET, MAT)
-        errs += e
-        serrs += se
-        n_tr += tr
-        n_lost += lo
-    err = np.concatenate(errs) if errs else np.zeros(1)
-    serr = np.concatenate(serrs) if serrs else np.zeros(1)
-    survival = n_tr / max(1, n_tr + n_lost)
 
-    # ---- roofline of the dominant kernel (HIP events on the launch stream) ----
-    # [steps, 6]: pyramid+detector, tracker, selection, features, network, whole frame
-    sm = np.array(stage_ms)
-    mean_ms = sm.mean(0)
-    mean_ms[3] = sm[:, 3].mean() if args.init == "learned" else -1.0
-    mean_ms[4] = sm[:, 4].mean() if args.init == "learned" else -1.0
-    have_times = bool((sm[:, :3] >= 0).all())
-    L, N = w0.levels, w0.gn_iters
-    fb = np.array(fallbacks, np.float64)
-    if args.init == "learned" or short_pred:
-        # every temporal track runs the short tracker; fallbacks rerun the full one
-        sl, si = (args.learned_levels, args.learned_iters) if args.init == "learned" else (args.pred_levels,
-                                                                                          args.pred_iters)
-        flops_step = n_temporal * track_flops_per_call(sl, si) + (fb + n_stereo) * track_flops_per_call(L, N)
-    else:
-        flops_step = (n_temporal + n_stereo) * track_flops_per_call(L, N)
-    pyr_b = sum(pyramid_bytes(w.width, w.height, L, w.n_cams) for w in ws)
-    total_rows = sum(w.max_keypoints * w.n_cams for w in ws)
-    kernels = {
-        "k_pyr_detect": {"bound": "hbm", "avg_ms": float(mean_ms[0]), "bytes_per_launch": pyr_b,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "achieved": pyr_b / (mean_ms[0] * 1e-3) / 1e9 if have_times else None},
-        "k_track": {"bound": "alu", "avg_ms": float(mean_ms[1]), "calls_per_launch": float((n_temporal + n_stereo).mean()),
-                    "flops_per_launch": float(flops_step.mean()), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "achieved": float(flops_step.mean()) / (mean_ms[1] * 1e-3) / 1e12 if have_times else None,
-                    },
-        "k_select": {"bound": "latency", "avg_ms": float(mean_ms[2])},
-    }
-    if args.init == "learned":
-        kernels["k_features"] = {"bound": "latency", "avg_ms": float(mean_ms[3])}
-        kernels["k_mlp_fwd"] = {"bound": "mfma", "avg_ms": float(mean_ms[4]),
-                                "flops_per_launch": 2 * (32 * 128 + 128 * 128 + 128 * 3) * total_rows}
-    roof = None
-    if have_times:
-        dom = ["k_pyr_detect", "k_track", "k_select"][int(np.argmax(mean_ms[:2]))]
-        kd = kernels[dom]
-        roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
-                "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"],
-                # counters were taken on the default configuration only
-                "traffic": measured_traffic(args.workload, dom) if profiled_config else None,
-                "avg_ms": kd["avg_ms"]}
+    def leg(init):
+        first_eager = args.launch == "eager"
+        records, wall, stats, elapsed = timed_run(init, first_eager)
+        steps_per_s = args.steps / elapsed
+        fallbacks = np.array([s_["last_fallback"] for s_ in stats], np.float64)
+        second, eager_stats = None, stats if first_eager else None
+        if not args.no_second:
+            rec2, wall2, stats2, elapsed2 = timed_run(init, not first_eager)
+            same = all(a.tobytes() == b.tobytes() for ra, rb in zip(records, rec2) for a, b in zip(ra, rb))
+            second = {"launch": "graph" if first_eager else "eager",
+                      "value": args.steps * len(ws) / elapsed2, "ms_per_step": 1000.0 * elapsed2 / args.steps,
+                      "gpu_ms_per_step": float(np.mean([s_["last_gpu_ms"] for s_ in stats2])),
+                      "latency_p50_ms": float(np.percentile(np.array(wall2) * 1e3, 50)),
+                      "latency_p99_ms": float(np.percentile(np.array(wall2) * 1e3, 99)),
+                      "records_identical": bool(same)}
+            if not first_eager:
+                eager_stats = stats2
+        kstats = eager_stats if eager_stats is not None else stats
+        # [steps, 6]: pyramid+detector, tracker, selection, learned features, network, whole frame
+        sm = np.array([s_["last_stage_ms"] + s_["last_learned_ms"] + [f_["last_gpu_ms"]]
+                       for s_, f_ in zip(kstats, stats)])
+        mean_ms = sm.mean(0)
+        have_times = bool((sm[:, :3] >= 0).all())
 
-    # ---- CPU baseline: the oracle on a bounded sample of the same workload ---
+        # tracked keypoints and accuracy against the synthetic ground truth
+        tracked = np.zeros(args.steps)
+        n_temporal = np.zeros(args.steps)
+        n_stereo = np.zeros(args.steps)
+        errs, serrs, n_tr, n_lost = [], [], 0, 0
+        for i, (w, seq) in enumerate(zip(ws, seqs)):
+            rec = records[i]
+            # records[i] holds the warmup frames too: frame t is rec[t]
+            for k, t in enumerate(range(warmup, n_frames)):
+                tracked[k] += int((rec[t]["status"] == TR).sum())
+                n_temporal[k] += int(np.isin(rec[t - 1]["status"], [TR, DET, MAT]).sum())
+                # each detection is matched into the pair's right camera, or a star's three other cameras
+                n_stereo[k] += int((rec[t]["status"] == DET).sum()) * (3 if w.star else 1) if w.stereo else 0
+            e, se, tr, lo = accuracy(w, seq, rec, TR, DET, MAT)
+            errs += e
+            serrs += se
+            n_tr += tr
+            n_lost += lo
+        err = np.concatenate(errs) if errs else np.zeros(1)
+        serr = np.concatenate(serrs) if serrs else np.zeros(1)
+        survival = n_tr / max(1, n_tr + n_lost)
+
+        L, N = w0.levels, w0.gn_iters
+        if init == "learned":
+            # every temporal track runs the short tracker, fallbacks the fallback budget; stereo matches
+            # run the neighbour budget (every match after the first frame has a paired neighbour) or the full one
+            fbl = args.learned_fb_levels or L
+            fbi = args.learned_fb_iters if args.learned_fb_levels else N
+            stereo_f = (track_flops_per_call(args.stereo_levels, args.stereo_iters)
+                        if args.learned_stereo == "neighbour" else track_flops_per_call(L, N))
+            flops_step = (n_temporal * track_flops_per_call(args.learned_levels, args.learned_iters) +
+                          fallbacks * track_flops_per_call(fbl, fbi) + n_stereo * stereo_f)
+        elif short_pred:
+            flops_step = (n_temporal * track_flops_per_call(args.pred_levels, args.pred_iters) +
+                          (fallbacks + n_stereo) * track_flops_per_call(L, N))
+        else:
+            flops_step = (n_temporal + n_stereo) * track_flops_per_call(L, N)
+        pyr_b = sum(pyramid_bytes(w.width, w.height, L, w.n_cams) for w in ws)
+        kernels = {
+            "k_pyr_detect": {"bound": "hbm", "avg_ms": float(mean_ms[0]), "bytes_per_launch": pyr_b,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "achieved": pyr_b / (mean_ms[0] * 1e-3) / 1e9 if have_times else None},
+            "k_track": {"bound": "alu", "avg_ms": float(mean_ms[1]),
+                        "calls_per_launch": float((n_temporal + n_stereo).mean()),
+                        "flops_per_launch": float(flops_step.mean()), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s",
+                        "achieved": float(flops_step.mean()) / (mean_ms[1] * 1e-3) / 1e12 if have_times else None},
+            "k_select": {"bound": "latency", "avg_ms": float(mean_ms[2])},
+        }
+        if init == "learned":
+            rows = n_temporal.mean()
+            kernels["learned_stage"] = {"bound": "latency", "avg_ms": float(sm[:, 3].mean() + max(0.0, sm[:, 4].mean())),
+                                        "rows_per_launch": float(rows), "mfma_flops_per_launch": MLP_FLOP_PER_ROW * rows}
+        roof = None
+        if have_times:
+            dom = ["k_pyr_detect", "k_track"][int(np.argmax(mean_ms[:2]))]
+            kd = kernels[dom]
+            roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
+                    "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"],
+                    "traffic": measured_traffic(f"{args.workload}_{'plain' if init == 'const_vel' else init}", dom)
+                    if profiled_config else None,
+                    "avg_ms": kd["avg_ms"]}
+        wall_ms = np.array(wall) * 1e3
+        extra, tuned = leg_params(init)
+        return {
+            "value": steps_per_s * len(ws), "ms_per_step": 1000.0 / steps_per_s,
+            "tracked_kpts_per_s": float(tracked.mean()) * steps_per_s,
+            "gpu_ms_per_step": float(mean_ms[5]),
+            "latency_ms": {"p50": float(np.percentile(wall_ms, 50)), "p99": float(np.percentile(wall_ms, 99)),
+                           "gpu_p50": float(np.percentile(sm[:, 5], 50)),
+                           "gpu_p99": float(np.percentile(sm[:, 5], 99))},
+            "accuracy": {"temporal_median_px": float(np.median(err)),
+                         "temporal_p90_px": float(np.percentile(err, 90)),
+                         "stereo_median_px": float(np.median(serr)), "survival": survival},
+            "fallback_per_step": float(fallbacks.mean()) if init == "learned" or short_pred else None,
+            "budget": ({"levels": args.learned_levels, "iters": args.learned_iters,
+                        "fallback_levels": args.learned_fb_levels or L,
+                        "fallback_iters": args.learned_fb_iters if args.learned_fb_levels else N,
+                        "stereo_start": args.learned_stereo,
+                        **({"stereo_levels": args.stereo_levels, "stereo_iters": args.stereo_iters}
+                           if args.learned_stereo == "neighbour" else {}),
+                        "rho": mlp[1], "weights": mlp[2]} if init == "learned"
+                       else {"levels": L, "iters": N, "stereo_start": "prior"}),
+            "launch": {**{k: v for k, v in extra.items() if k in ("track_waves_per_cu", "track_block_waves",
+                                                                   "pyr_tile", "stereo_mode")},
+                       "autotuned": tuned},
+            "roofline": roof, "second_launch": second, "kernels": kernels,
+            "host_image": None if args.no_host_leg else host_run(init),
+        }
+
+    legs = {init: leg(init) for init in inits}
+
+    # value: the faster leg that meets the accuracy bar (median <= 0.1 px; survival within 0.5 points of plain)
+    base_surv = legs["const_vel"]["accuracy"]["survival"] if "const_vel" in legs else None
+    ok = {k: v["accuracy"]["temporal_median_px"] <= 0.1 and
+          (base_surv is None or v["accuracy"]["survival"] >= base_surv - 0.005) for k, v in legs.items()}
+    for k, v in legs.items():
+        v["meets_accuracy_bar"] = ok[k]
+    cand = [k for k in legs if ok[k]] or list(legs)
+    best = max(cand, key=lambda k: legs[k]["value"])
+    if "const_vel" in legs and "learned" in legs:
+        legs["learned"]["speedup_vs_plain"] = legs["learned"]["value"] / legs["const_vel"]["value"]
+        if legs["learned"]["host_image"] and legs["const_vel"]["host_image"]:
+            legs["learned"]["host_image"]["speedup_vs_plain"] = (legs["learned"]["host_image"]["value"] /
+                                                                 legs["const_vel"]["host_image"]["value"])
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same workload (plain tracker) ----
     cpu = None
-    if not args.no_cpu_baseline and args.init == "const_vel":
+    if not args.no_cpu_baseline:
         import oracle
         nproc = os.cpu_count() or 1
         model = cpu_model_name()
@@ -414,7 +520,6 @@ def main():
             return [oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo, oracle.params_for(w))
                     for w in ws]
 
-        # (i) one thread, stream after stream, frame by frame
         log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s (one thread)")
         fos = new_oracles()
         n, c0 = 0, time.perf_counter()
@@ -427,10 +532,9 @@ def main():
         for fo in fos:
             fo.close()
         cpu = {"value": n * len(ws) / cpu_s, "unit": unit, "cores": 1, "kind": "oracle",
-               "sample": f"first {n} frames of the same {args.workload} sequence(s), single-threaded C++ oracle "
-                         f"(-O2), {cpu_s:.1f} s", "nproc": nproc, "cpu_model": model}
+               "sample": f"first {n} frames of the same {args.workload} sequence(s), plain tracker, single-threaded "
+                         f"C++ oracle (-O2), {cpu_s:.1f} s", "nproc": nproc, "cpu_model": model}
         if batched:
-            # (ii) one thread per stream (the oracle's calls release the GIL), the same frames
             from concurrent.futures import ThreadPoolExecutor
             threads = min(len(ws), nproc)
             log(f"cpu baseline: oracle, one thread per stream ({threads} threads), {n} frames")
@@ -450,47 +554,38 @@ def main():
             cpu["threaded"] = {"value": n * len(ws) / thr_s, "unit": unit, "threads": threads,
                                "sample": f"the same {n} frames, one thread per stream, {thr_s:.1f} s"}
 
-    wall_ms = np.array(wall) * 1e3
-    value = steps_per_s * len(ws)
+    vb = legs[best]
     out = {
         "metric": "stereo frames/s + tracked kpts/s, plain vs learned-init KLT at <=0.1px err",
-        "value": value,
+        "value": vb["value"],
         "unit": "stream-frames/s" if batched else "frames/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 / steps_per_s,
+        "warmup": warmup,
+        "ms_per_step": vb["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "streams": len(ws),
+        "config": {"workload": args.workload, "value_leg": best, "legs": inits, "streams": len(ws),
                    "cameras": sum(w.n_cams for w in ws),
                    "sizes": sorted({f"{w.width}x{w.height}x{w.n_cams}" for w in ws}),
-                   "levels": L, "gn_iters": N, "max_keypoints": sorted({w.max_keypoints for w in ws}),
+                   "levels": w0.levels, "gn_iters": w0.gn_iters, "max_keypoints": sorted({w.max_keypoints for w in ws}),
                    "preset": args.preset, "k_per_cell": w0.k_per_cell,
                    "motion": args.motion, **({"motion_noise_px": args.motion_noise, "focal": args.focal,
                                               "camera": args.camera} if args.motion != "none" else {}),
                    **({"pred_levels": args.pred_levels, "pred_iters": args.pred_iters, "pred_rho": args.pred_rho}
                       if short_pred else {}),
                    "cell_size": sorted({w.cell_size for w in ws}), "thresholds": list(w0.thresholds),
-                   "init": args.init, "launch": args.launch,
-                   "pipelined": args.launch != "eager" and not args.no_pipeline, "track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile,
-                   "stereo_mode": ["speculative", "deferred"][smode],
-                   "autotuned": tuned is not None, "parallelism": "single_gpu",
-                   **({"learned_levels": args.learned_levels, "learned_iters": args.learned_iters, "rho": rho}
-                      if args.init == "learned" else {})},
-        "tracked_kpts_per_s": float(tracked.mean()) * steps_per_s,
-        "gpu_ms_per_step": float(mean_ms[5]),
-        "latency_ms": {"p50": float(np.percentile(wall_ms, 50)), "p99": float(np.percentile(wall_ms, 99)),
-                       "gpu_p50": float(np.percentile(sm[:, 5], 50)), "gpu_p99": float(np.percentile(sm[:, 5], 99))},
-        "accuracy": {"temporal_median_px": float(np.median(err)), "temporal_p90_px": float(np.percentile(err, 90)),
-                     "stereo_median_px": float(np.median(serr)), "survival": survival},
-        "fallback_per_step": float(fb.mean()) if args.init == "learned" or short_pred else None,
-        "roofline": roof,
-        "second_launch": second,
-        "kernels": kernels,
+                   "launch": args.launch, "pipelined": args.launch != "eager" and not args.no_pipeline,
+                   "parallelism": "single_gpu"},
+        "tracked_kpts_per_s": vb["tracked_kpts_per_s"],
+        "gpu_ms_per_step": vb["gpu_ms_per_step"],
+        "latency_ms": vb["latency_ms"],
+        "accuracy": vb["accuracy"],
+        "roofline": vb["roofline"],
+        "legs": legs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

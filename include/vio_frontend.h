@@ -124,8 +124,29 @@ typedef struct vio_frontend_params {
   void* (*dev_alloc)(size_t bytes, void* ctx);
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
+  /* Learned initialisation: budget of the fallback from the constant-velocity
+   * start when the short track from the network's guess is not kept:
+   * learned_fb_levels levels (1..levels) with learned_fb_iters iterations
+   * (1..32); learned_fb_levels = 0 takes the full budget levels x gn_iters. */
+  int32_t learned_fb_levels;
+  int32_t learned_fb_iters;
+  /* Start of a new keypoint's stereo matches into a camera without the rig's
+   * extrinsics: VIO_STEREO_INIT_PRIOR, the disparity prior p - (disparity0, 0)
+   * with the full budget; or VIO_STEREO_INIT_NEIGHBOUR (a project addition, in
+   * the spirit of the learned initialisation): of the keypoints that, after
+   * the previous frame, lived in both the detecting and the target camera, the
+   * nearest to p by (squared distance between p and its detecting-camera
+   * position, id) lends its offset (x_target - x_detecting, y_target -
+   * y_detecting): the match starts at p plus that offset with stereo_levels
+   * levels (1..levels) and stereo_iters iterations (1..32); without such a
+   * keypoint, the disparity prior with the full budget. */
+  int32_t stereo_init;
+  int32_t stereo_levels;
+  int32_t stereo_iters;
 } vio_frontend_params;
 
+#define VIO_STEREO_INIT_PRIOR 0
+#define VIO_STEREO_INIT_NEIGHBOUR 1
 #define VIO_STEREO_SPECULATIVE 0
 #define VIO_STEREO_DEFERRED 1
 #define VIO_TOPOLOGY_PAIRS 0

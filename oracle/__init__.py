@@ -46,6 +46,8 @@ class Params(ctypes.Structure):
         ("init_mode", ctypes.c_int32), ("learned_levels", ctypes.c_int32), ("learned_iters", ctypes.c_int32),
         ("learned_rho", ctypes.c_float), ("pred_levels", ctypes.c_int32), ("pred_iters", ctypes.c_int32),
         ("pred_rho", ctypes.c_float), ("topology", ctypes.c_int32),
+        ("learned_fb_levels", ctypes.c_int32), ("learned_fb_iters", ctypes.c_int32),
+        ("stereo_init", ctypes.c_int32), ("stereo_levels", ctypes.c_int32), ("stereo_iters", ctypes.c_int32),
     ]
 
 
@@ -268,7 +270,8 @@ def inverse3(m):
 def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40, 20, 10, 5),
                 edge_margin=8, max_keypoints=300, fb_threshold=0.3, disparity0=32.5, init_mode=0,
                 learned_levels=2, learned_iters=3, learned_rho=0.0, pred_levels=0, pred_iters=0,
-                pred_rho=0.0, topology=0) -> Params:
+                pred_rho=0.0, topology=0, learned_fb_levels=0, learned_fb_iters=0, stereo_init=0,
+                stereo_levels=2, stereo_iters=3) -> Params:
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
@@ -281,6 +284,8 @@ def make_params(levels=4, gn_iters=5, cell_size=32, k_per_cell=1, thresholds=(40
         learned_rho
     p.pred_levels, p.pred_iters, p.pred_rho = pred_levels, pred_iters, pred_rho
     p.topology = topology
+    p.learned_fb_levels, p.learned_fb_iters = learned_fb_levels, learned_fb_iters
+    p.stereo_init, p.stereo_levels, p.stereo_iters = stereo_init, stereo_levels, stereo_iters
     return p
 
 

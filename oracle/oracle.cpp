@@ -437,6 +437,15 @@ struct Params {
   // a star (0 -> 1, 2, 3): detection in the first camera of each group of
   // four, its new keypoints matched into the other three
   int32_t topology;
+  // learned initialisation: budget of the fallback from the constant-velocity
+  // start (0 levels = the full budget levels x gn_iters)
+  int32_t learned_fb_levels, learned_fb_iters;
+  // stereo start of a new keypoint's match: 0 = the disparity prior; 1 = the
+  // neighbour start (the previous frame's nearest keypoint of the detecting
+  // camera that also lives in the target camera lends its offset between the
+  // two cameras), refined with stereo_levels x stereo_iters; without such a
+  // keypoint the disparity prior and the full budget
+  int32_t stereo_init, stereo_levels, stereo_iters;
 };
 
 struct Record {  // 40 bytes
@@ -835,6 +844,12 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
   F.records.clear();
   F.last_fallback = 0;
   std::vector<std::vector<Record>> rec(F.n_cams);
+  // the keypoints every camera held after the previous frame (the neighbour
+  // stereo start looks them up)
+  std::vector<std::vector<Keypoint>> prev_live(F.n_cams);
+  for (int c = 0; c < F.n_cams; ++c) prev_live[c] = F.cams[c].live;
+  const int fbL = P.learned_fb_levels > 0 ? P.learned_fb_levels : L;
+  const int fbN = P.learned_fb_levels > 0 ? P.learned_fb_iters : N;
   // temporal tracking with the constant-velocity initialisation; a camera with
   // no previous frame carries its keypoints over unchanged (nothing to track
   // against) and reports no temporal records
@@ -878,12 +893,16 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
         bool done = false;
         if (learned && !predicted) {
           // the tracker refines the guess on a smaller budget; a track that is
-          // not kept, or keeps a residual above rho, falls back to the plain
-          // budget from the constant-velocity initialisation
+          // not kept, or keeps a residual above rho, falls back to the
+          // constant-velocity initialisation with the fallback budget
           const float gx = k.x + 16.f * guess[ki * MO], gy = k.y + 16.f * guess[ki * MO + 1];
           r = track<float>(cam.prev, cur[c], k.x, k.y, gx, gy, P.learned_levels, P.learned_iters, P.fb_threshold);
           done = r.status == TRACKED && r.resid <= P.learned_rho;
-          if (!done) F.last_fallback++;
+          if (!done) {
+            F.last_fallback++;
+            r = track<float>(cam.prev, cur[c], k.x, k.y, ix, iy, fbL, fbN, P.fb_threshold, ith);
+            done = true;
+          }
         }
         if (predicted && P.pred_levels > 0) {
           // a predicted start needs a smaller search range: the short budget
@@ -950,16 +969,49 @@ static void push_frame(Frontend& F, const uint8_t* const* imgs, const int32_t* s
     for (int tc = g + 1; tc < g + group; ++tc) {
       Camera& right = F.cams[tc];
       const Motion& ext = F.stereo_ext[tc];
+      // neighbour start: the keypoints of the previous frame that live in both
+      // the detecting and this camera, in id order, with their offset between
+      // the two cameras
+      struct Pair {
+        float x, y, dx, dy;
+        int64_t id;
+      };
+      std::vector<Pair> pairs;
+      if (P.stereo_init == 1 && !ext.on) {
+        const std::vector<Keypoint>& ls = prev_live[g];
+        for (const Keypoint& q : prev_live[tc]) {
+          const auto it = std::lower_bound(ls.begin(), ls.end(), q.id,
+                                           [](const Keypoint& a, int64_t id) { return a.id < id; });
+          if (it != ls.end() && it->id == q.id) pairs.push_back({it->x, it->y, q.x - it->x, q.y - it->y, q.id});
+        }
+      }
       for (const Keypoint& kp : fresh) {
-        // the disparity prior, or the projection through the rig's extrinsics (Sec. III-E)
+        // the projection through the rig's extrinsics (Sec. III-E), else the
+        // neighbour start, else the disparity prior
         float ix = kp.x - P.disparity0, iy = kp.y, ith = 0.f;
+        int sL = L, sN = N;
         double mx, my, mth;
         if (ext.on && motion_start(ext, ext.rho, kp.x, kp.y, mx, my, mth)) {
           ix = (float)mx;
           iy = (float)my;
           ith = (float)mth;
+        } else if (!pairs.empty()) {
+          // nearest by (squared distance, id)
+          size_t best = 0;
+          double bd = dist2(pairs[0].x, pairs[0].y, kp.x, kp.y);
+          for (size_t q = 1; q < pairs.size(); ++q) {
+            const double d = dist2(pairs[q].x, pairs[q].y, kp.x, kp.y);
+            if (d < bd || (d == bd && pairs[q].id < pairs[best].id)) {
+              bd = d;
+              best = q;
+            }
+          }
+          ix = kp.x + pairs[best].dx;
+          iy = kp.y + pairs[best].dy;
+          sL = P.stereo_levels;
+          sN = P.stereo_iters;
         }
-        const TrackOut<float> r = track<float>(cur[g], cur[tc], kp.x, kp.y, ix, iy, L, N, P.fb_threshold, ith);
+        const TrackOut<float> r = track<float>(cur[g], cur[tc], kp.x, kp.y, ix, iy, sL, sN, P.fb_threshold, ith);
         int st = r.status == TRACKED ? MATCHED : r.status;
         if (st == MATCHED && (int)right.live.size() >= P.max_keypoints) st = LOST_CAP;
         if (st == MATCHED) right.live.push_back({kp.id, r.x, r.y, r.x, r.y, 0});
@@ -1111,6 +1163,12 @@ void* orc_fe_create(int n_cams, const int32_t* widths, const int32_t* heights, i
   if (!p || p->struct_size != sizeof(Params) || n_cams < 1 || (stereo && n_cams % 2)) return nullptr;
   if (p->pred_levels < 0 || p->pred_levels > p->levels || (p->pred_levels > 0 && p->pred_iters < 1)) return nullptr;
   if (p->topology != 0 && p->topology != 1) return nullptr;
+  if (p->learned_fb_levels < 0 || p->learned_fb_levels > p->levels ||
+      (p->learned_fb_levels > 0 && p->learned_fb_iters < 1))
+    return nullptr;
+  if (p->stereo_init != 0 && p->stereo_init != 1) return nullptr;
+  if (p->stereo_init == 1 && (p->stereo_levels < 1 || p->stereo_levels > p->levels || p->stereo_iters < 1))
+    return nullptr;
   auto* F = new Frontend();
   F->P = *p;
   F->n_cams = n_cams;

@@ -58,6 +58,8 @@ class vio_frontend_params(ctypes.Structure):
         ("pred_levels", ctypes.c_int32), ("pred_iters", ctypes.c_int32), ("pred_rho", ctypes.c_float),
         ("topology", ctypes.c_int32),
         ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
+        ("learned_fb_levels", ctypes.c_int32), ("learned_fb_iters", ctypes.c_int32),
+        ("stereo_init", ctypes.c_int32), ("stereo_levels", ctypes.c_int32), ("stereo_iters", ctypes.c_int32),
     ]
 
 # the optional device allocator of vio_frontend_params
@@ -71,6 +73,8 @@ VIO_STEREO_SPECULATIVE = 0
 VIO_STEREO_DEFERRED = 1
 VIO_TOPOLOGY_PAIRS = 0
 VIO_TOPOLOGY_STAR = 1
+VIO_STEREO_INIT_PRIOR = 0
+VIO_STEREO_INIT_NEIGHBOUR = 1
 
 
 class vio_kp_prediction(ctypes.Structure):

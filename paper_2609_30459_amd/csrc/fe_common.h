@@ -91,6 +91,10 @@ struct CamDesc {
   int32_t* stats_out[2];             // [kCamStats] counts (CamStat)
   int rec_cap;
   int row_off;                       // first row of this camera in the learned-init feature/guess buffers
+  // target cameras with the neighbour stereo start: the keypoints that live in
+  // both this camera and its detecting camera, in id order, as (x, y) in the
+  // detecting camera and the offset to this camera, by frame parity [cap]
+  float4* pairs[2];
 };
 
 // Per-camera counts of a frame, written by the selection kernel into mapped
@@ -144,6 +148,7 @@ struct Counters {
   // selection phase, matched by the second tracking launch)
   int32_t sel_base[kMaxCams];
   int32_t n_sel[kMaxCams];
+  int32_t n_pairs[2][kMaxCams];  // entries of CamDesc::pairs, [parity][target camera]
 };
 
 // Per-keypoint inverse depth of the camera-model start, 16 bytes.
@@ -165,6 +170,9 @@ struct Tuning {
   const KpDepth* depths;  // per-keypoint inverse depths of the camera-model start (FrameCam ranges)
   int plevels, piters;    // short budget of predicted tracks (plevels 0: none)
   float prho;             // residual RMS above which a predicted short track falls back
+  int fblevels, fbiters;  // budget of a learned track's fallback from the constant-velocity start
+  int stereo_nb;          // stereo matches start from the nearest paired keypoint's offset
+  int slevels, siters;    // budget of such a match
 };
 
 // Learned-initialisation network on the device (see vio_mlp.h).

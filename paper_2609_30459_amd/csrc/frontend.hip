@@ -224,6 +224,15 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   if (p->pred_levels > 0 && (p->pred_iters < 1 || p->pred_iters > 32))
     return why = "pred_iters out of 1..32", VIO_EINVAL;
   if (std::isnan(p->pred_rho)) return why = "pred_rho is NaN", VIO_EINVAL;
+  if (p->learned_fb_levels < 0 || p->learned_fb_levels > p->levels)
+    return why = "learned_fb_levels out of 0..levels", VIO_EINVAL;
+  if (p->learned_fb_levels > 0 && (p->learned_fb_iters < 1 || p->learned_fb_iters > 32))
+    return why = "learned_fb_iters out of 1..32", VIO_EINVAL;
+  if (p->stereo_init != VIO_STEREO_INIT_PRIOR && p->stereo_init != VIO_STEREO_INIT_NEIGHBOUR)
+    return why = "stereo_init must be VIO_STEREO_INIT_PRIOR or VIO_STEREO_INIT_NEIGHBOUR", VIO_EINVAL;
+  if (p->stereo_init == VIO_STEREO_INIT_NEIGHBOUR &&
+      (p->stereo_levels < 1 || p->stereo_levels > p->levels || p->stereo_iters < 1 || p->stereo_iters > 32))
+    return why = "stereo_levels out of 1..levels or stereo_iters out of 1..32", VIO_EINVAL;
   return VIO_OK;
 }
 
@@ -252,6 +261,9 @@ void vio_frontend_default_params(vio_frontend_params* p) {
   p->learned_levels = 2;
   p->learned_iters = 3;
   p->learned_rho = 0.f;
+  p->stereo_init = VIO_STEREO_INIT_PRIOR;
+  p->stereo_levels = 2;
+  p->stereo_iters = 3;
 }
 
 void vio_frontend_destroy(vio_frontend* h) {
@@ -299,7 +311,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     return o;
   };
   struct CamOffs {
-    size_t lvl[3][kMaxLevels], state[2], res, keys[3], sres, rec, mask;
+    size_t lvl[3][kMaxLevels], state[2], res, keys[3], sres, rec, mask, pairs[2];
   };
   std::vector<CamOffs> co(n_cams);
   int cam = 0, tiles = 0, rows_total = 0, items = 0;
@@ -353,6 +365,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
         for (int ps = 0; ps < 3; ++ps) co[cam].keys[ps] = take(sizeof(uint32_t) * c.nslots);
         co[cam].sres = take(sizeof(TrackRes) * c.nslots * std::max(1, c.n_targets));
         co[cam].mask = take((size_t)si.w * si.h);
+      } else if (P.stereo_init == VIO_STEREO_INIT_NEIGHBOUR && group > 1) {
+        for (int par = 0; par < 2; ++par) co[cam].pairs[par] = take(sizeof(float4) * si.cap);
       }
       c.rec_cap = 2 * si.cap;
       c.row_off = rows_total;
@@ -466,6 +480,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       for (int ps = 0; ps < 3; ++ps) d.keys[ps] = reinterpret_cast<uint32_t*>(base + co[c].keys[ps]);
       d.sres = reinterpret_cast<TrackRes*>(base + co[c].sres);
       d.mask = reinterpret_cast<const uint8_t*>(base + co[c].mask);
+    } else if (co[c].pairs[0]) {
+      for (int par = 0; par < 2; ++par) d.pairs[par] = reinterpret_cast<float4*>(base + co[c].pairs[par]);
     }
   }
   h->d_cams = reinterpret_cast<CamDesc*>(base + o_cams);
@@ -597,6 +613,11 @@ static Tuning tuning(const vio_frontend* h) {
   t.plevels = h->P.pred_levels;
   t.piters = h->P.pred_iters;
   t.prho = h->P.pred_rho;
+  t.fblevels = h->P.learned_fb_levels > 0 ? h->P.learned_fb_levels : h->P.levels;
+  t.fbiters = h->P.learned_fb_levels > 0 ? h->P.learned_fb_iters : h->P.gn_iters;
+  t.stereo_nb = h->P.stereo_init == VIO_STEREO_INIT_NEIGHBOUR ? 1 : 0;
+  t.slevels = h->P.stereo_levels;
+  t.siters = h->P.stereo_iters;
   return t;
 }
 
@@ -1315,6 +1336,42 @@ int vio_frontend_get_tracks_streams(vio_frontend* h, int32_t n, const int32_t* s
 
 static int state_slot(const StreamInfo& si) { return (int)((si.frames & 1) ^ 1); }
 
+// The neighbour stereo start's pair tables of stream s's target cameras, from
+// the states the next frame reads (slot): the selection kernel keeps them
+// after every frame; a host upload of keypoints rebuilds them here, in the
+// same order (the target camera's keypoints in id order that also live in
+// its detecting camera).
+static int rebuild_pairs(vio_frontend* h, int s, int slot) {
+  if (h->P.stereo_init != VIO_STEREO_INIT_NEIGHBOUR) return VIO_OK;
+  const StreamInfo& si = h->streams[s];
+  for (int k = 0; k < si.n_cams; ++k) {
+    const int lc = si.first_cam + k;
+    const CamDesc& L = h->cams[lc];
+    if (!L.detect || L.n_targets == 0) continue;
+    int32_t nl = 0;
+    HIP_CHECK(h, hipMemcpy(&nl, &h->d_cnt->n_live[slot][lc], sizeof nl, hipMemcpyDeviceToHost));
+    std::vector<Kp> ls((size_t)nl);
+    if (nl > 0) HIP_CHECK(h, hipMemcpy(ls.data(), L.state[slot], sizeof(Kp) * nl, hipMemcpyDeviceToHost));
+    for (int t = 0; t < L.n_targets; ++t) {
+      const int rc = lc + 1 + t;
+      const CamDesc& R = h->cams[rc];
+      int32_t nr = 0;
+      HIP_CHECK(h, hipMemcpy(&nr, &h->d_cnt->n_live[slot][rc], sizeof nr, hipMemcpyDeviceToHost));
+      std::vector<Kp> rs((size_t)nr);
+      if (nr > 0) HIP_CHECK(h, hipMemcpy(rs.data(), R.state[slot], sizeof(Kp) * nr, hipMemcpyDeviceToHost));
+      std::vector<float4> pr;
+      for (const Kp& q : rs) {
+        const auto it = std::lower_bound(ls.begin(), ls.end(), q.id, [](const Kp& a, int64_t id) { return a.id < id; });
+        if (it != ls.end() && it->id == q.id) pr.push_back(make_float4(it->x, it->y, q.x - it->x, q.y - it->y));
+      }
+      const int32_t np = (int32_t)pr.size();
+      if (np > 0) HIP_CHECK(h, hipMemcpy(R.pairs[slot], pr.data(), sizeof(float4) * np, hipMemcpyHostToDevice));
+      HIP_CHECK(h, hipMemcpy(&h->d_cnt->n_pairs[slot][rc], &np, sizeof np, hipMemcpyHostToDevice));
+    }
+  }
+  return VIO_OK;
+}
+
 int vio_frontend_set_keypoints(vio_frontend* h, int32_t s, int32_t camera, const vio_keypoint* kps, int32_t n) {
   if (!h) return VIO_EINVAL;
   if (h->poisoned) return VIO_EDEVICE;
@@ -1337,7 +1394,7 @@ int vio_frontend_set_keypoints(vio_frontend* h, int32_t s, int32_t camera, const
   HIP_CHECK(h, hipMemcpy(&next, &h->d_cnt->next_id[s], sizeof next, hipMemcpyDeviceToHost));
   next = std::max(next, max_id + 1);
   HIP_CHECK(h, hipMemcpy(&h->d_cnt->next_id[s], &next, sizeof next, hipMemcpyHostToDevice));
-  return VIO_OK;
+  return rebuild_pairs(h, s, slot);
 }
 
 int vio_frontend_get_keypoints(vio_frontend* h, int32_t s, int32_t camera, vio_keypoint* out, int32_t capacity,

@@ -163,9 +163,9 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
 // after its n_surv_r survivors and n_rec_r temporal records. sres(i): the
 // match of detection i.
 template <class SresOf>
-__device__ void accept_matches(const CamDesc& L, int P, int sel_base, const CamDesc& R, const FrameCam& fr,
-                               int rc, int n_new, int n_surv_r, int n_rec_r, SresOf sres, Counters* cnt,
-                               Scan& sc) {
+__device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDesc& R, const FrameCam& fr,
+                              int rc, int n_new, int n_surv_r, int n_rec_r, SresOf sres, Counters* cnt,
+                              Scan& sc) {
   const int PR = fr.parity;
   int m_base = 0;
   for (int i0 = 0; i0 < n_new; i0 += kSelectThreads) {
@@ -188,13 +188,48 @@ __device__ void accept_matches(const CamDesc& L, int P, int sel_base, const CamD
     }
     m_base += m_tot;
   }
+  const int accepted = min(m_base, max(0, R.cap - n_surv_r));
   if (threadIdx.x == 0) {
-    const int accepted = min(m_base, max(0, R.cap - n_surv_r));
     cnt->n_live[PR][rc] = n_surv_r + accepted;
     cnt->rec_count[rc] = n_rec_r + n_new;
     *R.rec_count_out[PR] = n_rec_r + n_new;
     R.stats_out[PR][kStatMatched] = accepted;
   }
+  return n_surv_r + accepted;
+}
+
+// The neighbour stereo start's table of target camera R (parity PR): its
+// n_right keypoints, in id order, that also live among detecting camera L's
+// n_left keypoints (parity P; both states are sorted by id), as L's position
+// and the offset from L to R. The next frame's stereo matches into R read it.
+__device__ void build_pairs(const CamDesc& L, int P, int n_left, const CamDesc& R, int PR, int rc, int n_right,
+                            Counters* cnt, Scan& sc) {
+  int base = 0;
+  for (int i0 = 0; i0 < n_right; i0 += kSelectThreads) {
+    const int i = i0 + (int)threadIdx.x;
+    bool found = false;
+    float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < n_right) {
+      const Kp q = R.state[PR][i];
+      int lo = 0, hi = n_left - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const Kp l = L.state[P][mid];
+        if (l.id == q.id) {
+          e = make_float4(l.x, l.y, q.x - l.x, q.y - l.y);
+          found = true;
+          break;
+        }
+        if (l.id < q.id) lo = mid + 1;
+        else hi = mid - 1;
+      }
+    }
+    int total;
+    const int pos = base + block_scan_flag(found, sc, total);
+    if (found) R.pairs[PR][pos] = e;
+    base += total;
+  }
+  if (threadIdx.x == 0) cnt->n_pairs[PR][rc] = base;
 }
 
 __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __restrict__ cams,
@@ -224,9 +259,13 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         const int PR = fr.parity;
         const int n_rec_r = fr.has_prev ? cnt->n_live[PR ^ 1][rc] : 0;
         const TrackRes* sr = L.sres + (size_t)t * L.nslots;
-        accept_matches(L, P, cnt->sel_base[lc], cams[rc], fr, rc, cnt->n_sel[lc], cnt->n_live[PR][rc], n_rec_r,
-                       [&](int i) { return sr[i]; }, cnt, sc);
+        const int n_r = accept_matches(L, P, cnt->sel_base[lc], cams[rc], fr, rc, cnt->n_sel[lc],
+                                       cnt->n_live[PR][rc], n_rec_r, [&](int i) { return sr[i]; }, cnt, sc);
         __syncthreads();
+        if (tune.stereo_nb) {
+          build_pairs(L, P, cnt->sel_base[lc] + cnt->n_sel[lc], cams[rc], PR, rc, n_r, cnt, sc);
+          __syncthreads();
+        }
       }
     }
     return;
@@ -340,8 +379,12 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, count_fb);
       if (phase == kSelectAll) {
         const TrackRes* sr = L.sres + (size_t)t * nslots;
-        accept_matches(L, P, n_surv, R, fr, rc, n_new, n_surv_r, n_rec_r, [&](int i) { return sr[s_sel[i]]; },
-                       cnt, sc);
+        const int n_r = accept_matches(L, P, n_surv, R, fr, rc, n_new, n_surv_r, n_rec_r,
+                                       [&](int i) { return sr[s_sel[i]]; }, cnt, sc);
+        if (tune.stereo_nb) {
+          __syncthreads();
+          build_pairs(L, P, n_surv + n_new, R, PR, rc, n_r, cnt, sc);
+        }
       } else if (threadIdx.x == 0) {
         // the matches come from the stereo tracking launch; kSelectRight appends them
         cnt->sel_base[lc] = n_surv;

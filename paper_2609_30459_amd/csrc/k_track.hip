@@ -523,7 +523,12 @@ __device__ __forceinline__ void store_result(TrackRes* dst, const TrackRes& r, i
 // tune.liters iterations from the network's guess, and a predicted one runs
 // tune.plevels x tune.piters from its prediction when tune.plevels > 0.
 // Otherwise, and whenever the short attempt does not hold, the full budget
-// runs from the track's start (pad[0] = 1 marks such a fallback).
+// runs from the track's start (pad[0] = 1 marks such a fallback); a learned
+// track's fallback from the constant-velocity start runs tune.fblevels x
+// tune.fbiters. A stereo match starts from the rig's extrinsics when the
+// target camera has them, else (tune.stereo_nb) from the nearest paired
+// keypoint's offset with tune.slevels x tune.siters, else from the disparity
+// prior with the full budget.
 template <int L>
 __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
                                              const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
@@ -551,6 +556,8 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   // tracked with a residual RMS <= srho, else the full budget from (ix, iy, ith)
   float px, py, ix, iy, ith = 0.f, gx = 0.f, gy = 0.f, gth = 0.f, srho = 0.f;
   int sl = 0, si = 0;
+  // the budget of the attempt from (ix, iy, ith): the full one unless stated
+  int fl = tune.levels, fi = tune.iters;
   bool try_short = false;
   TrackRes* out;
   if (sg.mode == kModeTemporal) {
@@ -625,6 +632,9 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       si = tune.liters;
       srho = tune.rho;
       try_short = true;
+      // the fallback from the constant-velocity start has its own budget
+      fl = tune.fblevels;
+      fi = tune.fbiters;
     }
     if (predicted && tune.plevels > 0) {
       // a predicted start needs a smaller search range: the short budget
@@ -659,9 +669,50 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       px = (float)(idx % cd.w);
       py = (float)(idx / cd.w);
     }
-    dst = &cams[c + 1 + t];
+    const int tc = c + 1 + t;
+    dst = &cams[tc];
     ix = px - tune.disparity0;
     iy = py;
+    if (tune.stereo_nb && !dst->has_ext) {
+      // neighbour start: of the keypoints that after the previous frame lived
+      // in both cameras (the target's pair table, id order), the nearest by
+      // (squared distance in double, where the float differences and squares
+      // are exact, then id) lends its offset; one candidate per lane per
+      // round, then a wave minimum
+      const int Pq = frame->cam[tc].parity ^ 1;
+      const int np = __builtin_amdgcn_readfirstlane(cnt->n_pairs[Pq][tc]);  // wave-uniform trip count
+      if (np > 0) {
+        const float4* pt = dst->pairs[Pq];
+        double bd = INFINITY;
+        int bi = 0x7FFFFFFF;
+        for (int q0 = 0; q0 < np; q0 += kW) {
+          const int q = q0 + lane;
+          if (q < np) {
+            const float4 e = pt[q];
+            const double dx = (double)e.x - (double)px, dy = (double)e.y - (double)py;
+            const double d = dx * dx + dy * dy;
+            if (d < bd) {  // q ascends per lane: an equal distance keeps the smaller index
+              bd = d;
+              bi = q;
+            }
+          }
+        }
+#pragma unroll
+        for (int o = kW / 2; o > 0; o >>= 1) {
+          const double od = __shfl_xor(bd, o);
+          const int oi = __shfl_xor(bi, o);
+          if (od < bd || (od == bd && oi < bi)) {
+            bd = od;
+            bi = oi;
+          }
+        }
+        const float4 e = pt[__builtin_amdgcn_readfirstlane(bi)];
+        ix = px + e.z;
+        iy = py + e.w;
+        fl = tune.slevels;
+        fi = tune.siters;
+      }
+    }
     if (dst->has_ext) {
       // the rig's extrinsics (Sec. III-E's camera-model start): back-project
       // through the detecting camera at the default inverse depth, move,
@@ -699,7 +750,7 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   for (int a = try_short ? 0 : 1; a < 2; ++a) {
     const bool short_run = a == 0;
     r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy, short_run ? gth : ith,
-                    short_run ? sl : tune.levels, short_run ? si : tune.iters, tune.fb_threshold, u, v, wgt, lane);
+                    short_run ? sl : fl, short_run ? si : fi, tune.fb_threshold, u, v, wgt, lane);
     if (short_run) {
       if (r.status == VIO_TRACKED && r.resid <= srho) break;
       fell_back = 1;

@@ -250,8 +250,10 @@ def run_pair(workload, seq, n_frames, inject_state=True, params_overrides=None, 
                 return _track_fp64(seq.frames, t, o, prev, idx, L, N, fb, d0, motion)
 
             # the FP64 referee rebuilds constant-velocity and camera-model starts
-            # (not the short budgets of learned or predicted tracks)
-            learned = po.get("init_mode", 0) != 0 or po.get("pred_levels", 0) > 0
+            # (not the short budgets of learned or predicted tracks, nor the
+            # neighbour stereo start)
+            learned = (po.get("init_mode", 0) != 0 or po.get("pred_levels", 0) > 0 or
+                       po.get("stereo_init", 0) != 0)
             exc = compare_records(g, o, workload.fb_threshold, where=f"{workload.name} frame {t}",
                                   referee=None if learned else referee, tally=tally)
             yield t, g, o, exc, fe_g, fe_o

@@ -138,12 +138,12 @@ def _learned_params(w, rho, levels=2, iters=3):
     return dict(init_mode=1, learned_levels=levels, learned_iters=iters, learned_rho=rho)
 
 
-def _learned_run(w, seq, P, rho, launch, frames, where):
+def _learned_run(w, seq, P, rho, launch, frames, where, extra=None):
     """Learned-init GPU frontend against the oracle with state injection: records,
     features (bit-exact) and fallback counts (exact) per frame; returns the
-    total fallbacks."""
+    total fallbacks. extra: further parameters for both sides."""
     import paper_2609_30459_amd as vf
-    po = _learned_params(w, rho)
+    po = {**_learned_params(w, rho), **(extra or {})}
     fe_o = oracle.Frontend([w.width] * w.n_cams, [w.height] * w.n_cams, w.stereo, oracle.params_for(w, **po))
     fe_o.set_mlp(P)
     n_fb = 0
@@ -175,14 +175,20 @@ def _learned_run(w, seq, P, rho, launch, frames, where):
     return n_fb
 
 
-@pytest.mark.parametrize("rho,launch", [(-1.0, {}), (0.02, {}), (1e9, {}), (0.02, {"eager": True}),
-                                        (0.02, {"stereo_mode": 1, "track_waves_per_cu": 4})])
-def test_learned_pipeline_parity_and_features(rho, launch):
+FB25 = dict(learned_fb_levels=2, learned_fb_iters=5)
+NB23 = dict(stereo_init=1, stereo_levels=2, stereo_iters=3)
+
+
+@pytest.mark.parametrize("rho,launch,extra", [(-1.0, {}, {}), (0.02, {}, {}), (1e9, {}, {}), (0.02, {"eager": True}, {}),
+                                              (0.02, {"stereo_mode": 1, "track_waves_per_cu": 4}, {}),
+                                              (-1.0, {}, FB25), (0.02, {}, {**FB25, **NB23}),
+                                              (0.02, {"stereo_mode": 1}, {**FB25, **NB23})])
+def test_learned_pipeline_parity_and_features(rho, launch, extra):
     w = synthgen.WORKLOADS["stereo752"]
     seq = synthgen.sequence(w, seq=7, n_frames=4)
     P = oracle.mlp_init(13) * 0.05
     P[-3:] = 0.0
-    n_fb = _learned_run(w, seq, P, rho, launch, 4, f"learned stereo752 rho={rho} {launch}")
+    n_fb = _learned_run(w, seq, P, rho, launch, 4, f"learned stereo752 rho={rho} {launch} {extra}", extra)
     if rho < 0:
         assert n_fb > 0
 
@@ -199,5 +205,9 @@ def test_learned_pipeline_parity_trained_weights_stereo1280():
     seq = synthgen.sequence(w, seq=3, n_frames=5)
     n_fb = _learned_run(w, seq, P, rho, {}, 5, "learned stereo1280 trained weights")
     assert n_fb > 0  # the fallback path is exercised
+    # the benchmark's learned configuration: 2 x 5 fallback, neighbour stereo start
+    n_fb = _learned_run(w, seq, P, rho, {}, 5, "learned stereo1280 trained weights, 2x5 fallback, neighbour stereo",
+                        {**FB25, **NB23})
+    assert n_fb > 0
 
 
