@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--learned-stereo", choices=["prior", "neighbour"], default="neighbour",
                     help="learned leg: stereo matches start from the nearest paired keypoint's offset (neighbour) "
                          "or from the disparity prior")
+    ap.add_argument("--parallel-fallback", type=int, choices=[0, 1], default=None,
+                    help="learned leg: fallbacks computed beside the short attempts (1) or after them (0); "
+                         "default: the autotuned choice, else 1 for one stream and 0 for batches")
     ap.add_argument("--stereo-levels", type=int, default=2, help="budget of neighbour-started stereo matches")
     ap.add_argument("--stereo-iters", type=int, default=3)
     ap.add_argument("--waves-per-cu", type=int, default=None,
@@ -218,6 +221,7 @@ def main():
     def launch_choice(init):
         """Launch parameters (never change the records): explicit flags, else the autotuned choice."""
         wpc, bw, tile, smode = args.waves_per_cu, args.block_waves, args.tile, args.stereo_mode
+        pfb = args.parallel_fallback
         tuned = None
         if wpc is None and bw is None and tile is None and smode is None:
             from paper_2609_30459_amd import autotune
@@ -225,8 +229,13 @@ def main():
             if tuned:
                 wpc, bw = tuned["track_waves_per_cu"], tuned["track_block_waves"]
                 tile, smode = tuned.get("pyr_tile", 64), tuned.get("stereo_mode", 0)
+                if pfb is None and "track_parallel_fallback" in tuned:
+                    pfb = tuned["track_parallel_fallback"]
+        if pfb is None:
+            pfb = 0 if batched else 1
         return dict(track_waves_per_cu=wpc or 0, track_block_waves=bw or 4, pyr_tile=tile or 64,
-                    stereo_mode=smode or 0), tuned is not None
+                    stereo_mode=smode or 0, track_parallel_fallback=pfb if init == "learned" else 0), \
+            tuned is not None
 
     mlp = None
     if "learned" in inits:
@@ -328,19 +337,20 @@ def main():
         log(f"{init}: timing {args.steps} steps")
         gc.collect()
         gc.disable()  # no garbage-collector pause inside the timed steps
+        # the production region reads only the records; the eager region also
+        # each frame's statistics (kernel times, device time, fallbacks)
         t0 = time.perf_counter()
         for t in range(warmup, n_frames):
             submit(t)
             if pipelined:
                 if t > warmup:
                     wall.append(collect(t - 1))
-                    stats.append(fe.stats())
             else:
                 wall.append(collect(t))
-                stats.append(fe.stats())
+                if eager:
+                    stats.append(fe.stats())
         if pipelined:
             wall.append(collect(n_frames - 1))
-            stats.append(fe.stats())
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         gc.enable()
@@ -382,23 +392,25 @@ def main():
         first_eager = args.launch == "eager"
         records, wall, stats, elapsed = timed_run(init, first_eager)
         steps_per_s = args.steps / elapsed
-        fallbacks = np.array([s_["last_fallback"] for s_ in stats], np.float64)
         second, eager_stats = None, stats if first_eager else None
         if not args.no_second:
             rec2, wall2, stats2, elapsed2 = timed_run(init, not first_eager)
             same = all(a.tobytes() == b.tobytes() for ra, rb in zip(records, rec2) for a, b in zip(ra, rb))
             second = {"launch": "graph" if first_eager else "eager",
                       "value": args.steps * len(ws) / elapsed2, "ms_per_step": 1000.0 * elapsed2 / args.steps,
-                      "gpu_ms_per_step": float(np.mean([s_["last_gpu_ms"] for s_ in stats2])),
+                      "gpu_ms_per_step": float(np.mean([s_["last_gpu_ms"] for s_ in stats2])) if stats2 else None,
                       "latency_p50_ms": float(np.percentile(np.array(wall2) * 1e3, 50)),
                       "latency_p99_ms": float(np.percentile(np.array(wall2) * 1e3, 99)),
                       "records_identical": bool(same)}
             if not first_eager:
                 eager_stats = stats2
-        kstats = eager_stats if eager_stats is not None else stats
-        # [steps, 6]: pyramid+detector, tracker, selection, learned features, network, whole frame
-        sm = np.array([s_["last_stage_ms"] + s_["last_learned_ms"] + [f_["last_gpu_ms"]]
-                       for s_, f_ in zip(kstats, stats)])
+        # per-frame statistics of the eager region (the same records as the
+        # first region, so the same fallbacks); [steps, 6]: pyramid+detector,
+        # tracker, selection, learned stage, (unused), whole frame
+        kstats = eager_stats or [{"last_stage_ms": [-1.0] * 3, "last_learned_ms": [-1.0] * 2, "last_gpu_ms": -1.0,
+                                  "last_fallback": 0}]
+        fallbacks = np.array([s_["last_fallback"] for s_ in kstats], np.float64)
+        sm = np.array([s_["last_stage_ms"] + s_["last_learned_ms"] + [s_["last_gpu_ms"]] for s_ in kstats])
         mean_ms = sm.mean(0)
         have_times = bool((sm[:, :3] >= 0).all())
 
@@ -486,7 +498,8 @@ def main():
                         "rho": mlp[1], "weights": mlp[2]} if init == "learned"
                        else {"levels": L, "iters": N, "stereo_start": "prior"}),
             "launch": {**{k: v for k, v in extra.items() if k in ("track_waves_per_cu", "track_block_waves",
-                                                                   "pyr_tile", "stereo_mode")},
+                                                                   "pyr_tile", "stereo_mode",
+                                                                   "track_parallel_fallback")},
                        "autotuned": tuned},
             "roofline": roof, "second_launch": second, "kernels": kernels,
             "host_image": None if args.no_host_leg else host_run(init),

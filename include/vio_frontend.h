@@ -143,6 +143,13 @@ typedef struct vio_frontend_params {
   int32_t stereo_init;
   int32_t stereo_levels;
   int32_t stereo_iters;
+  /* Launch choice that never changes the records: 1 = a track that first runs a
+   * short budget (learned guess or predicted start) has its fallback computed at
+   * the same time by a second wave, and the selection takes it when the short
+   * track is not kept (one frame's tracker chain is then the longer of the two,
+   * not their sum, for up to twice the tracker work); 0 = the fallback runs after
+   * the short attempt in the same wave. */
+  int32_t track_parallel_fallback;
 } vio_frontend_params;
 
 #define VIO_STEREO_INIT_PRIOR 0
@@ -226,13 +233,15 @@ typedef struct vio_kp_depth {
 
 typedef struct vio_stats {
   int64_t frames;        /* frames processed by the handle */
-  double last_gpu_ms;    /* device time of the last completed frame, from its frame-table copy to its
-                            selection (with frames in flight it overlaps the neighbouring frames') */
+  double last_gpu_ms;    /* device time of the last completed frame, from the start of its pyramid to its
+                            selection (with frames in flight it overlaps the neighbouring frames'); -1 with
+                            VIO_FLAG_PLAIN (no timestamps) */
   double last_stage_ms[3]; /* durations of the last frame's pyramid+detector, tracker and selection
                               kernels from their own dispatch timestamps (HIP events attached to the
                               launch); -1 unless launched one by one (VIO_FLAG_EAGER) */
-  double last_learned_ms[2]; /* the same for the learned initialisation's feature and network
-                                kernels; -1 otherwise */
+  double last_learned_ms[2]; /* the same for the learned initialisation's kernel (features and
+                                network in one launch) in [0]; [1] is -1 (the neighbour grids are
+                                built by the selection kernel) */
   int32_t last_tracked;  /* VIO_TRACKED records of the last frame, all cameras */
   int32_t last_lost;     /* lost temporal records of the last frame */
   int32_t last_detected; /* VIO_DETECTED records */

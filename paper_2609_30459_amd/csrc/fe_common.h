@@ -81,6 +81,7 @@ struct CamDesc {
                                      // is built while the last two frames' are still read)
   Kp* state[2];                      // keypoint state, double-buffered by frame parity
   TrackRes* res;                     // temporal results [cap]
+  TrackRes* res_fb;                  // parallel fallbacks of short temporal attempts [cap] (or null)
   uint32_t* keys[3];                 // packed winner keys, slot cell * k + rank, by pyramid slot [nslots]
   TrackRes* sres;                    // stereo matches [n_targets][nslots], by key slot or selection rank
   const uint8_t* mask;               // detection mask [h][w] (detecting cameras)
@@ -173,6 +174,7 @@ struct Tuning {
   int fblevels, fbiters;  // budget of a learned track's fallback from the constant-velocity start
   int stereo_nb;          // stereo matches start from the nearest paired keypoint's offset
   int slevels, siters;    // budget of such a match
+  int par_fb;             // short temporal attempts' fallbacks run as items of their own (CamDesc::res_fb)
 };
 
 // Learned-initialisation network on the device (see vio_mlp.h).
@@ -187,7 +189,9 @@ struct MlpDev {
 };
 
 // Work items of the tracking kernel: one segment per (camera, mode).
-enum : int { kModeTemporal = 0, kModeStereo = 1 };
+// kModeFallback: the fallback attempt of temporal item j, run beside it
+// (parallel fallbacks), into CamDesc::res_fb[j].
+enum : int { kModeTemporal = 0, kModeStereo = 1, kModeFallback = 2 };
 struct TrackSeg {
   int cam, mode, begin, count;
 };
@@ -198,11 +202,15 @@ struct Prediction {
 };
 
 // ---- launchers (defined in the kernel translation units) ----
-// Pyramid + detector over tiles [tile_base, tile_base + n_tiles) of cameras
-// [cam_begin, cam_end); tile: the level-0 tile edge the cameras' tile grids use (32 or 64).
-hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end,
-                                   int tile_base, int n_tiles, int levels, int tile, int tmin, int margin,
-                                   hipStream_t s);
+// Pyramid + detector over tiles [tile_base, tile_base + n_tiles) (at least
+// one) of cameras [cam_begin, cam_end); tile: the level-0 tile edge the
+// cameras' tile grids use (32 or 64). h_frame: the frame's table, mapped
+// pinned host memory, which the kernel reads and whose first copy_bytes (a
+// multiple of 4) its first workgroup copies to d_frame for the frame's later
+// kernels.
+hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* h_frame, FrameTable* d_frame,
+                                   int copy_bytes, int cam_begin, int cam_end, int tile_base, int n_tiles, int levels,
+                                   int tile, int tmin, int margin, hipStream_t s);
 size_t pyr_detect_lds_bytes(int levels, int tile);
 // Tracking work items [item_base, item_base + n_items) over the segments
 // d_segs[0..n_segs) (segment begins are global item indices). waves_per_cu = 0
@@ -218,24 +226,11 @@ struct TrackShape {
 hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
                         int n_segs, int item_base, int n_items, const Prediction* d_pred, Tuning tune,
                         TrackShape shape, hipStream_t s);
-// Neighbour grids of the learned init's features, per camera c: hdr[c] =
-// (cell edge px, cells x, cells y, 0), start[c][0 .. cells] the first slot of
-// each cell (row-major), pos/idx[row_off .. row_off + cap) the position and
-// state index of the tracks with a flow, by cell.
-constexpr int kFeatGridMax = 1024;
-struct FeatGrid {
-  int4* hdr;
-  int* start;  // [cameras][kFeatGridMax + 1]
-  float2* pos;
-  int* idx;
-};
-// Builds the grids of cameras [cam_begin, cam_end) from their previous keypoints.
-hipError_t launch_grid(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt, int cam_begin,
-                       int cam_end, const FeatGrid& fg, hipStream_t s);
-// Features of cameras [cam_begin, cam_end) from their grids; h_cams: host copy of the descriptors (caps).
-hipError_t launch_features(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt,
-                           const CamDesc* h_cams, int cam_begin, int cam_end, const FeatGrid& fg, float* d_feat,
-                           hipStream_t s);
+// Features (into d_feat) and network outputs (into d_guess) of the previous
+// keypoints of cameras [cam_begin, cam_end); h_cams: host copy of the
+// descriptors (caps).
+hipError_t launch_learn(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt, const CamDesc* h_cams,
+                        int cam_begin, int cam_end, const MlpDev& M, float* d_feat, float* d_guess, hipStream_t s);
 hipError_t mlp_forward_launch(const MlpDev& M, const float* X, int K, float* Y, hipStream_t s);
 hipError_t mlp_pack_launch(const MlpDev& M, hipStream_t s);
 // Selection phases: kSelectAll (speculative stereo: everything in one

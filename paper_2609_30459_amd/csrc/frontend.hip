@@ -125,7 +125,6 @@ struct vio_frontend {
   bool learned = false, mlp_ready = false;
   MlpDev mlp{};
   float* d_feat = nullptr;   // [rows][32]
-  FeatGrid grid{};           // neighbour grids of the features
   float* d_guess = nullptr;  // [rows][3]
   int32_t* h_camstats = nullptr;  // [parity][cameras][kCamStats], written by the selection kernel
   // pinned host
@@ -136,6 +135,8 @@ struct vio_frontend {
   // each camera's frame parity instead.
   FrameTable* h_frames[2] = {nullptr, nullptr};
   FrameTable* h_frame = nullptr;  // h_frames[sub & 1]
+  FrameTable* hm_frames[2] = {nullptr, nullptr};  // device mappings of h_frames
+  FrameTable* hm_frame = nullptr;                 // the slot being launched
   int64_t sub = 0;                // submissions so far
   struct Pending {
     LaunchSet ls;
@@ -152,7 +153,7 @@ struct vio_frontend {
   KpDepth* h_depth = nullptr;    // [slot][pred_cap]
   hipStream_t stream = nullptr;   // the launch stream: learned stage, tracking, selection
   hipStream_t pstream = nullptr;  // frame-table copies and pyramids/detections
-  hipEvent_t ev_copy[2] = {}, ev_pyr[2] = {}, ev_in = nullptr;  // per slot: copy and pyramid done
+  hipEvent_t ev_pyr[2] = {}, ev_in = nullptr;  // per slot: pyramid done; a caller stream's images ready
   hipEvent_t ev[2][2] = {};  // per submission slot: frame start and end on the launch stream
   // eager launches: start/stop events attached to each kernel's dispatch
   // (pyramid+detector, features, network, tracker, selection)
@@ -233,6 +234,8 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   if (p->stereo_init == VIO_STEREO_INIT_NEIGHBOUR &&
       (p->stereo_levels < 1 || p->stereo_levels > p->levels || p->stereo_iters < 1 || p->stereo_iters > 32))
     return why = "stereo_levels out of 1..levels or stereo_iters out of 1..32", VIO_EINVAL;
+  if (p->track_parallel_fallback != 0 && p->track_parallel_fallback != 1)
+    return why = "track_parallel_fallback must be 0 or 1", VIO_EINVAL;
   return VIO_OK;
 }
 
@@ -289,7 +292,6 @@ void vio_frontend_destroy(vio_frontend* h) {
     for (hipEvent_t& e : pr)
       if (e) (void)hipEventDestroy(e);
   for (int slot = 0; slot < 2; ++slot) {
-    if (h->ev_copy[slot]) (void)hipEventDestroy(h->ev_copy[slot]);
     if (h->ev_pyr[slot]) (void)hipEventDestroy(h->ev_pyr[slot]);
   }
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
@@ -311,8 +313,10 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     return o;
   };
   struct CamOffs {
-    size_t lvl[3][kMaxLevels], state[2], res, keys[3], sres, rec, mask, pairs[2];
+    size_t lvl[3][kMaxLevels], state[2], res, res_fb, keys[3], sres, rec, mask, pairs[2];
   };
+  // parallel fallbacks exist where a temporal track may first run a short budget
+  const bool par_fb = P.track_parallel_fallback && (P.init_mode == VIO_INIT_LEARNED || P.pred_levels > 0);
   std::vector<CamOffs> co(n_cams);
   int cam = 0, tiles = 0, rows_total = 0, items = 0;
   size_t rec_total = 0, stage = 0;
@@ -361,6 +365,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       }
       for (int par = 0; par < 2; ++par) co[cam].state[par] = take(sizeof(Kp) * si.cap);
       co[cam].res = take(sizeof(TrackRes) * si.cap);
+      if (par_fb) co[cam].res_fb = take(sizeof(TrackRes) * si.cap);
       if (c.detect) {
         for (int ps = 0; ps < 3; ++ps) co[cam].keys[ps] = take(sizeof(uint32_t) * c.nslots);
         co[cam].sres = take(sizeof(TrackRes) * c.nslots * std::max(1, c.n_targets));
@@ -389,8 +394,9 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
         si.st_items += n;
       }
     }
-    for (int k = 0; k < si.n_cams; ++k) {
-      h->segs.push_back({si.first_cam + k, kModeTemporal, items, si.cap});
+    for (int k = 0; k < si.n_cams * (par_fb ? 2 : 1); ++k) {
+      // temporal tracks of every camera, then (parallel fallbacks) their fallbacks
+      h->segs.push_back({si.first_cam + k % si.n_cams, k < si.n_cams ? kModeTemporal : kModeFallback, items, si.cap});
       items += si.cap;
     }
     si.n_segs = (int)h->segs.size() - si.seg_begin;
@@ -424,15 +430,10 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   const size_t o_pred = take(sizeof(Prediction) * std::max(1, h->pred_cap));
   const size_t o_depth = take(sizeof(KpDepth) * std::max(1, h->pred_cap));
   size_t o_feat = 0, o_guess = 0, o_P = 0, o_W1 = 0, o_W2 = 0, o_W2t = 0, o_W3 = 0;
-  size_t o_ghdr = 0, o_gstart = 0, o_gpos = 0, o_gidx = 0;
   if (h->learned) {
     const int rows = (rows_total + 15) / 16 * 16;
     o_feat = take(sizeof(float) * 32 * rows);
     o_guess = take(sizeof(float) * 3 * rows);
-    o_ghdr = take(sizeof(int4) * n_cams);
-    o_gstart = take(sizeof(int) * (kFeatGridMax + 1) * n_cams);
-    o_gpos = take(sizeof(float2) * rows);
-    o_gidx = take(sizeof(int) * rows);
     o_P = take(sizeof(float) * VIO_MLP_NPARAM);
     o_W1 = take(2 * 128 * 32);
     o_W2 = take(2 * 128 * 128);
@@ -476,6 +477,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
       for (int ps = 0; ps < 3; ++ps) d.lvl[ps][l] = base + co[c].lvl[ps][l];
     for (int par = 0; par < 2; ++par) d.state[par] = reinterpret_cast<Kp*>(base + co[c].state[par]);
     d.res = reinterpret_cast<TrackRes*>(base + co[c].res);
+    d.res_fb = par_fb ? reinterpret_cast<TrackRes*>(base + co[c].res_fb) : nullptr;
     if (d.detect) {
       for (int ps = 0; ps < 3; ++ps) d.keys[ps] = reinterpret_cast<uint32_t*>(base + co[c].keys[ps]);
       d.sres = reinterpret_cast<TrackRes*>(base + co[c].sres);
@@ -499,8 +501,6 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   if (h->learned) {
     h->d_feat = reinterpret_cast<float*>(base + o_feat);
     h->d_guess = reinterpret_cast<float*>(base + o_guess);
-    h->grid = FeatGrid{reinterpret_cast<int4*>(base + o_ghdr), reinterpret_cast<int*>(base + o_gstart),
-                       reinterpret_cast<float2*>(base + o_gpos), reinterpret_cast<int*>(base + o_gidx)};
     h->mlp.P = reinterpret_cast<float*>(base + o_P);
     h->mlp.W1b = reinterpret_cast<uint16_t*>(base + o_W1);
     h->mlp.W2b = reinterpret_cast<uint16_t*>(base + o_W2);
@@ -526,6 +526,9 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     return fail(h, VIO_ENOMEM, "pinned host buffers");
   for (FrameTable* f : h->h_frames) std::memset(f, 0, sizeof(FrameTable));
   h->h_frame = h->h_frames[0];
+  for (int slot = 0; slot < 2; ++slot)
+    HIP_CHECK(h, hipHostGetDevicePointer((void**)&h->hm_frames[slot], h->h_frames[slot], 0));
+  h->hm_frame = h->hm_frames[0];
   std::memset(h->h_rec_count, 0, sizeof(int32_t) * 2 * n_cams);
   std::memset(h->h_camstats, 0, sizeof(int32_t) * kCamStats * 2 * n_cams);
   vio_track* rec_dev = nullptr;
@@ -545,7 +548,6 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   HIP_CHECK(h, hipStreamCreate(&h->stream));
   HIP_CHECK(h, hipStreamCreate(&h->pstream));
   for (int slot = 0; slot < 2; ++slot) {
-    HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_copy[slot], hipEventDisableTiming));
     HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_pyr[slot], hipEventDisableTiming));
   }
   HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
@@ -618,6 +620,7 @@ static Tuning tuning(const vio_frontend* h) {
   t.stereo_nb = h->P.stereo_init == VIO_STEREO_INIT_NEIGHBOUR ? 1 : 0;
   t.slevels = h->P.stereo_levels;
   t.siters = h->P.stereo_iters;
+  t.par_fb = h->cams.empty() || h->cams[0].res_fb == nullptr ? 0 : 1;
   return t;
 }
 
@@ -664,28 +667,23 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
     ~Reset() { tl_timing = KernelTiming{}; }
   } reset;
   hipError_t e;
-  if (stage == 0)
-    return hipMemcpyAsync(h->d_frame, h->h_frame, offsetof(FrameTable, cam) + sizeof(FrameCam) * h->cams.size(),
-                          hipMemcpyHostToDevice, st);
   if (stage == 1) {
+    // the pyramid kernel reads the frame's table from its pinned host slot and
+    // copies it to the device table the later kernels read
     timing(kKernPyr);
-    return launch_pyr_detect_range(h->d_cams, h->d_frame, ls.cam_begin, ls.cam_end, ls.tile_begin, ls.n_tiles,
-                                   tune.levels, h->tile, tune.tmin, tune.margin, st);
+    return launch_pyr_detect_range(h->d_cams, h->hm_frame, h->d_frame,
+                                   (int)(offsetof(FrameTable, cam) + sizeof(FrameCam) * h->cams.size()), ls.cam_begin,
+                                   ls.cam_end, ls.tile_begin, ls.n_tiles, tune.levels, h->tile, tune.tmin, tune.margin,
+                                   st);
   }
   if (stage == 4) {
-    // features of every previous keypoint, then one network pass over the
-    // set's rows; the tracker reads the guesses
-    const int row0 = h->cams[ls.cam_begin].row_off;
-    int rows = 0;
-    for (int c = ls.cam_begin; c < ls.cam_end; ++c) rows += h->cams[c].cap;
-    timing(kKernGrid);
-    if ((e = launch_grid(h->d_cams, h->d_frame, h->d_cnt, ls.cam_begin, ls.cam_end, h->grid, st))) return e;
+    // the features of the previous keypoints and the network's guesses in one
+    // launch; the tracker reads the guesses
     timing(kKernFeatures);
-    if ((e = launch_features(h->d_cams, h->d_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->grid,
-                             h->d_feat, st)))
-      return e;
-    timing(kKernMlp);
-    return mlp_forward_launch(h->mlp, h->d_feat + (size_t)row0 * 32, rows, h->d_guess + (size_t)row0 * 3, st);
+    // (it runs beside the pyramid kernel, which copies the frame's table to
+    // the device: it reads the pinned host table)
+    return launch_learn(h->d_cams, h->hm_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->mlp,
+                        h->d_feat, h->d_guess, st);
   }
   if (stage == 2) {
     // speculative: every item; deferred: the temporal items only (they follow the stereo ones)
@@ -715,9 +713,6 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
 // tracking.
 static hipError_t enqueue_pyr_part(vio_frontend* h, const LaunchSet& ls, int slot, bool timed) {
   hipError_t e;
-  if ((e = enqueue_stage(h, ls, h->pstream, 0, timed))) return e;
-  // the learned stage starts after the copy (beside the pyramid)
-  if (h->learned && (e = hipEventRecord(h->ev_copy[slot], h->pstream))) return e;
   if ((e = enqueue_stage(h, ls, h->pstream, 1, timed))) return e;
   return hipEventRecord(h->ev_pyr[slot], h->pstream);
 }
@@ -766,6 +761,7 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
   if (h->n_pend == 2) return fail(h, VIO_ESTATE, "two frames in flight: call vio_frontend_wait first");
   const int slot = (int)(h->sub & 1);
   h->d_frame = h->d_frames[slot];
+  h->hm_frame = h->hm_frames[slot];
   ensure_graph(h, ls, &gr[slot]);
   const bool graphed = gr[slot].any();
   // eager launches time each kernel with shared events: one frame at a time
@@ -781,10 +777,12 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
     HIP_CHECK(h, hipEventRecord(h->ev_in, st));
     HIP_CHECK(h, hipStreamWaitEvent(h->pstream, h->ev_in, 0));
   }
-  HIP_CHECK(h, hipEventRecord(h->ev[slot][0], h->pstream));
+  // the frame's start timestamp (last_gpu_ms), not taken with plain launches
+  if (!h->plain) HIP_CHECK(h, hipEventRecord(h->ev[slot][0], h->pstream));
   HIP_CHECK(h, enqueue_pyr_part(h, ls, slot, timed));
   if (h->learned) {
-    HIP_CHECK(h, hipStreamWaitEvent(st, h->ev_copy[slot], 0));
+    // the learned stage's inputs are the previous frame's (ordered before it
+    // on this stream) and the pinned frame table: it starts at once
     if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].learn, st));
     else HIP_CHECK(h, enqueue_stage(h, ls, st, 4, timed));
   }
@@ -819,8 +817,8 @@ static int complete_oldest(vio_frontend* h) {
   h->n_pend -= 1;
   HIP_CHECK(h, hipEventSynchronize(h->ev[p.slot][1]));
   const FrameTable* ft = h->h_frames[p.slot];
-  float ms = 0.f;
-  HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[p.slot][0], h->ev[p.slot][1]));
+  float ms = -1.f;
+  if (!h->plain) HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev[p.slot][0], h->ev[p.slot][1]));
   float km[kKernels];
   for (int k = 0; k < kKernels; ++k) {
     km[k] = -1.f;
@@ -830,7 +828,7 @@ static int complete_oldest(vio_frontend* h) {
   h->stats.last_stage_ms[0] = km[kKernPyr];
   h->stats.last_stage_ms[1] = km[kKernTrack] + (km[kKernTrackStereo] > 0.f ? km[kKernTrackStereo] : 0.f);
   h->stats.last_stage_ms[2] = km[kKernSelect] + (km[kKernSelectRight] > 0.f ? km[kKernSelectRight] : 0.f);
-  h->stats.last_learned_ms[0] = km[kKernFeatures] + (km[kKernGrid] > 0.f ? km[kKernGrid] : 0.f);
+  h->stats.last_learned_ms[0] = km[kKernFeatures];
   h->stats.last_learned_ms[1] = km[kKernMlp];
   h->stats.last_gpu_ms = ms;
   h->stats.frames += 1;

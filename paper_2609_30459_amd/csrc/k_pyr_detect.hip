@@ -176,8 +176,9 @@ __device__ __forceinline__ uint32_t pyr_v_pair(uint32_t r0, uint32_t r1, uint32_
 template <int L, int T>
 __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDesc* __restrict__ cams,
                                                                       const FrameTable* __restrict__ frame,
-                                                                      int cam_begin, int cam_end, int tile_base,
-                                                                      int tmin, int margin) {
+                                                                      FrameTable* __restrict__ dframe,
+                                                                      int copy_words, int cam_begin, int cam_end,
+                                                                      int tile_base, int tmin, int margin) {
   using G = PyrGeom<L, T>;
   static_assert(G::threads == (T == 64 ? 1024 : 256), "launch bounds");
   constexpr int kTile = T;
@@ -190,6 +191,14 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
   __shared__ __align__(16) uint16_t s_v[G::vbytes];
   __shared__ __align__(16) uint8_t s_lv[2][G::lvl_bytes];
 
+  // `frame` is the frame's table in mapped pinned host memory; the first
+  // workgroup copies it to the device table that the later kernels of the
+  // frame read (no separate copy call on the host)
+  if (blockIdx.x == 0) {
+    const uint32_t* fs = reinterpret_cast<const uint32_t*>(frame);
+    uint32_t* fd = reinterpret_cast<uint32_t*>(dframe);
+    for (int i = (int)threadIdx.x; i < copy_words; i += kPyrThreads) fd[i] = fs[i];
+  }
   const int gtile = tile_base + (int)blockIdx.x;
   int c = cam_begin;
   while (c + 1 < cam_end && cams[c + 1].tile_begin <= gtile) ++c;
@@ -445,10 +454,10 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
 }
 
 template <int L, int T>
-hipError_t launch_LT(const CamDesc* cams, const FrameTable* frame, int cam_begin, int cam_end, int tile_base,
-                     int n_tiles, int tmin, int margin, hipStream_t s) {
-  launch_kernel(k_pyr_detect<L, T>, dim3(n_tiles), dim3(PyrGeom<L, T>::threads), 0, s, cams, frame, cam_begin,
-                cam_end, tile_base, tmin, margin);
+hipError_t launch_LT(const CamDesc* cams, const FrameTable* frame, FrameTable* dframe, int copy_words, int cam_begin,
+                     int cam_end, int tile_base, int n_tiles, int tmin, int margin, hipStream_t s) {
+  launch_kernel(k_pyr_detect<L, T>, dim3(n_tiles), dim3(PyrGeom<L, T>::threads), 0, s, cams, frame, dframe, copy_words,
+                cam_begin, cam_end, tile_base, tmin, margin);
   return hipGetLastError();
 }
 
@@ -469,15 +478,21 @@ size_t lds_bytes_T(int levels) {
 }
 
 template <int T>
-hipError_t launch_T(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end, int tile_base,
-                    int n_tiles, int levels, int tmin, int margin, hipStream_t s) {
+hipError_t launch_T(const CamDesc* d_cams, const FrameTable* h_frame, FrameTable* d_frame, int copy_words, int cam_begin,
+                    int cam_end, int tile_base, int n_tiles, int levels, int tmin, int margin, hipStream_t s) {
   switch (levels) {
-    case 1: return launch_LT<1, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 2: return launch_LT<2, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 3: return launch_LT<3, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 4: return launch_LT<4, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 5: return launch_LT<5, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
-    case 6: return launch_LT<6, T>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, tmin, margin, s);
+    case 1: return launch_LT<1, T>(d_cams, h_frame, d_frame, copy_words, cam_begin, cam_end, tile_base, n_tiles, tmin,
+                                       margin, s);
+    case 2: return launch_LT<2, T>(d_cams, h_frame, d_frame, copy_words, cam_begin, cam_end, tile_base, n_tiles, tmin,
+                                       margin, s);
+    case 3: return launch_LT<3, T>(d_cams, h_frame, d_frame, copy_words, cam_begin, cam_end, tile_base, n_tiles, tmin,
+                                       margin, s);
+    case 4: return launch_LT<4, T>(d_cams, h_frame, d_frame, copy_words, cam_begin, cam_end, tile_base, n_tiles, tmin,
+                                       margin, s);
+    case 5: return launch_LT<5, T>(d_cams, h_frame, d_frame, copy_words, cam_begin, cam_end, tile_base, n_tiles, tmin,
+                                       margin, s);
+    case 6: return launch_LT<6, T>(d_cams, h_frame, d_frame, copy_words, cam_begin, cam_end, tile_base, n_tiles, tmin,
+                                       margin, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -490,12 +505,15 @@ size_t pyr_detect_lds_bytes(int levels, int tile) {
   return tile == 32 ? lds_bytes_T<32>(levels) : tile == 64 ? lds_bytes_T<64>(levels) : 0;
 }
 
-hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* d_frame, int cam_begin, int cam_end,
-                                   int tile_base, int n_tiles, int levels, int tile, int tmin, int margin,
-                                   hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  if (tile == 32) return launch_T<32>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, levels, tmin, margin, s);
-  if (tile == 64) return launch_T<64>(d_cams, d_frame, cam_begin, cam_end, tile_base, n_tiles, levels, tmin, margin, s);
+hipError_t launch_pyr_detect_range(const CamDesc* d_cams, const FrameTable* h_frame, FrameTable* d_frame,
+                                   int copy_bytes, int cam_begin, int cam_end, int tile_base, int n_tiles, int levels,
+                                   int tile, int tmin, int margin, hipStream_t s) {
+  if (n_tiles <= 0 || copy_bytes % 4) return hipErrorInvalidValue;
+  const int w = copy_bytes / 4;
+  if (tile == 32)
+    return launch_T<32>(d_cams, h_frame, d_frame, w, cam_begin, cam_end, tile_base, n_tiles, levels, tmin, margin, s);
+  if (tile == 64)
+    return launch_T<64>(d_cams, h_frame, d_frame, w, cam_begin, cam_end, tile_base, n_tiles, levels, tmin, margin, s);
   return hipErrorInvalidValue;
 }
 

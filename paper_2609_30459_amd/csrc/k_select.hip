@@ -118,6 +118,8 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
       kp = cd.state[Q][j];
       if (fc.has_prev) {
         r = cd.res[j];
+        // a short attempt that was not kept: its fallback, computed beside it
+        if (r.pad[0] != 0 && cd.res_fb) r = cd.res_fb[j];
         alive = r.status == VIO_TRACKED;
       } else {
         r.x = kp.x;
@@ -202,8 +204,18 @@ __device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDe
 // n_right keypoints, in id order, that also live among detecting camera L's
 // n_left keypoints (parity P; both states are sorted by id), as L's position
 // and the offset from L to R. The next frame's stereo matches into R read it.
+// s_ids: LDS room for kPairIdsLds ids; the left ids are staged there when
+// they fit, so that the searches read LDS instead of the state in memory.
+constexpr int kPairIdsLds = kMaxCells / 2;  // int64 ids in the occupancy array's bytes
+
 __device__ void build_pairs(const CamDesc& L, int P, int n_left, const CamDesc& R, int PR, int rc, int n_right,
-                            Counters* cnt, Scan& sc) {
+                            Counters* cnt, Scan& sc, int64_t* s_ids) {
+  const bool staged = n_left <= kPairIdsLds;
+  if (staged) {
+    __syncthreads();  // the LDS array's previous use is over
+    for (int k = (int)threadIdx.x; k < n_left; k += kSelectThreads) s_ids[k] = L.state[P][k].id;
+    __syncthreads();
+  }
   int base = 0;
   for (int i0 = 0; i0 < n_right; i0 += kSelectThreads) {
     const int i = i0 + (int)threadIdx.x;
@@ -211,17 +223,21 @@ __device__ void build_pairs(const CamDesc& L, int P, int n_left, const CamDesc& 
     float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i < n_right) {
       const Kp q = R.state[PR][i];
-      int lo = 0, hi = n_left - 1;
+      int lo = 0, hi = n_left - 1, at = -1;
       while (lo <= hi) {
         const int mid = (lo + hi) >> 1;
-        const Kp l = L.state[P][mid];
-        if (l.id == q.id) {
-          e = make_float4(l.x, l.y, q.x - l.x, q.y - l.y);
-          found = true;
+        const int64_t id = staged ? s_ids[mid] : L.state[P][mid].id;
+        if (id == q.id) {
+          at = mid;
           break;
         }
-        if (l.id < q.id) lo = mid + 1;
+        if (id < q.id) lo = mid + 1;
         else hi = mid - 1;
+      }
+      if (at >= 0) {
+        const Kp l = L.state[P][at];
+        e = make_float4(l.x, l.y, q.x - l.x, q.y - l.y);
+        found = true;
       }
     }
     int total;
@@ -239,7 +255,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
   __shared__ ScanScratch s_scan;
   __shared__ int s_hsum[4];
   Scan sc{&s_scan, 0};
-  __shared__ unsigned s_occ[kMaxCells];
+  __shared__ __align__(8) unsigned s_occ[kMaxCells];  // cell occupancy; later the pair search's left ids
   __shared__ uint16_t s_sel[kMaxCells];  // key slot of selection rank i (rank < cap <= kMaxCells, slot < 2^16)
   __shared__ int s_hist[256];
   __shared__ int s_thr[2];
@@ -263,7 +279,8 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
                                        cnt->n_live[PR][rc], n_rec_r, [&](int i) { return sr[i]; }, cnt, sc);
         __syncthreads();
         if (tune.stereo_nb) {
-          build_pairs(L, P, cnt->sel_base[lc] + cnt->n_sel[lc], cams[rc], PR, rc, n_r, cnt, sc);
+          build_pairs(L, P, cnt->sel_base[lc] + cnt->n_sel[lc], cams[rc], PR, rc, n_r, cnt, sc,
+                      reinterpret_cast<int64_t*>(s_occ));
           __syncthreads();
         }
       }
@@ -383,7 +400,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
                                        [&](int i) { return sr[s_sel[i]]; }, cnt, sc);
         if (tune.stereo_nb) {
           __syncthreads();
-          build_pairs(L, P, n_surv + n_new, R, PR, rc, n_r, cnt, sc);
+          build_pairs(L, P, n_surv + n_new, R, PR, rc, n_r, cnt, sc, reinterpret_cast<int64_t*>(s_occ));
         }
       } else if (threadIdx.x == 0) {
         // the matches come from the stereo tracking launch; kSelectRight appends them

@@ -560,7 +560,7 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   int fl = tune.levels, fi = tune.iters;
   bool try_short = false;
   TrackRes* out;
-  if (sg.mode == kModeTemporal) {
+  if (sg.mode != kModeStereo) {  // a temporal track, or its parallel fallback
     if (!fc.has_prev || j >= cnt->n_live[P ^ 1][c]) return;
     const Kp kp = cd.state[P ^ 1][j];
     px = kp.x;
@@ -651,6 +651,17 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
     ssrc = fc.pyr_prev;
     sdst = fc.pyr;
     out = cd.res + j;
+    if (sg.mode == kModeFallback) {
+      // the fallback attempt only, for a track that tries a short budget
+      // first (its temporal item runs that, and the selection takes this
+      // result when the short track is not kept)
+      if (!try_short) return;
+      TrackRes r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, ix, iy, ith, fl, fi, tune.fb_threshold, u, v, wgt,
+                               lane);
+      r.pad[0] = 1;
+      store_result(cd.res_fb + j, r, lane);
+      return;
+    }
   } else {
     // stereo match of a detection into target camera c + 1 + t (item j =
     // t * nslots + i): speculative (i = the winner's key slot) or deferred
@@ -746,8 +757,10 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   }
   TrackRes r;
   int fell_back = 0;
+  // with parallel fallbacks a short attempt is the item's only one
+  const int last = try_short && tune.par_fb ? 0 : 1;
 #pragma unroll 1
-  for (int a = try_short ? 0 : 1; a < 2; ++a) {
+  for (int a = try_short ? 0 : 1; a <= last; ++a) {
     const bool short_run = a == 0;
     r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy, short_run ? gth : ith,
                     short_run ? sl : fl, short_run ? si : fi, tune.fb_threshold, u, v, wgt, lane);

@@ -61,3 +61,60 @@ def test_stereo_init_arguments():
                                                                                      learned_fb_iters=0)):
         with pytest.raises(vf.VioError):
             vf.Frontend([stream], vf.params_for(w, **bad))
+
+
+@pytest.mark.parametrize("name,extra", [
+    ("stereo752", dict(init_mode=1, learned_levels=2, learned_iters=3, learned_rho=0.03)),
+    ("stereo1280", dict(init_mode=1, learned_levels=2, learned_iters=3, learned_rho=0.03, learned_fb_levels=2,
+                        learned_fb_iters=5, stereo_init=1)),
+    ("stereo752", dict(init_mode=1, learned_levels=2, learned_iters=3, learned_rho=-1.0, learned_fb_levels=3,
+                       learned_fb_iters=4))])
+@pytest.mark.parametrize("launch", [{}, {"stereo_mode": 1}, {"track_waves_per_cu": 4}])
+def test_parallel_fallback_equals_serial_bitwise(name, extra, launch):
+    """The parallel fallbacks (a second wave per short attempt) give the records
+    of the serial ones, bit for bit, and the same fallback counts."""
+    import paper_2609_30459_amd as vf
+    w = synthgen.WORKLOADS[name]
+    seq = synthgen.sequence(w, seq=8, n_frames=5)
+    P = oracle.mlp_init(13) * 0.05
+    P[-3:] = 0.0
+    stream = (2, w.width, w.height, w.max_keypoints, w.cell_size)
+    fbs = 0
+    with vf.Frontend([stream], vf.params_for(w, **extra, **launch)) as a, \
+            vf.Frontend([stream], vf.params_for(w, track_parallel_fallback=1, **extra, **launch)) as b:
+        a.set_mlp(P)
+        b.set_mlp(P)
+        for t in range(5):
+            a.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            b.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            ra, rb = a.get_tracks(0), b.get_tracks(0)
+            assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), t
+            sa, sb = a.stats(), b.stats()
+            assert sa["last_fallback"] == sb["last_fallback"], t
+            fbs += sa["last_fallback"]
+    assert fbs > 0
+
+
+def test_parallel_fallback_of_predicted_tracks_equals_serial():
+    """Predicted (camera-model) starts with a short budget: parallel = serial."""
+    import paper_2609_30459_amd as vf
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=2, n_frames=5)
+    stream = (2, w.width, w.height, w.max_keypoints, w.cell_size)
+    over = dict(pred_levels=2, pred_iters=3, pred_rho=0.02)
+    fbs = 0
+    with vf.Frontend([stream], vf.params_for(w, **over)) as a, \
+            vf.Frontend([stream], vf.params_for(w, track_parallel_fallback=1, **over)) as b:
+        for t in range(5):
+            if t > 0:
+                K, R, tr = seq.camera_motion(t - 1, 450.0, 0.5)
+                for fe in (a, b):
+                    if t == 1:
+                        fe.set_camera_model(0, 0, K)
+                        fe.set_camera_model(0, 1, K)
+                    fe.set_motion(0, [(0, R, tr, 0.5), (1, R, tr, 0.5)])
+            a.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            b.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            assert a.get_tracks(0).tobytes() == b.get_tracks(0).tobytes(), t
+            fbs += a.stats()["last_fallback"]
+    assert fbs > 0
