@@ -162,6 +162,8 @@ def main():
                     help="tracker grid: 0 = one wave per keypoint, N = persistent N waves per CU "
                          "(default: the autotuned choice, else 0)")
     ap.add_argument("--block-waves", type=int, default=None, help="tracker waves per workgroup (1, 2, 4)")
+    ap.add_argument("--learned-block-waves", type=int, choices=[4, 8, 16], default=None,
+                    help="keypoints per learned-stage workgroup")
     ap.add_argument("--tile", type=int, default=None, help="pyramid/detector tile edge (32, 64)")
     ap.add_argument("--stereo-mode", type=int, default=None, help="0 speculative, 1 deferred stereo matching")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -221,7 +223,7 @@ def main():
     def launch_choice(init):
         """Launch parameters (never change the records): explicit flags, else the autotuned choice."""
         wpc, bw, tile, smode = args.waves_per_cu, args.block_waves, args.tile, args.stereo_mode
-        pfb = args.parallel_fallback
+        pfb, lbw = args.parallel_fallback, args.learned_block_waves
         tuned = None
         if wpc is None and bw is None and tile is None and smode is None:
             from paper_2609_30459_amd import autotune
@@ -231,10 +233,13 @@ def main():
                 tile, smode = tuned.get("pyr_tile", 64), tuned.get("stereo_mode", 0)
                 if pfb is None and "track_parallel_fallback" in tuned:
                     pfb = tuned["track_parallel_fallback"]
+                if lbw is None and "learned_block_waves" in tuned:
+                    lbw = tuned["learned_block_waves"]
         if pfb is None:
             pfb = 0 if batched else 1
         return dict(track_waves_per_cu=wpc or 0, track_block_waves=bw or 4, pyr_tile=tile or 64,
-                    stereo_mode=smode or 0, track_parallel_fallback=pfb if init == "learned" else 0), \
+                    stereo_mode=smode or 0, track_parallel_fallback=pfb if init == "learned" else 0,
+                    learned_block_waves=(lbw or 0) if init == "learned" else 0), \
             tuned is not None
 
     mlp = None
@@ -499,7 +504,7 @@ def main():
                        else {"levels": L, "iters": N, "stereo_start": "prior"}),
             "launch": {**{k: v for k, v in extra.items() if k in ("track_waves_per_cu", "track_block_waves",
                                                                    "pyr_tile", "stereo_mode",
-                                                                   "track_parallel_fallback")},
+                                                                   "track_parallel_fallback", "learned_block_waves")},
                        "autotuned": tuned},
             "roofline": roof, "second_launch": second, "kernels": kernels,
             "host_image": None if args.no_host_leg else host_run(init),

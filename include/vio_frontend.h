@@ -150,6 +150,10 @@ typedef struct vio_frontend_params {
    * not their sum, for up to twice the tracker work); 0 = the fallback runs after
    * the short attempt in the same wave. */
   int32_t track_parallel_fallback;
+  /* Launch choice that never changes the records: keypoints (one wave each) per
+   * workgroup of the learned stage, 4, 8 or 16 (0 = 4); fewer spread a camera's
+   * keypoints over more compute units. */
+  int32_t learned_block_waves;
 } vio_frontend_params;
 
 #define VIO_STEREO_INIT_PRIOR 0

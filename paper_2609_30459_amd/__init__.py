@@ -32,7 +32,8 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
                 learned_iters=3, learned_rho=0.0, eager=False, track_waves_per_cu=0,
                 track_block_waves=0, pyr_tile=0, stereo_mode=0, pred_levels=0, pred_iters=0,
                 pred_rho=0.0, topology=0, plain=False, learned_fb_levels=0, learned_fb_iters=0, stereo_init=0,
-                stereo_levels=2, stereo_iters=3, track_parallel_fallback=0) -> _n.vio_frontend_params:
+                stereo_levels=2, stereo_iters=3, track_parallel_fallback=0,
+                learned_block_waves=0) -> _n.vio_frontend_params:
     p = default_params()
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
     p.n_thresholds = len(thresholds)
@@ -51,6 +52,7 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
     p.learned_fb_levels, p.learned_fb_iters = learned_fb_levels, learned_fb_iters
     p.stereo_init, p.stereo_levels, p.stereo_iters = stereo_init, stereo_levels, stereo_iters
     p.track_parallel_fallback = track_parallel_fallback
+    p.learned_block_waves = learned_block_waves
     return p
 
 

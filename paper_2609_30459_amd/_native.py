@@ -60,7 +60,7 @@ class vio_frontend_params(ctypes.Structure):
         ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p),
         ("learned_fb_levels", ctypes.c_int32), ("learned_fb_iters", ctypes.c_int32),
         ("stereo_init", ctypes.c_int32), ("stereo_levels", ctypes.c_int32), ("stereo_iters", ctypes.c_int32),
-        ("track_parallel_fallback", ctypes.c_int32),
+        ("track_parallel_fallback", ctypes.c_int32), ("learned_block_waves", ctypes.c_int32),
     ]
 
 # the optional device allocator of vio_frontend_params

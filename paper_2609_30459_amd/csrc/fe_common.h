@@ -35,6 +35,7 @@ inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStre
 // byte-addressed range check).
 constexpr int kBufferWord3 = 0x00020000;
 constexpr int kTrackWaves = 4;  // most waves (keypoints) per tracking block
+constexpr int kLearnWavesDefault = 4;  // keypoints (waves) per learned-stage workgroup
 constexpr int kSelectThreads = 1024;
 
 // Live keypoint, 32 bytes (same layout as vio_keypoint).
@@ -230,7 +231,8 @@ hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_
 // keypoints of cameras [cam_begin, cam_end); h_cams: host copy of the
 // descriptors (caps).
 hipError_t launch_learn(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt, const CamDesc* h_cams,
-                        int cam_begin, int cam_end, const MlpDev& M, float* d_feat, float* d_guess, hipStream_t s);
+                        int cam_begin, int cam_end, const MlpDev& M, float* d_feat, float* d_guess, int waves,
+                        hipStream_t s);
 hipError_t mlp_forward_launch(const MlpDev& M, const float* X, int K, float* Y, hipStream_t s);
 hipError_t mlp_pack_launch(const MlpDev& M, hipStream_t s);
 // Selection phases: kSelectAll (speculative stereo: everything in one

@@ -236,6 +236,9 @@ int check_params(const vio_frontend_params* p, std::string& why) {
     return why = "stereo_levels out of 1..levels or stereo_iters out of 1..32", VIO_EINVAL;
   if (p->track_parallel_fallback != 0 && p->track_parallel_fallback != 1)
     return why = "track_parallel_fallback must be 0 or 1", VIO_EINVAL;
+  if (p->learned_block_waves != 0 && p->learned_block_waves != 4 && p->learned_block_waves != 8 &&
+      p->learned_block_waves != 16)
+    return why = "learned_block_waves must be 0, 4, 8 or 16", VIO_EINVAL;
   return VIO_OK;
 }
 
@@ -683,7 +686,8 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
     // (it runs beside the pyramid kernel, which copies the frame's table to
     // the device: it reads the pinned host table)
     return launch_learn(h->d_cams, h->hm_frame, h->d_cnt, h->cams.data(), ls.cam_begin, ls.cam_end, h->mlp,
-                        h->d_feat, h->d_guess, st);
+                        h->d_feat, h->d_guess, h->P.learned_block_waves ? h->P.learned_block_waves : kLearnWavesDefault,
+                        st);
   }
   if (stage == 2) {
     // speculative: every item; deferred: the temporal items only (they follow the stereo ones)

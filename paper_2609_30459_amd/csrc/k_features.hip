@@ -10,9 +10,9 @@
 //    cell_sum * 16 / patch_sum - 1 (integer sums, one correctly rounded
 //    division).
 //
-// One launch (k_learn): a workgroup takes 16 keypoints of one camera, stages
-// the camera's tracks in LDS chunk by chunk, and every wave searches all of
-// them for its keypoint: each lane keeps a sorted list of
+// One launch (k_learn): a workgroup takes W keypoints of one camera (one wave
+// each; W = 4, 8 or 16), stages the camera's tracks in LDS chunk by chunk, and
+// every wave searches all of them for its keypoint: each lane keeps a sorted list of
 // its best eight exact keys (squared distance in double, where the
 // differences and squares of float positions are exact, then index) over
 // the tracks it visits, and eight rounds of a wave minimum over the lanes'
@@ -26,7 +26,8 @@
 namespace vio {
 namespace {
 
-constexpr int kLearnWaves = 16;   // keypoints per workgroup: the rows of one MFMA tile
+constexpr int kTileRows = 16;     // rows of one MFMA tile: at most 16 keypoints per workgroup
+constexpr int kHidTiles = MH / 16;  // 16-unit output tiles of a hidden layer
 constexpr int kCandChunk = 2048;  // tracks staged in LDS at a time (16 KB)
 constexpr int kNone = 0x7FFFFFFF;
 constexpr uint64_t kInfBits = 0x7FF0000000000000ull;  // +inf as a key: an empty place
@@ -90,27 +91,30 @@ __device__ __forceinline__ void wave_min_key(NKey& k) {
   min_swap<false>(k); // rows 0 <-> 1, 2 <-> 3
 }
 
-// The features and the network's output for 16 keypoints of one camera per
-// workgroup (the 16 rows of one MFMA tile). Wave w computes keypoint
-// j0 + w's features (exact 8 nearest tracks, pooled patch) into the feature
-// matrix and, rounded to bfloat16, into the workgroup's input tile; then
-// waves 0..7 each compute 16 hidden units of layers 1 and 2 (one 16x16 output
-// tile, K = 32 and 4 x 32) and wave 0 the three outputs, with the same MFMA
-// sequence as the network kernel of vio_mlp.h (so the same results). Each
-// wave loads its weight slice into registers before the feature search, so
-// the weights' L2 latency hides behind it.
-__global__ __launch_bounds__(64 * kLearnWaves) void k_learn(const CamDesc* __restrict__ cams,
-                                                           const FrameTable* __restrict__ frame,
-                                                           const Counters* __restrict__ cnt, int cam_begin,
-                                                           int cam_end, MlpDev M, float* __restrict__ feat,
-                                                           float* __restrict__ guess) {
-  __shared__ float2 sCand[kCandChunk];                     // a chunk of the camera's tracks
-  __shared__ __align__(16) uint16_t sX[kLearnWaves][MI];  // bf16 inputs, one row per keypoint
-  __shared__ __align__(16) uint16_t sH[kLearnWaves][MH];  // h1, then h2
-  // the workgroup's camera and keypoints: ceil(cap / 16) workgroups per camera
+// The features and the network's output for W keypoints of one camera per
+// workgroup (rows 0..W-1 of one MFMA tile; the other rows are zero). Wave w
+// computes keypoint j0 + w's features (exact 8 nearest tracks, pooled patch)
+// into the feature matrix and, rounded to bfloat16, into the workgroup's input
+// tile; then wave w computes hidden tiles w, w + W, ... (16 units each, K = 32
+// for layer 1 and 4 x 32 for layer 2) and wave 0 the three outputs, with the
+// same MFMA sequence as the network kernel of vio_mlp.h (so the same results
+// row by row). Each wave loads its weight slices into registers before the
+// feature search, so their L2 latency hides behind it. Fewer waves per
+// workgroup spread a camera over more compute units, each wave with a larger
+// share of its SIMD.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
+                                                  const Counters* __restrict__ cnt, int cam_begin, int cam_end,
+                                                  MlpDev M, float* __restrict__ feat, float* __restrict__ guess) {
+  static_assert(W >= 1 && W <= kTileRows, "one tile of keypoints per workgroup");
+  constexpr int kTPW = (kHidTiles + W - 1) / W;  // hidden tiles per wave
+  __shared__ float2 sCand[kCandChunk];                   // a chunk of the camera's tracks
+  __shared__ __align__(16) uint16_t sX[kTileRows][MI];  // bf16 inputs, one row per keypoint
+  __shared__ __align__(16) uint16_t sH[kTileRows][MH];  // h1, then h2
+  // the workgroup's camera and keypoints: ceil(cap / W) workgroups per camera
   int c = cam_begin, b = (int)blockIdx.x;
   for (; c < cam_end; ++c) {
-    const int nb = (cams[c].cap + kLearnWaves - 1) / kLearnWaves;
+    const int nb = (cams[c].cap + W - 1) / W;
     if (b < nb) break;
     b -= nb;
   }
@@ -120,29 +124,41 @@ __global__ __launch_bounds__(64 * kLearnWaves) void k_learn(const CamDesc* __res
   if (!fc.active || !fc.has_prev) return;
   const int Q = fc.parity ^ 1;
   const int n = cnt->n_live[Q][c];
-  const int j0 = b * kLearnWaves;
+  const int j0 = b * W;
   if (j0 >= n) return;
   const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6);
   const int r = lane & 15, g = lane >> 4;
 
-  // ---- this wave's weight slices (waves 0..7: hidden units 16 wv + r) -----
+  // ---- this wave's weight slices (hidden tiles wv, wv + W, ...) -----------
   const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  bf16x8 w1 = pack8(z8), w2[MH / 32], w3[MH / 32];
+  bf16x8 w1[kTPW], w2[kTPW][MH / 32], w3[MH / 32];
+  float b1[kTPW], b2[kTPW], b3 = 0.f;
 #pragma unroll
-  for (int kc = 0; kc < MH / 32; ++kc) w2[kc] = w3[kc] = pack8(z8);
-  float b1 = 0.f, b2 = 0.f, b3 = 0.f;
-  if (wv < MH / 16) {
-    const int jn = 16 * wv + r;
-    w1 = load8(M.W1b + (size_t)jn * MI + 8 * g);
+  for (int t = 0; t < kTPW; ++t) {
+    const int tile = wv + W * t;
+    w1[t] = pack8(z8);
+    b1[t] = b2[t] = 0.f;
 #pragma unroll
-    for (int kc = 0; kc < MH / 32; ++kc) w2[kc] = load8(M.W2b + (size_t)jn * MH + 32 * kc + 8 * g);
-    b1 = M.P[OFF_B1 + jn];
-    b2 = M.P[OFF_B2 + jn];
+    for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = pack8(z8);
+    if (tile < kHidTiles) {
+      const int jn = 16 * tile + r;
+      w1[t] = load8(M.W1b + (size_t)jn * MI + 8 * g);
+#pragma unroll
+      for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = load8(M.W2b + (size_t)jn * MH + 32 * kc + 8 * g);
+      b1[t] = M.P[OFF_B1 + jn];
+      b2[t] = M.P[OFF_B2 + jn];
+    }
   }
+#pragma unroll
+  for (int kc = 0; kc < MH / 32; ++kc) w3[kc] = pack8(z8);
   if (wv == 0 && r < MO) {
 #pragma unroll
     for (int kc = 0; kc < MH / 32; ++kc) w3[kc] = load8(M.W3b + (size_t)r * MH + 32 * kc + 8 * g);
     b3 = M.P[OFF_B3 + r];
+  }
+  // rows past the workgroup's keypoints stay zero
+  if constexpr (W < kTileRows) {
+    for (int i = (int)threadIdx.x; i < (kTileRows - W) * MI; i += 64 * W) sX[W + i / MI][i % MI] = 0;
   }
 
   // ---- the 8 nearest tracks with a flow (keypoint j = j0 + wave) -----------
@@ -175,7 +191,7 @@ __global__ __launch_bounds__(64 * kLearnWaves) void k_learn(const CamDesc* __res
   for (int c0 = 0; c0 < n; c0 += kCandChunk) {
     const int nc = min(kCandChunk, n - c0);
     __syncthreads();  // the previous chunk has been read
-    for (int i = (int)threadIdx.x; i < nc; i += 64 * kLearnWaves) {
+    for (int i = (int)threadIdx.x; i < nc; i += 64 * W) {
       const Kp o = live[c0 + i];
       sCand[i] = o.age >= 1 ? make_float2(o.x, o.y) : make_float2(__int_as_float(0x7FC00000), 0.f);
     }
@@ -262,27 +278,38 @@ __global__ __launch_bounds__(64 * kLearnWaves) void k_learn(const CamDesc* __res
 
   // ---- network: 32 -> 128 -> 128 -> 3 --------------------------------------
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-  const int jn = 16 * wv + r;
-  if (wv < MH / 16) {
-    const f32x4 acc = mfma(load8(&sX[r][8 * g]), w1, zero);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = 4 * g + q;
-      sH[row][jn] = j0 + row < n ? bf16_bits(fmaxf(acc[q] + b1, 0.f)) : (uint16_t)0;
+  for (int t = 0; t < kTPW; ++t) {
+    const int tile = wv + W * t;
+    if (tile < kHidTiles) {
+      const f32x4 acc = mfma(load8(&sX[r][8 * g]), w1[t], zero);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 4 * g + q;
+        sH[row][16 * tile + r] = row < W && j0 + row < n ? bf16_bits(fmaxf(acc[q] + b1[t], 0.f)) : (uint16_t)0;
+      }
     }
   }
   __syncthreads();
-  f32x4 acc2 = zero;
-  if (wv < MH / 16) {
+  f32x4 acc2[kTPW];
 #pragma unroll
-    for (int kc = 0; kc < MH / 32; ++kc) acc2 = mfma(load8(&sH[r][32 * kc + 8 * g]), w2[kc], acc2);
+  for (int t = 0; t < kTPW; ++t) {
+    acc2[t] = zero;
+    if (wv + W * t < kHidTiles) {
+#pragma unroll
+      for (int kc = 0; kc < MH / 32; ++kc) acc2[t] = mfma(load8(&sH[r][32 * kc + 8 * g]), w2[t][kc], acc2[t]);
+    }
   }
   __syncthreads();  // every wave has read h1
-  if (wv < MH / 16) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = 4 * g + q;
-      sH[row][jn] = j0 + row < n ? bf16_bits(fmaxf(acc2[q] + b2, 0.f)) : (uint16_t)0;
+  for (int t = 0; t < kTPW; ++t) {
+    const int tile = wv + W * t;
+    if (tile < kHidTiles) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 4 * g + q;
+        sH[row][16 * tile + r] = row < W && j0 + row < n ? bf16_bits(fmaxf(acc2[t][q] + b2[t], 0.f)) : (uint16_t)0;
+      }
     }
   }
   __syncthreads();
@@ -294,7 +321,7 @@ __global__ __launch_bounds__(64 * kLearnWaves) void k_learn(const CamDesc* __res
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = 4 * g + q;
-        if (j0 + row < n) guess[(size_t)(cd.row_off + j0 + row) * MO + r] = acc[q] + b3;
+        if (row < W && j0 + row < n) guess[(size_t)(cd.row_off + j0 + row) * MO + r] = acc[q] + b3;
       }
     }
   }
@@ -302,14 +329,27 @@ __global__ __launch_bounds__(64 * kLearnWaves) void k_learn(const CamDesc* __res
 
 }  // namespace
 
-hipError_t launch_learn(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt, const CamDesc* h_cams,
-                        int cam_begin, int cam_end, const MlpDev& M, float* d_feat, float* d_guess, hipStream_t s) {
-  if (cam_end <= cam_begin) return hipSuccess;
+template <int W>
+static hipError_t launch_learn_w(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt,
+                                 const CamDesc* h_cams, int cam_begin, int cam_end, const MlpDev& M, float* d_feat,
+                                 float* d_guess, hipStream_t s) {
   int blocks = 0;
-  for (int c = cam_begin; c < cam_end; ++c) blocks += (h_cams[c].cap + kLearnWaves - 1) / kLearnWaves;
-  launch_kernel(k_learn, dim3(blocks), dim3(64 * kLearnWaves), 0, s, d_cams, d_frame, d_cnt, cam_begin, cam_end, M,
-                d_feat, d_guess);
+  for (int c = cam_begin; c < cam_end; ++c) blocks += (h_cams[c].cap + W - 1) / W;
+  launch_kernel(k_learn<W>, dim3(blocks), dim3(64 * W), 0, s, d_cams, d_frame, d_cnt, cam_begin, cam_end, M, d_feat,
+                d_guess);
   return hipGetLastError();
+}
+
+hipError_t launch_learn(const CamDesc* d_cams, const FrameTable* d_frame, const Counters* d_cnt, const CamDesc* h_cams,
+                        int cam_begin, int cam_end, const MlpDev& M, float* d_feat, float* d_guess, int waves,
+                        hipStream_t s) {
+  if (cam_end <= cam_begin) return hipSuccess;
+  switch (waves) {
+    case 4: return launch_learn_w<4>(d_cams, d_frame, d_cnt, h_cams, cam_begin, cam_end, M, d_feat, d_guess, s);
+    case 8: return launch_learn_w<8>(d_cams, d_frame, d_cnt, h_cams, cam_begin, cam_end, M, d_feat, d_guess, s);
+    case 16: return launch_learn_w<16>(d_cams, d_frame, d_cnt, h_cams, cam_begin, cam_end, M, d_feat, d_guess, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace vio
