@@ -2,10 +2,13 @@
 //
 // Device memory is one arena allocated at create (Sec. III-B: every resource
 // is allocated once and reused). Per frame the runtime fills a small frame
-// table in pinned memory, copies it (and the images, for a host push) to the
-// device, launches three kernels on one stream and waits: the synchronous
-// submit-and-fence of the paper's pipeline. The last kernel writes the
-// records into mapped pinned host memory, so nothing is copied back.
+// table in pinned memory and launches the frame's kernels on two streams: the
+// pyramid stream runs the pyramid+detector kernel (which copies the table to
+// the device and, for a host push, reads the staged images); the launch
+// stream runs the learned stage, then, once the pyramid stream's signal says
+// the pyramid is done, the tracker and the selection. The selection writes
+// the records into mapped pinned host memory, so nothing is copied back; the
+// host fences on an event after the selection.
 //
 // Per camera and frame parity p the arena holds: pyramid levels, keypoint
 // state, per-cell winner keys; plus temporal and stereo results and records.
@@ -18,6 +21,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -154,6 +159,10 @@ struct vio_frontend {
   hipStream_t stream = nullptr;   // the launch stream: learned stage, tracking, selection
   hipStream_t pstream = nullptr;  // frame-table copies and pyramids/detections
   hipEvent_t ev_pyr[2] = {}, ev_in = nullptr;  // per slot: pyramid done; a caller stream's images ready
+  // the pyramid stream's completion count in signal memory (stream value
+  // operations; null: events ev_pyr instead)
+  uint32_t* pyr_sig = nullptr;
+  uint32_t pyr_epoch = 0;  // the last value the pyramid stream was asked to write
   hipEvent_t ev[2][2] = {};  // per submission slot: frame start and end on the launch stream
   // eager launches: start/stop events attached to each kernel's dispatch
   // (pyramid+detector, features, network, tracker, selection)
@@ -169,6 +178,49 @@ struct vio_frontend {
 };
 
 namespace {
+
+// Signals of the pyramid streams: 8-byte signal-memory allocations, one per
+// live handle, taken from a per-device pool that is never freed (a handle
+// returns its signal with its last value, and the next handle on the device
+// continues from there). The launch stream waits for the value the pyramid
+// stream writes after the frame's pyramid: for the host about ten
+// microseconds per frame less than an event record and a wait on it.
+struct PyrSignal {
+  uint32_t* ptr;
+  uint32_t last;
+};
+std::mutex g_sig_mu;
+std::map<int, std::vector<PyrSignal>> g_sig_free;  // by device
+std::map<int, bool> g_sig_unsupported;
+
+bool signal_acquire(int device, uint32_t** ptr, uint32_t* last) {
+  std::lock_guard<std::mutex> lk(g_sig_mu);
+  std::vector<PyrSignal>& fr = g_sig_free[device];
+  if (!fr.empty()) {
+    *ptr = fr.back().ptr;
+    *last = fr.back().last;
+    fr.pop_back();
+    return true;
+  }
+  if (g_sig_unsupported[device]) return false;
+  int can = 0;
+  void* p = nullptr;
+  if (hipDeviceGetAttribute(&can, hipDeviceAttributeCanUseStreamWaitValue, device) != hipSuccess || !can ||
+      hipExtMallocWithFlags(&p, 8, hipMallocSignalMemory) != hipSuccess || hipMemset(p, 0, 8) != hipSuccess) {
+    // events instead (an allocation that could not be cleared is left alone)
+    g_sig_unsupported[device] = true;
+    (void)hipGetLastError();
+    return false;
+  }
+  *ptr = static_cast<uint32_t*>(p);
+  *last = 0;
+  return true;
+}
+
+void signal_release(int device, uint32_t* ptr, uint32_t last) {
+  std::lock_guard<std::mutex> lk(g_sig_mu);
+  g_sig_free[device].push_back(PyrSignal{ptr, last});
+}
 
 int fail(vio_frontend* h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int fail(vio_frontend* h, int code, const char* fmt, ...) {
@@ -298,6 +350,8 @@ void vio_frontend_destroy(vio_frontend* h) {
     if (h->ev_pyr[slot]) (void)hipEventDestroy(h->ev_pyr[slot]);
   }
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  // the streams were synchronized above: the signal holds its last value
+  if (h->pyr_sig) signal_release(h->device, h->pyr_sig, h->pyr_epoch);
   if (h->stream) (void)hipStreamDestroy(h->stream);
   if (h->pstream) (void)hipStreamDestroy(h->pstream);
   delete h;
@@ -554,6 +608,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_pyr[slot], hipEventDisableTiming));
   }
   HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+  if (!signal_acquire(h->device, &h->pyr_sig, &h->pyr_epoch)) h->pyr_sig = nullptr;
   for (auto& pr : h->ev)
     for (hipEvent_t& e : pr) HIP_CHECK(h, hipEventCreate(&e));
   for (auto& pr : h->kev)
@@ -708,17 +763,24 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
   return launch_select(h->d_cams, h->d_frame, h->d_cnt, sc, ls.n_streams, kSelectRight, tune, st);
 }
 
-// A frame runs on two streams. The pyramid stream copies the slot's frame
-// table and builds the pyramid and detections; the launch stream, after the
-// copy, runs the learned stage (its inputs are the previous frame's
-// keypoints and level 0, so it runs beside the pyramid) and, after the
-// pyramid, the tracker and the selection. The pyramid slots rotate over
-// three frames, so the next frame's pyramid can run beside this frame's
-// tracking.
+// A frame runs on two streams. The pyramid stream builds the pyramid and
+// detections (its kernel copies the slot's frame table to the device) and
+// then raises its signal; the launch stream runs the learned stage (its
+// inputs are the previous frame's keypoints and level 0, so it runs beside
+// the pyramid) and, once the signal reaches the frame's count, the tracker
+// and the selection. The pyramid slots rotate over three frames, so the next
+// frame's pyramid can run beside this frame's tracking.
 static hipError_t enqueue_pyr_part(vio_frontend* h, const LaunchSet& ls, int slot, bool timed) {
   hipError_t e;
   if ((e = enqueue_stage(h, ls, h->pstream, 1, timed))) return e;
+  if (h->pyr_sig) return hipStreamWriteValue32(h->pstream, h->pyr_sig, ++h->pyr_epoch, 0);
   return hipEventRecord(h->ev_pyr[slot], h->pstream);
+}
+
+// The launch stream waits for the pyramid part of the frame just enqueued.
+static hipError_t wait_pyr_part(vio_frontend* h, hipStream_t st, int slot) {
+  if (h->pyr_sig) return hipStreamWaitValue32(st, h->pyr_sig, h->pyr_epoch, hipStreamWaitValueGte, 0xFFFFFFFFu);
+  return hipStreamWaitEvent(st, h->ev_pyr[slot], 0);
 }
 
 static hipError_t enqueue_track_part(vio_frontend* h, const LaunchSet& ls, hipStream_t st, bool timed) {
@@ -763,6 +825,14 @@ static int complete_all(vio_frontend* h);
 // the next submission (their kernel timing events are shared).
 static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t st) {
   if (h->n_pend == 2) return fail(h, VIO_ESTATE, "two frames in flight: call vio_frontend_wait first");
+  if (h->pyr_sig && h->pyr_epoch >= 0x80000000u) {
+    // long before the 32-bit count could wrap: drain, then restart it at zero
+    const int rc = complete_all(h);
+    if (rc != VIO_OK) return rc;
+    HIP_CHECK(h, hipStreamSynchronize(h->pstream));
+    HIP_CHECK(h, hipMemset(h->pyr_sig, 0, 8));
+    h->pyr_epoch = 0;
+  }
   const int slot = (int)(h->sub & 1);
   h->d_frame = h->d_frames[slot];
   h->hm_frame = h->hm_frames[slot];
@@ -790,7 +860,7 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
     if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].learn, st));
     else HIP_CHECK(h, enqueue_stage(h, ls, st, 4, timed));
   }
-  HIP_CHECK(h, hipStreamWaitEvent(st, h->ev_pyr[slot], 0));
+  HIP_CHECK(h, wait_pyr_part(h, st, slot));
   if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].trk, st));
   else HIP_CHECK(h, enqueue_track_part(h, ls, st, timed));
   HIP_CHECK(h, hipEventRecord(h->ev[slot][1], st));
