@@ -15,7 +15,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_SAN = os.environ.get("VIO_SANITIZE") == "1"
+# VIO_SANITIZE=1: built with clang's AddressSanitizer and UndefinedBehaviorSanitizer instead
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SAN else "liboracle.so")
 _lib = None
 
 TRACKED, DETECTED, MATCHED, LOST_FB, LOST_OOB, LOST_DEGENERATE, LOST_CAP = range(7)
@@ -27,9 +29,18 @@ RECORD_DTYPE = np.dtype([
 assert RECORD_DTYPE.itemsize == 40
 
 
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
+
+
 def build() -> str:
-    """Compile the oracle with g++ -O2 (no fast-math, no SIMD intrinsics)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+    """Compile the oracle with g++ -O2 (no fast-math, no SIMD intrinsics); with VIO_SANITIZE=1, with
+    ROCm's clang and the address and undefined-behaviour sanitizers (one runtime with the product
+    library's sanitized host code)."""
+    if _SAN:
+        cmd = ["/opt/rocm/llvm/bin/clang++", "-O1", *SAN_FLAGS, "-std=c++17", "-shared", "-fPIC", "-o",
+               _LIB + ".tmp", _SRC]
+    else:
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvio_frontend.so")
+# VIO_SANITIZE=1: the variant whose host code carries AddressSanitizer and UndefinedBehaviorSanitizer
+LIB_PATH = os.path.join(_HERE, "libvio_frontend_san.so" if os.environ.get("VIO_SANITIZE") == "1"
+                        else "libvio_frontend.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

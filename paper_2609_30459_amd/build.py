@@ -9,6 +9,9 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libvio_frontend.so")
+# host code built with AddressSanitizer and UndefinedBehaviorSanitizer (device code as usual); loaded
+# instead of LIB when VIO_SANITIZE=1 (tests/sanitize.py)
+LIB_SAN = os.path.join(PKG, "libvio_frontend_san.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -23,21 +26,27 @@ HIPCC_FLAGS = [
 ]
 
 
+# host-only sanitizer flags: each -fsanitize= right after -Xarch_host
+SAN_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
 def sources():
     return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compiles every translation unit to an object, then links the shared library."""
+def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False) -> str:
+    """Compiles every translation unit to an object, then links the shared library (sanitize: the
+    host-sanitized variant LIB_SAN, objects in their own folder)."""
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-    objdir = os.path.join(PKG, "_build")
+    objdir = os.path.join(PKG, "_build_san" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
     procs, objs = [], []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc, *HIPCC_FLAGS, *inc, "-c", src, "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *(SAN_HOST_FLAGS if sanitize else []), *inc, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -55,11 +64,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         for src, text in failed:
             sys.stderr.write(f"--- {src}\n{text}\n")
         raise RuntimeError("hipcc failed for " + ", ".join(os.path.basename(s) for s, _ in failed))
-    tmp = LIB + ".tmp"
-    subprocess.run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    out = LIB_SAN if sanitize else LIB
+    tmp = out + ".tmp"
+    subprocess.run([hipcc, f"--offload-arch={ARCH}", *(SAN_HOST_FLAGS if sanitize else []), "-shared", "-fPIC", "-o",
+                    tmp, *objs], check=True)
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

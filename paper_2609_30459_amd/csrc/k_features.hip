@@ -129,33 +129,6 @@ __global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ ca
   const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6);
   const int r = lane & 15, g = lane >> 4;
 
-  // ---- this wave's weight slices (hidden tiles wv, wv + W, ...) -----------
-  const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  bf16x8 w1[kTPW], w2[kTPW][MH / 32], w3[MH / 32];
-  float b1[kTPW], b2[kTPW], b3 = 0.f;
-#pragma unroll
-  for (int t = 0; t < kTPW; ++t) {
-    const int tile = wv + W * t;
-    w1[t] = pack8(z8);
-    b1[t] = b2[t] = 0.f;
-#pragma unroll
-    for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = pack8(z8);
-    if (tile < kHidTiles) {
-      const int jn = 16 * tile + r;
-      w1[t] = load8(M.W1b + (size_t)jn * MI + 8 * g);
-#pragma unroll
-      for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = load8(M.W2b + (size_t)jn * MH + 32 * kc + 8 * g);
-      b1[t] = M.P[OFF_B1 + jn];
-      b2[t] = M.P[OFF_B2 + jn];
-    }
-  }
-#pragma unroll
-  for (int kc = 0; kc < MH / 32; ++kc) w3[kc] = pack8(z8);
-  if (wv == 0 && r < MO) {
-#pragma unroll
-    for (int kc = 0; kc < MH / 32; ++kc) w3[kc] = load8(M.W3b + (size_t)r * MH + 32 * kc + 8 * g);
-    b3 = M.P[OFF_B3 + r];
-  }
   // rows past the workgroup's keypoints stay zero
   if constexpr (W < kTileRows) {
     for (int i = (int)threadIdx.x; i < (kTileRows - W) * MI; i += 64 * W) sX[W + i / MI][i % MI] = 0;
@@ -177,6 +150,12 @@ __global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ ca
   int px4[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) px4[k] = j < n ? img[(size_t)yy * pitch + min(max(rx - 8 + col4 + k, 0), cd.w - 1)] : 0;
+  // this wave's weight slices (hidden tiles wv, wv + W, ...): loaded behind
+  // the first chunk's staging loads, so the search (LDS only) does not wait
+  // for them and their latency hides behind it
+  const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bf16x8 w1[kTPW], w2[kTPW][MH / 32], w3[MH / 32];
+  float b1[kTPW], b2[kTPW], b3 = 0.f;
   // this lane's best eight exact keys, ascending; +inf / kNone: empty. The
   // camera's tracks are staged in LDS chunk by chunk (no flow: NaN); the lane
   // visits tracks lane, lane + 64, ... of a chunk, so indices rise along its
@@ -196,6 +175,31 @@ __global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ ca
       sCand[i] = o.age >= 1 ? make_float2(o.x, o.y) : make_float2(__int_as_float(0x7FC00000), 0.f);
     }
     __syncthreads();
+    if (c0 == 0) {
+#pragma unroll
+      for (int t = 0; t < kTPW; ++t) {
+        const int tile = wv + W * t;
+        w1[t] = pack8(z8);
+        b1[t] = b2[t] = 0.f;
+#pragma unroll
+        for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = pack8(z8);
+        if (tile < kHidTiles) {
+          const int jn = 16 * tile + r;
+          w1[t] = load8(M.W1b + (size_t)jn * MI + 8 * g);
+#pragma unroll
+          for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = load8(M.W2b + (size_t)jn * MH + 32 * kc + 8 * g);
+          b1[t] = M.P[OFF_B1 + jn];
+          b2[t] = M.P[OFF_B2 + jn];
+        }
+      }
+#pragma unroll
+      for (int kc = 0; kc < MH / 32; ++kc) w3[kc] = pack8(z8);
+      if (wv == 0 && r < MO) {
+#pragma unroll
+        for (int kc = 0; kc < MH / 32; ++kc) w3[kc] = load8(M.W3b + (size_t)r * MH + 32 * kc + 8 * g);
+        b3 = M.P[OFF_B3 + r];
+      }
+    }
     if (j < n) {
       for (int k0 = 0; k0 < nc; k0 += 64) {
         const int k = k0 + lane;

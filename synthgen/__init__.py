@@ -18,13 +18,21 @@ from .workloads import WORKLOADS, Workload, eval_seed, splitmix64  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "synthgen.cpp")
-_LIB = os.path.join(_HERE, "libsynthgen.so")
+_SAN = os.environ.get("VIO_SANITIZE") == "1"
+# VIO_SANITIZE=1: built with clang's AddressSanitizer and UndefinedBehaviorSanitizer instead
+_LIB = os.path.join(_HERE, "libsynthgen_san.so" if _SAN else "libsynthgen.so")
 _lib = None
 
 
 def build() -> str:
-    """Compile the renderer with g++ (host code only)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _LIB + ".tmp", _SRC]
+    """Compile the renderer with g++ (host code only); with VIO_SANITIZE=1, with ROCm's clang and the
+    address and undefined-behaviour sanitizers."""
+    if _SAN:
+        cmd = ["/opt/rocm/llvm/bin/clang++", "-O1", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+               "-fno-omit-frame-pointer", "-g", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _LIB + ".tmp",
+               _SRC]
+    else:
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _LIB + ".tmp", _SRC]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB

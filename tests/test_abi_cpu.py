@@ -118,3 +118,20 @@ def test_null_handle_calls_are_safe(native):
     assert native.lib.vio_frontend_push_stereo_frame(None, 0, 0, None, None, None, 0) == native.VIO_EINVAL
     native.lib.vio_frontend_destroy(None)
     assert native.lib.vio_frontend_last_error(None) == b"null handle"
+
+
+def test_sanitized_run_loads_the_sanitized_variants():
+    """Under tests/sanitize.py (VIO_SANITIZE=1): the sanitizer runtime and the
+    three *_san.so libraries are the ones mapped into the process."""
+    if os.environ.get("VIO_SANITIZE") != "1":
+        pytest.skip("not a sanitized run")
+    import oracle
+    import synthgen
+    from paper_2609_30459_amd import _native
+    oracle._lib_()
+    synthgen._load()
+    maps = open("/proc/self/maps").read()
+    assert "libclang_rt.asan" in maps
+    for name in ("liboracle_san.so", "libsynthgen_san.so", "libvio_frontend_san.so"):
+        assert name in maps, name
+    assert _native.LIB_PATH.endswith("libvio_frontend_san.so")
