@@ -18,8 +18,8 @@ camera, run twice:
 Each leg's sequence is resident in HBM before timing starts. A step stages
 one frame's device images of every stream through the C ABI, submits it and
 reads the records back. The first timed region of a leg is the production
-path: pipelined submission (frame t is submitted before frame t-1's records
-are waited for and read, two frames in flight) with the kernels launched one
+path: pipelined submission (frame t is submitted before frame t-2's records
+are waited for and read, three frames in flight) with the kernels launched one
 by one (`--launch graph`: captured graphs; `--no-pipeline`: one frame at a
 time). A second region runs the same steps one frame at a time with each
 kernel's HIP start/stop events attached to its own dispatch: it gives the
@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--launch", choices=["plain", "graph", "eager"], default="plain",
                     help="first timed region: kernels launched one by one without timestamps (default), captured "
                          "graphs, or one by one with HIP events attached to each dispatch")
+    ap.add_argument("--in-flight", type=int, choices=[2, 3], default=3,
+                    help="frames in flight on the pipelined path (the library allows up to three)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="one frame at a time (no frame submitted before the last one's records are read)")
     ap.add_argument("--no-second-launch", "--no-graph-replay", dest="no_second", action="store_true",
@@ -164,6 +166,8 @@ def main():
     ap.add_argument("--block-waves", type=int, default=None, help="tracker waves per workgroup (1, 2, 4)")
     ap.add_argument("--learned-block-waves", type=int, choices=[4, 8, 16], default=None,
                     help="keypoints per learned-stage workgroup")
+    ap.add_argument("--learned-fused", type=int, choices=[0, 1], default=None,
+                    help="learned stage inside the tracker launch (default: on for one stream, off when batched)")
     ap.add_argument("--tile", type=int, default=None, help="pyramid/detector tile edge (32, 64)")
     ap.add_argument("--stereo-mode", type=int, default=None, help="0 speculative, 1 deferred stereo matching")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -223,7 +227,7 @@ def main():
     def launch_choice(init):
         """Launch parameters (never change the records): explicit flags, else the autotuned choice."""
         wpc, bw, tile, smode = args.waves_per_cu, args.block_waves, args.tile, args.stereo_mode
-        pfb, lbw = args.parallel_fallback, args.learned_block_waves
+        pfb, lbw, lfu = args.parallel_fallback, args.learned_block_waves, args.learned_fused
         tuned = None
         if wpc is None and bw is None and tile is None and smode is None:
             from paper_2609_30459_amd import autotune
@@ -235,11 +239,16 @@ def main():
                     pfb = tuned["track_parallel_fallback"]
                 if lbw is None and "learned_block_waves" in tuned:
                     lbw = tuned["learned_block_waves"]
+                if lfu is None and "learned_fused" in tuned:
+                    lfu = tuned["learned_fused"]
         if pfb is None:
             pfb = 0 if batched else 1
+        if lfu is None:
+            lfu = 0 if batched else 1
         return dict(track_waves_per_cu=wpc or 0, track_block_waves=bw or 4, pyr_tile=tile or 64,
                     stereo_mode=smode or 0, track_parallel_fallback=pfb if init == "learned" else 0,
-                    learned_block_waves=(lbw or 0) if init == "learned" else 0), \
+                    learned_block_waves=(lbw or 0) if init == "learned" else 0,
+                    learned_fused=lfu if init == "learned" else 0), \
             tuned is not None
 
     mlp = None
@@ -308,6 +317,7 @@ def main():
         records = [[] for _ in ws]
         wall, stats = [], []
         pipelined = not eager and not args.no_pipeline
+        depth = args.in_flight
         t_sub = {}
 
         def submit(t):
@@ -334,7 +344,8 @@ def main():
                 records[0].append(fe.get_tracks(0))
             return time.perf_counter() - t_sub.pop(t)
 
-        log(f"{init}: warmup {warmup} steps ({'eager' if eager else args.launch}{', pipelined' if pipelined else ''})")
+        log(f"{init}: warmup {warmup} steps ({'eager' if eager else args.launch}"
+            f"{f', {depth} frames in flight' if pipelined else ''})")
         for t in range(warmup):
             submit(t)
             collect(t)
@@ -348,14 +359,16 @@ def main():
         for t in range(warmup, n_frames):
             submit(t)
             if pipelined:
-                if t > warmup:
-                    wall.append(collect(t - 1))
+                # frame t - depth + 1 is read while the later ones run
+                if t - warmup >= depth - 1:
+                    wall.append(collect(t - depth + 1))
             else:
                 wall.append(collect(t))
                 if eager:
                     stats.append(fe.stats())
         if pipelined:
-            wall.append(collect(n_frames - 1))
+            for t in range(max(warmup, n_frames - depth + 1), n_frames):
+                wall.append(collect(t))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         gc.enable()
@@ -504,7 +517,8 @@ def main():
                        else {"levels": L, "iters": N, "stereo_start": "prior"}),
             "launch": {**{k: v for k, v in extra.items() if k in ("track_waves_per_cu", "track_block_waves",
                                                                    "pyr_tile", "stereo_mode",
-                                                                   "track_parallel_fallback", "learned_block_waves")},
+                                                                   "track_parallel_fallback", "learned_block_waves",
+                                                                   "learned_fused")},
                        "autotuned": tuned},
             "roofline": roof, "second_launch": second, "kernels": kernels,
             "host_image": None if args.no_host_leg else host_run(init),
@@ -597,6 +611,7 @@ def main():
                       if short_pred else {}),
                    "cell_size": sorted({w.cell_size for w in ws}), "thresholds": list(w0.thresholds),
                    "launch": args.launch, "pipelined": args.launch != "eager" and not args.no_pipeline,
+                   "in_flight": args.in_flight if args.launch != "eager" and not args.no_pipeline else 1,
                    "parallelism": "single_gpu"},
         "tracked_kpts_per_s": vb["tracked_kpts_per_s"],
         "gpu_ms_per_step": vb["gpu_ms_per_step"],

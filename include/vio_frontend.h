@@ -154,6 +154,12 @@ typedef struct vio_frontend_params {
    * workgroup of the learned stage, 4, 8 or 16 (0 = 4); fewer spread a camera's
    * keypoints over more compute units. */
   int32_t learned_block_waves;
+  /* Launch choice that never changes the records: 1 = the learned stage runs
+   * inside the tracker launch (each learned temporal track computes its own
+   * features and network output before its short attempt, beside the stereo
+   * and fallback work) instead of as a launch of its own before it; 0 = its
+   * own launch. */
+  int32_t learned_fused;
 } vio_frontend_params;
 
 #define VIO_STEREO_INIT_PRIOR 0
@@ -243,9 +249,8 @@ typedef struct vio_stats {
   double last_stage_ms[3]; /* durations of the last frame's pyramid+detector, tracker and selection
                               kernels from their own dispatch timestamps (HIP events attached to the
                               launch); -1 unless launched one by one (VIO_FLAG_EAGER) */
-  double last_learned_ms[2]; /* the same for the learned initialisation's kernel (features and
-                                network in one launch) in [0]; [1] is -1 (the neighbour grids are
-                                built by the selection kernel) */
+  double last_learned_ms[2]; /* the same for the learned stage's own launch (features and network) in
+                                [0], -1 when it is fused into the tracker; [1] is -1 (unused) */
   int32_t last_tracked;  /* VIO_TRACKED records of the last frame, all cameras */
   int32_t last_lost;     /* lost temporal records of the last frame */
   int32_t last_detected; /* VIO_DETECTED records */
@@ -303,11 +308,13 @@ int vio_frontend_step(vio_frontend* h);
 
 /* Pipelined stepping: vio_frontend_step_async submits the staged streams'
  * frames like vio_frontend_step but returns without waiting; while it runs
- * the host may stage the next frames and submit them too (at most two frames
- * in flight: staging, pushing or submitting a third returns VIO_ESTATE).
- * vio_frontend_wait waits for the oldest frame in flight (VIO_ESTATE when
- * none); afterwards vio_frontend_get_tracks returns its records, while the
- * next frame may still run (records are double-buffered by frame parity).
+ * the host may stage the next frames and submit them too (at most three
+ * frames in flight: staging, pushing or submitting a fourth returns
+ * VIO_ESTATE). vio_frontend_wait waits for the oldest frame in flight
+ * (VIO_ESTATE when none); afterwards vio_frontend_get_tracks returns its
+ * records, while the later frames may still run (records rotate over three
+ * buffers by frame: a completed frame's records stay valid until the next
+ * submission).
  * Every other call (pushes, keypoint and diagnostic calls) first waits for
  * all frames in flight. Device images staged for a frame must stay valid
  * until that frame is waited for. vio_frontend_in_flight returns the number

@@ -36,6 +36,11 @@ inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t lds, hipStre
 constexpr int kBufferWord3 = 0x00020000;
 constexpr int kTrackWaves = 4;  // most waves (keypoints) per tracking block
 constexpr int kLearnWavesDefault = 4;  // keypoints (waves) per learned-stage workgroup
+// Frames a handle may have in flight; a camera's pyramid slots hold those
+// frames' pyramids and the previous frame's, its record slots one frame each.
+constexpr int kInFlight = 3;
+constexpr int kPyrSlots = kInFlight + 1;
+constexpr int kRecSlots = kInFlight;
 constexpr int kSelectThreads = 1024;
 
 // Live keypoint, 32 bytes (same layout as vio_keypoint).
@@ -78,19 +83,19 @@ struct CamDesc {
   int local;           // camera index within its stream
   int tiles_x, tiles_y, tile_begin;  // pyramid/detector tiles of this camera
   int pitch[kMaxLevels];
-  uint8_t* lvl[3][kMaxLevels];       // three pyramid slots (frame index mod 3: the next frame's pyramid
-                                     // is built while the last two frames' are still read)
+  uint8_t* lvl[kPyrSlots][kMaxLevels];  // pyramid slots (frame index mod kPyrSlots: the frames in flight
+                                        // and the one before them)
   Kp* state[2];                      // keypoint state, double-buffered by frame parity
   TrackRes* res;                     // temporal results [cap]
   TrackRes* res_fb;                  // parallel fallbacks of short temporal attempts [cap] (or null)
-  uint32_t* keys[3];                 // packed winner keys, slot cell * k + rank, by pyramid slot [nslots]
+  uint32_t* keys[kPyrSlots];         // packed winner keys, slot cell * k + rank, by pyramid slot [nslots]
   TrackRes* sres;                    // stereo matches [n_targets][nslots], by key slot or selection rank
   const uint8_t* mask;               // detection mask [h][w] (detecting cameras)
-  // outputs in mapped pinned host memory, by frame parity (the host reads one
-  // frame's while the next frame runs)
-  vio_track* rec[2];                 // records [rec_cap]
-  int32_t* rec_count_out[2];         // record count
-  int32_t* stats_out[2];             // [kCamStats] counts (CamStat)
+  // outputs in mapped pinned host memory, by record slot (frame index mod
+  // kRecSlots: the host reads one frame's while the later ones run)
+  vio_track* rec[kRecSlots];         // records [rec_cap]
+  int32_t* rec_count_out[kRecSlots]; // record count
+  int32_t* stats_out[kRecSlots];     // [kCamStats] counts (CamStat)
   int rec_cap;
   int row_off;                       // first row of this camera in the learned-init feature/guess buffers
   // target cameras with the neighbour stereo start: the keypoints that live in
@@ -115,8 +120,9 @@ struct FrameCam {
   const uint8_t* src;  // level-0 image to read (own level 0 or the caller's)
   int src_pitch;
   int copy_l0;         // 1: write src into the own level-0 buffer
-  int parity;          // keypoint state and record slot; the previous frame's is parity ^ 1
-  int pyr, pyr_prev;   // pyramid and key slots (frame index mod 3) of this and the previous frame
+  int parity;          // keypoint state slot; the previous frame's is parity ^ 1
+  int pyr, pyr_prev;   // pyramid and key slots (frame index mod kPyrSlots) of this and the previous frame
+  int rec_slot;        // record slot (frame index mod kRecSlots)
   int has_prev;        // a previous frame exists (temporal tracking runs)
   int active;          // camera takes part in this frame
   int n_pred;          // caller predictions for this camera (ascending id)
@@ -176,6 +182,14 @@ struct Tuning {
   int stereo_nb;          // stereo matches start from the nearest paired keypoint's offset
   int slevels, siters;    // budget of such a match
   int par_fb;             // short temporal attempts' fallbacks run as items of their own (CamDesc::res_fb)
+  // learned stage fused into the tracker: each learned temporal item computes
+  // its own features (into feat) and network output before its short attempt
+  int fused;
+  float* feat;            // [rows][32] network inputs (learned mode)
+  const uint16_t* W1b;    // the network's bf16 weights and FP32 parameters (fused learned stage)
+  const uint16_t* W2b;
+  const uint16_t* W3b;
+  const float* mlpP;
 };
 
 // Learned-initialisation network on the device (see vio_mlp.h).

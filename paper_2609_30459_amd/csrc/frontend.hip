@@ -10,8 +10,8 @@
 // the records into mapped pinned host memory, so nothing is copied back; the
 // host fences on an event after the selection.
 //
-// Per camera and frame parity p the arena holds: pyramid levels, keypoint
-// state, per-cell winner keys; plus temporal and stereo results and records.
+// Per camera the arena holds: pyramid levels and per-cell winner keys by
+// pyramid slot, keypoint state by frame parity, temporal and stereo results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -69,7 +69,7 @@ struct StreamInfo {
   bool staged = false;     // a frame is staged for the next vio_frontend_step
   int64_t staged_t = 0;
   size_t rec_off = 0, rec_n = 0;  // record range (in vio_track units) of the stream's cameras
-  Graphs graph[2];                 // captured per-frame submit by submission slot, replayed every frame
+  Graphs graph[kInFlight];         // captured per-frame submit by submission slot, replayed every frame
   // camera-model start for the next frame (vio_frontend_set_motion)
   std::vector<vio_camera_motion> motion;  // at most one per camera
   std::vector<vio_kp_depth> depths;       // sorted by (camera, id)
@@ -102,7 +102,7 @@ struct vio_frontend {
   vio_frontend_params P{};
   int n_cus = 256;
   int tile = kTileDefault;  // pyramid/detector tile edge
-  Graphs graph_all[2];  // captured batched step by submission slot
+  Graphs graph_all[kInFlight];  // captured batched step by submission slot
   std::vector<StreamInfo> streams;
   std::vector<CamDesc> cams;
   std::vector<TrackSeg> segs;      // per stream: the stream's items are contiguous
@@ -113,7 +113,7 @@ struct vio_frontend {
   // device
   void* arena = nullptr;
   CamDesc* d_cams = nullptr;
-  FrameTable* d_frames[2] = {nullptr, nullptr};  // by submission slot
+  FrameTable* d_frames[kInFlight] = {};  // by submission slot
   FrameTable* d_frame = nullptr;                 // the slot being launched
   Counters* d_cnt = nullptr;
   TrackSeg* d_segs = nullptr;
@@ -131,16 +131,16 @@ struct vio_frontend {
   MlpDev mlp{};
   float* d_feat = nullptr;   // [rows][32]
   float* d_guess = nullptr;  // [rows][3]
-  int32_t* h_camstats = nullptr;  // [parity][cameras][kCamStats], written by the selection kernel
+  int32_t* h_camstats = nullptr;  // [record slot][cameras][kCamStats], written by the selection kernel
   // pinned host
-  // Submissions alternate between two slots: the frame table, the host image
+  // Submissions rotate over kInFlight slots: the frame table, the host image
   // staging and the prediction / depth lists being filled belong to slot
-  // sub & 1, so the next frame can be staged while the previous one runs.
-  // Records, their counts and the per-camera counts are double-buffered by
-  // each camera's frame parity instead.
-  FrameTable* h_frames[2] = {nullptr, nullptr};
-  FrameTable* h_frame = nullptr;  // h_frames[sub & 1]
-  FrameTable* hm_frames[2] = {nullptr, nullptr};  // device mappings of h_frames
+  // sub % kInFlight, so the next frame can be staged while earlier ones run.
+  // Records, their counts and the per-camera counts rotate over kRecSlots
+  // buffers by each camera's frame index instead.
+  FrameTable* h_frames[kInFlight] = {};
+  FrameTable* h_frame = nullptr;  // h_frames[sub % kInFlight]
+  FrameTable* hm_frames[kInFlight] = {};  // device mappings of h_frames
   FrameTable* hm_frame = nullptr;                 // the slot being launched
   int64_t sub = 0;                // submissions so far
   struct Pending {
@@ -148,22 +148,22 @@ struct vio_frontend {
     bool graphed;
     int slot;
   };
-  Pending pend[2];
+  Pending pend[kInFlight];
   int n_pend = 0, pend_head = 0;  // submitted, not yet completed (oldest first)
-  int32_t* h_rec_count = nullptr; // [parity][cameras]
-  vio_track* h_rec = nullptr;     // [parity][rec_total]
+  int32_t* h_rec_count = nullptr; // [record slot][cameras]
+  vio_track* h_rec = nullptr;     // [record slot][rec_total]
   uint8_t* h_stage = nullptr;     // [slot][stage_bytes]
   size_t stage_bytes = 0;
   Prediction* h_pred = nullptr;  // [slot][pred_cap]
   KpDepth* h_depth = nullptr;    // [slot][pred_cap]
   hipStream_t stream = nullptr;   // the launch stream: learned stage, tracking, selection
   hipStream_t pstream = nullptr;  // frame-table copies and pyramids/detections
-  hipEvent_t ev_pyr[2] = {}, ev_in = nullptr;  // per slot: pyramid done; a caller stream's images ready
+  hipEvent_t ev_pyr[kInFlight] = {}, ev_in = nullptr;  // per slot: pyramid done; a caller stream's images ready
   // the pyramid stream's completion count in signal memory (stream value
   // operations; null: events ev_pyr instead)
   uint32_t* pyr_sig = nullptr;
   uint32_t pyr_epoch = 0;  // the last value the pyramid stream was asked to write
-  hipEvent_t ev[2][2] = {};  // per submission slot: frame start and end on the launch stream
+  hipEvent_t ev[kInFlight][2] = {};  // per submission slot: frame start and end on the launch stream
   // eager launches: start/stop events attached to each kernel's dispatch
   // (pyramid+detector, features, network, tracker, selection)
   hipEvent_t kev[kKernels][2] = {};
@@ -291,6 +291,7 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   if (p->learned_block_waves != 0 && p->learned_block_waves != 4 && p->learned_block_waves != 8 &&
       p->learned_block_waves != 16)
     return why = "learned_block_waves must be 0, 4, 8 or 16", VIO_EINVAL;
+  if (p->learned_fused != 0 && p->learned_fused != 1) return why = "learned_fused must be 0 or 1", VIO_EINVAL;
   return VIO_OK;
 }
 
@@ -346,7 +347,7 @@ void vio_frontend_destroy(vio_frontend* h) {
   for (auto& pr : h->ev)
     for (hipEvent_t& e : pr)
       if (e) (void)hipEventDestroy(e);
-  for (int slot = 0; slot < 2; ++slot) {
+  for (int slot = 0; slot < kInFlight; ++slot) {
     if (h->ev_pyr[slot]) (void)hipEventDestroy(h->ev_pyr[slot]);
   }
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
@@ -370,7 +371,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     return o;
   };
   struct CamOffs {
-    size_t lvl[3][kMaxLevels], state[2], res, res_fb, keys[3], sres, rec, mask, pairs[2];
+    size_t lvl[kPyrSlots][kMaxLevels], state[2], res, res_fb, keys[kPyrSlots], sres, rec, mask, pairs[2];
   };
   // parallel fallbacks exist where a temporal track may first run a short budget
   const bool par_fb = P.track_parallel_fallback && (P.init_mode == VIO_INIT_LEARNED || P.pred_levels > 0);
@@ -417,14 +418,14 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
         c.pitch[l] = (int)round_up((size_t)(si.w >> l), 64);
         // one guard row: the tracker's template window reads up to one row and
         // one column past a level (with weight 0)
-        for (int ps = 0; ps < 3; ++ps)
+        for (int ps = 0; ps < kPyrSlots; ++ps)
           co[cam].lvl[ps][l] = take((size_t)c.pitch[l] * (size_t)((si.h >> l) + 1));
       }
       for (int par = 0; par < 2; ++par) co[cam].state[par] = take(sizeof(Kp) * si.cap);
       co[cam].res = take(sizeof(TrackRes) * si.cap);
       if (par_fb) co[cam].res_fb = take(sizeof(TrackRes) * si.cap);
       if (c.detect) {
-        for (int ps = 0; ps < 3; ++ps) co[cam].keys[ps] = take(sizeof(uint32_t) * c.nslots);
+        for (int ps = 0; ps < kPyrSlots; ++ps) co[cam].keys[ps] = take(sizeof(uint32_t) * c.nslots);
         co[cam].sres = take(sizeof(TrackRes) * c.nslots * std::max(1, c.n_targets));
         co[cam].mask = take((size_t)si.w * si.h);
       } else if (P.stereo_init == VIO_STEREO_INIT_NEIGHBOUR && group > 1) {
@@ -479,7 +480,7 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   h->pred_cap = 0;
   for (auto& c : h->cams) h->pred_cap += c.cap;
   const size_t o_cams = take(sizeof(CamDesc) * n_cams);
-  const size_t o_frame = take(2 * sizeof(FrameTable));
+  const size_t o_frame = take(kInFlight * sizeof(FrameTable));
   const size_t o_cnt = take(sizeof(Counters));
   const size_t o_segs = take(sizeof(TrackSeg) * h->segs.size());
   const size_t o_segs_all = take(sizeof(TrackSeg) * h->segs_all.size());
@@ -531,12 +532,12 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   for (int c = 0; c < n_cams; ++c) {
     CamDesc& d = h->cams[c];
     for (int l = 0; l < P.levels; ++l)
-      for (int ps = 0; ps < 3; ++ps) d.lvl[ps][l] = base + co[c].lvl[ps][l];
+      for (int ps = 0; ps < kPyrSlots; ++ps) d.lvl[ps][l] = base + co[c].lvl[ps][l];
     for (int par = 0; par < 2; ++par) d.state[par] = reinterpret_cast<Kp*>(base + co[c].state[par]);
     d.res = reinterpret_cast<TrackRes*>(base + co[c].res);
     d.res_fb = par_fb ? reinterpret_cast<TrackRes*>(base + co[c].res_fb) : nullptr;
     if (d.detect) {
-      for (int ps = 0; ps < 3; ++ps) d.keys[ps] = reinterpret_cast<uint32_t*>(base + co[c].keys[ps]);
+      for (int ps = 0; ps < kPyrSlots; ++ps) d.keys[ps] = reinterpret_cast<uint32_t*>(base + co[c].keys[ps]);
       d.sres = reinterpret_cast<TrackRes*>(base + co[c].sres);
       d.mask = reinterpret_cast<const uint8_t*>(base + co[c].mask);
     } else if (co[c].pairs[0]) {
@@ -544,7 +545,8 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
     }
   }
   h->d_cams = reinterpret_cast<CamDesc*>(base + o_cams);
-  for (int slot = 0; slot < 2; ++slot) h->d_frames[slot] = reinterpret_cast<FrameTable*>(base + o_frame) + slot;
+  for (int slot = 0; slot < kInFlight; ++slot)
+    h->d_frames[slot] = reinterpret_cast<FrameTable*>(base + o_frame) + slot;
   h->d_frame = h->d_frames[0];
   h->d_cnt = reinterpret_cast<Counters*>(base + o_cnt);
   h->d_segs = reinterpret_cast<TrackSeg*>(base + o_segs);
@@ -572,39 +574,40 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   // pinned host buffers; records and their counts are written by the
   // selection kernel through the device mapping of h_rec / h_rec_count
   h->stage_bytes = stage;
-  if (hipHostMalloc((void**)&h->h_frames[0], sizeof(FrameTable)) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_frames[1], sizeof(FrameTable)) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_rec_count, sizeof(int32_t) * 2 * n_cams) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_camstats, sizeof(int32_t) * kCamStats * 2 * n_cams) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * 2 * rec_total) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_stage, 2 * stage) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * 2 * std::max(1, h->pred_cap)) != hipSuccess ||
-      hipHostMalloc((void**)&h->h_depth, sizeof(KpDepth) * 2 * std::max(1, h->pred_cap)) != hipSuccess)
+  bool host_ok = true;
+  for (FrameTable*& f : h->h_frames) host_ok = host_ok && hipHostMalloc((void**)&f, sizeof(FrameTable)) == hipSuccess;
+  if (!host_ok ||
+      hipHostMalloc((void**)&h->h_rec_count, sizeof(int32_t) * kRecSlots * n_cams) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_camstats, sizeof(int32_t) * kCamStats * kRecSlots * n_cams) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_rec, sizeof(vio_track) * kRecSlots * rec_total) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_stage, kInFlight * stage) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_pred, sizeof(Prediction) * kInFlight * std::max(1, h->pred_cap)) != hipSuccess ||
+      hipHostMalloc((void**)&h->h_depth, sizeof(KpDepth) * kInFlight * std::max(1, h->pred_cap)) != hipSuccess)
     return fail(h, VIO_ENOMEM, "pinned host buffers");
   for (FrameTable* f : h->h_frames) std::memset(f, 0, sizeof(FrameTable));
   h->h_frame = h->h_frames[0];
-  for (int slot = 0; slot < 2; ++slot)
+  for (int slot = 0; slot < kInFlight; ++slot)
     HIP_CHECK(h, hipHostGetDevicePointer((void**)&h->hm_frames[slot], h->h_frames[slot], 0));
   h->hm_frame = h->hm_frames[0];
-  std::memset(h->h_rec_count, 0, sizeof(int32_t) * 2 * n_cams);
-  std::memset(h->h_camstats, 0, sizeof(int32_t) * kCamStats * 2 * n_cams);
+  std::memset(h->h_rec_count, 0, sizeof(int32_t) * kRecSlots * n_cams);
+  std::memset(h->h_camstats, 0, sizeof(int32_t) * kCamStats * kRecSlots * n_cams);
   vio_track* rec_dev = nullptr;
   int32_t *cnt_dev = nullptr, *stats_dev = nullptr;
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&rec_dev, h->h_rec, 0));
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&cnt_dev, h->h_rec_count, 0));
   HIP_CHECK(h, hipHostGetDevicePointer((void**)&stats_dev, h->h_camstats, 0));
   for (int c = 0; c < n_cams; ++c) {
-    for (int par = 0; par < 2; ++par) {
-      h->cams[c].rec[par] = rec_dev + par * rec_total + co[c].rec;
-      h->cams[c].rec_count_out[par] = cnt_dev + par * n_cams + c;
-      h->cams[c].stats_out[par] = stats_dev + (size_t)kCamStats * (par * n_cams + c);
+    for (int rs = 0; rs < kRecSlots; ++rs) {
+      h->cams[c].rec[rs] = rec_dev + rs * rec_total + co[c].rec;
+      h->cams[c].rec_count_out[rs] = cnt_dev + rs * n_cams + c;
+      h->cams[c].stats_out[rs] = stats_dev + (size_t)kCamStats * (rs * n_cams + c);
     }
     h->rec_host_off.push_back(co[c].rec);
   }
   HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
   HIP_CHECK(h, hipStreamCreate(&h->stream));
   HIP_CHECK(h, hipStreamCreate(&h->pstream));
-  for (int slot = 0; slot < 2; ++slot) {
+  for (int slot = 0; slot < kInFlight; ++slot) {
     HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_pyr[slot], hipEventDisableTiming));
   }
   HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
@@ -679,6 +682,12 @@ static Tuning tuning(const vio_frontend* h) {
   t.slevels = h->P.stereo_levels;
   t.siters = h->P.stereo_iters;
   t.par_fb = h->cams.empty() || h->cams[0].res_fb == nullptr ? 0 : 1;
+  t.fused = h->learned && h->P.learned_fused ? 1 : 0;
+  t.feat = h->d_feat;
+  t.W1b = h->mlp.W1b;
+  t.W2b = h->mlp.W2b;
+  t.W3b = h->mlp.W3b;
+  t.mlpP = h->mlp.P;
   return t;
 }
 
@@ -768,8 +777,9 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
 // then raises its signal; the launch stream runs the learned stage (its
 // inputs are the previous frame's keypoints and level 0, so it runs beside
 // the pyramid) and, once the signal reaches the frame's count, the tracker
-// and the selection. The pyramid slots rotate over three frames, so the next
-// frame's pyramid can run beside this frame's tracking.
+// and the selection. The pyramid slots rotate over kPyrSlots frames, so the
+// pyramids of the later frames in flight can run beside this frame's
+// tracking.
 static hipError_t enqueue_pyr_part(vio_frontend* h, const LaunchSet& ls, int slot, bool timed) {
   hipError_t e;
   if ((e = enqueue_stage(h, ls, h->pstream, 1, timed))) return e;
@@ -807,7 +817,7 @@ static void ensure_graph(vio_frontend* h, const LaunchSet& ls, Graphs* gr) {
     return ok;
   };
   bool ok = capture(&gr->trk, 2);
-  if (ok && h->learned) ok = capture(&gr->learn, 1);
+  if (ok && h->learned && !h->P.learned_fused) ok = capture(&gr->learn, 1);
   gr->captured = ok;
   if (!ok) {
     gr->destroy();
@@ -824,7 +834,7 @@ static int complete_all(vio_frontend* h);
 // At most two submissions are outstanding; eager ones are completed before
 // the next submission (their kernel timing events are shared).
 static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStream_t st) {
-  if (h->n_pend == 2) return fail(h, VIO_ESTATE, "two frames in flight: call vio_frontend_wait first");
+  if (h->n_pend == kInFlight) return fail(h, VIO_ESTATE, "%d frames in flight: call vio_frontend_wait first", kInFlight);
   if (h->pyr_sig && h->pyr_epoch >= 0x80000000u) {
     // long before the 32-bit count could wrap: drain, then restart it at zero
     const int rc = complete_all(h);
@@ -833,7 +843,7 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
     HIP_CHECK(h, hipMemset(h->pyr_sig, 0, 8));
     h->pyr_epoch = 0;
   }
-  const int slot = (int)(h->sub & 1);
+  const int slot = (int)(h->sub % kInFlight);
   h->d_frame = h->d_frames[slot];
   h->hm_frame = h->hm_frames[slot];
   ensure_graph(h, ls, &gr[slot]);
@@ -854,7 +864,7 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
   // the frame's start timestamp (last_gpu_ms), not taken with plain launches
   if (!h->plain) HIP_CHECK(h, hipEventRecord(h->ev[slot][0], h->pstream));
   HIP_CHECK(h, enqueue_pyr_part(h, ls, slot, timed));
-  if (h->learned) {
+  if (h->learned && !h->P.learned_fused) {
     // the learned stage's inputs are the previous frame's (ordered before it
     // on this stream) and the pinned frame table: it starts at once
     if (graphed) HIP_CHECK(h, hipGraphLaunch(gr[slot].learn, st));
@@ -866,12 +876,12 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
   HIP_CHECK(h, hipEventRecord(h->ev[slot][1], st));
   for (int s = ls.stream_begin; s < ls.stream_begin + ls.n_streams; ++s)
     if (h->h_frame->cam[h->streams[s].first_cam].active) h->streams[s].frames += 1;
-  h->pend[(h->pend_head + h->n_pend) & 1] = vio_frontend::Pending{ls, graphed, slot};
+  h->pend[(h->pend_head + h->n_pend) % kInFlight] = vio_frontend::Pending{ls, graphed, slot};
   h->n_pend += 1;
   h->sub += 1;
   // a stream staged for a later step but not in this submission keeps its
   // staged inputs in the next slot's table
-  FrameTable* next = h->h_frames[h->sub & 1];
+  FrameTable* next = h->h_frames[h->sub % kInFlight];
   for (int s = 0; s < (int)h->streams.size(); ++s) {
     const StreamInfo& si = h->streams[s];
     if (!si.staged || (s >= ls.stream_begin && s < ls.stream_begin + ls.n_streams)) continue;
@@ -887,7 +897,7 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
 static int complete_oldest(vio_frontend* h) {
   if (h->n_pend == 0) return fail(h, VIO_ESTATE, "no frame in flight");
   const vio_frontend::Pending p = h->pend[h->pend_head];
-  h->pend_head ^= 1;
+  h->pend_head = (h->pend_head + 1) % kInFlight;
   h->n_pend -= 1;
   HIP_CHECK(h, hipEventSynchronize(h->ev[p.slot][1]));
   const FrameTable* ft = h->h_frames[p.slot];
@@ -910,7 +920,7 @@ static int complete_oldest(vio_frontend* h) {
   int tr = 0, lost = 0, det = 0, mat = 0, fb = 0;
   for (int c = p.ls.cam_begin; c < p.ls.cam_end; ++c) {
     if (!ft->cam[c].active) continue;
-    const int32_t* st = h->h_camstats + (size_t)kCamStats * (ft->cam[c].parity * n_cams + c);
+    const int32_t* st = h->h_camstats + (size_t)kCamStats * (ft->cam[c].rec_slot * n_cams + c);
     tr += st[kStatTracked];
     lost += st[kStatLost];
     det += st[kStatDetected];
@@ -956,7 +966,7 @@ static int check_push(vio_frontend* h, int32_t s, int64_t t_ns) {
   if (s < 0 || s >= (int)h->streams.size()) return fail(h, VIO_EINVAL, "stream %d out of range", s);
   const StreamInfo& si = h->streams[s];
   if (si.frames > 0 && t_ns <= si.last_t) return fail(h, VIO_ESTATE, "timestamps must increase");
-  if (h->n_pend == 2) return fail(h, VIO_ESTATE, "two frames in flight: call vio_frontend_wait first");
+  if (h->n_pend == kInFlight) return fail(h, VIO_ESTATE, "%d frames in flight: call vio_frontend_wait first", kInFlight);
   if (h->fault_device) return fail(h, VIO_EDEVICE, "injected device failure");
   return VIO_OK;
 }
@@ -967,8 +977,9 @@ static void fill_stream(vio_frontend* h, int s) {
   for (int k = 0; k < si.n_cams; ++k) {
     FrameCam& f = h->h_frame->cam[si.first_cam + k];
     f.parity = par;
-    f.pyr = (int)(si.frames % 3);
-    f.pyr_prev = (int)((si.frames + 2) % 3);
+    f.pyr = (int)(si.frames % kPyrSlots);
+    f.pyr_prev = (int)((si.frames + kPyrSlots - 1) % kPyrSlots);
+    f.rec_slot = (int)(si.frames % kRecSlots);
     f.has_prev = si.frames > 0;
     f.active = 1;
     f.n_pred = 0;
@@ -1002,7 +1013,7 @@ static int stage_motion(vio_frontend* h, int s, hipStream_t st) {
     for (int i = 0; i < 3; ++i) f.t[i] = m.t[i];
     f.rho = m.inv_depth;
     f.depth_off = cd.row_off;
-    KpDepth* hd = h->h_depth + (h->sub & 1) * std::max(1, h->pred_cap);  // the staging slot's lists
+    KpDepth* hd = h->h_depth + (h->sub % kInFlight) * std::max(1, h->pred_cap);  // the staging slot's lists
     int n = 0;
     for (const vio_kp_depth& d : si.depths)
       if (d.camera == m.camera) hd[cd.row_off + n++] = KpDepth{d.id, d.inv_depth, 0};
@@ -1031,12 +1042,12 @@ static size_t stage_offset(const vio_frontend* h, int s) {
 // into the current pyramid slot's level 0.
 static int upload_host_images(vio_frontend* h, int s, const uint8_t* const* images, const int32_t* strides) {
   const StreamInfo& si = h->streams[s];
-  const int ps = (int)(si.frames % 3);
+  const int ps = (int)(si.frames % kPyrSlots);
   size_t so = stage_offset(h, s);
   for (int k = 0; k < si.n_cams; ++k) {
     const int c = si.first_cam + k;
     const CamDesc& cd = h->cams[c];
-    uint8_t* stg = h->h_stage + (h->sub & 1) * h->stage_bytes + so;
+    uint8_t* stg = h->h_stage + (h->sub % kInFlight) * h->stage_bytes + so;
     for (int y = 0; y < si.h; ++y) std::memcpy(stg + (size_t)y * si.w, images[k] + (size_t)y * strides[k], si.w);
     HIP_CHECK(h, hipMemcpy2DAsync(cd.lvl[ps][0], cd.pitch[0], stg, si.w, si.w, si.h, hipMemcpyHostToDevice,
                                   h->pstream));
@@ -1062,7 +1073,7 @@ static int upload_predictions(vio_frontend* h, int s, const vio_kp_prediction* p
   for (size_t i = 1; i < v.size(); ++i)
     if (v[i].camera == v[i - 1].camera && v[i].id == v[i - 1].id) return fail(h, VIO_EINVAL, "duplicate prediction");
   if (n_pred > h->pred_cap) return fail(h, VIO_EINVAL, "more predictions than keypoint capacity");
-  Prediction* hp = h->h_pred + (h->sub & 1) * std::max(1, h->pred_cap);  // the staging slot's list
+  Prediction* hp = h->h_pred + (h->sub % kInFlight) * std::max(1, h->pred_cap);  // the staging slot's list
   int at = 0;
   for (int k = 0; k < si.n_cams; ++k) {
     FrameCam& f = h->h_frame->cam[si.first_cam + k];
@@ -1345,15 +1356,15 @@ int vio_frontend_set_motion(vio_frontend* h, int32_t s, const vio_camera_motion*
 }
 
 // The record count and records of camera c's last completed frame (records
-// are double-buffered by frame parity).
+// rotate over kRecSlots buffers by frame index).
 static int rec_count(const vio_frontend* h, const StreamInfo& si, int c) {
-  const int par = (int)((si.done - 1) & 1);
-  return h->h_rec_count[par * (int)h->cams.size() + c];
+  const int rs = (int)((si.done - 1) % kRecSlots);
+  return h->h_rec_count[rs * (int)h->cams.size() + c];
 }
 
 static const vio_track* rec_ptr(const vio_frontend* h, const StreamInfo& si, int c) {
-  const int par = (int)((si.done - 1) & 1);
-  return h->h_rec + (size_t)par * h->rec_total + h->rec_host_off[c];
+  const int rs = (int)((si.done - 1) % kRecSlots);
+  return h->h_rec + (size_t)rs * h->rec_total + h->rec_host_off[c];
 }
 
 int vio_frontend_get_tracks(vio_frontend* h, int32_t s, vio_track* out, int32_t capacity, int32_t* n_out) {
@@ -1499,7 +1510,7 @@ int vio_frontend_get_pyramid(vio_frontend* h, int32_t s, int32_t camera, int32_t
   const CamDesc& c = h->cams[si.first_cam + camera];
   const int w = c.w >> level, hh = c.h >> level;
   if (capacity < (size_t)w * hh) return VIO_ETOOSMALL;
-  const int ps = (int)((si.frames - 1) % 3);
+  const int ps = (int)((si.frames - 1) % kPyrSlots);
   HIP_CHECK(h, hipMemcpy2D(out, w, c.lvl[ps][level], c.pitch[level], w, hh, hipMemcpyDeviceToHost));
   return VIO_OK;
 }
@@ -1519,7 +1530,7 @@ int vio_frontend_get_cell_winners(vio_frontend* h, int32_t s, int32_t camera, in
   if (capacity < 3 * c.nslots) return VIO_ETOOSMALL;
   if (!out) return VIO_EINVAL;
   std::vector<uint32_t> keys(c.nslots);
-  const int ps = (int)((si.frames - 1) % 3);
+  const int ps = (int)((si.frames - 1) % kPyrSlots);
   HIP_CHECK(h, hipMemcpy(keys.data(), c.keys[ps], sizeof(uint32_t) * c.nslots, hipMemcpyDeviceToHost));
   for (int i = 0; i < c.nslots; ++i) {
     if (!keys[i]) {

@@ -20,6 +20,7 @@
 // sorted by id, so index order is id order and the neighbour order is the
 // brute-force one, bit for bit. The same wave then pools the patch.
 #include "fe_common.h"
+#include "learn_ops.h"
 #include "mfma_ops.h"
 #include "wave_ops.h"
 
@@ -29,67 +30,6 @@ namespace {
 constexpr int kTileRows = 16;     // rows of one MFMA tile: at most 16 keypoints per workgroup
 constexpr int kHidTiles = MH / 16;  // 16-unit output tiles of a hidden layer
 constexpr int kCandChunk = 2048;  // tracks staged in LDS at a time (16 KB)
-constexpr int kNone = 0x7FFFFFFF;
-constexpr uint64_t kInfBits = 0x7FF0000000000000ull;  // +inf as a key: an empty place
-
-}  // namespace
-
-namespace {
-
-// Exact neighbour key: the squared distance as the bits of a non-negative
-// double (their unsigned order is the numeric order), then the index.
-struct NKey {
-  uint64_t d;
-  int ix;
-};
-
-__device__ __forceinline__ bool nkey_less(const NKey& a, const NKey& b) {
-  return a.d < b.d || (a.d == b.d && a.ix < b.ix);
-}
-
-// The smallest key over the 64 lanes, in every lane (every lane must be
-// active): a minimum over each quad (quad permutes), over each 16-lane row
-// (rotations by 4 and 8), then across the rows (permlane32 and permlane16
-// swaps) -- DPP and permlane moves only, no LDS round trip.
-template <int Ctrl>
-__device__ __forceinline__ void min_dpp(NKey& k) {
-  NKey p;
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)k.d, Ctrl, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k.d >> 32), Ctrl, 0xF, 0xF, false);
-  p.d = ((uint64_t)hi << 32) | lo;
-  p.ix = __builtin_amdgcn_update_dpp(0, k.ix, Ctrl, 0xF, 0xF, false);
-  const bool take = nkey_less(p, k);
-  // field by field: a select of the whole struct goes through private memory
-  k.d = take ? p.d : k.d;
-  k.ix = take ? p.ix : k.ix;
-}
-
-template <bool k32>
-__device__ __forceinline__ void min_swap(NKey& k) {
-  const uint32_t lo0 = (uint32_t)k.d, hi0 = (uint32_t)(k.d >> 32), ix0 = (uint32_t)k.ix;
-  // swap(v, v) leaves the partner row's value in one of the two results, the
-  // own value in the other; the minimum of the two is the same either way
-  const auto a = k32 ? __builtin_amdgcn_permlane32_swap(lo0, lo0, false, false)
-                     : __builtin_amdgcn_permlane16_swap(lo0, lo0, false, false);
-  const auto b = k32 ? __builtin_amdgcn_permlane32_swap(hi0, hi0, false, false)
-                     : __builtin_amdgcn_permlane16_swap(hi0, hi0, false, false);
-  const auto c = k32 ? __builtin_amdgcn_permlane32_swap(ix0, ix0, false, false)
-                     : __builtin_amdgcn_permlane16_swap(ix0, ix0, false, false);
-  const uint32_t la = a[0], lb = a[1], ha = b[0], hb = b[1], ia = c[0], ib = c[1];
-  NKey x{((uint64_t)ha << 32) | la, (int)ia}, y{((uint64_t)hb << 32) | lb, (int)ib};
-  const bool take = nkey_less(y, x);
-  k.d = take ? y.d : x.d;
-  k.ix = take ? y.ix : x.ix;
-}
-
-__device__ __forceinline__ void wave_min_key(NKey& k) {
-  min_dpp<0xB1>(k);   // quad lane ^ 1
-  min_dpp<0x4E>(k);   // quad lane ^ 2
-  min_dpp<0x124>(k);  // row rotate by 4
-  min_dpp<0x128>(k);  // row rotate by 8
-  min_swap<true>(k);  // rows 0, 1 <-> 2, 3
-  min_swap<false>(k); // rows 0 <-> 1, 2 <-> 3
-}
 
 // The features and the network's output for W keypoints of one camera per
 // workgroup (rows 0..W-1 of one MFMA tile; the other rows are zero). Wave w
@@ -141,32 +81,20 @@ __global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ ca
   if (j < n) me = live[j];
   const double mx = (double)me.x, my = (double)me.y;
   // the patch's pixels of the previous frame, loaded now so that they arrive
-  // during the search (lane: a row of the 16 x 16 patch, 4 columns)
-  const int rx = (int)floorf(me.x + 0.5f), ry = (int)floorf(me.y + 0.5f);
-  const uint8_t* img = cd.lvl[fc.pyr_prev][0];
-  const int pitch = cd.pitch[0];
-  const int prow = lane >> 2, col4 = (lane & 3) * 4;
-  const int yy = min(max(ry - 8 + prow, 0), cd.h - 1);
+  // during the search
   int px4[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) px4[k] = j < n ? img[(size_t)yy * pitch + min(max(rx - 8 + col4 + k, 0), cd.w - 1)] : 0;
+  patch_load(cd.lvl[fc.pyr_prev][0], cd.pitch[0], cd.w, cd.h, me.x, me.y, lane, j < n, px4);
   // this wave's weight slices (hidden tiles wv, wv + W, ...): loaded behind
   // the first chunk's staging loads, so the search (LDS only) does not wait
   // for them and their latency hides behind it
   const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bf16x8 w1[kTPW], w2[kTPW][MH / 32], w3[MH / 32];
   float b1[kTPW], b2[kTPW], b3 = 0.f;
-  // this lane's best eight exact keys, ascending; +inf / kNone: empty. The
-  // camera's tracks are staged in LDS chunk by chunk (no flow: NaN); the lane
-  // visits tracks lane, lane + 64, ... of a chunk, so indices rise along its
-  // visits and a tie in distance keeps the earlier (smaller id) key
-  uint64_t ld[8];
-  int li[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    ld[s] = kInfBits;
-    li[s] = kNone;
-  }
+  // this lane's best eight exact keys. The camera's tracks are staged in LDS
+  // chunk by chunk (no flow: NaN); the lane visits tracks lane, lane + 64, ...
+  // of a chunk, so indices rise along its visits
+  Top8 top;
+  top.clear();
   for (int c0 = 0; c0 < n; c0 += kCandChunk) {
     const int nc = min(kCandChunk, n - c0);
     __syncthreads();  // the previous chunk has been read
@@ -205,46 +133,13 @@ __global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ ca
         const int k = k0 + lane;
         if (k < nc) {
           const float2 e = sCand[k];
-          if (e.x == e.x) {  // a track with a flow
-            const double dx = (double)e.x - mx, dy = (double)e.y - my;
-            const uint64_t kd = (uint64_t)__double_as_longlong(dx * dx + dy * dy);
-            const int ki = c0 + k;
-            if (kd < ld[7]) {
-              bool lt[8];
-#pragma unroll
-              for (int s = 0; s < 8; ++s) lt[s] = kd < ld[s];
-#pragma unroll
-              for (int s = 7; s > 0; --s) {
-                ld[s] = lt[s - 1] ? ld[s - 1] : (lt[s] ? kd : ld[s]);
-                li[s] = lt[s - 1] ? li[s - 1] : (lt[s] ? ki : li[s]);
-              }
-              ld[0] = lt[0] ? kd : ld[0];
-              li[0] = lt[0] ? ki : li[0];
-            }
-          }
+          if (e.x == e.x) top.offer(e.x, e.y, mx, my, c0 + k);  // a track with a flow
         }
       }
     }
   }
-  // eight rounds: the wave minimum of the lanes' heads is the next nearest;
-  // its lane drops it (indices are unique, so exactly one lane does)
-  int best_ix = kNone;
-  if (j < n) {
-#pragma unroll 1
-    for (int r8 = 0; r8 < 8; ++r8) {
-      NKey m{ld[0], li[0]};
-      wave_min_key(m);
-      if (lane == r8) best_ix = m.ix;
-      const bool pop = li[0] == m.ix && m.ix != kNone;
-#pragma unroll
-      for (int s = 0; s < 7; ++s) {
-        ld[s] = pop ? ld[s + 1] : ld[s];
-        li[s] = pop ? li[s + 1] : li[s];
-      }
-      ld[7] = pop ? kInfBits : ld[7];
-      li[7] = pop ? kNone : li[7];
-    }
-  }
+  // lane r < 8: the r-th nearest track (nearest first)
+  const int best_ix = j < n ? top.extract(lane) : kNone;
   if (j < n) {
     float* f = feat + (size_t)(cd.row_off + j) * MI;
     {
@@ -263,15 +158,9 @@ __global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ ca
     }
 
     // pooled patch of the previous frame
-    const int ps = px4[0] + px4[1] + px4[2] + px4[3];
-    // cell (row / 4, lane & 3): the four lanes of a 16-lane row that agree in
-    // bits 0..1 share a cell (rotations by 8 and 4 sum them)
-    int csum = ps + dpp_i<0x128>(ps);
-    csum += dpp_i<0x124>(csum);
-    const int tot = wave_total_i(ps);
-    if (((lane >> 2) & 3) == 0) {
-      const int cell = (prow >> 2) * 4 + (lane & 3);
-      const float v = tot > 0 ? (float)(csum * 16) / (float)tot - 1.f : 0.f;
+    float v;
+    const int cell = patch_pool(px4, lane, v);
+    if (cell >= 0) {
       f[16 + cell] = v;
       sX[wv][16 + cell] = bf16_bits(v);
     }

@@ -143,14 +143,14 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
         cd.state[P][pos] = fc.has_prev ? make_kp(kp.id, r.x, r.y, kp.x, kp.y, kp.age + 1) : kp;
       }
       if (fc.has_prev)
-        cd.rec[P][j] = make_rec(kp.id, cd.local, r.status, r.x, r.y, r.theta, r.fb, r.resid,
+        cd.rec[fc.rec_slot][j] = make_rec(kp.id, cd.local, r.status, r.x, r.y, r.theta, r.fb, r.resid,
                              alive ? kp.age + 1 : kp.age, -1);
     }
     base += total;
   }
   *n_rec = fc.has_prev ? n_prev : 0;
   if (threadIdx.x == 0) {
-    int32_t* st = cd.stats_out[P];
+    int32_t* st = cd.stats_out[fc.rec_slot];
     st[kStatFallback] = n_fb;
     st[kStatTracked] = fc.has_prev ? base : 0;
     st[kStatLost] = fc.has_prev ? n_prev - base : 0;
@@ -185,7 +185,7 @@ __device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDe
     if (valid) {
       const bool accepted = matched && n_surv_r + mrank < R.cap;
       const int st = matched ? (accepted ? VIO_MATCHED : VIO_LOST_CAP) : sr.status;
-      R.rec[PR][n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
+      R.rec[fr.rec_slot][n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
       if (accepted) R.state[PR][n_surv_r + mrank] = make_kp(id, sr.x, sr.y, sr.x, sr.y, 0);
     }
     m_base += m_tot;
@@ -194,8 +194,8 @@ __device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDe
   if (threadIdx.x == 0) {
     cnt->n_live[PR][rc] = n_surv_r + accepted;
     cnt->rec_count[rc] = n_rec_r + n_new;
-    *R.rec_count_out[PR] = n_rec_r + n_new;
-    R.stats_out[PR][kStatMatched] = accepted;
+    *R.rec_count_out[fr.rec_slot] = n_rec_r + n_new;
+    R.stats_out[fr.rec_slot][kStatMatched] = accepted;
   }
   return n_surv_r + accepted;
 }
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         const float x = (float)(idx % L.w), y = (float)(idx / L.w);
         const int64_t id = next_id + rank;
         L.state[P][n_surv + rank] = make_kp(id, x, y, x, y, 0);
-        L.rec[P][n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
+        L.rec[fl.rec_slot][n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
         s_sel[rank] = (uint16_t)slot;
       }
       eq_base += eq_tot;
@@ -376,12 +376,14 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     if (threadIdx.x == 0) {
       cnt->n_live[P][lc] = n_surv + n_new;
       cnt->rec_count[lc] = n_rec + n_new;
-      *L.rec_count_out[P] = n_rec + n_new;
-      L.stats_out[P][kStatDetected] = n_new;
+      *L.rec_count_out[fl.rec_slot] = n_rec + n_new;
+      L.stats_out[fl.rec_slot][kStatDetected] = n_new;
     }
-    // the key buffer of the frame after next (the next frame's was cleared a
-    // frame ago, and its detector may already run beside this selection)
-    uint32_t* next_keys = L.keys[fl.pyr == 0 ? 2 : fl.pyr - 1];
+    // the key buffer of the frame kPyrSlots - 1 frames ahead: the frames in
+    // between may already run their detectors beside this selection (their
+    // buffers were cleared by earlier selections), and that frame cannot be
+    // submitted before this one has completed
+    uint32_t* next_keys = L.keys[(fl.pyr + kPyrSlots - 1) % kPyrSlots];
     for (int i = threadIdx.x; i < nslots; i += kSelectThreads) next_keys[i] = 0u;
     __syncthreads();
 

@@ -46,6 +46,7 @@
 #include <algorithm>
 
 #include "fe_common.h"
+#include "learn_ops.h"
 #include "wave_ops.h"
 
 namespace vio {
@@ -529,11 +530,68 @@ __device__ __forceinline__ void store_result(TrackRes* dst, const TrackRes& r, i
 // target camera has them, else (tune.stereo_nb) from the nearest paired
 // keypoint's offset with tune.slevels x tune.siters, else from the disparity
 // prior with the full budget.
-template <int L>
+// The learned start of a temporal item when the learned stage is fused into
+// the tracker: the keypoint's features -- the flows of the 8 nearest tracks
+// with a flow in the previous frame's live set (exact keys; each lane reads
+// its tracks straight from global memory in rising index order) and the
+// pooled level-0 patch -- go to its feature row and, rounded to bfloat16, to
+// the wave's LDS row; then the network runs on that row. The arithmetic is the
+// learned-stage kernel's, so features and outputs are bit-identical to it.
+__device__ __forceinline__ void learned_guess(const CamDesc& cd, const FrameCam& fc, const Kp* __restrict__ live,
+                                              int n, int j, float kx, float ky, const Tuning& tune,
+                                              uint16_t* sx, int lane, float out[3]) {
+  int px4[4];
+  patch_load(cd.lvl[fc.pyr_prev][0], cd.pitch[0], cd.w, cd.h, kx, ky, lane, true, px4);
+  const double mx = (double)kx, my = (double)ky;
+  Top8 top;
+  top.clear();
+  for (int k0 = 0; k0 < n; k0 += 4 * kW) {
+    // four tracks per lane in flight at once
+    float2 e[4];
+    int age[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * kW + lane;
+      e[u] = make_float2(0.f, 0.f);
+      age[u] = 0;
+      if (k < n) {
+        e[u] = make_float2(live[k].x, live[k].y);
+        age[u] = live[k].age;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * kW + lane;
+      if (k < n && age[u] >= 1) top.offer(e[u].x, e[u].y, mx, my, k);
+    }
+  }
+  const int best = top.extract(lane);  // lane r < 8: the r-th nearest
+  float* f = tune.feat + (size_t)(cd.row_off + j) * MI;
+  if (lane < 8) {
+    float fx = 0.f, fy = 0.f;
+    if (best != kNone) {
+      const Kp o = live[best];
+      fx = (o.x - o.px) * 0.0625f;
+      fy = (o.y - o.py) * 0.0625f;
+    }
+    reinterpret_cast<float2*>(f)[lane] = make_float2(fx, fy);
+    sx[2 * lane] = bf16_bits(fx);
+    sx[2 * lane + 1] = bf16_bits(fy);
+  }
+  float v;
+  const int cell = patch_pool(px4, lane, v);
+  if (cell >= 0) {
+    f[16 + cell] = v;
+    sx[16 + cell] = bf16_bits(v);
+  }
+  mlp_row(tune.W1b, tune.W2b, tune.W3b, tune.mlpP, sx, sx + MI, lane, out);
+}
+
+template <int L, bool F>
 __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
                                              const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
                                              int n_segs, const Prediction* __restrict__ pred, const Tuning& tune,
-                                             int item, int lane, float u, float v, float wgt) {
+                                             int item, int lane, float u, float v, float wgt, uint16_t* sx) {
   // the last segment that begins at or before the item (begins ascend)
   int lo = 0, hi = n_segs - 1;
   while (lo < hi) {
@@ -625,9 +683,20 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       }
     }
     if (tune.learned && !predicted) {
-      const float* gs = tune.guess + (size_t)(cd.row_off + j) * 3;
-      gx = kp.x + 16.f * gs[0];
-      gy = kp.y + 16.f * gs[1];
+      // the network's output: the learned stage's guess, or computed here when
+      // the stage is fused (a parallel fallback item needs none)
+      float gsv[3] = {0.f, 0.f, 0.f};
+      if constexpr (F) {
+        if (sg.mode != kModeFallback)
+          learned_guess(cd, fc, cd.state[P ^ 1], __builtin_amdgcn_readfirstlane(cnt->n_live[P ^ 1][c]), j, kp.x,
+                        kp.y, tune, sx, lane, gsv);
+      } else {
+        const float* gs = tune.guess + (size_t)(cd.row_off + j) * 3;
+        gsv[0] = gs[0];
+        gsv[1] = gs[1];
+      }
+      gx = kp.x + 16.f * gsv[0];
+      gy = kp.y + 16.f * gsv[1];
       sl = tune.llevels;
       si = tune.liters;
       srho = tune.rho;
@@ -773,8 +842,9 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   store_result(out, r, lane);
 }
 
-// One wave per work item.
-template <int L>
+// One wave per work item. F: the learned stage is fused (each wave has a row
+// of LDS for the network).
+template <int L, bool F>
 __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __restrict__ cams,
                                                           const FrameTable* __restrict__ frame,
                                                           const Counters* __restrict__ cnt,
@@ -787,9 +857,14 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
   // registers, loaded through the scalar cache)
   const int k = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (int)(blockDim.x / kW) + (int)(threadIdx.x / kW));
   if (k >= n_items) return;
+  uint16_t* sx = nullptr;
+  if constexpr (F) {
+    __shared__ __align__(16) uint16_t sLearn[kTrackWaves][MI + MH];
+    sx = sLearn[threadIdx.x / kW];
+  }
   float u, v, wgt;
   pattern_of(lane, u, v, wgt);
-  process_item<L>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
+  process_item<L, F>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt, sx);
 }
 
 // Persistent grid: every wave pops items from the frame's queue counter until
@@ -797,7 +872,7 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track(const CamDesc* __rest
 // The pop is branch-free: all lanes issue the atomic, lane 0 adding one and
 // the others zero, and the first lane's (lane 0's) old value is the item, so
 // no lane-dependent control flow enters the loop.
-template <int L>
+template <int L, bool F>
 __global__ __launch_bounds__(kW* kTrackWaves) void k_track_persistent(const CamDesc* __restrict__ cams,
                                                                      FrameTable* __restrict__ frame,
                                                                      const Counters* __restrict__ cnt,
@@ -806,30 +881,43 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track_persistent(const CamD
                                                                      const Prediction* __restrict__ pred,
                                                                      Tuning tune, int queue) {
   const int lane = threadIdx.x & (kW - 1);
+  uint16_t* sx = nullptr;
+  if constexpr (F) {
+    __shared__ __align__(16) uint16_t sLearn[kTrackWaves][MI + MH];
+    sx = sLearn[threadIdx.x / kW];
+  }
   float u, v, wgt;
   pattern_of(lane, u, v, wgt);
   for (;;) {
     const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&frame->queue_head[queue], lane == 0 ? 1 : 0));
     if (k >= n_items) break;
-    process_item<L>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt);
+    process_item<L, F>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + k, lane, u, v, wgt, sx);
   }
+}
+
+template <int L, bool F>
+hipError_t launch_LF(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
+                     int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape sh, hipStream_t s) {
+  const int bw = sh.block_waves;
+  if (sh.waves_per_cu > 0) {
+    const int waves = std::min(n_items, sh.waves_per_cu * sh.n_cus);
+    const int blocks = (waves + bw - 1) / bw;
+    launch_kernel(k_track_persistent<L, F>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs,
+                  n_segs, item_base, n_items, d_pred, tune, sh.queue);
+  } else {
+    const int blocks = (n_items + bw - 1) / bw;
+    launch_kernel(k_track<L, F>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
+                  item_base, n_items, d_pred, tune);
+  }
+  return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_L(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
                     int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape sh, hipStream_t s) {
-  const int bw = sh.block_waves;
-  if (sh.waves_per_cu > 0) {
-    const int waves = std::min(n_items, sh.waves_per_cu * sh.n_cus);
-    const int blocks = (waves + bw - 1) / bw;
-    launch_kernel(k_track_persistent<L>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
-                  item_base, n_items, d_pred, tune, sh.queue);
-  } else {
-    const int blocks = (n_items + bw - 1) / bw;
-    launch_kernel(k_track<L>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs, item_base,
-                  n_items, d_pred, tune);
-  }
-  return hipGetLastError();
+  if (tune.learned && tune.fused)
+    return launch_LF<L, true>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
+  return launch_LF<L, false>(d_cams, d_frame, d_cnt, d_segs, n_segs, item_base, n_items, d_pred, tune, sh, s);
 }
 
 }  // namespace

@@ -1,0 +1,213 @@
+// Wave-level pieces of the learned initialisation's inputs (the eight nearest
+// tracks with a flow, the pooled patch) and of the network on one row,
+// shared by the learned-stage kernel (several keypoints per workgroup, the
+// network on 16-row tiles) and the tracker's fused prologue (one keypoint per
+// wave, the network on one row). Both compute bit-identical features and
+// network outputs: the same exact keys, the same pooling arithmetic, and the
+// same MFMA sequence per row (an MFMA's output row depends only on its own
+// input row).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fe_common.h"
+#include "mfma_ops.h"
+#include "wave_ops.h"
+
+namespace vio {
+
+constexpr int kNone = 0x7FFFFFFF;
+constexpr uint64_t kInfBits = 0x7FF0000000000000ull;  // +inf as a key: an empty place
+
+// Exact neighbour key: the squared distance as the bits of a non-negative
+// double (their unsigned order is the numeric order), then the index.
+struct NKey {
+  uint64_t d;
+  int ix;
+};
+
+__device__ __forceinline__ bool nkey_less(const NKey& a, const NKey& b) {
+  return a.d < b.d || (a.d == b.d && a.ix < b.ix);
+}
+
+// The smallest key over the 64 lanes, in every lane (every lane must be
+// active): a minimum over each quad (quad permutes), over each 16-lane row
+// (rotations by 4 and 8), then across the rows (permlane32 and permlane16
+// swaps) -- DPP and permlane moves only, no LDS round trip.
+template <int Ctrl>
+__device__ __forceinline__ void min_dpp(NKey& k) {
+  NKey p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)k.d, Ctrl, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k.d >> 32), Ctrl, 0xF, 0xF, false);
+  p.d = ((uint64_t)hi << 32) | lo;
+  p.ix = __builtin_amdgcn_update_dpp(0, k.ix, Ctrl, 0xF, 0xF, false);
+  const bool take = nkey_less(p, k);
+  // field by field: a select of the whole struct goes through private memory
+  k.d = take ? p.d : k.d;
+  k.ix = take ? p.ix : k.ix;
+}
+
+template <bool k32>
+__device__ __forceinline__ void min_swap(NKey& k) {
+  const uint32_t lo0 = (uint32_t)k.d, hi0 = (uint32_t)(k.d >> 32), ix0 = (uint32_t)k.ix;
+  // swap(v, v) leaves the partner row's value in one of the two results, the
+  // own value in the other; the minimum of the two is the same either way
+  const auto a = k32 ? __builtin_amdgcn_permlane32_swap(lo0, lo0, false, false)
+                     : __builtin_amdgcn_permlane16_swap(lo0, lo0, false, false);
+  const auto b = k32 ? __builtin_amdgcn_permlane32_swap(hi0, hi0, false, false)
+                     : __builtin_amdgcn_permlane16_swap(hi0, hi0, false, false);
+  const auto c = k32 ? __builtin_amdgcn_permlane32_swap(ix0, ix0, false, false)
+                     : __builtin_amdgcn_permlane16_swap(ix0, ix0, false, false);
+  const uint32_t la = a[0], lb = a[1], ha = b[0], hb = b[1], ia = c[0], ib = c[1];
+  NKey x{((uint64_t)ha << 32) | la, (int)ia}, y{((uint64_t)hb << 32) | lb, (int)ib};
+  const bool take = nkey_less(y, x);
+  k.d = take ? y.d : x.d;
+  k.ix = take ? y.ix : x.ix;
+}
+
+__device__ __forceinline__ void wave_min_key(NKey& k) {
+  min_dpp<0xB1>(k);   // quad lane ^ 1
+  min_dpp<0x4E>(k);   // quad lane ^ 2
+  min_dpp<0x124>(k);  // row rotate by 4
+  min_dpp<0x128>(k);  // row rotate by 8
+  min_swap<true>(k);  // rows 0, 1 <-> 2, 3
+  min_swap<false>(k); // rows 0 <-> 1, 2 <-> 3
+}
+
+// A lane's best eight keys so far, ascending (+inf / kNone: an empty place).
+struct Top8 {
+  uint64_t d[8];
+  int ix[8];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      d[s] = kInfBits;
+      ix[s] = kNone;
+    }
+  }
+  // Offers the track at index ki, position (ex, ey), to the keypoint at
+  // (mx, my); the differences and squares of float positions are exact in
+  // double. A lane offers its tracks in rising index order, so a tie in
+  // distance keeps the earlier (smaller id) key.
+  __device__ __forceinline__ void offer(float ex, float ey, double mx, double my, int ki) {
+    const double dx = (double)ex - mx, dy = (double)ey - my;
+    const uint64_t kd = (uint64_t)__double_as_longlong(dx * dx + dy * dy);
+    if (kd < d[7]) {
+      bool lt[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) lt[s] = kd < d[s];
+#pragma unroll
+      for (int s = 7; s > 0; --s) {
+        d[s] = lt[s - 1] ? d[s - 1] : (lt[s] ? kd : d[s]);
+        ix[s] = lt[s - 1] ? ix[s - 1] : (lt[s] ? ki : ix[s]);
+      }
+      d[0] = lt[0] ? kd : d[0];
+      ix[0] = lt[0] ? ki : ix[0];
+    }
+  }
+  // Eight rounds: the wave minimum of the lanes' heads is the next nearest;
+  // its lane drops it (indices are unique, so exactly one lane does). Lane
+  // r < 8 receives the r-th nearest index (kNone: fewer tracks). Every lane
+  // of the wave must take part.
+  __device__ __forceinline__ int extract(int lane) {
+    int best = kNone;
+#pragma unroll 1
+    for (int r8 = 0; r8 < 8; ++r8) {
+      NKey m{d[0], ix[0]};
+      wave_min_key(m);
+      if (lane == r8) best = m.ix;
+      const bool pop = ix[0] == m.ix && m.ix != kNone;
+#pragma unroll
+      for (int s = 0; s < 7; ++s) {
+        d[s] = pop ? d[s + 1] : d[s];
+        ix[s] = pop ? ix[s + 1] : ix[s];
+      }
+      d[7] = pop ? kInfBits : d[7];
+      ix[7] = pop ? kNone : ix[7];
+    }
+    return best;
+  }
+};
+
+// The previous frame's level-0 patch of 16 x 16 pixels around round(p),
+// clamped to the image: lane l loads row l / 4, columns 4 (l % 4) .. + 3.
+__device__ __forceinline__ void patch_load(const uint8_t* img, int pitch, int w, int h, float x, float y, int lane,
+                                           bool valid, int px4[4]) {
+  const int rx = (int)floorf(x + 0.5f), ry = (int)floorf(y + 0.5f);
+  const int prow = lane >> 2, col4 = (lane & 3) * 4;
+  const int yy = min(max(ry - 8 + prow, 0), h - 1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) px4[k] = valid ? img[(size_t)yy * pitch + min(max(rx - 8 + col4 + k, 0), w - 1)] : 0;
+}
+
+// Pooled patch: cell_sum * 16 / patch_sum - 1 over 4 x 4 cells (integer sums,
+// one correctly rounded division). Returns the cell this lane reports
+// (-1: none) and its value; the four lanes of a 16-lane row that agree in
+// bits 0..1 share a cell (rotations by 8 and 4 sum them). Every lane of the
+// wave must take part.
+__device__ __forceinline__ int patch_pool(const int px4[4], int lane, float& v) {
+  const int ps = px4[0] + px4[1] + px4[2] + px4[3];
+  int csum = ps + dpp_i<0x128>(ps);
+  csum += dpp_i<0x124>(csum);
+  const int tot = wave_total_i(ps);
+  v = tot > 0 ? (float)(csum * 16) / (float)tot - 1.f : 0.f;
+  return ((lane >> 2) & 3) == 0 ? ((lane >> 4) * 4 + (lane & 3)) : -1;
+}
+
+// The network on one row by one wave, with the MFMA sequence of the 16-row
+// kernels (row 0 of each tile is the row; the other rows are zero). x: the
+// row's 32 bf16 inputs and h: 128 bf16 of scratch, both in the wave's own LDS
+// (16-byte aligned); returns output o (0..2) in every lane.
+__device__ __forceinline__ void mlp_row(const uint16_t* __restrict__ W1b, const uint16_t* __restrict__ W2b,
+                                        const uint16_t* __restrict__ W3b, const float* __restrict__ P, uint16_t* x,
+                                        uint16_t* h, int lane, float out[3]) {
+  const int r = lane & 15, g = lane >> 4;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const bf16x8 zb = pack8(z8);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // layer 1: lanes 16 g (row 0) carry inputs 8 g .. 8 g + 7
+  const bf16x8 a1 = r == 0 ? load8(x + 8 * g) : zb;
+#pragma unroll
+  for (int t = 0; t < MH / 16; ++t) {
+    const f32x4 acc = mfma(a1, load8(W1b + (size_t)(16 * t + r) * MI + 8 * g), zero);
+    if (lane < 16) h[16 * t + lane] = bf16_bits(fmaxf(acc[0] + P[OFF_B1 + 16 * t + lane], 0.f));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // layer 2: h1 as four 32-wide K chunks, read before h2 overwrites them
+  bf16x8 a2[MH / 32];
+#pragma unroll
+  for (int kc = 0; kc < MH / 32; ++kc) a2[kc] = r == 0 ? load8(h + 32 * kc + 8 * g) : zb;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int t = 0; t < MH / 16; ++t) {
+    f32x4 acc = zero;
+#pragma unroll
+    for (int kc = 0; kc < MH / 32; ++kc)
+      acc = mfma(a2[kc], load8(W2b + (size_t)(16 * t + r) * MH + 32 * kc + 8 * g), acc);
+    if (lane < 16) h[16 * t + lane] = bf16_bits(fmaxf(acc[0] + P[OFF_B2 + 16 * t + lane], 0.f));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // layer 3: output columns 0..2
+  f32x4 acc = zero;
+#pragma unroll
+  for (int kc = 0; kc < MH / 32; ++kc) {
+    const bf16x8 a3 = r == 0 ? load8(h + 32 * kc + 8 * g) : zb;
+    const bf16x8 b3 = r < MO ? load8(W3b + (size_t)r * MH + 32 * kc + 8 * g) : zb;
+    acc = mfma(a3, b3, acc);
+  }
+  const float o = r < MO ? acc[0] + P[OFF_B3 + r] : 0.f;
+#pragma unroll
+  for (int k = 0; k < MO; ++k) out[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, o), k));
+}
+
+}  // namespace vio

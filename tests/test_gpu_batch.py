@@ -189,18 +189,20 @@ def test_pipelined_steps_equal_synchronous_steps(learned):
             stage(b, t)
             b.step()
             want.append({s: b.get_tracks(s).tobytes() for s in staged(t)})
+        # three frames in flight: frame t - 2's records are read while t - 1 and t run
         got = []
-        stage(a, 0)
-        a.step_async()
-        for t in range(1, n + 1):
+        depth = 3
+        for t in range(n + depth - 1):
             if t < n:
                 stage(a, t)
                 a.step_async()
-                assert a.in_flight == 2
-                with pytest.raises(vf.VioError):
-                    a.stage_frame_device(1, 1000 + t, [devs[1][t, c] for c in range(2)])  # a third frame
-            a.wait()
-            got.append({s: a.get_tracks(s).tobytes() for s in staged(t - 1)})
+                assert a.in_flight == min(t + 1, depth)
+                if a.in_flight == depth:
+                    with pytest.raises(vf.VioError):
+                        a.stage_frame_device(1, 1000 + t, [devs[1][t, c] for c in range(2)])  # a fourth frame
+            if t >= depth - 1:
+                a.wait()
+                got.append({s: a.get_tracks(s).tobytes() for s in staged(t - depth + 1)})
         assert a.in_flight == 0
         with pytest.raises(vf.VioError):
             a.wait()

@@ -200,7 +200,12 @@ NB23 = dict(stereo_init=1, stereo_levels=2, stereo_iters=3)
                                               (-1.0, {}, FB25), (0.02, {}, {**FB25, **NB23}),
                                               (0.02, {"stereo_mode": 1}, {**FB25, **NB23}),
                                               (0.02, {"learned_block_waves": 8}, {}),
-                                              (-1.0, {"learned_block_waves": 16}, {**FB25, **NB23})])
+                                              (-1.0, {"learned_block_waves": 16}, {**FB25, **NB23}),
+                                              (0.02, {"learned_fused": 1}, {}),
+                                              (-1.0, {"learned_fused": 1, "track_parallel_fallback": 1},
+                                               {**FB25, **NB23}),
+                                              (0.02, {"learned_fused": 1, "track_waves_per_cu": 4, "stereo_mode": 1},
+                                               FB25)])
 def test_learned_pipeline_parity_and_features(rho, launch, extra):
     w = synthgen.WORKLOADS["stereo752"]
     seq = synthgen.sequence(w, seq=7, n_frames=4)
@@ -223,21 +228,56 @@ def test_learned_pipeline_parity_trained_weights_stereo1280():
     seq = synthgen.sequence(w, seq=3, n_frames=5)
     n_fb = _learned_run(w, seq, P, rho, {}, 5, "learned stereo1280 trained weights")
     assert n_fb > 0  # the fallback path is exercised
-    # the benchmark's learned configuration: 2 x 5 fallback, neighbour stereo start
-    n_fb = _learned_run(w, seq, P, rho, {}, 5, "learned stereo1280 trained weights, 2x5 fallback, neighbour stereo",
-                        {**FB25, **NB23})
+    # the benchmark's learned configuration: 2 x 5 fallback, neighbour stereo start, with the learned stage
+    # fused into the tracker and the fallbacks computed beside the short attempts
+    n_fb = _learned_run(w, seq, P, rho, {"learned_fused": 1, "track_parallel_fallback": 1}, 5,
+                        "learned stereo1280 trained weights, 2x5 fallback, neighbour stereo, fused", {**FB25, **NB23})
     assert n_fb > 0
 
 
+@pytest.mark.parametrize("name,launch", [("stereo1280", {}), ("stereo1280", {"track_parallel_fallback": 1}),
+                                         ("stereo752", {"stereo_mode": 1}),
+                                         ("stereo752", {"track_waves_per_cu": 4, "track_block_waves": 2})])
+def test_fused_learned_stage_equals_its_own_launch_bitwise(name, launch):
+    """The learned stage fused into the tracker gives the records, features and
+    fallback counts of its own launch, bit for bit (trained weights)."""
+    from paper_2609_30459_amd.train_mlp import load_weights
+    import os
+    import paper_2609_30459_amd as vf
+    P, rho, _ = load_weights(os.path.join(os.path.dirname(vf.__file__), "weights", "mlp_stereo1280.bin"))
+    w = synthgen.WORKLOADS[name]
+    seq = synthgen.sequence(w, seq=6, n_frames=6)
+    stream = (w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size)
+    po = dict(_learned_params(w, rho), **FB25, **NB23)
+    fbs = 0
+    with vf.Frontend([stream], vf.params_for(w, **po, **launch)) as a, \
+            vf.Frontend([stream], vf.params_for(w, learned_fused=1, **po, **launch)) as b:
+        a.set_mlp(P, rho)
+        b.set_mlp(P, rho)
+        for t in range(6):
+            a.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            b.push_stereo_frame(0, t + 1, list(seq.frames[t]))
+            ra, rb = a.get_tracks(0), b.get_tracks(0)
+            assert len(ra) > 0 and ra.tobytes() == rb.tobytes(), t
+            sa, sb = a.stats(), b.stats()
+            assert sa["last_fallback"] == sb["last_fallback"], t
+            fbs += sa["last_fallback"]
+            if t > 0:
+                for c in range(w.n_cams):
+                    assert a.get_features(0, c).tobytes() == b.get_features(0, c).tobytes(), (t, c)
+    assert fbs > 0
 
 
-@pytest.mark.parametrize("waves", [4, 16])
+
+
+@pytest.mark.parametrize("waves", [4, 16, 0])
 def test_learned_features_span_several_staged_chunks(waves):
     """Eight keypoints per cell on 1280x720 (about 3000 live keypoints per
     camera): the learned stage stages the camera's tracks in LDS 2048 at a
     time, so the nearest-neighbour search crosses chunks; features bit-exact,
     exact fallback counts and records against the oracle (k > 1 bar) for two
-    workgroup shapes."""
+    workgroup shapes and with the stage fused into the tracker (waves 0: each
+    track's wave reads the tracks straight from global memory)."""
     import dataclasses
     w = dataclasses.replace(synthgen.WORKLOADS["stereo1280"], max_keypoints=3240, k_per_cell=8)
     seq = synthgen.sequence(w, seq=5, n_frames=3)
@@ -251,5 +291,6 @@ def test_learned_features_span_several_staged_chunks(waves):
         fe_o.close()
     assert n_live > 2048, n_live
     # every learned track falls back, so the FP64 referee can rebuild every record
-    n_fb = _learned_run(w, seq, P, -1.0, {"learned_block_waves": waves}, 3, f"learned k=8 waves={waves}", k=8)
+    launch = {"learned_fused": 1} if waves == 0 else {"learned_block_waves": waves}
+    n_fb = _learned_run(w, seq, P, -1.0, launch, 3, f"learned k=8 {launch}", k=8)
     assert n_fb > 4000
