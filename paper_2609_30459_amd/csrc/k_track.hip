@@ -537,34 +537,42 @@ __device__ __forceinline__ void store_result(TrackRes* dst, const TrackRes& r, i
 // pooled level-0 patch -- go to its feature row and, rounded to bfloat16, to
 // the wave's LDS row; then the network runs on that row. The arithmetic is the
 // learned-stage kernel's, so features and outputs are bit-identical to it.
+// Loads are issued in the order they are needed (the patch and the first 512
+// tracks, then half the weights, the rest after the search), so each wait
+// covers only what it uses and the weights arrive during the search.
+constexpr int kLearnCand = 8;  // tracks per lane loaded ahead of the search
 __device__ __forceinline__ void learned_guess(const CamDesc& cd, const FrameCam& fc, const Kp* __restrict__ live,
                                               int n, int j, float kx, float ky, const Tuning& tune,
                                               uint16_t* sx, int lane, float out[3]) {
   int px4[4];
   patch_load(cd.lvl[fc.pyr_prev][0], cd.pitch[0], cd.w, cd.h, kx, ky, lane, true, px4);
   const double mx = (double)kx, my = (double)ky;
-  Top8 top;
-  top.clear();
-  for (int k0 = 0; k0 < n; k0 += 4 * kW) {
-    // four tracks per lane in flight at once
-    float2 e[4];
-    int age[4];
+  float2 e[kLearnCand];
+  int age[kLearnCand];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u * kW + lane;
-      e[u] = make_float2(0.f, 0.f);
-      age[u] = 0;
-      if (k < n) {
-        e[u] = make_float2(live[k].x, live[k].y);
-        age[u] = live[k].age;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + u * kW + lane;
-      if (k < n && age[u] >= 1) top.offer(e[u].x, e[u].y, mx, my, k);
+  for (int u = 0; u < kLearnCand; ++u) {
+    const int k = u * kW + lane;
+    e[u] = make_float2(0.f, 0.f);
+    age[u] = 0;
+    if (k < n) {
+      e[u] = make_float2(live[k].x, live[k].y);
+      age[u] = live[k].age;
     }
   }
+  RowWeights W;
+  W.load_first(tune.W1b, tune.W2b, lane);
+  Top8 top;
+  top.clear();
+#pragma unroll
+  for (int u = 0; u < kLearnCand; ++u) {
+    const int k = u * kW + lane;
+    if (k < n && age[u] >= 1) top.offer(e[u].x, e[u].y, mx, my, k);
+  }
+  for (int k = kLearnCand * kW + lane; k < n; k += kW) {  // more tracks than loaded ahead
+    const Kp o = live[k];
+    if (o.age >= 1) top.offer(o.x, o.y, mx, my, k);
+  }
+  W.load_second(tune.W2b, tune.W3b, lane);
   const int best = top.extract(lane);  // lane r < 8: the r-th nearest
   float* f = tune.feat + (size_t)(cd.row_off + j) * MI;
   if (lane < 8) {
@@ -584,7 +592,7 @@ __device__ __forceinline__ void learned_guess(const CamDesc& cd, const FrameCam&
     f[16 + cell] = v;
     sx[16 + cell] = bf16_bits(v);
   }
-  mlp_row(tune.W1b, tune.W2b, tune.W3b, tune.mlpP, sx, sx + MI, lane, out);
+  mlp_row(W, tune.mlpP, sx, sx + MI, lane, out);
 }
 
 template <int L, bool F>

@@ -155,57 +155,88 @@ __device__ __forceinline__ int patch_pool(const int px4[4], int lane, float& v) 
   return ((lane >> 2) & 3) == 0 ? ((lane >> 4) * 4 + (lane & 3)) : -1;
 }
 
+// The network's weights as one wave's MFMA B operands for one row: lane l
+// holds W1[16 t + l % 16][8 (l / 16) .. + 7] for hidden tile t, the same for
+// W2 and its four 32-wide K chunks, and W3's row l % 16 (zero past the three
+// outputs). Loaded in two parts, so that the first can be in flight during
+// the neighbour search and the second during the extraction.
+struct RowWeights {
+  bf16x8 w1[MH / 16];
+  bf16x8 w2[MH / 16][MH / 32];
+  bf16x8 w3[MH / 32];
+  __device__ __forceinline__ void load_first(const uint16_t* __restrict__ W1b, const uint16_t* __restrict__ W2b,
+                                             int lane) {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < MH / 16; ++t) w1[t] = load8(W1b + (size_t)(16 * t + r) * MI + 8 * g);
+#pragma unroll
+    for (int t = 0; t < MH / 32; ++t)
+#pragma unroll
+      for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = load8(W2b + (size_t)(16 * t + r) * MH + 32 * kc + 8 * g);
+  }
+  __device__ __forceinline__ void load_second(const uint16_t* __restrict__ W2b, const uint16_t* __restrict__ W3b,
+                                              int lane) {
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = MH / 32; t < MH / 16; ++t)
+#pragma unroll
+      for (int kc = 0; kc < MH / 32; ++kc) w2[t][kc] = load8(W2b + (size_t)(16 * t + r) * MH + 32 * kc + 8 * g);
+    const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < MH / 32; ++kc) w3[kc] = r < MO ? load8(W3b + (size_t)r * MH + 32 * kc + 8 * g) : pack8(z8);
+  }
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The network on one row by one wave, with the MFMA sequence of the 16-row
 // kernels (row 0 of each tile is the row; the other rows are zero). x: the
 // row's 32 bf16 inputs and h: 128 bf16 of scratch, both in the wave's own LDS
-// (16-byte aligned); returns output o (0..2) in every lane.
-__device__ __forceinline__ void mlp_row(const uint16_t* __restrict__ W1b, const uint16_t* __restrict__ W2b,
-                                        const uint16_t* __restrict__ W3b, const float* __restrict__ P, uint16_t* x,
-                                        uint16_t* h, int lane, float out[3]) {
+// (16-byte aligned); W: the loaded weights; returns the outputs in every lane.
+__device__ __forceinline__ void mlp_row(const RowWeights& W, const float* __restrict__ P, uint16_t* x, uint16_t* h,
+                                        int lane, float out[3]) {
   const int r = lane & 15, g = lane >> 4;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const bf16x8 zb = pack8(z8);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  float b1[MH / 16], b2[MH / 16];
+#pragma unroll
+  for (int t = 0; t < MH / 16; ++t) {
+    b1[t] = lane < 16 ? P[OFF_B1 + 16 * t + lane] : 0.f;
+    b2[t] = lane < 16 ? P[OFF_B2 + 16 * t + lane] : 0.f;
+  }
+  const float b3 = r < MO ? P[OFF_B3 + r] : 0.f;
+  wave_sync_lds();
   // layer 1: lanes 16 g (row 0) carry inputs 8 g .. 8 g + 7
   const bf16x8 a1 = r == 0 ? load8(x + 8 * g) : zb;
 #pragma unroll
   for (int t = 0; t < MH / 16; ++t) {
-    const f32x4 acc = mfma(a1, load8(W1b + (size_t)(16 * t + r) * MI + 8 * g), zero);
-    if (lane < 16) h[16 * t + lane] = bf16_bits(fmaxf(acc[0] + P[OFF_B1 + 16 * t + lane], 0.f));
+    const f32x4 acc = mfma(a1, W.w1[t], zero);
+    if (lane < 16) h[16 * t + lane] = bf16_bits(fmaxf(acc[0] + b1[t], 0.f));
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync_lds();
   // layer 2: h1 as four 32-wide K chunks, read before h2 overwrites them
   bf16x8 a2[MH / 32];
 #pragma unroll
   for (int kc = 0; kc < MH / 32; ++kc) a2[kc] = r == 0 ? load8(h + 32 * kc + 8 * g) : zb;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync_lds();
 #pragma unroll
   for (int t = 0; t < MH / 16; ++t) {
     f32x4 acc = zero;
 #pragma unroll
-    for (int kc = 0; kc < MH / 32; ++kc)
-      acc = mfma(a2[kc], load8(W2b + (size_t)(16 * t + r) * MH + 32 * kc + 8 * g), acc);
-    if (lane < 16) h[16 * t + lane] = bf16_bits(fmaxf(acc[0] + P[OFF_B2 + 16 * t + lane], 0.f));
+    for (int kc = 0; kc < MH / 32; ++kc) acc = mfma(a2[kc], W.w2[t][kc], acc);
+    if (lane < 16) h[16 * t + lane] = bf16_bits(fmaxf(acc[0] + b2[t], 0.f));
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync_lds();
   // layer 3: output columns 0..2
   f32x4 acc = zero;
 #pragma unroll
-  for (int kc = 0; kc < MH / 32; ++kc) {
-    const bf16x8 a3 = r == 0 ? load8(h + 32 * kc + 8 * g) : zb;
-    const bf16x8 b3 = r < MO ? load8(W3b + (size_t)r * MH + 32 * kc + 8 * g) : zb;
-    acc = mfma(a3, b3, acc);
-  }
-  const float o = r < MO ? acc[0] + P[OFF_B3 + r] : 0.f;
+  for (int kc = 0; kc < MH / 32; ++kc) acc = mfma(r == 0 ? load8(h + 32 * kc + 8 * g) : zb, W.w3[kc], acc);
+  const float o = acc[0] + b3;
 #pragma unroll
   for (int k = 0; k < MO; ++k) out[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, o), k));
 }
