@@ -52,6 +52,29 @@ struct Scan {
 // One barrier per call: the wave totals alternate between two buffers, and a
 // buffer is rewritten two calls later, which a thread reaches only after the
 // next call's barrier, i.e. after every thread has read this call's totals.
+// Two flags with one barrier: the prefix count of `flag` and both totals (a
+// wave's two counts share one word).
+__device__ __forceinline__ int block_scan_flag2(bool flag, bool flag2, Scan& sc, int& total, int& total2) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag), m2 = __ballot(flag2);
+  const int below = __popcll(m & ((1ull << lane) - 1ull));
+  int* tot = sc.sh->wave_tot[sc.tog];
+  sc.tog ^= 1;
+  if (lane == 0) tot[wave] = __popcll(m) | (__popcll(m2) << 16);
+  __syncthreads();
+  int off = 0, all = 0, all2 = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int t = tot[w];
+    off += w < wave ? (t & 0xFFFF) : 0;
+    all += t & 0xFFFF;
+    all2 += t >> 16;
+  }
+  total = all;
+  total2 = all2;
+  return off + below;
+}
+
 __device__ __forceinline__ int block_scan_flag(bool flag, Scan& sc, int& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long m = __ballot(flag);
@@ -101,12 +124,21 @@ __device__ __forceinline__ Kp make_kp(int64_t id, float x, float y, float px, fl
   return k;
 }
 
+// A live keypoint's id and position, kept in LDS for the neighbour stereo
+// start's pair table while the selection writes the state.
+struct PairRow {
+  int64_t id;
+  float x, y;
+};
+constexpr int kPairLds = 1024;  // rows per camera kept in LDS (cameras of larger caps read global memory)
+
 // Carries camera c's previous keypoints into its current state: the survivors
 // of temporal tracking (all of them when there was no previous frame) in their
-// old order, with their records. Adds the survivors to `occ` when given.
-// Returns the survivor count; *n_rec receives the number of records written.
+// old order, with their records. Adds the survivors to `occ` when given, and
+// their ids and positions to `tab` when given. Returns the survivor count;
+// *n_rec receives the number of records written.
 __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev, unsigned* occ, Scan& sc,
-                               int* n_rec, bool count_fallback) {
+                               int* n_rec, bool count_fallback, PairRow* tab = nullptr) {
   const int P = fc.parity, Q = P ^ 1;
   int base = 0, n_fb = 0;
   for (int j0 = 0; j0 < n_prev; j0 += kSelectThreads) {
@@ -127,13 +159,11 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
         alive = true;
       }
     }
-    int total;
-    const int pos = base + block_scan_flag(alive, sc, total);
-    if (count_fallback) {
-      int fb_tot;
-      (void)block_scan_flag(j < n_prev && fc.has_prev && r.pad[0] != 0, sc, fb_tot);
-      n_fb += fb_tot;
-    }
+    int total, fb_tot;
+    const int pos = base + (count_fallback ? block_scan_flag2(alive, j < n_prev && fc.has_prev && r.pad[0] != 0, sc,
+                                                              total, fb_tot)
+                                           : block_scan_flag(alive, sc, total));
+    if (count_fallback) n_fb += fb_tot;
     if (j < n_prev) {
       if (alive) {
         if (occ) {
@@ -141,6 +171,7 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
           if (cx >= 0 && cx < cd.ncx && cy >= 0 && cy < cd.ncy) atomicAdd(&occ[cy * cd.ncx + cx], 1u);
         }
         cd.state[P][pos] = fc.has_prev ? make_kp(kp.id, r.x, r.y, kp.x, kp.y, kp.age + 1) : kp;
+        if (tab) tab[pos] = PairRow{kp.id, fc.has_prev ? r.x : kp.x, fc.has_prev ? r.y : kp.y};
       }
       if (fc.has_prev)
         cd.rec[fc.rec_slot][j] = make_rec(kp.id, cd.local, r.status, r.x, r.y, r.theta, r.fb, r.resid,
@@ -167,7 +198,7 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
 template <class SresOf>
 __device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDesc& R, const FrameCam& fr,
                               int rc, int n_new, int n_surv_r, int n_rec_r, SresOf sres, Counters* cnt,
-                              Scan& sc) {
+                              Scan& sc, PairRow* tab = nullptr) {
   const int PR = fr.parity;
   int m_base = 0;
   for (int i0 = 0; i0 < n_new; i0 += kSelectThreads) {
@@ -186,7 +217,10 @@ __device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDe
       const bool accepted = matched && n_surv_r + mrank < R.cap;
       const int st = matched ? (accepted ? VIO_MATCHED : VIO_LOST_CAP) : sr.status;
       R.rec[fr.rec_slot][n_rec_r + i] = make_rec(id, R.local, st, sr.x, sr.y, sr.theta, sr.fb, sr.resid, 0, -1);
-      if (accepted) R.state[PR][n_surv_r + mrank] = make_kp(id, sr.x, sr.y, sr.x, sr.y, 0);
+      if (accepted) {
+        R.state[PR][n_surv_r + mrank] = make_kp(id, sr.x, sr.y, sr.x, sr.y, 0);
+        if (tab) tab[n_surv_r + mrank] = PairRow{id, sr.x, sr.y};
+      }
     }
     m_base += m_tot;
   }
@@ -204,13 +238,14 @@ __device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDe
 // n_right keypoints, in id order, that also live among detecting camera L's
 // n_left keypoints (parity P; both states are sorted by id), as L's position
 // and the offset from L to R. The next frame's stereo matches into R read it.
-// s_ids: LDS room for kPairIdsLds ids; the left ids are staged there when
-// they fit, so that the searches read LDS instead of the state in memory.
+// tl / tr: both cameras' ids and positions as the selection wrote them to
+// LDS (when they fit), else the states in memory, with the left ids staged
+// in s_ids (LDS room for kPairIdsLds ids) when they fit there.
 constexpr int kPairIdsLds = kMaxCells / 2;  // int64 ids in the occupancy array's bytes
 
 __device__ void build_pairs(const CamDesc& L, int P, int n_left, const CamDesc& R, int PR, int rc, int n_right,
-                            Counters* cnt, Scan& sc, int64_t* s_ids) {
-  const bool staged = n_left <= kPairIdsLds;
+                            Counters* cnt, Scan& sc, const PairRow* tl, const PairRow* tr, int64_t* s_ids) {
+  const bool staged = !tl && n_left <= kPairIdsLds;
   if (staged) {
     __syncthreads();  // the LDS array's previous use is over
     for (int k = (int)threadIdx.x; k < n_left; k += kSelectThreads) s_ids[k] = L.state[P][k].id;
@@ -222,21 +257,41 @@ __device__ void build_pairs(const CamDesc& L, int P, int n_left, const CamDesc& 
     bool found = false;
     float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
     if (i < n_right) {
-      const Kp q = R.state[PR][i];
+      int64_t qid;
+      float qx, qy;
+      if (tr) {
+        const PairRow q = tr[i];
+        qid = q.id;
+        qx = q.x;
+        qy = q.y;
+      } else {
+        const Kp q = R.state[PR][i];
+        qid = q.id;
+        qx = q.x;
+        qy = q.y;
+      }
       int lo = 0, hi = n_left - 1, at = -1;
       while (lo <= hi) {
         const int mid = (lo + hi) >> 1;
-        const int64_t id = staged ? s_ids[mid] : L.state[P][mid].id;
-        if (id == q.id) {
+        const int64_t id = tl ? tl[mid].id : staged ? s_ids[mid] : L.state[P][mid].id;
+        if (id == qid) {
           at = mid;
           break;
         }
-        if (id < q.id) lo = mid + 1;
+        if (id < qid) lo = mid + 1;
         else hi = mid - 1;
       }
       if (at >= 0) {
-        const Kp l = L.state[P][at];
-        e = make_float4(l.x, l.y, q.x - l.x, q.y - l.y);
+        float lx, ly;
+        if (tl) {
+          lx = tl[at].x;
+          ly = tl[at].y;
+        } else {
+          const Kp l = L.state[P][at];
+          lx = l.x;
+          ly = l.y;
+        }
+        e = make_float4(lx, ly, qx - lx, qy - ly);
         found = true;
       }
     }
@@ -259,6 +314,8 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
   __shared__ uint16_t s_sel[kMaxCells];  // key slot of selection rank i (rank < cap <= kMaxCells, slot < 2^16)
   __shared__ int s_hist[256];
   __shared__ int s_thr[2];
+  // the detecting and the target camera's rows for the neighbour stereo start's pair table
+  __shared__ PairRow s_pl[kPairLds], s_pr[kPairLds];
   const int s = blockIdx.x;
   const int cam0 = stream_cams[2 * s], ncam = stream_cams[2 * s + 1];
   if (!frame->cam[cam0].active) return;
@@ -279,7 +336,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
                                        cnt->n_live[PR][rc], n_rec_r, [&](int i) { return sr[i]; }, cnt, sc);
         __syncthreads();
         if (tune.stereo_nb) {
-          build_pairs(L, P, cnt->sel_base[lc] + cnt->n_sel[lc], cams[rc], PR, rc, n_r, cnt, sc,
+          build_pairs(L, P, cnt->sel_base[lc] + cnt->n_sel[lc], cams[rc], PR, rc, n_r, cnt, sc, nullptr, nullptr,
                       reinterpret_cast<int64_t*>(s_occ));
           __syncthreads();
         }
@@ -303,7 +360,10 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     // ---- left / mono camera: survivors and occupancy ----------------------
     int n_rec = 0;
     const bool count_fb = tune.learned != 0 || tune.plevels > 0;
-    const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec, count_fb);
+    // pair rows in LDS (all-in-one selection with the neighbour stereo start)
+    const bool pairs_lds = phase == kSelectAll && tune.stereo_nb && L.cap <= kPairLds;
+    const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec, count_fb,
+                                       pairs_lds ? s_pl : nullptr);
     __syncthreads();
 
     // ---- candidates of unmasked cells, score histogram --------------------
@@ -367,6 +427,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         const float x = (float)(idx % L.w), y = (float)(idx / L.w);
         const int64_t id = next_id + rank;
         L.state[P][n_surv + rank] = make_kp(id, x, y, x, y, 0);
+        if (pairs_lds) s_pl[n_surv + rank] = PairRow{id, x, y};
         L.rec[fl.rec_slot][n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
         s_sel[rank] = (uint16_t)slot;
       }
@@ -395,14 +456,17 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
       const FrameCam& fr = frame->cam[rc];
       const int PR = fr.parity;
       int n_rec_r = 0;
-      const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, count_fb);
+      const bool pairs_lds_r = pairs_lds && R.cap <= kPairLds;
+      const int n_surv_r = carry_survivors(R, fr, cnt->n_live[PR ^ 1][rc], nullptr, sc, &n_rec_r, count_fb,
+                                           pairs_lds_r ? s_pr : nullptr);
       if (phase == kSelectAll) {
         const TrackRes* sr = L.sres + (size_t)t * nslots;
         const int n_r = accept_matches(L, P, n_surv, R, fr, rc, n_new, n_surv_r, n_rec_r,
-                                       [&](int i) { return sr[s_sel[i]]; }, cnt, sc);
+                                       [&](int i) { return sr[s_sel[i]]; }, cnt, sc, pairs_lds_r ? s_pr : nullptr);
         if (tune.stereo_nb) {
           __syncthreads();
-          build_pairs(L, P, n_surv + n_new, R, PR, rc, n_r, cnt, sc, reinterpret_cast<int64_t*>(s_occ));
+          build_pairs(L, P, n_surv + n_new, R, PR, rc, n_r, cnt, sc, pairs_lds ? s_pl : nullptr,
+                      pairs_lds_r ? s_pr : nullptr, reinterpret_cast<int64_t*>(s_occ));
         }
       } else if (threadIdx.x == 0) {
         // the matches come from the stereo tracking launch; kSelectRight appends them
