@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--block-waves", type=int, default=None, help="tracker waves per workgroup (1, 2, 4)")
     ap.add_argument("--learned-block-waves", type=int, choices=[4, 8, 16], default=None,
                     help="keypoints per learned-stage workgroup")
+    ap.add_argument("--pyramid-stream", type=int, choices=[0, 1, 2], default=0,
+                    help="pyramid beside the tracking, waited for by a signal (0) or an event (1), or in order on "
+                         "the launch stream (2)")
     ap.add_argument("--learned-fused", type=int, choices=[0, 1], default=None,
                     help="learned stage inside the tracker launch (default: on for one stream, off when batched)")
     ap.add_argument("--tile", type=int, default=None, help="pyramid/detector tile edge (32, 64)")
@@ -248,7 +251,7 @@ def main():
         return dict(track_waves_per_cu=wpc or 0, track_block_waves=bw or 4, pyr_tile=tile or 64,
                     stereo_mode=smode or 0, track_parallel_fallback=pfb if init == "learned" else 0,
                     learned_block_waves=(lbw or 0) if init == "learned" else 0,
-                    learned_fused=lfu if init == "learned" else 0), \
+                    learned_fused=lfu if init == "learned" else 0, pyramid_stream=args.pyramid_stream), \
             tuned is not None
 
     mlp = None
@@ -518,7 +521,7 @@ def main():
             "launch": {**{k: v for k, v in extra.items() if k in ("track_waves_per_cu", "track_block_waves",
                                                                    "pyr_tile", "stereo_mode",
                                                                    "track_parallel_fallback", "learned_block_waves",
-                                                                   "learned_fused")},
+                                                                   "learned_fused", "pyramid_stream")},
                        "autotuned": tuned},
             "roofline": roof, "second_launch": second, "kernels": kernels,
             "host_image": None if args.no_host_leg else host_run(init),

@@ -160,7 +160,19 @@ typedef struct vio_frontend_params {
    * and fallback work) instead of as a launch of its own before it; 0 = its
    * own launch. */
   int32_t learned_fused;
+  /* Launch choice that never changes the records: where a frame's pyramid and
+   * detection run. VIO_PYRAMID_SIGNAL (0): on a stream of their own, so that
+   * the later frames' pyramids run beside this frame's tracking; the launch
+   * stream waits for a count the pyramid stream writes (stream value
+   * operations: the least host time per frame). VIO_PYRAMID_EVENT (1): the
+   * same with an event record and wait. VIO_PYRAMID_SAME_STREAM (2): on the
+   * launch stream, in order (no cross-stream dependency). */
+  int32_t pyramid_stream;
 } vio_frontend_params;
+
+#define VIO_PYRAMID_SIGNAL 0
+#define VIO_PYRAMID_EVENT 1
+#define VIO_PYRAMID_SAME_STREAM 2
 
 #define VIO_STEREO_INIT_PRIOR 0
 #define VIO_STEREO_INIT_NEIGHBOUR 1

@@ -63,7 +63,7 @@ class vio_frontend_params(ctypes.Structure):
         ("learned_fb_levels", ctypes.c_int32), ("learned_fb_iters", ctypes.c_int32),
         ("stereo_init", ctypes.c_int32), ("stereo_levels", ctypes.c_int32), ("stereo_iters", ctypes.c_int32),
         ("track_parallel_fallback", ctypes.c_int32), ("learned_block_waves", ctypes.c_int32),
-        ("learned_fused", ctypes.c_int32),
+        ("learned_fused", ctypes.c_int32), ("pyramid_stream", ctypes.c_int32),
     ]
 
 # the optional device allocator of vio_frontend_params
@@ -77,6 +77,7 @@ VIO_STEREO_SPECULATIVE = 0
 VIO_STEREO_DEFERRED = 1
 VIO_TOPOLOGY_PAIRS = 0
 VIO_TOPOLOGY_STAR = 1
+VIO_PYRAMID_SIGNAL, VIO_PYRAMID_EVENT, VIO_PYRAMID_SAME_STREAM = 0, 1, 2
 VIO_STEREO_INIT_PRIOR = 0
 VIO_STEREO_INIT_NEIGHBOUR = 1
 

@@ -292,6 +292,8 @@ int check_params(const vio_frontend_params* p, std::string& why) {
       p->learned_block_waves != 16)
     return why = "learned_block_waves must be 0, 4, 8 or 16", VIO_EINVAL;
   if (p->learned_fused != 0 && p->learned_fused != 1) return why = "learned_fused must be 0 or 1", VIO_EINVAL;
+  if (p->pyramid_stream < VIO_PYRAMID_SIGNAL || p->pyramid_stream > VIO_PYRAMID_SAME_STREAM)
+    return why = "pyramid_stream must be VIO_PYRAMID_SIGNAL, _EVENT or _SAME_STREAM", VIO_EINVAL;
   return VIO_OK;
 }
 
@@ -354,7 +356,7 @@ void vio_frontend_destroy(vio_frontend* h) {
   // the streams were synchronized above: the signal holds its last value
   if (h->pyr_sig) signal_release(h->device, h->pyr_sig, h->pyr_epoch);
   if (h->stream) (void)hipStreamDestroy(h->stream);
-  if (h->pstream) (void)hipStreamDestroy(h->pstream);
+  if (h->pstream && h->pstream != h->stream) (void)hipStreamDestroy(h->pstream);
   delete h;
 }
 
@@ -606,12 +608,15 @@ static int create_impl(vio_frontend* h, const vio_stream_desc* sd, int32_t n_str
   }
   HIP_CHECK(h, hipMemcpy(h->d_cams, h->cams.data(), sizeof(CamDesc) * n_cams, hipMemcpyHostToDevice));
   HIP_CHECK(h, hipStreamCreate(&h->stream));
-  HIP_CHECK(h, hipStreamCreate(&h->pstream));
+  // VIO_PYRAMID_SAME_STREAM: the pyramid runs on the launch stream, in order
+  if (h->P.pyramid_stream == VIO_PYRAMID_SAME_STREAM) h->pstream = h->stream;
+  else HIP_CHECK(h, hipStreamCreate(&h->pstream));
   for (int slot = 0; slot < kInFlight; ++slot) {
     HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_pyr[slot], hipEventDisableTiming));
   }
   HIP_CHECK(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
-  if (!signal_acquire(h->device, &h->pyr_sig, &h->pyr_epoch)) h->pyr_sig = nullptr;
+  if (h->P.pyramid_stream != VIO_PYRAMID_SIGNAL || !signal_acquire(h->device, &h->pyr_sig, &h->pyr_epoch))
+    h->pyr_sig = nullptr;
   for (auto& pr : h->ev)
     for (hipEvent_t& e : pr) HIP_CHECK(h, hipEventCreate(&e));
   for (auto& pr : h->kev)
@@ -780,15 +785,17 @@ static hipError_t enqueue_stage(vio_frontend* h, const LaunchSet& ls, hipStream_
 // and the selection. The pyramid slots rotate over kPyrSlots frames, so the
 // pyramids of the later frames in flight can run beside this frame's
 // tracking.
-static hipError_t enqueue_pyr_part(vio_frontend* h, const LaunchSet& ls, int slot, bool timed) {
+static hipError_t enqueue_pyr_part(vio_frontend* h, const LaunchSet& ls, int slot, bool timed, hipStream_t st) {
   hipError_t e;
   if ((e = enqueue_stage(h, ls, h->pstream, 1, timed))) return e;
+  if (h->pstream == st) return hipSuccess;  // the launch stream itself: stream order suffices
   if (h->pyr_sig) return hipStreamWriteValue32(h->pstream, h->pyr_sig, ++h->pyr_epoch, 0);
   return hipEventRecord(h->ev_pyr[slot], h->pstream);
 }
 
 // The launch stream waits for the pyramid part of the frame just enqueued.
 static hipError_t wait_pyr_part(vio_frontend* h, hipStream_t st, int slot) {
+  if (h->pstream == st) return hipSuccess;
   if (h->pyr_sig) return hipStreamWaitValue32(st, h->pyr_sig, h->pyr_epoch, hipStreamWaitValueGte, 0xFFFFFFFFu);
   return hipStreamWaitEvent(st, h->ev_pyr[slot], 0);
 }
@@ -863,7 +870,7 @@ static int submit_set(vio_frontend* h, const LaunchSet& ls, Graphs* gr, hipStrea
   }
   // the frame's start timestamp (last_gpu_ms), not taken with plain launches
   if (!h->plain) HIP_CHECK(h, hipEventRecord(h->ev[slot][0], h->pstream));
-  HIP_CHECK(h, enqueue_pyr_part(h, ls, slot, timed));
+  HIP_CHECK(h, enqueue_pyr_part(h, ls, slot, timed, st));
   if (h->learned && !h->P.learned_fused) {
     // the learned stage's inputs are the previous frame's (ordered before it
     // on this stream) and the pinned frame table: it starts at once

@@ -246,3 +246,41 @@ def test_push_between_staging_and_step_keeps_the_staged_frame():
             for s in (0, 1):
                 ra = a.get_tracks(s)
                 assert len(ra) > 0 and ra.tobytes() == b.get_tracks(s).tobytes(), (t, s)
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_pyramid_stream_choices_give_identical_records(learned):
+    """The pyramid beside the tracking with a signal or an event, or in order on
+    the launch stream: the same records, pipelined three frames deep."""
+    import os
+
+    import torch
+
+    import paper_2609_30459_amd as vf
+    w = synthgen.WORKLOADS["stereo752"]
+    seq = synthgen.sequence(w, seq=4, n_frames=6)
+    dev = torch.from_numpy(seq.frames).cuda()
+    extra = {}
+    if learned:
+        from paper_2609_30459_amd.train_mlp import load_weights
+        params, rho, _ = load_weights(os.path.join(os.path.dirname(vf.__file__), "weights", "mlp_stereo1280.bin"))
+        extra = dict(init_mode=1, learned_levels=2, learned_iters=3, learned_rho=rho, learned_fused=1,
+                     track_parallel_fallback=1)
+    stream = (2, w.width, w.height, w.max_keypoints, w.cell_size)
+    out = {}
+    for mode in (vf.VIO_PYRAMID_SIGNAL, vf.VIO_PYRAMID_EVENT, vf.VIO_PYRAMID_SAME_STREAM):
+        got = []
+        with vf.Frontend([stream], vf.params_for(w, pyramid_stream=mode, **extra)) as fe:
+            if learned:
+                fe.set_mlp(params, rho)
+            for t in range(6 + 2):
+                if t < 6:
+                    fe.stage_frame_device(0, t + 1, [dev[t, 0], dev[t, 1]])
+                    fe.step_async()
+                if t >= 2:
+                    fe.wait()
+                    got.append(fe.get_tracks(0).tobytes())
+        out[mode] = got
+    assert all(len(r) > 0 for r in out[0])
+    assert out[vf.VIO_PYRAMID_EVENT] == out[vf.VIO_PYRAMID_SIGNAL]
+    assert out[vf.VIO_PYRAMID_SAME_STREAM] == out[vf.VIO_PYRAMID_SIGNAL]
