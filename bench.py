@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--no-second-launch", "--no-graph-replay", dest="no_second", action="store_true",
                     help="skip the second timed region (one frame at a time with per-kernel events)")
     ap.add_argument("--weights", default=None, help="learned-init weights (default: the package's for the workload)")
+    ap.add_argument("--zero-network", action="store_true",
+                    help="ablation: the learned leg with the network's parameters set to zero (guess: no motion), "
+                         "same threshold and budgets")
     ap.add_argument("--levels", type=int, default=None, help="override the pyramid levels")
     ap.add_argument("--iters", type=int, default=None, help="override the Gauss-Newton iterations per level")
     ap.add_argument("--k-per-cell", type=int, default=None, help="keypoints per detection cell (default 1)")
@@ -262,7 +265,9 @@ def main():
         own = os.path.join(wdir, f"mlp_{args.workload}.bin")
         path = args.weights or (own if os.path.exists(own) else os.path.join(wdir, "mlp_stereo1280.bin"))
         params_, rho_, meta = load_weights(path)
-        mlp = (params_, rho_, os.path.basename(path))
+        if args.zero_network:
+            params_ = np.zeros_like(params_)
+        mlp = (params_, rho_, os.path.basename(path) + (" (zeroed)" if args.zero_network else ""))
         log(f"learned init: {path} ({meta}), rho {rho_:.4f}")
 
     ids = list(range(len(ws)))

@@ -49,8 +49,11 @@ __global__ __launch_bounds__(64 * W) void k_learn(const CamDesc* __restrict__ ca
   static_assert(W >= 1 && W <= kTileRows, "one tile of keypoints per workgroup");
   constexpr int kTPW = (kHidTiles + W - 1) / W;  // hidden tiles per wave
   __shared__ float2 sCand[kCandChunk];                   // a chunk of the camera's tracks
-  __shared__ __align__(16) uint16_t sX[kTileRows][MI];  // bf16 inputs, one row per keypoint
-  __shared__ __align__(16) uint16_t sH[kTileRows][MH];  // h1, then h2
+  // bf16 inputs (one row per keypoint) and h1, then h2; rows padded by 8
+  // entries, so that the 16 rows of an MFMA operand read (16 bytes per lane)
+  // start 4 banks apart instead of in the same bank
+  __shared__ __align__(16) uint16_t sX[kTileRows][MI + 8];
+  __shared__ __align__(16) uint16_t sH[kTileRows][MH + 8];
   // the workgroup's camera and keypoints: ceil(cap / W) workgroups per camera
   int c = cam_begin, b = (int)blockIdx.x;
   for (; c < cam_end; ++c) {

@@ -149,9 +149,14 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
     if (j < n_prev) {
       kp = cd.state[Q][j];
       if (fc.has_prev) {
-        r = cd.res[j];
         // a short attempt that was not kept: its fallback, computed beside it
-        if (r.pad[0] != 0 && cd.res_fb) r = cd.res_fb[j];
+        // (both results loaded at once, so the choice costs no second round
+        // trip; the fallback slot of a kept track is not used)
+        r = cd.res[j];
+        if (cd.res_fb) {
+          const TrackRes rf = cd.res_fb[j];
+          if (r.pad[0] != 0) r = rf;
+        }
         alive = r.status == VIO_TRACKED;
       } else {
         r.x = kp.x;
