@@ -138,7 +138,8 @@ constexpr int kPairLds = 1024;  // rows per camera kept in LDS (cameras of large
 // their ids and positions to `tab` when given. Returns the survivor count;
 // *n_rec receives the number of records written.
 __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev, unsigned* occ, Scan& sc,
-                               int* n_rec, bool count_fallback, PairRow* tab = nullptr) {
+                               int* n_rec, bool count_fallback, PairRow* tab = nullptr,
+                               int64_t* tab_ids = nullptr) {
   const int P = fc.parity, Q = P ^ 1;
   int base = 0, n_fb = 0;
   for (int j0 = 0; j0 < n_prev; j0 += kSelectThreads) {
@@ -177,6 +178,7 @@ __device__ int carry_survivors(const CamDesc& cd, const FrameCam& fc, int n_prev
         }
         cd.state[P][pos] = fc.has_prev ? make_kp(kp.id, r.x, r.y, kp.x, kp.y, kp.age + 1) : kp;
         if (tab) tab[pos] = PairRow{kp.id, fc.has_prev ? r.x : kp.x, fc.has_prev ? r.y : kp.y};
+        if (tab_ids) tab_ids[pos] = kp.id;
       }
       if (fc.has_prev)
         cd.rec[fc.rec_slot][j] = make_rec(kp.id, cd.local, r.status, r.x, r.y, r.theta, r.fb, r.resid,
@@ -244,12 +246,14 @@ __device__ int accept_matches(const CamDesc& L, int P, int sel_base, const CamDe
 // n_left keypoints (parity P; both states are sorted by id), as L's position
 // and the offset from L to R. The next frame's stereo matches into R read it.
 // tl / tr: both cameras' ids and positions as the selection wrote them to
-// LDS (when they fit), else the states in memory, with the left ids staged
-// in s_ids (LDS room for kPairIdsLds ids) when they fit there.
+// LDS (when they fit; tl_ids: the left ids again, contiguous, for the
+// search), else the states in memory, with the left ids staged in s_ids (LDS
+// room for kPairIdsLds ids) when they fit there.
 constexpr int kPairIdsLds = kMaxCells / 2;  // int64 ids in the occupancy array's bytes
 
 __device__ void build_pairs(const CamDesc& L, int P, int n_left, const CamDesc& R, int PR, int rc, int n_right,
-                            Counters* cnt, Scan& sc, const PairRow* tl, const PairRow* tr, int64_t* s_ids) {
+                            Counters* cnt, Scan& sc, const PairRow* tl, const int64_t* tl_ids, const PairRow* tr,
+                            int64_t* s_ids) {
   const bool staged = !tl && n_left <= kPairIdsLds;
   if (staged) {
     __syncthreads();  // the LDS array's previous use is over
@@ -275,16 +279,31 @@ __device__ void build_pairs(const CamDesc& L, int P, int n_left, const CamDesc& 
         qx = q.x;
         qy = q.y;
       }
-      int lo = 0, hi = n_left - 1, at = -1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int64_t id = tl ? tl[mid].id : staged ? s_ids[mid] : L.state[P][mid].id;
-        if (id == qid) {
-          at = mid;
-          break;
+      int at = -1;
+      if (tl_ids) {
+        // lower bound over the contiguous LDS ids, branch-free: every lane
+        // takes the same floor(log2(n_left)) + 1 steps of halving size
+        if (n_left > 0) {
+          int pos = 0;  // ids below qid so far
+          for (int step = 1 << (31 - __clz(n_left)); step > 0; step >>= 1) {
+            const int probe = pos + step;
+            const int64_t v = tl_ids[min(probe, n_left) - 1];
+            pos = probe <= n_left && v < qid ? probe : pos;
+          }
+          at = pos < n_left && tl_ids[pos] == qid ? pos : -1;
         }
-        if (id < qid) lo = mid + 1;
-        else hi = mid - 1;
+      } else {
+        int lo = 0, hi = n_left - 1;
+        while (lo <= hi) {
+          const int mid = (lo + hi) >> 1;
+          const int64_t id = staged ? s_ids[mid] : L.state[P][mid].id;
+          if (id == qid) {
+            at = mid;
+            break;
+          }
+          if (id < qid) lo = mid + 1;
+          else hi = mid - 1;
+        }
       }
       if (at >= 0) {
         float lx, ly;
@@ -321,6 +340,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
   __shared__ int s_thr[2];
   // the detecting and the target camera's rows for the neighbour stereo start's pair table
   __shared__ PairRow s_pl[kPairLds], s_pr[kPairLds];
+  __shared__ int64_t s_plid[kPairLds];  // s_pl's ids, contiguous for the pair search
   const int s = blockIdx.x;
   const int cam0 = stream_cams[2 * s], ncam = stream_cams[2 * s + 1];
   if (!frame->cam[cam0].active) return;
@@ -342,7 +362,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         __syncthreads();
         if (tune.stereo_nb) {
           build_pairs(L, P, cnt->sel_base[lc] + cnt->n_sel[lc], cams[rc], PR, rc, n_r, cnt, sc, nullptr, nullptr,
-                      reinterpret_cast<int64_t*>(s_occ));
+                      nullptr, reinterpret_cast<int64_t*>(s_occ));
           __syncthreads();
         }
       }
@@ -368,7 +388,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
     // pair rows in LDS (all-in-one selection with the neighbour stereo start)
     const bool pairs_lds = phase == kSelectAll && tune.stereo_nb && L.cap <= kPairLds;
     const int n_surv = carry_survivors(L, fl, cnt->n_live[Q][lc], s_occ, sc, &n_rec, count_fb,
-                                       pairs_lds ? s_pl : nullptr);
+                                       pairs_lds ? s_pl : nullptr, pairs_lds ? s_plid : nullptr);
     __syncthreads();
 
     // ---- candidates of unmasked cells, score histogram --------------------
@@ -432,7 +452,10 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         const float x = (float)(idx % L.w), y = (float)(idx / L.w);
         const int64_t id = next_id + rank;
         L.state[P][n_surv + rank] = make_kp(id, x, y, x, y, 0);
-        if (pairs_lds) s_pl[n_surv + rank] = PairRow{id, x, y};
+        if (pairs_lds) {
+          s_pl[n_surv + rank] = PairRow{id, x, y};
+          s_plid[n_surv + rank] = id;
+        }
         L.rec[fl.rec_slot][n_rec + rank] = make_rec(id, L.local, VIO_DETECTED, x, y, 0.f, 0.f, 0.f, 0, score);
         s_sel[rank] = (uint16_t)slot;
       }
@@ -471,7 +494,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(const CamDesc* __rest
         if (tune.stereo_nb) {
           __syncthreads();
           build_pairs(L, P, n_surv + n_new, R, PR, rc, n_r, cnt, sc, pairs_lds ? s_pl : nullptr,
-                      pairs_lds_r ? s_pr : nullptr, reinterpret_cast<int64_t*>(s_occ));
+                      pairs_lds ? s_plid : nullptr, pairs_lds_r ? s_pr : nullptr, reinterpret_cast<int64_t*>(s_occ));
         }
       } else if (threadIdx.x == 0) {
         // the matches come from the stereo tracking launch; kSelectRight appends them
