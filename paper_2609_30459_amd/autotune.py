@@ -127,6 +127,13 @@ def tune(workload: str, init: str, frames=40, path=CACHE, log=print, **kw):
              "track_ms": best["track_ms"], "pyr_ms": pick["pyr_ms"], "frame_ms": pick["frame_ms"],
              "frames": frames, "candidates": res}
     cache = _load_cache(path)
+    # the learned stage's choices (its own launch or fused into the tracker,
+    # parallel fallbacks, keypoints per workgroup) are set from pipelined
+    # benchmark sweeps, not by this kernel-time tuner: kept across re-tuning
+    old = cache.get(device_key(), {}).get(f"{workload}:{init}", {})
+    for k in ("learned_fused", "track_parallel_fallback", "learned_block_waves"):
+        if k in old:
+            entry[k] = old[k]
     cache.setdefault(device_key(), {})[f"{workload}:{init}"] = entry
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path + ".tmp", "w") as f:
