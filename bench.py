@@ -174,6 +174,9 @@ def main():
                          "the launch stream (2)")
     ap.add_argument("--learned-fused", type=int, choices=[0, 1], default=None,
                     help="learned stage inside the tracker launch (default: on for one stream, off when batched)")
+    ap.add_argument("--kp-per-wave", type=int, choices=[1, 2], default=None,
+                    help="keypoints per tracking wavefront (default: the autotuned choice, else 1); 2 needs the "
+                         "learned stage in its own launch")
     ap.add_argument("--tile", type=int, default=None, help="pyramid/detector tile edge (32, 64)")
     ap.add_argument("--stereo-mode", type=int, default=None, help="0 speculative, 1 deferred stereo matching")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -233,7 +236,7 @@ def main():
     def launch_choice(init):
         """Launch parameters (never change the records): explicit flags, else the autotuned choice."""
         wpc, bw, tile, smode = args.waves_per_cu, args.block_waves, args.tile, args.stereo_mode
-        pfb, lbw, lfu = args.parallel_fallback, args.learned_block_waves, args.learned_fused
+        pfb, lbw, lfu, kpw = args.parallel_fallback, args.learned_block_waves, args.learned_fused, args.kp_per_wave
         tuned = None
         if wpc is None and bw is None and tile is None and smode is None:
             from paper_2609_30459_amd import autotune
@@ -247,14 +250,19 @@ def main():
                     lbw = tuned["learned_block_waves"]
                 if lfu is None and "learned_fused" in tuned:
                     lfu = tuned["learned_fused"]
+                if kpw is None and "track_kp_per_wave" in tuned:
+                    kpw = tuned["track_kp_per_wave"]
         if pfb is None:
             pfb = 0 if batched else 1
+        if kpw == 2 and args.learned_fused is None:
+            lfu = 0  # the fused learned stage runs one keypoint per wave
         if lfu is None:
             lfu = 0 if batched else 1
         return dict(track_waves_per_cu=wpc or 0, track_block_waves=bw or 4, pyr_tile=tile or 64,
                     stereo_mode=smode or 0, track_parallel_fallback=pfb if init == "learned" else 0,
                     learned_block_waves=(lbw or 0) if init == "learned" else 0,
-                    learned_fused=lfu if init == "learned" else 0, pyramid_stream=args.pyramid_stream), \
+                    learned_fused=lfu if init == "learned" else 0, pyramid_stream=args.pyramid_stream,
+                    track_kp_per_wave=kpw or 1), \
             tuned is not None
 
     mlp = None
@@ -526,7 +534,8 @@ def main():
             "launch": {**{k: v for k, v in extra.items() if k in ("track_waves_per_cu", "track_block_waves",
                                                                    "pyr_tile", "stereo_mode",
                                                                    "track_parallel_fallback", "learned_block_waves",
-                                                                   "learned_fused", "pyramid_stream")},
+                                                                   "learned_fused", "pyramid_stream",
+                                                                   "track_kp_per_wave")},
                        "autotuned": tuned},
             "roofline": roof, "second_launch": second, "kernels": kernels,
             "host_image": None if args.no_host_leg else host_run(init),

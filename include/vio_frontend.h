@@ -168,6 +168,13 @@ typedef struct vio_frontend_params {
    * same with an event record and wait. VIO_PYRAMID_SAME_STREAM (2): on the
    * launch stream, in order (no cross-stream dependency). */
   int32_t pyramid_stream;
+  /* Launch choice that never changes the records: keypoints per tracking
+   * wavefront. 1 (or 0): one wave64 per keypoint, a lane per pattern point
+   * (the shortest chain per keypoint: few keypoints, one frame at a time);
+   * 2: two keypoints per wave, one per 32-lane half, two pattern points per
+   * lane (fewer instructions per keypoint: many keypoints, batched streams).
+   * 2 needs learned_fused = 0 when init_mode is VIO_INIT_LEARNED. */
+  int32_t track_kp_per_wave;
 } vio_frontend_params;
 
 #define VIO_PYRAMID_SIGNAL 0

@@ -34,7 +34,8 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
                 track_block_waves=0, pyr_tile=0, stereo_mode=0, pred_levels=0, pred_iters=0,
                 pred_rho=0.0, topology=0, plain=False, learned_fb_levels=0, learned_fb_iters=0, stereo_init=0,
                 stereo_levels=2, stereo_iters=3, track_parallel_fallback=0,
-                learned_block_waves=0, learned_fused=0, pyramid_stream=0) -> _n.vio_frontend_params:
+                learned_block_waves=0, learned_fused=0, pyramid_stream=0,
+                track_kp_per_wave=0) -> _n.vio_frontend_params:
     p = default_params()
     p.levels, p.gn_iters, p.cell_size, p.k_per_cell = levels, gn_iters, cell_size, k_per_cell
     p.n_thresholds = len(thresholds)
@@ -56,6 +57,7 @@ def make_params(levels=4, gn_iters=5, cell_size=50, k_per_cell=1, thresholds=(40
     p.learned_block_waves = learned_block_waves
     p.learned_fused = learned_fused
     p.pyramid_stream = pyramid_stream
+    p.track_kp_per_wave = track_kp_per_wave
     return p
 
 

@@ -64,6 +64,7 @@ class vio_frontend_params(ctypes.Structure):
         ("stereo_init", ctypes.c_int32), ("stereo_levels", ctypes.c_int32), ("stereo_iters", ctypes.c_int32),
         ("track_parallel_fallback", ctypes.c_int32), ("learned_block_waves", ctypes.c_int32),
         ("learned_fused", ctypes.c_int32), ("pyramid_stream", ctypes.c_int32),
+        ("track_kp_per_wave", ctypes.c_int32),
     ]
 
 # the optional device allocator of vio_frontend_params

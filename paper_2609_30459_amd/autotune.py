@@ -1,9 +1,11 @@
 """Picks the kernels' launch shapes per workload and device by measurement.
 
-Three choices are free and leave the records bit for bit the same:
+Four choices are free and leave the records bit for bit the same:
   * the tracker's launch shape: one wave64 per work item in workgroups of 1, 2
     or 4 waves, or a persistent grid of 1..16 waves per compute unit popping
     items from a shared queue;
+  * keypoints per tracking wavefront: one (a lane per pattern point) or two
+    (one per 32-lane half, two pattern points per lane);
   * the pyramid/detector tile: 64x64 level-0 pixels per 1024-thread workgroup
     or 32x32 per 256-thread workgroup (more, smaller workgroups, at the cost
     of a larger share of recomputed apron);
@@ -14,8 +16,14 @@ Which is fastest depends on the image sizes, the item count, the levels and
 iterations, and the chip. Each candidate runs the same frames of the workload
 (device-resident, kernels launched one by one with HIP events attached to
 their dispatches). The tracker shape is chosen first by the tracker kernel's
-mean duration, then the tile by the pyramid/detector kernel's, then the
-stereo mode by the frame's device time. The winners go into a JSON cache
+mean duration (one keypoint per wave over all grids, then two per wave with
+the best grid and with one launch per item), then the tile by the
+pyramid/detector kernel's, then the stereo mode by the frame's device time.
+Last, keypoints per wave are decided again in the production setting -- three
+frames in flight, the next frames' pyramids running beside this frame's
+tracking -- by the pipelined frame time of the winner against the same shape
+with the other choice: a kernel alone on the chip and a kernel that shares it
+with the pyramid can favour different shapes. The winners go into a JSON cache
 keyed by the device's architecture and compute-unit count, which the
 benchmark reads.
 
@@ -66,7 +74,7 @@ def _workloads(name):
 def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None, learned_levels=2,
             learned_iters=3, log=print):
     """Mean pyramid, tracker, all-kernel and frame device times (ms) of each
-    (waves_per_cu, block_waves, tile, stereo_mode) candidate."""
+    (waves_per_cu, block_waves, tile, stereo_mode, kp_per_wave) candidate."""
     import torch
 
     import paper_2609_30459_amd as vf
@@ -84,9 +92,9 @@ def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None,
         extra = dict(init_mode=1, learned_levels=learned_levels, learned_iters=learned_iters, learned_rho=rho)
     ids = list(range(len(ws)))
     out = []
-    for wpc, bw, tile, smode in shapes:
+    for wpc, bw, tile, smode, kpw in shapes:
         p = vf.params_for(ws[0], eager=True, track_waves_per_cu=wpc, track_block_waves=bw, pyr_tile=tile,
-                          stereo_mode=smode, **extra)
+                          stereo_mode=smode, track_kp_per_wave=kpw, **extra)
         pyr, track, total, frame = [], [], [], []
         with vf.Frontend(streams, p) as fe:
             if init == "learned":
@@ -102,35 +110,105 @@ def measure(workload: str, init: str, shapes, frames=40, warmup=8, weights=None,
                     total.append(sum(st["last_stage_ms"]) + sum(max(0.0, m) for m in st["last_learned_ms"]))
                     frame.append(st["last_gpu_ms"])
         r = {"track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile, "stereo_mode": smode,
-             "pyr_ms": float(np.mean(pyr)), "track_ms": float(np.mean(track)), "kernels_ms": float(np.mean(total)),
+             "track_kp_per_wave": kpw, "pyr_ms": float(np.mean(pyr)), "track_ms": float(np.mean(track)), "kernels_ms": float(np.mean(total)),
              "frame_ms": float(np.mean(frame))}
-        log(f"  waves/CU {wpc:2d}  waves/block {bw}  tile {tile}  stereo {smode}: pyramid {r['pyr_ms'] * 1e3:7.1f} "
+        log(f"  waves/CU {wpc:2d}  waves/block {bw}  keypoints/wave {kpw}  tile {tile}  stereo {smode}: "
+            f"pyramid {r['pyr_ms'] * 1e3:7.1f} "
             f"us, tracker {r['track_ms'] * 1e3:7.1f} us, kernels {r['kernels_ms'] * 1e3:7.1f} us, frame "
             f"{r['frame_ms'] * 1e3:7.1f} us")
         out.append(r)
     return out
 
 
+def pipelined_ms(workload: str, init: str, shape, frames=60, warmup=15, depth=3, weights=None, learned_levels=2,
+                 learned_iters=3):
+    """Wall time per frame (ms) of the pipelined production loop -- plain launches, `depth` frames in
+    flight, records read for every frame -- with shape = (waves_per_cu, block_waves, tile,
+    stereo_mode, kp_per_wave)."""
+    import torch
+
+    import paper_2609_30459_amd as vf
+    import synthgen
+    from paper_2609_30459_amd.train_mlp import load_weights
+
+    ws = _workloads(workload)
+    n = warmup + frames
+    seqs = [synthgen.sequence(w, seq=0, stream=i, n_frames=n) for i, w in enumerate(ws)]
+    devs = [torch.from_numpy(q.frames).cuda() for q in seqs]
+    streams = [(w.n_cams, w.width, w.height, w.max_keypoints, w.cell_size) for w in ws]
+    wpc, bw, tile, smode, kpw = shape
+    extra, params, rho = {}, None, None
+    if init == "learned":
+        params, rho, _ = load_weights(weights or os.path.join(HERE, "weights", "mlp_stereo1280.bin"))
+        extra = dict(init_mode=1, learned_levels=learned_levels, learned_iters=learned_iters, learned_rho=rho)
+    ids = list(range(len(ws)))
+    fe = vf.Frontend(streams, vf.params_for(ws[0], plain=True, track_waves_per_cu=wpc, track_block_waves=bw,
+                                            pyr_tile=tile, stereo_mode=smode, track_kp_per_wave=kpw, **extra))
+    try:
+        if params is not None:
+            fe.set_mlp(params, rho)
+        imgs = [fe.device_images([devs[i][t, c] for i, w in enumerate(ws) for c in range(w.n_cams)])
+                for t in range(n)]
+
+        def submit(t):
+            fe.stage_frames_device(ids, [t + 1] * len(ws), imgs[t])
+            fe.step_async()
+
+        def collect():
+            fe.wait()
+            fe.get_tracks_many(ids)
+
+        for t in range(warmup):
+            submit(t)
+            collect()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(warmup, n):
+            submit(t)
+            if t - warmup >= depth - 1:
+                collect()
+        for _ in range(min(depth - 1, frames)):
+            collect()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / frames
+    finally:
+        fe.close()
+
+
 def tune(workload: str, init: str, frames=40, path=CACHE, log=print, **kw):
     """Measures every candidate, stores the fastest in the cache and returns it."""
     t0 = time.time()
-    res = measure(workload, init, [(w, b, 64, 0) for w, b in SHAPES], frames=frames, log=log, **kw)
+    res = measure(workload, init, [(w, b, 64, 0, 1) for w, b in SHAPES], frames=frames, log=log, **kw)
     best = min(res, key=lambda r: r["track_ms"])
     wpc, bw = best["track_waves_per_cu"], best["track_block_waves"]
-    res += measure(workload, init, [(wpc, bw, 32, 0)], frames=frames, log=log, **kw)
-    tile = min((r for r in res if (r["track_waves_per_cu"], r["track_block_waves"]) == (wpc, bw)),
-               key=lambda r: r["pyr_ms"])["pyr_tile"]
-    res += measure(workload, init, [(wpc, bw, tile, 1)], frames=frames, log=log, **kw)
-    final = [r for r in res if (r["track_waves_per_cu"], r["track_block_waves"], r["pyr_tile"]) == (wpc, bw, tile)]
+    # keypoints per wavefront: two per wave with the best grid, and with the
+    # one-launch-per-item grid
+    res += measure(workload, init, sorted({(wpc, bw, 64, 0, 2), (0, 4, 64, 0, 2)}), frames=frames, log=log, **kw)
+    best = min(res, key=lambda r: r["track_ms"])
+    wpc, bw, kpw = best["track_waves_per_cu"], best["track_block_waves"], best["track_kp_per_wave"]
+    shape = lambda r: (r["track_waves_per_cu"], r["track_block_waves"], r["track_kp_per_wave"])  # noqa: E731
+    res += measure(workload, init, [(wpc, bw, 32, 0, kpw)], frames=frames, log=log, **kw)
+    tile = min((r for r in res if shape(r) == (wpc, bw, kpw)), key=lambda r: r["pyr_ms"])["pyr_tile"]
+    res += measure(workload, init, [(wpc, bw, tile, 1, kpw)], frames=frames, log=log, **kw)
+    final = [r for r in res if shape(r) == (wpc, bw, kpw) and r["pyr_tile"] == tile]
     pick = min(final, key=lambda r: r["frame_ms"])
-    entry = {"track_waves_per_cu": wpc, "track_block_waves": bw, "pyr_tile": tile, "stereo_mode": pick["stereo_mode"],
-             "track_ms": best["track_ms"], "pyr_ms": pick["pyr_ms"], "frame_ms": pick["frame_ms"],
-             "frames": frames, "candidates": res}
+    smode = pick["stereo_mode"]
     cache = _load_cache(path)
+    old = cache.get(device_key(), {}).get(f"{workload}:{init}", {})
+    # keypoints per wave in the pipelined production loop; a learned stage
+    # fused into the tracker (a choice kept from the benchmark sweeps) runs one
+    # keypoint per wave
+    kps = (1,) if init == "learned" and old.get("learned_fused") else (1, 2)
+    piped = {k: pipelined_ms(workload, init, (wpc, bw, tile, smode, k), **kw) for k in kps}
+    log("  pipelined: " + ", ".join(f"{k} keypoint(s) per wave {v * 1e3:.1f} us/frame" for k, v in piped.items()))
+    kpw = min(piped, key=piped.get)
+    entry = {"track_waves_per_cu": wpc, "track_block_waves": bw, "track_kp_per_wave": kpw, "pyr_tile": tile,
+             "stereo_mode": smode, "track_ms": best["track_ms"], "pyr_ms": pick["pyr_ms"],
+             "frame_ms": pick["frame_ms"], "pipelined_ms": {str(k): v for k, v in piped.items()}, "frames": frames,
+             "candidates": res}
     # the learned stage's choices (its own launch or fused into the tracker,
     # parallel fallbacks, keypoints per workgroup) are set from pipelined
     # benchmark sweeps, not by this kernel-time tuner: kept across re-tuning
-    old = cache.get(device_key(), {}).get(f"{workload}:{init}", {})
     for k in ("learned_fused", "track_parallel_fallback", "learned_block_waves"):
         if k in old:
             entry[k] = old[k]
@@ -139,7 +217,8 @@ def tune(workload: str, init: str, frames=40, path=CACHE, log=print, **kw):
     with open(path + ".tmp", "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(path + ".tmp", path)
-    log(f"{workload}:{init} -> waves/CU {wpc}, waves/block {bw}, tile {tile}, stereo mode {entry['stereo_mode']} "
+    log(f"{workload}:{init} -> waves/CU {wpc}, waves/block {bw}, keypoints/wave {kpw}, tile {tile}, "
+        f"stereo mode {entry['stereo_mode']} "
         f"({time.time() - t0:.1f} s)")
     return entry
 

@@ -26,6 +26,13 @@ HIPCC_FLAGS = [
 ]
 
 
+# Per-file flags. k_track.hip: LLVM's sinking of common trailing code merges
+# the stores that end the two chunk layouts of the two-keypoint level sums into
+# one store through a pointer phi, which keeps two floats of the odd-level
+# kernels in scratch memory; without it every array stays in registers (the
+# one-keypoint kernels' code hardly changes: a few instructions).
+FILE_FLAGS = {"k_track.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
+
 # host-only sanitizer flags: each -fsanitize= right after -Xarch_host
 SAN_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                   "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
@@ -46,7 +53,8 @@ def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False) -> str:
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc, *HIPCC_FLAGS, *(SAN_HOST_FLAGS if sanitize else []), *inc, "-c", src, "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []),
+               *(SAN_HOST_FLAGS if sanitize else []), *inc, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -231,12 +231,14 @@ size_t pyr_detect_lds_bytes(int levels, int tile);
 // d_segs[0..n_segs) (segment begins are global item indices). waves_per_cu = 0
 // launches one wave per item; > 0 launches a persistent grid of that many
 // waves per compute unit that pops items from FrameTable::queue_head[shape.queue].
-// Launch shape of the tracker: waves_per_cu = 0 gives one wave per work item,
-// > 0 a persistent grid of waves_per_cu * n_cus waves; block_waves waves
-// (1, 2 or kTrackWaves) per workgroup.
+// Launch shape of the tracker: waves_per_cu = 0 gives one wave per work item
+// (kp_per_wave = 1) or per two (kp_per_wave = 2, one per 32-lane half), > 0 a
+// persistent grid of waves_per_cu * n_cus waves; block_waves waves (1, 2 or
+// kTrackWaves) per workgroup.
 struct TrackShape {
   int waves_per_cu, block_waves, n_cus;
   int queue;  // the frame's work-queue counter the persistent grid pops (one per tracking launch)
+  int kp_per_wave;
 };
 hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs,
                         int n_segs, int item_base, int n_items, const Prediction* d_pred, Tuning tune,

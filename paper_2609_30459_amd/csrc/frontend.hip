@@ -291,6 +291,11 @@ int check_params(const vio_frontend_params* p, std::string& why) {
   if (p->learned_block_waves != 0 && p->learned_block_waves != 4 && p->learned_block_waves != 8 &&
       p->learned_block_waves != 16)
     return why = "learned_block_waves must be 0, 4, 8 or 16", VIO_EINVAL;
+  if (p->track_kp_per_wave < 0 || p->track_kp_per_wave > 2)
+    return why = "track_kp_per_wave must be 0, 1 or 2", VIO_EINVAL;
+  if (p->track_kp_per_wave == 2 && p->init_mode == VIO_INIT_LEARNED && p->learned_fused)
+    return why = "track_kp_per_wave 2 needs learned_fused 0 (the fused learned stage runs one keypoint per wave)",
+           VIO_EINVAL;
   if (p->learned_fused != 0 && p->learned_fused != 1) return why = "learned_fused must be 0 or 1", VIO_EINVAL;
   if (p->pyramid_stream < VIO_PYRAMID_SIGNAL || p->pyramid_stream > VIO_PYRAMID_SAME_STREAM)
     return why = "pyramid_stream must be VIO_PYRAMID_SIGNAL, _EVENT or _SAME_STREAM", VIO_EINVAL;
@@ -719,7 +724,8 @@ static hipError_t track_range(vio_frontend* h, const LaunchSet& ls, int seg_begi
   return launch_track(h->d_cams, h->d_frame, h->d_cnt, (ls.all ? h->d_segs_all : h->d_segs) + seg_begin, n_segs,
                       item_begin, n_items, h->d_pred, tune,
                       TrackShape{h->P.track_waves_per_cu,
-                                 h->P.track_block_waves ? h->P.track_block_waves : kTrackWaves, h->n_cus, queue},
+                                 h->P.track_block_waves ? h->P.track_block_waves : kTrackWaves, h->n_cus, queue,
+                                 h->P.track_kp_per_wave ? h->P.track_kp_per_wave : 1},
                       st);
 }
 

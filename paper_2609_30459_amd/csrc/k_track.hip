@@ -49,6 +49,12 @@
 #include "learn_ops.h"
 #include "wave_ops.h"
 
+// Multiply-adds are fused only within one expression (a * b + c), never
+// across statements, so the rounding of every step follows from the source
+// alone: the one- and two-keypoint-per-wave kernels, whose surrounding code
+// differs, compute the same values.
+#pragma clang fp contract(on)
+
 namespace vio {
 namespace {
 
@@ -514,22 +520,6 @@ __device__ __forceinline__ void store_result(TrackRes* dst, const TrackRes& r, i
   __builtin_amdgcn_raw_buffer_store_b32(val, rs, lane * 4, 0, 0);
 }
 
-// One work item: a temporal track (camera c, slot j) or the stereo match of a
-// detection (camera c, item j). A temporal track starts from the caller's
-// prediction, else from the camera-model projection when the frame carries a
-// motion for the camera, else from the constant-velocity guess. Two tracks
-// first try a short budget and are kept when they pass the forward-backward
-// check with a residual RMS within a limit: with learned initialisation
-// (tune.learned), an unpredicted track runs tune.llevels levels with
-// tune.liters iterations from the network's guess, and a predicted one runs
-// tune.plevels x tune.piters from its prediction when tune.plevels > 0.
-// Otherwise, and whenever the short attempt does not hold, the full budget
-// runs from the track's start (pad[0] = 1 marks such a fallback); a learned
-// track's fallback from the constant-velocity start runs tune.fblevels x
-// tune.fbiters. A stereo match starts from the rig's extrinsics when the
-// target camera has them, else (tune.stereo_nb) from the nearest paired
-// keypoint's offset with tune.slevels x tune.siters, else from the disparity
-// prior with the full budget.
 // The learned start of a temporal item when the learned stage is fused into
 // the tracker: the keypoint's features -- the flows of the 8 nearest tracks
 // with a flow in the previous frame's live set (exact keys; each lane reads
@@ -595,11 +585,46 @@ __device__ __forceinline__ void learned_guess(const CamDesc& cd, const FrameCam&
   mlp_row(W, tune.mlpP, sx, sx + MI, lane, out);
 }
 
-template <int L, bool F>
-__device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
-                                             const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
-                                             int n_segs, const Prediction* __restrict__ pred, const Tuning& tune,
-                                             int item, int lane, float u, float v, float wgt, uint16_t* sx) {
+// What one work item runs: cameras and pyramid slots, the keypoint, the
+// starts and budgets of its attempts, and its record (out == nullptr: the item
+// has nothing to do). Attempts first..last run, 0 the short budget from
+// (gx, gy, gth), 1 the full one from (ix, iy, ith); a short track is kept when
+// it passes the forward-backward check with a residual RMS <= srho.
+struct Plan {
+  const CamDesc* src;
+  const CamDesc* dst;
+  TrackRes* out;
+  int ssrc, sdst;
+  float px, py, ix, iy, ith, gx, gy, gth, srho;
+  int sl, si, fl, fi;
+  int first, last;
+  int pad0;  // 1: a parallel fallback item, whose record always marks the fallback
+};
+
+// The plan of work item `item` (G = lanes per item: 64, or 32 with two items
+// per wave, each half planning its own). A temporal track (camera c, slot j)
+// starts from the caller's prediction, else from the camera-model projection
+// when the frame carries a motion for the camera, else from the
+// constant-velocity guess. Two tracks first try a short budget: with learned
+// initialisation (tune.learned), an unpredicted track runs tune.llevels levels
+// with tune.liters iterations from the network's guess, and a predicted one
+// runs tune.plevels x tune.piters from its prediction when tune.plevels > 0.
+// Otherwise, and whenever the short attempt does not hold, the full budget
+// runs from the track's start (pad[0] = 1 marks such a fallback); a learned
+// track's fallback from the constant-velocity start runs tune.fblevels x
+// tune.fbiters. A stereo match of a detection (camera c, item j) starts from
+// the rig's extrinsics when the target camera has them, else
+// (tune.stereo_nb) from the nearest paired keypoint's offset with
+// tune.slevels x tune.siters, else from the disparity prior with the full
+// budget.
+template <bool F, int G>
+__device__ __forceinline__ Plan plan_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
+                                          const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
+                                          int n_segs, const Prediction* __restrict__ pred, const Tuning& tune,
+                                          int item, bool in_range, int lane, uint16_t* sx) {
+  static_assert(G == kW || (G == kW / 2 && !F), "the fused learned stage runs one item per wave");
+  Plan pl{};
+  if (!in_range) return pl;
   // the last segment that begins at or before the item (begins ascend)
   int lo = 0, hi = n_segs - 1;
   while (lo < hi) {
@@ -609,30 +634,26 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
   }
   const TrackSeg sg = segs[lo];
   const int j = item - sg.begin;
-  if (j < 0 || j >= sg.count) return;
+  if (j < 0 || j >= sg.count) return pl;
   const int c = sg.cam;
   const CamDesc& cd = cams[c];
   const FrameCam& fc = frame->cam[c];
-  if (!fc.active) return;
+  if (!fc.active) return pl;
   const int P = fc.parity;
-  const CamDesc* src = &cd;
-  const CamDesc* dst;
-  int ssrc, sdst;
-  // the short attempt: start (gx, gy, gth), budget (sl, si), kept when
-  // tracked with a residual RMS <= srho, else the full budget from (ix, iy, ith)
-  float px, py, ix, iy, ith = 0.f, gx = 0.f, gy = 0.f, gth = 0.f, srho = 0.f;
-  int sl = 0, si = 0;
+  pl.src = &cd;
+  pl.ith = 0.f;
   // the budget of the attempt from (ix, iy, ith): the full one unless stated
-  int fl = tune.levels, fi = tune.iters;
+  pl.fl = tune.levels;
+  pl.fi = tune.iters;
   bool try_short = false;
   TrackRes* out;
   if (sg.mode != kModeStereo) {  // a temporal track, or its parallel fallback
-    if (!fc.has_prev || j >= cnt->n_live[P ^ 1][c]) return;
+    if (!fc.has_prev || j >= cnt->n_live[P ^ 1][c]) return pl;
     const Kp kp = cd.state[P ^ 1][j];
-    px = kp.x;
-    py = kp.y;
-    ix = kp.x + (kp.x - kp.px);
-    iy = kp.y + (kp.y - kp.py);
+    pl.px = kp.x;
+    pl.py = kp.y;
+    pl.ix = kp.x + (kp.x - kp.px);
+    pl.iy = kp.y + (kp.y - kp.py);
     bool predicted = false;
     const int np = fc.n_pred;
     if (np > 0) {  // caller predictions, ascending id: binary search
@@ -642,8 +663,8 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
         const int mid = (lo + hi) >> 1;
         const int64_t mid_id = pp[mid].id;
         if (mid_id == kp.id) {
-          ix = pp[mid].x;
-          iy = pp[mid].y;
+          pl.ix = pp[mid].x;
+          pl.iy = pp[mid].y;
           predicted = true;
           break;
         }
@@ -682,11 +703,11 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
       const float Z = R[6] * a + R[7] * b + R[8] + rho * fc.t[2];
       if (fc.kb4) {
         const Model m{fc.K, fc.kk, 1};
-        predicted = model_start(m, m, R, fc.t, rho, kp.x, kp.y, ix, iy, ith);
+        predicted = model_start(m, m, R, fc.t, rho, kp.x, kp.y, pl.ix, pl.iy, pl.ith);
       } else if (Z > 1e-6f && Z + R[6] / fx > 1e-6f) {
-        ix = fx * (X / Z) + fc.K[2];
-        iy = fy * (Y / Z) + fc.K[3];
-        ith = atan2f((fy / fx) * (R[3] * Z - R[6] * Y), R[0] * Z - R[6] * X);
+        pl.ix = fx * (X / Z) + fc.K[2];
+        pl.iy = fy * (Y / Z) + fc.K[3];
+        pl.ith = atan2f((fy / fx) * (R[3] * Z - R[6] * Y), R[0] * Z - R[6] * X);
         predicted = true;
       }
     }
@@ -703,41 +724,40 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
         gsv[0] = gs[0];
         gsv[1] = gs[1];
       }
-      gx = kp.x + 16.f * gsv[0];
-      gy = kp.y + 16.f * gsv[1];
-      sl = tune.llevels;
-      si = tune.liters;
-      srho = tune.rho;
+      pl.gx = kp.x + 16.f * gsv[0];
+      pl.gy = kp.y + 16.f * gsv[1];
+      pl.sl = tune.llevels;
+      pl.si = tune.liters;
+      pl.srho = tune.rho;
       try_short = true;
       // the fallback from the constant-velocity start has its own budget
-      fl = tune.fblevels;
-      fi = tune.fbiters;
+      pl.fl = tune.fblevels;
+      pl.fi = tune.fbiters;
     }
     if (predicted && tune.plevels > 0) {
       // a predicted start needs a smaller search range: the short budget
       // first, the full one from the same start when it does not hold
-      gx = ix;
-      gy = iy;
-      gth = ith;
-      sl = tune.plevels;
-      si = tune.piters;
-      srho = tune.prho;
+      pl.gx = pl.ix;
+      pl.gy = pl.iy;
+      pl.gth = pl.ith;
+      pl.sl = tune.plevels;
+      pl.si = tune.piters;
+      pl.srho = tune.prho;
       try_short = true;
     }
-    dst = &cd;
-    ssrc = fc.pyr_prev;
-    sdst = fc.pyr;
+    pl.dst = &cd;
+    pl.ssrc = fc.pyr_prev;
+    pl.sdst = fc.pyr;
     out = cd.res + j;
     if (sg.mode == kModeFallback) {
       // the fallback attempt only, for a track that tries a short budget
       // first (its temporal item runs that, and the selection takes this
       // result when the short track is not kept)
-      if (!try_short) return;
-      TrackRes r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, ix, iy, ith, fl, fi, tune.fb_threshold, u, v, wgt,
-                               lane);
-      r.pad[0] = 1;
-      store_result(cd.res_fb + j, r, lane);
-      return;
+      if (!try_short) return pl;
+      pl.first = pl.last = 1;
+      pl.pad0 = 1;
+      pl.out = cd.res_fb + j;
+      return pl;
     }
   } else {
     // stereo match of a detection into target camera c + 1 + t (item j =
@@ -746,35 +766,38 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
     const int t = cd.n_targets > 1 ? j / cd.nslots : 0;
     const int i = j - t * cd.nslots;
     if (tune.deferred) {
-      if (i >= cnt->n_sel[c]) return;
+      if (i >= cnt->n_sel[c]) return pl;
       const Kp kp = cd.state[P][cnt->sel_base[c] + i];
-      px = kp.x;
-      py = kp.y;
+      pl.px = kp.x;
+      pl.py = kp.y;
     } else {
       const uint32_t key = cd.keys[fc.pyr][i];
-      if (key == 0) return;
+      if (key == 0) return pl;
       const int idx = 0xFFFFFF - (int)(key & 0xFFFFFFu);
-      px = (float)(idx % cd.w);
-      py = (float)(idx / cd.w);
+      pl.px = (float)(idx % cd.w);
+      pl.py = (float)(idx / cd.w);
     }
+    const float px = pl.px, py = pl.py;
     const int tc = c + 1 + t;
-    dst = &cams[tc];
-    ix = px - tune.disparity0;
-    iy = py;
+    const CamDesc* dst = &cams[tc];
+    pl.dst = dst;
+    pl.ix = px - tune.disparity0;
+    pl.iy = py;
     if (tune.stereo_nb && !dst->has_ext) {
       // neighbour start: of the keypoints that after the previous frame lived
       // in both cameras (the target's pair table, id order), the nearest by
       // (squared distance in double, where the float differences and squares
       // are exact, then id) lends its offset; one candidate per lane per
-      // round, then a wave minimum
+      // round, then a minimum over the item's lanes
       const int Pq = frame->cam[tc].parity ^ 1;
-      const int np = __builtin_amdgcn_readfirstlane(cnt->n_pairs[Pq][tc]);  // wave-uniform trip count
+      int np = cnt->n_pairs[Pq][tc];
+      if constexpr (G == kW) np = __builtin_amdgcn_readfirstlane(np);  // wave-uniform trip count
       if (np > 0) {
         const float4* pt = dst->pairs[Pq];
         double bd = INFINITY;
         int bi = 0x7FFFFFFF;
-        for (int q0 = 0; q0 < np; q0 += kW) {
-          const int q = q0 + lane;
+        for (int q0 = 0; q0 < np; q0 += G) {
+          const int q = q0 + (lane & (G - 1));
           if (q < np) {
             const float4 e = pt[q];
             const double dx = (double)e.x - (double)px, dy = (double)e.y - (double)py;
@@ -786,7 +809,7 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
           }
         }
 #pragma unroll
-        for (int o = kW / 2; o > 0; o >>= 1) {
+        for (int o = G / 2; o > 0; o >>= 1) {
           const double od = __shfl_xor(bd, o);
           const int oi = __shfl_xor(bi, o);
           if (od < bd || (od == bd && oi < bi)) {
@@ -794,11 +817,12 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
             bi = oi;
           }
         }
-        const float4 e = pt[__builtin_amdgcn_readfirstlane(bi)];
-        ix = px + e.z;
-        iy = py + e.w;
-        fl = tune.slevels;
-        fi = tune.siters;
+        if constexpr (G == kW) bi = __builtin_amdgcn_readfirstlane(bi);
+        const float4 e = pt[bi];
+        pl.ix = px + e.z;
+        pl.iy = py + e.w;
+        pl.fl = tune.slevels;
+        pl.fi = tune.siters;
       }
     }
     if (dst->has_ext) {
@@ -818,36 +842,398 @@ __device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, c
         const Model ms{Ks, dst->ext_ks, dst->ext_kbs}, mt{Kt, dst->ext_kt, dst->ext_kbt};
         float sx, sy, sth;
         if (model_start(ms, mt, R, dst->ext_t, rho, px, py, sx, sy, sth)) {
-          ix = sx;
-          iy = sy;
-          ith = sth;
+          pl.ix = sx;
+          pl.iy = sy;
+          pl.ith = sth;
         }
       } else if (Z > 1e-6f && Z + R[6] / Ks[0] > 1e-6f) {
-        ix = Kt[0] * (X / Z) + Kt[2];
-        iy = Kt[1] * (Y / Z) + Kt[3];
-        ith = atan2f(Kt[1] * (R[3] * Z - R[6] * Y), Kt[0] * (R[0] * Z - R[6] * X));
+        pl.ix = Kt[0] * (X / Z) + Kt[2];
+        pl.iy = Kt[1] * (Y / Z) + Kt[3];
+        pl.ith = atan2f(Kt[1] * (R[3] * Z - R[6] * Y), Kt[0] * (R[0] * Z - R[6] * X));
       }
     }
-    ssrc = fc.pyr;
-    sdst = fc.pyr;
+    pl.ssrc = fc.pyr;
+    pl.sdst = fc.pyr;
     out = cd.sres + j;
   }
-  TrackRes r;
-  int fell_back = 0;
   // with parallel fallbacks a short attempt is the item's only one
-  const int last = try_short && tune.par_fb ? 0 : 1;
+  pl.first = try_short ? 0 : 1;
+  pl.last = try_short && tune.par_fb ? 0 : 1;
+  pl.out = out;
+  return pl;
+}
+
+// One work item per wave.
+template <int L, bool F>
+__device__ __forceinline__ void process_item(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
+                                             const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
+                                             int n_segs, const Prediction* __restrict__ pred, const Tuning& tune,
+                                             int item, int lane, float u, float v, float wgt, uint16_t* sx) {
+  const Plan pl = plan_item<F, kW>(cams, frame, cnt, segs, n_segs, pred, tune, item, true, lane, sx);
+  if (!pl.out) return;
+  TrackRes r;
+  int fell_back = pl.pad0;
 #pragma unroll 1
-  for (int a = try_short ? 0 : 1; a <= last; ++a) {
+  for (int a = pl.first; a <= pl.last; ++a) {
     const bool short_run = a == 0;
-    r = track_fb<L>(*src, ssrc, *dst, sdst, px, py, short_run ? gx : ix, short_run ? gy : iy, short_run ? gth : ith,
-                    short_run ? sl : fl, short_run ? si : fi, tune.fb_threshold, u, v, wgt, lane);
+    r = track_fb<L>(*pl.src, pl.ssrc, *pl.dst, pl.sdst, pl.px, pl.py, short_run ? pl.gx : pl.ix,
+                    short_run ? pl.gy : pl.iy, short_run ? pl.gth : pl.ith, short_run ? pl.sl : pl.fl,
+                    short_run ? pl.si : pl.fi, tune.fb_threshold, u, v, wgt, lane);
     if (short_run) {
-      if (r.status == VIO_TRACKED && r.resid <= srho) break;
+      if (r.status == VIO_TRACKED && r.resid <= pl.srho) break;
       fell_back = 1;
     }
   }
   r.pad[0] = fell_back;
-  store_result(out, r, lane);
+  store_result(pl.out, r, lane);
+}
+
+// ---- two keypoints per wave -------------------------------------------------
+// Half h = lane / 32 of the wave tracks one keypoint; lane g = lane mod 32 of a
+// half holds pattern points g (index 0 of the per-lane arrays) and g + 32
+// (index 1; weight 0 from g = 20 on, where the index passes the 52 points).
+// Per keypoint the steps, decisions and arithmetic are those of klt_pass, and
+// the sums over the pattern run through the same tree (half_sums), so a half
+// computes what one wave computes for the same keypoint, bit for bit. Levels,
+// iterations and descriptors are the wave's; `act` (uniform across each half)
+// says which halves run the pass. A half that leaves the procedure keeps its
+// status and idles (its loads masked off) while the other half goes on.
+// level_sums for two keypoints per wave: out[K l + k] <- the half's total of
+// value k of level l, gen(K l + k, point) giving each lane's two values.
+template <int L, int K, int l = 0, class Gen>
+__device__ __forceinline__ void level_pair_sums2(float* out, const Gen& gen, int nl, int lane) {
+  if constexpr (l < L) {
+    if (l < nl) half_sums_of<(l + 1 < L ? 2 : 1) * K, K * l>(out, gen, lane);
+    level_pair_sums2<L, K, l + 2>(out, gen, nl, lane);
+  }
+}
+template <int L, int K, class Gen>
+__device__ __forceinline__ void level_sums2(float* out, const Gen& gen, int nl, int lane) {
+  if (nl >= L) half_sums_of<K * L, 0>(out, gen, lane);
+  else level_pair_sums2<L, K>(out, gen, nl, lane);
+}
+
+template <int L>
+__device__ __forceinline__ PassOut klt_pass2(const CamDesc& csrc_in, int ssrc_in, const CamDesc& cdst_in, int sdst_in,
+                                             float px, float py, float ix, float iy, float ith, int nl_in, int N_in,
+                                             const float* u, const float* v, float wb, bool act, int lane) {
+  // point g < 32 is always one of the 52: its weight is 1
+  const float wgt[2] = {1.f, wb};
+  const cdesc_k csrc = (cdesc_k)uniform_ptr(&csrc_in);
+  const cdesc_k cdst = (cdesc_k)uniform_ptr(&cdst_in);
+  const int ssrc = __builtin_amdgcn_readfirstlane(ssrc_in), sdst = __builtin_amdgcn_readfirstlane(sdst_in);
+  const int nl = __builtin_amdgcn_readfirstlane(nl_in), N = __builtin_amdgcn_readfirstlane(N_in);
+  PassOut o{VIO_TRACKED, 0.f, 0.f, 0.f, 0.f};
+  bool live = act;  // the half is still in the procedure
+  // ---- templates of all levels (Sec. III-E) ------------------------------
+  bool fits[L], valid[L];
+  float T[L][2], G0[L][2], G1[L][2], G2[L][2], k[3 * L];
+  float I0[L][2], gxr[L][2], gyr[L][2];
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    fits[l] = false;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) I0[l][q] = gxr[l][q] = gyr[l][q] = 0.f;
+    if (l < nl) {
+      const Level S = level_of(csrc, ssrc, l);
+      const float sc = 1.f / (float)(1 << l);
+      float sx[2], sy[2];
+      bool in = true;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        sx[q] = px * sc + u[q];
+        sy[q] = py * sc + v[q];
+        in = in & in_dom(S, sx[q] - 1.f, sy[q]) & in_dom(S, sx[q] + 1.f, sy[q]) & in_dom(S, sx[q], sy[q] - 1.f) &
+             in_dom(S, sx[q], sy[q] + 1.f);
+      }
+      fits[l] = half_all(in, lane) && live;
+      if (fits[l]) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) template_samples(S, sx[q], sy[q], I0[l][q], gxr[l][q], gyr[l][q]);
+      }
+    }
+  }
+  float mean[L];
+  level_sums2<L, 1>(mean, [&](int l, int q) { return wgt[q] * I0[l][q]; }, nl, lane);
+  float J0[L][2], J1[L][2], J2[L][2];
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    mean[l] *= 1.f / 52.f;
+    const float im = rcp(mean[l]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      T[l][q] = I0[l][q] * im;
+      J0[l][q] = gxr[l][q] * im;
+      J1[l][q] = gyr[l][q] * im;
+      J2[l][q] = J1[l][q] * u[q] - J0[l][q] * v[q];
+    }
+  }
+  // H_l = sum w J^T J: (00, 01, 02, 11, 12, 22) of level l at 6 l .. 6 l + 5
+  float hs[6 * L];
+  level_sums2<L, 6>(
+      hs,
+      [&](int i, int q) {
+        const int l = i / 6, m = i % 6;
+        const float a = m < 3 ? J0[l][q] : m < 5 ? J1[l][q] : J2[l][q];
+        const float b = m == 0 ? J0[l][q] : m == 1 || m == 3 ? J1[l][q] : J2[l][q];
+        return wgt[q] * a * b;
+      },
+      nl, lane);
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    valid[l] = false;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) G0[l][q] = G1[l][q] = G2[l][q] = 0.f;
+    if (l >= nl) continue;  // a level the pass does not visit
+    const float h00 = hs[6 * l + 0], h01 = hs[6 * l + 1], h02 = hs[6 * l + 2];
+    const float h11 = hs[6 * l + 3], h12 = hs[6 * l + 4], h22 = hs[6 * l + 5];
+    // 3x3 inverse by cofactors (H symmetric); degenerate when det <= 1e-6 (tr/3)^3
+    const float c00 = h11 * h22 - h12 * h12;
+    const float c01 = h12 * h02 - h01 * h22;
+    const float c02 = h01 * h12 - h11 * h02;
+    const float det = h00 * c00 + h01 * c01 + h02 * c02;
+    const float tr3 = (h00 + h11 + h22) * (1.f / 3.f);
+    const float id = rcp(det);
+    const float i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
+    const float i11 = (h00 * h22 - h02 * h02) * id;
+    const float i12 = (h02 * h01 - h00 * h12) * id;
+    const float i22 = (h00 * h11 - h01 * h01) * id;
+    bool fin = true;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      G0[l][q] = wgt[q] * (i00 * J0[l][q] + i01 * J1[l][q] + i02 * J2[l][q]);
+      G1[l][q] = wgt[q] * (i01 * J0[l][q] + i11 * J1[l][q] + i12 * J2[l][q]);
+      G2[l][q] = wgt[q] * (i02 * J0[l][q] + i12 * J1[l][q] + i22 * J2[l][q]);
+      fin = fin & isfinite(G0[l][q]) & isfinite(G1[l][q]) & isfinite(G2[l][q]);
+    }
+    valid[l] = mean[l] > 0.f && det > 1e-6f * tr3 * tr3 * tr3 && half_all(fin, lane);
+  }
+  // c_l = sum G_i T_i
+  level_sums2<L, 3>(
+      k,
+      [&](int i, int q) {
+        const int l = i / 3, m = i % 3;
+        return (m == 0 ? G0[l][q] : m == 1 ? G1[l][q] : G2[l][q]) * T[l][q];
+      },
+      nl, lane);
+  // ---- coarse-to-fine Gauss-Newton (eqs. 4-5) ------------------------------
+  float tx = ldexpf(ix, 1 - nl), ty = ldexpf(iy, 1 - nl), th = ith;
+#pragma unroll
+  for (int l = L - 1; l >= 0; --l) {
+    if (l >= nl) continue;
+    if (l < nl - 1) {
+      tx = tx * 2.f;
+      ty = ty * 2.f;
+    }
+    // a level whose template does not fit is skipped, and at level 0 the track is lost
+    if (live && !fits[l] && l == 0) {
+      o.status = VIO_LOST_OOB;
+      live = false;
+    }
+    if (live && fits[l] && !valid[l]) {
+      o.status = VIO_LOST_DEGENERATE;
+      live = false;
+    }
+    bool run = live && fits[l];
+    if (!wave_any(run)) {
+      if (!wave_any(live)) break;
+      continue;
+    }
+    const Level D = level_of(cdst, sdst, l);
+    for (int it = 0; it < N; ++it) {
+      const float cs = __cosf(th), sn = __sinf(th);
+      float wx[2], wy[2];
+      bool in = true;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        wx[q] = (cs * u[q] - sn * v[q]) + tx;
+        wy[q] = (sn * u[q] + cs * v[q]) + ty;
+        in = in & in_dom(D, wx[q], wy[q]);
+      }
+      if (half_any(!in, lane) && run) {
+        o.status = VIO_LOST_OOB;
+        live = run = false;
+      }
+      if (!wave_any(run)) break;
+      float Iw[2] = {0.f, 0.f};
+      if (run) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) Iw[q] = bilinear(D, wx[q], wy[q]);
+      }
+      float S[4] = {wgt[0] * Iw[0], G0[l][0] * Iw[0], G1[l][0] * Iw[0], G2[l][0] * Iw[0]};
+      const float Sb[4] = {wgt[1] * Iw[1], G0[l][1] * Iw[1], G1[l][1] * Iw[1], G2[l][1] * Iw[1]};
+      half_sums<4>(S, Sb, lane);
+      const float mw = S[0] * (1.f / 52.f);
+      if (run && !(mw > 0.f)) {
+        o.status = VIO_LOST_OOB;
+        live = run = false;
+      }
+      const float imw = rcp(mw);
+      if (l == 0 && it == N - 1) {
+        const float e0 = Iw[0] * imw - T[l][0], e1 = Iw[1] * imw - T[l][1];
+        const float rs = sqrtf(half_sum(wgt[0] * e0 * e0, wgt[1] * e1 * e1, lane) * (1.f / 52.f));
+        if (run) o.resid = rs;
+      }
+      const float d0 = k[3 * l + 0] - S[1] * imw, d1 = k[3 * l + 1] - S[2] * imw, d2 = k[3 * l + 2] - S[3] * imw;
+      float a, b;
+      se2_v(d2, a, b);
+      const float vx = a * d0 - b * d1, vy = b * d0 + a * d1;
+      const float ntx = tx + (cs * vx - sn * vy);
+      const float nty = ty + (sn * vx + cs * vy);
+      const float nth = th + d2;
+      if (run) {
+        tx = ntx;
+        ty = nty;
+        th = nth;
+      }
+    }
+    if (!wave_any(live)) break;
+  }
+  o.tx = tx;
+  o.ty = ty;
+  o.th = th;
+  return o;
+}
+
+// track_fb for two keypoints per wave: the forward pass from (ix, iy, ith),
+// then, for each half whose forward track holds, the backward pass from it.
+template <int L>
+__device__ __forceinline__ TrackRes track_fb2(const CamDesc& csrc, int ssrc, const CamDesc& cdst, int sdst, float px,
+                                              float py, float ix, float iy, float ith, int nl, int N, float fb_thr,
+                                              const float* u, const float* v, float wb, bool act, int lane) {
+  TrackRes r;
+  r.x = ix;
+  r.y = iy;
+  r.theta = 0.f;
+  r.fb = 0.f;
+  r.resid = 0.f;
+  r.status = VIO_TRACKED;
+  r.pad[0] = r.pad[1] = 0;
+  const CamDesc* A = &csrc;
+  const CamDesc* B = &cdst;
+  int sa = ssrc, sb = sdst;
+  float qx = px, qy = py, gx = ix, gy = iy, gth = ith;
+  bool run = act;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    if (!wave_any(run)) break;
+    const PassOut o = klt_pass2<L>(*A, sa, *B, sb, qx, qy, gx, gy, gth, nl, N, u, v, wb, run, lane);
+    const bool ok = run && o.status == VIO_TRACKED;
+    if (run && !ok) r.status = o.status;
+    if (pass == 0) {
+      if (ok) {
+        r.x = o.tx;
+        r.y = o.ty;
+        r.theta = o.th;
+        r.resid = o.resid;
+      }
+      const CamDesc* t = A;
+      A = B;
+      B = t;
+      const int st = sa;
+      sa = sb;
+      sb = st;
+      qx = o.tx;
+      qy = o.ty;
+      gx = px;
+      gy = py;
+      gth = -o.th;
+    } else if (ok) {
+      const float dx = o.tx - px, dy = o.ty - py;
+      r.fb = sqrtf(dx * dx + dy * dy);
+      r.status = r.fb > fb_thr ? VIO_LOST_FB : VIO_TRACKED;
+    }
+    run = ok;
+  }
+  return r;
+}
+
+// A value of lane `src` (a wave-uniform constant) to every lane.
+template <class T>
+__device__ __forceinline__ T* lane_ptr(T* p, int src) {
+  const uint64_t x = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int lane_int(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
+__device__ __forceinline__ float lane_float(float x, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src));
+}
+
+// store_result for two keypoints per wave: lanes 32h .. 32h + 7 write half h's
+// record (dst of lane 32h; nullptr: none), the other lanes' stores fall
+// outside each record's buffer range.
+__device__ __forceinline__ void store_result2(TrackRes* dst, const TrackRes& r, int lane) {
+  const uint32_t w[8] = {__builtin_bit_cast(uint32_t, r.x),     __builtin_bit_cast(uint32_t, r.y),
+                         __builtin_bit_cast(uint32_t, r.theta), __builtin_bit_cast(uint32_t, r.fb),
+                         __builtin_bit_cast(uint32_t, r.resid), (uint32_t)r.status,
+                         (uint32_t)r.pad[0],                    (uint32_t)r.pad[1]};
+  const int g = lane & 31;
+  uint32_t val = w[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) val = g == k ? w[k] : val;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    TrackRes* d = lane_ptr(dst, 32 * h);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(d, (short)0, d ? (int)sizeof(TrackRes) : 0, kBufferWord3);
+    __builtin_amdgcn_raw_buffer_store_b32(val, rs, (lane >> 5) == h ? g * 4 : 1024, 0, 0);
+  }
+}
+
+// Two work items per wave, one per half (item_in_range: the half's item
+// exists). Each half plans its item and parks the plan in the wave's LDS (two
+// slots, sp), read back field by field where used, so the plan does not hold
+// registers through the tracking. The attempts then run for both halves at
+// once when they share cameras, pyramid slots and budget, else one half after
+// the other (a pair that straddles two segments or two budgets).
+template <int L>
+__device__ __forceinline__ void process_pair(const CamDesc* __restrict__ cams, const FrameTable* __restrict__ frame,
+                                             const Counters* __restrict__ cnt, const TrackSeg* __restrict__ segs,
+                                             int n_segs, const Prediction* __restrict__ pred, const Tuning& tune,
+                                             int item, bool item_in_range, int lane, const float* u, const float* v,
+                                             float wb, Plan* sp) {
+  {
+    const Plan pl =
+        plan_item<false, kW / 2>(cams, frame, cnt, segs, n_segs, pred, tune, item, item_in_range, lane, nullptr);
+    if ((lane & 31) == 0) sp[lane >> 5] = pl;
+    wave_sync_lds();
+  }
+  const Plan& me = sp[lane >> 5];
+  const Plan& p0 = sp[0];
+  const Plan& p1 = sp[1];
+  TrackRes r{};
+  int fell_back = me.pad0;
+  bool done = false;
+#pragma unroll 1
+  for (int a = 0; a <= 1; ++a) {
+    const bool want = me.out != nullptr && !done && me.first <= a && a <= me.last;
+    if (!wave_any(want)) continue;
+    const bool short_run = a == 0;
+    const bool w0 = lane_int(want, 0) != 0, w1 = lane_int(want, 32) != 0;
+    const bool same = w0 && w1 && p0.src == p1.src && p0.dst == p1.dst && p0.ssrc == p1.ssrc &&
+                      p0.sdst == p1.sdst && (short_run ? p0.sl == p1.sl && p0.si == p1.si
+                                                       : p0.fl == p1.fl && p0.fi == p1.fi);
+    const int rounds = w0 && w1 && !same ? 2 : 1;
+#pragma unroll 1
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int hs = rd == 1 || !w0 ? 1 : 0;  // the half whose cameras, slots and budget the round takes
+      const bool act = want && (same || (lane >> 5) == hs);
+      const Plan& ph = sp[hs];
+      const TrackRes t = track_fb2<L>(*ph.src, ph.ssrc, *ph.dst, ph.sdst, me.px, me.py, short_run ? me.gx : me.ix,
+                                      short_run ? me.gy : me.iy, short_run ? me.gth : me.ith,
+                                      short_run ? ph.sl : ph.fl, short_run ? ph.si : ph.fi, tune.fb_threshold, u, v,
+                                      wb, act, lane);
+      if (act) r = t;
+    }
+    if (short_run && want) {
+      done = r.status == VIO_TRACKED && r.resid <= me.srho;
+      if (!done) fell_back = 1;
+    }
+  }
+  r.pad[0] = fell_back;
+  store_result2(me.out, r, lane);
 }
 
 // One wave per work item. F: the learned stage is fused (each wave has a row
@@ -903,17 +1289,77 @@ __global__ __launch_bounds__(kW* kTrackWaves) void k_track_persistent(const CamD
   }
 }
 
+// Two work items per wave (the throughput shape for many items): wave k runs
+// items 2k (half 0) and 2k + 1 (half 1).
+template <int L>
+__global__ __launch_bounds__(kW* kTrackWaves) void k_track2(const CamDesc* __restrict__ cams,
+                                                           const FrameTable* __restrict__ frame,
+                                                           const Counters* __restrict__ cnt,
+                                                           const TrackSeg* __restrict__ segs, int n_segs,
+                                                           int item_base, int n_items,
+                                                           const Prediction* __restrict__ pred, Tuning tune) {
+  const int lane = threadIdx.x & (kW - 1);
+  const int k = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (int)(blockDim.x / kW) + (int)(threadIdx.x / kW));
+  if (2 * k >= n_items) return;
+  __shared__ Plan sPlan[kTrackWaves][2];
+  float u[2], v[2], w0, wb;
+  pattern_of(lane & 31, u[0], v[0], w0);
+  pattern_of((lane & 31) + 32, u[1], v[1], wb);
+  const int it = 2 * k + (lane >> 5);
+  process_pair<L>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + it, it < n_items, lane, u, v, wb,
+                  sPlan[threadIdx.x / kW]);
+}
+
+// The persistent grid with two items per wave: each pop takes two items.
+template <int L>
+__global__ __launch_bounds__(kW* kTrackWaves) void k_track2_persistent(const CamDesc* __restrict__ cams,
+                                                                      FrameTable* __restrict__ frame,
+                                                                      const Counters* __restrict__ cnt,
+                                                                      const TrackSeg* __restrict__ segs, int n_segs,
+                                                                      int item_base, int n_items,
+                                                                      const Prediction* __restrict__ pred,
+                                                                      Tuning tune, int queue) {
+  const int lane = threadIdx.x & (kW - 1);
+  __shared__ Plan sPlan[kTrackWaves][2];
+  float u[2], v[2], w0, wb;
+  pattern_of(lane & 31, u[0], v[0], w0);
+  pattern_of((lane & 31) + 32, u[1], v[1], wb);
+  for (;;) {
+    const int k = __builtin_amdgcn_readfirstlane(atomicAdd(&frame->queue_head[queue], lane == 0 ? 2 : 0));
+    if (k >= n_items) break;
+    const int it = k + (lane >> 5);
+    process_pair<L>(cams, frame, cnt, segs, n_segs, pred, tune, item_base + it, it < n_items, lane, u, v, wb,
+                    sPlan[threadIdx.x / kW]);
+    wave_sync_lds();  // the next item's plan overwrites this one's
+  }
+}
+
 template <int L, bool F>
 hipError_t launch_LF(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_cnt, const TrackSeg* d_segs, int n_segs,
                      int item_base, int n_items, const Prediction* d_pred, Tuning tune, TrackShape sh, hipStream_t s) {
   const int bw = sh.block_waves;
+  const int item_waves = sh.kp_per_wave == 2 ? (n_items + 1) / 2 : n_items;
   if (sh.waves_per_cu > 0) {
-    const int waves = std::min(n_items, sh.waves_per_cu * sh.n_cus);
+    const int waves = std::min(item_waves, sh.waves_per_cu * sh.n_cus);
     const int blocks = (waves + bw - 1) / bw;
+    if constexpr (!F) {
+      if (sh.kp_per_wave == 2) {
+        launch_kernel(k_track2_persistent<L>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs,
+                      n_segs, item_base, n_items, d_pred, tune, sh.queue);
+        return hipGetLastError();
+      }
+    }
     launch_kernel(k_track_persistent<L, F>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs,
                   n_segs, item_base, n_items, d_pred, tune, sh.queue);
   } else {
-    const int blocks = (n_items + bw - 1) / bw;
+    const int blocks = (item_waves + bw - 1) / bw;
+    if constexpr (!F) {
+      if (sh.kp_per_wave == 2) {
+        launch_kernel(k_track2<L>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
+                      item_base, n_items, d_pred, tune);
+        return hipGetLastError();
+      }
+    }
     launch_kernel(k_track<L, F>, dim3(blocks), dim3(kW * bw), 0, s, d_cams, d_frame, d_cnt, d_segs, n_segs,
                   item_base, n_items, d_pred, tune);
   }
@@ -935,8 +1381,10 @@ hipError_t launch_track(const CamDesc* d_cams, FrameTable* d_frame, Counters* d_
                         hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (shape.block_waves < 1 || shape.block_waves > kTrackWaves || shape.n_cus < 1 || shape.waves_per_cu < 0 ||
-      shape.queue < 0 || shape.queue >= 4)
+      shape.queue < 0 || shape.queue >= 4 || (shape.kp_per_wave != 1 && shape.kp_per_wave != 2))
     return hipErrorInvalidValue;
+  // the fused learned stage runs one item per wave
+  if (shape.kp_per_wave == 2 && tune.learned && tune.fused) return hipErrorInvalidValue;
   // the short tracker of learned initialisation runs within the full one's levels
   if (tune.learned && (tune.llevels < 1 || tune.llevels > tune.levels || tune.liters < 1)) return hipErrorInvalidValue;
   switch (tune.levels) {

@@ -52,10 +52,10 @@ __device__ __forceinline__ float rowswap_sum16(float x) {
   return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
 }
 
-// v[i] <- sum of v[i] over the 64 lanes, i < N (N = 1, 2, 4, 8 or 16), as
-// wave-uniform values.
+// The four exchange stages over N values (N = 1, 2, 4, 8 or 16): returns, in
+// lane j of every 16-lane row, sum (j mod N) of the row.
 template <int N>
-__device__ __forceinline__ void wave_sums_pow2(float* v, int lane) {
+__device__ __forceinline__ float row_sums_pow2(const float* v, int lane) {
   static_assert(N == 1 || N == 2 || N == 4 || N == 8 || N == 16, "power of two up to 16");
   float w[N];
 #pragma unroll
@@ -64,8 +64,14 @@ __device__ __forceinline__ void wave_sums_pow2(float* v, int lane) {
   xstage<0x4E, 1, (N > 2 ? N / 2 : 1)>(w, lane);
   xstage<0x124, 2, (N > 4 ? N / 4 : 1)>(w, lane);
   xstage<0x128, 3, (N > 8 ? N / 8 : 1)>(w, lane);
-  // lane j of every row holds sum j (j = lane mod N) of its row
-  const float x = rowswap_sum16(rowswap_sum32(w[0]));
+  return w[0];
+}
+
+// v[i] <- sum of v[i] over the 64 lanes, i < N (N = 1, 2, 4, 8 or 16), as
+// wave-uniform values.
+template <int N>
+__device__ __forceinline__ void wave_sums_pow2(float* v, int lane) {
+  const float x = rowswap_sum16(rowswap_sum32(row_sums_pow2<N>(v, lane)));
 #pragma unroll
   for (int i = 0; i < N; ++i) v[i] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
 }
@@ -83,6 +89,81 @@ __device__ __forceinline__ void wave_sums(float* v, int lane) {
 __device__ __forceinline__ float wave_sum(float x, int lane) {
   wave_sums_pow2<1>(&x, lane);
   return x;
+}
+
+// Sums for two items per wave, one per 32-lane half, each lane of a half
+// carrying two values of its item: a[i] at position g = lane mod 32 and b[i]
+// at position g + 32 of the item's 64. a[i] <- the item's total of value i,
+// uniform across the half, summed in exactly the order wave_sums_pow2 sums 64
+// values held one per lane: the row stages run on a and on b alone (the rows
+// of positions 0..31 and 32..63), a + b stands in for the permlane32 swap, and
+// the permlane16 swap pairs the two rows of each half. row_newbcast:i then
+// hands lane i's total to its row -- lane i's also for a single value (N = 1),
+// which every lane holds but each through its own order of the row's terms:
+// lane 0's is the one wave_sums_pow2 reads.
+template <int ctrl>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+}
+template <int N, int i = 0>
+__device__ __forceinline__ void row_broadcasts(float* v, float x) {
+  if constexpr (i < N) {
+    v[i] = dpp_mov<0x150 + i>(x);
+    row_broadcasts<N, i + 1>(v, x);
+  }
+}
+template <int N>
+__device__ __forceinline__ void half_sums_pow2(float* a, const float* b, int lane) {
+  row_broadcasts<N>(a, rowswap_sum16(row_sums_pow2<N>(a, lane) + row_sums_pow2<N>(b, lane)));
+}
+
+// a[i] <- half-wave totals of (a[i], b[i]) for i < M, chunked as wave_sums<M>
+template <int M>
+__device__ __forceinline__ void half_sums(float* a, const float* b, int lane) {
+  if constexpr (M > 0) {
+    constexpr int C = M >= 16 ? 16 : M >= 8 ? 8 : M >= 4 ? 4 : M >= 2 ? 2 : 1;
+    half_sums_pow2<C>(a, b, lane);
+    half_sums<M - C>(a + C, b + C, lane);
+  }
+}
+
+// out[i] <- half-wave totals of gen(i, 0) + gen(i, 1) for i in [OFF, OFF + M),
+// chunked and summed as half_sums (and so as wave_sums<M> on out + OFF), each
+// chunk's values made just before its stages (a's, then b's), so only one
+// chunk of one position is held at a time.
+template <int M, int OFF, class Gen>
+__device__ __forceinline__ void half_sums_of(float* out, const Gen& gen, int lane) {
+  if constexpr (M > 0) {
+    constexpr int C = M >= 16 ? 16 : M >= 8 ? 8 : M >= 4 ? 4 : M >= 2 ? 2 : 1;
+    float w[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) w[i] = gen(OFF + i, 0);
+    const float xa = row_sums_pow2<C>(w, lane);
+#pragma unroll
+    for (int i = 0; i < C; ++i) w[i] = gen(OFF + i, 1);
+    row_broadcasts<C>(out + OFF, rowswap_sum16(xa + row_sums_pow2<C>(w, lane)));
+    half_sums_of<M - C, OFF + C>(out, gen, lane);
+  }
+}
+
+__device__ __forceinline__ float half_sum(float a, float b, int lane) {
+  half_sums_pow2<1>(&a, &b, lane);
+  return a;
+}
+
+// Votes over each 32-lane half (all 64 lanes active): the half's all / any,
+// decided on the scalar unit from the ballot and handed back to the lanes as a
+// lane mask.
+__device__ __forceinline__ uint64_t half_mask(bool h0, bool h1) {
+  return (h0 ? 0x00000000FFFFFFFFull : 0ull) | (h1 ? 0xFFFFFFFF00000000ull : 0ull);
+}
+__device__ __forceinline__ bool half_all(bool p, int) {
+  const uint64_t m = __ballot(p);
+  return __builtin_amdgcn_inverse_ballot_w64(half_mask((uint32_t)m == 0xFFFFFFFFu, (uint32_t)(m >> 32) == 0xFFFFFFFFu));
+}
+__device__ __forceinline__ bool half_any(bool p, int) {
+  const uint64_t m = __ballot(p);
+  return __builtin_amdgcn_inverse_ballot_w64(half_mask((uint32_t)m != 0u, (uint32_t)(m >> 32) != 0u));
 }
 
 template <int ctrl>

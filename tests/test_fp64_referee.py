@@ -83,7 +83,13 @@ def test_tally_caps():
     t.check(1)
     t.referred.append(("unit", 7, 1e-3, 2e-3))
     with pytest.raises(AssertionError):
-        t.check(1)          # one keypoint per cell: no referral at all
+        t.check(1)          # one keypoint per cell: only a ratio below 1e-3
+    t.referred[0] = ("unit", 7, 5e-4, 2e-3)
+    t.check(1)              # ... and only one per run
+    t.referred.append(("unit", 8, 5e-4, 2e-3))
+    with pytest.raises(AssertionError):
+        t.check(1)
+    t.referred.pop()
     t.check(3)              # k > 1: up to 0.5 % of the compared tracks
     t.referred += [("unit", i, 1e-3, 2e-3) for i in range(5)]
     with pytest.raises(AssertionError):
