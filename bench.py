@@ -204,7 +204,8 @@ def main():
 
     batched = args.workload == "batch16"
     if args.steps is None:
-        args.steps = 80 if args.workload in ("batch16", "rig4") else 150
+        from paper_2609_30459_amd.autotune import bench_steps
+        args.steps = bench_steps(args.workload)
     warmup = max(args.warmup, 10)
     if batched:
         ws = list(BATCH16)
