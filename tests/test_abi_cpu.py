@@ -75,7 +75,8 @@ def test_create_rejects_bad_arguments_before_any_device_call(native):
     assert _create(native, [ok], bad) == native.VIO_EINVAL
     for field, value in (("levels", 0), ("levels", 7), ("gn_iters", 0), ("edge_margin", 3),
                          ("n_thresholds", 0), ("fb_threshold", 0.0), ("track_block_waves", 3),
-                         ("track_waves_per_cu", 65), ("flags", 8), ("pyr_tile", 48), ("stereo_mode", 2)):
+                         ("track_waves_per_cu", 65), ("flags", 8), ("pyr_tile", 48), ("stereo_mode", 2),
+                         ("track_kp_per_wave", 3), ("track_kp_per_wave", -1)):
         q = vf.default_params()
         setattr(q, field, value)
         assert _create(native, [ok], q) == native.VIO_EINVAL, field
@@ -86,6 +87,12 @@ def test_create_rejects_bad_arguments_before_any_device_call(native):
     q = vf.default_params()
     q.flags = native.VIO_FLAG_EAGER | native.VIO_FLAG_PLAIN
     assert _create(native, [ok], q) == native.VIO_EINVAL
+    # two keypoints per wave cannot host the fused learned stage
+    q = vf.default_params()
+    q.track_kp_per_wave, q.init_mode, q.learned_fused = 2, 1, 1
+    assert _create(native, [ok], q) == native.VIO_EINVAL
+    q.learned_fused = 0  # its own launch: the arguments pass (the device call that follows fails here)
+    assert _create(native, [ok], q) != native.VIO_EINVAL
     # a device allocator needs both callbacks
     cb = native.DEV_ALLOC(lambda n, ctx: None)
     q = vf.default_params()
