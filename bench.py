@@ -46,6 +46,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP32 vector without packed (two-per-lane) math, the form the tracker is built in:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_VECTOR_UNPACKED_TFLOPS = 78.6
+
+
+def copy_peak_gbs(nbytes=1 << 29, reps=10):
+    """Achievable device bandwidth on this GPU: a device-to-device copy of nbytes, timed with HIP
+    events over reps copies; each copy moves 2 nbytes (read + write). GB/s."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    e.synchronize()
+    gbs = 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 # Algorithmic FP32 work of the tracker, per level and pass of one keypoint:
 # the template (52 samples, gradients, normalisation, J, H, its inverse, G,
 # c) about 4.6 kFLOP, one Gauss-Newton iteration (warp, bilinear samples,
@@ -487,15 +510,18 @@ def main():
         else:
             flops_step = (n_temporal + n_stereo) * track_flops_per_call(L, N)
         pyr_b = sum(pyramid_bytes(w.width, w.height, L, w.n_cams) for w in ws)
+        pyr_gbs = pyr_b / (mean_ms[0] * 1e-3) / 1e9 if have_times else None
+        trk_tf = float(flops_step.mean()) / (mean_ms[1] * 1e-3) / 1e12 if have_times else None
         kernels = {
             "k_pyr_detect": {"bound": "hbm", "avg_ms": float(mean_ms[0]), "bytes_per_launch": pyr_b,
-                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "achieved": pyr_b / (mean_ms[0] * 1e-3) / 1e9 if have_times else None},
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "achieved": pyr_gbs,
+                             "copy_peak": copy_gbs,
+                             "frac_of_copy": pyr_gbs / copy_gbs if pyr_gbs is not None else None},
             "k_track": {"bound": "alu", "avg_ms": float(mean_ms[1]),
                         "calls_per_launch": float((n_temporal + n_stereo).mean()),
                         "flops_per_launch": float(flops_step.mean()), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                        "unit": "TFLOP/s",
-                        "achieved": float(flops_step.mean()) / (mean_ms[1] * 1e-3) / 1e12 if have_times else None},
+                        "unit": "TFLOP/s", "achieved": trk_tf, "peak_unpacked": FP32_VECTOR_UNPACKED_TFLOPS,
+                        "frac_unpacked": trk_tf / FP32_VECTOR_UNPACKED_TFLOPS if trk_tf is not None else None},
             "k_select": {"bound": "latency", "avg_ms": float(mean_ms[2])},
         }
         if init == "learned":
@@ -542,6 +568,9 @@ def main():
             "host_image": None if args.no_host_leg else host_run(init),
         }
 
+    # the achievable device bandwidth beside the vendor figure (before the legs: nothing else runs)
+    copy_gbs = copy_peak_gbs()
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     legs = {init: leg(init) for init in inits}
 
     # value: the faster leg that meets the accuracy bar (median <= 0.1 px; survival within 0.5 points of plain)
@@ -636,6 +665,8 @@ def main():
         "latency_ms": vb["latency_ms"],
         "accuracy": vb["accuracy"],
         "roofline": vb["roofline"],
+        "hbm_copy": {"gbs": copy_gbs, "vendor_peak_gbs": HBM_PEAK_GBS, "frac_of_vendor": copy_gbs / HBM_PEAK_GBS,
+                     "bytes_per_copy": 2 * (1 << 29)},
         "legs": legs,
         "cpu_baseline": cpu,
     }
