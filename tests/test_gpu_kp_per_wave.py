@@ -148,8 +148,9 @@ def test_star_rig(stereo_mode):
     assert n_rec > 0
 
 
-@pytest.mark.parametrize("name,frames", [("stereo752", 6), ("rig4", 3)])
+@pytest.mark.parametrize("name,frames", [("stereo752", 6), ("rig4", 3), ("mono320", 5)])
 def test_oracle_parity(name, frames):
+    """L = 4, 5 and 3: the kernels of odd level counts as well."""
     w = synthgen.WORKLOADS[name]
     seq = synthgen.sequence(w, seq=12, n_frames=frames)
     print(f"case oracle {name}", flush=True)
