@@ -148,10 +148,14 @@ def test_star_rig(stereo_mode):
     assert n_rec > 0
 
 
-@pytest.mark.parametrize("name,frames", [("stereo752", 6), ("rig4", 3), ("mono320", 5)])
+@pytest.mark.parametrize("name,frames", [("stereo752", 6), ("rig4", 3), ("mono320_free", 5)])
 def test_oracle_parity(name, frames):
-    """L = 4, 5 and 3: the kernels of odd level counts as well."""
-    w = synthgen.WORKLOADS[name]
+    """L = 4, 5 and 3: the kernels of odd level counts as well (mono320 in free
+    motion: its default is a two-frame warp)."""
+    if name == "mono320_free":
+        w = synthgen.WORKLOADS["mono320"].with_(warp_second=False, name="mono320_free")
+    else:
+        w = synthgen.WORKLOADS[name]
     seq = synthgen.sequence(w, seq=12, n_frames=frames)
     print(f"case oracle {name}", flush=True)
     n_tr = 0
