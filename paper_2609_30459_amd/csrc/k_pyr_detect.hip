@@ -63,9 +63,29 @@ struct PyrGeom {
   static constexpr int h_shift0 = a0x - apron(0);
   static_assert(L == 1 || (h_shift0 >= 0 && h_shift0 < 4), "paired pass byte shift");
   static constexpr int lvl_bytes = L > 1 ? region(1) * region(1) : 1;
+  // tiles per XCD run: 512 level-0 pixels
+  static constexpr int xcd_run = 512 / T;
 };
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Tile of workgroup b among n. Workgroups go to the 8 XCDs in turn (b mod 8),
+// each XCD with its own L2, and a staged row (tile plus aprons) spans two
+// 128-byte lines that the horizontal neighbours share: with tiles in raster
+// order every neighbour sits on another XCD and each L2 fetches the shared
+// lines again. Here XCD x takes runs of R consecutive tiles (workgroups x,
+// x + 8, x + 16, ... take run x, then run x + 8, ...), so a run's shared lines
+// are fetched once into one L2, while the runs still interleave finely over
+// the XCDs (no band of the image lands on one XCD). Workgroups past the last
+// whole group of 8 runs keep their own index. A permutation of 0..n-1.
+constexpr int kXcds = 8;
+template <int R>
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int group = kXcds * R;
+  if (b >= n / group * group) return b;
+  const int x = b % kXcds, j = b / kXcds;
+  return ((j / R) * kXcds + x) * R + j % R;
+}
 
 // Signed differences of the 16 circle pixels to the centre (Bresenham circle
 // of radius 3 from (0,-3) clockwise), read from the LDS tile at offset `o`
@@ -199,7 +219,7 @@ __global__ __launch_bounds__(T == 64 ? 1024 : 256) void k_pyr_detect(const CamDe
     uint32_t* fd = reinterpret_cast<uint32_t*>(dframe);
     for (int i = (int)threadIdx.x; i < copy_words; i += kPyrThreads) fd[i] = fs[i];
   }
-  const int gtile = tile_base + (int)blockIdx.x;
+  const int gtile = tile_base + xcd_tile<G::xcd_run>((int)blockIdx.x, (int)gridDim.x);
   int c = cam_begin;
   while (c + 1 < cam_end && cams[c + 1].tile_begin <= gtile) ++c;
   const CamDesc& cd = cams[c];
