@@ -386,9 +386,17 @@ def main():
 
         log(f"{init}: warmup {warmup} steps ({'eager' if eager else args.launch}"
             f"{f', {depth} frames in flight' if pipelined else ''})")
+        # the warmup runs the timed region's own loop (pipelined when it is), so
+        # the first timed frames find its code paths and buffers warm
         for t in range(warmup):
             submit(t)
-            collect(t)
+            if not pipelined:
+                collect(t)
+            elif t >= depth - 1:
+                collect(t - depth + 1)
+        if pipelined:
+            for t in range(max(0, warmup - depth + 1), warmup):
+                collect(t)
         torch.cuda.synchronize()
         log(f"{init}: timing {args.steps} steps")
         gc.collect()
