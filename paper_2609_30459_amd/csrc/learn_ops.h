@@ -21,58 +21,36 @@ constexpr int kNone = 0x7FFFFFFF;
 constexpr uint64_t kInfBits = 0x7FF0000000000000ull;  // +inf as a key: an empty place
 
 // Exact neighbour key: the squared distance as the bits of a non-negative
-// double (their unsigned order is the numeric order), then the index.
-struct NKey {
-  uint64_t d;
-  int ix;
-};
+// double (their unsigned order is the numeric order), then the index; keys are
+// compared lexicographically.
 
-__device__ __forceinline__ bool nkey_less(const NKey& a, const NKey& b) {
-  return a.d < b.d || (a.d == b.d && a.ix < b.ix);
+// Minimum of an unsigned value over the 64 lanes, in every lane: quads, rows
+// (rotations by 4 and 8), then the row swaps.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad lane ^ 1
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad lane ^ 2
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));  // row rotate by 4
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));  // row rotate by 8
+  const auto a = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  v = min((uint32_t)a[0], (uint32_t)a[1]);
+  const auto b = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return min((uint32_t)b[0], (uint32_t)b[1]);
 }
 
-// The smallest key over the 64 lanes, in every lane (every lane must be
-// active): a minimum over each quad (quad permutes), over each 16-lane row
-// (rotations by 4 and 8), then across the rows (permlane32 and permlane16
-// swaps) -- DPP and permlane moves only, no LDS round trip.
-template <int Ctrl>
-__device__ __forceinline__ void min_dpp(NKey& k) {
-  NKey p;
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)k.d, Ctrl, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k.d >> 32), Ctrl, 0xF, 0xF, false);
-  p.d = ((uint64_t)hi << 32) | lo;
-  p.ix = __builtin_amdgcn_update_dpp(0, k.ix, Ctrl, 0xF, 0xF, false);
-  const bool take = nkey_less(p, k);
-  // field by field: a select of the whole struct goes through private memory
-  k.d = take ? p.d : k.d;
-  k.ix = take ? p.ix : k.ix;
-}
-
-template <bool k32>
-__device__ __forceinline__ void min_swap(NKey& k) {
-  const uint32_t lo0 = (uint32_t)k.d, hi0 = (uint32_t)(k.d >> 32), ix0 = (uint32_t)k.ix;
-  // swap(v, v) leaves the partner row's value in one of the two results, the
-  // own value in the other; the minimum of the two is the same either way
-  const auto a = k32 ? __builtin_amdgcn_permlane32_swap(lo0, lo0, false, false)
-                     : __builtin_amdgcn_permlane16_swap(lo0, lo0, false, false);
-  const auto b = k32 ? __builtin_amdgcn_permlane32_swap(hi0, hi0, false, false)
-                     : __builtin_amdgcn_permlane16_swap(hi0, hi0, false, false);
-  const auto c = k32 ? __builtin_amdgcn_permlane32_swap(ix0, ix0, false, false)
-                     : __builtin_amdgcn_permlane16_swap(ix0, ix0, false, false);
-  const uint32_t la = a[0], lb = a[1], ha = b[0], hb = b[1], ia = c[0], ib = c[1];
-  NKey x{((uint64_t)ha << 32) | la, (int)ia}, y{((uint64_t)hb << 32) | lb, (int)ib};
-  const bool take = nkey_less(y, x);
-  k.d = take ? y.d : x.d;
-  k.ix = take ? y.ix : x.ix;
-}
-
-__device__ __forceinline__ void wave_min_key(NKey& k) {
-  min_dpp<0xB1>(k);   // quad lane ^ 1
-  min_dpp<0x4E>(k);   // quad lane ^ 2
-  min_dpp<0x124>(k);  // row rotate by 4
-  min_dpp<0x128>(k);  // row rotate by 8
-  min_swap<true>(k);  // rows 0, 1 <-> 2, 3
-  min_swap<false>(k); // rows 0 <-> 1, 2 <-> 3
+// The index of the smallest key (d, ix) over the 64 lanes, in every lane (every
+// lane must be active), taken word by word.
+// The high words of d first; when a single lane holds their minimum (the usual
+// case: a tie needs equal exponents and top 20 mantissa bits) its key is the
+// minimum and its index is read from it; otherwise the low words among the
+// tied lanes, then the indices among the lanes tied on both (indices are
+// non-negative, so their unsigned order is their order).
+__device__ __forceinline__ int wave_min_head(uint64_t d, int ix) {
+  const uint32_t hi = (uint32_t)(d >> 32), lo = (uint32_t)d;
+  const uint32_t mh = wave_min_u32(hi);
+  const uint64_t tied = __ballot(hi == mh);
+  if (__popcll(tied) == 1) return __builtin_amdgcn_readlane(ix, (int)__ffsll((long long)tied) - 1);
+  const uint32_t ml = wave_min_u32(hi == mh ? lo : 0xFFFFFFFFu);
+  return (int)wave_min_u32(hi == mh && lo == ml ? (uint32_t)ix : 0xFFFFFFFFu);
 }
 
 // A lane's best eight keys so far, ascending (+inf / kNone: an empty place).
@@ -114,10 +92,9 @@ struct Top8 {
     int best = kNone;
 #pragma unroll 1
     for (int r8 = 0; r8 < 8; ++r8) {
-      NKey m{d[0], ix[0]};
-      wave_min_key(m);
-      if (lane == r8) best = m.ix;
-      const bool pop = ix[0] == m.ix && m.ix != kNone;
+      const int mix = wave_min_head(d[0], ix[0]);
+      if (lane == r8) best = mix;
+      const bool pop = ix[0] == mix && mix != kNone;
 #pragma unroll
       for (int s = 0; s < 7; ++s) {
         d[s] = pop ? d[s + 1] : d[s];
