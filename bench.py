@@ -109,10 +109,23 @@ def pyramid_bytes(width, height, levels, cams):
     return a0 + p1
 
 
+def kernel_source_hash(source):
+    """First 16 hex digits of the SHA-256 of a kernel's source file followed by
+    every header of the kernel sources (sorted by name), so that a change to a
+    shared header counts as a change of the kernel."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2609_30459_amd", "csrc")
+    h = hashlib.sha256()
+    for path in [os.path.join(csrc, source)] + sorted(glob.glob(os.path.join(csrc, "*.h"))):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch from the committed counter profile of this workload,
-    or None when the kernel source changed since the counters were taken."""
-    import hashlib
+    or None when the kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{workload}_counters.json")
     if not os.path.exists(path):
         return None
@@ -121,9 +134,8 @@ def measured_traffic(workload, kernel):
     k = prof.get("kernels", {}).get(kernel)
     if not k or k.get("traffic_bytes") is None:
         return None
-    with open(os.path.join(ROOT, "paper_2609_30459_amd", "csrc", k["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != k["source_sha256_16"]:
-            return None
+    if kernel_source_hash(k["source"]) != k["source_sha256_16"]:
+        return None
     return k["traffic_bytes"]
 
 
