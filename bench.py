@@ -396,8 +396,12 @@ def main():
                 records[0].append(fe.get_tracks(0))
             return time.perf_counter() - t_sub.pop(t)
 
+        # no garbage-collector pause inside the warmup or the timed steps, and
+        # no idle gap between them (the device would lower its clocks in one)
+        gc.collect()
+        gc.disable()
         log(f"{init}: warmup {warmup} steps ({'eager' if eager else args.launch}"
-            f"{f', {depth} frames in flight' if pipelined else ''})")
+            f"{f', {depth} frames in flight' if pipelined else ''}), then {args.steps} timed steps")
         # the warmup runs the timed region's own loop (pipelined when it is), so
         # the first timed frames find its code paths and buffers warm
         for t in range(warmup):
@@ -410,9 +414,6 @@ def main():
             for t in range(max(0, warmup - depth + 1), warmup):
                 collect(t)
         torch.cuda.synchronize()
-        log(f"{init}: timing {args.steps} steps")
-        gc.collect()
-        gc.disable()  # no garbage-collector pause inside the timed steps
         # the production region reads only the records; the eager region also
         # each frame's statistics (kernel times, device time, fallbacks)
         t0 = time.perf_counter()
